@@ -1,0 +1,232 @@
+/*
+ * ddmgnn.h - C ABI of the DDM-GNN preconditioned flexible-CG solver for
+ * MI355X (gfx950).
+ *
+ * The operation is the paper's hybrid solver (arXiv 2402.08296): a Krylov
+ * method (Algorithm 1; here flexible CG by default) whose preconditioner is the
+ * DDM-GNN apply of Sec. III.A:
+ *   1. coarse problem  r_c = R_0^T (R_0 A R_0^T)^{-1} R_0 r           (step 1)
+ *   2. local problems  r~_i = DSS_theta(G_i), G_i = (Omega_{h,i}, R_i r/|R_i r|)
+ *                      with the DSS_theta model of Sec. III.B         (step 2)
+ *   3. gluing          z = r_c + sum_i R_i^T w_i |R_i r| r~_i          (step 3)
+ * where w_i = 1 is the paper's glue and w_i = D_i (partition of unity) the
+ * weighted variant.
+ *
+ * Conventions for every entry point:
+ *   - Returns DDMGNN_OK (0) or a negative status; nothing aborts. The text of
+ *     the last error of the calling thread is returned by ddmgnn_last_error().
+ *   - Pointers documented as "host" are read during the call only; the library
+ *     copies what it keeps. Pointers documented as "device" are HIP device
+ *     memory owned by the caller, on the device current at ctx creation.
+ *   - All device work is enqueued on the context's stream. Calls that return
+ *     results (solve, apply, forward, spmv) synchronise that stream before
+ *     returning.
+ *   - Handles are owned by the library until the matching *_destroy call.
+ *     One context per host thread.
+ */
+#ifndef DDMGNN_H
+#define DDMGNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DDMGNN_OK = 0,
+    DDMGNN_E_INVALID = -1,    /* malformed input or unsupported option */
+    DDMGNN_E_NOMEM = -2,      /* device or host allocation failed */
+    DDMGNN_E_HIP = -3,        /* HIP runtime error */
+    DDMGNN_E_NOT_SPD = -4,    /* coarse matrix R_0 A R_0^T not positive definite */
+    DDMGNN_E_BREAKDOWN = -5,  /* <p, A p> <= 0 in the Krylov recurrence */
+    DDMGNN_E_MAXIT = -6,      /* not converged within max_it; u holds the last iterate */
+    DDMGNN_E_NONFINITE = -7,  /* NaN/Inf in the residual; u holds the last finite iterate */
+    DDMGNN_E_BUDGET = -8,     /* request exceeds the memory budget */
+    DDMGNN_E_PENDING = -9     /* result not ready yet */
+};
+
+/* Krylov method (Algorithm 1 is PCG; FCG is its flexible variant). */
+enum { DDMGNN_FCG = 0, DDMGNN_PCG = 1, DDMGNN_CG = 2 };
+/* Arithmetic of the DSS_theta forward pass. Krylov vectors, dot products,
+ * the residual update and the coarse level are always FP64. */
+enum { DDMGNN_FP64 = 0, DDMGNN_FP32 = 1, DDMGNN_BF16 = 2 };
+/* Weights of the gluing step 3: partition of unity D_i, or 1 (paper). */
+enum { DDMGNN_PROLONG_POU = 0, DDMGNN_PROLONG_UNWEIGHTED = 1 };
+
+typedef struct ddmgnn_ctx ddmgnn_ctx;
+typedef struct ddmgnn_model ddmgnn_model;
+typedef struct ddmgnn_problem ddmgnn_problem;
+
+/* Text of the last error on this thread (empty when none). */
+const char* ddmgnn_last_error(void);
+const char* ddmgnn_version(void);
+
+/* Context bound to the current HIP device and to `hip_stream` (a hipStream_t,
+ * NULL = the null stream). The stream must outlive the context. */
+int ddmgnn_ctx_create(void* hip_stream, ddmgnn_ctx** out);
+int ddmgnn_ctx_destroy(ddmgnn_ctx* ctx);
+
+/* DSS_theta hyper-parameters (Sec. IV.B: kbar = 30, d = 10, hidden width d,
+ * alpha = 1e-3). Only d = 10 is compiled in this build. */
+typedef struct {
+    int32_t kbar;
+    int32_t d;
+    double alpha;
+} ddmgnn_model_desc;
+
+/* Create a model from `theta` (host, float32, n_theta values). n_theta must be
+ * kbar * (11 d^2 + 15 d + 1) (the parameter counts of Table II). Layout, block
+ * k = 1..kbar in order, matrices row-major [out][in]:
+ *   Phi_out {W1[d][2d+3], b1[d], W2[d][d], b2[d]}   inputs (h_j, h_l, d_jl, |d_jl|)
+ *   Phi_in  {W1[d][2d+3], b1[d], W2[d][d], b2[d]}   inputs (h_j, h_l, d_lj, |d_lj|)
+ *   Psi     {W1[d][3d+1], b1[d], W2[d][d], b2[d]}   inputs (h_j, c_j, phi_out_j, phi_in_j)
+ *   Dec     {W1[d][d],    b1[d], W2[1][d], b2[1]}   input  h_j
+ * (eqs. (14)-(18)). Copied at call time. */
+int ddmgnn_model_create(ddmgnn_ctx* ctx, const ddmgnn_model_desc* desc, const float* theta,
+                        int64_t n_theta, ddmgnn_model** out);
+int ddmgnn_model_destroy(ddmgnn_model* model);
+
+/* One Poisson-Dirichlet problem A u = b (eqs. (1)-(2)) with its overlapping
+ * decomposition (Sec. II.A). All pointers are host pointers.
+ *   xy[2N]            node coordinates (x0, y0, x1, y1, ...)
+ *   tri[3T]           triangles (node ids), used for the DSS graphs (Sec. III.B)
+ *   dirichlet[N]      1 at Dirichlet nodes, else 0. Dirichlet rows of A must be
+ *                     identity rows, decoupled from the free rows.
+ *   a_rowptr[N+1], a_col[nnz], a_val[nnz]
+ *                     A in CSR, symmetric, columns strictly ascending per row.
+ *   b[N], u0[N]       right-hand side and initial guess.
+ *   sub_ptr[K+1], sub_nodes[sub_ptr[K]]
+ *                     sub-mesh i holds nodes sub_nodes[sub_ptr[i] .. sub_ptr[i+1]),
+ *                     strictly ascending; the local index of a node is its rank.
+ *                     Every node belongs to at least one sub-mesh.
+ *   weights[sub_ptr[K]]
+ *                     partition-of-unity weights D_i aligned with sub_nodes:
+ *                     >= 0, summing to 1 over the sub-meshes of each free node
+ *                     and 0 at Dirichlet nodes. They define the Nicolaides
+ *                     coarse basis (column i of R_0^T is R_i^T D_i R_i 1).
+ * Setup builds the local DSS graphs (edges l -> j for mesh edges inside the
+ * sub-mesh, none received by Dirichlet nodes), R_0 A R_0^T and its inverse
+ * (E_NOT_SPD if Cholesky fails), and uploads everything to the device. */
+typedef struct {
+    int64_t n_nodes;
+    const double* xy;
+    int64_t n_tri;
+    const int32_t* tri;
+    const uint8_t* dirichlet;
+    const int32_t* a_rowptr;
+    const int32_t* a_col;
+    const double* a_val;
+    const double* b;
+    const double* u0;
+    int32_t n_sub;
+    const int64_t* sub_ptr;
+    const int32_t* sub_nodes;
+    const double* weights;
+} ddmgnn_problem_desc;
+
+/* Validate a descriptor on the host (no device needed). */
+int ddmgnn_validate_problem(const ddmgnn_problem_desc* desc);
+
+/* Largest sub-mesh the DSS kernels accept (nodes). */
+int32_t ddmgnn_max_subdomain_nodes(void);
+
+int ddmgnn_problem_create(ddmgnn_ctx* ctx, const ddmgnn_problem_desc* desc, const ddmgnn_model* model,
+                          ddmgnn_problem** out);
+int ddmgnn_problem_destroy(ddmgnn_problem* prob);
+
+typedef struct {
+    int32_t krylov;      /* DDMGNN_FCG / PCG / CG */
+    int32_t m_max;       /* FCG truncation: directions kept for A-orthogonalisation (1) */
+    double rtol;         /* stop when |r_i| <= rtol |r_0| (1e-6, Sec. IV.C) */
+    int32_t max_it;
+    int32_t precision;   /* DDMGNN_FP64 / FP32 / BF16 for the DSS forward */
+    int32_t prolong;     /* DDMGNN_PROLONG_POU / UNWEIGHTED */
+    int32_t coarse;      /* 1: add the coarse correction (step 1), 0: one-level */
+    int32_t check_every; /* iterations between host checks of the converged flag */
+} ddmgnn_solve_opts;
+
+typedef struct {
+    int32_t iterations;
+    int32_t converged;
+    double rel_residual;       /* |r_it| / |r_0| of the recurrence */
+    double true_rel_residual;  /* |b - A u| / |r_0| recomputed at exit */
+    double solve_ms;           /* device time of the whole solve (HIP events) */
+} ddmgnn_stats;
+
+/* Fill opts with defaults (FCG, m_max 1, rtol 1e-6, max_it 10000, FP32, POU, coarse on). */
+void ddmgnn_default_opts(ddmgnn_solve_opts* opts);
+
+/* Solve A u = b from the problem's u0. u_out: device, N doubles. On
+ * E_MAXIT / E_NONFINITE / E_BREAKDOWN u_out holds the last finite iterate. */
+int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const ddmgnn_solve_opts* opts, double* u_out,
+                 ddmgnn_stats* stats);
+
+/* One preconditioner apply z = M(r) (Sec. III.A steps 1-3). r, z: device, N
+ * doubles, must not alias. */
+int ddmgnn_precond_apply(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const ddmgnn_solve_opts* opts,
+                         const double* r, double* z);
+
+/* Intermediates of the last ddmgnn_precond_apply on this problem, copied to
+ * device buffers the caller owns (any pointer may be NULL):
+ *   s[K]        |R_i r|
+ *   y0[K]       R_0 r
+ *   y[K]        (R_0 A R_0^T)^{-1} R_0 r
+ *   local[sk]   |R_i r| r~_i per sub-mesh node, in sub_nodes order (sk = sub_ptr[K]). */
+int ddmgnn_apply_intermediates(ddmgnn_ctx* ctx, ddmgnn_problem* prob, double* s, double* y0, double* y,
+                               double* local);
+
+/* DSS_theta forward pass (Sec. III.B) on every sub-mesh of the problem. c and
+ * out: device, sub_ptr[K] doubles in sub_nodes order; c holds each sub-mesh's
+ * input c_i, out receives r~_i = D^kbar(H^kbar). */
+int ddmgnn_dss_forward(ddmgnn_ctx* ctx, ddmgnn_problem* prob, int32_t precision, const double* c,
+                       double* out);
+
+/* y = A x with the problem's matrix (the q = A p step of Algorithm 1). x, y:
+ * device, N doubles. */
+int ddmgnn_spmv(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const double* x, double* y);
+
+/* Deterministic FP64 dot product of two device vectors of length n (the
+ * reductions of Algorithm 1); result written to *out (host). */
+int ddmgnn_dot(ddmgnn_ctx* ctx, int64_t n, const double* x, const double* y, double* out);
+
+/* ---- host-only helpers (no device needed) ---- */
+
+/* Overlapping sub-meshes: part i grown by `delta` layers of mesh adjacency
+ * (Sec. II.A, overlap of Sec. IV.A). part[N] in [0, n_part). On success
+ * *sub_ptr_out (n_part+1 int64) and *sub_nodes_out (int32, ascending per
+ * sub-mesh) are allocated by the library; free them with ddmgnn_free. */
+int ddmgnn_expand_overlap(int64_t n_nodes, int64_t n_tri, const int32_t* tri, const int32_t* part,
+                          int32_t n_part, int32_t delta, int64_t** sub_ptr_out, int32_t** sub_nodes_out);
+
+/* Partition-of-unity weights D_i = 1/multiplicity at free nodes, 0 at Dirichlet
+ * nodes, aligned with sub_nodes (weights_out: caller-allocated, sub_ptr[K]). */
+int ddmgnn_pou_weights(int64_t n_nodes, const uint8_t* dirichlet, int32_t n_sub, const int64_t* sub_ptr,
+                       const int32_t* sub_nodes, double* weights_out);
+
+void ddmgnn_free(void* p);
+
+/* Sizes of a problem: N, nnz, K, sum k_i, number of directed DSS edges. */
+int ddmgnn_problem_sizes(const ddmgnn_problem* prob, int64_t* n, int64_t* nnz, int32_t* k,
+                         int64_t* sum_k, int64_t* n_edges);
+
+/* Local DSS graph of sub-mesh `sub` as setup builds it from a descriptor
+ * (Sec. III.B: edge l -> j for every mesh edge {j, l} inside the sub-mesh
+ * whose receiver j is not a Dirichlet node). Outputs (host, caller-owned):
+ * in-edge row pointers rowptr[k_sub+1] and sender local ids col[n_edges_sub],
+ * receiver-major with senders ascending. Pass NULL rowptr/col to query
+ * *n_edges_sub only. The descriptor is validated first. */
+int ddmgnn_setup_local_graph(const ddmgnn_problem_desc* desc, int32_t sub, int32_t* rowptr, int32_t* col,
+                             int64_t* n_edges_sub);
+
+/* Coarse operator A_0 = R_0 A R_0^T (eq. (7), Nicolaides basis from the
+ * weights) and its inverse as setup forms them, row-major K x K into
+ * caller-owned host buffers (either may be NULL). E_NOT_SPD when the Cholesky
+ * factorisation fails. */
+int ddmgnn_setup_coarse(const ddmgnn_problem_desc* desc, double* a0, double* a0inv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDMGNN_H */

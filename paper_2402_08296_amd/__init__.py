@@ -1,0 +1,339 @@
+"""Python binding of libddmgnn (DDM-GNN preconditioned flexible CG on MI355X).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+Device buffers are torch CUDA (HIP) tensors, passed by pointer; torch supplies
+device memory and the stream, nothing else. There is no CPU fallback: when the
+library is missing every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from ._build import LIB as _LIB_PATH
+
+FCG, PCG, CG = 0, 1, 2
+FP64, FP32, BF16 = 0, 1, 2
+PROLONG_POU, PROLONG_UNWEIGHTED = 0, 1
+STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_HIP", -4: "E_NOT_SPD", -5: "E_BREAKDOWN",
+          -6: "E_MAXIT", -7: "E_NONFINITE", -8: "E_BUDGET", -9: "E_PENDING"}
+PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+
+_p = ctypes.c_void_p
+_i32, _i64, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+
+
+class DDMGNNError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class ModelDesc(ctypes.Structure):
+    _fields_ = [("kbar", _i32), ("d", _i32), ("alpha", _f64)]
+
+
+class ProblemDesc(ctypes.Structure):
+    _fields_ = [("n_nodes", _i64), ("xy", _p), ("n_tri", _i64), ("tri", _p), ("dirichlet", _p),
+                ("a_rowptr", _p), ("a_col", _p), ("a_val", _p), ("b", _p), ("u0", _p),
+                ("n_sub", _i32), ("sub_ptr", _p), ("sub_nodes", _p), ("weights", _p)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("krylov", _i32), ("m_max", _i32), ("rtol", _f64), ("max_it", _i32), ("precision", _i32),
+                ("prolong", _i32), ("coarse", _i32), ("check_every", _i32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", _i32), ("converged", _i32), ("rel_residual", _f64),
+                ("true_rel_residual", _f64), ("solve_ms", _f64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the in-tree libddmgnn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "ddmgnn_last_error": (ctypes.c_char_p, []),
+        "ddmgnn_version": (ctypes.c_char_p, []),
+        "ddmgnn_ctx_create": (ctypes.c_int, [_p, ctypes.POINTER(_p)]),
+        "ddmgnn_ctx_destroy": (ctypes.c_int, [_p]),
+        "ddmgnn_model_create": (ctypes.c_int, [_p, ctypes.POINTER(ModelDesc), _p, _i64, ctypes.POINTER(_p)]),
+        "ddmgnn_model_destroy": (ctypes.c_int, [_p]),
+        "ddmgnn_validate_problem": (ctypes.c_int, [ctypes.POINTER(ProblemDesc)]),
+        "ddmgnn_max_subdomain_nodes": (_i32, []),
+        "ddmgnn_problem_create": (ctypes.c_int, [_p, ctypes.POINTER(ProblemDesc), _p, ctypes.POINTER(_p)]),
+        "ddmgnn_problem_destroy": (ctypes.c_int, [_p]),
+        "ddmgnn_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
+        "ddmgnn_solve": (ctypes.c_int, [_p, _p, ctypes.POINTER(SolveOpts), _p, ctypes.POINTER(Stats)]),
+        "ddmgnn_precond_apply": (ctypes.c_int, [_p, _p, ctypes.POINTER(SolveOpts), _p, _p]),
+        "ddmgnn_apply_intermediates": (ctypes.c_int, [_p, _p, _p, _p, _p, _p]),
+        "ddmgnn_dss_forward": (ctypes.c_int, [_p, _p, _i32, _p, _p]),
+        "ddmgnn_spmv": (ctypes.c_int, [_p, _p, _p, _p]),
+        "ddmgnn_dot": (ctypes.c_int, [_p, _i64, _p, _p, ctypes.POINTER(_f64)]),
+        "ddmgnn_expand_overlap": (ctypes.c_int, [_i64, _i64, _p, _p, _i32, _i32, ctypes.POINTER(_p),
+                                                 ctypes.POINTER(_p)]),
+        "ddmgnn_pou_weights": (ctypes.c_int, [_i64, _p, _i32, _p, _p, _p]),
+        "ddmgnn_free": (None, [_p]),
+        "ddmgnn_problem_sizes": (ctypes.c_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                                ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+        "ddmgnn_setup_local_graph": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), _i32, _p, _p,
+                                                    ctypes.POINTER(_i64)]),
+        "ddmgnn_setup_coarse": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), _p, _p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise DDMGNNError(rc, lib().ddmgnn_last_error().decode())
+
+
+def _np(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(_p)
+
+
+def _dev(t, dtype_name="float64"):
+    """Pointer of a contiguous torch device tensor of the given dtype."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a torch device tensor")
+    if not t.is_contiguous() or str(t.dtype) != f"torch.{dtype_name}":
+        raise TypeError(f"expected a contiguous {dtype_name} tensor")
+    return _p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ host-only helpers
+def expand_overlap(n: int, tri, part, n_part: int, delta: int):
+    """Overlapping sub-meshes (library implementation); returns (sub_ptr int64, sub_nodes int32)."""
+    tri, tp = _np(tri, np.int32)
+    part, pp = _np(part, np.int32)
+    sp, sn = _p(), _p()
+    _check(lib().ddmgnn_expand_overlap(n, tri.size // 3, tp, pp, n_part, delta, ctypes.byref(sp), ctypes.byref(sn)))
+    try:
+        ptr = np.ctypeslib.as_array(ctypes.cast(sp, ctypes.POINTER(_i64)), (n_part + 1,)).copy()
+        nodes = np.ctypeslib.as_array(ctypes.cast(sn, ctypes.POINTER(_i32)), (int(ptr[-1]),)).copy()
+    finally:
+        lib().ddmgnn_free(sp)
+        lib().ddmgnn_free(sn)
+    return ptr, nodes
+
+
+def pou_weights(n: int, dirichlet, sub_ptr, sub_nodes):
+    dirichlet, dp = _np(dirichlet, np.uint8)
+    sub_ptr, spp = _np(sub_ptr, np.int64)
+    sub_nodes, snp = _np(sub_nodes, np.int32)
+    w = np.empty(sub_nodes.size, np.float64)
+    _check(lib().ddmgnn_pou_weights(n, dp, sub_ptr.size - 1, spp, snp, w.ctypes.data_as(_p)))
+    return w
+
+
+@dataclass
+class HostProblem:
+    """Host arrays of one problem in the layout of ddmgnn_problem_desc."""
+    xy: np.ndarray
+    tri: np.ndarray
+    dirichlet: np.ndarray
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+    b: np.ndarray
+    u0: np.ndarray
+    sub_ptr: np.ndarray
+    sub_nodes: np.ndarray
+    weights: np.ndarray
+
+    def __post_init__(self):
+        self.xy = np.ascontiguousarray(self.xy, np.float64)
+        self.tri = np.ascontiguousarray(self.tri, np.int32)
+        self.dirichlet = np.ascontiguousarray(self.dirichlet, np.uint8)
+        self.rowptr = np.ascontiguousarray(self.rowptr, np.int32)
+        self.col = np.ascontiguousarray(self.col, np.int32)
+        self.val = np.ascontiguousarray(self.val, np.float64)
+        self.b = np.ascontiguousarray(self.b, np.float64)
+        self.u0 = np.ascontiguousarray(self.u0, np.float64)
+        self.sub_ptr = np.ascontiguousarray(self.sub_ptr, np.int64)
+        self.sub_nodes = np.ascontiguousarray(self.sub_nodes, np.int32)
+        self.weights = np.ascontiguousarray(self.weights, np.float64)
+
+    @property
+    def n(self) -> int:
+        return self.xy.shape[0]
+
+    @property
+    def K(self) -> int:
+        return self.sub_ptr.size - 1
+
+    def desc(self) -> ProblemDesc:
+        P = lambda a: a.ctypes.data_as(_p)
+        return ProblemDesc(self.n, P(self.xy), self.tri.size // 3, P(self.tri), P(self.dirichlet),
+                           P(self.rowptr), P(self.col), P(self.val), P(self.b), P(self.u0), self.K,
+                           P(self.sub_ptr), P(self.sub_nodes), P(self.weights))
+
+
+def host_problem(xy, tri, dirichlet, rowptr, col, val, b, u0, part, n_part, delta=2) -> HostProblem:
+    """Problem arrays with the library's overlap expansion and partition-of-unity weights."""
+    n = np.asarray(xy).shape[0]
+    sub_ptr, sub_nodes = expand_overlap(n, tri, part, n_part, delta)
+    w = pou_weights(n, dirichlet, sub_ptr, sub_nodes)
+    return HostProblem(xy, tri, dirichlet, rowptr, col, val, b, u0, sub_ptr, sub_nodes, w)
+
+
+def validate(hp: HostProblem):
+    d = hp.desc()
+    _check(lib().ddmgnn_validate_problem(ctypes.byref(d)))
+
+
+def setup_local_graph(hp: HostProblem, sub: int):
+    d = hp.desc()
+    ne = _i64()
+    _check(lib().ddmgnn_setup_local_graph(ctypes.byref(d), sub, None, None, ctypes.byref(ne)))
+    k = int(hp.sub_ptr[sub + 1] - hp.sub_ptr[sub])
+    rowptr = np.empty(k + 1, np.int32)
+    col = np.empty(max(1, ne.value), np.int32)
+    _check(lib().ddmgnn_setup_local_graph(ctypes.byref(d), sub, rowptr.ctypes.data_as(_p),
+                                          col.ctypes.data_as(_p), ctypes.byref(ne)))
+    return rowptr, col[:ne.value]
+
+
+def setup_coarse(hp: HostProblem):
+    d = hp.desc()
+    a0 = np.empty((hp.K, hp.K))
+    a0inv = np.empty((hp.K, hp.K))
+    _check(lib().ddmgnn_setup_coarse(ctypes.byref(d), a0.ctypes.data_as(_p), a0inv.ctypes.data_as(_p)))
+    return a0, a0inv
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    lib().ddmgnn_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISION[v]
+        setattr(o, k, v)
+    return o
+
+
+# ------------------------------------------------------------------ device objects
+class Context:
+    """A library context bound to the current device and a torch stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        h = _p()
+        _check(lib().ddmgnn_ctx_create(_p(s.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ddmgnn_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dot(self, x, y) -> float:
+        out = _f64()
+        _check(lib().ddmgnn_dot(self.h, x.numel(), _dev(x), _dev(y), ctypes.byref(out)))
+        return out.value
+
+
+class Model:
+    def __init__(self, ctx: Context, theta, kbar: int = 30, d: int = 10, alpha: float = 1e-3):
+        th, tp = _np(theta, np.float32)
+        self._theta = th
+        desc = ModelDesc(kbar, d, alpha)
+        h = _p()
+        _check(lib().ddmgnn_model_create(ctx.h, ctypes.byref(desc), tp, th.size, ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ddmgnn_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    def __init__(self, ctx: Context, hp: HostProblem, model: Model):
+        self.ctx = ctx
+        self.hp = hp
+        d = hp.desc()
+        h = _p()
+        _check(lib().ddmgnn_problem_create(ctx.h, ctypes.byref(d), model.h, ctypes.byref(h)))
+        self.h = h
+        n, nnz, e = _i64(), _i64(), _i64()
+        k, sk = _i32(), _i64()
+        _check(lib().ddmgnn_problem_sizes(h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(k), ctypes.byref(sk),
+                                          ctypes.byref(e)))
+        self.n, self.nnz, self.K, self.sum_k, self.n_edges = n.value, nnz.value, k.value, sk.value, e.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ddmgnn_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, u_out, opts: SolveOpts | None = None, check=True) -> Stats:
+        o = opts or default_opts()
+        st = Stats()
+        rc = lib().ddmgnn_solve(self.ctx.h, self.h, ctypes.byref(o), _dev(u_out), ctypes.byref(st))
+        if check:
+            _check(rc)
+        st.status = rc
+        return st
+
+    def apply(self, r, z, opts: SolveOpts | None = None):
+        o = opts or default_opts()
+        _check(lib().ddmgnn_precond_apply(self.ctx.h, self.h, ctypes.byref(o), _dev(r), _dev(z)))
+
+    def intermediates(self):
+        import torch
+        dev = self.ctx.stream.device
+        s = torch.empty(self.K, dtype=torch.float64, device=dev)
+        y0 = torch.empty_like(s)
+        y = torch.empty_like(s)
+        loc = torch.empty(self.sum_k, dtype=torch.float64, device=dev)
+        _check(lib().ddmgnn_apply_intermediates(self.ctx.h, self.h, _dev(s), _dev(y0), _dev(y), _dev(loc)))
+        return s, y0, y, loc
+
+    def dss_forward(self, c, out, precision=FP32):
+        if isinstance(precision, str):
+            precision = PRECISION[precision]
+        _check(lib().ddmgnn_dss_forward(self.ctx.h, self.h, precision, _dev(c), _dev(out)))
+
+    def spmv(self, x, y):
+        _check(lib().ddmgnn_spmv(self.ctx.h, self.h, _dev(x), _dev(y)))

@@ -1,0 +1,278 @@
+// Host-side setup of a DDM-GNN problem. See setup.h.
+#include "setup.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace ddmgnn {
+
+namespace {
+
+// Sorted, de-duplicated mesh adjacency (nodes sharing a triangle edge).
+void mesh_adjacency(int64_t n, int64_t nt, const int32_t* tri, std::vector<int64_t>& ptr,
+                    std::vector<int32_t>& adj) {
+    std::vector<int64_t> cnt(n + 1, 0);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int i = 0; i < 3; ++i) cnt[tri[3 * t + i] + 1] += 2;
+    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    std::vector<int32_t> tmp(cnt[n]);
+    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+    for (int64_t t = 0; t < nt; ++t) {
+        for (int i = 0; i < 3; ++i) {
+            int32_t a = tri[3 * t + i], b = tri[3 * t + (i + 1) % 3];
+            tmp[pos[a]++] = b;
+            tmp[pos[b]++] = a;
+        }
+    }
+    ptr.assign(n + 1, 0);
+    adj.clear();
+    adj.reserve(tmp.size() / 2 + 1);
+    for (int64_t i = 0; i < n; ++i) {
+        auto b = tmp.begin() + cnt[i], e = tmp.begin() + cnt[i + 1];
+        std::sort(b, e);
+        auto u = std::unique(b, e);
+        adj.insert(adj.end(), b, u);
+        ptr[i + 1] = (int64_t)adj.size();
+    }
+}
+
+}  // namespace
+
+std::string validate(const ddmgnn_problem_desc& d) {
+    const int64_t n = d.n_nodes;
+    if (n <= 0) return "n_nodes must be positive";
+    if (n >= (1ll << 31)) return "n_nodes must fit int32";
+    if (!d.xy || !d.tri || !d.dirichlet || !d.a_rowptr || !d.a_col || !d.a_val || !d.b || !d.u0 ||
+        !d.sub_ptr || !d.sub_nodes || !d.weights)
+        return "null pointer in problem descriptor";
+    if (d.n_tri <= 0) return "n_tri must be positive";
+    for (int64_t t = 0; t < 3 * d.n_tri; ++t)
+        if (d.tri[t] < 0 || d.tri[t] >= n) return "triangle node id out of range";
+    for (int64_t i = 0; i < n; ++i) {
+        if (d.dirichlet[i] > 1) return "dirichlet flags must be 0 or 1";
+        if (!std::isfinite(d.xy[2 * i]) || !std::isfinite(d.xy[2 * i + 1])) return "non-finite coordinate";
+        if (!std::isfinite(d.b[i]) || !std::isfinite(d.u0[i])) return "non-finite b or u0";
+    }
+    if (d.a_rowptr[0] != 0) return "a_rowptr[0] must be 0";
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t s = d.a_rowptr[i], e = d.a_rowptr[i + 1];
+        if (e < s) return "a_rowptr must be non-decreasing";
+        bool diag = false;
+        for (int32_t k = s; k < e; ++k) {
+            int32_t c = d.a_col[k];
+            if (c < 0 || c >= n) return "column index out of range";
+            if (k > s && c <= d.a_col[k - 1]) return "columns must be strictly ascending in each row";
+            if (!std::isfinite(d.a_val[k])) return "non-finite matrix value";
+            if (c == i) diag = true;
+            if (d.dirichlet[i] && c != i) return "Dirichlet rows must be identity rows";
+            if (d.dirichlet[i] && d.a_val[k] != 1.0) return "Dirichlet rows must be identity rows";
+            if (!d.dirichlet[i] && d.dirichlet[c]) return "free rows must not couple to Dirichlet nodes";
+        }
+        if (!diag) return "missing diagonal entry";
+    }
+    // Symmetry: for every (i, c, v) the entry (c, i) exists with the same value.
+    for (int64_t i = 0; i < n; ++i) {
+        for (int32_t k = d.a_rowptr[i]; k < d.a_rowptr[i + 1]; ++k) {
+            int32_t c = d.a_col[k];
+            const int32_t* b = d.a_col + d.a_rowptr[c];
+            const int32_t* e = d.a_col + d.a_rowptr[c + 1];
+            const int32_t* it = std::lower_bound(b, e, (int32_t)i);
+            if (it == e || *it != i || d.a_val[it - d.a_col] != d.a_val[k]) return "matrix is not symmetric";
+        }
+    }
+    if (d.n_sub <= 0) return "n_sub must be positive";
+    if (d.sub_ptr[0] != 0) return "sub_ptr[0] must be 0";
+    std::vector<double> wsum(n, 0.0);
+    std::vector<int32_t> cover(n, 0);
+    for (int32_t s = 0; s < d.n_sub; ++s) {
+        int64_t b = d.sub_ptr[s], e = d.sub_ptr[s + 1];
+        if (e <= b) return "empty sub-mesh";
+        if (e - b > kMaxSubNodes) return "sub-mesh larger than the supported maximum (2048 nodes)";
+        for (int64_t k = b; k < e; ++k) {
+            int32_t v = d.sub_nodes[k];
+            if (v < 0 || v >= n) return "sub_nodes id out of range";
+            if (k > b && v <= d.sub_nodes[k - 1]) return "sub_nodes must be strictly ascending per sub-mesh";
+            double w = d.weights[k];
+            if (!std::isfinite(w) || w < 0) return "weights must be finite and non-negative";
+            wsum[v] += w;
+            cover[v] += 1;
+        }
+    }
+    if (d.sub_ptr[d.n_sub] >= (1ll << 31)) return "total sub-mesh size must fit int32";
+    for (int64_t i = 0; i < n; ++i) {
+        if (!cover[i]) return "node not covered by any sub-mesh";
+        if (d.dirichlet[i] && wsum[i] != 0.0) return "weights must be 0 at Dirichlet nodes";
+        if (!d.dirichlet[i] && std::fabs(wsum[i] - 1.0) > 1e-12) return "weights are not a partition of unity";
+    }
+    return "";
+}
+
+void expand_overlap(int64_t n, int64_t nt, const int32_t* tri, const int32_t* part, int32_t n_part,
+                    int32_t delta, std::vector<int64_t>& sub_ptr, std::vector<int32_t>& sub_nodes) {
+    std::vector<int64_t> aptr;
+    std::vector<int32_t> adj;
+    mesh_adjacency(n, nt, tri, aptr, adj);
+    std::vector<std::vector<int32_t>> core(n_part);
+    for (int64_t i = 0; i < n; ++i) core[part[i]].push_back((int32_t)i);
+    std::vector<int32_t> mark(n, -1);
+    sub_ptr.assign(1, 0);
+    sub_nodes.clear();
+    for (int32_t p = 0; p < n_part; ++p) {
+        std::vector<int32_t> members = core[p], front = core[p];
+        for (int32_t v : members) mark[v] = p;
+        for (int32_t layer = 0; layer < delta; ++layer) {
+            std::vector<int32_t> next;
+            for (int32_t v : front)
+                for (int64_t e = aptr[v]; e < aptr[v + 1]; ++e)
+                    if (mark[adj[e]] != p) {
+                        mark[adj[e]] = p;
+                        next.push_back(adj[e]);
+                    }
+            members.insert(members.end(), next.begin(), next.end());
+            front.swap(next);
+        }
+        std::sort(members.begin(), members.end());
+        sub_nodes.insert(sub_nodes.end(), members.begin(), members.end());
+        sub_ptr.push_back((int64_t)sub_nodes.size());
+    }
+}
+
+void build_local_graphs(const ddmgnn_problem_desc& d, HostSetup& s) {
+    const int64_t n = d.n_nodes;
+    const int32_t K = d.n_sub;
+    s.n = n;
+    s.nnz = d.a_rowptr[n];
+    s.K = K;
+    s.sk = d.sub_ptr[K];
+    std::vector<int64_t> aptr;
+    std::vector<int32_t> adj;
+    mesh_adjacency(n, d.n_tri, d.tri, aptr, adj);
+
+    // Local DSS graphs. Local order equals ascending global order, so walking
+    // a receiver's sorted global neighbours yields senders in ascending local order.
+    std::vector<int32_t> loc(n, -1);
+    s.edge_ptr.assign(s.sk + 1, 0);
+    s.edge_src.clear();
+    s.slot_sub.assign(s.sk, 0);
+    s.max_k = 0;
+    for (int32_t i = 0; i < K; ++i) {
+        int64_t b = d.sub_ptr[i], e = d.sub_ptr[i + 1];
+        s.max_k = std::max<int32_t>(s.max_k, (int32_t)(e - b));
+        for (int64_t k = b; k < e; ++k) loc[d.sub_nodes[k]] = (int32_t)(k - b);
+        for (int64_t k = b; k < e; ++k) {
+            int32_t j = d.sub_nodes[k];
+            s.slot_sub[k] = i;
+            if (!d.dirichlet[j]) {
+                for (int64_t a = aptr[j]; a < aptr[j + 1]; ++a) {
+                    int32_t l = adj[a];
+                    if (loc[l] >= 0) s.edge_src.push_back((uint16_t)loc[l]);
+                }
+            }
+            s.edge_ptr[k + 1] = (int64_t)s.edge_src.size();
+        }
+        for (int64_t k = b; k < e; ++k) loc[d.sub_nodes[k]] = -1;
+    }
+    s.n_edges = (int64_t)s.edge_src.size();
+
+    // Membership lists: slots of every node, in increasing slot order.
+    s.node_ptr.assign(n + 1, 0);
+    for (int64_t k = 0; k < s.sk; ++k) s.node_ptr[d.sub_nodes[k] + 1]++;
+    for (int64_t i = 0; i < n; ++i) s.node_ptr[i + 1] += s.node_ptr[i];
+    s.node_slots.assign(s.sk, 0);
+    {
+        std::vector<int64_t> pos(s.node_ptr.begin(), s.node_ptr.end() - 1);
+        for (int64_t k = 0; k < s.sk; ++k) s.node_slots[pos[d.sub_nodes[k]]++] = (int32_t)k;
+    }
+    s.work_order.resize(K);
+    std::iota(s.work_order.begin(), s.work_order.end(), 0);
+    std::stable_sort(s.work_order.begin(), s.work_order.end(), [&](int32_t a, int32_t b) {
+        return d.sub_ptr[a + 1] - d.sub_ptr[a] > d.sub_ptr[b + 1] - d.sub_ptr[b];
+    });
+}
+
+std::string build_setup(const ddmgnn_problem_desc& d, HostSetup& s) {
+    build_local_graphs(d, s);
+    const int64_t n = d.n_nodes;
+    const int32_t K = d.n_sub;
+
+    // Coarse operator: column j of Z is D_j on sub-mesh j; A_0[i][j] = Z_i^T A Z_j.
+    // For each j, v = A Z_j is accumulated on the rows it touches, then
+    // scattered to A_0[sub(slot)][j] through the membership lists.
+    s.a0.assign((size_t)K * K, 0.0);
+    std::vector<double> v(n, 0.0);
+    std::vector<char> touched(n, 0);
+    std::vector<int32_t> rows;
+    for (int32_t j = 0; j < K; ++j) {
+        rows.clear();
+        for (int64_t k = d.sub_ptr[j]; k < d.sub_ptr[j + 1]; ++k) {
+            int32_t m = d.sub_nodes[k];
+            double w = d.weights[k];
+            if (w == 0.0) continue;
+            // column m of A equals row m (symmetric)
+            for (int32_t e = d.a_rowptr[m]; e < d.a_rowptr[m + 1]; ++e) {
+                int32_t r = d.a_col[e];
+                if (!touched[r]) { touched[r] = 1; rows.push_back(r); }
+                v[r] += d.a_val[e] * w;
+            }
+        }
+        for (int32_t r : rows) {
+            for (int64_t q = s.node_ptr[r]; q < s.node_ptr[r + 1]; ++q) {
+                int32_t slot = s.node_slots[q];
+                s.a0[(size_t)s.slot_sub[slot] * K + j] += d.weights[slot] * v[r];
+            }
+            v[r] = 0.0;
+            touched[r] = 0;
+        }
+    }
+    // Symmetrise exactly (both triangles hold the same value up to rounding order).
+    for (int32_t i = 0; i < K; ++i)
+        for (int32_t j = i + 1; j < K; ++j) {
+            double a = 0.5 * (s.a0[(size_t)i * K + j] + s.a0[(size_t)j * K + i]);
+            s.a0[(size_t)i * K + j] = s.a0[(size_t)j * K + i] = a;
+        }
+    // Cholesky A_0 = L L^T (lower, row-major), then A_0^{-1} = L^{-T} L^{-1}.
+    std::vector<double> L(s.a0);
+    for (int32_t j = 0; j < K; ++j) {
+        double* Lj = &L[(size_t)j * K];
+        double dsum = Lj[j];
+        for (int32_t p = 0; p < j; ++p) dsum -= Lj[p] * Lj[p];
+        if (!(dsum > 0.0) || !std::isfinite(dsum)) return "NOT_SPD";
+        double ljj = std::sqrt(dsum);
+        Lj[j] = ljj;
+        for (int32_t i = j + 1; i < K; ++i) {
+            double* Li = &L[(size_t)i * K];
+            double acc = Li[j];
+            for (int32_t p = 0; p < j; ++p) acc -= Li[p] * Lj[p];
+            Li[j] = acc / ljj;
+        }
+    }
+    // Column j of L^{-1} by forward substitution, stored as row j of LinvT.
+    std::vector<double> LinvT((size_t)K * K, 0.0);
+    for (int32_t j = 0; j < K; ++j) {
+        double* x = &LinvT[(size_t)j * K];
+        x[j] = 1.0 / L[(size_t)j * K + j];
+        for (int32_t i = j + 1; i < K; ++i) {
+            const double* Li = &L[(size_t)i * K];
+            double acc = 0.0;
+            for (int32_t p = j; p < i; ++p) acc += Li[p] * x[p];
+            x[i] = -acc / Li[i];
+        }
+    }
+    // A_0^{-1} = L^{-T} L^{-1}: entry (i, j) = sum_{p >= max(i,j)} Linv[p][i] Linv[p][j].
+    s.a0inv.assign((size_t)K * K, 0.0);
+    for (int32_t i = 0; i < K; ++i) {
+        const double* xi = &LinvT[(size_t)i * K];
+        for (int32_t j = 0; j <= i; ++j) {
+            const double* xj = &LinvT[(size_t)j * K];
+            double acc = 0.0;
+            for (int32_t p = i; p < K; ++p) acc += xi[p] * xj[p];
+            s.a0inv[(size_t)i * K + j] = acc;
+            s.a0inv[(size_t)j * K + i] = acc;
+        }
+    }
+    return "";
+}
+
+}  // namespace ddmgnn

@@ -1,0 +1,15 @@
+"""Shared problem builders for the tests (generator + library host helpers)."""
+import numpy as np
+
+import paper_2402_08296_amd as dg
+import workload as W
+
+
+def host_problem(p, delta=2):
+    return dg.host_problem(p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, p.A.rowptr, p.A.col, p.A.val, p.b, p.u0,
+                           p.part, p.n_parts, delta)
+
+
+def small_problem(seed=5, n=1800, parts=4, jitter=0.2):
+    p = W.make_problem(seed, n, parts, jitter)
+    return p, host_problem(p)

@@ -1,0 +1,118 @@
+"""C ABI on the host: exports, validation, and setup structures against the oracle (no GPU)."""
+import copy
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2402_08296_amd as dg
+import workload as W
+from oracle import decomp as dc
+from tests._cases import small_problem
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "ddmgnn.h")
+
+
+def test_library_exports_every_declared_symbol():
+    L = dg.lib()
+    names = set(re.findall(r"\b(ddmgnn_[a-z_0-9]+)\s*\(", open(HEADER).read()))
+    assert len(names) > 20
+    for name in sorted(names):
+        assert hasattr(L, name), name
+    assert b"gfx950" in L.ddmgnn_version()
+    assert L.ddmgnn_max_subdomain_nodes() == 2048
+
+
+def test_overlap_bitexact_vs_oracle():
+    for seed, n, parts, delta in [(1, 2500, 5, 2), (2, 4000, 9, 1), (3, 3000, 4, 4)]:
+        p = W.make_problem(seed, n, parts, 0.3)
+        ptr, nodes = dg.expand_overlap(p.n, p.mesh.tri, p.part, parts, delta)
+        optr, onodes = dc.expand_overlap(p.n, p.mesh.tri, p.part, parts, delta)
+        assert np.array_equal(ptr, optr) and np.array_equal(nodes, onodes)
+        w = dg.pou_weights(p.n, p.mesh.dirichlet, ptr, nodes)
+        ow = dc.pou_weights(p.n, p.mesh.dirichlet, optr, onodes)
+        assert w.tobytes() == ow.tobytes()
+
+
+def test_local_graphs_bitexact_vs_oracle():
+    p, hp = small_problem()
+    for i in range(hp.K):
+        rowptr, col = dg.setup_local_graph(hp, i)
+        nodes = hp.sub_nodes[hp.sub_ptr[i]:hp.sub_ptr[i + 1]]
+        g = dc.local_graph(nodes, p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
+        recv = np.repeat(np.arange(nodes.size), np.diff(rowptr))
+        assert np.array_equal(recv, g.recv) and np.array_equal(col, g.send)
+
+
+def test_coarse_operator_vs_oracle():
+    p, hp = small_problem()
+    a0, a0inv = dg.setup_coarse(hp)
+    dec = dc.Decomposition(p.n, hp.sub_ptr, hp.sub_nodes, hp.weights)
+    Z = dc.nicolaides_basis(dec)
+    ref = (Z.T @ (p.A.to_scipy() @ Z)).toarray()
+    assert np.abs(a0 - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.abs(a0inv @ ref - np.eye(hp.K)).max() <= 1e-10
+
+
+def _offdiag(h):
+    rows = np.repeat(np.arange(h.n), np.diff(h.rowptr))
+    return int(np.flatnonzero(rows != h.col)[0])
+
+
+def _desc_copy(hp):
+    return copy.deepcopy(hp)
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda h: h.val.__setitem__(_offdiag(h), h.val[_offdiag(h)] + 1.0), "symmetric"),
+    (lambda h: h.col.__setitem__(3, h.n + 7), "out of range"),
+    (lambda h: h.weights.__setitem__(0, h.weights[0] + 0.5) if not h.dirichlet[h.sub_nodes[0]] else
+     h.weights.__setitem__(np.flatnonzero(h.dirichlet[h.sub_nodes] == 0)[0],
+                           h.weights[np.flatnonzero(h.dirichlet[h.sub_nodes] == 0)[0]] + 0.5), "partition of unity"),
+    (lambda h: h.b.__setitem__(10, np.nan), "non-finite"),
+    (lambda h: h.sub_nodes.__setitem__(slice(0, 2), h.sub_nodes[0:2][::-1].copy()), "ascending"),
+    (lambda h: h.dirichlet.__setitem__(0, 2), "0 or 1"),
+])
+def test_validate_rejects(mutate, msg):
+    _, hp = small_problem()
+    dg.validate(hp)
+    bad = _desc_copy(hp)
+    mutate(bad)
+    with pytest.raises(dg.DDMGNNError) as ei:
+        dg.validate(bad)
+    assert ei.value.code == -1 and msg in str(ei.value)
+
+
+def test_validate_rejects_oversized_subdomain_and_uncovered_node():
+    p = W.make_problem(2, 5000, 1)
+    hp = dg.host_problem(p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, p.A.rowptr, p.A.col, p.A.val, p.b, p.u0,
+                         p.part, 1, 0)
+    with pytest.raises(dg.DDMGNNError, match="maximum"):
+        dg.validate(hp)
+    p = W.make_problem(2, 1500, 3)
+    hp = dg.host_problem(p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, p.A.rowptr, p.A.col, p.A.val, p.b, p.u0,
+                         p.part, 3, 1)
+    drop = hp.sub_nodes[hp.sub_ptr[0]:hp.sub_ptr[1]]
+    keep = np.ones(hp.sub_nodes.size, bool)
+    keep[:hp.sub_ptr[1]] = False
+    hp2 = dg.HostProblem(hp.xy, hp.tri, hp.dirichlet, hp.rowptr, hp.col, hp.val, hp.b, hp.u0,
+                         np.concatenate([[0], hp.sub_ptr[2:] - hp.sub_ptr[1]]), hp.sub_nodes[keep], hp.weights[keep])
+    assert drop.size > 0
+    with pytest.raises(dg.DDMGNNError):
+        dg.validate(hp2)
+
+
+def test_setup_detects_singular_coarse():
+    """Two identical sub-meshes make R_0 A R_0^T singular: setup reports E_NOT_SPD."""
+    p, hp = small_problem()
+    sp = np.concatenate([hp.sub_ptr, [hp.sub_ptr[-1] + hp.sub_ptr[1]]])
+    sn = np.concatenate([hp.sub_nodes, hp.sub_nodes[:hp.sub_ptr[1]]])
+    w = np.concatenate([hp.weights, hp.weights[:hp.sub_ptr[1]]])
+    # keep a partition of unity: halve the weights of the duplicated sub-mesh
+    w[:hp.sub_ptr[1]] *= 0.5
+    w[hp.sub_ptr[-1]:] *= 0.5
+    hp2 = dg.HostProblem(hp.xy, hp.tri, hp.dirichlet, hp.rowptr, hp.col, hp.val, hp.b, hp.u0, sp, sn, w)
+    with pytest.raises(dg.DDMGNNError) as ei:
+        dg.setup_coarse(hp2)
+    assert ei.value.code == -4

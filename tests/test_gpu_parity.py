@@ -1,0 +1,257 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Tolerances:
+  * SpMV, dots, FP64 DSS and FP64 applies: reordering of FP64 sums only,
+    relative 1e-12 (DSS) / 1e-13 (linear algebra) of the largest magnitude.
+  * FP32 DSS: one FP32 rounding per operation over 30 blocks; relative 3e-5
+    of the largest output magnitude (measured errors are ~1e-6).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2402_08296_amd as dg  # noqa: E402
+import workload as W  # noqa: E402
+from oracle import decomp as dc, dss, krylov as kr, schwarz as sw  # noqa: E402
+from tests._cases import host_problem, small_problem  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+XAVIER = W.xavier_theta(W.THETA_SEED)
+SMOOTHER = W.smoother_theta(omega=0.15, out_scale=1.7)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float64)).cuda()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("[gpu] creating context", flush=True)
+    return dg.Context()
+
+
+@pytest.fixture(scope="module")
+def c1(ctx):
+    p = W.config_problem("c1", 0)
+    hp = host_problem(p)
+    return p, hp
+
+
+def _oracle_M(p, hp, theta, prolong="pou", coarse=True):
+    dec = dc.Decomposition(p.n, hp.sub_ptr, hp.sub_nodes, hp.weights)
+    return sw.DDMGNN(p.A.to_scipy(), p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, dec, theta, prolong=prolong,
+                     coarse=coarse)
+
+
+def test_spmv_and_dot(ctx):
+    print("[gpu] spmv/dot", flush=True)
+    p, hp = small_problem(seed=11, n=3000, parts=5)
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, XAVIER))
+    x = np.random.default_rng(0).standard_normal(p.n)
+    y = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    prob.spmv(_dev(x), y)
+    ref = p.A.to_scipy() @ x
+    scale = np.abs(p.A.to_scipy()) @ np.abs(x)
+    assert np.all(np.abs(y.cpu().numpy() - ref) <= 1e-14 * scale + 1e-300)
+    for n in [0, 1, 63, 64, 65, 1000, 262_145]:
+        a = np.random.default_rng(n).standard_normal(n)
+        b = np.random.default_rng(n + 1).standard_normal(n)
+        got = ctx.dot(_dev(a), _dev(b))
+        assert abs(got - float(a @ b)) <= 1e-13 * max(1.0, float(np.abs(a) @ np.abs(b)))
+        assert got == ctx.dot(_dev(a), _dev(b))  # deterministic
+
+
+def _c_inputs(p, hp, seed):
+    """Per-slot normalised restrictions c_i = R_i r / |R_i r| of a random residual."""
+    r = np.random.default_rng(seed).standard_normal(p.n)
+    r[p.mesh.dirichlet == 1] = 0
+    c = np.empty(hp.sub_nodes.size)
+    for i in range(hp.K):
+        sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
+        ri = r[hp.sub_nodes[sl]]
+        c[sl] = ri / np.linalg.norm(ri)
+    return c
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5)])
+@pytest.mark.parametrize("theta_name", ["xavier", "smoother"])
+def test_dss_forward_all_subdomains(ctx, c1, prec, tol, theta_name):
+    print(f"[gpu] dss_forward {prec} {theta_name}", flush=True)
+    p, hp = c1
+    theta = XAVIER if theta_name == "xavier" else SMOOTHER
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, theta))
+    c = _c_inputs(p, hp, 1)
+    out = torch.empty(hp.sub_nodes.size, dtype=torch.float64, device="cuda")
+    prob.dss_forward(_dev(c), out, prec)
+    got = out.cpu().numpy()
+    blocks = dss.unpack(theta, 30, 10)
+    worst = 0.0
+    for i in range(hp.K):
+        sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
+        g = dc.local_graph(hp.sub_nodes[sl], p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
+        ref = dss.forward(blocks, g, c[sl], 1e-3, 10)
+        err = np.abs(got[sl] - ref).max() / np.abs(ref).max()
+        worst = max(worst, err)
+    print(f"[gpu]   worst relative error {worst:.3e}", flush=True)
+    assert worst <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5)])
+@pytest.mark.parametrize("prolong", [dg.PROLONG_POU, dg.PROLONG_UNWEIGHTED])
+def test_apply_and_intermediates(ctx, c1, prec, tol, prolong):
+    print(f"[gpu] apply {prec} prolong={prolong}", flush=True)
+    p, hp = c1
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, XAVIER))
+    r = np.random.default_rng(2).standard_normal(p.n)
+    r[p.mesh.dirichlet == 1] = 0
+    z = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    opts = dg.default_opts(precision=prec, prolong=prolong)
+    prob.apply(_dev(r), z, opts)
+    s, y0, y, loc = [t.cpu().numpy() for t in prob.intermediates()]
+    M = _oracle_M(p, hp, XAVIER, "pou" if prolong == dg.PROLONG_POU else "unweighted")
+    ref_z = M(r)
+    # a5: restriction norms and coarse restriction
+    for i in range(hp.K):
+        ri = r[hp.sub_nodes[hp.sub_ptr[i]:hp.sub_ptr[i + 1]]]
+        assert abs(s[i] - np.linalg.norm(ri)) <= 1e-14 * np.linalg.norm(ri)
+    ref_y0 = M.coarse.Z.T @ r
+    assert np.abs(y0 - ref_y0).max() <= 1e-13 * np.abs(r).max() * 100
+    # a6: coarse solve
+    ref_y = np.linalg.solve(M.coarse.A0, y0)
+    assert np.abs(y - ref_y).max() <= 1e-10 * np.abs(ref_y).max()
+    # a7: local terms s_i r~_i
+    for i in range(hp.K):
+        sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
+        si, rt = M.local(i, r)
+        assert np.abs(loc[sl] - si * rt).max() <= tol * np.abs(si * rt).max()
+    # a8: glued z
+    zg = z.cpu().numpy()
+    assert np.all(zg[p.mesh.dirichlet == 1] == 0)
+    assert np.abs(zg - ref_z).max() <= max(tol, 1e-10) * np.abs(ref_z).max()
+
+
+def test_apply_deterministic_and_homogeneous(ctx, c1):
+    print("[gpu] apply determinism", flush=True)
+    p, hp = c1
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, XAVIER))
+    r = np.random.default_rng(3).standard_normal(p.n)
+    r[p.mesh.dirichlet == 1] = 0
+    z1 = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    z2 = torch.empty_like(z1)
+    z3 = torch.empty_like(z1)
+    for prec in ("fp64", "fp32"):
+        o = dg.default_opts(precision=prec)
+        prob.apply(_dev(r), z1, o)
+        prob.apply(_dev(r), z2, o)
+        prob.apply(_dev(8.0 * r), z3, o)
+        assert torch.equal(z1, z2)
+        assert torch.equal(z3, 8.0 * z1)
+
+
+def test_zero_residual_subdomain(ctx, c1):
+    """A sub-mesh with R_i r = 0 contributes nothing (s_i = 0 branch)."""
+    p, hp = c1
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, XAVIER))
+    r = np.zeros(p.n)
+    only0 = np.setdiff1d(hp.sub_nodes[:hp.sub_ptr[1]], hp.sub_nodes[hp.sub_ptr[1]:])
+    only0 = only0[p.mesh.dirichlet[only0] == 0]
+    r[only0[:10]] = 1.0
+    z = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    prob.apply(_dev(r), z, dg.default_opts(precision="fp64"))
+    s, _, _, loc = [t.cpu().numpy() for t in prob.intermediates()]
+    assert s[0] > 0 and np.all(s[1:] == 0)
+    assert np.all(loc[hp.sub_ptr[1]:] == 0)
+    ref = _oracle_M(p, hp, XAVIER)(r)
+    assert np.abs(z.cpu().numpy() - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_solve_fp64_matches_oracle(ctx, c1):
+    print("[gpu] solve fp64", flush=True)
+    p, hp = c1
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, SMOOTHER))
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    st = prob.solve(u, dg.default_opts(precision="fp64", rtol=1e-10))
+    ref = kr.fcg(p.A.to_scipy(), p.b, p.u0, _oracle_M(p, hp, SMOOTHER), 1e-10, max_it=2000)
+    print(f"[gpu]   iterations gpu={st.iterations} oracle={ref.iterations} "
+          f"true_rel={st.true_rel_residual:.2e}", flush=True)
+    assert st.converged and abs(st.iterations - ref.iterations) <= 1
+    assert st.true_rel_residual <= 2e-10
+    ug = u.cpu().numpy()
+    assert np.linalg.norm(ug - ref.u) / np.linalg.norm(ref.u) <= 1e-6
+    import scipy.sparse.linalg as spl
+    ud = spl.spsolve(p.A.to_scipy().tocsc(), p.b)
+    assert np.linalg.norm(ug - ud) / np.linalg.norm(ud) <= 1e-6
+
+
+def test_solve_fp32_converges_to_tolerance(ctx, c1):
+    print("[gpu] solve fp32", flush=True)
+    p, hp = c1
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, SMOOTHER))
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    st = prob.solve(u, dg.default_opts(precision="fp32", rtol=1e-6))
+    ref = kr.fcg(p.A.to_scipy(), p.b, p.u0, _oracle_M(p, hp, SMOOTHER), 1e-6, max_it=2000)
+    print(f"[gpu]   iterations gpu={st.iterations} oracle={ref.iterations}", flush=True)
+    assert st.converged and st.true_rel_residual <= 1.5e-6
+    assert abs(st.iterations - ref.iterations) <= max(2, 0.1 * ref.iterations)
+
+
+def test_krylov_modes(ctx, c1):
+    print("[gpu] cg/pcg", flush=True)
+    p, hp = c1
+    A = p.A.to_scipy()
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, SMOOTHER))
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    st = prob.solve(u, dg.default_opts(krylov=dg.CG, rtol=1e-6))
+    ref = kr.cg(A, p.b, p.u0, 1e-6)
+    assert st.converged and abs(st.iterations - ref.iterations) <= 1
+    # Algorithm 1 needs a symmetric positive definite M: unweighted glue and a
+    # Richardson step with omega * lambda_max(L) < 2 give one.
+    spd = W.smoother_theta(omega=0.08)
+    prob_spd = dg.Problem(ctx, hp, dg.Model(ctx, spd))
+    st = prob_spd.solve(u, dg.default_opts(krylov=dg.PCG, precision="fp64", rtol=1e-8,
+                                           prolong=dg.PROLONG_UNWEIGHTED, max_it=500))
+    ref = kr.pcg(A, p.b, p.u0, _oracle_M(p, hp, spd, prolong="unweighted"), 1e-8, max_it=500)
+    assert ref.converged and st.converged and abs(st.iterations - ref.iterations) <= 1
+    st = prob.solve(u, dg.default_opts(m_max=3, precision="fp64", rtol=1e-8))
+    ref = kr.fcg(A, p.b, p.u0, _oracle_M(p, hp, SMOOTHER), 1e-8, m_max=3)
+    assert st.converged and abs(st.iterations - ref.iterations) <= 1
+
+
+def test_xavier_history_matches_oracle(ctx, c1):
+    """The seeded (untrained) model stagnates; the GPU recurrence tracks the oracle's."""
+    print("[gpu] xavier history", flush=True)
+    p, hp = c1
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, XAVIER))
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    st = prob.solve(u, dg.default_opts(precision="fp64", max_it=15), check=False)
+    ref = kr.fcg(p.A.to_scipy(), p.b, p.u0, _oracle_M(p, hp, XAVIER), 1e-6, max_it=15)
+    assert st.status == -6 and st.iterations == 15
+    assert abs(st.rel_residual - ref.history[-1]) <= 1e-8 * ref.history[-1]
+    assert np.linalg.norm(u.cpu().numpy() - ref.u) <= 1e-8 * np.linalg.norm(ref.u)
+
+
+def test_zero_rhs_and_large_subdomain(ctx):
+    print("[gpu] edge cases", flush=True)
+    # a single sub-mesh close to the size limit exercises the global-Q FP64 path
+    p = W.make_problem(31, 1900, 1)
+    hp = host_problem(p, delta=0)
+    assert hp.sub_ptr[1] <= 2048
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, XAVIER))
+    c = _c_inputs(p, hp, 5)
+    blocks = dss.unpack(XAVIER, 30, 10)
+    g = dc.local_graph(hp.sub_nodes, p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
+    ref = dss.forward(blocks, g, c, 1e-3, 10)
+    out = torch.empty(hp.sub_nodes.size, dtype=torch.float64, device="cuda")
+    for prec, tol in (("fp64", 1e-12), ("fp32", 3e-5)):
+        prob.dss_forward(_dev(c), out, prec)
+        assert np.abs(out.cpu().numpy() - ref).max() <= tol * np.abs(ref).max()
+    # b = A u0: the initial residual is zero, nothing to do
+    hp0 = dg.HostProblem(hp.xy, hp.tri, hp.dirichlet, hp.rowptr, hp.col, hp.val, p.A.to_scipy() @ p.u0, p.u0,
+                         hp.sub_ptr, hp.sub_nodes, hp.weights)
+    prob0 = dg.Problem(ctx, hp0, dg.Model(ctx, XAVIER))
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    st = prob0.solve(u)
+    assert st.converged and st.iterations == 0
+    assert torch.equal(u.cpu(), torch.from_numpy(p.u0))
