@@ -145,6 +145,7 @@ typedef struct {
     int32_t prolong;     /* DDMGNN_PROLONG_POU / UNWEIGHTED */
     int32_t coarse;      /* 1: add the coarse correction (step 1), 0: one-level */
     int32_t check_every; /* iterations between host checks of the converged flag */
+    int32_t profile;     /* 1: time every stage with HIP events on the context stream */
 } ddmgnn_solve_opts;
 
 typedef struct {
@@ -153,6 +154,13 @@ typedef struct {
     double rel_residual;       /* |r_it| / |r_0| of the recurrence */
     double true_rel_residual;  /* |b - A u| / |r_0| recomputed at exit */
     double solve_ms;           /* device time of the whole solve (HIP events) */
+    /* Filled when opts.profile = 1 (HIP event pairs around each launch of the
+     * iterations that did work): */
+    int32_t dss_launches;      /* DSS forward launches timed */
+    double dss_ms;             /* total time of the DSS forward kernel (steps 2 with restriction) */
+    double coarse_ms;          /* coarse solve (step 1) */
+    double prolong_ms;         /* gluing (step 3) with its fused dot products */
+    double krylov_ms;          /* direction update, SpMV with dots, solution update */
 } ddmgnn_stats;
 
 /* Fill opts with defaults (FCG, m_max 1, rtol 1e-6, max_it 10000, FP32, POU, coarse on). */

@@ -44,12 +44,13 @@ class ProblemDesc(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("krylov", _i32), ("m_max", _i32), ("rtol", _f64), ("max_it", _i32), ("precision", _i32),
-                ("prolong", _i32), ("coarse", _i32), ("check_every", _i32)]
+                ("prolong", _i32), ("coarse", _i32), ("check_every", _i32), ("profile", _i32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("converged", _i32), ("rel_residual", _f64),
-                ("true_rel_residual", _f64), ("solve_ms", _f64)]
+                ("true_rel_residual", _f64), ("solve_ms", _f64), ("dss_launches", _i32), ("dss_ms", _f64),
+                ("coarse_ms", _f64), ("prolong_ms", _f64), ("krylov_ms", _f64)]
 
 
 _lib = None

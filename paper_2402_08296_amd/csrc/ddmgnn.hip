@@ -728,16 +728,19 @@ int launch_dss(ddmgnn_problem* P, int precision, bool apply, const double* r, co
 }
 
 // Enqueue one preconditioner apply z = M(r) with the Krylov dots of `mode`.
+// ev (optional): events recorded after the DSS (ev[1]), coarse (ev[2]) and prolong (ev[3]) launches.
 int enqueue_apply(ddmgnn_problem* P, const ddmgnn_solve_opts& o, const double* r, double* z, int mode,
-                  double* const* qk, const int* pslot, int m, KState* st) {
+                  double* const* qk, const int* pslot, int m, KState* st, hipEvent_t* ev = nullptr) {
     int rc = launch_dss(P, o.precision, true, r, nullptr, P->local.p, st);
     if (rc) return rc;
     hipStream_t s = P->ctx->stream;
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     const int K = P->hs.K;
     if (o.coarse) {
         hipLaunchKernelGGL(coarse_kernel, dim3((K + 3) / 4), dim3(VEC_BLOCK), 0, s, P->a0inv.p, P->y0.p, P->y.p, K,
                            st);
     }
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     ProlongArgs a{};
     a.node_ptr = P->node_ptr.p; a.node_slots = P->node_slots.p; a.slot_sub = P->slot_sub.p;
     a.weights = P->weights.p; a.local = P->local.p; a.y = o.coarse ? P->y.p : nullptr;
@@ -750,6 +753,7 @@ int enqueue_apply(ddmgnn_problem* P, const ddmgnn_solve_opts& o, const double* r
     a.partials = P->partials.p; a.counter = P->counters.p; a.st = st;
     hipLaunchKernelGGL(prolong_kernel, dim3(vec_grid(P->hs.n)), dim3(VEC_BLOCK), 0, s, a);
     HIP_TRY(hipGetLastError());
+    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     return DDMGNN_OK;
 }
 
@@ -781,6 +785,7 @@ void ddmgnn_default_opts(ddmgnn_solve_opts* o) {
     o->prolong = DDMGNN_PROLONG_POU;
     o->coarse = 1;
     o->check_every = 8;
+    o->profile = 0;
 }
 
 int ddmgnn_ctx_create(void* hip_stream, ddmgnn_ctx** out) {
@@ -1041,10 +1046,22 @@ int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* op
     HIP_TRY(hipGetLastError());
     KState host_state{};
     const int check = std::max(1, o.check_every);
+    // Profiling: 5 events per iteration of a chunk (before DSS, after DSS,
+    // after coarse, after prolong, after the Krylov kernels).
+    std::vector<hipEvent_t> pev;
+    if (o.profile) {
+        pev.resize((size_t)check * 5);
+        for (auto& e : pev) HIP_TRY(hipEventCreate(&e));
+    }
+    double t_dss = 0, t_coarse = 0, t_prolong = 0, t_krylov = 0;
+    int n_dss = 0;
     int it = 0;
     bool done = false;
     while (!done) {
-        for (int c = 0; c < check && it < o.max_it; ++c, ++it) {
+        const int it_chunk0 = it;
+        int n_chunk = 0;
+        for (int c = 0; c < check && it < o.max_it; ++c, ++it, ++n_chunk) {
+            hipEvent_t* ev = o.profile ? &pev[(size_t)c * 5] : nullptr;
             // ring slots: new direction goes to slot it % nring; previous ones are
             // it-1, ..., it-m (their q vectors in the same slots).
             const int cur = it % nring;
@@ -1058,10 +1075,13 @@ int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* op
                 prev_slot[kk] = sl;
             }
             const double* zsrc = P->z.p;
+            if (ev) HIP_TRY(hipEventRecord(ev[0], s));
             if (mode == DDMGNN_CG) {
                 zsrc = P->r.p;
+                if (ev)
+                    for (int q = 1; q < 4; ++q) HIP_TRY(hipEventRecord(ev[q], s));
             } else {
-                rc = enqueue_apply(P, o, P->r.p, P->z.p, mode, prev_q, prev_slot, m, P->st.p);
+                rc = enqueue_apply(P, o, P->r.p, P->z.p, mode, prev_q, prev_slot, m, P->st.p, ev);
                 if (rc) return rc;
             }
             hipLaunchKernelGGL(pupdate_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, zsrc, pv[cur], prev_p[0], prev_p[1],
@@ -1071,12 +1091,31 @@ int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* op
             hipLaunchKernelGGL(update_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, P->u.p, P->r.p, pv[cur], qv[cur],
                                (int)n, mode, P->partials.p, P->counters.p, P->st.p);
             HIP_TRY(hipGetLastError());
+            if (ev) HIP_TRY(hipEventRecord(ev[4], s));
         }
         HIP_TRY(hipMemcpyAsync(ctx->host_pinned, P->st.p, sizeof(KState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         std::memcpy(&host_state, ctx->host_pinned, sizeof(KState));
         done = host_state.done || it >= o.max_it;
+        if (o.profile) {
+            // iterations it_chunk0 .. host_state.it-1 did work; later ones exited early
+            const int worked = std::min(n_chunk, std::max(0, host_state.it - it_chunk0));
+            for (int c = 0; c < worked; ++c) {
+                hipEvent_t* ev = &pev[(size_t)c * 5];
+                float a = 0, b = 0, cc = 0, d = 0;
+                HIP_TRY(hipEventElapsedTime(&a, ev[0], ev[1]));
+                HIP_TRY(hipEventElapsedTime(&b, ev[1], ev[2]));
+                HIP_TRY(hipEventElapsedTime(&cc, ev[2], ev[3]));
+                HIP_TRY(hipEventElapsedTime(&d, ev[3], ev[4]));
+                t_dss += a;
+                t_coarse += b;
+                t_prolong += cc;
+                t_krylov += d;
+                if (mode != DDMGNN_CG) ++n_dss;
+            }
+        }
     }
+    for (auto& e : pev) (void)hipEventDestroy(e);
     HIP_TRY(hipEventRecord(ev1, s));
     // true residual |b - A u| / |r_0|
     hipLaunchKernelGGL(resid_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, P->rowptr.p, P->col.p, P->val.p, P->b.p,
@@ -1096,6 +1135,11 @@ int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* op
         stats->rel_residual = host_state.rel;
         stats->true_rel_residual = host_state.r0n > 0 ? std::sqrt(tr) / host_state.r0n : 0.0;
         stats->solve_ms = ms;
+        stats->dss_launches = n_dss;
+        stats->dss_ms = t_dss;
+        stats->coarse_ms = t_coarse;
+        stats->prolong_ms = t_prolong;
+        stats->krylov_ms = t_krylov;
     }
     if (host_state.status) return fail(host_state.status, "Krylov breakdown or non-finite residual");
     if (!host_state.done) return fail(DDMGNN_E_MAXIT, "not converged within max_it");

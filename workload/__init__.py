@@ -262,8 +262,8 @@ def xavier_theta(seed: int, kbar: int = 30, d: int = 10) -> np.ndarray:
 # few percent because the mesh is clipped to the polygon.
 CONFIGS = {
     "c1": dict(target_nodes=5_000, n_parts=8, jitter=0.0, seeds=list(range(10))),
-    "c2": dict(target_nodes=100_000, n_parts=150, jitter=0.2, seeds=list(range(100, 105))),
-    "c3": dict(target_nodes=1_000_000, n_parts=1500, jitter=0.35, seeds=[1000, 1001, 1002]),
+    "c2": dict(target_nodes=100_000, n_parts=150, jitter=0.15, seeds=list(range(100, 105))),
+    "c3": dict(target_nodes=1_000_000, n_parts=1500, jitter=0.12, seeds=[1000, 1001, 1002]),
 }
 THETA_SEED = 42
 
