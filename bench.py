@@ -23,7 +23,7 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector peaks
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 157.3}   # MI355X FP32/FP64 vector peaks
 HBM_GBPS = 8000.0
 
 
@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--theta", default="smoother", choices=["smoother", "xavier"])
     ap.add_argument("--cpu-sample", type=int, default=160, help="sub-meshes in the oracle sample (0: skip)")
     args = ap.parse_args()
@@ -172,7 +172,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "fp32" else "f64",
+        "dtype": {"bf16": "bf16+f32+f64", "fp32": "f32+f64", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: P1-FEM Poisson on a Delaunay mesh of a star polygon, "
                                f"N={p.n}, K={hp.K} sub-meshes (overlap 2), sum k_i={hp.sub_nodes.size}, "

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "ddmgnn.h"
+#include "dss_mfma.h"
 #include "setup.h"
 
 namespace {
@@ -138,7 +139,8 @@ struct DssArgs {
     const int32_t* work_order;
     const int32_t* edge_ptr;
     const uint16_t* edge_src;
-    const T* xy;              // per slot (x, y)
+    const T* xy;              // per slot (x, y); centred on the sub-mesh when SEP
+    const float* edge_nd;     // per edge |d_jl| (SEP); padded by 8 entries
     const T* theta;           // kbar blocks of BLOCK_W
     const int32_t* sub_nodes;
     const double* weights;
@@ -164,15 +166,22 @@ __device__ inline double relu(double x) { return fmax(x, 0.0); }
 // whose register footprint would spill).
 // theta is a separate __restrict__ parameter so the compiler can prove the
 // weight loads uniform and unclobbered and read them through the scalar cache.
-template <typename T, bool HREG>
+// QLDS: Q lives in LDS (compile-time, so its accesses are ds_* rather than flat).
+// SEP: the coordinate part of the message first layer is split per node,
+// W1_d d_jl = W1_d x_l - W1_d x_j, and added to the projections (P and Q then
+// carry it), so an edge only adds w_|d| |d_jl|; coordinates are centred on the
+// sub-mesh to keep the cancellation small. Used for FP32; the FP64 path
+// evaluates W1_d d_jl per edge.
+template <typename T, bool HREG, bool QLDS>
 __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* __restrict__ theta) {
+    constexpr bool SEP = sizeof(T) == 4;
     if (a.st && a.st->done) return;
     extern __shared__ unsigned char dyn_smem[];
     __shared__ double red[DSS_BLOCK / 64 + 1];
     const int sub = a.work_order[blockIdx.x];
     const int base = a.sub_ptr[sub];
     const int k = a.sub_ptr[sub + 1] - base;
-    T* Q = a.q_in_lds ? reinterpret_cast<T*>(dyn_smem) : a.qglobal + (size_t)base * 2 * D;
+    T* Q = QLDS ? reinterpret_cast<T*>(dyn_smem) : a.qglobal + (size_t)base * 2 * D;
     const int tid = threadIdx.x;
 
     T c[DSS_NPT];
@@ -244,9 +253,14 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
                 T h[D];
 #pragma unroll
                 for (int v = 0; v < D; ++v) h[v] = HREG ? hreg[HREG ? t : 0][v] : hg[j * D + v];
+                const T xl = a.xy[2 * (base + j)], yl = a.xy[2 * (base + j) + 1];
 #pragma unroll
                 for (int u = 0; u < D; ++u) {
                     T qo = (T)0, qi = (T)0;
+                    if (SEP) {  // Q_out += W1_d x_l, Q_in -= W1_d x_l (d_lj = -d_jl)
+                        qo = fma(Wo[u * IN_PHI + 2 * D], xl, fma(Wo[u * IN_PHI + 2 * D + 1], yl, qo));
+                        qi = -fma(Wi[u * IN_PHI + 2 * D], xl, Wi[u * IN_PHI + 2 * D + 1] * yl);
+                    }
 #pragma unroll
                     for (int v = 0; v < D; ++v) {
                         qo = fma(Wo[u * IN_PHI + D + v], h[v], qo);
@@ -282,25 +296,58 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
                     si[u] = (T)0;
                 }
                 const T xj = a.xy[2 * (base + j)], yj = a.xy[2 * (base + j) + 1];
-                const int e0 = a.edge_ptr[base + j], e1 = a.edge_ptr[base + j + 1];
-                for (int e = e0; e < e1; ++e) {
-                    const int l = a.edge_src[e];
-                    const T dx = a.xy[2 * (base + l)] - xj;
-                    const T dy = a.xy[2 * (base + l) + 1] - yj;
-                    const T nr = sqrt(dx * dx + dy * dy);
-                    const T* ql = Q + l * 2 * D;
+                if (SEP) {
 #pragma unroll
                     for (int u = 0; u < D; ++u) {
-                        T vo = po[u] + ql[u];
-                        vo = fma(Wo[u * IN_PHI + 2 * D], dx, vo);
-                        vo = fma(Wo[u * IN_PHI + 2 * D + 1], dy, vo);
-                        vo = fma(Wo[u * IN_PHI + 2 * D + 2], nr, vo);
-                        so[u] += relu(vo);
-                        T vi = pi[u] + ql[D + u];
-                        vi = fma(Wi[u * IN_PHI + 2 * D], -dx, vi);
-                        vi = fma(Wi[u * IN_PHI + 2 * D + 1], -dy, vi);
-                        vi = fma(Wi[u * IN_PHI + 2 * D + 2], nr, vi);
-                        si[u] += relu(vi);
+                        po[u] = po[u] - fma(Wo[u * IN_PHI + 2 * D], xj, Wo[u * IN_PHI + 2 * D + 1] * yj);
+                        pi[u] = fma(Wi[u * IN_PHI + 2 * D], xj, fma(Wi[u * IN_PHI + 2 * D + 1], yj, pi[u]));
+                    }
+                }
+                const int e0 = a.edge_ptr[base + j], e1 = a.edge_ptr[base + j + 1];
+                // Edges in chunks of 4: the chunk's loads are issued before any
+                // use (the edge arrays are padded, so reads past e1 stay in bounds).
+                for (int e = e0; e < e1; e += 4) {
+                    int ls[4];
+                    T ex[4], ey[4];
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        ls[w] = a.edge_src[e + w];
+                        if (SEP) {
+                            ex[w] = (T)a.edge_nd[e + w];
+                        } else {
+                            const int lw = e + w < e1 ? ls[w] : j;
+                            ex[w] = a.xy[2 * (base + lw)] - xj;
+                            ey[w] = a.xy[2 * (base + lw) + 1] - yj;
+                        }
+                    }
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        if (e + w >= e1) break;
+                        const T* ql = Q + ls[w] * 2 * D;
+                        if (SEP) {
+                            const T nr = ex[w];
+#pragma unroll
+                            for (int u = 0; u < D; ++u) {
+                                so[u] += relu(fma(Wo[u * IN_PHI + 2 * D + 2], nr, po[u] + ql[u]));
+                                si[u] += relu(fma(Wi[u * IN_PHI + 2 * D + 2], nr, pi[u] + ql[D + u]));
+                            }
+                        } else {
+                            const T dx = ex[w], dy = ey[w];
+                            const T nr = sqrt(dx * dx + dy * dy);
+#pragma unroll
+                            for (int u = 0; u < D; ++u) {
+                                T vo = po[u] + ql[u];
+                                vo = fma(Wo[u * IN_PHI + 2 * D], dx, vo);
+                                vo = fma(Wo[u * IN_PHI + 2 * D + 1], dy, vo);
+                                vo = fma(Wo[u * IN_PHI + 2 * D + 2], nr, vo);
+                                so[u] += relu(vo);
+                                T vi = pi[u] + ql[D + u];
+                                vi = fma(Wi[u * IN_PHI + 2 * D], -dx, vi);
+                                vi = fma(Wi[u * IN_PHI + 2 * D + 1], -dy, vi);
+                                vi = fma(Wi[u * IN_PHI + 2 * D + 2], nr, vi);
+                                si[u] += relu(vi);
+                            }
+                        }
                     }
                 }
                 const T deg = (T)(e1 - e0);
@@ -652,6 +699,8 @@ struct ddmgnn_model {
     int kbar = 0, d = 0;
     double alpha = 0;
     std::vector<float> theta;
+    std::vector<ddmgnn::MfmaLane> mfma_lanes;  // per block, per lane A operands and constants
+    std::vector<ddmgnn::MfmaDec> mfma_dec;
 };
 
 struct ddmgnn_problem {
@@ -667,9 +716,13 @@ struct ddmgnn_problem {
     DevBuf<int32_t> sub_ptr, sub_nodes, work_order, edge_ptr, node_ptr, node_slots, slot_sub;
     DevBuf<uint16_t> edge_src;
     DevBuf<double> weights, xy64, a0inv;
-    DevBuf<float> xy32;
+    DevBuf<float> xyc32;  // per slot, centred on the sub-mesh
     DevBuf<float> theta32;
     DevBuf<double> theta64;
+    DevBuf<ddmgnn::MfmaLane> mfma_lanes;
+    DevBuf<ddmgnn::MfmaDec> mfma_dec;
+    DevBuf<uint16_t> tnode, xyhl;
+    DevBuf<float> edge_nd;
     // apply buffers
     DevBuf<double> s, y0, y, local;
     DevBuf<double> qglobal64, hglobal64;
@@ -689,7 +742,21 @@ int launch_dss(ddmgnn_problem* P, int precision, bool apply, const double* r, co
                const KState* st) {
     hipStream_t s = P->ctx->stream;
     const int K = P->hs.K;
-    if (precision == DDMGNN_BF16) return fail(DDMGNN_E_INVALID, "BF16 DSS path not available in this build");
+    if (precision == DDMGNN_BF16) {
+        const size_t need = ddmgnn::mfma_lds_bytes(P->hs.max_k);
+        const bool in_lds = need + 1024 <= LDS_LIMIT;
+        if (!in_lds && P->qglobal32.n < (size_t)P->hs.sk * 2 * D) HIP_TRY(P->qglobal32.alloc((size_t)P->hs.sk * 2 * D));
+        ddmgnn::DssMfmaArgs a{};
+        a.sub_ptr = P->sub_ptr.p; a.work_order = P->work_order.p; a.edge_ptr = P->edge_ptr.p;
+        a.edge_src = P->edge_src.p; a.edge_nd = P->edge_nd.p; a.tnode = P->tnode.p; a.xyhl = P->xyhl.p;
+        a.sub_nodes = P->sub_nodes.p; a.weights = P->weights.p; a.r = r; a.c_in = c_in; a.out = out;
+        a.s_out = P->s.p; a.y0_out = P->y0.p; a.qglobal = P->qglobal32.p; a.done = st ? &st->done : nullptr;
+        a.lanes = P->mfma_lanes.p; a.dec = P->mfma_dec.p; a.kbar = P->kbar; a.alpha = (float)P->alpha;
+        a.apply = apply; a.q_in_lds = in_lds;
+        const size_t shmem = in_lds ? need : (size_t)P->hs.max_k * sizeof(float);
+        HIP_TRY(ddmgnn::launch_dss_mfma(a, K, shmem, s));
+        return DDMGNN_OK;
+    }
     const bool f64 = precision == DDMGNN_FP64;
     const size_t esz = f64 ? sizeof(double) : sizeof(float);
     const size_t need = (size_t)P->hs.max_k * 2 * D * esz;
@@ -707,21 +774,32 @@ int launch_dss(ddmgnn_problem* P, int precision, bool apply, const double* r, co
         a.weights = P->weights.p; a.r = r; a.c_in = c_in; a.out = out; a.s_out = P->s.p; a.y0_out = P->y0.p;
         a.qglobal = P->qglobal64.p; a.hglobal = P->hglobal64.p; a.st = st; a.kbar = P->kbar; a.alpha = P->alpha;
         a.apply = apply; a.q_in_lds = in_lds;
-        HIP_TRY(hipFuncSetAttribute((const void*)dss_kernel<double, false>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-        hipLaunchKernelGGL((dss_kernel<double, false>), dim3(K), dim3(DSS_BLOCK), shmem, s, a,
-                           (const double*)P->theta64.p);
+        if (in_lds) {
+            HIP_TRY(hipFuncSetAttribute((const void*)dss_kernel<double, false, true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+            hipLaunchKernelGGL((dss_kernel<double, false, true>), dim3(K), dim3(DSS_BLOCK), shmem, s, a,
+                               (const double*)P->theta64.p);
+        } else {
+            hipLaunchKernelGGL((dss_kernel<double, false, false>), dim3(K), dim3(DSS_BLOCK), 0, s, a,
+                               (const double*)P->theta64.p);
+        }
     } else {
         DssArgs<float> a{};
         a.sub_ptr = P->sub_ptr.p; a.work_order = P->work_order.p; a.edge_ptr = P->edge_ptr.p;
-        a.edge_src = P->edge_src.p; a.xy = P->xy32.p; a.theta = P->theta32.p; a.sub_nodes = P->sub_nodes.p;
+        a.edge_src = P->edge_src.p; a.xy = P->xyc32.p; a.edge_nd = P->edge_nd.p; a.theta = P->theta32.p;
+        a.sub_nodes = P->sub_nodes.p;
         a.weights = P->weights.p; a.r = r; a.c_in = c_in; a.out = out; a.s_out = P->s.p; a.y0_out = P->y0.p;
         a.qglobal = P->qglobal32.p; a.hglobal = nullptr; a.st = st; a.kbar = P->kbar; a.alpha = (float)P->alpha;
         a.apply = apply; a.q_in_lds = in_lds;
-        HIP_TRY(hipFuncSetAttribute((const void*)dss_kernel<float, true>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-        hipLaunchKernelGGL((dss_kernel<float, true>), dim3(K), dim3(DSS_BLOCK), shmem, s, a,
-                           (const float*)P->theta32.p);
+        if (in_lds) {
+            HIP_TRY(hipFuncSetAttribute((const void*)dss_kernel<float, true, true>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+            hipLaunchKernelGGL((dss_kernel<float, true, true>), dim3(K), dim3(DSS_BLOCK), shmem, s, a,
+                               (const float*)P->theta32.p);
+        } else {
+            hipLaunchKernelGGL((dss_kernel<float, true, false>), dim3(K), dim3(DSS_BLOCK), 0, s, a,
+                               (const float*)P->theta32.p);
+        }
     }
     HIP_TRY(hipGetLastError());
     return DDMGNN_OK;
@@ -825,6 +903,7 @@ int ddmgnn_model_create(ddmgnn_ctx* ctx, const ddmgnn_model_desc* desc, const fl
     m->d = desc->d;
     m->alpha = desc->alpha;
     m->theta.assign(theta, theta + n_theta);
+    ddmgnn::build_mfma_blobs(m->theta.data(), m->kbar, m->mfma_lanes, m->mfma_dec);
     *out = m.release();
     return DDMGNN_OK;
 }
@@ -872,27 +951,41 @@ int ddmgnn_problem_create(ddmgnn_ctx* ctx, const ddmgnn_problem_desc* desc, cons
     std::vector<int32_t> ep32(sk + 1);
     for (int64_t i = 0; i <= sk; ++i) ep32[i] = (int32_t)hs.edge_ptr[i];
     HIP_TRY(P->edge_ptr.upload(ep32.data(), sk + 1, s));
-    HIP_TRY(P->edge_src.upload(hs.edge_src.data(), hs.edge_src.size(), s));
+    {
+        // padded by 8 entries: the chunked edge loops read up to 3 past a node's last edge
+        std::vector<uint16_t> src(hs.edge_src);
+        src.resize(src.size() + 8, 0);
+        HIP_TRY(P->edge_src.upload(src.data(), src.size(), s));
+    }
     std::vector<int32_t> np32(n + 1);
     for (int64_t i = 0; i <= n; ++i) np32[i] = (int32_t)hs.node_ptr[i];
     HIP_TRY(P->node_ptr.upload(np32.data(), n + 1, s));
     HIP_TRY(P->node_slots.upload(hs.node_slots.data(), sk, s));
     HIP_TRY(P->slot_sub.upload(hs.slot_sub.data(), sk, s));
     std::vector<double> xy64(2 * sk);
-    std::vector<float> xy32(2 * sk);
+    std::vector<float> xyc32(2 * sk);
     for (int64_t k = 0; k < sk; ++k) {
         const int32_t v = desc->sub_nodes[k];
         xy64[2 * k] = desc->xy[2 * v];
         xy64[2 * k + 1] = desc->xy[2 * v + 1];
-        xy32[2 * k] = (float)xy64[2 * k];
-        xy32[2 * k + 1] = (float)xy64[2 * k + 1];
+        xyc32[2 * k] = (float)hs.xyc[2 * k];
+        xyc32[2 * k + 1] = (float)hs.xyc[2 * k + 1];
     }
     HIP_TRY(P->xy64.upload(xy64.data(), 2 * sk, s));
-    HIP_TRY(P->xy32.upload(xy32.data(), 2 * sk, s));
+    HIP_TRY(P->xyc32.upload(xyc32.data(), 2 * sk, s));
     HIP_TRY(P->a0inv.upload(hs.a0inv.data(), (size_t)K * K, s));
     std::vector<double> th64(model->theta.begin(), model->theta.end());
     HIP_TRY(P->theta32.upload(model->theta.data(), model->theta.size(), s));
     HIP_TRY(P->theta64.upload(th64.data(), th64.size(), s));
+    HIP_TRY(P->mfma_lanes.upload(model->mfma_lanes.data(), model->mfma_lanes.size(), s));
+    HIP_TRY(P->mfma_dec.upload(model->mfma_dec.data(), model->mfma_dec.size(), s));
+    HIP_TRY(P->tnode.upload(hs.tnode.data(), hs.tnode.size(), s));
+    HIP_TRY(P->xyhl.upload(hs.xyhl.data(), hs.xyhl.size(), s));
+    {
+        std::vector<float> nd(hs.edge_nd);
+        nd.resize(nd.size() + 8, 0.0f);
+        HIP_TRY(P->edge_nd.upload(nd.data(), nd.size(), s));
+    }
     HIP_TRY(P->s.alloc(K));
     HIP_TRY(P->y0.alloc(K));
     HIP_TRY(P->y.alloc(K));

@@ -1,0 +1,439 @@
+// DSS_theta forward pass (Sec. III.B, eqs. (14)-(18)) with the dense MLP
+// layers on BF16 MFMA and FP32 accumulation.
+//
+// Layout. A wavefront processes tiles of 32 nodes: the nodes are the N
+// dimension of v_mfma_f32_32x32x16_bf16, the features the M and K dimensions.
+// Lane l serves node (l % 32) of the tile and half hf = l / 32. An MFMA output
+// row r lands in item 4*(r/8) + r%4 of the lanes with hf = (r/4)%2, and a B
+// operand lane holds the 8 consecutive K entries 8*hf..8*hf+7, so a layer's
+// output items feed the next layer's B operand without moving data between
+// lanes once the weight rows and columns are permuted to match (done on the
+// host in build_mfma_blobs). Half hf of a node holds:
+//   * latent components 5*hf .. 5*hf+4 of h (FP32, registers, all kbar blocks);
+//   * message units 0..9 of direction hf (hf = 0: Phi_out, hf = 1: Phi_in).
+//
+// One block k:
+//   Q'_l = W1[:, h_l] h_l + W1[:, d] x_l        (per node, MFMA; stored to LDS in FP32)
+//   P'_j = W1[:, h_j] h_j + b1 - W1[:, d] x_j    (per node, MFMA)
+//   S_j  = sum_{l in N(j)} ReLU(P'_j + Q'_l + w_|d| |d_jl|)   (per edge, VALU)
+// which equals sum_l ReLU(W1 (h_j, h_l, d_jl, |d_jl|) + b1) because d_jl =
+// x_l - x_j (for Phi_in the signs of the coordinate terms flip, d_lj = -d_jl).
+// Coordinates enter the MFMA as bf16 hi/lo pairs of sub-mesh-centred values,
+// so the large per-node terms cancel to FP32 accuracy in P' + Q'. Then
+//   hid = ReLU(W1_psi (h, c, phi_out, phi_in) + b1_psi) with phi = W2 S + deg b2
+// is one MFMA chain over (h, 1, c, deg) and S (the second message layers are
+// folded into W1_psi on the host), and h += alpha (W2_psi hid + b2_psi).
+#include "dss_mfma.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace ddmgnn {
+
+namespace {
+
+constexpr int D = 10;
+constexpr int IN_PHI = 2 * D + 3;
+constexpr int IN_PSI = 3 * D + 1;
+constexpr int OFF_PO = 0;
+constexpr int OFF_PI = OFF_PO + D * IN_PHI + D + D * D + D;
+constexpr int OFF_PS = OFF_PI + D * IN_PHI + D + D * D + D;
+constexpr int OFF_DE = OFF_PS + D * IN_PSI + D + D * D + D;
+constexpr int BLOCK_W = OFF_DE + D * D + D + D + 1;
+constexpr int MAX_TILES_PER_WAVE = (2048 / MFMA_TILE + (MFMA_BLOCK / 64) - 1) / (MFMA_BLOCK / 64);
+
+// Round-to-nearest-even float -> bf16 bits (host).
+uint16_t bf16_bits(double v) {
+    float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// K-index roles of the B operands (k = 8*hf + m).
+enum Role { H, ONE, XHI, XLO, YHI, YLO, C, DEG, ZERO };
+Role pq_role(int k, int* hidx) {
+    const int hf = k / 8, m = k % 8;
+    if (m < 5) { *hidx = 5 * hf + m; return H; }
+    if (hf == 0) return m == 5 ? ONE : (m == 6 ? XHI : XLO);
+    return m == 5 ? YHI : (m == 6 ? YLO : ZERO);
+}
+Role psi_role(int k, int* hidx) {
+    const int hf = k / 8, m = k % 8;
+    if (m < 5) { *hidx = 5 * hf + m; return H; }
+    if (hf == 0) return m == 5 ? ONE : (m == 6 ? C : DEG);
+    return ZERO;
+}
+// Output row r -> (half, item) of the lanes that receive it.
+inline int row_half(int r) { return (r / 4) % 2; }
+inline int row_item(int r) { return 4 * (r / 8) + r % 4; }
+
+}  // namespace
+
+void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaLane>& lanes, std::vector<MfmaDec>& dec) {
+    lanes.assign((size_t)kbar * 64, MfmaLane{});
+    std::vector<double> A(32 * 16);
+    auto put = [&](uint16_t* dst, int lane) {
+        const int row = lane % 32, k0 = 8 * (lane / 32);
+        for (int m = 0; m < 8; ++m) dst[m] = bf16_bits(A[row * 16 + k0 + m]);
+    };
+    for (int step = 0; step < kbar; ++step) {
+        const float* th = theta + (size_t)step * BLOCK_W;
+        auto W1 = [&](int dir, int u, int i) { return (double)th[(dir ? OFF_PI : OFF_PO) + u * IN_PHI + i]; };
+        auto B1 = [&](int dir, int u) { return (double)th[(dir ? OFF_PI : OFF_PO) + D * IN_PHI + u]; };
+        auto W2 = [&](int dir, int v, int w) { return (double)th[(dir ? OFF_PI : OFF_PO) + D * IN_PHI + D + v * D + w]; };
+        auto B2 = [&](int dir, int v) { return (double)th[(dir ? OFF_PI : OFF_PO) + D * IN_PHI + D + D * D + v]; };
+        auto P1 = [&](int u, int i) { return (double)th[OFF_PS + u * IN_PSI + i]; };
+        auto PB1 = [&](int u) { return (double)th[OFF_PS + D * IN_PSI + u]; };
+        auto P2 = [&](int o, int u) { return (double)th[OFF_PS + D * IN_PSI + D + o * D + u]; };
+        auto PB2 = [&](int o) { return (double)th[OFF_PS + D * IN_PSI + D + D * D + o]; };
+        // Folded message second layers: M_dir[u][w] = sum_v W1_psi[u][phi_dir v] W2_dir[v][w].
+        double M[2][D][D], degb[D];
+        for (int u = 0; u < D; ++u) {
+            degb[u] = 0;
+            for (int dir = 0; dir < 2; ++dir) {
+                const int off = dir ? 2 * D + 1 : D + 1;
+                for (int w = 0; w < D; ++w) {
+                    double acc = 0;
+                    for (int v = 0; v < D; ++v) acc += P1(u, off + v) * W2(dir, v, w);
+                    M[dir][u][w] = acc;
+                }
+                for (int v = 0; v < D; ++v) degb[u] += P1(u, off + v) * B2(dir, v);
+            }
+        }
+        MfmaLane* L = &lanes[(size_t)step * 64];
+        // Q' and P' tiles: row r -> (direction, unit) = (row_half, row_item) for items < 10.
+        for (int which = 0; which < 2; ++which) {  // 0: Q', 1: P'
+            std::fill(A.begin(), A.end(), 0.0);
+            for (int r = 0; r < 32; ++r) {
+                const int dir = row_half(r), u = row_item(r);
+                if (u >= D) continue;
+                const double sx = dir == 0 ? 1.0 : -1.0;  // d_jl for Phi_out, d_lj = -d_jl for Phi_in
+                for (int k = 0; k < 16; ++k) {
+                    int hi = 0;
+                    const Role role = pq_role(k, &hi);
+                    double v = 0;
+                    if (role == H) v = W1(dir, u, which == 0 ? D + hi : hi);
+                    else if (role == ONE) v = which == 0 ? 0.0 : B1(dir, u);
+                    else if (role == XHI || role == XLO) v = (which == 0 ? sx : -sx) * W1(dir, u, 2 * D);
+                    else if (role == YHI || role == YLO) v = (which == 0 ? sx : -sx) * W1(dir, u, 2 * D + 1);
+                    A[r * 16 + k] = v;
+                }
+            }
+            for (int lane = 0; lane < 64; ++lane) put(which == 0 ? L[lane].aq : L[lane].ap, lane);
+        }
+        // Psi hidden layer: output row r -> unit 5*row_half + row_item for items < 5.
+        auto hidden_unit = [](int r) { return row_item(r) < 5 ? 5 * row_half(r) + row_item(r) : -1; };
+        std::fill(A.begin(), A.end(), 0.0);
+        for (int r = 0; r < 32; ++r) {
+            const int u = hidden_unit(r);
+            if (u < 0) continue;
+            for (int k = 0; k < 16; ++k) {
+                int hi = 0;
+                const Role role = psi_role(k, &hi);
+                double v = 0;
+                if (role == H) v = P1(u, hi);
+                else if (role == ONE) v = PB1(u);
+                else if (role == C) v = P1(u, D);
+                else if (role == DEG) v = degb[u];
+                A[r * 16 + k] = v;
+            }
+        }
+        for (int lane = 0; lane < 64; ++lane) put(L[lane].ah, lane);
+        for (int part = 0; part < 2; ++part) {  // message sums, units 0..7 then 8..9
+            std::fill(A.begin(), A.end(), 0.0);
+            for (int r = 0; r < 32; ++r) {
+                const int u = hidden_unit(r);
+                if (u < 0) continue;
+                for (int k = 0; k < 16; ++k) {
+                    const int dir = k / 8, m = k % 8;
+                    const int w = part == 0 ? m : 8 + m;
+                    if (part == 1 && m >= 2) continue;
+                    A[r * 16 + k] = M[dir][u][w];
+                }
+            }
+            for (int lane = 0; lane < 64; ++lane) put(part == 0 ? L[lane].asa : L[lane].asb, lane);
+        }
+        // Psi output layer: output rows as hidden units, input k -> hidden unit 5*(k/8) + k%8.
+        std::fill(A.begin(), A.end(), 0.0);
+        for (int r = 0; r < 32; ++r) {
+            const int o = hidden_unit(r);
+            if (o < 0) continue;
+            for (int k = 0; k < 16; ++k)
+                if (k % 8 < 5) A[r * 16 + k] = P2(o, 5 * (k / 8) + k % 8);
+        }
+        for (int lane = 0; lane < 64; ++lane) put(L[lane].a2, lane);
+        for (int lane = 0; lane < 64; ++lane) {
+            const int hf = lane / 32;
+            for (int t = 0; t < D; ++t) L[lane].wn[t] = (float)W1(hf, t, 2 * D + 2);
+            for (int t = 0; t < 5; ++t) L[lane].b2[t] = (float)PB2(5 * hf + t);
+        }
+    }
+    // Decoder of the last block.
+    const float* th = theta + (size_t)(kbar - 1) * BLOCK_W + OFF_DE;
+    dec.assign(64, MfmaDec{});
+    std::fill(A.begin(), A.end(), 0.0);
+    for (int r = 0; r < 32; ++r) {
+        const int u = row_item(r) < 5 ? 5 * row_half(r) + row_item(r) : -1;
+        if (u < 0) continue;
+        for (int k = 0; k < 16; ++k) {
+            int hi = 0;
+            const Role role = psi_role(k, &hi);
+            if (role == H) A[r * 16 + k] = th[u * D + hi];
+            else if (role == ONE) A[r * 16 + k] = th[D * D + u];
+        }
+    }
+    for (int lane = 0; lane < 64; ++lane) put(dec[lane].ad1, lane);
+    std::fill(A.begin(), A.end(), 0.0);
+    for (int k = 0; k < 16; ++k)
+        if (k % 8 < 5) A[0 * 16 + k] = th[D * D + D + 5 * (k / 8) + k % 8];
+    for (int lane = 0; lane < 64; ++lane) {
+        put(dec[lane].ad2, lane);
+        dec[lane].bd2 = th[D * D + 2 * D];
+    }
+}
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ inline f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline bf16x8 load_a(const uint16_t* p) {
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+
+__device__ inline __bf16 bits_bf16(uint32_t b) { return __builtin_bit_cast(__bf16, (uint16_t)(b & 0xffffu)); }
+
+__device__ inline double block_sum(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int i = 0; i < MFMA_BLOCK / 64; ++i) acc += sh[i];
+        sh[MFMA_BLOCK / 64] = acc;
+    }
+    __syncthreads();
+    return sh[MFMA_BLOCK / 64];
+}
+
+// B operand of the P'/Q' products: (h 5 components, then 1, x_hi, x_lo) for
+// hf = 0 and (h 5 components, y_hi, y_lo, 0) for hf = 1.
+__device__ inline bf16x8 b_pq(const float (&h)[5], uint32_t xy2, int hf, bool valid) {
+    bf16x8 b;
+    const __bf16 z = (__bf16)0.0f;
+    const __bf16 first = bits_bf16(xy2), second = bits_bf16(xy2 >> 16);
+#pragma unroll
+    for (int m = 0; m < 5; ++m) b[m] = valid ? (__bf16)h[m] : z;
+    b[5] = !valid ? z : (hf == 0 ? (__bf16)1.0f : first);
+    b[6] = !valid ? z : (hf == 0 ? first : second);
+    b[7] = !valid || hf ? z : second;
+    return b;
+}
+
+// B operand of the Psi hidden layer: (h, 1, c, deg) for hf = 0, (h, 0, 0, 0) for hf = 1.
+__device__ inline bf16x8 b_psi(const float (&h)[5], float c, float deg, int hf, bool valid) {
+    bf16x8 b;
+    const __bf16 z = (__bf16)0.0f;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) b[m] = valid ? (__bf16)h[m] : z;
+    b[5] = valid && hf == 0 ? (__bf16)1.0f : z;
+    b[6] = valid && hf == 0 ? (__bf16)c : z;
+    b[7] = valid && hf == 0 ? (__bf16)deg : z;
+    return b;
+}
+
+// QLDS: the Q' table lives in LDS (compile-time, so accesses are ds_* rather
+// than flat); otherwise it lives in a per-slot global buffer.
+template <bool QLDS>
+__global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
+    if (a.done && *a.done) return;
+    extern __shared__ float lds[];
+    __shared__ double red[MFMA_BLOCK / 64 + 1];
+    const int sub = a.work_order[blockIdx.x];
+    const int base = a.sub_ptr[sub];
+    const int k = a.sub_ptr[sub + 1] - base;
+    const int tid = threadIdx.x;
+    float* cbuf = lds;                                   // [k] normalised residual c
+    float* Q = QLDS ? lds + k : a.qglobal + (size_t)base * 20;  // [k][2][10]
+
+    // Restriction and normalisation (Sec. III.A step 2).
+    double s = 1.0;
+    if (a.apply) {
+        double ss = 0.0, yy = 0.0;
+        for (int j = tid; j < k; j += MFMA_BLOCK) {
+            const double rv = a.r[a.sub_nodes[base + j]];
+            ss = fma(rv, rv, ss);
+            yy = fma(a.weights[base + j], rv, yy);
+        }
+        ss = block_sum(ss, red);
+        yy = block_sum(yy, red);
+        s = sqrt(ss);
+        if (tid == 0) {
+            a.s_out[sub] = s;
+            a.y0_out[sub] = yy;
+        }
+        if (s == 0.0) {
+            for (int j = tid; j < k; j += MFMA_BLOCK) a.out[base + j] = 0.0;
+            return;
+        }
+        const double inv = 1.0 / s;
+        for (int j = tid; j < k; j += MFMA_BLOCK) cbuf[j] = (float)(a.r[a.sub_nodes[base + j]] * inv);
+    } else {
+        for (int j = tid; j < k; j += MFMA_BLOCK) cbuf[j] = (float)a.c_in[base + j];
+    }
+    __syncthreads();
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int n = lane & 31, hf = lane >> 5;
+    const int ntiles = (k + MFMA_TILE - 1) / MFMA_TILE;
+    float h[MAX_TILES_PER_WAVE][5];
+#pragma unroll
+    for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt)
+#pragma unroll
+        for (int t = 0; t < 5; ++t) h[tt][t] = 0.0f;
+    const uint32_t* xy32 = reinterpret_cast<const uint32_t*>(a.xyhl);
+    const f32x16 zero = {};
+
+    for (int step = 0; step < a.kbar; ++step) {
+        const MfmaLane* L = a.lanes + (size_t)step * 64 + lane;
+        // Phase A: neighbour projections Q' -> LDS.
+        {
+            const bf16x8 AQ = load_a(L->aq);
+#pragma unroll
+            for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt) {
+                const int tile = wave + (MFMA_BLOCK / 64) * tt;
+                if (tile >= ntiles) break;
+                const int p = tile * MFMA_TILE + n;
+                const bool valid = p < k;
+                const int j = valid ? a.tnode[base + p] : 0;
+                const uint32_t xy2 = valid ? xy32[2 * (base + j) + hf] : 0u;
+                const f32x16 q = mfma(AQ, b_pq(h[tt], xy2, hf, valid), zero);
+                if (valid) {
+                    float* dst = Q + j * 20 + 10 * hf;
+#pragma unroll
+                    for (int t = 0; t < 10; t += 2) *reinterpret_cast<float2*>(dst + t) = make_float2(q[t], q[t + 1]);
+                }
+            }
+        }
+        __syncthreads();
+        // Phase B: receiver projections, edge sums, Psi update.
+        {
+            const bf16x8 AP = load_a(L->ap), AH = load_a(L->ah), ASA = load_a(L->asa), ASB = load_a(L->asb),
+                         A2 = load_a(L->a2);
+            float wn[10], b2[5];
+#pragma unroll
+            for (int t = 0; t < 10; ++t) wn[t] = L->wn[t];
+#pragma unroll
+            for (int t = 0; t < 5; ++t) b2[t] = L->b2[t];
+#pragma unroll
+            for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt) {
+                const int tile = wave + (MFMA_BLOCK / 64) * tt;
+                if (tile >= ntiles) break;
+                const int p = tile * MFMA_TILE + n;
+                const bool valid = p < k;
+                const int j = valid ? a.tnode[base + p] : 0;
+                const uint32_t xy2 = valid ? xy32[2 * (base + j) + hf] : 0u;
+                const f32x16 P = mfma(AP, b_pq(h[tt], xy2, hf, valid), zero);
+                float S[10];
+#pragma unroll
+                for (int t = 0; t < 10; ++t) S[t] = 0.0f;
+                int deg = 0;
+                if (valid) {
+                    const int e0 = a.edge_ptr[base + j], e1 = a.edge_ptr[base + j + 1];
+                    deg = e1 - e0;
+                    // chunks of 4 edges: loads first (arrays padded past the end), then the sums
+                    for (int e = e0; e < e1; e += 4) {
+                        int ls[4];
+                        float nds[4];
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) {
+                            ls[w] = a.edge_src[e + w];
+                            nds[w] = a.edge_nd[e + w];
+                        }
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) {
+                            if (e + w >= e1) break;
+                            const float* q = Q + ls[w] * 20 + 10 * hf;
+#pragma unroll
+                            for (int t = 0; t < 10; t += 2) {
+                                const float2 qq = *reinterpret_cast<const float2*>(q + t);
+                                S[t] += fmaxf(fmaf(wn[t], nds[w], P[t] + qq.x), 0.0f);
+                                S[t + 1] += fmaxf(fmaf(wn[t + 1], nds[w], P[t + 1] + qq.y), 0.0f);
+                            }
+                        }
+                    }
+                }
+                const float c = valid ? cbuf[j] : 0.0f;
+                bf16x8 sa, sb;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) sa[m] = (__bf16)S[m];
+                sb[0] = (__bf16)S[8];
+                sb[1] = (__bf16)S[9];
+#pragma unroll
+                for (int m = 2; m < 8; ++m) sb[m] = (__bf16)0.0f;
+                f32x16 hid = mfma(AH, b_psi(h[tt], c, (float)deg, hf, valid), zero);
+                hid = mfma(ASA, sa, hid);
+                hid = mfma(ASB, sb, hid);
+                bf16x8 bh;
+#pragma unroll
+                for (int m = 0; m < 5; ++m) bh[m] = (__bf16)fmaxf(hid[m], 0.0f);
+#pragma unroll
+                for (int m = 5; m < 8; ++m) bh[m] = (__bf16)0.0f;
+                const f32x16 o = mfma(A2, bh, zero);
+                if (valid) {
+#pragma unroll
+                    for (int t = 0; t < 5; ++t) h[tt][t] = fmaf(a.alpha, o[t] + b2[t], h[tt][t]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // Decoder of the last block.
+    const MfmaDec* Ld = a.dec + lane;
+    const bf16x8 AD1 = load_a(Ld->ad1), AD2 = load_a(Ld->ad2);
+    const float bd2 = Ld->bd2;
+#pragma unroll
+    for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt) {
+        const int tile = wave + (MFMA_BLOCK / 64) * tt;
+        if (tile >= ntiles) break;
+        const int p = tile * MFMA_TILE + n;
+        const bool valid = p < k;
+        const int j = valid ? a.tnode[base + p] : 0;
+        const f32x16 hd = mfma(AD1, b_psi(h[tt], 0.0f, 0.0f, hf, valid), zero);
+        bf16x8 bh;
+#pragma unroll
+        for (int m = 0; m < 5; ++m) bh[m] = (__bf16)fmaxf(hd[m], 0.0f);
+#pragma unroll
+        for (int m = 5; m < 8; ++m) bh[m] = (__bf16)0.0f;
+        const f32x16 o = mfma(AD2, bh, zero);
+        if (valid && hf == 0) {
+            const double r_tilde = (double)(o[0] + bd2);
+            a.out[base + j] = a.apply ? s * r_tilde : r_tilde;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_sub, size_t shmem, hipStream_t stream) {
+    const void* fn = a.q_in_lds ? (const void*)dss_mfma_kernel<true> : (const void*)dss_mfma_kernel<false>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    if (a.q_in_lds)
+        hipLaunchKernelGGL(dss_mfma_kernel<true>, dim3(n_sub), dim3(MFMA_BLOCK), shmem, stream, a);
+    else
+        hipLaunchKernelGGL(dss_mfma_kernel<false>, dim3(n_sub), dim3(MFMA_BLOCK), shmem, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace ddmgnn

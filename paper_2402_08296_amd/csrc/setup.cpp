@@ -190,6 +190,48 @@ void build_local_graphs(const ddmgnn_problem_desc& d, HostSetup& s) {
     std::stable_sort(s.work_order.begin(), s.work_order.end(), [&](int32_t a, int32_t b) {
         return d.sub_ptr[a + 1] - d.sub_ptr[a] > d.sub_ptr[b + 1] - d.sub_ptr[b];
     });
+
+    // Tile order, centred split coordinates and edge lengths.
+    s.tnode.assign(s.sk, 0);
+    s.xyhl.assign(4 * s.sk, 0);
+    s.xyc.assign(2 * s.sk, 0.0);
+    s.edge_nd.assign(s.n_edges, 0.0f);
+    std::vector<int32_t> ord;
+    for (int32_t i = 0; i < K; ++i) {
+        const int64_t b = d.sub_ptr[i], e = d.sub_ptr[i + 1];
+        const int32_t k = (int32_t)(e - b);
+        ord.resize(k);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
+            return s.edge_ptr[b + x + 1] - s.edge_ptr[b + x] > s.edge_ptr[b + y + 1] - s.edge_ptr[b + y];
+        });
+        for (int32_t q = 0; q < k; ++q) s.tnode[b + q] = (uint16_t)ord[q];
+        double cx = 0, cy = 0;
+        for (int64_t q = b; q < e; ++q) {
+            cx += d.xy[2 * d.sub_nodes[q]];
+            cy += d.xy[2 * d.sub_nodes[q] + 1];
+        }
+        cx /= k;
+        cy /= k;
+        for (int64_t q = b; q < e; ++q) {
+            const double x = d.xy[2 * d.sub_nodes[q]] - cx, y = d.xy[2 * d.sub_nodes[q] + 1] - cy;
+            s.xyc[2 * q] = x;
+            s.xyc[2 * q + 1] = y;
+            const uint16_t xh = bf16_rne_bits((float)x), yh = bf16_rne_bits((float)y);
+            s.xyhl[4 * q + 0] = xh;
+            s.xyhl[4 * q + 1] = bf16_rne_bits((float)(x - bf16_bits_float(xh)));
+            s.xyhl[4 * q + 2] = yh;
+            s.xyhl[4 * q + 3] = bf16_rne_bits((float)(y - bf16_bits_float(yh)));
+        }
+        for (int64_t q = b; q < e; ++q) {
+            const int32_t j = d.sub_nodes[q];
+            for (int64_t t = s.edge_ptr[q]; t < s.edge_ptr[q + 1]; ++t) {
+                const int32_t l = d.sub_nodes[b + s.edge_src[t]];
+                const double dx = d.xy[2 * l] - d.xy[2 * j], dy = d.xy[2 * l + 1] - d.xy[2 * j + 1];
+                s.edge_nd[t] = (float)std::sqrt(dx * dx + dy * dy);
+            }
+        }
+    }
 }
 
 std::string build_setup(const ddmgnn_problem_desc& d, HostSetup& s) {

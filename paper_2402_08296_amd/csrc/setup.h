@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdint>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -35,7 +36,30 @@ struct HostSetup {
     // Sub-meshes ordered by decreasing size (largest first) for the DSS launch.
     std::vector<int32_t> work_order;
     int32_t max_k = 0;
+    // For the MFMA kernel: per slot position, the local node id in order of
+    // decreasing in-degree (tiles of nodes with similar degree); per slot, the
+    // bf16 bits of (x_hi, x_lo, y_hi, y_lo) of the coordinates relative to the
+    // sub-mesh centroid; per edge, |d_jl| in FP32.
+    std::vector<uint16_t> tnode;
+    std::vector<uint16_t> xyhl;
+    std::vector<double> xyc;   // per slot, coordinates relative to the sub-mesh centroid
+    std::vector<float> edge_nd;
 };
+
+// Round-to-nearest-even float -> bf16 bits.
+inline uint16_t bf16_rne_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+inline float bf16_bits_float(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
 
 // Local DSS graphs, slot_sub, node membership lists and work order only.
 void build_local_graphs(const ddmgnn_problem_desc& d, HostSetup& s);

@@ -5,6 +5,8 @@ Tolerances:
     relative 1e-12 (DSS) / 1e-13 (linear algebra) of the largest magnitude.
   * FP32 DSS: one FP32 rounding per operation over 30 blocks; relative 3e-5
     of the largest output magnitude (measured errors are ~1e-6).
+  * BF16 DSS (MFMA operands rounded to bf16, 8-bit significand, FP32
+    accumulation): relative 5e-2 of the largest output magnitude.
 """
 import numpy as np
 import pytest
@@ -75,7 +77,7 @@ def _c_inputs(p, hp, seed):
     return c
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16", 5e-2)])
 @pytest.mark.parametrize("theta_name", ["xavier", "smoother"])
 def test_dss_forward_all_subdomains(ctx, c1, prec, tol, theta_name):
     print(f"[gpu] dss_forward {prec} {theta_name}", flush=True)
@@ -98,7 +100,7 @@ def test_dss_forward_all_subdomains(ctx, c1, prec, tol, theta_name):
     assert worst <= tol
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16", 5e-2)])
 @pytest.mark.parametrize("prolong", [dg.PROLONG_POU, dg.PROLONG_UNWEIGHTED])
 def test_apply_and_intermediates(ctx, c1, prec, tol, prolong):
     print(f"[gpu] apply {prec} prolong={prolong}", flush=True)
@@ -122,10 +124,13 @@ def test_apply_and_intermediates(ctx, c1, prec, tol, prolong):
     ref_y = np.linalg.solve(M.coarse.A0, y0)
     assert np.abs(y - ref_y).max() <= 1e-10 * np.abs(ref_y).max()
     # a7: local terms s_i r~_i
+    worst = 0.0
     for i in range(hp.K):
         sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
         si, rt = M.local(i, r)
-        assert np.abs(loc[sl] - si * rt).max() <= tol * np.abs(si * rt).max()
+        worst = max(worst, np.abs(loc[sl] - si * rt).max() / np.abs(si * rt).max())
+    print(f"[gpu]   local terms worst relative error {worst:.3e}", flush=True)
+    assert worst <= tol
     # a8: glued z
     zg = z.cpu().numpy()
     assert np.all(zg[p.mesh.dirichlet == 1] == 0)
@@ -141,7 +146,7 @@ def test_apply_deterministic_and_homogeneous(ctx, c1):
     z1 = torch.empty(p.n, dtype=torch.float64, device="cuda")
     z2 = torch.empty_like(z1)
     z3 = torch.empty_like(z1)
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16"):
         o = dg.default_opts(precision=prec)
         prob.apply(_dev(r), z1, o)
         prob.apply(_dev(r), z2, o)
@@ -197,6 +202,23 @@ def test_solve_fp32_converges_to_tolerance(ctx, c1):
     assert abs(st.iterations - ref.iterations) <= max(2, 0.1 * ref.iterations)
 
 
+def test_solve_bf16_converges_to_tolerance(ctx, c1):
+    print("[gpu] solve bf16", flush=True)
+    p, hp = c1
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, SMOOTHER))
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    st = prob.solve(u, dg.default_opts(precision="bf16", rtol=1e-6, max_it=2000))
+    ref = kr.fcg(p.A.to_scipy(), p.b, p.u0, _oracle_M(p, hp, SMOOTHER), 1e-6, max_it=2000)
+    print(f"[gpu]   iterations gpu={st.iterations} oracle={ref.iterations}", flush=True)
+    assert st.converged and st.true_rel_residual <= 1.5e-6
+    assert st.iterations <= 1.5 * ref.iterations + 5
+    import scipy.sparse.linalg as spl
+    ud = spl.spsolve(p.A.to_scipy().tocsc(), p.b)
+    err = np.linalg.norm(u.cpu().numpy() - ud) / np.linalg.norm(ud)
+    print(f"[gpu]   rel. L2 error vs direct solve {err:.2e}", flush=True)
+    assert err <= 1e-4
+
+
 def test_krylov_modes(ctx, c1):
     print("[gpu] cg/pcg", flush=True)
     p, hp = c1
@@ -244,9 +266,11 @@ def test_zero_rhs_and_large_subdomain(ctx):
     g = dc.local_graph(hp.sub_nodes, p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
     ref = dss.forward(blocks, g, c, 1e-3, 10)
     out = torch.empty(hp.sub_nodes.size, dtype=torch.float64, device="cuda")
-    for prec, tol in (("fp64", 1e-12), ("fp32", 3e-5)):
+    for prec, tol in (("fp64", 1e-12), ("fp32", 3e-5), ("bf16", 5e-2)):
         prob.dss_forward(_dev(c), out, prec)
-        assert np.abs(out.cpu().numpy() - ref).max() <= tol * np.abs(ref).max()
+        err = np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max()
+        print(f"[gpu]   k={hp.sub_ptr[1]} {prec} relative error {err:.3e}", flush=True)
+        assert err <= tol
     # b = A u0: the initial residual is zero, nothing to do
     hp0 = dg.HostProblem(hp.xy, hp.tri, hp.dirichlet, hp.rowptr, hp.col, hp.val, p.A.to_scipy() @ p.u0, p.u0,
                          hp.sub_ptr, hp.sub_nodes, hp.weights)
