@@ -146,6 +146,8 @@ typedef struct {
     int32_t coarse;      /* 1: add the coarse correction (step 1), 0: one-level */
     int32_t check_every; /* iterations between host checks of the converged flag */
     int32_t profile;     /* 1: time every stage with HIP events on the context stream */
+    int32_t graph;       /* 1: replay chunks of check_every iterations as one captured HIP graph
+                          * (ignored when profile = 1) */
 } ddmgnn_solve_opts;
 
 typedef struct {
@@ -163,7 +165,8 @@ typedef struct {
     double krylov_ms;          /* direction update, SpMV with dots, solution update */
 } ddmgnn_stats;
 
-/* Fill opts with defaults (FCG, m_max 1, rtol 1e-6, max_it 10000, FP32, POU, coarse on). */
+/* Fill opts with defaults (FCG, m_max 1, rtol 1e-6, max_it 10000, FP32, POU, coarse on,
+ * check_every 16, graph replay on). */
 void ddmgnn_default_opts(ddmgnn_solve_opts* opts);
 
 /* Solve A u = b from the problem's u0. u_out: device, N doubles. On

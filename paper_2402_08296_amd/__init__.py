@@ -44,7 +44,8 @@ class ProblemDesc(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("krylov", _i32), ("m_max", _i32), ("rtol", _f64), ("max_it", _i32), ("precision", _i32),
-                ("prolong", _i32), ("coarse", _i32), ("check_every", _i32), ("profile", _i32)]
+                ("prolong", _i32), ("coarse", _i32), ("check_every", _i32), ("profile", _i32),
+                ("graph", _i32)]
 
 
 class Stats(ctypes.Structure):

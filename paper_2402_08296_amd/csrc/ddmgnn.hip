@@ -75,7 +75,7 @@ struct KState {
     int it;
     int done;
     int status;
-    int pad;
+    int max_it;            // the update kernel raises done once it reaches max_it
 };
 
 // ------------------------------------------------------------------ reductions
@@ -304,49 +304,48 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
                     }
                 }
                 const int e0 = a.edge_ptr[base + j], e1 = a.edge_ptr[base + j + 1];
-                // Edges in chunks of 4: the chunk's loads are issued before any
-                // use (the edge arrays are padded, so reads past e1 stay in bounds).
-                for (int e = e0; e < e1; e += 4) {
-                    int ls[4];
-                    T ex[4], ey[4];
+                if (SEP) {
+                    // Chunks of 2 edges as straight-line code: both rows are read from
+                    // LDS before the sums. An edge past e1 reads the node's own row
+                    // (the edge arrays are padded) and is masked with a 0 weight.
+                    for (int e = e0; e < e1; e += 2) {
+                        const bool in1 = e + 1 < e1;
+                        const int l0 = a.edge_src[e], l1 = in1 ? (int)a.edge_src[e + 1] : j;
+                        const T n0 = (T)a.edge_nd[e], n1 = (T)a.edge_nd[e + 1];
+                        const T m1 = in1 ? (T)1 : (T)0;
+                        T q0[2 * D], q1[2 * D];
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        ls[w] = a.edge_src[e + w];
-                        if (SEP) {
-                            ex[w] = (T)a.edge_nd[e + w];
-                        } else {
-                            const int lw = e + w < e1 ? ls[w] : j;
-                            ex[w] = a.xy[2 * (base + lw)] - xj;
-                            ey[w] = a.xy[2 * (base + lw) + 1] - yj;
+                        for (int u = 0; u < 2 * D; ++u) {
+                            q0[u] = Q[l0 * 2 * D + u];
+                            q1[u] = Q[l1 * 2 * D + u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < D; ++u) {
+                            const T wo = Wo[u * IN_PHI + 2 * D + 2], wi = Wi[u * IN_PHI + 2 * D + 2];
+                            so[u] += relu(fma(wo, n0, po[u] + q0[u]));
+                            si[u] += relu(fma(wi, n0, pi[u] + q0[D + u]));
+                            so[u] = fma(m1, relu(fma(wo, n1, po[u] + q1[u])), so[u]);
+                            si[u] = fma(m1, relu(fma(wi, n1, pi[u] + q1[D + u])), si[u]);
                         }
                     }
+                } else {
+                    for (int e = e0; e < e1; ++e) {
+                        const int l = a.edge_src[e];
+                        const T dx = a.xy[2 * (base + l)] - xj, dy = a.xy[2 * (base + l) + 1] - yj;
+                        const T nr = sqrt(dx * dx + dy * dy);
+                        const T* ql = Q + l * 2 * D;
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        if (e + w >= e1) break;
-                        const T* ql = Q + ls[w] * 2 * D;
-                        if (SEP) {
-                            const T nr = ex[w];
-#pragma unroll
-                            for (int u = 0; u < D; ++u) {
-                                so[u] += relu(fma(Wo[u * IN_PHI + 2 * D + 2], nr, po[u] + ql[u]));
-                                si[u] += relu(fma(Wi[u * IN_PHI + 2 * D + 2], nr, pi[u] + ql[D + u]));
-                            }
-                        } else {
-                            const T dx = ex[w], dy = ey[w];
-                            const T nr = sqrt(dx * dx + dy * dy);
-#pragma unroll
-                            for (int u = 0; u < D; ++u) {
-                                T vo = po[u] + ql[u];
-                                vo = fma(Wo[u * IN_PHI + 2 * D], dx, vo);
-                                vo = fma(Wo[u * IN_PHI + 2 * D + 1], dy, vo);
-                                vo = fma(Wo[u * IN_PHI + 2 * D + 2], nr, vo);
-                                so[u] += relu(vo);
-                                T vi = pi[u] + ql[D + u];
-                                vi = fma(Wi[u * IN_PHI + 2 * D], -dx, vi);
-                                vi = fma(Wi[u * IN_PHI + 2 * D + 1], -dy, vi);
-                                vi = fma(Wi[u * IN_PHI + 2 * D + 2], nr, vi);
-                                si[u] += relu(vi);
-                            }
+                        for (int u = 0; u < D; ++u) {
+                            T vo = po[u] + ql[u];
+                            vo = fma(Wo[u * IN_PHI + 2 * D], dx, vo);
+                            vo = fma(Wo[u * IN_PHI + 2 * D + 1], dy, vo);
+                            vo = fma(Wo[u * IN_PHI + 2 * D + 2], nr, vo);
+                            so[u] += relu(vo);
+                            T vi = pi[u] + ql[D + u];
+                            vi = fma(Wi[u * IN_PHI + 2 * D], -dx, vi);
+                            vi = fma(Wi[u * IN_PHI + 2 * D + 1], -dy, vi);
+                            vi = fma(Wi[u * IN_PHI + 2 * D + 2], nr, vi);
+                            si[u] += relu(vi);
                         }
                     }
                 }
@@ -573,7 +572,7 @@ __global__ __launch_bounds__(VEC_BLOCK) void update_kernel(double* __restrict__ 
         st->beta[0] = rr / st->rho;
         st->rho = rr;
     }
-    if (st->rel <= st->rtol) st->done = 1;
+    if (st->rel <= st->rtol || st->it >= st->max_it) st->done = 1;
 }
 
 // r = b - A u with |r|^2; zero the direction buffers; initialise the state.
@@ -582,8 +581,8 @@ __global__ __launch_bounds__(VEC_BLOCK) void init_kernel(const int32_t* __restri
                                                         const double* __restrict__ val,
                                                         const double* __restrict__ b, const double* __restrict__ u,
                                                         double* __restrict__ r, double* const* ring, int n_ring,
-                                                        int n, double rtol, double* partials, unsigned* counter,
-                                                        KState* st) {
+                                                        int n, double rtol, int max_it, double* partials,
+                                                        unsigned* counter, KState* st) {
     __shared__ double sh[VEC_BLOCK / 64 + 1];
     double d[1] = {0.0};
     for (int i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
@@ -599,14 +598,15 @@ __global__ __launch_bounds__(VEC_BLOCK) void init_kernel(const int32_t* __restri
     if (threadIdx.x != 0) return;
     st->r0n = sqrt(tot[0]);
     st->rtol = rtol;
-    st->rel = 1.0;
+    st->rel = tot[0] == 0.0 ? 0.0 : 1.0;
     st->alpha = 0.0;
     for (int i = 0; i < MAX_M; ++i) st->beta[i] = 0.0;
     for (int i = 0; i <= MAX_M; ++i) st->pq[i] = 1.0;
     st->rho = tot[0];
     st->it = 0;
+    st->max_it = max_it;
     st->status = isfinite(tot[0]) ? 0 : DDMGNN_E_NONFINITE;
-    st->done = (tot[0] == 0.0 || !isfinite(tot[0])) ? 1 : 0;
+    st->done = (tot[0] == 0.0 || !isfinite(tot[0]) || max_it <= 0) ? 1 : 0;
 }
 
 // Plain y = A x and a deterministic dot (hooks and the final true residual).
@@ -687,7 +687,9 @@ struct DevBuf {
 
 // ------------------------------------------------------------------ handles
 struct ddmgnn_ctx {
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // the caller's stream: all work runs here
+    hipStream_t launch = nullptr;   // where kernels are enqueued (= stream, or cap while capturing)
+    hipStream_t cap = nullptr;      // own non-blocking stream for graph capture (the null stream cannot be captured)
     int device = 0;
     DevBuf<double> partials;
     DevBuf<unsigned> counters;
@@ -699,7 +701,7 @@ struct ddmgnn_model {
     int kbar = 0, d = 0;
     double alpha = 0;
     std::vector<float> theta;
-    std::vector<ddmgnn::MfmaLane> mfma_lanes;  // per block, per lane A operands and constants
+    std::vector<ddmgnn::MfmaStep> mfma_steps;  // per block: A operands and lane constants
     std::vector<ddmgnn::MfmaDec> mfma_dec;
 };
 
@@ -719,9 +721,11 @@ struct ddmgnn_problem {
     DevBuf<float> xyc32;  // per slot, centred on the sub-mesh
     DevBuf<float> theta32;
     DevBuf<double> theta64;
-    DevBuf<ddmgnn::MfmaLane> mfma_lanes;
+    DevBuf<ddmgnn::MfmaStep> mfma_steps;
     DevBuf<ddmgnn::MfmaDec> mfma_dec;
-    DevBuf<uint16_t> tnode, xyhl;
+    DevBuf<ddmgnn::TileNode> tiles;
+    DevBuf<uint32_t> erec;   // padded by 8 entries
+    bool mfma_fits = false;  // every sub-mesh fits the MFMA kernel's LDS
     DevBuf<float> edge_nd;
     // apply buffers
     DevBuf<double> s, y0, y, local;
@@ -734,39 +738,65 @@ struct ddmgnn_problem {
     DevBuf<KState> st;
     DevBuf<double> partials;
     DevBuf<unsigned> counters;
+    // captured FCG chunk (kernels and pointers fixed per options key)
+    hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_key = 0;
+    ~ddmgnn_problem() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    }
 };
 
 namespace {
 
-int launch_dss(ddmgnn_problem* P, int precision, bool apply, const double* r, const double* c_in, double* out,
-               const KState* st) {
-    hipStream_t s = P->ctx->stream;
-    const int K = P->hs.K;
-    if (precision == DDMGNN_BF16) {
-        const size_t need = ddmgnn::mfma_lds_bytes(P->hs.max_k);
-        const bool in_lds = need + 1024 <= LDS_LIMIT;
-        if (!in_lds && P->qglobal32.n < (size_t)P->hs.sk * 2 * D) HIP_TRY(P->qglobal32.alloc((size_t)P->hs.sk * 2 * D));
-        ddmgnn::DssMfmaArgs a{};
-        a.sub_ptr = P->sub_ptr.p; a.work_order = P->work_order.p; a.edge_ptr = P->edge_ptr.p;
-        a.edge_src = P->edge_src.p; a.edge_nd = P->edge_nd.p; a.tnode = P->tnode.p; a.xyhl = P->xyhl.p;
-        a.sub_nodes = P->sub_nodes.p; a.weights = P->weights.p; a.r = r; a.c_in = c_in; a.out = out;
-        a.s_out = P->s.p; a.y0_out = P->y0.p; a.qglobal = P->qglobal32.p; a.done = st ? &st->done : nullptr;
-        a.lanes = P->mfma_lanes.p; a.dec = P->mfma_dec.p; a.kbar = P->kbar; a.alpha = (float)P->alpha;
-        a.apply = apply; a.q_in_lds = in_lds;
-        const size_t shmem = in_lds ? need : (size_t)P->hs.max_k * sizeof(float);
-        HIP_TRY(ddmgnn::launch_dss_mfma(a, K, shmem, s));
+// Allocates the global fallback buffers a DSS launch of this precision needs
+// (done before any stream capture, which must not allocate).
+int prepare_dss(ddmgnn_problem* P, int precision) {
+    const int64_t sk = P->hs.sk;
+    if (precision == DDMGNN_BF16 && P->mfma_fits) {
+        HIP_TRY(ddmgnn::prepare_dss_mfma(ddmgnn::MFMA_LDS_LIMIT));
         return DDMGNN_OK;
     }
+    if (precision == DDMGNN_BF16) precision = DDMGNN_FP32;  // sub-mesh too large for the MFMA kernel
+    const bool f64 = precision == DDMGNN_FP64;
+    const size_t need = (size_t)P->hs.max_k * 2 * D * (f64 ? sizeof(double) : sizeof(float));
+    const bool in_lds = need + 1024 <= LDS_LIMIT;
+    if (!in_lds) {
+        if (f64 && P->qglobal64.n == 0) HIP_TRY(P->qglobal64.alloc((size_t)sk * 2 * D));
+        if (!f64 && P->qglobal32.n < (size_t)sk * 2 * D) HIP_TRY(P->qglobal32.alloc((size_t)sk * 2 * D));
+    }
+    if (f64 && P->hglobal64.n == 0) HIP_TRY(P->hglobal64.alloc((size_t)sk * D));
+    if (in_lds) {
+        const void* fn = f64 ? (const void*)dss_kernel<double, false, true> : (const void*)dss_kernel<float, true, true>;
+        HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need));
+    }
+    return DDMGNN_OK;
+}
+
+// capturing: the stream is being captured into a graph; prepare_dss has run
+// and no HIP call other than the launch is allowed.
+int launch_dss(ddmgnn_problem* P, int precision, bool apply, const double* r, const double* c_in, double* out,
+               const KState* st, bool capturing = false) {
+    if (!capturing)
+        if (int rc = prepare_dss(P, precision)) return rc;
+    hipStream_t s = P->ctx->launch;
+    const int K = P->hs.K;
+    if (precision == DDMGNN_BF16 && P->mfma_fits) {
+        ddmgnn::DssMfmaArgs a{};
+        a.sub_ptr = P->sub_ptr.p; a.work_order = P->work_order.p; a.edge_ptr = P->edge_ptr.p;
+        a.erec = P->erec.p; a.tiles = P->tiles.p;
+        a.sub_nodes = P->sub_nodes.p; a.weights = P->weights.p; a.r = r; a.c_in = c_in; a.out = out;
+        a.s_out = P->s.p; a.y0_out = P->y0.p; a.done = st ? &st->done : nullptr;
+        a.steps = P->mfma_steps.p; a.dec = P->mfma_dec.p; a.kbar = P->kbar; a.alpha = (float)P->alpha;
+        a.apply = apply;
+        HIP_TRY(ddmgnn::launch_dss_mfma(a, K, ddmgnn::MFMA_LDS_LIMIT, s, !capturing));
+        return DDMGNN_OK;
+    }
+    if (precision == DDMGNN_BF16) precision = DDMGNN_FP32;  // sub-mesh too large for the MFMA kernel
     const bool f64 = precision == DDMGNN_FP64;
     const size_t esz = f64 ? sizeof(double) : sizeof(float);
     const size_t need = (size_t)P->hs.max_k * 2 * D * esz;
     const bool in_lds = need + 1024 <= LDS_LIMIT;
-    if (!in_lds) {
-        if (f64 && P->qglobal64.n == 0) HIP_TRY(P->qglobal64.alloc((size_t)P->hs.sk * 2 * D));
-        if (!f64 && P->qglobal32.n == 0) HIP_TRY(P->qglobal32.alloc((size_t)P->hs.sk * 2 * D));
-    }
     const size_t shmem = in_lds ? need : 0;
-    if (f64 && P->hglobal64.n == 0) HIP_TRY(P->hglobal64.alloc((size_t)P->hs.sk * D));
     if (f64) {
         DssArgs<double> a{};
         a.sub_ptr = P->sub_ptr.p; a.work_order = P->work_order.p; a.edge_ptr = P->edge_ptr.p;
@@ -775,8 +805,6 @@ int launch_dss(ddmgnn_problem* P, int precision, bool apply, const double* r, co
         a.qglobal = P->qglobal64.p; a.hglobal = P->hglobal64.p; a.st = st; a.kbar = P->kbar; a.alpha = P->alpha;
         a.apply = apply; a.q_in_lds = in_lds;
         if (in_lds) {
-            HIP_TRY(hipFuncSetAttribute((const void*)dss_kernel<double, false, true>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
             hipLaunchKernelGGL((dss_kernel<double, false, true>), dim3(K), dim3(DSS_BLOCK), shmem, s, a,
                                (const double*)P->theta64.p);
         } else {
@@ -792,8 +820,6 @@ int launch_dss(ddmgnn_problem* P, int precision, bool apply, const double* r, co
         a.qglobal = P->qglobal32.p; a.hglobal = nullptr; a.st = st; a.kbar = P->kbar; a.alpha = (float)P->alpha;
         a.apply = apply; a.q_in_lds = in_lds;
         if (in_lds) {
-            HIP_TRY(hipFuncSetAttribute((const void*)dss_kernel<float, true, true>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
             hipLaunchKernelGGL((dss_kernel<float, true, true>), dim3(K), dim3(DSS_BLOCK), shmem, s, a,
                                (const float*)P->theta32.p);
         } else {
@@ -801,17 +827,18 @@ int launch_dss(ddmgnn_problem* P, int precision, bool apply, const double* r, co
                                (const float*)P->theta32.p);
         }
     }
-    HIP_TRY(hipGetLastError());
+    if (!capturing) HIP_TRY(hipGetLastError());
     return DDMGNN_OK;
 }
 
 // Enqueue one preconditioner apply z = M(r) with the Krylov dots of `mode`.
 // ev (optional): events recorded after the DSS (ev[1]), coarse (ev[2]) and prolong (ev[3]) launches.
 int enqueue_apply(ddmgnn_problem* P, const ddmgnn_solve_opts& o, const double* r, double* z, int mode,
-                  double* const* qk, const int* pslot, int m, KState* st, hipEvent_t* ev = nullptr) {
-    int rc = launch_dss(P, o.precision, true, r, nullptr, P->local.p, st);
+                  double* const* qk, const int* pslot, int m, KState* st, hipEvent_t* ev = nullptr,
+                  bool capturing = false) {
+    int rc = launch_dss(P, o.precision, true, r, nullptr, P->local.p, st, capturing);
     if (rc) return rc;
-    hipStream_t s = P->ctx->stream;
+    hipStream_t s = P->ctx->launch;
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     const int K = P->hs.K;
     if (o.coarse) {
@@ -830,8 +857,51 @@ int enqueue_apply(ddmgnn_problem* P, const ddmgnn_solve_opts& o, const double* r
     a.m = m; a.n = (int)P->hs.n; a.unweighted = o.prolong == DDMGNN_PROLONG_UNWEIGHTED; a.mode = mode;
     a.partials = P->partials.p; a.counter = P->counters.p; a.st = st;
     hipLaunchKernelGGL(prolong_kernel, dim3(vec_grid(P->hs.n)), dim3(VEC_BLOCK), 0, s, a);
-    HIP_TRY(hipGetLastError());
+    if (!capturing) HIP_TRY(hipGetLastError());
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    return DDMGNN_OK;
+}
+
+// Enqueue FCG/PCG/CG iteration `it` (ring slots depend on it % (m+1)). ev:
+// optional 5 profiling events (before DSS, after DSS/coarse/prolong, end).
+int enqueue_iteration(ddmgnn_problem* P, const ddmgnn_solve_opts& o, int it, hipEvent_t* ev,
+                      bool capturing = false) {
+    hipStream_t s = P->ctx->launch;
+    const int64_t n = P->hs.n;
+    const int grid = vec_grid(n);
+    const int mode = o.krylov;
+    const int m = mode == DDMGNN_FCG ? o.m_max : 1;
+    const int nring = m + 1;
+    const int cur = it % nring;
+    double* pv_cur = P->ring.p + (size_t)cur * n;
+    double* qv_cur = P->ring.p + (size_t)(MAX_M + 1 + cur) * n;
+    double* prev_p[MAX_M] = {nullptr, nullptr, nullptr, nullptr};
+    double* prev_q[MAX_M] = {nullptr, nullptr, nullptr, nullptr};
+    int prev_slot[MAX_M] = {0, 0, 0, 0};
+    for (int kk = 0; kk < m; ++kk) {
+        const int sl = ((it - 1 - kk) % nring + nring) % nring;
+        prev_p[kk] = P->ring.p + (size_t)sl * n;
+        prev_q[kk] = P->ring.p + (size_t)(MAX_M + 1 + sl) * n;
+        prev_slot[kk] = sl;
+    }
+    const double* zsrc = P->z.p;
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    if (mode == DDMGNN_CG) {
+        zsrc = P->r.p;
+        if (ev)
+            for (int q = 1; q < 4; ++q) HIP_TRY(hipEventRecord(ev[q], s));
+    } else {
+        int rc = enqueue_apply(P, o, P->r.p, P->z.p, mode, prev_q, prev_slot, m, P->st.p, ev, capturing);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(pupdate_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, zsrc, pv_cur, prev_p[0], prev_p[1],
+                       prev_p[2], prev_p[3], (mode == DDMGNN_FCG) ? m : 1, (int)n, P->st.p);
+    hipLaunchKernelGGL(spmv_dots_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, P->rowptr.p, P->col.p, P->val.p, pv_cur,
+                       qv_cur, P->r.p, (int)n, mode, cur, P->partials.p, P->counters.p, P->st.p);
+    hipLaunchKernelGGL(update_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, P->u.p, P->r.p, pv_cur, qv_cur, (int)n, mode,
+                       P->partials.p, P->counters.p, P->st.p);
+    if (!capturing) HIP_TRY(hipGetLastError());
+    if (ev) HIP_TRY(hipEventRecord(ev[4], s));
     return DDMGNN_OK;
 }
 
@@ -862,15 +932,18 @@ void ddmgnn_default_opts(ddmgnn_solve_opts* o) {
     o->precision = DDMGNN_FP32;
     o->prolong = DDMGNN_PROLONG_POU;
     o->coarse = 1;
-    o->check_every = 8;
+    o->check_every = 16;
     o->profile = 0;
+    o->graph = 1;
 }
 
 int ddmgnn_ctx_create(void* hip_stream, ddmgnn_ctx** out) {
     if (!out) return fail(DDMGNN_E_INVALID, "null output pointer");
     auto c = std::make_unique<ddmgnn_ctx>();
     c->stream = (hipStream_t)hip_stream;
+    c->launch = c->stream;
     HIP_TRY(hipGetDevice(&c->device));
+    HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
     HIP_TRY(c->partials.alloc(VEC_GRID));
     HIP_TRY(c->counters.alloc(4));
     HIP_TRY(hipMemset(c->counters.p, 0, 4 * sizeof(unsigned)));
@@ -884,6 +957,7 @@ int ddmgnn_ctx_create(void* hip_stream, ddmgnn_ctx** out) {
 int ddmgnn_ctx_destroy(ddmgnn_ctx* ctx) {
     if (!ctx) return DDMGNN_OK;
     if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     delete ctx;
     return DDMGNN_OK;
 }
@@ -903,7 +977,7 @@ int ddmgnn_model_create(ddmgnn_ctx* ctx, const ddmgnn_model_desc* desc, const fl
     m->d = desc->d;
     m->alpha = desc->alpha;
     m->theta.assign(theta, theta + n_theta);
-    ddmgnn::build_mfma_blobs(m->theta.data(), m->kbar, m->mfma_lanes, m->mfma_dec);
+    ddmgnn::build_mfma_blobs(m->theta.data(), m->kbar, m->mfma_steps, m->mfma_dec);
     *out = m.release();
     return DDMGNN_OK;
 }
@@ -977,10 +1051,36 @@ int ddmgnn_problem_create(ddmgnn_ctx* ctx, const ddmgnn_problem_desc* desc, cons
     std::vector<double> th64(model->theta.begin(), model->theta.end());
     HIP_TRY(P->theta32.upload(model->theta.data(), model->theta.size(), s));
     HIP_TRY(P->theta64.upload(th64.data(), th64.size(), s));
-    HIP_TRY(P->mfma_lanes.upload(model->mfma_lanes.data(), model->mfma_lanes.size(), s));
+    HIP_TRY(P->mfma_steps.upload(model->mfma_steps.data(), model->mfma_steps.size(), s));
     HIP_TRY(P->mfma_dec.upload(model->mfma_dec.data(), model->mfma_dec.size(), s));
-    HIP_TRY(P->tnode.upload(hs.tnode.data(), hs.tnode.size(), s));
-    HIP_TRY(P->xyhl.upload(hs.xyhl.data(), hs.xyhl.size(), s));
+    {
+        std::vector<ddmgnn::TileNode> tiles(sk);
+        for (int i = 0; i < K; ++i) {
+            const int64_t b = desc->sub_ptr[i], e = desc->sub_ptr[i + 1];
+            for (int64_t q = b; q < e; ++q) {
+                const int32_t j = hs.tnode[q];
+                const int64_t slot = b + j;
+                ddmgnn::TileNode& t = tiles[q];
+                t.e0 = (int32_t)hs.edge_ptr[slot];
+                t.j = (uint16_t)j;
+                t.deg = (uint16_t)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]);
+                t.xh = hs.xyhl[4 * slot + 0];
+                t.xl = hs.xyhl[4 * slot + 1];
+                t.yh = hs.xyhl[4 * slot + 2];
+                t.yl = hs.xyhl[4 * slot + 3];
+            }
+        }
+        HIP_TRY(P->tiles.upload(tiles.data(), tiles.size(), s));
+        std::vector<uint32_t> er(hs.erec);
+        er.resize(er.size() + 8, 0u);
+        HIP_TRY(P->erec.upload(er.data(), er.size(), s));
+        size_t need = 0;
+        for (int i = 0; i < K; ++i) {
+            const int64_t b = desc->sub_ptr[i], e = desc->sub_ptr[i + 1];
+            need = std::max(need, ddmgnn::mfma_lds_need((int)(e - b), hs.edge_ptr[e] - hs.edge_ptr[b]));
+        }
+        P->mfma_fits = need <= ddmgnn::MFMA_LDS_LIMIT;
+    }
     {
         std::vector<float> nd(hs.edge_nd);
         nd.resize(nd.size() + 8, 0.0f);
@@ -1119,32 +1219,69 @@ int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* op
     hipStream_t s = ctx->stream;
     const int64_t n = P->hs.n;
     const int grid = vec_grid(n);
-    const int mode = o.krylov;
-    const int m = mode == DDMGNN_FCG ? o.m_max : 1;
-    const int nring = m + 1;
-    double* pv[MAX_M + 1];
-    double* qv[MAX_M + 1];
-    for (int i = 0; i < nring; ++i) {
-        pv[i] = P->ring.p + (size_t)i * n;
-        qv[i] = P->ring.p + (size_t)(MAX_M + 1 + i) * n;
-    }
+    const int nring = (o.krylov == DDMGNN_FCG ? o.m_max : 1) + 1;
     hipEvent_t ev0, ev1;
     HIP_TRY(hipEventCreate(&ev0));
     HIP_TRY(hipEventCreate(&ev1));
     HIP_TRY(hipMemcpyAsync(P->u.p, P->u0.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipEventRecord(ev0, s));
     hipLaunchKernelGGL(init_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, P->rowptr.p, P->col.p, P->val.p, P->b.p,
-                       P->u.p, P->r.p, P->ring_ptrs.p, 2 * (MAX_M + 1), (int)n, o.rtol, P->partials.p,
+                       P->u.p, P->r.p, P->ring_ptrs.p, 2 * (MAX_M + 1), (int)n, o.rtol, o.max_it, P->partials.p,
                        P->counters.p, P->st.p);
     HIP_TRY(hipGetLastError());
     KState host_state{};
-    const int check = std::max(1, o.check_every);
+    // Iterations between host polls of the converged flag. With graph replay
+    // the chunk length is a multiple of the direction-ring length, so every
+    // chunk has the same kernels and pointers and one captured graph serves all.
+    int check = std::max(1, o.check_every);
+    const bool use_graph = o.graph && !o.profile;
+    if (use_graph) check = ((check + nring - 1) / nring) * nring;
     // Profiling: 5 events per iteration of a chunk (before DSS, after DSS,
     // after coarse, after prolong, after the Krylov kernels).
     std::vector<hipEvent_t> pev;
     if (o.profile) {
         pev.resize((size_t)check * 5);
         for (auto& e : pev) HIP_TRY(hipEventCreate(&e));
+    }
+    hipGraphExec_t gexec = nullptr;
+    if (use_graph) {
+        const uint64_t key = ((uint64_t)o.krylov << 40) | ((uint64_t)o.m_max << 32) | ((uint64_t)o.precision << 24) |
+                             ((uint64_t)o.prolong << 16) | ((uint64_t)o.coarse << 8) | (uint64_t)check;
+        if (!P->graph_exec || P->graph_key != key) {
+            if (P->graph_exec) {
+                (void)hipGraphExecDestroy(P->graph_exec);
+                P->graph_exec = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            if (o.krylov != DDMGNN_CG)
+                if (int prc = prepare_dss(P, o.precision)) return prc;
+            // Capture on the context's own stream (the caller's stream may be the
+            // null stream, which cannot be captured); the graph runs on s.
+            hipStream_t cs_stream = ctx->cap;
+            HIP_TRY(hipStreamBeginCapture(cs_stream, hipStreamCaptureModeRelaxed));
+            ctx->launch = cs_stream;
+            int crc = 0;
+            for (int c = 0; c < check && crc == 0; ++c) crc = enqueue_iteration(P, o, c, nullptr, true);
+            ctx->launch = ctx->stream;
+            hipError_t ce = hipStreamEndCapture(cs_stream, &g);
+            if (crc || ce != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+                if (hipStreamIsCapturing(cs_stream, &cst) == hipSuccess && cst != hipStreamCaptureStatusNone) {
+                    hipGraph_t g2 = nullptr;
+                    (void)hipStreamEndCapture(cs_stream, &g2);
+                    if (g2) (void)hipGraphDestroy(g2);
+                }
+                if (crc) return crc;
+                HIP_TRY(ce);
+            }
+            HIP_TRY(hipGetLastError());
+            hipError_t ie = hipGraphInstantiate(&P->graph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIP_TRY(ie);
+            P->graph_key = key;
+        }
+        gexec = P->graph_exec;
     }
     double t_dss = 0, t_coarse = 0, t_prolong = 0, t_krylov = 0;
     int n_dss = 0;
@@ -1153,38 +1290,15 @@ int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* op
     while (!done) {
         const int it_chunk0 = it;
         int n_chunk = 0;
-        for (int c = 0; c < check && it < o.max_it; ++c, ++it, ++n_chunk) {
-            hipEvent_t* ev = o.profile ? &pev[(size_t)c * 5] : nullptr;
-            // ring slots: new direction goes to slot it % nring; previous ones are
-            // it-1, ..., it-m (their q vectors in the same slots).
-            const int cur = it % nring;
-            double* prev_p[MAX_M] = {nullptr, nullptr, nullptr, nullptr};
-            double* prev_q[MAX_M] = {nullptr, nullptr, nullptr, nullptr};
-            int prev_slot[MAX_M] = {0, 0, 0, 0};
-            for (int kk = 0; kk < m; ++kk) {
-                const int sl = ((it - 1 - kk) % nring + nring) % nring;
-                prev_p[kk] = pv[sl];
-                prev_q[kk] = qv[sl];
-                prev_slot[kk] = sl;
-            }
-            const double* zsrc = P->z.p;
-            if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-            if (mode == DDMGNN_CG) {
-                zsrc = P->r.p;
-                if (ev)
-                    for (int q = 1; q < 4; ++q) HIP_TRY(hipEventRecord(ev[q], s));
-            } else {
-                rc = enqueue_apply(P, o, P->r.p, P->z.p, mode, prev_q, prev_slot, m, P->st.p, ev);
+        if (gexec) {
+            HIP_TRY(hipGraphLaunch(gexec, s));
+            it += check;
+            n_chunk = check;
+        } else {
+            for (int c = 0; c < check && it < o.max_it; ++c, ++it, ++n_chunk) {
+                rc = enqueue_iteration(P, o, it, o.profile ? &pev[(size_t)c * 5] : nullptr);
                 if (rc) return rc;
             }
-            hipLaunchKernelGGL(pupdate_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, zsrc, pv[cur], prev_p[0], prev_p[1],
-                               prev_p[2], prev_p[3], (mode == DDMGNN_FCG) ? m : 1, (int)n, P->st.p);
-            hipLaunchKernelGGL(spmv_dots_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, P->rowptr.p, P->col.p, P->val.p,
-                               pv[cur], qv[cur], P->r.p, (int)n, mode, cur, P->partials.p, P->counters.p, P->st.p);
-            hipLaunchKernelGGL(update_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, P->u.p, P->r.p, pv[cur], qv[cur],
-                               (int)n, mode, P->partials.p, P->counters.p, P->st.p);
-            HIP_TRY(hipGetLastError());
-            if (ev) HIP_TRY(hipEventRecord(ev[4], s));
         }
         HIP_TRY(hipMemcpyAsync(ctx->host_pinned, P->st.p, sizeof(KState), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
@@ -1204,7 +1318,7 @@ int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* op
                 t_coarse += b;
                 t_prolong += cc;
                 t_krylov += d;
-                if (mode != DDMGNN_CG) ++n_dss;
+                if (o.krylov != DDMGNN_CG) ++n_dss;
             }
         }
     }
@@ -1222,9 +1336,10 @@ int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* op
     HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
     HIP_TRY(hipEventDestroy(ev0));
     HIP_TRY(hipEventDestroy(ev1));
+    const bool converged = host_state.status == 0 && host_state.rel <= o.rtol;
     if (stats) {
         stats->iterations = host_state.it;
-        stats->converged = host_state.done && host_state.status == 0;
+        stats->converged = converged;
         stats->rel_residual = host_state.rel;
         stats->true_rel_residual = host_state.r0n > 0 ? std::sqrt(tr) / host_state.r0n : 0.0;
         stats->solve_ms = ms;
@@ -1235,7 +1350,7 @@ int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* op
         stats->krylov_ms = t_krylov;
     }
     if (host_state.status) return fail(host_state.status, "Krylov breakdown or non-finite residual");
-    if (!host_state.done) return fail(DDMGNN_E_MAXIT, "not converged within max_it");
+    if (!converged) return fail(DDMGNN_E_MAXIT, "not converged within max_it");
     return DDMGNN_OK;
 }
 

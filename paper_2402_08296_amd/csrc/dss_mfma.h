@@ -12,20 +12,17 @@ namespace ddmgnn {
 constexpr int MFMA_BLOCK = 1024;  // 16 wavefronts, one sub-mesh per workgroup
 constexpr int MFMA_TILE = 32;    // nodes per MFMA tile (the N dimension)
 
-// Per step, per lane of a wavefront: the A operands (8 bf16 per lane, stored
-// as raw bits) of the six 32x16 weight tiles, and the lane's FP32 constants.
-struct MfmaLane {
-    uint16_t aq[8];   // neighbour projections Q' (both message directions)
-    uint16_t ap[8];   // receiver projections P'
-    uint16_t ah[8];   // Psi hidden layer from (h, 1, c, deg)
-    uint16_t asa[8];  // Psi hidden layer from the message sums, units 0..7
-    uint16_t asb[8];  // Psi hidden layer from the message sums, units 8..9
-    uint16_t a2[8];   // Psi output layer
-    float wn[10];     // |d| coefficient of the lane's 10 message units
-    float b2[5];      // Psi output bias of the lane's 5 latent components
-    float pad;
+// Per step: the A operands (8 bf16 per lane, raw bits) of the six 32x16
+// weight tiles and the lanes' FP32 constants, stored structure-of-arrays
+// ([field][lane]) so that the 64 lanes read consecutive addresses. The kernel
+// copies each step's blob into LDS.
+enum { A_Q = 0, A_P = 1, A_H = 2, A_SA = 3, A_SB = 4, A_2 = 5, N_ATILES = 6 };
+struct MfmaStep {
+    uint16_t a[N_ATILES][64][8];  // Q', P', Psi hidden from (h,1,c,deg), from sums 0..7, 8..9, Psi output
+    float wn[10][64];             // |d| coefficient of the lane's 10 message units
+    float b2[5][64];              // Psi output bias of the lane's 5 latent components
 };
-static_assert(sizeof(MfmaLane) == 160, "lane blob layout");
+static_assert(sizeof(MfmaStep) % 16 == 0, "step blob is copied in 16-byte units");
 
 struct MfmaDec {
     uint16_t ad1[8];  // decoder hidden layer from (h, 1)
@@ -35,20 +32,29 @@ struct MfmaDec {
 };
 static_assert(sizeof(MfmaDec) == 48, "decoder blob layout");
 
+// Per slot position in tile order (nodes of a sub-mesh by decreasing
+// in-degree): the node's local id, in-degree, first in-edge, and the bf16 bits
+// of its sub-mesh-centred coordinates split as x = x_hi + x_lo, y = y_hi + y_lo.
+struct TileNode {
+    int32_t e0;
+    uint16_t j;
+    uint16_t deg;
+    uint16_t xh, xl, yh, yl;
+};
+static_assert(sizeof(TileNode) == 16, "tile record layout");
+
 // Builds the per-lane blobs from the flat FP32 weights (layout of ddmgnn.h).
 // The message second layers are folded into the Psi hidden layer
 // (no activation lies between them), and the coordinate terms of the message
 // first layers are split into receiver and sender parts.
-void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaLane>& lanes, std::vector<MfmaDec>& dec);
+void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaStep>& steps, std::vector<MfmaDec>& dec);
 
 struct DssMfmaArgs {
     const int32_t* sub_ptr;
     const int32_t* work_order;
     const int32_t* edge_ptr;     // per slot, in-edge range (global edge index)
-    const uint16_t* edge_src;    // per edge, sender local index (padded by 8 entries)
-    const float* edge_nd;        // per edge, |d_jl| (padded by 8 entries)
-    const uint16_t* tnode;       // per slot position, local node id in tile order (by in-degree)
-    const uint16_t* xyhl;        // per slot, bf16 bits of (x_hi, x_lo, y_hi, y_lo), centred coordinates
+    const uint32_t* erec;        // per edge: sender local index | FP16 bits of |d_jl| << 16
+    const TileNode* tiles;       // per slot position in tile order
     const int32_t* sub_nodes;
     const double* weights;
     const double* r;             // apply: global residual
@@ -56,19 +62,25 @@ struct DssMfmaArgs {
     double* out;
     double* s_out;
     double* y0_out;
-    float* qglobal;              // Q' storage when it does not fit LDS (20 floats per slot)
     const int* done;             // Krylov converged flag (may be null)
-    const MfmaLane* lanes;
+    const MfmaStep* steps;
     const MfmaDec* dec;
     int kbar;
     float alpha;
     int apply;
-    int q_in_lds;
 };
 
-// LDS bytes needed for a sub-mesh of k nodes with Q' in LDS.
-inline size_t mfma_lds_bytes(int k) { return (size_t)k * (20 + 1) * sizeof(float); }
+// LDS of a workgroup: c (k floats, padded to 4), Q' (k x 48 bytes), edge
+// records (ne + 4 uint32). A problem whose largest need exceeds the limit is
+// not run by this kernel.
+constexpr size_t MFMA_LDS_LIMIT = 160 * 1024 - 1024;
+inline size_t mfma_lds_need(int k, int64_t ne) {
+    return (size_t)((k + 3) & ~3) * 4 + (size_t)k * 48 + (size_t)(ne + 4) * 4;
+}
 
-hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_sub, size_t shmem, hipStream_t stream);
+// Sets the dynamic-LDS limit of the kernel (not allowed during stream capture).
+hipError_t prepare_dss_mfma(size_t shmem);
+// check = false skips hipGetLastError (used while a stream is being captured).
+hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_sub, size_t shmem, hipStream_t stream, bool check);
 
 }  // namespace ddmgnn

@@ -40,6 +40,7 @@ constexpr int OFF_PI = OFF_PO + D * IN_PHI + D + D * D + D;
 constexpr int OFF_PS = OFF_PI + D * IN_PHI + D + D * D + D;
 constexpr int OFF_DE = OFF_PS + D * IN_PSI + D + D * D + D;
 constexpr int BLOCK_W = OFF_DE + D * D + D + D + 1;
+constexpr int EC = 4;  // edges per straight-line chunk of the message sums
 constexpr int MAX_TILES_PER_WAVE = (2048 / MFMA_TILE + (MFMA_BLOCK / 64) - 1) / (MFMA_BLOCK / 64);
 
 // Round-to-nearest-even float -> bf16 bits (host).
@@ -72,8 +73,8 @@ inline int row_item(int r) { return 4 * (r / 8) + r % 4; }
 
 }  // namespace
 
-void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaLane>& lanes, std::vector<MfmaDec>& dec) {
-    lanes.assign((size_t)kbar * 64, MfmaLane{});
+void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaStep>& steps, std::vector<MfmaDec>& dec) {
+    steps.assign((size_t)kbar, MfmaStep{});
     std::vector<double> A(32 * 16);
     auto put = [&](uint16_t* dst, int lane) {
         const int row = lane % 32, k0 = 8 * (lane / 32);
@@ -103,7 +104,7 @@ void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaLane>& lanes
                 for (int v = 0; v < D; ++v) degb[u] += P1(u, off + v) * B2(dir, v);
             }
         }
-        MfmaLane* L = &lanes[(size_t)step * 64];
+        MfmaStep& L = steps[(size_t)step];
         // Q' and P' tiles: row r -> (direction, unit) = (row_half, row_item) for items < 10.
         for (int which = 0; which < 2; ++which) {  // 0: Q', 1: P'
             std::fill(A.begin(), A.end(), 0.0);
@@ -122,7 +123,7 @@ void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaLane>& lanes
                     A[r * 16 + k] = v;
                 }
             }
-            for (int lane = 0; lane < 64; ++lane) put(which == 0 ? L[lane].aq : L[lane].ap, lane);
+            for (int lane = 0; lane < 64; ++lane) put(L.a[which == 0 ? A_Q : A_P][lane], lane);
         }
         // Psi hidden layer: output row r -> unit 5*row_half + row_item for items < 5.
         auto hidden_unit = [](int r) { return row_item(r) < 5 ? 5 * row_half(r) + row_item(r) : -1; };
@@ -141,7 +142,7 @@ void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaLane>& lanes
                 A[r * 16 + k] = v;
             }
         }
-        for (int lane = 0; lane < 64; ++lane) put(L[lane].ah, lane);
+        for (int lane = 0; lane < 64; ++lane) put(L.a[A_H][lane], lane);
         for (int part = 0; part < 2; ++part) {  // message sums, units 0..7 then 8..9
             std::fill(A.begin(), A.end(), 0.0);
             for (int r = 0; r < 32; ++r) {
@@ -154,7 +155,7 @@ void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaLane>& lanes
                     A[r * 16 + k] = M[dir][u][w];
                 }
             }
-            for (int lane = 0; lane < 64; ++lane) put(part == 0 ? L[lane].asa : L[lane].asb, lane);
+            for (int lane = 0; lane < 64; ++lane) put(L.a[part == 0 ? A_SA : A_SB][lane], lane);
         }
         // Psi output layer: output rows as hidden units, input k -> hidden unit 5*(k/8) + k%8.
         std::fill(A.begin(), A.end(), 0.0);
@@ -164,11 +165,11 @@ void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaLane>& lanes
             for (int k = 0; k < 16; ++k)
                 if (k % 8 < 5) A[r * 16 + k] = P2(o, 5 * (k / 8) + k % 8);
         }
-        for (int lane = 0; lane < 64; ++lane) put(L[lane].a2, lane);
+        for (int lane = 0; lane < 64; ++lane) put(L.a[A_2][lane], lane);
         for (int lane = 0; lane < 64; ++lane) {
             const int hf = lane / 32;
-            for (int t = 0; t < D; ++t) L[lane].wn[t] = (float)W1(hf, t, 2 * D + 2);
-            for (int t = 0; t < 5; ++t) L[lane].b2[t] = (float)PB2(5 * hf + t);
+            for (int t = 0; t < D; ++t) L.wn[t][lane] = (float)W1(hf, t, 2 * D + 2);
+            for (int t = 0; t < 5; ++t) L.b2[t][lane] = (float)PB2(5 * hf + t);
         }
     }
     // Decoder of the last block.
@@ -251,9 +252,16 @@ __device__ inline bf16x8 b_psi(const float (&h)[5], float c, float deg, int hf, 
     return b;
 }
 
-// QLDS: the Q' table lives in LDS (compile-time, so accesses are ds_* rather
-// than flat); otherwise it lives in a per-slot global buffer.
-template <bool QLDS>
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+__device__ inline h2 pk(float x, float y) { return (h2){(_Float16)x, (_Float16)y}; }
+
+// One workgroup per sub-mesh, everything the kbar blocks touch in LDS:
+//   c   [k]        normalised residual (FP32)
+//   Q'  [k][2][12] neighbour projections (FP16; 10 used per direction, rows
+//                  padded to 48 bytes for aligned 8-byte reads)
+//   E   [ne + EC]  in-edges of the sub-mesh: sender id | FP16 |d| << 16
+// The message sums run in packed FP16 (two units per instruction).
 __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     if (a.done && *a.done) return;
     extern __shared__ float lds[];
@@ -262,8 +270,12 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     const int base = a.sub_ptr[sub];
     const int k = a.sub_ptr[sub + 1] - base;
     const int tid = threadIdx.x;
-    float* cbuf = lds;                                   // [k] normalised residual c
-    float* Q = QLDS ? lds + k : a.qglobal + (size_t)base * 20;  // [k][2][10]
+    const int ebase = a.edge_ptr[base];
+    const int ne = a.edge_ptr[base + k] - ebase;
+    float* cbuf = lds;
+    _Float16* Q = reinterpret_cast<_Float16*>(lds + ((k + 3) & ~3));
+    uint32_t* E = reinterpret_cast<uint32_t*>(Q + (size_t)k * 24);
+    for (int i = tid; i < ne + EC; i += MFMA_BLOCK) E[i] = i < ne ? a.erec[ebase + i] : 0u;
 
     // Restriction and normalisation (Sec. III.A step 2).
     double s = 1.0;
@@ -300,98 +312,110 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt)
 #pragma unroll
         for (int t = 0; t < 5; ++t) h[tt][t] = 0.0f;
-    const uint32_t* xy32 = reinterpret_cast<const uint32_t*>(a.xyhl);
     const f32x16 zero = {};
+    const h2 hzero = {(_Float16)0.0f, (_Float16)0.0f};
 
     for (int step = 0; step < a.kbar; ++step) {
-        const MfmaLane* L = a.lanes + (size_t)step * 64 + lane;
-        // Phase A: neighbour projections Q' -> LDS.
+        const MfmaStep* L = a.steps + step;
+        // Phase A: neighbour projections Q' -> LDS (FP16).
         {
-            const bf16x8 AQ = load_a(L->aq);
+            const bf16x8 AQ = load_a(L->a[A_Q][lane]);
 #pragma unroll
             for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt) {
                 const int tile = wave + (MFMA_BLOCK / 64) * tt;
                 if (tile >= ntiles) break;
                 const int p = tile * MFMA_TILE + n;
                 const bool valid = p < k;
-                const int j = valid ? a.tnode[base + p] : 0;
-                const uint32_t xy2 = valid ? xy32[2 * (base + j) + hf] : 0u;
+                const TileNode tn = a.tiles[base + (valid ? p : 0)];
+                const uint32_t xy2 = hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
                 const f32x16 q = mfma(AQ, b_pq(h[tt], xy2, hf, valid), zero);
                 if (valid) {
-                    float* dst = Q + j * 20 + 10 * hf;
+                    h2* dst = reinterpret_cast<h2*>(Q + tn.j * 24 + 12 * hf);
 #pragma unroll
-                    for (int t = 0; t < 10; t += 2) *reinterpret_cast<float2*>(dst + t) = make_float2(q[t], q[t + 1]);
+                    for (int t = 0; t < 5; ++t) dst[t] = pk(q[2 * t], q[2 * t + 1]);
                 }
             }
         }
         __syncthreads();
         // Phase B: receiver projections, edge sums, Psi update.
         {
-            const bf16x8 AP = load_a(L->ap), AH = load_a(L->ah), ASA = load_a(L->asa), ASB = load_a(L->asb),
-                         A2 = load_a(L->a2);
-            float wn[10], b2[5];
+            const bf16x8 AP = load_a(L->a[A_P][lane]);
+            h2 wn[5];
 #pragma unroll
-            for (int t = 0; t < 10; ++t) wn[t] = L->wn[t];
-#pragma unroll
-            for (int t = 0; t < 5; ++t) b2[t] = L->b2[t];
+            for (int t = 0; t < 5; ++t) wn[t] = pk(L->wn[2 * t][lane], L->wn[2 * t + 1][lane]);
 #pragma unroll
             for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt) {
                 const int tile = wave + (MFMA_BLOCK / 64) * tt;
                 if (tile >= ntiles) break;
                 const int p = tile * MFMA_TILE + n;
                 const bool valid = p < k;
-                const int j = valid ? a.tnode[base + p] : 0;
-                const uint32_t xy2 = valid ? xy32[2 * (base + j) + hf] : 0u;
-                const f32x16 P = mfma(AP, b_pq(h[tt], xy2, hf, valid), zero);
-                float S[10];
+                const TileNode tn = a.tiles[base + (valid ? p : 0)];
+                const int j = tn.j;
+                const uint32_t xy2 = hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
+                const f32x16 Pf = mfma(AP, b_pq(h[tt], xy2, hf, valid), zero);
+                h2 P[5], S[5];
 #pragma unroll
-                for (int t = 0; t < 10; ++t) S[t] = 0.0f;
-                int deg = 0;
-                if (valid) {
-                    const int e0 = a.edge_ptr[base + j], e1 = a.edge_ptr[base + j + 1];
-                    deg = e1 - e0;
-                    // chunks of 4 edges: loads first (arrays padded past the end), then the sums
-                    for (int e = e0; e < e1; e += 4) {
-                        int ls[4];
-                        float nds[4];
+                for (int t = 0; t < 5; ++t) {
+                    P[t] = pk(Pf[2 * t], Pf[2 * t + 1]);
+                    S[t] = hzero;
+                }
+                const int deg = valid ? (int)tn.deg : 0;
+                const int e0 = tn.e0 - ebase, e1 = e0 + deg;
+                // Chunks of EC edges as straight-line code: all LDS reads of the
+                // chunk are issued before the sums; an edge past e1 reads the
+                // node's own row (E is padded) and is masked with a 0 weight.
+                for (int e = e0; e < e1; e += EC) {
+                    uint32_t rec[EC];
+                    h2 msk[EC];
 #pragma unroll
-                        for (int w = 0; w < 4; ++w) {
-                            ls[w] = a.edge_src[e + w];
-                            nds[w] = a.edge_nd[e + w];
-                        }
+                    for (int w = 0; w < EC; ++w) {
+                        const bool in = e + w < e1;
+                        const uint32_t r0 = E[e + w];
+                        rec[w] = in ? r0 : (uint32_t)j;
+                        msk[w] = in ? (h2){(_Float16)1.0f, (_Float16)1.0f} : hzero;
+                    }
+                    h2 qq[EC][5];
 #pragma unroll
-                        for (int w = 0; w < 4; ++w) {
-                            if (e + w >= e1) break;
-                            const float* q = Q + ls[w] * 20 + 10 * hf;
+                    for (int w = 0; w < EC; ++w) {
+                        const h2* q = reinterpret_cast<const h2*>(Q + (rec[w] & 0xffffu) * 24 + 12 * hf);
 #pragma unroll
-                            for (int t = 0; t < 10; t += 2) {
-                                const float2 qq = *reinterpret_cast<const float2*>(q + t);
-                                S[t] += fmaxf(fmaf(wn[t], nds[w], P[t] + qq.x), 0.0f);
-                                S[t + 1] += fmaxf(fmaf(wn[t + 1], nds[w], P[t + 1] + qq.y), 0.0f);
-                            }
+                        for (int t = 0; t < 5; ++t) qq[w][t] = q[t];
+                    }
+#pragma unroll
+                    for (int w = 0; w < EC; ++w) {
+                        const _Float16 ndh = __builtin_bit_cast(_Float16, (uint16_t)(rec[w] >> 16));
+                        const h2 nd = {ndh, ndh};
+#pragma unroll
+                        for (int t = 0; t < 5; ++t) {
+                            const h2 v = __builtin_elementwise_max(__builtin_elementwise_fma(wn[t], nd, P[t] + qq[w][t]),
+                                                                   hzero);
+                            S[t] = __builtin_elementwise_fma(msk[w], v, S[t]);
                         }
                     }
                 }
                 const float c = valid ? cbuf[j] : 0.0f;
                 bf16x8 sa, sb;
 #pragma unroll
-                for (int m = 0; m < 8; ++m) sa[m] = (__bf16)S[m];
-                sb[0] = (__bf16)S[8];
-                sb[1] = (__bf16)S[9];
+                for (int t = 0; t < 4; ++t) {
+                    sa[2 * t] = (__bf16)(float)S[t][0];
+                    sa[2 * t + 1] = (__bf16)(float)S[t][1];
+                }
+                sb[0] = (__bf16)(float)S[4][0];
+                sb[1] = (__bf16)(float)S[4][1];
 #pragma unroll
                 for (int m = 2; m < 8; ++m) sb[m] = (__bf16)0.0f;
-                f32x16 hid = mfma(AH, b_psi(h[tt], c, (float)deg, hf, valid), zero);
-                hid = mfma(ASA, sa, hid);
-                hid = mfma(ASB, sb, hid);
+                f32x16 hid = mfma(load_a(L->a[A_H][lane]), b_psi(h[tt], c, (float)deg, hf, valid), zero);
+                hid = mfma(load_a(L->a[A_SA][lane]), sa, hid);
+                hid = mfma(load_a(L->a[A_SB][lane]), sb, hid);
                 bf16x8 bh;
 #pragma unroll
                 for (int m = 0; m < 5; ++m) bh[m] = (__bf16)fmaxf(hid[m], 0.0f);
 #pragma unroll
                 for (int m = 5; m < 8; ++m) bh[m] = (__bf16)0.0f;
-                const f32x16 o = mfma(A2, bh, zero);
+                const f32x16 o = mfma(load_a(L->a[A_2][lane]), bh, zero);
                 if (valid) {
 #pragma unroll
-                    for (int t = 0; t < 5; ++t) h[tt][t] = fmaf(a.alpha, o[t] + b2[t], h[tt][t]);
+                    for (int t = 0; t < 5; ++t) h[tt][t] = fmaf(a.alpha, o[t] + L->b2[t][lane], h[tt][t]);
                 }
             }
         }
@@ -408,7 +432,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
         if (tile >= ntiles) break;
         const int p = tile * MFMA_TILE + n;
         const bool valid = p < k;
-        const int j = valid ? a.tnode[base + p] : 0;
+        const TileNode tn = a.tiles[base + (valid ? p : 0)];
         const f32x16 hd = mfma(AD1, b_psi(h[tt], 0.0f, 0.0f, hf, valid), zero);
         bf16x8 bh;
 #pragma unroll
@@ -418,22 +442,20 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
         const f32x16 o = mfma(AD2, bh, zero);
         if (valid && hf == 0) {
             const double r_tilde = (double)(o[0] + bd2);
-            a.out[base + j] = a.apply ? s * r_tilde : r_tilde;
+            a.out[base + tn.j] = a.apply ? s * r_tilde : r_tilde;
         }
     }
 }
 
 }  // namespace
 
-hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_sub, size_t shmem, hipStream_t stream) {
-    const void* fn = a.q_in_lds ? (const void*)dss_mfma_kernel<true> : (const void*)dss_mfma_kernel<false>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-    if (e != hipSuccess) return e;
-    if (a.q_in_lds)
-        hipLaunchKernelGGL(dss_mfma_kernel<true>, dim3(n_sub), dim3(MFMA_BLOCK), shmem, stream, a);
-    else
-        hipLaunchKernelGGL(dss_mfma_kernel<false>, dim3(n_sub), dim3(MFMA_BLOCK), shmem, stream, a);
-    return hipGetLastError();
+hipError_t prepare_dss_mfma(size_t shmem) {
+    return hipFuncSetAttribute((const void*)dss_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+}
+
+hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_sub, size_t shmem, hipStream_t stream, bool check) {
+    hipLaunchKernelGGL(dss_mfma_kernel, dim3(n_sub), dim3(MFMA_BLOCK), shmem, stream, a);
+    return check ? hipGetLastError() : hipSuccess;
 }
 
 }  // namespace ddmgnn

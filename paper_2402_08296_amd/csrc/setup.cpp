@@ -195,6 +195,8 @@ void build_local_graphs(const ddmgnn_problem_desc& d, HostSetup& s) {
     s.tnode.assign(s.sk, 0);
     s.xyhl.assign(4 * s.sk, 0);
     s.xyc.assign(2 * s.sk, 0.0);
+    s.erec.assign(s.n_edges, 0u);
+    s.max_edges_sub = 0;
     s.edge_nd.assign(s.n_edges, 0.0f);
     std::vector<int32_t> ord;
     for (int32_t i = 0; i < K; ++i) {
@@ -229,8 +231,13 @@ void build_local_graphs(const ddmgnn_problem_desc& d, HostSetup& s) {
                 const int32_t l = d.sub_nodes[b + s.edge_src[t]];
                 const double dx = d.xy[2 * l] - d.xy[2 * j], dy = d.xy[2 * l + 1] - d.xy[2 * j + 1];
                 s.edge_nd[t] = (float)std::sqrt(dx * dx + dy * dy);
+                const _Float16 hnd = (_Float16)s.edge_nd[t];
+                uint16_t bits;
+                std::memcpy(&bits, &hnd, 2);
+                s.erec[t] = (uint32_t)s.edge_src[t] | ((uint32_t)bits << 16);
             }
         }
+        s.max_edges_sub = std::max<int64_t>(s.max_edges_sub, s.edge_ptr[e] - s.edge_ptr[b]);
     }
 }
 

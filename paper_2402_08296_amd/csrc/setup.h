@@ -43,6 +43,8 @@ struct HostSetup {
     std::vector<uint16_t> tnode;
     std::vector<uint16_t> xyhl;
     std::vector<double> xyc;   // per slot, coordinates relative to the sub-mesh centroid
+    std::vector<uint32_t> erec;  // per edge: sender local id | FP16 bits of |d_jl| << 16
+    int64_t max_edges_sub = 0;   // largest in-edge count of a sub-mesh
     std::vector<float> edge_nd;
 };
 

@@ -219,6 +219,24 @@ def test_solve_bf16_converges_to_tolerance(ctx, c1):
     assert err <= 1e-4
 
 
+def test_graph_replay_matches_eager(ctx, c1):
+    """Chunks of iterations replayed as a captured graph give the eager result, bit for bit."""
+    print("[gpu] graph replay", flush=True)
+    p, hp = c1
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, SMOOTHER))
+    ue = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    ug = torch.empty_like(ue)
+    z = torch.empty_like(ue)
+    r = _dev(np.random.default_rng(9).standard_normal(p.n))
+    for prec in ("fp32", "bf16"):
+        st_e = prob.solve(ue, dg.default_opts(precision=prec, graph=0, check_every=4))
+        for rep in range(3):
+            st_g = prob.solve(ug, dg.default_opts(precision=prec, graph=1, check_every=4))
+            assert st_g.iterations == st_e.iterations and torch.equal(ug, ue), (prec, rep)
+            prob.apply(r, z, dg.default_opts(precision=prec))  # eager work between replays
+            torch.cuda.synchronize()
+
+
 def test_krylov_modes(ctx, c1):
     print("[gpu] cg/pcg", flush=True)
     p, hp = c1
