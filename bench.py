@@ -145,6 +145,7 @@ def main():
         st = prob.solve(u, opts, check=False)
         stats.append((st.iterations, st.converged, st.true_rel_residual, st.solve_ms, st.dss_launches, st.dss_ms,
                       st.coarse_ms, st.prolong_ms, st.krylov_ms))
+        dss_kernel = {0: "dss_kernel<double>", 1: "dss_kernel<float>", 2: "dss_mfma_kernel"}[st.dss_kernel]
         log(f"step {k}: iterations={st.iterations} converged={st.converged} true_rel={st.true_rel_residual:.2e} "
             f"solve_ms={st.solve_ms:.1f}")
     torch.cuda.synchronize()
@@ -188,7 +189,7 @@ def main():
         "breakdown_ms_per_iteration": {
             "dss": dss_ms / max(1, dss_launches), "coarse": coarse_ms / max(1, dss_launches),
             "prolong": prolong_ms / max(1, dss_launches), "krylov": krylov_ms / max(1, dss_launches)},
-        "roofline": {"kernel": "dss_kernel", "bound": "alu", "achieved": achieved,
+        "roofline": {"kernel": dss_kernel, "bound": "alu", "achieved": achieved,
                      "peak": PEAK_TFLOPS[args.precision], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS[args.precision], "traffic": None,
                      "flops_per_launch": flops, "avg_launch_ms": dss_avg_ms},

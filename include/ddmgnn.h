@@ -163,6 +163,8 @@ typedef struct {
     double coarse_ms;          /* coarse solve (step 1) */
     double prolong_ms;         /* gluing (step 3) with its fused dot products */
     double krylov_ms;          /* direction update, SpMV with dots, solution update */
+    int32_t dss_kernel;        /* kernel that ran the DSS forward: 0 FP64 VALU, 1 FP32 VALU,
+                                * 2 BF16 MFMA (BF16 falls back to 1 when a sub-mesh exceeds its LDS budget) */
 } ddmgnn_stats;
 
 /* Fill opts with defaults (FCG, m_max 1, rtol 1e-6, max_it 10000, FP32, POU, coarse on,

@@ -51,7 +51,7 @@ class SolveOpts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("converged", _i32), ("rel_residual", _f64),
                 ("true_rel_residual", _f64), ("solve_ms", _f64), ("dss_launches", _i32), ("dss_ms", _f64),
-                ("coarse_ms", _f64), ("prolong_ms", _f64), ("krylov_ms", _f64)]
+                ("coarse_ms", _f64), ("prolong_ms", _f64), ("krylov_ms", _f64), ("dss_kernel", _i32)]
 
 
 _lib = None

@@ -1348,6 +1348,7 @@ int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* op
         stats->coarse_ms = t_coarse;
         stats->prolong_ms = t_prolong;
         stats->krylov_ms = t_krylov;
+        stats->dss_kernel = o.precision == DDMGNN_FP64 ? 0 : (o.precision == DDMGNN_BF16 && P->mfma_fits ? 2 : 1);
     }
     if (host_state.status) return fail(host_state.status, "Krylov breakdown or non-finite residual");
     if (!converged) return fail(DDMGNN_E_MAXIT, "not converged within max_it");

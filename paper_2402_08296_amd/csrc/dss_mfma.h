@@ -71,11 +71,11 @@ struct DssMfmaArgs {
 };
 
 // LDS of a workgroup: c (k floats, padded to 4), Q' (k x 48 bytes), edge
-// records (ne + 4 uint32). A problem whose largest need exceeds the limit is
-// not run by this kernel.
+// records (ne + 4 uint32, padded to 4), tile records (k x 16 bytes). A
+// problem whose largest need exceeds the limit is not run by this kernel.
 constexpr size_t MFMA_LDS_LIMIT = 160 * 1024 - 1024;
 inline size_t mfma_lds_need(int k, int64_t ne) {
-    return (size_t)((k + 3) & ~3) * 4 + (size_t)k * 48 + (size_t)(ne + 4) * 4;
+    return (size_t)((k + 3) & ~3) * 4 + (size_t)k * 48 + (size_t)((ne + 4 + 3) & ~3) * 4 + (size_t)k * 16;
 }
 
 // Sets the dynamic-LDS limit of the kernel (not allowed during stream capture).

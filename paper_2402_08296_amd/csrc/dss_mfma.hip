@@ -261,6 +261,7 @@ __device__ inline h2 pk(float x, float y) { return (h2){(_Float16)x, (_Float16)y
 //   Q'  [k][2][12] neighbour projections (FP16; 10 used per direction, rows
 //                  padded to 48 bytes for aligned 8-byte reads)
 //   E   [ne + EC]  in-edges of the sub-mesh: sender id | FP16 |d| << 16
+//   T   [k]        tile records (node id, degree, first edge, split coordinates)
 // The message sums run in packed FP16 (two units per instruction).
 __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     if (a.done && *a.done) return;
@@ -275,7 +276,10 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     float* cbuf = lds;
     _Float16* Q = reinterpret_cast<_Float16*>(lds + ((k + 3) & ~3));
     uint32_t* E = reinterpret_cast<uint32_t*>(Q + (size_t)k * 24);
+    TileNode* T = reinterpret_cast<TileNode*>(E + ((ne + EC + 3) & ~3));
     for (int i = tid; i < ne + EC; i += MFMA_BLOCK) E[i] = i < ne ? a.erec[ebase + i] : 0u;
+    for (int i = tid; i < k; i += MFMA_BLOCK)
+        reinterpret_cast<uint4*>(T)[i] = reinterpret_cast<const uint4*>(a.tiles + base)[i];
 
     // Restriction and normalisation (Sec. III.A step 2).
     double s = 1.0;
@@ -326,7 +330,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                 if (tile >= ntiles) break;
                 const int p = tile * MFMA_TILE + n;
                 const bool valid = p < k;
-                const TileNode tn = a.tiles[base + (valid ? p : 0)];
+                const TileNode tn = T[valid ? p : 0];
                 const uint32_t xy2 = hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
                 const f32x16 q = mfma(AQ, b_pq(h[tt], xy2, hf, valid), zero);
                 if (valid) {
@@ -349,10 +353,13 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                 if (tile >= ntiles) break;
                 const int p = tile * MFMA_TILE + n;
                 const bool valid = p < k;
-                const TileNode tn = a.tiles[base + (valid ? p : 0)];
+                const TileNode tn = T[valid ? p : 0];
                 const int j = tn.j;
                 const uint32_t xy2 = hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
                 const f32x16 Pf = mfma(AP, b_pq(h[tt], xy2, hf, valid), zero);
+                // Psi weights, fetched now so their latency overlaps the edge sums
+                const bf16x8 AH = load_a(L->a[A_H][lane]), ASA = load_a(L->a[A_SA][lane]);
+                const bf16x8 ASB = load_a(L->a[A_SB][lane]), A2 = load_a(L->a[A_2][lane]);
                 h2 P[5], S[5];
 #pragma unroll
                 for (int t = 0; t < 5; ++t) {
@@ -404,15 +411,15 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                 sb[1] = (__bf16)(float)S[4][1];
 #pragma unroll
                 for (int m = 2; m < 8; ++m) sb[m] = (__bf16)0.0f;
-                f32x16 hid = mfma(load_a(L->a[A_H][lane]), b_psi(h[tt], c, (float)deg, hf, valid), zero);
-                hid = mfma(load_a(L->a[A_SA][lane]), sa, hid);
-                hid = mfma(load_a(L->a[A_SB][lane]), sb, hid);
+                f32x16 hid = mfma(AH, b_psi(h[tt], c, (float)deg, hf, valid), zero);
+                hid = mfma(ASA, sa, hid);
+                hid = mfma(ASB, sb, hid);
                 bf16x8 bh;
 #pragma unroll
                 for (int m = 0; m < 5; ++m) bh[m] = (__bf16)fmaxf(hid[m], 0.0f);
 #pragma unroll
                 for (int m = 5; m < 8; ++m) bh[m] = (__bf16)0.0f;
-                const f32x16 o = mfma(load_a(L->a[A_2][lane]), bh, zero);
+                const f32x16 o = mfma(A2, bh, zero);
                 if (valid) {
 #pragma unroll
                     for (int t = 0; t < 5; ++t) h[tt][t] = fmaf(a.alpha, o[t] + L->b2[t][lane], h[tt][t]);
@@ -432,7 +439,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
         if (tile >= ntiles) break;
         const int p = tile * MFMA_TILE + n;
         const bool valid = p < k;
-        const TileNode tn = a.tiles[base + (valid ? p : 0)];
+        const TileNode tn = T[valid ? p : 0];
         const f32x16 hd = mfma(AD1, b_psi(h[tt], 0.0f, 0.0f, hf, valid), zero);
         bf16x8 bh;
 #pragma unroll
