@@ -57,7 +57,7 @@ constexpr int BLOCK_W = OFF_DE + D * D + D + D + 1;  // 11 d^2 + 15 d + 1
 static_assert(BLOCK_W == 1251, "weight block size");
 
 constexpr int VEC_BLOCK = 256;   // threads of the vector kernels
-constexpr int VEC_GRID = 1024;   // max workgroups of the vector kernels (partials per dot)
+constexpr int VEC_GRID = 2048;   // max workgroups of the vector kernels (partials per dot)
 constexpr int MAX_M = 4;         // largest FCG truncation supported
 constexpr int DSS_BLOCK = 512;
 constexpr int DSS_NPT = (ddmgnn::kMaxSubNodes + DSS_BLOCK - 1) / DSS_BLOCK;
@@ -542,6 +542,48 @@ __global__ __launch_bounds__(VEC_BLOCK) void spmv_dots_kernel(const int32_t* __r
     st->alpha = (mode == DDMGNN_FCG ? tot[1] : st->rho) / pq;
 }
 
+// One truncation direction (FCG(1), PCG, CG): p_new = z + beta p_old is formed
+// on the fly for every column, q = A p_new, with the dots of spmv_dots_kernel.
+// Every row evaluates fma(beta, p_old, z) identically, so q is exactly A times
+// the stored p_new.
+__global__ __launch_bounds__(VEC_BLOCK) void spmv_p_dots_kernel(const int32_t* __restrict__ rowptr,
+                                                               const int32_t* __restrict__ col,
+                                                               const double* __restrict__ val,
+                                                               const double* __restrict__ z,
+                                                               const double* __restrict__ p_old,
+                                                               double* __restrict__ p_new, double* __restrict__ q,
+                                                               const double* __restrict__ r, int n, int mode, int slot,
+                                                               double* partials, unsigned* counter, KState* st) {
+    if (st->done) return;
+    __shared__ double sh[VEC_BLOCK / 64 + 1];
+    const double beta = st->beta[0];
+    double d[2] = {0.0, 0.0};
+    for (int i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
+        double acc = 0.0;
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            const int c = col[e];
+            acc = fma(val[e], fma(beta, p_old[c], z[c]), acc);
+        }
+        const double pi = fma(beta, p_old[i], z[i]);
+        p_new[i] = pi;
+        q[i] = acc;
+        d[0] = fma(pi, acc, d[0]);
+        d[1] = fma(pi, r[i], d[1]);
+    }
+    double tot[2];
+    if (!grid_sum<2, VEC_BLOCK>(d, partials, counter, tot, sh)) return;
+    if (threadIdx.x != 0) return;
+    const double pq = tot[0];
+    st->pq[slot] = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        st->status = isfinite(pq) ? DDMGNN_E_BREAKDOWN : DDMGNN_E_NONFINITE;
+        st->done = 1;
+        st->alpha = 0.0;
+        return;
+    }
+    st->alpha = (mode == DDMGNN_FCG ? tot[1] : st->rho) / pq;
+}
+
 // u += alpha p; r -= alpha q; convergence test on |r| / |r_0|.
 __global__ __launch_bounds__(VEC_BLOCK) void update_kernel(double* __restrict__ u, double* __restrict__ r,
                                                           const double* __restrict__ p,
@@ -894,10 +936,16 @@ int enqueue_iteration(ddmgnn_problem* P, const ddmgnn_solve_opts& o, int it, hip
         int rc = enqueue_apply(P, o, P->r.p, P->z.p, mode, prev_q, prev_slot, m, P->st.p, ev, capturing);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(pupdate_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, zsrc, pv_cur, prev_p[0], prev_p[1],
-                       prev_p[2], prev_p[3], (mode == DDMGNN_FCG) ? m : 1, (int)n, P->st.p);
-    hipLaunchKernelGGL(spmv_dots_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, P->rowptr.p, P->col.p, P->val.p, pv_cur,
-                       qv_cur, P->r.p, (int)n, mode, cur, P->partials.p, P->counters.p, P->st.p);
+    if (m == 1) {
+        hipLaunchKernelGGL(spmv_p_dots_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, P->rowptr.p, P->col.p, P->val.p,
+                           zsrc, prev_p[0], pv_cur, qv_cur, P->r.p, (int)n, mode, cur, P->partials.p, P->counters.p,
+                           P->st.p);
+    } else {
+        hipLaunchKernelGGL(pupdate_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, zsrc, pv_cur, prev_p[0], prev_p[1],
+                           prev_p[2], prev_p[3], m, (int)n, P->st.p);
+        hipLaunchKernelGGL(spmv_dots_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, P->rowptr.p, P->col.p, P->val.p,
+                           pv_cur, qv_cur, P->r.p, (int)n, mode, cur, P->partials.p, P->counters.p, P->st.p);
+    }
     hipLaunchKernelGGL(update_kernel, dim3(grid), dim3(VEC_BLOCK), 0, s, P->u.p, P->r.p, pv_cur, qv_cur, (int)n, mode,
                        P->partials.p, P->counters.p, P->st.p);
     if (!capturing) HIP_TRY(hipGetLastError());
