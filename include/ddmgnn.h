@@ -22,7 +22,8 @@
  *     results (solve, apply, forward, spmv) synchronise that stream before
  *     returning.
  *   - Handles are owned by the library until the matching *_destroy call.
- *     One context per host thread.
+ *     One context per host thread. Destroy a context's problems, models and
+ *     server before the context.
  */
 #ifndef DDMGNN_H
 #define DDMGNN_H
@@ -58,6 +59,7 @@ enum { DDMGNN_PROLONG_POU = 0, DDMGNN_PROLONG_UNWEIGHTED = 1 };
 typedef struct ddmgnn_ctx ddmgnn_ctx;
 typedef struct ddmgnn_model ddmgnn_model;
 typedef struct ddmgnn_problem ddmgnn_problem;
+typedef struct ddmgnn_server ddmgnn_server;
 
 /* Text of the last error on this thread (empty when none). */
 const char* ddmgnn_last_error(void);
@@ -83,7 +85,8 @@ typedef struct {
  *   Phi_in  {W1[d][2d+3], b1[d], W2[d][d], b2[d]}   inputs (h_j, h_l, d_lj, |d_lj|)
  *   Psi     {W1[d][3d+1], b1[d], W2[d][d], b2[d]}   inputs (h_j, c_j, phi_out_j, phi_in_j)
  *   Dec     {W1[d][d],    b1[d], W2[1][d], b2[1]}   input  h_j
- * (eqs. (14)-(18)). Copied at call time. */
+ * (eqs. (14)-(18)). Copied at call time (to the host and to the device). Problems
+ * keep a reference to the device copy, so the model may be destroyed before them. */
 int ddmgnn_model_create(ddmgnn_ctx* ctx, const ddmgnn_model_desc* desc, const float* theta,
                         int64_t n_theta, ddmgnn_model** out);
 int ddmgnn_model_destroy(ddmgnn_model* model);
@@ -165,6 +168,9 @@ typedef struct {
     double krylov_ms;          /* direction update, SpMV with dots, solution update */
     int32_t dss_kernel;        /* kernel that ran the DSS forward: 0 FP64 VALU, 1 FP32 VALU,
                                 * 2 BF16 MFMA (BF16 falls back to 1 when a sub-mesh exceeds its LDS budget) */
+    int32_t status;            /* this problem's own status (DDMGNN_OK, E_MAXIT, E_BREAKDOWN, ...) */
+    double latency_ms;         /* served requests: completion - submission (host clock);
+                                * solves: equal to solve_ms */
 } ddmgnn_stats;
 
 /* Fill opts with defaults (FCG, m_max 1, rtol 1e-6, max_it 10000, FP32, POU, coarse on,
@@ -175,6 +181,44 @@ void ddmgnn_default_opts(ddmgnn_solve_opts* opts);
  * E_MAXIT / E_NONFINITE / E_BREAKDOWN u_out holds the last finite iterate. */
 int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const ddmgnn_solve_opts* opts, double* u_out,
                  ddmgnn_stats* stats);
+
+/* Solve n independent problems together (all created on ctx with the same
+ * model): every kernel of an iteration is one launch over all of them, the
+ * DSS forward over all their sub-meshes by decreasing size, and each problem
+ * stops under its own converged flag (its workgroups return at once while
+ * the others continue). u_out[i]: device, N_i doubles; stats (may be NULL):
+ * n entries, each with the problem's own status. A problem's iterates do not
+ * depend on the other members (per-problem reductions in a fixed order), so
+ * they are bitwise those of ddmgnn_solve on it alone. Returns DDMGNN_OK when
+ * every problem converged, else the status of the first that did not. */
+int ddmgnn_solve_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int32_t n, const ddmgnn_solve_opts* opts,
+                       double* const* u_out, ddmgnn_stats* stats);
+
+/* ---- serving: a stream of independent requests with continuous batching ----
+ * The server owns ctx (its stream and device) until ddmgnn_server_destroy:
+ * the caller makes no other call on ctx meanwhile. Requests are copied at
+ * submission; `setup_threads` host threads (0: 4) run their setup; one GPU
+ * thread admits set-up requests in submission order while their device
+ * memory (ddmgnn_problem_device_bytes) fits `hbm_budget` bytes and at most
+ * `max_active` are active, advances all active requests together by chunks
+ * of opts.check_every iterations (as ddmgnn_solve_batch) and retires each as
+ * it converges. Requests batch together only when their Krylov method,
+ * m_max, precision, prolong and coarse options agree; one that differs from
+ * the active set waits until that set has drained (rtol and max_it are per
+ * request). A request larger than the budget fails with E_BUDGET. */
+int ddmgnn_server_create(ddmgnn_ctx* ctx, const ddmgnn_model* model, int64_t hbm_budget, int32_t max_active,
+                         int32_t setup_threads, ddmgnn_server** out);
+/* Non-blocking. *ticket identifies the request (> 0). */
+int ddmgnn_server_submit(ddmgnn_server* srv, const ddmgnn_problem_desc* desc, const ddmgnn_solve_opts* opts,
+                         uint64_t* ticket);
+/* DDMGNN_E_PENDING while the request runs; otherwise its status, with u_out
+ * (host, N doubles, may be NULL) and stats filled (stats.latency_ms =
+ * completion - submission). A finished request is collected once. */
+int ddmgnn_server_poll(ddmgnn_server* srv, uint64_t ticket, double* u_out, ddmgnn_stats* stats);
+/* Blocks until every submitted request has finished. */
+int ddmgnn_server_drain(ddmgnn_server* srv);
+/* Drains, stops the threads and frees uncollected results. */
+int ddmgnn_server_destroy(ddmgnn_server* srv);
 
 /* One preconditioner apply z = M(r) (Sec. III.A steps 1-3). r, z: device, N
  * doubles, must not alias. */
@@ -223,6 +267,9 @@ void ddmgnn_free(void* p);
 /* Sizes of a problem: N, nnz, K, sum k_i, number of directed DSS edges. */
 int ddmgnn_problem_sizes(const ddmgnn_problem* prob, int64_t* n, int64_t* nnz, int32_t* k,
                          int64_t* sum_k, int64_t* n_edges);
+
+/* Device memory a problem holds (the budget unit of the server). */
+int ddmgnn_problem_device_bytes(const ddmgnn_problem* prob, int64_t* bytes);
 
 /* Local DSS graph of sub-mesh `sub` as setup builds it from a descriptor
  * (Sec. III.B: edge l -> j for every mesh edge {j, l} inside the sub-mesh

@@ -51,7 +51,8 @@ class SolveOpts(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("converged", _i32), ("rel_residual", _f64),
                 ("true_rel_residual", _f64), ("solve_ms", _f64), ("dss_launches", _i32), ("dss_ms", _f64),
-                ("coarse_ms", _f64), ("prolong_ms", _f64), ("krylov_ms", _f64), ("dss_kernel", _i32)]
+                ("coarse_ms", _f64), ("prolong_ms", _f64), ("krylov_ms", _f64), ("dss_kernel", _i32),
+                ("status", _i32), ("latency_ms", _f64)]
 
 
 _lib = None
@@ -78,6 +79,15 @@ def lib():
         "ddmgnn_problem_destroy": (ctypes.c_int, [_p]),
         "ddmgnn_default_opts": (None, [ctypes.POINTER(SolveOpts)]),
         "ddmgnn_solve": (ctypes.c_int, [_p, _p, ctypes.POINTER(SolveOpts), _p, ctypes.POINTER(Stats)]),
+        "ddmgnn_solve_batch": (ctypes.c_int, [_p, ctypes.POINTER(_p), _i32, ctypes.POINTER(SolveOpts),
+                                              ctypes.POINTER(_p), ctypes.POINTER(Stats)]),
+        "ddmgnn_server_create": (ctypes.c_int, [_p, _p, _i64, _i32, _i32, ctypes.POINTER(_p)]),
+        "ddmgnn_server_submit": (ctypes.c_int, [_p, ctypes.POINTER(ProblemDesc), ctypes.POINTER(SolveOpts),
+                                                ctypes.POINTER(ctypes.c_uint64)]),
+        "ddmgnn_server_poll": (ctypes.c_int, [_p, ctypes.c_uint64, _p, ctypes.POINTER(Stats)]),
+        "ddmgnn_server_drain": (ctypes.c_int, [_p]),
+        "ddmgnn_server_destroy": (ctypes.c_int, [_p]),
+        "ddmgnn_problem_device_bytes": (ctypes.c_int, [_p, ctypes.POINTER(_i64)]),
         "ddmgnn_precond_apply": (ctypes.c_int, [_p, _p, ctypes.POINTER(SolveOpts), _p, _p]),
         "ddmgnn_apply_intermediates": (ctypes.c_int, [_p, _p, _p, _p, _p, _p]),
         "ddmgnn_dss_forward": (ctypes.c_int, [_p, _p, _i32, _p, _p]),
@@ -315,8 +325,12 @@ class Problem:
         rc = lib().ddmgnn_solve(self.ctx.h, self.h, ctypes.byref(o), _dev(u_out), ctypes.byref(st))
         if check:
             _check(rc)
-        st.status = rc
         return st
+
+    def device_bytes(self) -> int:
+        b = _i64()
+        _check(lib().ddmgnn_problem_device_bytes(self.h, ctypes.byref(b)))
+        return b.value
 
     def apply(self, r, z, opts: SolveOpts | None = None):
         o = opts or default_opts()
@@ -339,3 +353,64 @@ class Problem:
 
     def spmv(self, x, y):
         _check(lib().ddmgnn_spmv(self.ctx.h, self.h, _dev(x), _dev(y)))
+
+
+def solve_batch(ctx: Context, problems, u_outs, opts: SolveOpts | None = None, check=True):
+    """Solve several problems of one context and model together; returns one Stats per problem."""
+    o = opts or default_opts()
+    n = len(problems)
+    hs = (_p * n)(*[p.h for p in problems])
+    outs = (_p * n)(*[_dev(u) for u in u_outs])
+    st = (Stats * n)()
+    rc = lib().ddmgnn_solve_batch(ctx.h, hs, n, ctypes.byref(o), outs, st)
+    if check:
+        _check(rc)
+    return list(st)
+
+
+class Server:
+    """Serving loop with continuous batching (owns the context while it runs)."""
+
+    def __init__(self, ctx: Context, model: Model, hbm_budget: int, max_active: int = 64, setup_threads: int = 0):
+        self.ctx = ctx
+        self.model = model
+        self._n = {}
+        h = _p()
+        _check(lib().ddmgnn_server_create(ctx.h, model.h, int(hbm_budget), max_active, setup_threads,
+                                          ctypes.byref(h)))
+        self.h = h
+
+    def submit(self, hp: HostProblem, opts: SolveOpts | None = None) -> int:
+        o = opts or default_opts()
+        d = hp.desc()
+        t = ctypes.c_uint64()
+        _check(lib().ddmgnn_server_submit(self.h, ctypes.byref(d), ctypes.byref(o), ctypes.byref(t)))
+        self._n[t.value] = hp.n
+        return t.value
+
+    def poll(self, ticket: int, with_solution: bool = True):
+        """None while pending, else (status, Stats, u or None); a finished request is returned once."""
+        if ticket not in self._n:
+            raise KeyError(f"unknown or already collected ticket {ticket}")
+        u = np.empty(self._n[ticket], np.float64) if with_solution else None
+        st = Stats()
+        rc = lib().ddmgnn_server_poll(self.h, ticket, u.ctypes.data_as(_p) if u is not None else None,
+                                      ctypes.byref(st))
+        if rc == -9:
+            return None
+        del self._n[ticket]
+        return rc, st, u
+
+    def drain(self):
+        _check(lib().ddmgnn_server_drain(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ddmgnn_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

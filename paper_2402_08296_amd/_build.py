@@ -7,8 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libddmgnn.so")
-SOURCES = [os.path.join(HERE, "csrc", "ddmgnn.hip"), os.path.join(HERE, "csrc", "dss_mfma.hip"),
-           os.path.join(HERE, "csrc", "setup.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in
+           ("kernels.hip", "dss_mfma.hip", "runtime.cpp", "server.cpp", "setup.cpp")]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

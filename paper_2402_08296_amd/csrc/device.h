@@ -1,0 +1,143 @@
+// Device-side types shared by the kernel translation units and the host
+// runtime: Krylov scalars, the per-problem pointer table, work items and the
+// kernel launchers.
+//
+// Every kernel is table driven. A launch serves one or several problems (a
+// batch): workgroup b looks up its work item (problem index, sub-mesh / row /
+// local workgroup) and reads that problem's pointers from the table. A single
+// solve is a batch of one. Problems that have converged keep their slots in
+// the grid but their workgroups return at once (the per-problem done flag).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ddmgnn {
+
+constexpr int D = 10;           // latent width (Sec. IV.B)
+constexpr int MAX_M = 4;        // largest FCG truncation supported
+constexpr int VEC_BLOCK = 256;  // threads of the vector kernels
+constexpr int VEC_GRID = 2048;  // max workgroups per problem in the vector kernels
+constexpr int DSS_BLOCK = 512;  // threads of the VALU DSS kernel
+constexpr int COARSE_ROWS = VEC_BLOCK / 64;  // coarse rows per workgroup (one per wavefront)
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+// Krylov scalars of one problem, resident in device memory.
+struct KState {
+    double r0n;            // |r_0|
+    double rtol;
+    double rel;            // |r_it| / |r_0|
+    double alpha;
+    double beta[MAX_M];    // p_new = z + sum_k beta[k] p_(it-1-k)
+    double pq[MAX_M + 1];  // <p, A p> of each direction-ring slot
+    double rho;            // PCG/CG: <r, z> of the current iteration
+    double rr_true;        // |b - A u|^2 at exit
+    int it;                // completed iterations
+    int done;
+    int status;
+    int max_it;            // the update kernel raises done once it reaches max_it
+};
+
+// Per slot position in tile order (nodes of a sub-mesh by decreasing
+// in-degree): the node's local id, in-degree, first in-edge, and the bf16 bits
+// of its sub-mesh-centred coordinates split as x = x_hi + x_lo, y = y_hi + y_lo.
+struct TileNode {
+    int32_t e0;
+    uint16_t j;
+    uint16_t deg;
+    uint16_t xh, xl, yh, yl;
+};
+static_assert(sizeof(TileNode) == 16, "tile record layout");
+
+// Device view of one problem (all pointers device memory).
+struct DevProb {
+    // matrix, right-hand side, boundary
+    const int32_t* rowptr;
+    const int32_t* col;
+    const double* val;
+    const double* b;
+    const double* u0;
+    const uint8_t* dirichlet;
+    // decomposition and DSS graphs (slot = position in sub_nodes)
+    const int32_t* sub_ptr;
+    const int32_t* sub_nodes;
+    const double* weights;
+    const int32_t* edge_ptr;    // per slot, in-edge range (global edge index)
+    const uint16_t* edge_src;   // per edge, sender local id; padded by 8 entries
+    const float* edge_nd;       // per edge, |d_jl|; padded by 8 entries
+    const uint32_t* erec;       // per edge, sender | FP16 |d_jl| << 16; padded by 8 entries
+    const TileNode* tiles;      // per slot position in tile order
+    const double* xy64;         // per slot, raw coordinates
+    const float* xyc32;         // per slot, sub-mesh-centred coordinates
+    const int32_t* node_ptr;    // per node, range of its slots
+    const int32_t* node_slots;
+    const int32_t* slot_sub;
+    const double* a0inv;        // K x K
+    // iteration vectors
+    double* u;
+    double* r;                  // residual; input of the apply
+    double* z;                  // output of the apply
+    const double* c_in;         // DSS forward entry: per-slot inputs (null in solves)
+    double* p[MAX_M + 1];       // direction ring
+    double* q[MAX_M + 1];       // A p of each ring slot
+    double* s;                  // [K] |R_i r|
+    double* y0;                 // [K] R_0 r
+    double* y;                  // [K] coarse solution
+    double* local;              // per slot, |R_i r| r~_i (or r~_i for the forward entry)
+    double* qg64;               // DSS fallback storage when LDS is too small (may be null)
+    double* hg64;               // FP64 DSS latent state
+    float* qg32;
+    KState* st;                 // null: no Krylov scalars, no done flag
+    double* partials;           // (MAX_M + 1) x VEC_GRID
+    unsigned* counter;          // zero between launches
+    double rtol;                // read by the init kernel
+    int max_it;
+    int n;
+    int K;
+    int nblk;                   // workgroups of this problem in the vector kernels
+};
+
+// Options of one Krylov iteration, common to the problems of a launch.
+struct IterArgs {
+    int mode;        // DDMGNN_FCG / PCG / CG; < 0: bare apply (no Krylov scalars)
+    int m;           // directions kept (FCG m_max; 1 for PCG and CG)
+    int unweighted;  // gluing without partition-of-unity weights
+    int coarse;      // add the coarse correction
+};
+
+// Ring slots of iteration `it` with `m` kept directions: the new direction
+// goes to it % (m+1), previous direction k (0 = most recent) is in (it-1-k) mod (m+1).
+__host__ __device__ inline int ring_cur(int it, int m) { return it % (m + 1); }
+__host__ __device__ inline int ring_prev(int it, int m, int k) {
+    const int nr = m + 1;
+    return ((it - 1 - k) % nr + nr) % nr;
+}
+
+// Launchers (kernels.hip). tab: device table; the int2 lists are device
+// arrays of (problem, item) pairs, one per workgroup. check = false skips
+// hipGetLastError (not allowed while a stream is being captured).
+hipError_t prepare_dss_valu(int precision, size_t shmem);
+hipError_t launch_dss_valu(const DevProb* tab, const int2* work, int n_work, int precision, bool qlds, int kbar,
+                           double alpha, int apply, const float* theta32, const double* theta64, size_t shmem,
+                           hipStream_t s, bool check);
+hipError_t launch_coarse(const DevProb* tab, const int2* rows, int n_rows, hipStream_t s, bool check);
+hipError_t launch_prolong(const DevProb* tab, const int2* blk, int n_blk, const IterArgs& it, hipStream_t s,
+                          bool check);
+hipError_t launch_krylov(const DevProb* tab, const int2* blk, int n_blk, const IterArgs& it, hipStream_t s,
+                         bool check);
+hipError_t launch_init(const DevProb* tab, const int2* blk, int n_blk, hipStream_t s);
+hipError_t launch_resid(const DevProb* tab, const int2* blk, int n_blk, hipStream_t s);
+hipError_t launch_gather_states(const DevProb* tab, int n, KState* out, hipStream_t s);
+hipError_t launch_spmv(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, double* y,
+                       int n, hipStream_t s);
+hipError_t launch_dot(const double* x, const double* y, int64_t n, double* partials, unsigned* counter, double* out,
+                      hipStream_t s);
+
+// Workgroups a problem of n rows takes in the vector kernels.
+inline int vec_blocks(int64_t n) {
+    const int64_t g = (n + VEC_BLOCK - 1) / VEC_BLOCK;
+    return (int)(g < 1 ? 1 : (g > VEC_GRID ? VEC_GRID : g));
+}
+
+}  // namespace ddmgnn

@@ -7,6 +7,8 @@
 #include <cstdint>
 #include <vector>
 
+#include "device.h"
+
 namespace ddmgnn {
 
 constexpr int MFMA_BLOCK = 1024;  // 16 wavefronts, one sub-mesh per workgroup
@@ -32,16 +34,6 @@ struct MfmaDec {
 };
 static_assert(sizeof(MfmaDec) == 48, "decoder blob layout");
 
-// Per slot position in tile order (nodes of a sub-mesh by decreasing
-// in-degree): the node's local id, in-degree, first in-edge, and the bf16 bits
-// of its sub-mesh-centred coordinates split as x = x_hi + x_lo, y = y_hi + y_lo.
-struct TileNode {
-    int32_t e0;
-    uint16_t j;
-    uint16_t deg;
-    uint16_t xh, xl, yh, yl;
-};
-static_assert(sizeof(TileNode) == 16, "tile record layout");
 
 // Builds the per-lane blobs from the flat FP32 weights (layout of ddmgnn.h).
 // The message second layers are folded into the Psi hidden layer
@@ -50,24 +42,13 @@ static_assert(sizeof(TileNode) == 16, "tile record layout");
 void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaStep>& steps, std::vector<MfmaDec>& dec);
 
 struct DssMfmaArgs {
-    const int32_t* sub_ptr;
-    const int32_t* work_order;
-    const int32_t* edge_ptr;     // per slot, in-edge range (global edge index)
-    const uint32_t* erec;        // per edge: sender local index | FP16 bits of |d_jl| << 16
-    const TileNode* tiles;       // per slot position in tile order
-    const int32_t* sub_nodes;
-    const double* weights;
-    const double* r;             // apply: global residual
-    const double* c_in;          // forward hook: per-slot inputs
-    double* out;
-    double* s_out;
-    double* y0_out;
-    const int* done;             // Krylov converged flag (may be null)
+    const DevProb* tab;          // per problem: graphs, tile records, vectors, done flag
+    const int2* work;            // (problem, sub-mesh) per workgroup, largest sub-meshes first
     const MfmaStep* steps;
     const MfmaDec* dec;
     int kbar;
     float alpha;
-    int apply;
+    int apply;                   // 1: restrict P.r and write s r~ to P.local; 0: read P.c_in, write r~
 };
 
 // LDS of a workgroup: c (k floats, padded to 4), Q' (k x 48 bytes), edge
@@ -81,6 +62,6 @@ inline size_t mfma_lds_need(int k, int64_t ne) {
 // Sets the dynamic-LDS limit of the kernel (not allowed during stream capture).
 hipError_t prepare_dss_mfma(size_t shmem);
 // check = false skips hipGetLastError (used while a stream is being captured).
-hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_sub, size_t shmem, hipStream_t stream, bool check);
+hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_work, size_t shmem, hipStream_t stream, bool check);
 
 }  // namespace ddmgnn

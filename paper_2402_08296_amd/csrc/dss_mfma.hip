@@ -32,7 +32,6 @@ namespace ddmgnn {
 
 namespace {
 
-constexpr int D = 10;
 constexpr int IN_PHI = 2 * D + 3;
 constexpr int IN_PSI = 3 * D + 1;
 constexpr int OFF_PO = 0;
@@ -264,47 +263,50 @@ __device__ inline h2 pk(float x, float y) { return (h2){(_Float16)x, (_Float16)y
 //   T   [k]        tile records (node id, degree, first edge, split coordinates)
 // The message sums run in packed FP16 (two units per instruction).
 __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
-    if (a.done && *a.done) return;
+    const int2 wi = a.work[blockIdx.x];
+    const DevProb& P = a.tab[wi.x];
+    if (P.st && P.st->done) return;
     extern __shared__ float lds[];
     __shared__ double red[MFMA_BLOCK / 64 + 1];
-    const int sub = a.work_order[blockIdx.x];
-    const int base = a.sub_ptr[sub];
-    const int k = a.sub_ptr[sub + 1] - base;
+    const int sub = wi.y;
+    const int base = P.sub_ptr[sub];
+    const int k = P.sub_ptr[sub + 1] - base;
     const int tid = threadIdx.x;
-    const int ebase = a.edge_ptr[base];
-    const int ne = a.edge_ptr[base + k] - ebase;
+    const int ebase = P.edge_ptr[base];
+    const int ne = P.edge_ptr[base + k] - ebase;
+    double* __restrict__ out = P.local;
     float* cbuf = lds;
     _Float16* Q = reinterpret_cast<_Float16*>(lds + ((k + 3) & ~3));
     uint32_t* E = reinterpret_cast<uint32_t*>(Q + (size_t)k * 24);
     TileNode* T = reinterpret_cast<TileNode*>(E + ((ne + EC + 3) & ~3));
-    for (int i = tid; i < ne + EC; i += MFMA_BLOCK) E[i] = i < ne ? a.erec[ebase + i] : 0u;
+    for (int i = tid; i < ne + EC; i += MFMA_BLOCK) E[i] = i < ne ? P.erec[ebase + i] : 0u;
     for (int i = tid; i < k; i += MFMA_BLOCK)
-        reinterpret_cast<uint4*>(T)[i] = reinterpret_cast<const uint4*>(a.tiles + base)[i];
+        reinterpret_cast<uint4*>(T)[i] = reinterpret_cast<const uint4*>(P.tiles + base)[i];
 
     // Restriction and normalisation (Sec. III.A step 2).
     double s = 1.0;
     if (a.apply) {
         double ss = 0.0, yy = 0.0;
         for (int j = tid; j < k; j += MFMA_BLOCK) {
-            const double rv = a.r[a.sub_nodes[base + j]];
+            const double rv = P.r[P.sub_nodes[base + j]];
             ss = fma(rv, rv, ss);
-            yy = fma(a.weights[base + j], rv, yy);
+            yy = fma(P.weights[base + j], rv, yy);
         }
         ss = block_sum(ss, red);
         yy = block_sum(yy, red);
         s = sqrt(ss);
         if (tid == 0) {
-            a.s_out[sub] = s;
-            a.y0_out[sub] = yy;
+            P.s[sub] = s;
+            P.y0[sub] = yy;
         }
         if (s == 0.0) {
-            for (int j = tid; j < k; j += MFMA_BLOCK) a.out[base + j] = 0.0;
+            for (int j = tid; j < k; j += MFMA_BLOCK) out[base + j] = 0.0;
             return;
         }
         const double inv = 1.0 / s;
-        for (int j = tid; j < k; j += MFMA_BLOCK) cbuf[j] = (float)(a.r[a.sub_nodes[base + j]] * inv);
+        for (int j = tid; j < k; j += MFMA_BLOCK) cbuf[j] = (float)(P.r[P.sub_nodes[base + j]] * inv);
     } else {
-        for (int j = tid; j < k; j += MFMA_BLOCK) cbuf[j] = (float)a.c_in[base + j];
+        for (int j = tid; j < k; j += MFMA_BLOCK) cbuf[j] = (float)P.c_in[base + j];
     }
     __syncthreads();
 
@@ -449,7 +451,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
         const f32x16 o = mfma(AD2, bh, zero);
         if (valid && hf == 0) {
             const double r_tilde = (double)(o[0] + bd2);
-            a.out[base + tn.j] = a.apply ? s * r_tilde : r_tilde;
+            out[base + tn.j] = a.apply ? s * r_tilde : r_tilde;
         }
     }
 }
@@ -460,8 +462,9 @@ hipError_t prepare_dss_mfma(size_t shmem) {
     return hipFuncSetAttribute((const void*)dss_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
 }
 
-hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_sub, size_t shmem, hipStream_t stream, bool check) {
-    hipLaunchKernelGGL(dss_mfma_kernel, dim3(n_sub), dim3(MFMA_BLOCK), shmem, stream, a);
+hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_work, size_t shmem, hipStream_t stream, bool check) {
+    if (n_work <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dss_mfma_kernel, dim3(n_work), dim3(MFMA_BLOCK), shmem, stream, a);
     return check ? hipGetLastError() : hipSuccess;
 }
 

@@ -1,0 +1,846 @@
+// VALU kernels of the DDM-GNN apply and of the Krylov iteration, all table
+// driven (one launch serves every problem of a batch).
+//
+// One preconditioner apply (Sec. III.A) is three launches:
+//   DSS forward     one workgroup per sub-mesh, largest first. Restricts the
+//                   residual (s_i = |R_i r|, y0_i = (R_0 r)_i, c_i = R_i r / s_i)
+//                   and runs the kbar DSS_theta blocks (Sec. III.B); writes
+//                   s_i r~_i per slot. This file holds the FP64/FP32 VALU
+//                   form; dss_mfma.hip the BF16 matrix-core form.
+//   coarse_kernel   y = (R_0 A R_0^T)^{-1} y0 as a GEMV with the inverse
+//                   formed at setup (step 1).
+//   prolong_kernel  z(n) = sum over the sub-meshes holding n of
+//                   w_i(n) s_i r~_i(n) + D_i(n) y_i; z = 0 at Dirichlet nodes
+//                   (step 3), fused with the Krylov dot products that need z.
+// The Krylov iteration adds the direction update with the SpMV and its dots,
+// and the solution update with the convergence test. Scalar recurrences
+// (alpha, beta, the test) run on the device in the last workgroup of the
+// kernel that completes a reduction, so the host only polls a flag.
+#include <hip/hip_runtime.h>
+
+#include "ddmgnn.h"
+#include "device.h"
+#include "setup.h"
+
+namespace ddmgnn {
+
+namespace {
+
+constexpr int IN_PHI = 2 * D + 3;                  // (h_j, h_l, d, |d|)
+constexpr int IN_PSI = 3 * D + 1;                  // (h_j, c_j, phi_out, phi_in)
+constexpr int OFF_PO = 0;                          // Phi_out
+constexpr int OFF_PI = OFF_PO + D * IN_PHI + D + D * D + D;
+constexpr int OFF_PS = OFF_PI + D * IN_PHI + D + D * D + D;
+constexpr int OFF_DE = OFF_PS + D * IN_PSI + D + D * D + D;
+constexpr int BLOCK_W = OFF_DE + D * D + D + D + 1;  // 11 d^2 + 15 d + 1
+static_assert(BLOCK_W == 1251, "weight block size");
+constexpr int DSS_NPT = (kMaxSubNodes + DSS_BLOCK - 1) / DSS_BLOCK;
+
+// ------------------------------------------------------------------ reductions
+// Deterministic: fixed shuffle tree inside a wave, fixed order across waves,
+// fixed order across workgroups (the last workgroup of a problem sums its
+// partials), so a problem's result does not depend on what else is in the launch.
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <int BLOCK>
+__device__ inline double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int i = 0; i < BLOCK / 64; ++i) acc += sh[i];
+        sh[BLOCK / 64] = acc;
+    }
+    __syncthreads();
+    return sh[BLOCK / 64];
+}
+
+// NV block sums at once (one barrier round for all of them); the totals are
+// valid in every thread. sh holds NV * (BLOCK / 64) doubles.
+template <int NV, int BLOCK>
+__device__ inline void block_sum_n(double (&v)[NV], double* sh) {
+    constexpr int W = BLOCK / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    __syncthreads();
+    if (lane == 0)
+        for (int i = 0; i < NV; ++i) sh[i * W + w] = v[i];
+    __syncthreads();
+    for (int i = 0; i < NV; ++i) {
+        double acc = 0.0;
+        for (int k = 0; k < W; ++k) acc += sh[i * W + k];
+        v[i] = acc;
+    }
+    __syncthreads();
+}
+
+// Sums NV values over the nb workgroups of one problem (this one is local
+// workgroup lb). Returns true in the last of them to finish, where out[]
+// holds the totals (valid in every thread of that workgroup). Each workgroup
+// publishes its partial sums, then takes a ticket from the problem's counter
+// (release fence before, so the partials are visible to whoever draws the
+// last ticket); the last one reads all partials after an acquire fence, with
+// ordinary loads that can all be in flight at once.
+template <int NV, int BLOCK>
+__device__ bool grid_sum(const double (&v)[NV], double* partials, unsigned* counter, int lb, int nb,
+                         double (&out)[NV], double* /*unused*/) {
+    __shared__ double sh[NV * (BLOCK / 64)];
+    __shared__ int is_last;
+    double bs[NV];
+    for (int i = 0; i < NV; ++i) bs[i] = v[i];
+    block_sum_n<NV, BLOCK>(bs, sh);
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < NV; ++i) partials[i * VEC_GRID + lb] = bs[i];
+        __threadfence();
+        const unsigned t = atomicAdd(counter, 1u);
+        is_last = (t == (unsigned)nb - 1);
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    for (int i = 0; i < NV; ++i) out[i] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BLOCK)
+        for (int i = 0; i < NV; ++i) out[i] += partials[i * VEC_GRID + b];
+    block_sum_n<NV, BLOCK>(out, sh);
+    if (threadIdx.x == 0) *counter = 0u;
+    return true;
+}
+
+// Work item of a vector-kernel workgroup: its problem and local workgroup.
+struct Seg {
+    const DevProb* P;
+    int lb;
+};
+__device__ inline Seg seg(const DevProb* __restrict__ tab, const int2* __restrict__ blk) {
+    const int2 w = blk[blockIdx.x];
+    return {tab + w.x, w.y};
+}
+
+// ------------------------------------------------------------------ DSS forward (VALU)
+template <typename T>
+struct DssArgs {
+    const DevProb* tab;
+    const int2* work;         // (problem, sub-mesh), largest sub-meshes first
+    int kbar;
+    T alpha;
+    int apply;                // 1: restrict P.r and write s r~; 0: read P.c_in, write r~
+};
+
+__device__ inline float relu(float x) { return fmaxf(x, 0.0f); }
+__device__ inline double relu(double x) { return fmax(x, 0.0); }
+
+// HREG: the latent state h of the thread's nodes stays in registers across all
+// kbar blocks (FP32). Otherwise it lives in a per-slot global buffer (FP64,
+// whose register footprint would spill).
+// theta is a separate __restrict__ parameter so the compiler can prove the
+// weight loads uniform and unclobbered and read them through the scalar cache.
+// QLDS: Q lives in LDS (compile-time, so its accesses are ds_* rather than flat).
+// SEP: the coordinate part of the message first layer is split per node,
+// W1_d d_jl = W1_d x_l - W1_d x_j, and added to the projections (P and Q then
+// carry it), so an edge only adds w_|d| |d_jl|; coordinates are centred on the
+// sub-mesh to keep the cancellation small. Used for FP32; the FP64 path
+// evaluates W1_d d_jl per edge.
+template <typename T, bool HREG, bool QLDS>
+__global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* __restrict__ theta) {
+    constexpr bool SEP = sizeof(T) == 4;
+    const int2 wi = a.work[blockIdx.x];
+    const DevProb& P = a.tab[wi.x];
+    if (P.st && P.st->done) return;
+    extern __shared__ unsigned char dyn_smem[];
+    __shared__ double red[DSS_BLOCK / 64 + 1];
+    const int sub = wi.y;
+    const int base = P.sub_ptr[sub];
+    const int k = P.sub_ptr[sub + 1] - base;
+    const T* xy;
+    T* qglobal;
+    if constexpr (SEP) {
+        xy = P.xyc32;
+        qglobal = P.qg32;
+    } else {
+        xy = P.xy64;
+        qglobal = P.qg64;
+    }
+    T* Q = QLDS ? reinterpret_cast<T*>(dyn_smem) : qglobal + (size_t)base * 2 * D;
+    const int32_t* __restrict__ edge_ptr = P.edge_ptr;
+    const uint16_t* __restrict__ edge_src = P.edge_src;
+    const float* __restrict__ edge_nd = P.edge_nd;
+    double* __restrict__ out = P.local;
+    const int tid = threadIdx.x;
+
+    T c[DSS_NPT];
+    double s = 1.0;
+    if (a.apply) {
+        const double* __restrict__ r = P.r;
+        double ss = 0.0, yy = 0.0, rv[DSS_NPT];
+#pragma unroll
+        for (int t = 0; t < DSS_NPT; ++t) {
+            const int j = tid + t * DSS_BLOCK;
+            rv[t] = 0.0;
+            if (j < k) {
+                rv[t] = r[P.sub_nodes[base + j]];
+                ss = fma(rv[t], rv[t], ss);
+                yy = fma(P.weights[base + j], rv[t], yy);
+            }
+        }
+        ss = block_sum<DSS_BLOCK>(ss, red);
+        yy = block_sum<DSS_BLOCK>(yy, red);
+        s = sqrt(ss);
+        if (tid == 0) {
+            P.s[sub] = s;
+            P.y0[sub] = yy;
+        }
+        if (s == 0.0) {  // R_i r = 0: the local term is 0
+            for (int j = tid; j < k; j += DSS_BLOCK) out[base + j] = 0.0;
+            return;
+        }
+#pragma unroll
+        for (int t = 0; t < DSS_NPT; ++t) c[t] = (T)(rv[t] / s);
+    } else {
+#pragma unroll
+        for (int t = 0; t < DSS_NPT; ++t) {
+            const int j = tid + t * DSS_BLOCK;
+            c[t] = j < k ? (T)P.c_in[base + j] : (T)0;
+        }
+    }
+
+    T hreg[HREG ? DSS_NPT : 1][D];
+#pragma unroll
+    for (int t = 0; t < (HREG ? DSS_NPT : 1); ++t)
+#pragma unroll
+        for (int u = 0; u < D; ++u) hreg[t][u] = (T)0;
+    T* hg = nullptr;
+    if constexpr (!HREG) {
+        hg = P.hg64 + (size_t)base * D;
+        for (int j = tid; j < k; j += DSS_BLOCK)
+#pragma unroll
+            for (int u = 0; u < D; ++u) hg[j * D + u] = (T)0;
+    }
+
+    for (int step = 0; step < a.kbar; ++step) {
+        const T* __restrict__ w = theta + (size_t)step * BLOCK_W;
+        const T* Wo = w + OFF_PO;                 // Phi_out W1 [D][IN_PHI]
+        const T* bo = Wo + D * IN_PHI;
+        const T* Vo = bo + D;                     // Phi_out W2 [D][D]
+        const T* co = Vo + D * D;
+        const T* Wi = w + OFF_PI;
+        const T* bi = Wi + D * IN_PHI;
+        const T* Vi = bi + D;
+        const T* ci = Vi + D * D;
+        const T* Wp = w + OFF_PS;                 // Psi W1 [D][IN_PSI]
+        const T* bp = Wp + D * IN_PSI;
+        const T* Vp = bp + D;
+        const T* cp = Vp + D * D;
+
+        // Phase A: neighbour projections Q_out = W1_out[:, D:2D] h, Q_in likewise.
+#pragma unroll
+        for (int t = 0; t < DSS_NPT; ++t) {
+            const int j = tid + t * DSS_BLOCK;
+            if (j < k) {
+                T h[D];
+#pragma unroll
+                for (int v = 0; v < D; ++v) h[v] = HREG ? hreg[HREG ? t : 0][v] : hg[j * D + v];
+                const T xl = xy[2 * (base + j)], yl = xy[2 * (base + j) + 1];
+#pragma unroll
+                for (int u = 0; u < D; ++u) {
+                    T qo = (T)0, qi = (T)0;
+                    if (SEP) {  // Q_out += W1_d x_l, Q_in -= W1_d x_l (d_lj = -d_jl)
+                        qo = fma(Wo[u * IN_PHI + 2 * D], xl, fma(Wo[u * IN_PHI + 2 * D + 1], yl, qo));
+                        qi = -fma(Wi[u * IN_PHI + 2 * D], xl, Wi[u * IN_PHI + 2 * D + 1] * yl);
+                    }
+#pragma unroll
+                    for (int v = 0; v < D; ++v) {
+                        qo = fma(Wo[u * IN_PHI + D + v], h[v], qo);
+                        qi = fma(Wi[u * IN_PHI + D + v], h[v], qi);
+                    }
+                    Q[j * 2 * D + u] = qo;
+                    Q[j * 2 * D + D + u] = qi;
+                }
+            }
+        }
+        __syncthreads();
+
+        // Phase B: per receiver, message sums over in-edges, then the Psi update.
+#pragma unroll
+        for (int t = 0; t < DSS_NPT; ++t) {
+            const int j = tid + t * DSS_BLOCK;
+            if (j < k) {
+                T h[D];
+#pragma unroll
+                for (int v = 0; v < D; ++v) h[v] = HREG ? hreg[HREG ? t : 0][v] : hg[j * D + v];
+                T po[D], pi[D], so[D], si[D];
+#pragma unroll
+                for (int u = 0; u < D; ++u) {
+                    T ao = bo[u], ai = bi[u];
+#pragma unroll
+                    for (int v = 0; v < D; ++v) {
+                        ao = fma(Wo[u * IN_PHI + v], h[v], ao);
+                        ai = fma(Wi[u * IN_PHI + v], h[v], ai);
+                    }
+                    po[u] = ao;
+                    pi[u] = ai;
+                    so[u] = (T)0;
+                    si[u] = (T)0;
+                }
+                const T xj = xy[2 * (base + j)], yj = xy[2 * (base + j) + 1];
+                if (SEP) {
+#pragma unroll
+                    for (int u = 0; u < D; ++u) {
+                        po[u] = po[u] - fma(Wo[u * IN_PHI + 2 * D], xj, Wo[u * IN_PHI + 2 * D + 1] * yj);
+                        pi[u] = fma(Wi[u * IN_PHI + 2 * D], xj, fma(Wi[u * IN_PHI + 2 * D + 1], yj, pi[u]));
+                    }
+                }
+                const int e0 = edge_ptr[base + j], e1 = edge_ptr[base + j + 1];
+                if (SEP) {
+                    // Chunks of 2 edges as straight-line code: both rows are read from
+                    // LDS before the sums. An edge past e1 reads the node's own row
+                    // (the edge arrays are padded) and is masked with a 0 weight.
+                    for (int e = e0; e < e1; e += 2) {
+                        const bool in1 = e + 1 < e1;
+                        const int l0 = edge_src[e], l1 = in1 ? (int)edge_src[e + 1] : j;
+                        const T n0 = (T)edge_nd[e], n1 = (T)edge_nd[e + 1];
+                        const T m1 = in1 ? (T)1 : (T)0;
+                        T q0[2 * D], q1[2 * D];
+#pragma unroll
+                        for (int u = 0; u < 2 * D; ++u) {
+                            q0[u] = Q[l0 * 2 * D + u];
+                            q1[u] = Q[l1 * 2 * D + u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < D; ++u) {
+                            const T wo = Wo[u * IN_PHI + 2 * D + 2], wi = Wi[u * IN_PHI + 2 * D + 2];
+                            so[u] += relu(fma(wo, n0, po[u] + q0[u]));
+                            si[u] += relu(fma(wi, n0, pi[u] + q0[D + u]));
+                            so[u] = fma(m1, relu(fma(wo, n1, po[u] + q1[u])), so[u]);
+                            si[u] = fma(m1, relu(fma(wi, n1, pi[u] + q1[D + u])), si[u]);
+                        }
+                    }
+                } else {
+                    for (int e = e0; e < e1; ++e) {
+                        const int l = edge_src[e];
+                        const T dx = xy[2 * (base + l)] - xj, dy = xy[2 * (base + l) + 1] - yj;
+                        const T nr = sqrt(dx * dx + dy * dy);
+                        const T* ql = Q + l * 2 * D;
+#pragma unroll
+                        for (int u = 0; u < D; ++u) {
+                            T vo = po[u] + ql[u];
+                            vo = fma(Wo[u * IN_PHI + 2 * D], dx, vo);
+                            vo = fma(Wo[u * IN_PHI + 2 * D + 1], dy, vo);
+                            vo = fma(Wo[u * IN_PHI + 2 * D + 2], nr, vo);
+                            so[u] += relu(vo);
+                            T vi = pi[u] + ql[D + u];
+                            vi = fma(Wi[u * IN_PHI + 2 * D], -dx, vi);
+                            vi = fma(Wi[u * IN_PHI + 2 * D + 1], -dy, vi);
+                            vi = fma(Wi[u * IN_PHI + 2 * D + 2], nr, vi);
+                            si[u] += relu(vi);
+                        }
+                    }
+                }
+                const T deg = (T)(e1 - e0);
+                T phio[D], phii[D];
+#pragma unroll
+                for (int u = 0; u < D; ++u) {
+                    T ao = co[u] * deg, ai = ci[u] * deg;
+#pragma unroll
+                    for (int v = 0; v < D; ++v) {
+                        ao = fma(Vo[u * D + v], so[v], ao);
+                        ai = fma(Vi[u * D + v], si[v], ai);
+                    }
+                    phio[u] = ao;
+                    phii[u] = ai;
+                }
+                T hid[D];
+#pragma unroll
+                for (int u = 0; u < D; ++u) {
+                    T acc = bp[u];
+#pragma unroll
+                    for (int v = 0; v < D; ++v) acc = fma(Wp[u * IN_PSI + v], h[v], acc);
+                    acc = fma(Wp[u * IN_PSI + D], c[t], acc);
+#pragma unroll
+                    for (int v = 0; v < D; ++v) acc = fma(Wp[u * IN_PSI + D + 1 + v], phio[v], acc);
+#pragma unroll
+                    for (int v = 0; v < D; ++v) acc = fma(Wp[u * IN_PSI + 2 * D + 1 + v], phii[v], acc);
+                    hid[u] = relu(acc);
+                }
+#pragma unroll
+                for (int u = 0; u < D; ++u) {
+                    T acc = cp[u];
+#pragma unroll
+                    for (int v = 0; v < D; ++v) acc = fma(Vp[u * D + v], hid[v], acc);
+                    const T hn = fma(a.alpha, acc, h[u]);
+                    if (HREG)
+                        hreg[HREG ? t : 0][u] = hn;
+                    else
+                        hg[j * D + u] = hn;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // Decoder of the last block: r~_j = D^kbar(h_j).
+    const T* dw = theta + (size_t)(a.kbar - 1) * BLOCK_W + OFF_DE;
+    const T* db = dw + D * D;
+    const T* dv = db + D;
+    const T* dc = dv + D;
+#pragma unroll
+    for (int t = 0; t < DSS_NPT; ++t) {
+        const int j = tid + t * DSS_BLOCK;
+        if (j < k) {
+            T h[D];
+#pragma unroll
+            for (int v = 0; v < D; ++v) h[v] = HREG ? hreg[HREG ? t : 0][v] : hg[j * D + v];
+            T acc = dc[0];
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                T hu = db[u];
+#pragma unroll
+                for (int v = 0; v < D; ++v) hu = fma(dw[u * D + v], h[v], hu);
+                acc = fma(dv[u], relu(hu), acc);
+            }
+            out[base + j] = a.apply ? s * (double)acc : (double)acc;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ coarse solve
+// y = A0inv y0, one wavefront per row; work item = (problem, first row).
+__global__ __launch_bounds__(VEC_BLOCK) void coarse_kernel(const DevProb* __restrict__ tab,
+                                                          const int2* __restrict__ rows) {
+    const int2 w = rows[blockIdx.x];
+    const DevProb& P = tab[w.x];
+    if (P.st && P.st->done) return;
+    const int row = w.y + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int K = P.K;
+    if (row >= K) return;
+    const double* __restrict__ a = P.a0inv + (size_t)row * K;
+    const double* __restrict__ y0 = P.y0;
+    double acc = 0.0;
+    for (int j = lane; j < K; j += 64) acc = fma(a[j], y0[j], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) P.y[row] = acc;
+}
+
+// ------------------------------------------------------------------ prolong + dots
+// The per-row loops live in force-inlined bodies whose pointer parameters are
+// __restrict__: the pointers come from the problem table, and the no-alias
+// scopes the inliner attaches let loads of later rows move above the stores
+// of earlier ones.
+
+// z over rows i0, i0 + stride, ... with the dots of the mode (FCG: <z, q_k>;
+// PCG: <r, z>).
+template <int MODE>
+__device__ __forceinline__ void prolong_rows(const int32_t* __restrict__ node_ptr,
+                                             const int32_t* __restrict__ node_slots,
+                                             const int32_t* __restrict__ slot_sub,
+                                             const double* __restrict__ weights, const double* __restrict__ local,
+                                             const double* __restrict__ y, const uint8_t* __restrict__ dirichlet,
+                                             const double* __restrict__ r, double* __restrict__ z,
+                                             const double* __restrict__ q0, const double* __restrict__ q1,
+                                             const double* __restrict__ q2, const double* __restrict__ q3, int m,
+                                             bool unweighted, int i0, int stride, int n, double (&dots)[MAX_M + 1]) {
+    for (int i = i0; i < n; i += stride) {
+        double zn = 0.0;
+        if (!dirichlet[i]) {
+            for (int q = node_ptr[i]; q < node_ptr[i + 1]; ++q) {
+                const int slot = node_slots[q];
+                const double w = weights[slot];
+                zn = fma(unweighted ? 1.0 : w, local[slot], zn);
+                if (y) zn = fma(w, y[slot_sub[slot]], zn);
+            }
+        }
+        z[i] = zn;
+        if (MODE == DDMGNN_FCG) {
+            dots[0] = fma(zn, q0[i], dots[0]);
+            if (m > 1) dots[1] = fma(zn, q1[i], dots[1]);
+            if (m > 2) dots[2] = fma(zn, q2[i], dots[2]);
+            if (m > 3) dots[3] = fma(zn, q3[i], dots[3]);
+        } else if (MODE == DDMGNN_PCG) {
+            dots[0] = fma(r[i], zn, dots[0]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(VEC_BLOCK) void prolong_kernel(const DevProb* __restrict__ tab,
+                                                           const int2* __restrict__ blk, IterArgs ia) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    KState* st = P.st;
+    if (st && st->done) return;
+    __shared__ double sh[VEC_BLOCK / 64 + 1];
+    const int mode = st ? ia.mode : -1;
+    const int m = ia.m;
+    const int it = st ? st->it : 0;
+    const double* qk[MAX_M] = {nullptr, nullptr, nullptr, nullptr};
+    if (mode == DDMGNN_FCG)
+        for (int i = 0; i < MAX_M; ++i) qk[i] = i < m ? P.q[ring_prev(it, m, i)] : nullptr;
+    const double* y = ia.coarse ? P.y : nullptr;
+    double dots[MAX_M + 1];
+    for (int i = 0; i <= MAX_M; ++i) dots[i] = 0.0;
+    const int i0 = g.lb * VEC_BLOCK + threadIdx.x, stride = P.nblk * VEC_BLOCK;
+    const bool uw = ia.unweighted;
+    if (mode == DDMGNN_FCG)
+        prolong_rows<DDMGNN_FCG>(P.node_ptr, P.node_slots, P.slot_sub, P.weights, P.local, y, P.dirichlet, P.r,
+                                 P.z, qk[0], qk[1], qk[2], qk[3], m, uw, i0, stride, P.n, dots);
+    else if (mode == DDMGNN_PCG)
+        prolong_rows<DDMGNN_PCG>(P.node_ptr, P.node_slots, P.slot_sub, P.weights, P.local, y, P.dirichlet, P.r,
+                                 P.z, nullptr, nullptr, nullptr, nullptr, m, uw, i0, stride, P.n, dots);
+    else
+        prolong_rows<-1>(P.node_ptr, P.node_slots, P.slot_sub, P.weights, P.local, y, P.dirichlet, P.r, P.z,
+                         nullptr, nullptr, nullptr, nullptr, m, uw, i0, stride, P.n, dots);
+    if (mode < 0) return;
+    double tot[MAX_M + 1];
+    if (!grid_sum<MAX_M + 1, VEC_BLOCK>(dots, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
+    if (threadIdx.x != 0) return;
+    if (mode == DDMGNN_FCG) {
+        // p_new = z - sum_k (<z, q_k> / <p_k, q_k>) p_k
+        for (int i = 0; i < MAX_M; ++i) st->beta[i] = i < m ? -tot[i] / st->pq[ring_prev(it, m, i)] : 0.0;
+    } else {
+        // Algorithm 1: beta = rho_{i+1} / rho_i, p = z + beta p
+        const double rho_new = tot[0];
+        st->beta[0] = it == 0 ? 0.0 : rho_new / st->rho;
+        st->rho = rho_new;
+    }
+}
+
+// ------------------------------------------------------------------ Krylov kernels
+// Direction source of the iteration: z = M(r), or r itself for CG (M = I).
+__device__ inline const double* dir_src(const DevProb& P, int mode) { return mode == DDMGNN_CG ? P.r : P.z; }
+
+// Step length from <p, A p> and <p, r> (FCG) or rho (PCG/CG, Algorithm 1).
+__device__ inline void set_alpha(KState* st, const double (&tot)[2], int mode, int slot) {
+    const double pq = tot[0];
+    st->pq[slot] = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        st->status = isfinite(pq) ? DDMGNN_E_BREAKDOWN : DDMGNN_E_NONFINITE;
+        st->done = 1;
+        st->alpha = 0.0;
+        return;
+    }
+    st->alpha = (mode == DDMGNN_FCG ? tot[1] : st->rho) / pq;
+}
+
+__device__ __forceinline__ void pupdate_rows(const double* __restrict__ z, double* __restrict__ pn,
+                                             const double* __restrict__ p0, const double* __restrict__ p1,
+                                             const double* __restrict__ p2, const double* __restrict__ p3, double b0,
+                                             double b1, double b2, double b3, int m, int i0, int stride, int n) {
+    for (int i = i0; i < n; i += stride) {
+        double p = fma(b0, p0[i], z[i]);
+        if (m > 1) p = fma(b1, p1[i], p);
+        if (m > 2) p = fma(b2, p2[i], p);
+        if (m > 3) p = fma(b3, p3[i], p);
+        pn[i] = p;
+    }
+}
+
+// p_new = z + sum_k beta[k] p_(it-1-k)  (FCG with m_max > 1)
+__global__ __launch_bounds__(VEC_BLOCK) void pupdate_kernel(const DevProb* __restrict__ tab,
+                                                           const int2* __restrict__ blk, IterArgs ia) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    const KState* st = P.st;
+    if (st->done) return;
+    const int it = st->it, m = ia.m;
+    const double* pk[MAX_M] = {nullptr, nullptr, nullptr, nullptr};
+    for (int i = 0; i < MAX_M; ++i)
+        if (i < m) pk[i] = P.p[ring_prev(it, m, i)];
+    pupdate_rows(dir_src(P, ia.mode), P.p[ring_cur(it, m)], pk[0], pk[1], pk[2], pk[3], st->beta[0], st->beta[1],
+                 st->beta[2], st->beta[3], m, g.lb * VEC_BLOCK + threadIdx.x, P.nblk * VEC_BLOCK, P.n);
+}
+
+__device__ __forceinline__ void spmv_dots_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                               const double* __restrict__ val, const double* __restrict__ p,
+                                               double* __restrict__ q, const double* __restrict__ r, int i0,
+                                               int stride, int n, double (&d)[2]) {
+    for (int i = i0; i < n; i += stride) {
+        double acc = 0.0;
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc = fma(val[e], p[col[e]], acc);
+        q[i] = acc;
+        d[0] = fma(p[i], acc, d[0]);
+        d[1] = fma(p[i], r[i], d[1]);
+    }
+}
+
+// q = A p with the dots the step length needs.
+__global__ __launch_bounds__(VEC_BLOCK) void spmv_dots_kernel(const DevProb* __restrict__ tab,
+                                                             const int2* __restrict__ blk, IterArgs ia) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    KState* st = P.st;
+    if (st->done) return;
+    __shared__ double sh[VEC_BLOCK / 64 + 1];
+    const int slot = ring_cur(st->it, ia.m);
+    double d[2] = {0.0, 0.0};
+    spmv_dots_rows(P.rowptr, P.col, P.val, P.p[slot], P.q[slot], P.r, g.lb * VEC_BLOCK + threadIdx.x,
+                   P.nblk * VEC_BLOCK, P.n, d);
+    double tot[2];
+    if (!grid_sum<2, VEC_BLOCK>(d, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
+    if (threadIdx.x == 0) set_alpha(st, tot, ia.mode, slot);
+}
+
+__device__ __forceinline__ void spmv_p_dots_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                                 const double* __restrict__ val, const double* __restrict__ z,
+                                                 const double* __restrict__ p_old, double* __restrict__ p_new,
+                                                 double* __restrict__ q, const double* __restrict__ r, double beta,
+                                                 int i0, int stride, int n, double (&d)[2]) {
+    for (int i = i0; i < n; i += stride) {
+        double acc = 0.0;
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            const int c = col[e];
+            acc = fma(val[e], fma(beta, p_old[c], z[c]), acc);
+        }
+        const double pi = fma(beta, p_old[i], z[i]);
+        p_new[i] = pi;
+        q[i] = acc;
+        d[0] = fma(pi, acc, d[0]);
+        d[1] = fma(pi, r[i], d[1]);
+    }
+}
+
+// One kept direction (FCG(1), PCG, CG): p_new = z + beta p_old is formed on the
+// fly for every column, q = A p_new, with the dots of spmv_dots_kernel. Every
+// row evaluates fma(beta, p_old, z) identically, so q is exactly A times the
+// stored p_new.
+__global__ __launch_bounds__(VEC_BLOCK) void spmv_p_dots_kernel(const DevProb* __restrict__ tab,
+                                                               const int2* __restrict__ blk, IterArgs ia) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    KState* st = P.st;
+    if (st->done) return;
+    __shared__ double sh[VEC_BLOCK / 64 + 1];
+    const int it = st->it;
+    const int slot = ring_cur(it, 1);
+    double d[2] = {0.0, 0.0};
+    spmv_p_dots_rows(P.rowptr, P.col, P.val, dir_src(P, ia.mode), P.p[ring_prev(it, 1, 0)], P.p[slot], P.q[slot],
+                     P.r, st->beta[0], g.lb * VEC_BLOCK + threadIdx.x, P.nblk * VEC_BLOCK, P.n, d);
+    double tot[2];
+    if (!grid_sum<2, VEC_BLOCK>(d, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
+    if (threadIdx.x == 0) set_alpha(st, tot, ia.mode, slot);
+}
+
+__device__ __forceinline__ void update_rows(double* __restrict__ u, double* __restrict__ r,
+                                            const double* __restrict__ p, const double* __restrict__ q, double alpha,
+                                            int i0, int stride, int n, double (&d)[1]) {
+    for (int i = i0; i < n; i += stride) {
+        u[i] = fma(alpha, p[i], u[i]);
+        const double ri = fma(-alpha, q[i], r[i]);
+        r[i] = ri;
+        d[0] = fma(ri, ri, d[0]);
+    }
+}
+
+// u += alpha p; r -= alpha q; convergence test on |r| / |r_0|.
+__global__ __launch_bounds__(VEC_BLOCK) void update_kernel(const DevProb* __restrict__ tab,
+                                                          const int2* __restrict__ blk, IterArgs ia) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    KState* st = P.st;
+    if (st->done) return;
+    __shared__ double sh[VEC_BLOCK / 64 + 1];
+    const int slot = ring_cur(st->it, ia.m);
+    double d[1] = {0.0};
+    update_rows(P.u, P.r, P.p[slot], P.q[slot], st->alpha, g.lb * VEC_BLOCK + threadIdx.x, P.nblk * VEC_BLOCK, P.n,
+                d);
+    double tot[1];
+    if (!grid_sum<1, VEC_BLOCK>(d, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
+    if (threadIdx.x != 0) return;
+    const double rr = tot[0];
+    st->it += 1;
+    if (!isfinite(rr)) {
+        st->status = DDMGNN_E_NONFINITE;
+        st->done = 1;
+        return;
+    }
+    st->rel = sqrt(rr) / st->r0n;
+    if (ia.mode == DDMGNN_CG) {  // M = I: rho = <r, r>, beta = rho_new / rho_old
+        st->beta[0] = rr / st->rho;
+        st->rho = rr;
+    }
+    if (st->rel <= st->rtol || st->it >= st->max_it) st->done = 1;
+}
+
+__device__ __forceinline__ void residual_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                              const double* __restrict__ val, const double* __restrict__ b,
+                                              const double* __restrict__ u, double* __restrict__ u_copy,
+                                              double* __restrict__ r, int i0, int stride, int n, double (&d)[1]) {
+    for (int i = i0; i < n; i += stride) {
+        double acc = 0.0;
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc = fma(val[e], u[col[e]], acc);
+        const double ri = b[i] - acc;
+        if (u_copy) u_copy[i] = u[i];
+        if (r) r[i] = ri;
+        d[0] = fma(ri, ri, d[0]);
+    }
+}
+
+// u = u0; r = b - A u0 with |r|^2; zero the direction ring; initialise the state.
+__global__ __launch_bounds__(VEC_BLOCK) void init_kernel(const DevProb* __restrict__ tab,
+                                                        const int2* __restrict__ blk) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    KState* st = P.st;
+    __shared__ double sh[VEC_BLOCK / 64 + 1];
+    const int i0 = g.lb * VEC_BLOCK + threadIdx.x, stride = P.nblk * VEC_BLOCK;
+    double d[1] = {0.0};
+    residual_rows(P.rowptr, P.col, P.val, P.b, P.u0, P.u, P.r, i0, stride, P.n, d);
+    for (int k = 0; k <= MAX_M; ++k) {
+        double* __restrict__ pk = P.p[k];
+        double* __restrict__ qk = P.q[k];
+        for (int i = i0; i < P.n; i += stride) {
+            pk[i] = 0.0;
+            qk[i] = 0.0;
+        }
+    }
+    double tot[1];
+    if (!grid_sum<1, VEC_BLOCK>(d, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
+    if (threadIdx.x != 0) return;
+    st->r0n = sqrt(tot[0]);
+    st->rtol = P.rtol;
+    st->rel = tot[0] == 0.0 ? 0.0 : 1.0;
+    st->alpha = 0.0;
+    for (int i = 0; i < MAX_M; ++i) st->beta[i] = 0.0;
+    for (int i = 0; i <= MAX_M; ++i) st->pq[i] = 1.0;
+    st->rho = tot[0];
+    st->rr_true = 0.0;
+    st->it = 0;
+    st->max_it = P.max_it;
+    st->status = isfinite(tot[0]) ? 0 : DDMGNN_E_NONFINITE;
+    st->done = (tot[0] == 0.0 || !isfinite(tot[0]) || P.max_it <= 0) ? 1 : 0;
+}
+
+// |b - A u|^2 of each problem into its state.
+__global__ __launch_bounds__(VEC_BLOCK) void resid_kernel(const DevProb* __restrict__ tab,
+                                                         const int2* __restrict__ blk) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    __shared__ double sh[VEC_BLOCK / 64 + 1];
+    double d[1] = {0.0};
+    residual_rows(P.rowptr, P.col, P.val, P.b, P.u, nullptr, nullptr, g.lb * VEC_BLOCK + threadIdx.x,
+                  P.nblk * VEC_BLOCK, P.n, d);
+    double tot[1];
+    if (!grid_sum<1, VEC_BLOCK>(d, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
+    if (threadIdx.x == 0) P.st->rr_true = tot[0];
+}
+
+// Plain y = A x and a deterministic dot (entry points outside the solve).
+__global__ __launch_bounds__(VEC_BLOCK) void spmv_kernel(const int32_t* __restrict__ rowptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val, const double* __restrict__ x,
+                                                        double* __restrict__ y, int n) {
+    for (int i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
+        double acc = 0.0;
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc = fma(val[e], x[col[e]], acc);
+        y[i] = acc;
+    }
+}
+
+__global__ __launch_bounds__(VEC_BLOCK) void dot_kernel(const double* __restrict__ x, const double* __restrict__ y,
+                                                       int64_t n, double* partials, unsigned* counter,
+                                                       double* out) {
+    __shared__ double sh[VEC_BLOCK / 64 + 1];
+    double d[1] = {0.0};
+    for (int64_t i = blockIdx.x * (int64_t)VEC_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VEC_BLOCK)
+        d[0] = fma(x[i], y[i], d[0]);
+    double tot[1];
+    if (!grid_sum<1, VEC_BLOCK>(d, partials, counter, blockIdx.x, gridDim.x, tot, sh)) return;
+    if (threadIdx.x == 0) *out = tot[0];
+}
+
+// Copies the Krylov state of every problem of a table to one array (one host poll per chunk).
+__global__ __launch_bounds__(VEC_BLOCK) void gather_states_kernel(const DevProb* __restrict__ tab, int n,
+                                                                 KState* __restrict__ out) {
+    const int i = blockIdx.x * VEC_BLOCK + threadIdx.x;
+    if (i < n) out[i] = *tab[i].st;
+}
+
+inline hipError_t done(bool check) { return check ? hipGetLastError() : hipSuccess; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+hipError_t prepare_dss_valu(int precision, size_t shmem) {
+    const void* fn = precision == DDMGNN_FP64 ? (const void*)dss_kernel<double, false, true>
+                                              : (const void*)dss_kernel<float, true, true>;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+}
+
+hipError_t launch_dss_valu(const DevProb* tab, const int2* work, int n_work, int precision, bool qlds, int kbar,
+                           double alpha, int apply, const float* theta32, const double* theta64, size_t shmem,
+                           hipStream_t s, bool check) {
+    if (n_work <= 0) return hipSuccess;
+    if (precision == DDMGNN_FP64) {
+        DssArgs<double> a{tab, work, kbar, alpha, apply};
+        if (qlds)
+            hipLaunchKernelGGL((dss_kernel<double, false, true>), dim3(n_work), dim3(DSS_BLOCK), shmem, s, a, theta64);
+        else
+            hipLaunchKernelGGL((dss_kernel<double, false, false>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a, theta64);
+    } else {
+        DssArgs<float> a{tab, work, kbar, (float)alpha, apply};
+        if (qlds)
+            hipLaunchKernelGGL((dss_kernel<float, true, true>), dim3(n_work), dim3(DSS_BLOCK), shmem, s, a, theta32);
+        else
+            hipLaunchKernelGGL((dss_kernel<float, true, false>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a, theta32);
+    }
+    return done(check);
+}
+
+hipError_t launch_coarse(const DevProb* tab, const int2* rows, int n_rows, hipStream_t s, bool check) {
+    if (n_rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(coarse_kernel, dim3(n_rows), dim3(VEC_BLOCK), 0, s, tab, rows);
+    return done(check);
+}
+
+hipError_t launch_prolong(const DevProb* tab, const int2* blk, int n_blk, const IterArgs& it, hipStream_t s,
+                          bool check) {
+    hipLaunchKernelGGL(prolong_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    return done(check);
+}
+
+hipError_t launch_krylov(const DevProb* tab, const int2* blk, int n_blk, const IterArgs& it, hipStream_t s,
+                         bool check) {
+    if (it.m == 1) {
+        hipLaunchKernelGGL(spmv_p_dots_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    } else {
+        hipLaunchKernelGGL(pupdate_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+        hipLaunchKernelGGL(spmv_dots_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    }
+    hipLaunchKernelGGL(update_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    return done(check);
+}
+
+hipError_t launch_init(const DevProb* tab, const int2* blk, int n_blk, hipStream_t s) {
+    hipLaunchKernelGGL(init_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid(const DevProb* tab, const int2* blk, int n_blk, hipStream_t s) {
+    hipLaunchKernelGGL(resid_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_states(const DevProb* tab, int n, KState* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_states_kernel, dim3((n + VEC_BLOCK - 1) / VEC_BLOCK), dim3(VEC_BLOCK), 0, s, tab, n,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, double* y,
+                       int n, hipStream_t s) {
+    hipLaunchKernelGGL(spmv_kernel, dim3(vec_blocks(n)), dim3(VEC_BLOCK), 0, s, rowptr, col, val, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(const double* x, const double* y, int64_t n, double* partials, unsigned* counter, double* out,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(dot_kernel, dim3(vec_blocks(n)), dim3(VEC_BLOCK), 0, s, x, y, n, partials, counter, out);
+    return hipGetLastError();
+}
+
+}  // namespace ddmgnn

@@ -1,0 +1,928 @@
+// Host runtime of the DDM-GNN solver: contexts, models, problems, batches of
+// problems solved in lockstep, the solve driver (graph-captured chunks of
+// iterations, host polls of the per-problem converged flags) and the C ABI
+// declared in include/ddmgnn.h (the serving entry points are in server.cpp).
+#include "runtime.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace ddmgnn {
+
+namespace {
+thread_local std::string g_err;
+std::atomic<uint64_t> g_next_id{1};
+}  // namespace
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+// ------------------------------------------------------------------ batch
+struct Batch {
+    ddmgnn_ctx* ctx = nullptr;
+    std::vector<ddmgnn_problem*> probs;
+    std::vector<uint64_t> ids;
+    std::shared_ptr<ModelDev> model;
+    std::vector<DevProb> views;        // host copy of tab
+    DevBuf<DevProb> tab;               // table of the solve
+    DevBuf<DevProb> hook;              // one-problem table of the entry points that redirect vectors
+    // DSS work lists, (problem, sub-mesh) by decreasing sub-mesh size:
+    // all sub-meshes; those of problems that fit the MFMA kernel; the others.
+    DevBuf<int2> work_all, work_mfma, work_rest;
+    int n_all = 0, n_mfma = 0, n_rest = 0;
+    int max_k_all = 0, max_k_rest = 0;
+    DevBuf<int2> vec_blk;              // (problem, local workgroup)
+    int n_vec = 0;
+    DevBuf<int2> coarse_rows;          // (problem, first of COARSE_ROWS rows)
+    int n_coarse = 0;
+    DevBuf<int2> sub_blk;              // subset of vec_blk (init and residual of some problems)
+    int n_sub_blk = 0;
+    DevBuf<KState> st_gather;
+    KState* host_st = nullptr;         // pinned, one per problem
+    hipGraphExec_t graph = nullptr;    // captured chunk of iterations
+    uint64_t graph_key = 0;
+    ~Batch() {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (host_st) (void)hipHostFree(host_st);
+    }
+};
+
+namespace {
+
+DevProb make_view(ddmgnn_problem* P) {
+    DevProb v{};
+    v.rowptr = P->rowptr.p; v.col = P->col.p; v.val = P->val.p; v.b = P->b.p; v.u0 = P->u0.p;
+    v.dirichlet = P->dirichlet.p;
+    v.sub_ptr = P->sub_ptr.p; v.sub_nodes = P->sub_nodes.p; v.weights = P->weights.p;
+    v.edge_ptr = P->edge_ptr.p; v.edge_src = P->edge_src.p; v.edge_nd = P->edge_nd.p; v.erec = P->erec.p;
+    v.tiles = P->tiles.p; v.xy64 = P->xy64.p; v.xyc32 = P->xyc32.p;
+    v.node_ptr = P->node_ptr.p; v.node_slots = P->node_slots.p; v.slot_sub = P->slot_sub.p; v.a0inv = P->a0inv.p;
+    v.u = P->u.p; v.r = P->r.p; v.z = P->z.p; v.c_in = nullptr;
+    const int64_t n = P->hs.n;
+    for (int i = 0; i <= MAX_M; ++i) {
+        v.p[i] = P->ring.p + (size_t)i * n;
+        v.q[i] = P->ring.p + (size_t)(MAX_M + 1 + i) * n;
+    }
+    v.s = P->s.p; v.y0 = P->y0.p; v.y = P->y.p; v.local = P->local.p;
+    v.qg64 = P->qglobal64.p; v.hg64 = P->hglobal64.p; v.qg32 = P->qglobal32.p;
+    v.st = P->st.p;
+    v.partials = P->partials.p;
+    v.counter = P->counters.p;
+    v.rtol = P->rtol;
+    v.max_it = P->max_it;
+    v.n = (int)n;
+    v.K = P->hs.K;
+    v.nblk = vec_blocks(n);
+    return v;
+}
+
+hipError_t upload_async(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+template <typename T>
+int upload_list(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
+    if (buf.n < v.size() || !buf.p) HIP_TRY(buf.alloc(std::max<size_t>(v.size(), 1)));
+    HIP_TRY(upload_async(buf.p, v.data(), v.size() * sizeof(T), s));
+    return DDMGNN_OK;
+}
+
+bool valu_q_in_lds(int max_k, int precision) {
+    const size_t esz = precision == DDMGNN_FP64 ? sizeof(double) : sizeof(float);
+    return (size_t)max_k * 2 * D * esz + 1024 <= LDS_LIMIT;
+}
+
+size_t valu_shmem(int max_k, int precision) {
+    const size_t esz = precision == DDMGNN_FP64 ? sizeof(double) : sizeof(float);
+    return (size_t)max_k * 2 * D * esz;
+}
+
+// Allocates what the DSS launches of this precision need (fallback storage,
+// LDS attributes). Not allowed during stream capture; returns true in
+// `changed` when a problem's buffers moved (the table must be re-uploaded).
+int prepare_dss(Batch& B, int precision, bool& changed) {
+    changed = false;
+    const bool bf16 = precision == DDMGNN_BF16;
+    if (bf16 && B.n_mfma) HIP_TRY(prepare_dss_mfma(MFMA_LDS_LIMIT));
+    const int valu_prec = bf16 ? DDMGNN_FP32 : precision;
+    const int max_k = bf16 ? B.max_k_rest : B.max_k_all;
+    const int n_valu = bf16 ? B.n_rest : B.n_all;
+    if (n_valu == 0) return DDMGNN_OK;
+    const bool f64 = valu_prec == DDMGNN_FP64;
+    const bool in_lds = valu_q_in_lds(max_k, valu_prec);
+    for (ddmgnn_problem* P : B.probs) {
+        if (bf16 && P->mfma_fits) continue;
+        const size_t sk = (size_t)P->hs.sk;
+        if (!in_lds) {
+            if (f64 && P->qglobal64.n < sk * 2 * D) {
+                HIP_TRY(P->qglobal64.alloc(sk * 2 * D));
+                changed = true;
+            }
+            if (!f64 && P->qglobal32.n < sk * 2 * D) {
+                HIP_TRY(P->qglobal32.alloc(sk * 2 * D));
+                changed = true;
+            }
+        }
+        if (f64 && P->hglobal64.n < sk * D) {
+            HIP_TRY(P->hglobal64.alloc(sk * D));
+            changed = true;
+        }
+    }
+    if (in_lds) HIP_TRY(prepare_dss_valu(valu_prec, LDS_LIMIT - 1024));
+    return DDMGNN_OK;
+}
+
+// DSS forward over every sub-mesh of the table (apply: restriction and s r~).
+int enqueue_dss(Batch& B, const DevProb* tab, int precision, int apply, bool capturing) {
+    hipStream_t s = B.ctx->launch;
+    const ModelDev& M = *B.model;
+    const bool check = !capturing;
+    if (precision == DDMGNN_BF16) {
+        DssMfmaArgs a{tab, B.work_mfma.p, M.steps.p, M.dec.p, M.kbar, (float)M.alpha, apply};
+        HIP_TRY(launch_dss_mfma(a, B.n_mfma, MFMA_LDS_LIMIT, s, check));
+        const bool qlds = valu_q_in_lds(B.max_k_rest, DDMGNN_FP32);
+        HIP_TRY(launch_dss_valu(tab, B.work_rest.p, B.n_rest, DDMGNN_FP32, qlds, M.kbar, M.alpha, apply,
+                                M.theta32.p, M.theta64.p, qlds ? valu_shmem(B.max_k_rest, DDMGNN_FP32) : 0, s,
+                                check));
+    } else {
+        const bool qlds = valu_q_in_lds(B.max_k_all, precision);
+        HIP_TRY(launch_dss_valu(tab, B.work_all.p, B.n_all, precision, qlds, M.kbar, M.alpha, apply, M.theta32.p,
+                                M.theta64.p, qlds ? valu_shmem(B.max_k_all, precision) : 0, s, check));
+    }
+    return DDMGNN_OK;
+}
+
+IterArgs iter_args(const ddmgnn_solve_opts& o, int mode) {
+    IterArgs ia{};
+    ia.mode = mode;
+    ia.m = mode == DDMGNN_FCG ? o.m_max : 1;
+    ia.unweighted = o.prolong == DDMGNN_PROLONG_UNWEIGHTED;
+    ia.coarse = o.coarse;
+    return ia;
+}
+
+// One preconditioner apply z = M(r) over the table (mode < 0: no Krylov dots).
+// ev (optional): events recorded after the DSS (ev[1]), coarse (ev[2]) and prolong (ev[3]) launches.
+int enqueue_apply(Batch& B, const DevProb* tab, const ddmgnn_solve_opts& o, int mode, hipEvent_t* ev,
+                  bool capturing) {
+    if (int rc = enqueue_dss(B, tab, o.precision, 1, capturing)) return rc;
+    hipStream_t s = B.ctx->launch;
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    if (o.coarse) HIP_TRY(launch_coarse(tab, B.coarse_rows.p, B.n_coarse, s, !capturing));
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    HIP_TRY(launch_prolong(tab, B.vec_blk.p, B.n_vec, iter_args(o, mode), s, !capturing));
+    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    return DDMGNN_OK;
+}
+
+// One FCG/PCG/CG iteration of every problem of the batch. ev: optional 5
+// profiling events (before DSS, after DSS / coarse / prolong, end).
+int enqueue_iteration(Batch& B, const ddmgnn_solve_opts& o, hipEvent_t* ev, bool capturing) {
+    hipStream_t s = B.ctx->launch;
+    const int mode = o.krylov;
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    if (mode == DDMGNN_CG) {
+        if (ev)
+            for (int q = 1; q < 4; ++q) HIP_TRY(hipEventRecord(ev[q], s));
+    } else {
+        if (int rc = enqueue_apply(B, B.tab.p, o, mode, ev, capturing)) return rc;
+    }
+    HIP_TRY(launch_krylov(B.tab.p, B.vec_blk.p, B.n_vec, iter_args(o, mode), s, !capturing));
+    if (ev) HIP_TRY(hipEventRecord(ev[4], s));
+    return DDMGNN_OK;
+}
+
+uint64_t graph_key(const ddmgnn_solve_opts& o, int count) {
+    return ((uint64_t)o.krylov << 44) | ((uint64_t)o.m_max << 40) | ((uint64_t)o.precision << 36) |
+           ((uint64_t)o.prolong << 34) | ((uint64_t)o.coarse << 32) | (uint64_t)(uint32_t)count;
+}
+
+// Captures `count` iterations of the batch into B.graph (on the context's own
+// stream: the caller's stream may be the null stream, which cannot be captured).
+int capture_chunk(Batch& B, const ddmgnn_solve_opts& o, int count) {
+    ddmgnn_ctx* ctx = B.ctx;
+    if (B.graph) {
+        (void)hipGraphExecDestroy(B.graph);
+        B.graph = nullptr;
+        B.graph_key = 0;
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed));
+    ctx->launch = ctx->cap;
+    int crc = 0;
+    for (int c = 0; c < count && crc == 0; ++c) crc = enqueue_iteration(B, o, nullptr, true);
+    ctx->launch = ctx->stream;
+    hipError_t ce = hipStreamEndCapture(ctx->cap, &g);
+    if (crc || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(ctx->cap, &cst) == hipSuccess && cst != hipStreamCaptureStatusNone) {
+            hipGraph_t g2 = nullptr;
+            (void)hipStreamEndCapture(ctx->cap, &g2);
+            if (g2) (void)hipGraphDestroy(g2);
+        }
+        if (crc) return crc;
+        HIP_TRY(ce);
+    }
+    HIP_TRY(hipGetLastError());
+    hipError_t ie = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(ie);
+    B.graph_key = graph_key(o, count);
+    return DDMGNN_OK;
+}
+
+int upload_table(Batch& B) {
+    B.views.resize(B.probs.size());
+    for (size_t i = 0; i < B.probs.size(); ++i) B.views[i] = make_view(B.probs[i]);
+    return upload_list(B.tab, B.views, B.ctx->stream);
+}
+
+// Workgroup list of the problems flagged in `which`.
+int upload_subset(Batch& B, const std::vector<uint8_t>* which) {
+    std::vector<int2> sub;
+    for (size_t i = 0; i < B.probs.size(); ++i) {
+        if (which && !(*which)[i]) continue;
+        const int nb = vec_blocks(B.probs[i]->hs.n);
+        for (int b = 0; b < nb; ++b) sub.push_back(make_int2((int)i, b));
+    }
+    B.n_sub_blk = (int)sub.size();
+    return upload_list(B.sub_blk, sub, B.ctx->stream);
+}
+
+int solo_batch(ddmgnn_problem* P) {
+    if (P->solo) return DDMGNN_OK;
+    ddmgnn_problem* one[1] = {P};
+    return build_batch(P->ctx, one, 1, P->solo);
+}
+
+// Solve every problem of the batch from its u0 with options o.
+int solve_batch(ddmgnn_ctx* ctx, Batch& B, const ddmgnn_solve_opts& o, double* const* u_out, ddmgnn_stats* stats) {
+    hipStream_t s = ctx->stream;
+    const int nb = (int)B.probs.size();
+    for (ddmgnn_problem* P : B.probs) {
+        P->rtol = o.rtol;
+        P->max_it = o.max_it;
+    }
+    hipEvent_t ev0, ev1;
+    HIP_TRY(hipEventCreate(&ev0));
+    HIP_TRY(hipEventCreate(&ev1));
+    struct EvGuard {
+        hipEvent_t a, b;
+        std::vector<hipEvent_t> v;
+        ~EvGuard() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            for (auto e : v) (void)hipEventDestroy(e);
+        }
+    } guard{ev0, ev1, {}};
+    if (int rc = batch_begin(B, o, nullptr)) return rc;
+    HIP_TRY(hipEventRecord(ev0, s));
+    HIP_TRY(launch_init(B.tab.p, B.vec_blk.p, B.n_vec, s));
+    // Iterations between host polls of the converged flags; a captured chunk
+    // is replayed as a whole (problems that finish inside it idle).
+    const int check = std::max(1, o.check_every);
+    const bool use_graph = o.graph && !o.profile;
+    if (o.profile) {
+        guard.v.resize((size_t)check * 5);
+        for (auto& e : guard.v) HIP_TRY(hipEventCreate(&e));
+    }
+    double t_dss = 0, t_coarse = 0, t_prolong = 0, t_krylov = 0;
+    int n_dss = 0, it = 0, it_seen = 0;
+    bool done = o.max_it <= 0;
+    while (!done) {
+        const int n_chunk = use_graph ? check : std::min(check, o.max_it - it);
+        if (use_graph) {
+            if (!B.graph || B.graph_key != graph_key(o, n_chunk))
+                if (int rc = capture_chunk(B, o, n_chunk)) return rc;
+            HIP_TRY(hipGraphLaunch(B.graph, s));
+        } else {
+            for (int c = 0; c < n_chunk; ++c)
+                if (int rc = enqueue_iteration(B, o, o.profile ? &guard.v[(size_t)c * 5] : nullptr, false)) return rc;
+        }
+        if (int rc = batch_poll(B)) return rc;
+        it += n_chunk;
+        bool all = true;
+        int max_it_done = 0;
+        for (int i = 0; i < nb; ++i) {
+            all = all && B.host_st[i].done;
+            max_it_done = std::max(max_it_done, B.host_st[i].it);
+        }
+        done = all || it >= o.max_it;
+        if (o.profile) {
+            // iterations it_seen .. max_it_done-1 did work; later ones exited at once
+            const int worked = std::min(n_chunk, std::max(0, max_it_done - it_seen));
+            for (int c = 0; c < worked; ++c) {
+                hipEvent_t* ev = &guard.v[(size_t)c * 5];
+                float a = 0, b = 0, cc = 0, d = 0;
+                HIP_TRY(hipEventElapsedTime(&a, ev[0], ev[1]));
+                HIP_TRY(hipEventElapsedTime(&b, ev[1], ev[2]));
+                HIP_TRY(hipEventElapsedTime(&cc, ev[2], ev[3]));
+                HIP_TRY(hipEventElapsedTime(&d, ev[3], ev[4]));
+                t_dss += a;
+                t_coarse += b;
+                t_prolong += cc;
+                t_krylov += d;
+                if (o.krylov != DDMGNN_CG) ++n_dss;
+            }
+        }
+        it_seen = max_it_done;
+    }
+    HIP_TRY(hipEventRecord(ev1, s));
+    if (int rc = batch_true_residual(B, nullptr)) return rc;
+    for (int i = 0; i < nb; ++i)
+        HIP_TRY(hipMemcpyAsync(u_out[i], B.probs[i]->u.p, B.probs[i]->hs.n * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1));
+    int first_bad = DDMGNN_OK;
+    for (int i = 0; i < nb; ++i) {
+        const KState& k = B.host_st[i];
+        const bool converged = k.status == 0 && k.rel <= o.rtol;
+        if (stats) {
+            ddmgnn_stats& S = stats[i];
+            std::memset(&S, 0, sizeof(S));
+            S.iterations = k.it;
+            S.converged = converged;
+            S.rel_residual = k.rel;
+            S.true_rel_residual = k.r0n > 0 ? std::sqrt(k.rr_true) / k.r0n : 0.0;
+            S.solve_ms = ms;
+            S.dss_launches = n_dss;
+            S.dss_ms = t_dss;
+            S.coarse_ms = t_coarse;
+            S.prolong_ms = t_prolong;
+            S.krylov_ms = t_krylov;
+            S.dss_kernel = dss_kernel_of(B.probs[i], o.precision);
+            S.status = k.status ? k.status : (converged ? DDMGNN_OK : DDMGNN_E_MAXIT);
+            S.latency_ms = ms;
+        }
+        if (first_bad == DDMGNN_OK) {
+            if (k.status) first_bad = fail(k.status, "Krylov breakdown or non-finite residual");
+            else if (!converged) first_bad = fail(DDMGNN_E_MAXIT, "not converged within max_it");
+        }
+    }
+    return first_bad;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ batch API
+void BatchDeleter::operator()(Batch* b) const { delete b; }
+
+int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& out) {
+    BatchPtr B(new Batch());
+    B->ctx = ctx;
+    B->probs.assign(probs, probs + n);
+    for (int i = 0; i < n; ++i) B->ids.push_back(probs[i]->id);
+    B->model = probs[0]->model;
+    struct W {
+        int k, p, sub;
+    };
+    std::vector<W> all;
+    std::vector<int2> vec, rows;
+    for (int i = 0; i < n; ++i) {
+        const ddmgnn_problem* P = probs[i];
+        const auto& sp = P->hs.sub_ptr;
+        for (int j = 0; j < P->hs.K; ++j) all.push_back({(int)(sp[j + 1] - sp[j]), i, j});
+        const int nb = vec_blocks(P->hs.n);
+        for (int b = 0; b < nb; ++b) vec.push_back(make_int2(i, b));
+        for (int r = 0; r < P->hs.K; r += COARSE_ROWS) rows.push_back(make_int2(i, r));
+    }
+    // Largest sub-meshes first (a deterministic order: size, then problem, then sub-mesh).
+    std::stable_sort(all.begin(), all.end(), [](const W& a, const W& b) {
+        if (a.k != b.k) return a.k > b.k;
+        if (a.p != b.p) return a.p < b.p;
+        return a.sub < b.sub;
+    });
+    std::vector<int2> wa, wm, wr;
+    for (const W& w : all) {
+        wa.push_back(make_int2(w.p, w.sub));
+        B->max_k_all = std::max(B->max_k_all, w.k);
+        if (probs[w.p]->mfma_fits) {
+            wm.push_back(make_int2(w.p, w.sub));
+        } else {
+            wr.push_back(make_int2(w.p, w.sub));
+            B->max_k_rest = std::max(B->max_k_rest, w.k);
+        }
+    }
+    hipStream_t s = ctx->stream;
+    if (int rc = upload_list(B->work_all, wa, s)) return rc;
+    if (int rc = upload_list(B->work_mfma, wm, s)) return rc;
+    if (int rc = upload_list(B->work_rest, wr, s)) return rc;
+    if (int rc = upload_list(B->vec_blk, vec, s)) return rc;
+    if (int rc = upload_list(B->coarse_rows, rows, s)) return rc;
+    B->n_all = (int)wa.size();
+    B->n_mfma = (int)wm.size();
+    B->n_rest = (int)wr.size();
+    B->n_vec = (int)vec.size();
+    B->n_coarse = (int)rows.size();
+    HIP_TRY(B->st_gather.alloc(n));
+    HIP_TRY(B->hook.alloc(1));
+    HIP_TRY(hipHostMalloc((void**)&B->host_st, sizeof(KState) * n, hipHostMallocDefault));
+    std::memset(B->host_st, 0, sizeof(KState) * n);
+    if (int rc = upload_table(*B)) return rc;
+    out = std::move(B);
+    return DDMGNN_OK;
+}
+
+int batch_begin(Batch& B, const ddmgnn_solve_opts& o, const std::vector<uint8_t>* init) {
+    bool changed = false;
+    if (o.krylov != DDMGNN_CG)
+        if (int rc = prepare_dss(B, o.precision, changed)) return rc;
+    if (changed && B.graph) {  // captured launches point at moved buffers
+        (void)hipGraphExecDestroy(B.graph);
+        B.graph = nullptr;
+        B.graph_key = 0;
+    }
+    if (int rc = upload_table(B)) return rc;
+    if (init) {
+        if (int rc = upload_subset(B, init)) return rc;
+        if (B.n_sub_blk) HIP_TRY(launch_init(B.tab.p, B.sub_blk.p, B.n_sub_blk, B.ctx->stream));
+    }
+    return DDMGNN_OK;
+}
+
+int batch_iterate(Batch& B, const ddmgnn_solve_opts& o, int count, bool use_graph) {
+    if (use_graph) {
+        if (!B.graph || B.graph_key != graph_key(o, count))
+            if (int rc = capture_chunk(B, o, count)) return rc;
+        HIP_TRY(hipGraphLaunch(B.graph, B.ctx->stream));
+        return DDMGNN_OK;
+    }
+    for (int c = 0; c < count; ++c)
+        if (int rc = enqueue_iteration(B, o, nullptr, false)) return rc;
+    return DDMGNN_OK;
+}
+
+int batch_poll(Batch& B) {
+    hipStream_t s = B.ctx->stream;
+    const int n = (int)B.probs.size();
+    HIP_TRY(launch_gather_states(B.tab.p, n, B.st_gather.p, s));
+    HIP_TRY(hipMemcpyAsync(B.host_st, B.st_gather.p, sizeof(KState) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return DDMGNN_OK;
+}
+
+const KState& batch_state(const Batch& B, int i) { return B.host_st[i]; }
+int batch_size(const Batch& B) { return (int)B.probs.size(); }
+ddmgnn_problem* batch_problem(const Batch& B, int i) { return B.probs[i]; }
+
+int batch_true_residual(Batch& B, const std::vector<uint8_t>* which) {
+    if (which) {
+        if (int rc = upload_subset(B, which)) return rc;
+        if (B.n_sub_blk) HIP_TRY(launch_resid(B.tab.p, B.sub_blk.p, B.n_sub_blk, B.ctx->stream));
+    } else {
+        HIP_TRY(launch_resid(B.tab.p, B.vec_blk.p, B.n_vec, B.ctx->stream));
+    }
+    return batch_poll(B);
+}
+
+int dss_kernel_of(const ddmgnn_problem* P, int precision) {
+    if (precision == DDMGNN_FP64) return 0;
+    return precision == DDMGNN_BF16 && P->mfma_fits ? 2 : 1;
+}
+
+int check_opts(const ddmgnn_solve_opts& o) {
+    if (o.krylov < 0 || o.krylov > 2) return fail(DDMGNN_E_INVALID, "krylov must be FCG, PCG or CG");
+    if (o.krylov == DDMGNN_FCG && (o.m_max < 1 || o.m_max > MAX_M)) return fail(DDMGNN_E_INVALID, "m_max must be in [1, 4]");
+    if (!(o.rtol >= 0.0)) return fail(DDMGNN_E_INVALID, "rtol must be >= 0");
+    if (o.max_it < 0) return fail(DDMGNN_E_INVALID, "max_it must be >= 0");
+    if (o.precision < 0 || o.precision > 2) return fail(DDMGNN_E_INVALID, "precision must be FP64, FP32 or BF16");
+    if (o.prolong < 0 || o.prolong > 1) return fail(DDMGNN_E_INVALID, "prolong must be POU or UNWEIGHTED");
+    return DDMGNN_OK;
+}
+
+size_t problem_device_bytes(int64_t n, int64_t nnz, int32_t K, int64_t sk, int64_t ne) {
+    size_t b = 0;
+    b += 4 * (n + 1) + 12 * nnz;                 // CSR
+    b += 8 * n * 2 + n;                          // b, u0, dirichlet
+    b += 4 * (K + 1) + 12 * sk;                  // sub_ptr, sub_nodes, weights
+    b += 4 * (sk + 1) + (2 + 4 + 4) * (ne + 8);  // edge_ptr, edge_src, erec, edge_nd
+    b += 16 * sk + 16 * sk + 8 * sk;             // tiles, xy64, xyc32
+    b += 4 * (n + 1) + 8 * sk;                   // node_ptr, node_slots, slot_sub
+    b += 8 * (size_t)K * K + 24 * (size_t)K;     // a0inv, s, y0, y
+    b += 8 * sk;                                 // local
+    b += 8 * n * (3 + 2 * (MAX_M + 1));          // u, r, z, direction ring
+    b += 8 * (MAX_M + 1) * VEC_GRID + 16 + sizeof(KState);
+    return b;
+}
+
+int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared_ptr<ModelDev> model,
+                   HostSetup&& hs_in, ddmgnn_problem** out) {
+    auto P = std::make_unique<ddmgnn_problem>();
+    P->ctx = ctx;
+    P->id = g_next_id.fetch_add(1);
+    P->hs = std::move(hs_in);
+    P->model = std::move(model);
+    const auto& hs = P->hs;
+    const int64_t n = hs.n, sk = hs.sk;
+    const int K = hs.K;
+    hipStream_t s = ctx->stream;
+    HIP_TRY(P->rowptr.upload(desc.a_rowptr, n + 1, s));
+    HIP_TRY(P->col.upload(desc.a_col, hs.nnz, s));
+    HIP_TRY(P->val.upload(desc.a_val, hs.nnz, s));
+    HIP_TRY(P->b.upload(desc.b, n, s));
+    HIP_TRY(P->u0.upload(desc.u0, n, s));
+    HIP_TRY(P->dirichlet.upload(desc.dirichlet, n, s));
+    std::vector<int32_t> sp32(K + 1);
+    for (int i = 0; i <= K; ++i) sp32[i] = (int32_t)desc.sub_ptr[i];
+    HIP_TRY(P->sub_ptr.upload(sp32.data(), K + 1, s));
+    HIP_TRY(P->sub_nodes.upload(desc.sub_nodes, sk, s));
+    HIP_TRY(P->weights.upload(desc.weights, sk, s));
+    std::vector<int32_t> ep32(sk + 1);
+    for (int64_t i = 0; i <= sk; ++i) ep32[i] = (int32_t)hs.edge_ptr[i];
+    HIP_TRY(P->edge_ptr.upload(ep32.data(), sk + 1, s));
+    {
+        // padded by 8 entries: the chunked edge loops read up to 3 past a node's last edge
+        std::vector<uint16_t> src(hs.edge_src);
+        src.resize(src.size() + 8, 0);
+        HIP_TRY(P->edge_src.upload(src.data(), src.size(), s));
+    }
+    std::vector<int32_t> np32(n + 1);
+    for (int64_t i = 0; i <= n; ++i) np32[i] = (int32_t)hs.node_ptr[i];
+    HIP_TRY(P->node_ptr.upload(np32.data(), n + 1, s));
+    HIP_TRY(P->node_slots.upload(hs.node_slots.data(), sk, s));
+    HIP_TRY(P->slot_sub.upload(hs.slot_sub.data(), sk, s));
+    std::vector<double> xy64(2 * sk);
+    std::vector<float> xyc32(2 * sk);
+    for (int64_t k = 0; k < sk; ++k) {
+        const int32_t v = desc.sub_nodes[k];
+        xy64[2 * k] = desc.xy[2 * v];
+        xy64[2 * k + 1] = desc.xy[2 * v + 1];
+        xyc32[2 * k] = (float)hs.xyc[2 * k];
+        xyc32[2 * k + 1] = (float)hs.xyc[2 * k + 1];
+    }
+    HIP_TRY(P->xy64.upload(xy64.data(), 2 * sk, s));
+    HIP_TRY(P->xyc32.upload(xyc32.data(), 2 * sk, s));
+    HIP_TRY(P->a0inv.upload(hs.a0inv.data(), (size_t)K * K, s));
+    {
+        std::vector<TileNode> tiles(sk);
+        for (int i = 0; i < K; ++i) {
+            const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
+            for (int64_t q = b; q < e; ++q) {
+                const int32_t j = hs.tnode[q];
+                const int64_t slot = b + j;
+                TileNode& t = tiles[q];
+                t.e0 = (int32_t)hs.edge_ptr[slot];
+                t.j = (uint16_t)j;
+                t.deg = (uint16_t)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]);
+                t.xh = hs.xyhl[4 * slot + 0];
+                t.xl = hs.xyhl[4 * slot + 1];
+                t.yh = hs.xyhl[4 * slot + 2];
+                t.yl = hs.xyhl[4 * slot + 3];
+            }
+        }
+        HIP_TRY(P->tiles.upload(tiles.data(), tiles.size(), s));
+        std::vector<uint32_t> er(hs.erec);
+        er.resize(er.size() + 8, 0u);
+        HIP_TRY(P->erec.upload(er.data(), er.size(), s));
+        size_t need = 0;
+        for (int i = 0; i < K; ++i) {
+            const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
+            need = std::max(need, mfma_lds_need((int)(e - b), hs.edge_ptr[e] - hs.edge_ptr[b]));
+        }
+        P->mfma_fits = need <= MFMA_LDS_LIMIT;
+    }
+    {
+        std::vector<float> nd(hs.edge_nd);
+        nd.resize(nd.size() + 8, 0.0f);
+        HIP_TRY(P->edge_nd.upload(nd.data(), nd.size(), s));
+    }
+    HIP_TRY(P->s.alloc(K));
+    HIP_TRY(P->y0.alloc(K));
+    HIP_TRY(P->y.alloc(K));
+    HIP_TRY(P->local.alloc(sk));
+    HIP_TRY(P->u.alloc(n));
+    HIP_TRY(P->r.alloc(n));
+    HIP_TRY(P->z.alloc(n));
+    HIP_TRY(P->ring.alloc((size_t)2 * (MAX_M + 1) * n));
+    HIP_TRY(P->st.alloc(1));
+    HIP_TRY(P->partials.alloc((size_t)(MAX_M + 1) * VEC_GRID));
+    HIP_TRY(P->counters.alloc(4));
+    HIP_TRY(hipMemsetAsync(P->counters.p, 0, 4 * sizeof(unsigned), s));
+    HIP_TRY(hipMemsetAsync(P->st.p, 0, sizeof(KState), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    P->device_bytes = problem_device_bytes(n, hs.nnz, K, sk, hs.n_edges);
+    *out = P.release();
+    return DDMGNN_OK;
+}
+
+}  // namespace ddmgnn
+
+using namespace ddmgnn;
+
+ddmgnn_ctx::~ddmgnn_ctx() {
+    last_batch.reset();
+    if (host_pinned) (void)hipHostFree(host_pinned);
+    if (cap) (void)hipStreamDestroy(cap);
+}
+
+ddmgnn_problem::~ddmgnn_problem() {
+    solo.reset();
+    if (ctx && ctx->last_batch) {
+        const auto& B = *ctx->last_batch;
+        if (std::find(B.ids.begin(), B.ids.end(), id) != B.ids.end()) ctx->last_batch.reset();
+    }
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* ddmgnn_last_error(void) { return g_err.c_str(); }
+const char* ddmgnn_version(void) { return "ddmgnn 0.2 gfx950"; }
+int32_t ddmgnn_max_subdomain_nodes(void) { return kMaxSubNodes; }
+
+void ddmgnn_default_opts(ddmgnn_solve_opts* o) {
+    o->krylov = DDMGNN_FCG;
+    o->m_max = 1;
+    o->rtol = 1e-6;
+    o->max_it = 10000;
+    o->precision = DDMGNN_FP32;
+    o->prolong = DDMGNN_PROLONG_POU;
+    o->coarse = 1;
+    o->check_every = 16;
+    o->profile = 0;
+    o->graph = 1;
+}
+
+int ddmgnn_ctx_create(void* hip_stream, ddmgnn_ctx** out) {
+    if (!out) return fail(DDMGNN_E_INVALID, "null output pointer");
+    auto c = std::make_unique<ddmgnn_ctx>();
+    c->stream = (hipStream_t)hip_stream;
+    c->launch = c->stream;
+    HIP_TRY(hipGetDevice(&c->device));
+    HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    HIP_TRY(c->partials.alloc(VEC_GRID));
+    HIP_TRY(c->counters.alloc(4));
+    HIP_TRY(hipMemset(c->counters.p, 0, 4 * sizeof(unsigned)));
+    HIP_TRY(c->scalar.alloc(1));
+    HIP_TRY(hipHostMalloc((void**)&c->host_pinned, 256, hipHostMallocDefault));
+    *out = c.release();
+    return DDMGNN_OK;
+}
+
+int ddmgnn_ctx_destroy(ddmgnn_ctx* ctx) {
+    delete ctx;
+    return DDMGNN_OK;
+}
+
+int ddmgnn_model_create(ddmgnn_ctx* ctx, const ddmgnn_model_desc* desc, const float* theta, int64_t n_theta,
+                        ddmgnn_model** out) {
+    if (!ctx || !desc || !theta || !out) return fail(DDMGNN_E_INVALID, "null argument");
+    if (desc->d != D) return fail(DDMGNN_E_INVALID, "only latent width d = 10 is compiled");
+    if (desc->kbar < 1) return fail(DDMGNN_E_INVALID, "kbar must be >= 1");
+    const int64_t expect = (int64_t)desc->kbar * (11 * D * D + 15 * D + 1);
+    if (n_theta != expect) return fail(DDMGNN_E_INVALID, "n_theta must equal kbar*(11d^2+15d+1)");
+    for (int64_t i = 0; i < n_theta; ++i)
+        if (!std::isfinite(theta[i])) return fail(DDMGNN_E_INVALID, "non-finite weight");
+    auto m = std::make_unique<ddmgnn_model>();
+    m->kbar = desc->kbar;
+    m->d = desc->d;
+    m->alpha = desc->alpha;
+    m->theta.assign(theta, theta + n_theta);
+    std::vector<MfmaStep> steps;
+    std::vector<MfmaDec> dec;
+    build_mfma_blobs(m->theta.data(), m->kbar, steps, dec);
+    auto dev = std::make_shared<ModelDev>();
+    dev->id = g_next_id.fetch_add(1);
+    dev->kbar = m->kbar;
+    dev->alpha = m->alpha;
+    hipStream_t s = ctx->stream;
+    std::vector<double> th64(m->theta.begin(), m->theta.end());
+    HIP_TRY(dev->theta32.upload(m->theta.data(), m->theta.size(), s));
+    HIP_TRY(dev->theta64.upload(th64.data(), th64.size(), s));
+    HIP_TRY(dev->steps.upload(steps.data(), steps.size(), s));
+    HIP_TRY(dev->dec.upload(dec.data(), dec.size(), s));
+    m->dev = std::move(dev);
+    *out = m.release();
+    return DDMGNN_OK;
+}
+
+int ddmgnn_model_destroy(ddmgnn_model* m) {
+    delete m;
+    return DDMGNN_OK;
+}
+
+int ddmgnn_validate_problem(const ddmgnn_problem_desc* desc) {
+    if (!desc) return fail(DDMGNN_E_INVALID, "null descriptor");
+    std::string e = validate(*desc);
+    if (!e.empty()) return fail(DDMGNN_E_INVALID, e);
+    return DDMGNN_OK;
+}
+
+int ddmgnn_problem_create(ddmgnn_ctx* ctx, const ddmgnn_problem_desc* desc, const ddmgnn_model* model,
+                          ddmgnn_problem** out) {
+    if (!ctx || !desc || !model || !out) return fail(DDMGNN_E_INVALID, "null argument");
+    int rc = ddmgnn_validate_problem(desc);
+    if (rc) return rc;
+    HostSetup hs;
+    std::string e = build_setup(*desc, hs);
+    if (e == "NOT_SPD") return fail(DDMGNN_E_NOT_SPD, "coarse matrix R_0 A R_0^T is not positive definite");
+    if (!e.empty()) return fail(DDMGNN_E_INVALID, e);
+    return create_problem(ctx, *desc, model->dev, std::move(hs), out);
+}
+
+int ddmgnn_problem_destroy(ddmgnn_problem* P) {
+    delete P;
+    return DDMGNN_OK;
+}
+
+int ddmgnn_problem_sizes(const ddmgnn_problem* P, int64_t* n, int64_t* nnz, int32_t* k, int64_t* sum_k,
+                         int64_t* n_edges) {
+    if (!P) return fail(DDMGNN_E_INVALID, "null problem");
+    if (n) *n = P->hs.n;
+    if (nnz) *nnz = P->hs.nnz;
+    if (k) *k = P->hs.K;
+    if (sum_k) *sum_k = P->hs.sk;
+    if (n_edges) *n_edges = P->hs.n_edges;
+    return DDMGNN_OK;
+}
+
+int ddmgnn_problem_device_bytes(const ddmgnn_problem* P, int64_t* bytes) {
+    if (!P || !bytes) return fail(DDMGNN_E_INVALID, "null argument");
+    *bytes = (int64_t)P->device_bytes;
+    return DDMGNN_OK;
+}
+
+int ddmgnn_setup_local_graph(const ddmgnn_problem_desc* desc, int32_t sub, int32_t* rowptr, int32_t* col,
+                             int64_t* n_edges_sub) {
+    int rc = ddmgnn_validate_problem(desc);
+    if (rc) return rc;
+    if (sub < 0 || sub >= desc->n_sub) return fail(DDMGNN_E_INVALID, "sub-mesh index out of range");
+    HostSetup hs;
+    build_local_graphs(*desc, hs);
+    const int64_t b = desc->sub_ptr[sub], e = desc->sub_ptr[sub + 1];
+    const int64_t e0 = hs.edge_ptr[b], e1 = hs.edge_ptr[e];
+    if (n_edges_sub) *n_edges_sub = e1 - e0;
+    if (rowptr)
+        for (int64_t k = b; k <= e; ++k) rowptr[k - b] = (int32_t)(hs.edge_ptr[k] - e0);
+    if (col)
+        for (int64_t q = e0; q < e1; ++q) col[q - e0] = hs.edge_src[q];
+    return DDMGNN_OK;
+}
+
+int ddmgnn_setup_coarse(const ddmgnn_problem_desc* desc, double* a0, double* a0inv) {
+    int rc = ddmgnn_validate_problem(desc);
+    if (rc) return rc;
+    HostSetup hs;
+    std::string e = build_setup(*desc, hs);
+    if (!hs.a0.empty() && a0) std::memcpy(a0, hs.a0.data(), hs.a0.size() * sizeof(double));
+    if (e == "NOT_SPD") return fail(DDMGNN_E_NOT_SPD, "coarse matrix R_0 A R_0^T is not positive definite");
+    if (!e.empty()) return fail(DDMGNN_E_INVALID, e);
+    if (a0inv) std::memcpy(a0inv, hs.a0inv.data(), hs.a0inv.size() * sizeof(double));
+    return DDMGNN_OK;
+}
+
+int ddmgnn_spmv(ddmgnn_ctx* ctx, ddmgnn_problem* P, const double* x, double* y) {
+    if (!ctx || !P || !x || !y) return fail(DDMGNN_E_INVALID, "null argument");
+    HIP_TRY(launch_spmv(P->rowptr.p, P->col.p, P->val.p, x, y, (int)P->hs.n, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DDMGNN_OK;
+}
+
+int ddmgnn_dot(ddmgnn_ctx* ctx, int64_t n, const double* x, const double* y, double* out) {
+    if (!ctx || !out || n < 0 || (n > 0 && (!x || !y))) return fail(DDMGNN_E_INVALID, "invalid argument");
+    if (n == 0) {
+        *out = 0.0;
+        return DDMGNN_OK;
+    }
+    HIP_TRY(launch_dot(x, y, n, ctx->partials.p, ctx->counters.p, ctx->scalar.p, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->host_pinned, ctx->scalar.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    *out = ctx->host_pinned[0];
+    return DDMGNN_OK;
+}
+
+int ddmgnn_dss_forward(ddmgnn_ctx* ctx, ddmgnn_problem* P, int32_t precision, const double* c, double* out) {
+    if (!ctx || !P || !c || !out) return fail(DDMGNN_E_INVALID, "null argument");
+    if (precision < 0 || precision > 2) return fail(DDMGNN_E_INVALID, "bad precision");
+    if (int rc = solo_batch(P)) return rc;
+    Batch& B = *P->solo;
+    bool changed = false;
+    if (int rc = prepare_dss(B, precision, changed)) return rc;
+    DevProb v = make_view(P);
+    v.c_in = c;
+    v.local = out;
+    v.st = nullptr;
+    HIP_TRY(upload_async(B.hook.p, &v, sizeof(v), ctx->stream));
+    if (int rc = enqueue_dss(B, B.hook.p, precision, 0, false)) return rc;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DDMGNN_OK;
+}
+
+int ddmgnn_precond_apply(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* opts, const double* r,
+                         double* z) {
+    if (!ctx || !P || !opts || !r || !z) return fail(DDMGNN_E_INVALID, "null argument");
+    if (r == z) return fail(DDMGNN_E_INVALID, "r and z must not alias");
+    if (int rc = check_opts(*opts)) return rc;
+    if (int rc = solo_batch(P)) return rc;
+    Batch& B = *P->solo;
+    bool changed = false;
+    if (int rc = prepare_dss(B, opts->precision, changed)) return rc;
+    DevProb v = make_view(P);
+    v.r = const_cast<double*>(r);  // read only: the apply never writes its input
+    v.z = z;
+    v.st = nullptr;
+    HIP_TRY(upload_async(B.hook.p, &v, sizeof(v), ctx->stream));
+    if (int rc = enqueue_apply(B, B.hook.p, *opts, -1, nullptr, false)) return rc;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DDMGNN_OK;
+}
+
+int ddmgnn_apply_intermediates(ddmgnn_ctx* ctx, ddmgnn_problem* P, double* s, double* y0, double* y,
+                               double* local) {
+    if (!ctx || !P) return fail(DDMGNN_E_INVALID, "null argument");
+    hipStream_t st = ctx->stream;
+    const int K = P->hs.K;
+    if (s) HIP_TRY(hipMemcpyAsync(s, P->s.p, K * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (y0) HIP_TRY(hipMemcpyAsync(y0, P->y0.p, K * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (y) HIP_TRY(hipMemcpyAsync(y, P->y.p, K * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (local) HIP_TRY(hipMemcpyAsync(local, P->local.p, P->hs.sk * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return DDMGNN_OK;
+}
+
+int ddmgnn_solve(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* opts, double* u_out,
+                 ddmgnn_stats* stats) {
+    if (!ctx || !P || !opts || !u_out) return fail(DDMGNN_E_INVALID, "null argument");
+    if (int rc = check_opts(*opts)) return rc;
+    if (int rc = solo_batch(P)) return rc;
+    double* outs[1] = {u_out};
+    return solve_batch(ctx, *P->solo, *opts, outs, stats);
+}
+
+int ddmgnn_solve_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int32_t n, const ddmgnn_solve_opts* opts,
+                       double* const* u_out, ddmgnn_stats* stats) {
+    if (!ctx || !probs || n < 1 || !opts || !u_out) return fail(DDMGNN_E_INVALID, "null argument or n < 1");
+    if (int rc = check_opts(*opts)) return rc;
+    for (int i = 0; i < n; ++i) {
+        if (!probs[i] || !u_out[i]) return fail(DDMGNN_E_INVALID, "null problem or output");
+        if (probs[i]->ctx != ctx) return fail(DDMGNN_E_INVALID, "problem belongs to another context");
+        if (probs[i]->model->id != probs[0]->model->id)
+            return fail(DDMGNN_E_INVALID, "all problems of a batch must share the model");
+        for (int j = 0; j < i; ++j)
+            if (probs[j] == probs[i]) return fail(DDMGNN_E_INVALID, "a problem appears twice in the batch");
+    }
+    if (n == 1) return ddmgnn_solve(ctx, probs[0], opts, u_out[0], stats);
+    bool hit = ctx->last_batch && (int)ctx->last_batch->ids.size() == n;
+    for (int i = 0; hit && i < n; ++i) hit = ctx->last_batch->ids[i] == probs[i]->id;
+    if (!hit) {
+        ctx->last_batch.reset();
+        if (int rc = build_batch(ctx, probs, n, ctx->last_batch)) return rc;
+    }
+    return solve_batch(ctx, *ctx->last_batch, *opts, u_out, stats);
+}
+
+int ddmgnn_expand_overlap(int64_t n_nodes, int64_t n_tri, const int32_t* tri, const int32_t* part, int32_t n_part,
+                          int32_t delta, int64_t** sub_ptr_out, int32_t** sub_nodes_out) {
+    if (n_nodes <= 0 || n_tri <= 0 || !tri || !part || n_part <= 0 || delta < 0 || !sub_ptr_out || !sub_nodes_out)
+        return fail(DDMGNN_E_INVALID, "invalid argument");
+    for (int64_t t = 0; t < 3 * n_tri; ++t)
+        if (tri[t] < 0 || tri[t] >= n_nodes) return fail(DDMGNN_E_INVALID, "triangle node id out of range");
+    for (int64_t i = 0; i < n_nodes; ++i)
+        if (part[i] < 0 || part[i] >= n_part) return fail(DDMGNN_E_INVALID, "part id out of range");
+    std::vector<int64_t> sp;
+    std::vector<int32_t> sn;
+    expand_overlap(n_nodes, n_tri, tri, part, n_part, delta, sp, sn);
+    auto* a = (int64_t*)std::malloc(sp.size() * sizeof(int64_t));
+    auto* b = (int32_t*)std::malloc(std::max<size_t>(1, sn.size()) * sizeof(int32_t));
+    if (!a || !b) {
+        std::free(a);
+        std::free(b);
+        return fail(DDMGNN_E_NOMEM, "host allocation failed");
+    }
+    std::memcpy(a, sp.data(), sp.size() * sizeof(int64_t));
+    std::memcpy(b, sn.data(), sn.size() * sizeof(int32_t));
+    *sub_ptr_out = a;
+    *sub_nodes_out = b;
+    return DDMGNN_OK;
+}
+
+int ddmgnn_pou_weights(int64_t n_nodes, const uint8_t* dirichlet, int32_t n_sub, const int64_t* sub_ptr,
+                       const int32_t* sub_nodes, double* weights_out) {
+    if (n_nodes <= 0 || !dirichlet || n_sub <= 0 || !sub_ptr || !sub_nodes || !weights_out)
+        return fail(DDMGNN_E_INVALID, "invalid argument");
+    std::vector<int32_t> mult(n_nodes, 0);
+    for (int64_t k = 0; k < sub_ptr[n_sub]; ++k) {
+        if (sub_nodes[k] < 0 || sub_nodes[k] >= n_nodes) return fail(DDMGNN_E_INVALID, "node id out of range");
+        mult[sub_nodes[k]]++;
+    }
+    for (int64_t k = 0; k < sub_ptr[n_sub]; ++k) {
+        const int32_t v = sub_nodes[k];
+        weights_out[k] = dirichlet[v] ? 0.0 : 1.0 / (double)mult[v];
+    }
+    return DDMGNN_OK;
+}
+
+void ddmgnn_free(void* p) { std::free(p); }
+
+}  // extern "C"

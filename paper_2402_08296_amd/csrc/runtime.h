@@ -1,0 +1,161 @@
+// Host runtime shared by the C ABI (runtime.cpp) and the serving loop
+// (server.cpp): handle layouts, device buffers, batches of problems and the
+// solve driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "ddmgnn.h"
+#include "device.h"
+#include "dss_mfma.h"
+#include "setup.h"
+
+namespace ddmgnn {
+
+// Records the error text of the calling thread and returns code.
+int fail(int code, const std::string& msg);
+
+#define HIP_TRY(expr)                                                                                  \
+    do {                                                                                               \
+        hipError_t e_ = (expr);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return ::ddmgnn::fail(DDMGNN_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t alloc(size_t count) {
+        reset();
+        n = count;
+        if (count == 0) return hipSuccess;
+        return hipMalloc(&p, count * sizeof(T));
+    }
+    // Synchronous upload on stream s (the source may be pageable).
+    hipError_t upload(const T* src, size_t count, hipStream_t s) {
+        hipError_t e = alloc(count);
+        if (e != hipSuccess || count == 0) return e;
+        e = hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    }
+};
+
+// Device copy of a model's weights, shared by the model handle and every
+// problem created with it (freed with the last of them).
+struct ModelDev {
+    uint64_t id = 0;
+    int kbar = 0;
+    double alpha = 0;
+    DevBuf<float> theta32;
+    DevBuf<double> theta64;
+    DevBuf<MfmaStep> steps;
+    DevBuf<MfmaDec> dec;
+};
+
+struct Batch;
+struct BatchDeleter {
+    void operator()(Batch* b) const;
+};
+using BatchPtr = std::unique_ptr<Batch, BatchDeleter>;
+
+// Bytes of device memory a problem of these sizes holds (all buffers of a
+// solve, excluding the DSS fallback storage of sub-meshes too large for LDS).
+size_t problem_device_bytes(int64_t n, int64_t nnz, int32_t K, int64_t sk, int64_t n_edges);
+
+// Creates a problem from a validated descriptor and its host setup (moved in).
+int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared_ptr<ModelDev> model,
+                   HostSetup&& hs, ddmgnn_problem** out);
+
+// Batch of problems solved in lockstep (one launch per kernel and iteration).
+// All must share the model. Built once per membership; cheap to rebuild.
+int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& out);
+
+// Prepares the DSS launches for o, uploads the table (with each problem's
+// rtol and max_it) and initialises the problems flagged in `init` (none when null).
+int batch_begin(Batch& B, const ddmgnn_solve_opts& o, const std::vector<uint8_t>* init);
+// Enqueues `count` iterations eagerly (or replays the captured chunk when use_graph).
+int batch_iterate(Batch& B, const ddmgnn_solve_opts& o, int count, bool use_graph);
+// Copies the states of all problems to the host (synchronises the stream).
+int batch_poll(Batch& B);
+const KState& batch_state(const Batch& B, int i);
+int batch_size(const Batch& B);
+ddmgnn_problem* batch_problem(const Batch& B, int i);
+// True residuals of the problems flagged in `which` (all when null) into their states, synchronised.
+int batch_true_residual(Batch& B, const std::vector<uint8_t>* which);
+// DSS kernel that runs problem i at precision p: 0 FP64 VALU, 1 FP32 VALU, 2 BF16 MFMA.
+int dss_kernel_of(const ddmgnn_problem* P, int precision);
+
+int check_opts(const ddmgnn_solve_opts& o);
+
+}  // namespace ddmgnn
+
+struct ddmgnn_ctx {
+    hipStream_t stream = nullptr;   // the caller's stream: all work runs here
+    hipStream_t launch = nullptr;   // where kernels are enqueued (= stream, or cap while capturing)
+    hipStream_t cap = nullptr;      // own non-blocking stream for graph capture (the null stream cannot be captured)
+    int device = 0;
+    ddmgnn::DevBuf<double> partials;
+    ddmgnn::DevBuf<unsigned> counters;
+    ddmgnn::DevBuf<double> scalar;
+    double* host_pinned = nullptr;
+    ddmgnn::BatchPtr last_batch;  // batch of the last multi-problem solve
+    ~ddmgnn_ctx();
+};
+
+struct ddmgnn_model {
+    int kbar = 0, d = 0;
+    double alpha = 0;
+    std::vector<float> theta;
+    std::shared_ptr<ddmgnn::ModelDev> dev;
+};
+
+struct ddmgnn_problem {
+    ddmgnn_ctx* ctx = nullptr;
+    uint64_t id = 0;                 // unique per process (batch cache key)
+    ddmgnn::HostSetup hs;
+    std::shared_ptr<ddmgnn::ModelDev> model;
+    size_t device_bytes = 0;
+    // matrix and vectors
+    ddmgnn::DevBuf<int32_t> rowptr, col;
+    ddmgnn::DevBuf<double> val, b, u0;
+    ddmgnn::DevBuf<uint8_t> dirichlet;
+    // decomposition
+    ddmgnn::DevBuf<int32_t> sub_ptr, sub_nodes, edge_ptr, node_ptr, node_slots, slot_sub;
+    ddmgnn::DevBuf<uint16_t> edge_src;
+    ddmgnn::DevBuf<double> weights, xy64, a0inv;
+    ddmgnn::DevBuf<float> xyc32;     // per slot, centred on the sub-mesh
+    ddmgnn::DevBuf<ddmgnn::TileNode> tiles;
+    ddmgnn::DevBuf<uint32_t> erec;   // padded by 8 entries
+    ddmgnn::DevBuf<float> edge_nd;   // padded by 8 entries
+    bool mfma_fits = false;          // every sub-mesh fits the MFMA kernel's LDS
+    // apply buffers
+    ddmgnn::DevBuf<double> s, y0, y, local;
+    ddmgnn::DevBuf<double> qglobal64, hglobal64;
+    ddmgnn::DevBuf<float> qglobal32;
+    // Krylov vectors
+    ddmgnn::DevBuf<double> u, r, z;
+    ddmgnn::DevBuf<double> ring;     // (MAX_M + 1) p vectors then (MAX_M + 1) q vectors
+    ddmgnn::DevBuf<ddmgnn::KState> st;
+    ddmgnn::DevBuf<double> partials;
+    ddmgnn::DevBuf<unsigned> counters;
+    double rtol = 1e-6;              // of the current solve (read by the init kernel)
+    int max_it = 0;
+    ddmgnn::BatchPtr solo;  // batch of this problem alone
+    ~ddmgnn_problem();
+};

@@ -1,0 +1,397 @@
+// Serving loop: a stream of independent solve requests with continuous
+// batching. Requests are copied at submission; a pool of host threads runs
+// their setup (validation, local graphs, coarse operator and its inverse);
+// one GPU thread admits set-up requests while their device memory fits the
+// budget, advances every active problem by a chunk of iterations with one
+// launch per kernel (a batch whose per-problem done flags mask finished
+// problems), and retires the problems that converged, freeing their memory
+// for the next admissions. A problem's arithmetic does not depend on the
+// other members of its batch (per-problem reductions in a fixed order), so a
+// served result equals the result of solving it alone.
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <set>
+#include <thread>
+
+#include "runtime.h"
+
+namespace ddmgnn {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+struct Request {
+    uint64_t ticket = 0;
+    // owned copy of the descriptor
+    std::vector<double> xy, a_val, b, u0, weights;
+    std::vector<int32_t> tri, a_rowptr, a_col, sub_nodes;
+    std::vector<uint8_t> dirichlet;
+    std::vector<int64_t> sub_ptr;
+    ddmgnn_problem_desc desc{};
+    ddmgnn_solve_opts opts{};
+    HostSetup hs;
+    int setup_rc = DDMGNN_OK;
+    std::string err;
+    size_t bytes = 0;
+    Clock::time_point t_submit, t_admit, t_done;
+    ddmgnn_problem* prob = nullptr;
+    bool fresh = false;  // admitted, not initialised yet
+    // result
+    std::vector<double> u;
+    ddmgnn_stats stats{};
+    int status = DDMGNN_E_PENDING;
+};
+
+template <typename T>
+void copy_in(std::vector<T>& dst, const T* src, int64_t n) {
+    if (src && n > 0) dst.assign(src, src + n);
+}
+
+// Options that must agree among the problems of one batch.
+uint64_t structure_key(const ddmgnn_solve_opts& o) {
+    const int m = o.krylov == DDMGNN_FCG ? o.m_max : 1;
+    return ((uint64_t)o.krylov << 24) | ((uint64_t)m << 16) | ((uint64_t)o.precision << 8) |
+           ((uint64_t)o.prolong << 4) | (uint64_t)(o.coarse != 0);
+}
+
+}  // namespace
+}  // namespace ddmgnn
+
+using namespace ddmgnn;
+
+struct ddmgnn_server {
+    ddmgnn_ctx* ctx = nullptr;
+    std::shared_ptr<ModelDev> model;
+    size_t budget = 0;
+    int max_active = 0;
+    std::mutex mu;
+    std::condition_variable cv;        // work for the GPU thread or setup workers
+    std::condition_variable cv_done;   // a request finished
+    std::deque<Request*> pending;      // submitted, waiting for host setup
+    std::map<uint64_t, Request*> ready;  // set up, waiting for admission (ticket order)
+    std::map<uint64_t, Request*> finished;
+    std::set<uint64_t> live;           // submitted and not collected
+    size_t in_flight = 0;              // submitted and not finished
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread gpu;
+    std::vector<std::thread> workers;
+    std::string loop_error;
+
+    void setup_worker();
+    void gpu_loop();
+    void finish(Request* r);
+};
+
+void ddmgnn_server::finish(Request* r) {
+    r->t_done = Clock::now();
+    r->stats.latency_ms = ms_between(r->t_submit, r->t_done);
+    r->stats.status = r->status;
+    std::lock_guard<std::mutex> lk(mu);
+    finished[r->ticket] = r;
+    --in_flight;
+    cv_done.notify_all();
+}
+
+void ddmgnn_server::setup_worker() {
+    for (;;) {
+        Request* r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return stop || !pending.empty(); });
+            if (pending.empty()) return;
+            r = pending.front();
+            pending.pop_front();
+        }
+        std::string e = validate(r->desc);
+        if (e.empty()) e = build_setup(r->desc, r->hs);
+        if (e == "NOT_SPD") {
+            r->setup_rc = DDMGNN_E_NOT_SPD;
+            r->err = "coarse matrix R_0 A R_0^T is not positive definite";
+        } else if (!e.empty()) {
+            r->setup_rc = DDMGNN_E_INVALID;
+            r->err = e;
+        } else {
+            r->bytes = problem_device_bytes(r->hs.n, r->hs.nnz, r->hs.K, r->hs.sk, r->hs.n_edges);
+        }
+        std::lock_guard<std::mutex> lk(mu);
+        ready[r->ticket] = r;
+        cv.notify_all();
+    }
+}
+
+void ddmgnn_server::gpu_loop() {
+    (void)hipSetDevice(ctx->device);
+    std::vector<Request*> active;
+    BatchPtr B;
+    bool changed = false;
+    size_t bytes_active = 0;
+    uint64_t group = 0;
+    ddmgnn_solve_opts gopts{};
+    auto fail_all = [&](int rc) {
+        const std::string msg = "serving loop: " + std::string(ddmgnn_last_error());
+        B.reset();
+        for (Request* r : active) {
+            delete r->prob;
+            r->prob = nullptr;
+            r->status = rc;
+            r->err = msg;
+            finish(r);
+        }
+        active.clear();
+        bytes_active = 0;
+    };
+    for (;;) {
+        std::vector<Request*> admit, reject;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv.wait(lk, [&] { return !active.empty() || !ready.empty() || (stop && in_flight == 0); });
+            if (active.empty() && ready.empty() && stop && in_flight == 0) return;
+            // Admission in ticket order; the first request that does not fit waits (no overtaking).
+            size_t bytes = bytes_active;
+            uint64_t g = active.empty() ? 0 : group;
+            int n_active = (int)active.size();
+            for (auto it = ready.begin(); it != ready.end();) {
+                Request* r = it->second;
+                if (r->setup_rc != DDMGNN_OK || r->bytes > budget) {
+                    reject.push_back(r);
+                    it = ready.erase(it);
+                    continue;
+                }
+                const uint64_t key = structure_key(r->opts);
+                if (n_active > 0 && key != g) break;
+                if (n_active >= max_active || bytes + r->bytes > budget) break;
+                g = key;
+                bytes += r->bytes;
+                ++n_active;
+                admit.push_back(r);
+                it = ready.erase(it);
+            }
+        }
+        for (Request* r : reject) {
+            if (r->setup_rc == DDMGNN_OK) {
+                r->setup_rc = DDMGNN_E_BUDGET;
+                r->err = "request needs more device memory than the server budget";
+            }
+            r->status = r->setup_rc;
+            finish(r);
+        }
+        for (Request* r : admit) {
+            r->t_admit = Clock::now();
+            ddmgnn_problem* P = nullptr;
+            const int rc = create_problem(ctx, r->desc, model, std::move(r->hs), &P);
+            r->hs = HostSetup();
+            if (rc) {
+                r->status = rc;
+                r->err = ddmgnn_last_error();
+                finish(r);
+                continue;
+            }
+            P->rtol = r->opts.rtol;
+            P->max_it = r->opts.max_it;
+            r->prob = P;
+            r->fresh = true;
+            if (active.empty()) {
+                group = structure_key(r->opts);
+                gopts = r->opts;
+            }
+            bytes_active += r->bytes;
+            active.push_back(r);
+            changed = true;
+        }
+        if (active.empty()) continue;
+        if (changed) {
+            std::vector<ddmgnn_problem*> probs;
+            std::vector<uint8_t> init;
+            for (Request* r : active) {
+                probs.push_back(r->prob);
+                init.push_back(r->fresh ? 1 : 0);
+                r->fresh = false;
+            }
+            B.reset();
+            int rc = build_batch(ctx, probs.data(), (int)probs.size(), B);
+            if (!rc) rc = batch_begin(*B, gopts, &init);
+            if (rc) {
+                fail_all(rc);
+                continue;
+            }
+            changed = false;
+        }
+        int rc = batch_iterate(*B, gopts, std::max(1, gopts.check_every), false);
+        if (!rc) rc = batch_poll(*B);
+        if (rc) {
+            fail_all(rc);
+            continue;
+        }
+        std::vector<uint8_t> done(active.size(), 0);
+        bool any = false;
+        for (size_t i = 0; i < active.size(); ++i) {
+            done[i] = batch_state(*B, (int)i).done ? 1 : 0;
+            any = any || done[i];
+        }
+        if (!any) continue;
+        rc = batch_true_residual(*B, &done);
+        if (rc) {
+            fail_all(rc);
+            continue;
+        }
+        std::vector<Request*> keep;
+        for (size_t i = 0; i < active.size(); ++i) {
+            Request* r = active[i];
+            if (!done[i]) {
+                keep.push_back(r);
+                continue;
+            }
+            const KState& k = batch_state(*B, (int)i);
+            ddmgnn_problem* P = r->prob;
+            r->u.resize(P->hs.n);
+            hipError_t e = hipMemcpyAsync(r->u.data(), P->u.p, P->hs.n * sizeof(double), hipMemcpyDeviceToHost,
+                                          ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+            const bool converged = k.status == 0 && k.rel <= r->opts.rtol;
+            ddmgnn_stats& S = r->stats;
+            std::memset(&S, 0, sizeof(S));
+            S.iterations = k.it;
+            S.converged = converged;
+            S.rel_residual = k.rel;
+            S.true_rel_residual = k.r0n > 0 ? std::sqrt(k.rr_true) / k.r0n : 0.0;
+            S.solve_ms = ms_between(r->t_admit, Clock::now());
+            S.dss_kernel = dss_kernel_of(P, gopts.precision);
+            if (e != hipSuccess) {
+                r->status = DDMGNN_E_HIP;
+                r->err = std::string("result copy: ") + hipGetErrorString(e);
+            } else {
+                r->status = k.status ? k.status : (converged ? DDMGNN_OK : DDMGNN_E_MAXIT);
+                if (r->status) r->err = k.status ? "Krylov breakdown or non-finite residual" : "not converged within max_it";
+            }
+            bytes_active -= r->bytes;
+            delete P;
+            r->prob = nullptr;
+            finish(r);
+        }
+        active.swap(keep);
+        changed = true;
+        if (active.empty()) B.reset();
+    }
+}
+
+extern "C" {
+
+int ddmgnn_server_create(ddmgnn_ctx* ctx, const ddmgnn_model* model, int64_t hbm_budget, int32_t max_active,
+                         int32_t setup_threads, ddmgnn_server** out) {
+    if (!ctx || !model || !out) return fail(DDMGNN_E_INVALID, "null argument");
+    if (hbm_budget <= 0 || max_active < 1) return fail(DDMGNN_E_INVALID, "budget and max_active must be positive");
+    if (setup_threads < 0 || setup_threads > 64) return fail(DDMGNN_E_INVALID, "setup_threads must be in [0, 64]");
+    auto s = std::make_unique<ddmgnn_server>();
+    s->ctx = ctx;
+    s->model = model->dev;
+    s->budget = (size_t)hbm_budget;
+    s->max_active = max_active;
+    const int nw = setup_threads ? setup_threads : 4;
+    for (int i = 0; i < nw; ++i) s->workers.emplace_back(&ddmgnn_server::setup_worker, s.get());
+    s->gpu = std::thread(&ddmgnn_server::gpu_loop, s.get());
+    *out = s.release();
+    return DDMGNN_OK;
+}
+
+int ddmgnn_server_submit(ddmgnn_server* srv, const ddmgnn_problem_desc* desc, const ddmgnn_solve_opts* opts,
+                         uint64_t* ticket) {
+    if (!srv || !desc || !opts || !ticket) return fail(DDMGNN_E_INVALID, "null argument");
+    if (int rc = check_opts(*opts)) return rc;
+    if (desc->n_nodes <= 0 || desc->n_tri <= 0 || desc->n_sub <= 0 || !desc->sub_ptr)
+        return fail(DDMGNN_E_INVALID, "empty problem");
+    auto r = std::make_unique<Request>();
+    const int64_t n = desc->n_nodes, nt = desc->n_tri, K = desc->n_sub;
+    const int64_t nnz = desc->a_rowptr ? desc->a_rowptr[n] : 0;
+    const int64_t sk = desc->sub_ptr[K];
+    if (nnz < 0 || sk < 0) return fail(DDMGNN_E_INVALID, "negative sizes");
+    copy_in(r->xy, desc->xy, 2 * n);
+    copy_in(r->tri, desc->tri, 3 * nt);
+    copy_in(r->dirichlet, desc->dirichlet, n);
+    copy_in(r->a_rowptr, desc->a_rowptr, n + 1);
+    copy_in(r->a_col, desc->a_col, nnz);
+    copy_in(r->a_val, desc->a_val, nnz);
+    copy_in(r->b, desc->b, n);
+    copy_in(r->u0, desc->u0, n);
+    copy_in(r->sub_ptr, desc->sub_ptr, K + 1);
+    copy_in(r->sub_nodes, desc->sub_nodes, sk);
+    copy_in(r->weights, desc->weights, sk);
+    ddmgnn_problem_desc& d = r->desc;
+    d.n_nodes = n;
+    d.xy = r->xy.empty() ? nullptr : r->xy.data();
+    d.n_tri = nt;
+    d.tri = r->tri.empty() ? nullptr : r->tri.data();
+    d.dirichlet = r->dirichlet.empty() ? nullptr : r->dirichlet.data();
+    d.a_rowptr = r->a_rowptr.empty() ? nullptr : r->a_rowptr.data();
+    d.a_col = r->a_col.empty() ? nullptr : r->a_col.data();
+    d.a_val = r->a_val.empty() ? nullptr : r->a_val.data();
+    d.b = r->b.empty() ? nullptr : r->b.data();
+    d.u0 = r->u0.empty() ? nullptr : r->u0.data();
+    d.n_sub = (int32_t)K;
+    d.sub_ptr = r->sub_ptr.data();
+    d.sub_nodes = r->sub_nodes.empty() ? nullptr : r->sub_nodes.data();
+    d.weights = r->weights.empty() ? nullptr : r->weights.data();
+    r->opts = *opts;
+    r->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop) return fail(DDMGNN_E_INVALID, "server is shutting down");
+    r->ticket = srv->next_ticket++;
+    *ticket = r->ticket;
+    ++srv->in_flight;
+    srv->live.insert(r->ticket);
+    srv->pending.push_back(r.release());
+    srv->cv.notify_all();
+    return DDMGNN_OK;
+}
+
+int ddmgnn_server_poll(ddmgnn_server* srv, uint64_t ticket, double* u_out, ddmgnn_stats* stats) {
+    if (!srv) return fail(DDMGNN_E_INVALID, "null server");
+    Request* r = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (!srv->live.count(ticket)) return fail(DDMGNN_E_INVALID, "unknown or already collected ticket");
+        auto it = srv->finished.find(ticket);
+        if (it == srv->finished.end()) return DDMGNN_E_PENDING;
+        r = it->second;
+        srv->finished.erase(it);
+        srv->live.erase(ticket);
+    }
+    std::unique_ptr<Request> hold(r);
+    if (stats) *stats = r->stats;
+    if (u_out && !r->u.empty()) std::memcpy(u_out, r->u.data(), r->u.size() * sizeof(double));
+    if (r->status) return fail(r->status, r->err);
+    return DDMGNN_OK;
+}
+
+int ddmgnn_server_drain(ddmgnn_server* srv) {
+    if (!srv) return fail(DDMGNN_E_INVALID, "null server");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv_done.wait(lk, [&] { return srv->in_flight == 0; });
+    return DDMGNN_OK;
+}
+
+int ddmgnn_server_destroy(ddmgnn_server* srv) {
+    if (!srv) return DDMGNN_OK;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        srv->cv.notify_all();
+    }
+    if (srv->gpu.joinable()) srv->gpu.join();
+    for (auto& t : srv->workers)
+        if (t.joinable()) t.join();
+    for (auto& kv : srv->finished) delete kv.second;
+    delete srv;
+    return DDMGNN_OK;
+}
+
+}  // extern "C"

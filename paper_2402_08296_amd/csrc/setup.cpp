@@ -146,6 +146,7 @@ void build_local_graphs(const ddmgnn_problem_desc& d, HostSetup& s) {
     s.nnz = d.a_rowptr[n];
     s.K = K;
     s.sk = d.sub_ptr[K];
+    s.sub_ptr.assign(d.sub_ptr, d.sub_ptr + K + 1);
     std::vector<int64_t> aptr;
     std::vector<int32_t> adj;
     mesh_adjacency(n, d.n_tri, d.tri, aptr, adj);

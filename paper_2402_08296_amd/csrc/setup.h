@@ -22,6 +22,7 @@ void expand_overlap(int64_t n, int64_t nt, const int32_t* tri, const int32_t* pa
 struct HostSetup {
     int64_t n = 0, nnz = 0, sk = 0, n_edges = 0;
     int32_t K = 0;
+    std::vector<int64_t> sub_ptr;    // [K + 1] slot ranges of the sub-meshes
     // Local DSS graphs, one receiver-major CSR per sub-mesh, concatenated:
     // rows of sub-mesh i are slots sub_ptr[i]..sub_ptr[i+1]; edge_ptr[slot]
     // indexes edge_src (sender slot, local id) for the in-edges of that slot.

@@ -267,6 +267,46 @@ CONFIGS = {
 }
 THETA_SEED = 42
 
+# Many independent problems solved together: 64 problems with N log-uniform
+# in [10k, 200k] and parts of about 700 nodes.
+BATCH_CONFIGS = {
+    "c4": dict(count=64, lo=10_000, hi=200_000, nodes_per_part=700, jitter=0.15, seed=2000),
+}
+# A stream of independent solve requests: Poisson arrivals at `rate` per
+# second, N log-uniform in [lo, hi], parts of about 700 nodes.
+STREAM_CONFIGS = {
+    "c5": dict(count=500, rate=20.0, lo=5_000, hi=2_000_000, nodes_per_part=700, jitter=0.15, seed=3000),
+}
+
+
+def log_uniform_sizes(seed: int, count: int, lo: int, hi: int) -> np.ndarray:
+    """count integers log-uniform in [lo, hi] from a seeded generator."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), count)).astype(np.int64)
+
+
+def batch_specs(name: str = "c4", count: int | None = None):
+    """(seed, target_nodes, n_parts, jitter) of each problem of a batch configuration."""
+    c = BATCH_CONFIGS[name]
+    cnt = c["count"] if count is None else count
+    sizes = log_uniform_sizes(c["seed"], c["count"], c["lo"], c["hi"])[:cnt]
+    return [(c["seed"] + 1 + i, int(nn), max(1, int(round(nn / c["nodes_per_part"]))), c["jitter"])
+            for i, nn in enumerate(sizes)]
+
+
+def stream_specs(name: str = "c5", count: int | None = None, rate: float | None = None,
+                 hi: int | None = None):
+    """(arrival time in s, seed, target_nodes, n_parts, jitter) of each request of a stream."""
+    c = STREAM_CONFIGS[name]
+    cnt = c["count"] if count is None else count
+    lam = c["rate"] if rate is None else rate
+    rng = np.random.default_rng(c["seed"])
+    gaps = rng.exponential(1.0 / lam, c["count"])[:cnt]
+    sizes = log_uniform_sizes(c["seed"] + 1, c["count"], c["lo"], c["hi"] if hi is None else hi)[:cnt]
+    t = np.cumsum(gaps) - gaps[0]
+    return [(float(t[i]), c["seed"] + 2 + i, int(nn), max(1, int(round(nn / c["nodes_per_part"]))), c["jitter"])
+            for i, nn in enumerate(sizes)]
+
 
 def config_problem(name: str, index: int = 0) -> Problem:
     c = CONFIGS[name]
