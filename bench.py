@@ -1,13 +1,24 @@
 #!/usr/bin/env python
-"""Benchmark of the DDM-GNN preconditioned flexible-CG solve on one MI355X.
+"""Benchmark of the DDM-GNN preconditioned flexible-CG solver on one MI355X.
 
 One step is one complete solve A u = b from u0 to relative residual 1e-6 of
 the ~1M-node, 1500-sub-mesh problem (every FCG iteration runs SpMV, dots,
 updates, convergence test, restriction, coarse solve, the 30-block DSS forward
 on every sub-mesh and the gluing). Inputs are resident in HBM before the timed
-region. `value` is solves per second. The JSON line also carries the roofline
-of the dominant kernel (the DSS forward, timed with HIP events on its stream)
-and the CPU oracle timed on a bounded sample of the same workload.
+region. `value` is solves per second, one solve after another.
+
+The same JSON line carries:
+  * roofline: the dominant kernel (the DSS forward), timed with HIP events on
+    its stream, against the composite peak of its flop mix, with the HBM
+    traffic of the committed counter summary while the kernel is unchanged;
+  * batched: the same problem 8 times in one batched solve, and the batch of
+    64 problems of 10k-200k nodes, batched and one after another;
+  * serve: a bounded prefix of the request stream (Poisson arrivals, 5k-2M
+    nodes) through the serving loop, with p50/p99 latency;
+  * cpu_baseline: the CPU oracle timed on a bounded sample of the main workload.
+
+  python bench.py --pmc-workload    copies of known size and a few applies of the
+                                    main workload, for rocprofv3 counter passes
 """
 from __future__ import annotations
 
@@ -23,25 +34,41 @@ if ROOT not in sys.path:
 
 import numpy as np  # noqa: E402
 
-PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6, "bf16": 157.3}   # MI355X FP32/FP64 vector peaks
+FP32_VALU_TF = 157.3    # MI355X FP32 vector peak
+FP64_VALU_TF = 78.6
+FP16_PACKED_TF = 2 * FP32_VALU_TF  # packed FP16 VALU: two lanes per FP32 lane
+BF16_MFMA_TF = 2500.0   # dense BF16 matrix-core peak
 HBM_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dss_mfma_kernel_c3_bf16_traffic.md")
+PMC_COPY_BYTES = 1 << 30
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def dss_flops(kbar: int, d: int, sum_k: int, n_edges: int) -> float:
+def dss_flops(kbar: int, d: int, sum_k: int, n_edges: int):
     """Algorithmic flops of one DSS forward launch (multiply-add = 2 flops).
 
-    Per node and block: neighbour projections 4d^2, receiver projections
-    4d^2+2d, message second layers 4d^2+2d, Psi 8d^2+7d (2110 at d = 10);
-    per directed edge and block: 2 (dx, dy) + 4 (|d|) + 2d * 9 (186 at d = 10);
-    final decoder 2d^2+4d+1 per node.
+    Per node and block (dense layers): neighbour projections 4d^2, receiver
+    projections 4d^2+2d, message second layers 4d^2+2d, Psi 8d^2+7d (2110 at
+    d = 10); per directed edge and block: 2 (dx, dy) + 4 (|d|) + 2d * 9 (186 at
+    d = 10); final decoder 2d^2+4d+1 per node. Returns (dense, per-edge).
     """
     per_node = 4 * d * d + (4 * d * d + 2 * d) + (4 * d * d + 2 * d) + (8 * d * d + 7 * d)
     per_edge = 6 + 2 * d * 9
-    return kbar * (per_node * sum_k + per_edge * n_edges) + (2 * d * d + 4 * d + 1) * sum_k
+    dense = kbar * per_node * sum_k + (2 * d * d + 4 * d + 1) * sum_k
+    return float(dense), float(kbar * per_edge * n_edges)
+
+
+def dss_peak_tflops(precision: str, dense: float, edge: float) -> float:
+    """Peak rate for the DSS flop mix: the MFMA kernel runs the dense layers on
+    BF16 matrix cores and the edge sums in packed FP16 VALU, so its floor time
+    is dense/BF16 peak + edge/packed FP16 peak; the VALU kernels run all of it
+    on FP32 or FP64 vector units."""
+    if precision == "bf16":
+        return (dense + edge) / (dense / BF16_MFMA_TF + edge / FP16_PACKED_TF)
+    return FP64_VALU_TF if precision == "fp64" else FP32_VALU_TF
 
 
 def apply_bytes(n: int, K: int, sum_k: int, n_edges: int, xy_bytes: int = 8) -> float:
@@ -54,6 +81,26 @@ def apply_bytes(n: int, K: int, sum_k: int, n_edges: int, xy_bytes: int = 8) -> 
     """
     return (sum_k * (8 + 4 + 8 + xy_bytes + 4 + 8) + 2 * n_edges + 8.0 * K * K
             + n * (4 + 1 + 8 + 8) + sum_k * (4 + 4 + 8 + 8))
+
+
+def _make(spec):
+    """(seed, target_nodes, n_parts, jitter) -> (problem, host arrays); runs in a worker process."""
+    import paper_2402_08296_amd as dg
+    import workload as W
+    seed, nn, parts, jit = spec
+    p = W.make_problem(seed, nn, parts, jit)
+    hp = dg.host_problem(p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, p.A.rowptr, p.A.col, p.A.val, p.b, p.u0,
+                         p.part, p.n_parts, 2)
+    return p, hp
+
+
+def generate(specs, workers: int):
+    """Host problems of the given specs, built in worker processes (before the GPU is touched)."""
+    if workers <= 1 or len(specs) <= 1:
+        return [_make(s) for s in specs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(workers, len(specs))) as pool:
+        return pool.map(_make, specs, chunksize=1)
 
 
 def cpu_baseline(p, hp, theta, iterations: int, sample: int) -> dict:
@@ -97,6 +144,96 @@ def cpu_baseline(p, hp, theta, iterations: int, sample: int) -> dict:
                       f"times the GPU solve's {iterations} iterations; {per_solve:.1f} s per solve"}
 
 
+def bench_batched(dg, ctx, model, items, opts, reps: int, sequential: bool) -> dict:
+    """One batched solve of all items (after a warm-up), and optionally the same one after another."""
+    import torch
+    probs = [dg.Problem(ctx, hp, model) for _, hp in items]
+    outs = [torch.empty(pr.n, dtype=torch.float64, device="cuda") for pr in probs]
+    dg.solve_batch(ctx, probs, outs, opts, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sts = dg.solve_batch(ctx, probs, outs, opts, check=False)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    res = {"problems": len(probs), "nodes": int(sum(pr.n for pr in probs)),
+           "subdomains": int(sum(pr.K for pr in probs)),
+           "batched_s": t_batch, "batched_solves_per_s": len(probs) / t_batch,
+           "converged": int(sum(1 for s in sts if s.converged)),
+           "iterations_max": int(max(s.iterations for s in sts)),
+           "iterations_mean": float(np.mean([s.iterations for s in sts]))}
+    if sequential:
+        for pr, u in zip(probs, outs):  # warm (graph capture per problem)
+            pr.solve(u, opts, check=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for pr, u in zip(probs, outs):
+            pr.solve(u, opts, check=False)
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        res.update({"sequential_s": t_seq, "sequential_solves_per_s": len(probs) / t_seq,
+                    "batch_speedup": t_seq / t_batch})
+    for pr in probs:
+        pr.close()
+    return res
+
+
+def bench_serve(dg, model, stream, opts, budget: int) -> dict:
+    """Replays a stream of requests (arrival offsets in s) through the serving loop."""
+    import torch
+    sctx = dg.Context(torch.cuda.Stream())
+    srv = dg.Server(sctx, model, hbm_budget=budget, max_active=64, setup_threads=8)
+    t0 = time.perf_counter()
+    tickets = []
+    for t_arr, hp in stream:
+        wait = t0 + t_arr - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        tickets.append(srv.submit(hp, opts))
+    srv.drain()
+    makespan = time.perf_counter() - t0
+    lat, its, ok = [], [], 0
+    for t in tickets:
+        rc, st, _ = srv.poll(t, with_solution=False)
+        lat.append(st.latency_ms)
+        its.append(st.iterations)
+        ok += int(rc == 0)
+    srv.close()
+    sctx.close()
+    nodes = sum(hp.n for _, hp in stream)
+    return {"requests": len(stream), "completed_ok": ok, "makespan_s": makespan,
+            "solves_per_s": len(stream) / makespan, "offered_rate_per_s": len(stream) / max(stream[-1][0], 1e-9),
+            "nodes_total": int(nodes), "p50_latency_ms": float(np.percentile(lat, 50)),
+            "p99_latency_ms": float(np.percentile(lat, 99)), "max_latency_ms": float(np.max(lat)),
+            "iterations_mean": float(np.mean(its))}
+
+
+def pmc_workload(args):
+    """Copies of known size (counter calibration) and a few DSS applies of the main workload."""
+    import torch
+
+    import paper_2402_08296_amd as dg
+    import workload as W
+    p, hp = _make((W.CONFIGS[args.config]["seeds"][0], W.CONFIGS[args.config]["target_nodes"],
+                   W.CONFIGS[args.config]["n_parts"], W.CONFIGS[args.config]["jitter"]))
+    torch.cuda.set_device(0)
+    ctx = dg.Context()
+    model = dg.Model(ctx, W.smoother_theta(omega=0.15, out_scale=1.7))
+    prob = dg.Problem(ctx, hp, model)
+    x = torch.ones(PMC_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    r = torch.from_numpy(np.ascontiguousarray(p.b - p.A.to_scipy() @ p.u0)).cuda()
+    z = torch.empty_like(r)
+    opts = dg.default_opts(precision=args.precision)
+    for _ in range(6):
+        prob.apply(r, z, opts)
+    torch.cuda.synchronize()
+    log(f"pmc workload done: 3 copies of {PMC_COPY_BYTES} B, 6 applies ({args.precision})")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,26 +243,50 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--theta", default="smoother", choices=["smoother", "xavier"])
     ap.add_argument("--cpu-sample", type=int, default=160, help="sub-meshes in the oracle sample (0: skip)")
+    ap.add_argument("--batch8", type=int, default=8, help="copies of the main problem in one batch (0: skip)")
+    ap.add_argument("--batch", type=int, default=64, help="problems of the 10k-200k batch (0: skip)")
+    ap.add_argument("--serve", type=int, default=40, help="requests of the stream prefix (0: skip)")
+    ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--pmc-workload", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.pmc_workload:
+        pmc_workload(args)
+        return
+
+    import workload as W
+
+    # ---- all host inputs first, in worker processes, before the GPU is touched
+    t = time.perf_counter()
+    cfg = W.CONFIGS[args.config]
+    p, hp = _make((cfg["seeds"][0], cfg["target_nodes"], cfg["n_parts"], cfg["jitter"]))
+    log(f"problem {args.config}: N={p.n} nnz={p.A.val.size} K={hp.K} sum_k={hp.sub_nodes.size} "
+        f"({time.perf_counter() - t:.1f}s)")
+    batch_items = []
+    if args.batch > 0:
+        t = time.perf_counter()
+        batch_items = generate(W.batch_specs("c4", args.batch), args.workers)
+        log(f"batch c4: {len(batch_items)} problems, {sum(q.n for q, _ in batch_items)} nodes "
+            f"({time.perf_counter() - t:.1f}s)")
+    stream = []
+    if args.serve > 0:
+        t = time.perf_counter()
+        specs = W.stream_specs("c5", args.serve)
+        made = generate([s[1:] for s in specs], args.workers)
+        stream = [(s[0], hp_) for s, (_, hp_) in zip(specs, made)]
+        log(f"stream c5: {len(stream)} requests, {sum(h.n for _, h in stream)} nodes over "
+            f"{specs[-1][0]:.2f}s of arrivals ({time.perf_counter() - t:.1f}s)")
 
     import torch
 
     import paper_2402_08296_amd as dg
-    import workload as W
+    from paper_2402_08296_amd import profiling
 
-    t = time.perf_counter()
-    cfg = W.CONFIGS[args.config]
-    p = W.config_problem(args.config, 0)
-    hp = dg.host_problem(p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, p.A.rowptr, p.A.col, p.A.val, p.b, p.u0,
-                         p.part, p.n_parts, 2)
     theta = W.smoother_theta(omega=0.15, out_scale=1.7) if args.theta == "smoother" else \
         W.xavier_theta(W.THETA_SEED)
-    log(f"problem {args.config}: N={p.n} nnz={p.A.val.size} K={hp.K} sum_k={hp.sub_nodes.size} "
-        f"({time.perf_counter() - t:.1f}s)")
     torch.cuda.set_device(0)
     ctx = dg.Context()
     model = dg.Model(ctx, theta)
@@ -134,7 +295,8 @@ def main():
     log(f"library setup {time.perf_counter() - t:.1f}s; edges={prob.n_edges}")
     u = torch.empty(p.n, dtype=torch.float64, device="cuda")
     max_it = 5000 if args.theta == "smoother" else 200
-    opts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, profile=1, check_every=16)
+    opts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, check_every=16)
+    popts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, profile=1, check_every=16)
     for w in range(args.warmup):
         st = prob.solve(u, opts, check=False)
         log(f"warmup {w}: iterations={st.iterations} status={st.status} true_rel={st.true_rel_residual:.2e}")
@@ -143,28 +305,30 @@ def main():
     stats = []
     for k in range(args.steps):
         st = prob.solve(u, opts, check=False)
-        stats.append((st.iterations, st.converged, st.true_rel_residual, st.solve_ms, st.dss_launches, st.dss_ms,
-                      st.coarse_ms, st.prolong_ms, st.krylov_ms))
-        dss_kernel = {0: "dss_kernel<double>", 1: "dss_kernel<float>", 2: "dss_mfma_kernel"}[st.dss_kernel]
+        stats.append((st.iterations, st.converged, st.true_rel_residual, st.solve_ms))
         log(f"step {k}: iterations={st.iterations} converged={st.converged} true_rel={st.true_rel_residual:.2e} "
             f"solve_ms={st.solve_ms:.1f}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    iters = stats[-1][0]
-    dss_launches = sum(s[4] for s in stats)
-    dss_ms = sum(s[5] for s in stats)
-    coarse_ms = sum(s[6] for s in stats)
-    prolong_ms = sum(s[7] for s in stats)
-    krylov_ms = sum(s[8] for s in stats)
-    dss_avg_ms = dss_ms / max(1, dss_launches)
-    flops = dss_flops(30, 10, prob.sum_k, prob.n_edges)
+    # One more solve with HIP events around every stage (outside the timed steps).
+    sp = prob.solve(u, popts, check=False)
+    dss_kernel = {0: "dss_kernel<double>", 1: "dss_kernel<float>", 2: "dss_mfma_kernel"}[sp.dss_kernel]
+    n_it = max(1, sp.dss_launches)
+    dss_avg_ms = sp.dss_ms / n_it
+    dense, edge = dss_flops(30, 10, prob.sum_k, prob.n_edges)
+    flops = dense + edge
     achieved = flops / (dss_avg_ms * 1e-3) / 1e12
-    apply_ms = (dss_ms + coarse_ms + prolong_ms) / max(1, dss_launches)
+    peak = dss_peak_tflops(args.precision if sp.dss_kernel == 2 or args.precision != "bf16" else "fp32", dense, edge)
+    apply_ms = (sp.dss_ms + sp.coarse_ms + sp.prolong_ms) / n_it
     abytes = apply_bytes(prob.n, prob.K, prob.sum_k, prob.n_edges, 8 if args.precision == "fp64" else 4)
-    value = args.steps / elapsed
+    traffic = None
+    tr = profiling.read_traffic(TRAFFIC_FILE)
+    if tr and sp.dss_kernel == 2 and tr.get("source_hash") == profiling.source_hash():
+        traffic = tr["traffic_bytes_per_dispatch"]
+    iters = stats[-1][0]
     out = {
         "metric": "time-to-1e-6 residual & solves/s at 1M nodes; precond-apply HBM GB/s; p99 latency",
-        "value": value,
+        "value": args.steps / elapsed,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -173,7 +337,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"bf16": "bf16+f32+f64", "fp32": "f32+f64", "fp64": "f64"}[args.precision],
+        "dtype": {"bf16": "bf16+f16+f32+f64", "fp32": "f32+f64", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.config}: P1-FEM Poisson on a Delaunay mesh of a star polygon, "
                                f"N={p.n}, K={hp.K} sub-meshes (overlap 2), sum k_i={hp.sub_nodes.size}, "
@@ -186,15 +350,26 @@ def main():
         "time_to_solution_ms": 1e3 * elapsed / args.steps,
         "apply_ms": apply_ms,
         "apply_hbm_GBps": abytes / (apply_ms * 1e-3) / 1e9,
-        "breakdown_ms_per_iteration": {
-            "dss": dss_ms / max(1, dss_launches), "coarse": coarse_ms / max(1, dss_launches),
-            "prolong": prolong_ms / max(1, dss_launches), "krylov": krylov_ms / max(1, dss_launches)},
-        "roofline": {"kernel": dss_kernel, "bound": "alu", "achieved": achieved,
-                     "peak": PEAK_TFLOPS[args.precision], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS[args.precision], "traffic": None,
-                     "flops_per_launch": flops, "avg_launch_ms": dss_avg_ms},
+        "breakdown_ms_per_iteration": {"dss": sp.dss_ms / n_it, "coarse": sp.coarse_ms / n_it,
+                                       "prolong": sp.prolong_ms / n_it, "krylov": sp.krylov_ms / n_it},
+        "roofline": {"kernel": dss_kernel, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": traffic, "flops_per_launch": flops,
+                     "flops_dense": dense, "flops_edge": edge, "avg_launch_ms": dss_avg_ms,
+                     "algorithmic_bytes_per_apply": abytes},
         "p99_latency_ms": None,
     }
+    if args.batch8 > 1:
+        log(f"{args.config} x{args.batch8} in one batch")
+        out["batched_same_x8"] = bench_batched(dg, ctx, model, [(p, hp)] * args.batch8, opts, 1, False)
+        out["batched_same_x8"]["vs_sequential_value"] = out["batched_same_x8"]["batched_solves_per_s"] / out["value"]
+    if batch_items:
+        log("batch c4")
+        out["batch_c4"] = bench_batched(dg, ctx, model, batch_items, opts, 2, True)
+    if stream:
+        log("stream c5")
+        sopts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, check_every=8, graph=0)
+        out["serve_c5"] = bench_serve(dg, model, stream, sopts, 64 << 30)
+        out["p99_latency_ms"] = out["serve_c5"]["p99_latency_ms"]
     if args.cpu_sample > 0:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(p, hp, theta, iters, args.cpu_sample)

@@ -2,11 +2,121 @@
 #include "setup.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 namespace ddmgnn {
+
+namespace {
+
+// Rows (or columns) 0..n-1 of a dense kernel spread over host threads; each
+// index is handled by one thread, so results do not depend on the thread count.
+template <class F>
+void parallel_for(int64_t n, F&& f) {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int64_t T = std::min<int64_t>({n, (int64_t)hw, 16});
+    if (T <= 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    auto work = [&] {
+        for (int64_t i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
+    };
+    std::vector<std::thread> th;
+    for (int64_t t = 1; t < T; ++t) th.emplace_back(work);
+    work();
+    for (auto& t : th) t.join();
+}
+
+// sum_p a[p] b[p] with four interleaved partial sums (a fixed order).
+inline double dot4(const double* a, const double* b, int64_t len) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t p = 0;
+    for (; p + 4 <= len; p += 4) {
+        s0 += a[p] * b[p];
+        s1 += a[p + 1] * b[p + 1];
+        s2 += a[p + 2] * b[p + 2];
+        s3 += a[p + 3] * b[p + 3];
+    }
+    for (; p < len; ++p) s0 += a[p] * b[p];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// Blocked right-looking Cholesky of the symmetric K x K matrix a (row-major),
+// then inv = A^{-1} by forward and backward substitution on blocks of 64
+// identity columns. Returns false when a pivot is not positive.
+bool dense_cholesky(const std::vector<double>& a, int32_t K, std::vector<double>& inv) {
+    constexpr int32_t B = 64;
+    std::vector<double> L(a);
+    auto at = [&](int64_t i, int64_t j) -> double& { return L[(size_t)i * K + j]; };
+    std::vector<double> panel;
+    for (int32_t kb = 0; kb < K; kb += B) {
+        const int32_t ke = std::min(K, kb + B), w = ke - kb;
+        // diagonal block (earlier panels already applied by the trailing updates)
+        for (int32_t j = kb; j < ke; ++j) {
+            const double dsum = at(j, j) - dot4(&at(j, kb), &at(j, kb), j - kb);
+            if (!(dsum > 0.0) || !std::isfinite(dsum)) return false;
+            at(j, j) = std::sqrt(dsum);
+            for (int32_t i = j + 1; i < ke; ++i) at(i, j) = (at(i, j) - dot4(&at(i, kb), &at(j, kb), j - kb)) / at(j, j);
+        }
+        // panel rows below the block, then a packed copy of rows ke.. of the panel
+        parallel_for(K - ke, [&](int64_t t) {
+            const int64_t i = ke + t;
+            for (int32_t j = kb; j < ke; ++j) at(i, j) = (at(i, j) - dot4(&at(i, kb), &at(j, kb), j - kb)) / at(j, j);
+        });
+        panel.assign((size_t)(K - ke) * w, 0.0);
+        for (int64_t i = ke; i < K; ++i) std::memcpy(&panel[(size_t)(i - ke) * w], &at(i, kb), w * sizeof(double));
+        // trailing update of the lower triangle
+        parallel_for(K - ke, [&](int64_t t) {
+            const double* pi = &panel[(size_t)t * w];
+            double* row = &at(ke + t, ke);
+            for (int64_t u = 0; u <= t; ++u) row[u] -= dot4(pi, &panel[(size_t)u * w], w);
+        });
+    }
+    // L^T (row-major) for the backward substitution.
+    std::vector<double> LT((size_t)K * K, 0.0);
+    for (int64_t i = 0; i < K; ++i)
+        for (int64_t j = 0; j <= i; ++j) LT[(size_t)j * K + i] = at(i, j);
+    // Columns c0..c0+63 of A^{-1} on rows c0..K-1 (the lower triangle; the
+    // inverse is symmetric): L Y = E from row c0 down, then L^T X = Y from row
+    // K-1 up to row c0 (rows below c0 of X are not needed). Each row update is
+    // a multiply-add over 8 columns held in registers, p in a fixed order.
+    inv.assign((size_t)K * K, 0.0);
+    const int32_t nblk = (K + B - 1) / B;
+    parallel_for(nblk, [&](int64_t cb) {
+        const int32_t c0 = (int32_t)cb * B, w = std::min(K, c0 + B) - c0;
+        std::vector<double> Y((size_t)K * B, 0.0);  // row i: columns c0.. of Y, then of X
+        auto row_update = [&](const double* coef, int32_t p0, int32_t p1, int32_t i, bool forward) {
+            double* yi = &Y[(size_t)i * B];
+            for (int32_t cc = 0; cc < w; cc += 8) {
+                double acc[8];
+                for (int32_t c = 0; c < 8; ++c) acc[c] = forward ? ((i == c0 + cc + c) ? 1.0 : 0.0) : yi[cc + c];
+                for (int32_t p = p0; p < p1; ++p) {
+                    const double l = coef[p];
+                    const double* yp = &Y[(size_t)p * B + cc];
+                    for (int32_t c = 0; c < 8; ++c) acc[c] -= l * yp[c];
+                }
+                const double dinv = coef[i];
+                for (int32_t c = 0; c < 8; ++c) yi[cc + c] = acc[c] / dinv;
+            }
+        };
+        for (int32_t i = c0; i < K; ++i) row_update(&at(i, 0), c0, i, i, true);
+        for (int32_t i = K - 1; i >= c0; --i) row_update(&LT[(size_t)i * K], i + 1, K, i, false);
+        for (int32_t i = c0; i < K; ++i)
+            for (int32_t c = 0; c < w; ++c) inv[(size_t)i * K + c0 + c] = Y[(size_t)i * B + c];
+    });
+    // mirror the lower triangle (exactly symmetric inverse)
+    for (int64_t i = 0; i < K; ++i)
+        for (int64_t j = 0; j < i; ++j) inv[(size_t)j * K + i] = inv[(size_t)i * K + j];
+    return true;
+}
+
+}  // namespace
+
 
 namespace {
 
@@ -151,31 +261,34 @@ void build_local_graphs(const ddmgnn_problem_desc& d, HostSetup& s) {
     std::vector<int32_t> adj;
     mesh_adjacency(n, d.n_tri, d.tri, aptr, adj);
 
-    // Local DSS graphs. Local order equals ascending global order, so walking
-    // a receiver's sorted global neighbours yields senders in ascending local order.
-    std::vector<int32_t> loc(n, -1);
+    // Local DSS graphs. The local index of a node is its rank in the sorted
+    // sub-mesh list, and a receiver's global neighbours are sorted, so walking
+    // them yields senders in ascending local order. Sub-meshes are independent:
+    // first count each slot's in-edges, then fill them.
+    auto local_of = [&](int64_t b, int64_t e, int32_t g) -> int32_t {
+        const int32_t* first = d.sub_nodes + b;
+        const int32_t* last = d.sub_nodes + e;
+        const int32_t* it = std::lower_bound(first, last, g);
+        return (it != last && *it == g) ? (int32_t)(it - first) : -1;
+    };
     s.edge_ptr.assign(s.sk + 1, 0);
-    s.edge_src.clear();
     s.slot_sub.assign(s.sk, 0);
-    s.max_k = 0;
-    for (int32_t i = 0; i < K; ++i) {
-        int64_t b = d.sub_ptr[i], e = d.sub_ptr[i + 1];
-        s.max_k = std::max<int32_t>(s.max_k, (int32_t)(e - b));
-        for (int64_t k = b; k < e; ++k) loc[d.sub_nodes[k]] = (int32_t)(k - b);
+    parallel_for(K, [&](int64_t i) {
+        const int64_t b = d.sub_ptr[i], e = d.sub_ptr[i + 1];
         for (int64_t k = b; k < e; ++k) {
-            int32_t j = d.sub_nodes[k];
-            s.slot_sub[k] = i;
-            if (!d.dirichlet[j]) {
-                for (int64_t a = aptr[j]; a < aptr[j + 1]; ++a) {
-                    int32_t l = adj[a];
-                    if (loc[l] >= 0) s.edge_src.push_back((uint16_t)loc[l]);
-                }
-            }
-            s.edge_ptr[k + 1] = (int64_t)s.edge_src.size();
+            const int32_t j = d.sub_nodes[k];
+            s.slot_sub[k] = (int32_t)i;
+            int64_t c = 0;
+            if (!d.dirichlet[j])
+                for (int64_t a = aptr[j]; a < aptr[j + 1]; ++a) c += local_of(b, e, adj[a]) >= 0;
+            s.edge_ptr[k + 1] = c;
         }
-        for (int64_t k = b; k < e; ++k) loc[d.sub_nodes[k]] = -1;
-    }
-    s.n_edges = (int64_t)s.edge_src.size();
+    });
+    for (int64_t k = 0; k < s.sk; ++k) s.edge_ptr[k + 1] += s.edge_ptr[k];
+    s.n_edges = s.edge_ptr[s.sk];
+    s.edge_src.assign(s.n_edges, 0);
+    s.max_k = 0;
+    for (int32_t i = 0; i < K; ++i) s.max_k = std::max<int32_t>(s.max_k, (int32_t)(d.sub_ptr[i + 1] - d.sub_ptr[i]));
 
     // Membership lists: slots of every node, in increasing slot order.
     s.node_ptr.assign(n + 1, 0);
@@ -192,18 +305,25 @@ void build_local_graphs(const ddmgnn_problem_desc& d, HostSetup& s) {
         return d.sub_ptr[a + 1] - d.sub_ptr[a] > d.sub_ptr[b + 1] - d.sub_ptr[b];
     });
 
-    // Tile order, centred split coordinates and edge lengths.
+    // Per sub-mesh: senders, tile order, centred split coordinates and edge lengths.
     s.tnode.assign(s.sk, 0);
     s.xyhl.assign(4 * s.sk, 0);
     s.xyc.assign(2 * s.sk, 0.0);
     s.erec.assign(s.n_edges, 0u);
-    s.max_edges_sub = 0;
     s.edge_nd.assign(s.n_edges, 0.0f);
-    std::vector<int32_t> ord;
-    for (int32_t i = 0; i < K; ++i) {
+    parallel_for(K, [&](int64_t i) {
         const int64_t b = d.sub_ptr[i], e = d.sub_ptr[i + 1];
         const int32_t k = (int32_t)(e - b);
-        ord.resize(k);
+        for (int64_t q = b; q < e; ++q) {
+            const int32_t j = d.sub_nodes[q];
+            if (d.dirichlet[j]) continue;
+            int64_t t = s.edge_ptr[q];
+            for (int64_t a = aptr[j]; a < aptr[j + 1]; ++a) {
+                const int32_t l = local_of(b, e, adj[a]);
+                if (l >= 0) s.edge_src[t++] = (uint16_t)l;
+            }
+        }
+        std::vector<int32_t> ord(k);
         std::iota(ord.begin(), ord.end(), 0);
         std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) {
             return s.edge_ptr[b + x + 1] - s.edge_ptr[b + x] > s.edge_ptr[b + y + 1] - s.edge_ptr[b + y];
@@ -238,8 +358,10 @@ void build_local_graphs(const ddmgnn_problem_desc& d, HostSetup& s) {
                 s.erec[t] = (uint32_t)s.edge_src[t] | ((uint32_t)bits << 16);
             }
         }
-        s.max_edges_sub = std::max<int64_t>(s.max_edges_sub, s.edge_ptr[e] - s.edge_ptr[b]);
-    }
+    });
+    s.max_edges_sub = 0;
+    for (int32_t i = 0; i < K; ++i)
+        s.max_edges_sub = std::max<int64_t>(s.max_edges_sub, s.edge_ptr[d.sub_ptr[i + 1]] - s.edge_ptr[d.sub_ptr[i]]);
 }
 
 std::string build_setup(const ddmgnn_problem_desc& d, HostSetup& s) {
@@ -283,45 +405,7 @@ std::string build_setup(const ddmgnn_problem_desc& d, HostSetup& s) {
             s.a0[(size_t)i * K + j] = s.a0[(size_t)j * K + i] = a;
         }
     // Cholesky A_0 = L L^T (lower, row-major), then A_0^{-1} = L^{-T} L^{-1}.
-    std::vector<double> L(s.a0);
-    for (int32_t j = 0; j < K; ++j) {
-        double* Lj = &L[(size_t)j * K];
-        double dsum = Lj[j];
-        for (int32_t p = 0; p < j; ++p) dsum -= Lj[p] * Lj[p];
-        if (!(dsum > 0.0) || !std::isfinite(dsum)) return "NOT_SPD";
-        double ljj = std::sqrt(dsum);
-        Lj[j] = ljj;
-        for (int32_t i = j + 1; i < K; ++i) {
-            double* Li = &L[(size_t)i * K];
-            double acc = Li[j];
-            for (int32_t p = 0; p < j; ++p) acc -= Li[p] * Lj[p];
-            Li[j] = acc / ljj;
-        }
-    }
-    // Column j of L^{-1} by forward substitution, stored as row j of LinvT.
-    std::vector<double> LinvT((size_t)K * K, 0.0);
-    for (int32_t j = 0; j < K; ++j) {
-        double* x = &LinvT[(size_t)j * K];
-        x[j] = 1.0 / L[(size_t)j * K + j];
-        for (int32_t i = j + 1; i < K; ++i) {
-            const double* Li = &L[(size_t)i * K];
-            double acc = 0.0;
-            for (int32_t p = j; p < i; ++p) acc += Li[p] * x[p];
-            x[i] = -acc / Li[i];
-        }
-    }
-    // A_0^{-1} = L^{-T} L^{-1}: entry (i, j) = sum_{p >= max(i,j)} Linv[p][i] Linv[p][j].
-    s.a0inv.assign((size_t)K * K, 0.0);
-    for (int32_t i = 0; i < K; ++i) {
-        const double* xi = &LinvT[(size_t)i * K];
-        for (int32_t j = 0; j <= i; ++j) {
-            const double* xj = &LinvT[(size_t)j * K];
-            double acc = 0.0;
-            for (int32_t p = i; p < K; ++p) acc += xi[p] * xj[p];
-            s.a0inv[(size_t)i * K + j] = acc;
-            s.a0inv[(size_t)j * K + i] = acc;
-        }
-    }
+    if (!dense_cholesky(s.a0, K, s.a0inv)) return "NOT_SPD";
     return "";
 }
 

@@ -1,0 +1,158 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+  python -m paper_2402_08296_amd.profiling stats <kernel_stats.csv> <out.md> --title T --command C
+      kernel-trace statistics as a markdown table
+  python -m paper_2402_08296_amd.profiling traffic <fetch counter_collection.csv> <write counter_collection.csv>
+      <out.md> --kernel NAME --copy-bytes B --fetch-command C1 --write-command C2
+      HBM bytes per dispatch of a kernel from FETCH_SIZE and WRITE_SIZE (KiB per
+      dispatch), each scaled by the ratio of a plain copy kernel's known bytes
+      to what the same counter reads for it
+
+The traffic summary records a hash of the kernel sources; bench.py reports
+the traffic only while the sources still hash the same.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+# Sources whose change invalidates a traffic measurement of the MFMA DSS kernel.
+KERNEL_SOURCES = ("csrc/dss_mfma.hip", "csrc/dss_mfma.h", "csrc/device.h")
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    """Kernel name without namespaces and argument lists (template arguments kept)."""
+    n = re.sub(r"\(anonymous namespace\)::|ddmgnn::", "", name)
+    n = re.sub(r"^void ", "", n)
+    depth, out = 0, []
+    for ch in n:
+        if ch == "(" and depth == 0:
+            break
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def stats_markdown(csv_path: str, title: str, command: str, notes: str = "") -> str:
+    rows = list(csv.DictReader(open(csv_path)))
+    lines = [f"# {title}", "", "Command (run from /tmp with TMPDIR=/tmp, repository at <repo>):", "", "```",
+             command, "```", "", "| Kernel | Calls | Total ms | Average us | Min us | Max us | % |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| {short_name(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
+    if notes:
+        lines += ["", notes]
+    return "\n".join(lines) + "\n"
+
+
+def per_dispatch(csv_path: str, counter: str) -> dict:
+    """{short kernel name: [counter value per dispatch]} from a counter_collection.csv."""
+    out = defaultdict(list)
+    for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] == counter:
+            out[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return out
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, fetch_cmd: str,
+                    write_cmd: str) -> dict:
+    fetch = per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = per_dispatch(write_csv, "WRITE_SIZE")
+    copy_name = next(k for k in fetch if "copyBuffer" in k)
+    # the copy dispatches of the calibration buffer are the largest ones
+    cf = max(fetch[copy_name])
+    cw = max(write[copy_name])
+    f_fetch = copy_bytes / (cf * 1024.0)
+    f_write = copy_bytes / (cw * 1024.0)
+    kf, kw = fetch[kernel], write[kernel]
+    fetch_b = sum(kf) / len(kf) * 1024.0 * f_fetch
+    write_b = sum(kw) / len(kw) * 1024.0 * f_write
+    return {
+        "kernel": kernel, "dispatches": len(kf),
+        "fetch_kib_per_dispatch": sum(kf) / len(kf), "write_kib_per_dispatch": sum(kw) / len(kw),
+        "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
+        "fetch_scale": f_fetch, "write_scale": f_write,
+        "fetch_bytes_per_dispatch": fetch_b, "write_bytes_per_dispatch": write_b,
+        "traffic_bytes_per_dispatch": fetch_b + write_b,
+        "source_hash": source_hash(), "fetch_command": fetch_cmd, "write_command": write_cmd,
+    }
+
+
+def traffic_markdown(res: dict) -> str:
+    """Human-readable traffic summary with the figures in a JSON block (read by bench.py)."""
+    mb = lambda b: f"{b / 1e6:.1f} MB"
+    lines = [f"# HBM traffic per dispatch: {res['kernel']}", "",
+             "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two rocprofv3 counter passes, each scaled by",
+             "known bytes / counter reading of the largest plain copy (hipMemcpy device-to-device blit) in the",
+             "same run. Commands (from /tmp with TMPDIR=/tmp, repository at <repo>):", "", "```",
+             res["fetch_command"], res["write_command"], "```", "",
+             "| | fetch | write |", "|---|---|---|",
+             f"| copy calibration ({mb(res['copy_bytes'])} each way) | {res['copy_fetch_kib']:.0f} KiB | "
+             f"{res['copy_write_kib']:.0f} KiB |",
+             f"| scale | {res['fetch_scale']:.4f} | {res['write_scale']:.4f} |",
+             f"| {res['kernel']} (mean of {res['dispatches']} dispatches) | "
+             f"{res['fetch_kib_per_dispatch']:.0f} KiB -> {mb(res['fetch_bytes_per_dispatch'])} | "
+             f"{res['write_kib_per_dispatch']:.0f} KiB -> {mb(res['write_bytes_per_dispatch'])} |",
+             "", f"Traffic per dispatch: {mb(res['traffic_bytes_per_dispatch'])}. Kernel sources hash "
+             f"{res['source_hash']}.", "", "```json", json.dumps(res, indent=1), "```", ""]
+    return "\n".join(lines)
+
+
+def read_traffic(path: str) -> dict | None:
+    """The JSON block of a traffic summary, or None when the file is absent."""
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    return json.loads(m.group(1)) if m else None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("out")
+    s.add_argument("--title", required=True)
+    s.add_argument("--command", required=True)
+    s.add_argument("--notes", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_csv")
+    t.add_argument("write_csv")
+    t.add_argument("out")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--fetch-command", required=True)
+    t.add_argument("--write-command", required=True)
+    a = ap.parse_args()
+    if a.cmd == "stats":
+        with open(a.out, "w") as f:
+            f.write(stats_markdown(a.csv, a.title, a.command, a.notes))
+    else:
+        res = traffic_summary(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, a.fetch_command, a.write_command)
+        with open(a.out, "w") as f:
+            f.write(traffic_markdown(res))
+        print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
