@@ -192,16 +192,18 @@ def bench_serve(dg, model, stream, opts, budget: int) -> dict:
         tickets.append(srv.submit(hp, opts))
     srv.drain()
     makespan = time.perf_counter() - t0
-    lat, its, ok = [], [], 0
+    lat, its, ok, status = [], [], 0, {}
     for t in tickets:
         rc, st, _ = srv.poll(t, with_solution=False)
         lat.append(st.latency_ms)
         its.append(st.iterations)
         ok += int(rc == 0)
+        name = dg.STATUS.get(rc, str(rc))
+        status[name] = status.get(name, 0) + 1
     srv.close()
     sctx.close()
     nodes = sum(hp.n for _, hp in stream)
-    return {"requests": len(stream), "completed_ok": ok, "makespan_s": makespan,
+    return {"requests": len(stream), "completed_ok": ok, "status": status, "makespan_s": makespan,
             "solves_per_s": len(stream) / makespan, "offered_rate_per_s": len(stream) / max(stream[-1][0], 1e-9),
             "nodes_total": int(nodes), "p50_latency_ms": float(np.percentile(lat, 50)),
             "p99_latency_ms": float(np.percentile(lat, 99)), "max_latency_ms": float(np.max(lat)),
@@ -246,6 +248,7 @@ def main():
     ap.add_argument("--batch8", type=int, default=8, help="copies of the main problem in one batch (0: skip)")
     ap.add_argument("--batch", type=int, default=64, help="problems of the 10k-200k batch (0: skip)")
     ap.add_argument("--serve", type=int, default=40, help="requests of the stream prefix (0: skip)")
+    ap.add_argument("--serve-slow-rate", type=float, default=6.0, help="arrival rate of the sustained replay (1/s)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--pmc-workload", action="store_true")
     args = ap.parse_args()
@@ -271,12 +274,15 @@ def main():
         batch_items = generate(W.batch_specs("c4", args.batch), args.workers)
         log(f"batch c4: {len(batch_items)} problems, {sum(q.n for q, _ in batch_items)} nodes "
             f"({time.perf_counter() - t:.1f}s)")
-    stream = []
+    stream, stream_slow = [], []
     if args.serve > 0:
         t = time.perf_counter()
         specs = W.stream_specs("c5", args.serve)
         made = generate([s[1:] for s in specs], args.workers)
         stream = [(s[0], hp_) for s, (_, hp_) in zip(specs, made)]
+        # the same requests at a rate one GPU sustains
+        slow = W.stream_specs("c5", args.serve, rate=args.serve_slow_rate)
+        stream_slow = [(s[0], hp_) for s, (_, hp_) in zip(slow, made)]
         log(f"stream c5: {len(stream)} requests, {sum(h.n for _, h in stream)} nodes over "
             f"{specs[-1][0]:.2f}s of arrivals ({time.perf_counter() - t:.1f}s)")
 
@@ -369,6 +375,9 @@ def main():
         log("stream c5")
         sopts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, check_every=8, graph=0)
         out["serve_c5"] = bench_serve(dg, model, stream, sopts, 64 << 30)
+        out["serve_c5"]["rate_per_s"] = W.STREAM_CONFIGS["c5"]["rate"]
+        out["serve_c5_sustained"] = bench_serve(dg, model, stream_slow, sopts, 64 << 30)
+        out["serve_c5_sustained"]["rate_per_s"] = args.serve_slow_rate
         out["p99_latency_ms"] = out["serve_c5"]["p99_latency_ms"]
     if args.cpu_sample > 0:
         log("timing the CPU oracle on a sample")

@@ -65,6 +65,13 @@ def lib():
         return _lib
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is missing: build it with __graft_entry__.build()")
+    # torch bundles its own HIP runtime, loaded by file name; loading ours first
+    # would put two HIP runtimes in the process (the second then finds no
+    # device). With torch loaded first, the library binds to torch's runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(_LIB_PATH)
     sig = {
         "ddmgnn_last_error": (ctypes.c_char_p, []),

@@ -268,14 +268,15 @@ CONFIGS = {
 THETA_SEED = 42
 
 # Many independent problems solved together: 64 problems with N log-uniform
-# in [10k, 200k] and parts of about 700 nodes.
+# in [10k, 200k] and parts of about 600 nodes (sub-meshes of about 800 nodes
+# with the overlap, all below the 2048-node kernel limit).
 BATCH_CONFIGS = {
-    "c4": dict(count=64, lo=10_000, hi=200_000, nodes_per_part=700, jitter=0.15, seed=2000),
+    "c4": dict(count=64, lo=10_000, hi=200_000, nodes_per_part=600, jitter=0.12, seed=2000),
 }
 # A stream of independent solve requests: Poisson arrivals at `rate` per
-# second, N log-uniform in [lo, hi], parts of about 700 nodes.
+# second, N log-uniform in [lo, hi], parts of about 600 nodes.
 STREAM_CONFIGS = {
-    "c5": dict(count=500, rate=20.0, lo=5_000, hi=2_000_000, nodes_per_part=700, jitter=0.15, seed=3000),
+    "c5": dict(count=500, rate=20.0, lo=5_000, hi=2_000_000, nodes_per_part=600, jitter=0.12, seed=3000),
 }
 
 
