@@ -40,7 +40,7 @@ struct KState {
 };
 
 // Per slot position in tile order (nodes of a sub-mesh by decreasing
-// in-degree): the node's local id, in-degree, first in-edge, and the bf16 bits
+// in-degree): the node's local id, in-degree, first padded in-edge record, and the bf16 bits
 // of its sub-mesh-centred coordinates split as x = x_hi + x_lo, y = y_hi + y_lo.
 struct TileNode {
     int32_t e0;
@@ -66,8 +66,10 @@ struct DevProb {
     const int32_t* edge_ptr;    // per slot, in-edge range (global edge index)
     const uint16_t* edge_src;   // per edge, sender local id; padded by 8 entries
     const float* edge_nd;       // per edge, |d_jl|; padded by 8 entries
-    const uint32_t* erec;       // per edge, sender | FP16 |d_jl| << 16; padded by 8 entries
-    const TileNode* tiles;      // per slot position in tile order
+    const uint32_t* erec;       // per node of each sub-mesh, its in-edges (sender | FP16 |d_jl| << 16)
+                                // padded with sentinel records (sender k_i, |d| 0) to a multiple of MFMA_EC
+    const int32_t* epad_sub;    // [K + 1] range of each sub-mesh in erec
+    const TileNode* tiles;      // per slot position in tile order (e0 indexes erec)
     const double* xy64;         // per slot, raw coordinates
     const float* xyc32;         // per slot, sub-mesh-centred coordinates
     const int32_t* node_ptr;    // per node, range of its slots

@@ -13,6 +13,10 @@ namespace ddmgnn {
 
 constexpr int MFMA_BLOCK = 1024;  // 16 wavefronts, one sub-mesh per workgroup
 constexpr int MFMA_TILE = 32;    // nodes per MFMA tile (the N dimension)
+// Edges per straight-line chunk of the message sums. Each node's in-edge
+// records are padded to a multiple of it with records of a sentinel sender
+// whose projections are -inf, so a padded edge contributes ReLU(-inf) = 0.
+constexpr int MFMA_EC = 2;
 
 // Per step: the A operands (8 bf16 per lane, raw bits) of the six 32x16
 // weight tiles and the lanes' FP32 constants, stored structure-of-arrays
@@ -51,12 +55,14 @@ struct DssMfmaArgs {
     int apply;                   // 1: restrict P.r and write s r~ to P.local; 0: read P.c_in, write r~
 };
 
-// LDS of a workgroup: c (k floats, padded to 4), Q' (k x 48 bytes), edge
-// records (ne + 4 uint32, padded to 4), tile records (k x 16 bytes). A
-// problem whose largest need exceeds the limit is not run by this kernel.
+// LDS of a workgroup: c (k floats), Q' (2 x (k + 1) x 5 dwords, the last row
+// of each direction the sentinel), padded edge records (ne_pad uint32), each
+// region padded to 16 bytes, then tile records (k x 16 bytes). A problem whose
+// largest need exceeds the limit is not run by this kernel.
 constexpr size_t MFMA_LDS_LIMIT = 160 * 1024 - 1024;
-inline size_t mfma_lds_need(int k, int64_t ne) {
-    return (size_t)((k + 3) & ~3) * 4 + (size_t)k * 48 + (size_t)((ne + 4 + 3) & ~3) * 4 + (size_t)k * 16;
+inline size_t mfma_lds_need(int k, int64_t ne_pad) {
+    return (size_t)((k + 3) & ~3) * 4 + (size_t)((10 * ((int64_t)k + 1) + 3) & ~3) * 4 +
+           (size_t)((ne_pad + 3) & ~3) * 4 + (size_t)k * 16;
 }
 
 // Sets the dynamic-LDS limit of the kernel (not allowed during stream capture).

@@ -13,7 +13,7 @@
 //   * message units 0..9 of direction hf (hf = 0: Phi_out, hf = 1: Phi_in).
 //
 // One block k:
-//   Q'_l = W1[:, h_l] h_l + W1[:, d] x_l        (per node, MFMA; stored to LDS in FP32)
+//   Q'_l = W1[:, h_l] h_l + W1[:, d] x_l        (per node, MFMA; stored to LDS in FP16)
 //   P'_j = W1[:, h_j] h_j + b1 - W1[:, d] x_j    (per node, MFMA)
 //   S_j  = sum_{l in N(j)} ReLU(P'_j + Q'_l + w_|d| |d_jl|)   (per edge, VALU)
 // which equals sum_l ReLU(W1 (h_j, h_l, d_jl, |d_jl|) + b1) because d_jl =
@@ -39,7 +39,7 @@ constexpr int OFF_PI = OFF_PO + D * IN_PHI + D + D * D + D;
 constexpr int OFF_PS = OFF_PI + D * IN_PHI + D + D * D + D;
 constexpr int OFF_DE = OFF_PS + D * IN_PSI + D + D * D + D;
 constexpr int BLOCK_W = OFF_DE + D * D + D + D + 1;
-constexpr int EC = 4;  // edges per straight-line chunk of the message sums
+constexpr int EC = MFMA_EC;
 constexpr int MAX_TILES_PER_WAVE = (2048 / MFMA_TILE + (MFMA_BLOCK / 64) - 1) / (MFMA_BLOCK / 64);
 
 // Round-to-nearest-even float -> bf16 bits (host).
@@ -257,9 +257,12 @@ __device__ inline h2 pk(float x, float y) { return (h2){(_Float16)x, (_Float16)y
 
 // One workgroup per sub-mesh, everything the kbar blocks touch in LDS:
 //   c   [k]        normalised residual (FP32)
-//   Q'  [k][2][12] neighbour projections (FP16; 10 used per direction, rows
-//                  padded to 48 bytes for aligned 8-byte reads)
-//   E   [ne + EC]  in-edges of the sub-mesh: sender id | FP16 |d| << 16
+//   Q'  [2][k+1][5] neighbour projections (FP16 pairs), one array per
+//                  direction, row k the -inf sentinel; the odd 5-dword row
+//                  stride spreads the random sender rows of an edge gather
+//                  over all LDS banks
+//   E   [ne_pad]   in-edges of each node, padded to a multiple of EC with
+//                  sentinel records: sender id | FP16 |d| << 16
 //   T   [k]        tile records (node id, degree, first edge, split coordinates)
 // The message sums run in packed FP16 (two units per instruction).
 __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
@@ -272,14 +275,18 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     const int base = P.sub_ptr[sub];
     const int k = P.sub_ptr[sub + 1] - base;
     const int tid = threadIdx.x;
-    const int ebase = P.edge_ptr[base];
-    const int ne = P.edge_ptr[base + k] - ebase;
+    const int ebase = P.epad_sub[sub];
+    const int ne = P.epad_sub[sub + 1] - ebase;
     double* __restrict__ out = P.local;
     float* cbuf = lds;
-    _Float16* Q = reinterpret_cast<_Float16*>(lds + ((k + 3) & ~3));
-    uint32_t* E = reinterpret_cast<uint32_t*>(Q + (size_t)k * 24);
-    TileNode* T = reinterpret_cast<TileNode*>(E + ((ne + EC + 3) & ~3));
-    for (int i = tid; i < ne + EC; i += MFMA_BLOCK) E[i] = i < ne ? P.erec[ebase + i] : 0u;
+    h2* Qd = reinterpret_cast<h2*>(lds + ((k + 3) & ~3));
+    uint32_t* E = reinterpret_cast<uint32_t*>(Qd + ((10 * (k + 1) + 3) & ~3));
+    TileNode* T = reinterpret_cast<TileNode*>(E + ((ne + 3) & ~3));
+    for (int i = tid; i < ne; i += MFMA_BLOCK) E[i] = P.erec[ebase + i];
+    if (tid < 10) {  // sentinel rows: every message through them is ReLU(-inf) = 0
+        const _Float16 ninf = __builtin_bit_cast(_Float16, (uint16_t)0xFC00u);
+        Qd[(size_t)(tid / 5) * 5 * (k + 1) + 5 * k + tid % 5] = (h2){ninf, ninf};
+    }
     for (int i = tid; i < k; i += MFMA_BLOCK)
         reinterpret_cast<uint4*>(T)[i] = reinterpret_cast<const uint4*>(P.tiles + base)[i];
 
@@ -312,6 +319,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
 
     const int wave = tid >> 6, lane = tid & 63;
     const int n = lane & 31, hf = lane >> 5;
+    const h2* Qh = Qd + (size_t)hf * 5 * (k + 1);  // this lane's direction
     const int ntiles = (k + MFMA_TILE - 1) / MFMA_TILE;
     float h[MAX_TILES_PER_WAVE][5];
 #pragma unroll
@@ -336,7 +344,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                 const uint32_t xy2 = hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
                 const f32x16 q = mfma(AQ, b_pq(h[tt], xy2, hf, valid), zero);
                 if (valid) {
-                    h2* dst = reinterpret_cast<h2*>(Q + tn.j * 24 + 12 * hf);
+                    h2* dst = Qd + (size_t)(hf * (k + 1) + tn.j) * 5;
 #pragma unroll
                     for (int t = 0; t < 5; ++t) dst[t] = pk(q[2 * t], q[2 * t + 1]);
                 }
@@ -369,24 +377,18 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                     S[t] = hzero;
                 }
                 const int deg = valid ? (int)tn.deg : 0;
-                const int e0 = tn.e0 - ebase, e1 = e0 + deg;
-                // Chunks of EC edges as straight-line code: all LDS reads of the
-                // chunk are issued before the sums; an edge past e1 reads the
-                // node's own row (E is padded) and is masked with a 0 weight.
-                for (int e = e0; e < e1; e += EC) {
+                const int e0 = tn.e0 - ebase, nch = (deg + EC - 1) / EC;
+                // Chunks of EC padded edge records as straight-line code: all LDS
+                // reads of a chunk are issued before its sums.
+                for (int ch = 0; ch < nch; ++ch) {
+                    const int e = e0 + ch * EC;
                     uint32_t rec[EC];
-                    h2 msk[EC];
 #pragma unroll
-                    for (int w = 0; w < EC; ++w) {
-                        const bool in = e + w < e1;
-                        const uint32_t r0 = E[e + w];
-                        rec[w] = in ? r0 : (uint32_t)j;
-                        msk[w] = in ? (h2){(_Float16)1.0f, (_Float16)1.0f} : hzero;
-                    }
+                    for (int w = 0; w < EC; ++w) rec[w] = E[e + w];
                     h2 qq[EC][5];
 #pragma unroll
                     for (int w = 0; w < EC; ++w) {
-                        const h2* q = reinterpret_cast<const h2*>(Q + (rec[w] & 0xffffu) * 24 + 12 * hf);
+                        const h2* q = Qh + (rec[w] & 0xffffu) * 5;
 #pragma unroll
                         for (int t = 0; t < 5; ++t) qq[w][t] = q[t];
                     }
@@ -395,11 +397,8 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                         const _Float16 ndh = __builtin_bit_cast(_Float16, (uint16_t)(rec[w] >> 16));
                         const h2 nd = {ndh, ndh};
 #pragma unroll
-                        for (int t = 0; t < 5; ++t) {
-                            const h2 v = __builtin_elementwise_max(__builtin_elementwise_fma(wn[t], nd, P[t] + qq[w][t]),
-                                                                   hzero);
-                            S[t] = __builtin_elementwise_fma(msk[w], v, S[t]);
-                        }
+                        for (int t = 0; t < 5; ++t)
+                            S[t] += __builtin_elementwise_max(__builtin_elementwise_fma(wn[t], nd, P[t] + qq[w][t]), hzero);
                     }
                 }
                 const float c = valid ? cbuf[j] : 0.0f;

@@ -60,6 +60,7 @@ DevProb make_view(ddmgnn_problem* P) {
     v.dirichlet = P->dirichlet.p;
     v.sub_ptr = P->sub_ptr.p; v.sub_nodes = P->sub_nodes.p; v.weights = P->weights.p;
     v.edge_ptr = P->edge_ptr.p; v.edge_src = P->edge_src.p; v.edge_nd = P->edge_nd.p; v.erec = P->erec.p;
+    v.epad_sub = P->epad_sub.p;
     v.tiles = P->tiles.p; v.xy64 = P->xy64.p; v.xyc32 = P->xyc32.p;
     v.node_ptr = P->node_ptr.p; v.node_slots = P->node_slots.p; v.slot_sub = P->slot_sub.p; v.a0inv = P->a0inv.p;
     v.u = P->u.p; v.r = P->r.p; v.z = P->z.p; v.c_in = nullptr;
@@ -506,7 +507,8 @@ size_t problem_device_bytes(int64_t n, int64_t nnz, int32_t K, int64_t sk, int64
     b += 4 * (n + 1) + 12 * nnz;                 // CSR
     b += 8 * n * 2 + n;                          // b, u0, dirichlet
     b += 4 * (K + 1) + 12 * sk;                  // sub_ptr, sub_nodes, weights
-    b += 4 * (sk + 1) + (2 + 4 + 4) * (ne + 8);  // edge_ptr, edge_src, erec, edge_nd
+    b += 4 * (sk + 1) + (2 + 4) * (ne + 8);      // edge_ptr, edge_src, edge_nd
+    b += 4 * (ne + sk * (MFMA_EC - 1)) + 4 * (K + 1);  // padded edge records (bound), their ranges
     b += 16 * sk + 16 * sk + 8 * sk;             // tiles, xy64, xyc32
     b += 4 * (n + 1) + 8 * sk;                   // node_ptr, node_slots, slot_sub
     b += 8 * (size_t)K * K + 24 * (size_t)K;     // a0inv, s, y0, y
@@ -565,6 +567,25 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
     HIP_TRY(P->xyc32.upload(xyc32.data(), 2 * sk, s));
     HIP_TRY(P->a0inv.upload(hs.a0inv.data(), (size_t)K * K, s));
     {
+        // MFMA kernel records: each node's in-edges padded to a multiple of
+        // MFMA_EC with sentinel records (sender k_i, |d| 0), and the tile
+        // records pointing at them.
+        std::vector<uint32_t> er;
+        er.reserve((size_t)hs.n_edges + (size_t)sk * (MFMA_EC - 1));
+        std::vector<int32_t> epad(K + 1, 0), e0pad(sk, 0);
+        size_t need = 0;
+        for (int i = 0; i < K; ++i) {
+            const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
+            epad[i] = (int32_t)er.size();
+            for (int64_t slot = b; slot < e; ++slot) {
+                e0pad[slot] = (int32_t)er.size();
+                for (int64_t t = hs.edge_ptr[slot]; t < hs.edge_ptr[slot + 1]; ++t) er.push_back(hs.erec[t]);
+                while ((er.size() - e0pad[slot]) % MFMA_EC) er.push_back((uint32_t)(e - b));
+            }
+            need = std::max(need, mfma_lds_need((int)(e - b), (int64_t)er.size() - epad[i]));
+        }
+        epad[K] = (int32_t)er.size();
+        P->mfma_fits = need <= MFMA_LDS_LIMIT;
         std::vector<TileNode> tiles(sk);
         for (int i = 0; i < K; ++i) {
             const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
@@ -572,7 +593,7 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
                 const int32_t j = hs.tnode[q];
                 const int64_t slot = b + j;
                 TileNode& t = tiles[q];
-                t.e0 = (int32_t)hs.edge_ptr[slot];
+                t.e0 = e0pad[slot];
                 t.j = (uint16_t)j;
                 t.deg = (uint16_t)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]);
                 t.xh = hs.xyhl[4 * slot + 0];
@@ -582,15 +603,8 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
             }
         }
         HIP_TRY(P->tiles.upload(tiles.data(), tiles.size(), s));
-        std::vector<uint32_t> er(hs.erec);
-        er.resize(er.size() + 8, 0u);
-        HIP_TRY(P->erec.upload(er.data(), er.size(), s));
-        size_t need = 0;
-        for (int i = 0; i < K; ++i) {
-            const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
-            need = std::max(need, mfma_lds_need((int)(e - b), hs.edge_ptr[e] - hs.edge_ptr[b]));
-        }
-        P->mfma_fits = need <= MFMA_LDS_LIMIT;
+        HIP_TRY(P->erec.upload(er.data(), std::max<size_t>(er.size(), 1), s));
+        HIP_TRY(P->epad_sub.upload(epad.data(), epad.size(), s));
     }
     {
         std::vector<float> nd(hs.edge_nd);

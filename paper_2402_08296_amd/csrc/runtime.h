@@ -141,7 +141,8 @@ struct ddmgnn_problem {
     ddmgnn::DevBuf<double> weights, xy64, a0inv;
     ddmgnn::DevBuf<float> xyc32;     // per slot, centred on the sub-mesh
     ddmgnn::DevBuf<ddmgnn::TileNode> tiles;
-    ddmgnn::DevBuf<uint32_t> erec;   // padded by 8 entries
+    ddmgnn::DevBuf<uint32_t> erec;   // MFMA kernel edge records, padded per node
+    ddmgnn::DevBuf<int32_t> epad_sub;  // [K + 1] ranges of the sub-meshes in erec
     ddmgnn::DevBuf<float> edge_nd;   // padded by 8 entries
     bool mfma_fits = false;          // every sub-mesh fits the MFMA kernel's LDS
     // apply buffers
