@@ -36,7 +36,7 @@ import numpy as np  # noqa: E402
 
 FP32_VALU_TF = 157.3    # MI355X FP32 vector peak
 FP64_VALU_TF = 78.6
-FP16_PACKED_TF = 2 * FP32_VALU_TF  # packed FP16 VALU: two lanes per FP32 lane
+FP16_PACKED_TF = FP32_VALU_TF  # packed FP16 VALU: two FP16 lanes per FP32 lane, the packed FP32 rate
 BF16_MFMA_TF = 2500.0   # dense BF16 matrix-core peak
 HBM_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dss_mfma_kernel_c3_bf16_traffic.md")

@@ -18,15 +18,14 @@ constexpr int MFMA_TILE = 32;    // nodes per MFMA tile (the N dimension)
 // whose projections are -inf, so a padded edge contributes ReLU(-inf) = 0.
 constexpr int MFMA_EC = 2;
 
-// Per step: the A operands (8 bf16 per lane, raw bits) of the six 32x16
+// Per step: the A operands (8 values per lane, raw bits) of the six 32x16
 // weight tiles and the lanes' FP32 constants, stored structure-of-arrays
-// ([field][lane]) so that the 64 lanes read consecutive addresses. The kernel
-// copies each step's blob into LDS.
+// ([field][lane]) so that the 64 lanes read consecutive addresses. The tiles
+// are bf16, except the two that multiply the FP16 message sums (fp16).
 enum { A_Q = 0, A_P = 1, A_H = 2, A_SA = 3, A_SB = 4, A_2 = 5, N_ATILES = 6 };
 struct MfmaStep {
-    uint16_t a[N_ATILES][64][8];  // Q', P', Psi hidden from (h,1,c,deg), from sums 0..7, 8..9, Psi output
+    uint16_t a[N_ATILES][64][8];  // Q', P', Psi hidden from (h,1,c,deg), from sums 0..7, 8..9, Psi output (with bias)
     float wn[10][64];             // |d| coefficient of the lane's 10 message units
-    float b2[5][64];              // Psi output bias of the lane's 5 latent components
 };
 static_assert(sizeof(MfmaStep) % 16 == 0, "step blob is copied in 16-byte units");
 

@@ -54,10 +54,13 @@ uint16_t bf16_bits(double v) {
 
 // K-index roles of the B operands (k = 8*hf + m).
 enum Role { H, ONE, XHI, XLO, YHI, YLO, C, DEG, ZERO };
+// Both halves carry the same kinds of entries at m = 5..7, so the kernel
+// builds its B operands without selecting on the half; an entry whose role is
+// ZERO meets a zero weight column.
 Role pq_role(int k, int* hidx) {
     const int hf = k / 8, m = k % 8;
     if (m < 5) { *hidx = 5 * hf + m; return H; }
-    if (hf == 0) return m == 5 ? ONE : (m == 6 ? XHI : XLO);
+    if (hf == 0) return m == 5 ? XHI : (m == 6 ? XLO : ONE);
     return m == 5 ? YHI : (m == 6 ? YLO : ZERO);
 }
 Role psi_role(int k, int* hidx) {
@@ -78,6 +81,13 @@ void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaStep>& steps
     auto put = [&](uint16_t* dst, int lane) {
         const int row = lane % 32, k0 = 8 * (lane / 32);
         for (int m = 0; m < 8; ++m) dst[m] = bf16_bits(A[row * 16 + k0 + m]);
+    };
+    auto put16 = [&](uint16_t* dst, int lane) {  // FP16 operands (the message-sum tiles)
+        const int row = lane % 32, k0 = 8 * (lane / 32);
+        for (int m = 0; m < 8; ++m) {
+            const _Float16 hv = (_Float16)(float)A[row * 16 + k0 + m];
+            std::memcpy(&dst[m], &hv, 2);
+        }
     };
     for (int step = 0; step < kbar; ++step) {
         const float* th = theta + (size_t)step * BLOCK_W;
@@ -154,21 +164,22 @@ void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaStep>& steps
                     A[r * 16 + k] = M[dir][u][w];
                 }
             }
-            for (int lane = 0; lane < 64; ++lane) put(L.a[part == 0 ? A_SA : A_SB][lane], lane);
+            for (int lane = 0; lane < 64; ++lane) put16(L.a[part == 0 ? A_SA : A_SB][lane], lane);
         }
-        // Psi output layer: output rows as hidden units, input k -> hidden unit 5*(k/8) + k%8.
+        // Psi output layer: output rows as latent components, input k -> hidden
+        // unit 5*(k/8) + k%8 for k%8 < 5; k = 5 carries the constant 1 (bias).
         std::fill(A.begin(), A.end(), 0.0);
         for (int r = 0; r < 32; ++r) {
             const int o = hidden_unit(r);
             if (o < 0) continue;
             for (int k = 0; k < 16; ++k)
                 if (k % 8 < 5) A[r * 16 + k] = P2(o, 5 * (k / 8) + k % 8);
+            A[r * 16 + 5] = PB2(o);
         }
         for (int lane = 0; lane < 64; ++lane) put(L.a[A_2][lane], lane);
         for (int lane = 0; lane < 64; ++lane) {
             const int hf = lane / 32;
             for (int t = 0; t < D; ++t) L.wn[t][lane] = (float)W1(hf, t, 2 * D + 2);
-            for (int t = 0; t < 5; ++t) L.b2[t][lane] = (float)PB2(5 * hf + t);
         }
     }
     // Decoder of the last block.
@@ -200,12 +211,20 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
 __device__ inline f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x16 mfma16(const f16x8& a, const f16x8& b, const f32x16& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
 __device__ inline bf16x8 load_a(const uint16_t* p) {
     return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+__device__ inline f16x8 load_a16(const uint16_t* p) {
+    return __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4*>(p));
 }
 
 __device__ inline __bf16 bits_bf16(uint32_t b) { return __builtin_bit_cast(__bf16, (uint16_t)(b & 0xffffu)); }
@@ -225,29 +244,28 @@ __device__ inline double block_sum(double v, double* sh) {
     return sh[MFMA_BLOCK / 64];
 }
 
-// B operand of the P'/Q' products: (h 5 components, then 1, x_hi, x_lo) for
-// hf = 0 and (h 5 components, y_hi, y_lo, 0) for hf = 1.
-__device__ inline bf16x8 b_pq(const float (&h)[5], uint32_t xy2, int hf, bool valid) {
+// B operands. A lane past the end of the sub-mesh feeds finite values (its h
+// stays 0, its tile record is node 0's) into its own output column only, so
+// no entry is masked.
+// P'/Q' products: (h 5 components, coordinate hi, lo, 1): x in half 0, y in half 1.
+__device__ inline bf16x8 b_pq(const float (&h)[5], uint32_t xy2) {
     bf16x8 b;
-    const __bf16 z = (__bf16)0.0f;
-    const __bf16 first = bits_bf16(xy2), second = bits_bf16(xy2 >> 16);
 #pragma unroll
-    for (int m = 0; m < 5; ++m) b[m] = valid ? (__bf16)h[m] : z;
-    b[5] = !valid ? z : (hf == 0 ? (__bf16)1.0f : first);
-    b[6] = !valid ? z : (hf == 0 ? first : second);
-    b[7] = !valid || hf ? z : second;
+    for (int m = 0; m < 5; ++m) b[m] = (__bf16)h[m];
+    b[5] = bits_bf16(xy2);
+    b[6] = bits_bf16(xy2 >> 16);
+    b[7] = (__bf16)1.0f;
     return b;
 }
 
-// B operand of the Psi hidden layer: (h, 1, c, deg) for hf = 0, (h, 0, 0, 0) for hf = 1.
-__device__ inline bf16x8 b_psi(const float (&h)[5], float c, float deg, int hf, bool valid) {
+// Psi hidden layer: (h 5 components, 1, c, deg) (the weight columns of half 1 at m >= 5 are zero).
+__device__ inline bf16x8 b_psi(const float (&h)[5], float c, float deg) {
     bf16x8 b;
-    const __bf16 z = (__bf16)0.0f;
 #pragma unroll
-    for (int m = 0; m < 5; ++m) b[m] = valid ? (__bf16)h[m] : z;
-    b[5] = valid && hf == 0 ? (__bf16)1.0f : z;
-    b[6] = valid && hf == 0 ? (__bf16)c : z;
-    b[7] = valid && hf == 0 ? (__bf16)deg : z;
+    for (int m = 0; m < 5; ++m) b[m] = (__bf16)h[m];
+    b[5] = (__bf16)1.0f;
+    b[6] = (__bf16)c;
+    b[7] = (__bf16)deg;
     return b;
 }
 
@@ -342,7 +360,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                 const bool valid = p < k;
                 const TileNode tn = T[valid ? p : 0];
                 const uint32_t xy2 = hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
-                const f32x16 q = mfma(AQ, b_pq(h[tt], xy2, hf, valid), zero);
+                const f32x16 q = mfma(AQ, b_pq(h[tt], xy2), zero);
                 if (valid) {
                     h2* dst = Qd + (size_t)(hf * (k + 1) + tn.j) * 5;
 #pragma unroll
@@ -366,10 +384,10 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                 const TileNode tn = T[valid ? p : 0];
                 const int j = tn.j;
                 const uint32_t xy2 = hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
-                const f32x16 Pf = mfma(AP, b_pq(h[tt], xy2, hf, valid), zero);
+                const f32x16 Pf = mfma(AP, b_pq(h[tt], xy2), zero);
                 // Psi weights, fetched now so their latency overlaps the edge sums
-                const bf16x8 AH = load_a(L->a[A_H][lane]), ASA = load_a(L->a[A_SA][lane]);
-                const bf16x8 ASB = load_a(L->a[A_SB][lane]), A2 = load_a(L->a[A_2][lane]);
+                const bf16x8 AH = load_a(L->a[A_H][lane]), A2 = load_a(L->a[A_2][lane]);
+                const f16x8 ASA = load_a16(L->a[A_SA][lane]), ASB = load_a16(L->a[A_SB][lane]);
                 h2 P[5], S[5];
 #pragma unroll
                 for (int t = 0; t < 5; ++t) {
@@ -401,29 +419,24 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                             S[t] += __builtin_elementwise_max(__builtin_elementwise_fma(wn[t], nd, P[t] + qq[w][t]), hzero);
                     }
                 }
-                const float c = valid ? cbuf[j] : 0.0f;
-                bf16x8 sa, sb;
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    sa[2 * t] = (__bf16)(float)S[t][0];
-                    sa[2 * t + 1] = (__bf16)(float)S[t][1];
-                }
-                sb[0] = (__bf16)(float)S[4][0];
-                sb[1] = (__bf16)(float)S[4][1];
-#pragma unroll
-                for (int m = 2; m < 8; ++m) sb[m] = (__bf16)0.0f;
-                f32x16 hid = mfma(AH, b_psi(h[tt], c, (float)deg, hf, valid), zero);
-                hid = mfma(ASA, sa, hid);
-                hid = mfma(ASB, sb, hid);
+                const float c = cbuf[j];
+                // The message sums enter the FP16 matrix product as they are.
+                const f16x8 sa = {S[0][0], S[0][1], S[1][0], S[1][1], S[2][0], S[2][1], S[3][0], S[3][1]};
+                const _Float16 hz = (_Float16)0.0f;
+                const f16x8 sb = {S[4][0], S[4][1], hz, hz, hz, hz, hz, hz};
+                f32x16 hid = mfma(AH, b_psi(h[tt], c, (float)deg), zero);
+                hid = mfma16(ASA, sa, hid);
+                hid = mfma16(ASB, sb, hid);
                 bf16x8 bh;
 #pragma unroll
                 for (int m = 0; m < 5; ++m) bh[m] = (__bf16)fmaxf(hid[m], 0.0f);
-#pragma unroll
-                for (int m = 5; m < 8; ++m) bh[m] = (__bf16)0.0f;
+                bh[5] = (__bf16)1.0f;  // output bias column
+                bh[6] = (__bf16)0.0f;
+                bh[7] = (__bf16)0.0f;
                 const f32x16 o = mfma(A2, bh, zero);
                 if (valid) {
 #pragma unroll
-                    for (int t = 0; t < 5; ++t) h[tt][t] = fmaf(a.alpha, o[t] + L->b2[t][lane], h[tt][t]);
+                    for (int t = 0; t < 5; ++t) h[tt][t] = fmaf(a.alpha, o[t], h[tt][t]);
                 }
             }
         }
@@ -441,7 +454,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
         const int p = tile * MFMA_TILE + n;
         const bool valid = p < k;
         const TileNode tn = T[valid ? p : 0];
-        const f32x16 hd = mfma(AD1, b_psi(h[tt], 0.0f, 0.0f, hf, valid), zero);
+        const f32x16 hd = mfma(AD1, b_psi(h[tt], 0.0f, 0.0f), zero);
         bf16x8 bh;
 #pragma unroll
         for (int m = 0; m < 5; ++m) bh[m] = (__bf16)fmaxf(hd[m], 0.0f);
