@@ -20,7 +20,6 @@ constexpr int MAX_M = 4;        // largest FCG truncation supported
 constexpr int VEC_BLOCK = 256;  // threads of the vector kernels
 constexpr int VEC_GRID = 512;   // max workgroups per problem in the vector kernels (each pays a fenced ticket in every reduction)
 constexpr int DSS_BLOCK = 512;  // threads of the VALU DSS kernel
-constexpr int COARSE_ROWS = VEC_BLOCK / 64;  // coarse rows per workgroup (one per wavefront)
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
 // Krylov scalars of one problem, resident in device memory.
@@ -66,7 +65,7 @@ struct DevProb {
     const int32_t* edge_ptr;    // per slot, in-edge range (global edge index)
     const uint16_t* edge_src;   // per edge, sender local id; padded by 8 entries
     const float* edge_nd;       // per edge, |d_jl|; padded by 8 entries
-    const uint32_t* erec;       // per node of each sub-mesh, its in-edges (sender | FP16 |d_jl| << 16)
+    const uint32_t* erec;       // per node of each sub-mesh, its in-edges (FP16 |d_jl| | 20 * sender << 16)
                                 // padded with sentinel records (sender k_i, |d| 0) to a multiple of MFMA_EC
     const int32_t* epad_sub;    // [K + 1] range of each sub-mesh in erec
     const TileNode* tiles;      // per slot position in tile order (e0 indexes erec)
@@ -91,8 +90,8 @@ struct DevProb {
     double* hg64;               // FP64 DSS latent state
     float* qg32;
     KState* st;                 // null: no Krylov scalars, no done flag
-    double* partials;           // (MAX_M + 1) x VEC_GRID
-    unsigned* counter;          // zero between launches
+    double* partials;           // (MAX_M + 1) x VEC_GRID per-workgroup partial sums
+    unsigned* counter;          // unused by the solve kernels (kept zero)
     double rtol;                // read by the init kernel
     int max_it;
     int n;
@@ -124,12 +123,14 @@ hipError_t launch_dss_valu(const DevProb* tab, const int2* work, int n_work, int
                            double alpha, int apply, const float* theta32, const double* theta64, size_t shmem,
                            hipStream_t s, bool check);
 hipError_t launch_coarse(const DevProb* tab, const int2* rows, int n_rows, hipStream_t s, bool check);
-hipError_t launch_prolong(const DevProb* tab, const int2* blk, int n_blk, const IterArgs& it, hipStream_t s,
-                          bool check);
-hipError_t launch_krylov(const DevProb* tab, const int2* blk, int n_blk, const IterArgs& it, hipStream_t s,
-                         bool check);
-hipError_t launch_init(const DevProb* tab, const int2* blk, int n_blk, hipStream_t s);
-hipError_t launch_resid(const DevProb* tab, const int2* blk, int n_blk, hipStream_t s);
+// The Krylov launchers end with a finalize launch of one workgroup per
+// problem: n_prob = all problems of the table, or the problems of `list`.
+hipError_t launch_prolong(const DevProb* tab, const int2* blk, int n_blk, int n_prob, const IterArgs& it,
+                          hipStream_t s, bool check);
+hipError_t launch_krylov(const DevProb* tab, const int2* blk, int n_blk, int n_prob, const IterArgs& it,
+                         hipStream_t s, bool check);
+hipError_t launch_init(const DevProb* tab, const int2* blk, int n_blk, const int* list, int n_list, hipStream_t s);
+hipError_t launch_resid(const DevProb* tab, const int2* blk, int n_blk, const int* list, int n_list, hipStream_t s);
 hipError_t launch_gather_states(const DevProb* tab, int n, KState* out, hipStream_t s);
 hipError_t launch_spmv(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, double* y,
                        int n, hipStream_t s);

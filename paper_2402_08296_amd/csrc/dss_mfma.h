@@ -18,6 +18,13 @@ constexpr int MFMA_TILE = 32;    // nodes per MFMA tile (the N dimension)
 // whose projections are -inf, so a padded edge contributes ReLU(-inf) = 0.
 constexpr int MFMA_EC = 2;
 
+// Edge record of the MFMA kernel: FP16 bits of |d_jl| in the low half, the
+// byte offset of the sender's row in a direction's Q' array (5 dwords per
+// row) in the high half.
+inline uint32_t mfma_edge_record(int sender, uint16_t nd_fp16_bits) {
+    return (uint32_t)nd_fp16_bits | ((uint32_t)(sender * 20) << 16);
+}
+
 // Per step: the A operands (8 values per lane, raw bits) of the six 32x16
 // weight tiles and the lanes' FP32 constants, stored structure-of-arrays
 // ([field][lane]) so that the 64 lanes read consecutive addresses. The tiles

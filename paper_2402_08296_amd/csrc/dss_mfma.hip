@@ -279,8 +279,10 @@ __device__ inline h2 pk(float x, float y) { return (h2){(_Float16)x, (_Float16)y
 //                  direction, row k the -inf sentinel; the odd 5-dword row
 //                  stride spreads the random sender rows of an edge gather
 //                  over all LDS banks
-//   E   [ne_pad]   in-edges of each node, padded to a multiple of EC with
-//                  sentinel records: sender id | FP16 |d| << 16
+//   E   [ne_pad]   in-edge records per tile, slot-major ([slot][lane], so a
+//                  wavefront reads consecutive dwords), padded with sentinel
+//                  records to the tile's largest in-degree rounded up to EC:
+//                  FP16 |d| | sender row byte offset << 16
 //   T   [k]        tile records (node id, degree, first edge, split coordinates)
 // The message sums run in packed FP16 (two units per instruction).
 __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                 if (tile >= ntiles) break;
                 const int p = tile * MFMA_TILE + n;
                 const bool valid = p < k;
-                const TileNode tn = T[valid ? p : 0];
+                const TileNode tn = T[valid ? p : tile * MFMA_TILE];
                 const uint32_t xy2 = hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
                 const f32x16 q = mfma(AQ, b_pq(h[tt], xy2), zero);
                 if (valid) {
@@ -381,7 +383,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                 if (tile >= ntiles) break;
                 const int p = tile * MFMA_TILE + n;
                 const bool valid = p < k;
-                const TileNode tn = T[valid ? p : 0];
+                const TileNode tn = T[valid ? p : tile * MFMA_TILE];  // past the end: the tile's first node
                 const int j = tn.j;
                 const uint32_t xy2 = hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
                 const f32x16 Pf = mfma(AP, b_pq(h[tt], xy2), zero);
@@ -395,24 +397,24 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                     S[t] = hzero;
                 }
                 const int deg = valid ? (int)tn.deg : 0;
-                const int e0 = tn.e0 - ebase, nch = (deg + EC - 1) / EC;
-                // Chunks of EC padded edge records as straight-line code: all LDS
-                // reads of a chunk are issued before its sums.
+                // The tile's edge block: EC slots per chunk, one column per lane
+                // (lanes past the end of the sub-mesh read sentinel records).
+                const uint32_t* Et = E + (tn.e0 & 0xffffff) + n;
+                const int nch = __builtin_amdgcn_readfirstlane((int)((uint32_t)tn.e0 >> 24));
                 for (int ch = 0; ch < nch; ++ch) {
-                    const int e = e0 + ch * EC;
                     uint32_t rec[EC];
 #pragma unroll
-                    for (int w = 0; w < EC; ++w) rec[w] = E[e + w];
+                    for (int w = 0; w < EC; ++w) rec[w] = Et[(ch * EC + w) * MFMA_TILE];
                     h2 qq[EC][5];
 #pragma unroll
                     for (int w = 0; w < EC; ++w) {
-                        const h2* q = Qh + (rec[w] & 0xffffu) * 5;
+                        const h2* q = reinterpret_cast<const h2*>(reinterpret_cast<const char*>(Qh) + (rec[w] >> 16));
 #pragma unroll
                         for (int t = 0; t < 5; ++t) qq[w][t] = q[t];
                     }
 #pragma unroll
                     for (int w = 0; w < EC; ++w) {
-                        const _Float16 ndh = __builtin_bit_cast(_Float16, (uint16_t)(rec[w] >> 16));
+                        const _Float16 ndh = __builtin_bit_cast(_Float16, (uint16_t)(rec[w] & 0xffffu));
                         const h2 nd = {ndh, ndh};
 #pragma unroll
                         for (int t = 0; t < 5; ++t)
@@ -453,7 +455,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
         if (tile >= ntiles) break;
         const int p = tile * MFMA_TILE + n;
         const bool valid = p < k;
-        const TileNode tn = T[valid ? p : 0];
+        const TileNode tn = T[valid ? p : tile * MFMA_TILE];
         const f32x16 hd = mfma(AD1, b_psi(h[tt], 0.0f, 0.0f), zero);
         bf16x8 bh;
 #pragma unroll

@@ -36,6 +36,9 @@ constexpr int BLOCK_W = OFF_DE + D * D + D + D + 1;  // 11 d^2 + 15 d + 1
 static_assert(BLOCK_W == 1251, "weight block size");
 constexpr int DSS_NPT = (kMaxSubNodes + DSS_BLOCK - 1) / DSS_BLOCK;
 
+// Which reduction a finalize launch completes.
+enum FinStage { FIN_PROLONG, FIN_SPMV, FIN_UPDATE, FIN_INIT, FIN_RESID };
+
 // ------------------------------------------------------------------ reductions
 // Deterministic: fixed shuffle tree inside a wave, fixed order across waves,
 // fixed order across workgroups (the last workgroup of a problem sums its
@@ -110,6 +113,29 @@ __device__ bool grid_sum(const double (&v)[NV], double* partials, unsigned* coun
     block_sum_n<NV, BLOCK>(out, sh);
     if (threadIdx.x == 0) *counter = 0u;
     return true;
+}
+
+// Two-kernel reductions of the Krylov iteration: every workgroup of a large
+// kernel stores its partial sums with plain stores (no fence, no shared
+// counter), and a finalize kernel with one workgroup per problem sums them in
+// a fixed order after the large kernel has ended (the kernel boundary makes
+// the stores visible). The sums therefore do not depend on which workgroup
+// finishes last, nor on the other problems of the launch.
+template <int NV>
+__device__ inline void put_partials(double (&v)[NV], double* partials, int lb) {
+    __shared__ double sh[NV * (VEC_BLOCK / 64)];
+    block_sum_n<NV, VEC_BLOCK>(v, sh);
+    if (threadIdx.x == 0)
+        for (int i = 0; i < NV; ++i) partials[i * VEC_GRID + lb] = v[i];
+}
+
+template <int NV>
+__device__ inline void sum_partials(const double* __restrict__ partials, int nb, double (&out)[NV]) {
+    __shared__ double sh[NV * (VEC_BLOCK / 64)];
+    for (int i = 0; i < NV; ++i) out[i] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += VEC_BLOCK)
+        for (int i = 0; i < NV; ++i) out[i] += partials[i * VEC_GRID + b];
+    block_sum_n<NV, VEC_BLOCK>(out, sh);
 }
 
 // Work item of a vector-kernel workgroup: its problem and local workgroup.
@@ -409,22 +435,27 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
 }
 
 // ------------------------------------------------------------------ coarse solve
-// y = A0inv y0, one wavefront per row; work item = (problem, first row).
+// y = A0inv y0: one workgroup per row (work item = (problem, row)), its four
+// wavefronts over interleaved column segments, combined in a fixed order.
 __global__ __launch_bounds__(VEC_BLOCK) void coarse_kernel(const DevProb* __restrict__ tab,
                                                           const int2* __restrict__ rows) {
     const int2 w = rows[blockIdx.x];
     const DevProb& P = tab[w.x];
     if (P.st && P.st->done) return;
-    const int row = w.y + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int K = P.K;
-    if (row >= K) return;
+    __shared__ double sh[VEC_BLOCK / 64];
+    const int row = w.y, K = P.K;
     const double* __restrict__ a = P.a0inv + (size_t)row * K;
     const double* __restrict__ y0 = P.y0;
     double acc = 0.0;
-    for (int j = lane; j < K; j += 64) acc = fma(a[j], y0[j], acc);
+    for (int j = threadIdx.x; j < K; j += VEC_BLOCK) acc = fma(a[j], y0[j], acc);
     acc = wave_sum(acc);
-    if (lane == 0) P.y[row] = acc;
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < VEC_BLOCK / 64; ++i) t += sh[i];
+        P.y[row] = t;
+    }
 }
 
 // ------------------------------------------------------------------ prolong + dots
@@ -473,7 +504,6 @@ __global__ __launch_bounds__(VEC_BLOCK) void prolong_kernel(const DevProb* __res
     const DevProb& P = *g.P;
     KState* st = P.st;
     if (st && st->done) return;
-    __shared__ double sh[VEC_BLOCK / 64 + 1];
     const int mode = st ? ia.mode : -1;
     const int m = ia.m;
     const int it = st ? st->it : 0;
@@ -495,18 +525,7 @@ __global__ __launch_bounds__(VEC_BLOCK) void prolong_kernel(const DevProb* __res
         prolong_rows<-1>(P.node_ptr, P.node_slots, P.slot_sub, P.weights, P.local, y, P.dirichlet, P.r, P.z,
                          nullptr, nullptr, nullptr, nullptr, m, uw, i0, stride, P.n, dots);
     if (mode < 0) return;
-    double tot[MAX_M + 1];
-    if (!grid_sum<MAX_M + 1, VEC_BLOCK>(dots, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
-    if (threadIdx.x != 0) return;
-    if (mode == DDMGNN_FCG) {
-        // p_new = z - sum_k (<z, q_k> / <p_k, q_k>) p_k
-        for (int i = 0; i < MAX_M; ++i) st->beta[i] = i < m ? -tot[i] / st->pq[ring_prev(it, m, i)] : 0.0;
-    } else {
-        // Algorithm 1: beta = rho_{i+1} / rho_i, p = z + beta p
-        const double rho_new = tot[0];
-        st->beta[0] = it == 0 ? 0.0 : rho_new / st->rho;
-        st->rho = rho_new;
-    }
+    put_partials<MAX_M + 1>(dots, P.partials, g.lb);
 }
 
 // ------------------------------------------------------------------ Krylov kernels
@@ -574,14 +593,11 @@ __global__ __launch_bounds__(VEC_BLOCK) void spmv_dots_kernel(const DevProb* __r
     const DevProb& P = *g.P;
     KState* st = P.st;
     if (st->done) return;
-    __shared__ double sh[VEC_BLOCK / 64 + 1];
     const int slot = ring_cur(st->it, ia.m);
     double d[2] = {0.0, 0.0};
     spmv_dots_rows(P.rowptr, P.col, P.val, P.p[slot], P.q[slot], P.r, g.lb * VEC_BLOCK + threadIdx.x,
                    P.nblk * VEC_BLOCK, P.n, d);
-    double tot[2];
-    if (!grid_sum<2, VEC_BLOCK>(d, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
-    if (threadIdx.x == 0) set_alpha(st, tot, ia.mode, slot);
+    put_partials<2>(d, P.partials, g.lb);
 }
 
 __device__ __forceinline__ void spmv_p_dots_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -613,15 +629,12 @@ __global__ __launch_bounds__(VEC_BLOCK) void spmv_p_dots_kernel(const DevProb* _
     const DevProb& P = *g.P;
     KState* st = P.st;
     if (st->done) return;
-    __shared__ double sh[VEC_BLOCK / 64 + 1];
     const int it = st->it;
     const int slot = ring_cur(it, 1);
     double d[2] = {0.0, 0.0};
     spmv_p_dots_rows(P.rowptr, P.col, P.val, dir_src(P, ia.mode), P.p[ring_prev(it, 1, 0)], P.p[slot], P.q[slot],
                      P.r, st->beta[0], g.lb * VEC_BLOCK + threadIdx.x, P.nblk * VEC_BLOCK, P.n, d);
-    double tot[2];
-    if (!grid_sum<2, VEC_BLOCK>(d, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
-    if (threadIdx.x == 0) set_alpha(st, tot, ia.mode, slot);
+    put_partials<2>(d, P.partials, g.lb);
 }
 
 __device__ __forceinline__ void update_rows(double* __restrict__ u, double* __restrict__ r,
@@ -642,27 +655,11 @@ __global__ __launch_bounds__(VEC_BLOCK) void update_kernel(const DevProb* __rest
     const DevProb& P = *g.P;
     KState* st = P.st;
     if (st->done) return;
-    __shared__ double sh[VEC_BLOCK / 64 + 1];
     const int slot = ring_cur(st->it, ia.m);
     double d[1] = {0.0};
     update_rows(P.u, P.r, P.p[slot], P.q[slot], st->alpha, g.lb * VEC_BLOCK + threadIdx.x, P.nblk * VEC_BLOCK, P.n,
                 d);
-    double tot[1];
-    if (!grid_sum<1, VEC_BLOCK>(d, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
-    if (threadIdx.x != 0) return;
-    const double rr = tot[0];
-    st->it += 1;
-    if (!isfinite(rr)) {
-        st->status = DDMGNN_E_NONFINITE;
-        st->done = 1;
-        return;
-    }
-    st->rel = sqrt(rr) / st->r0n;
-    if (ia.mode == DDMGNN_CG) {  // M = I: rho = <r, r>, beta = rho_new / rho_old
-        st->beta[0] = rr / st->rho;
-        st->rho = rr;
-    }
-    if (st->rel <= st->rtol || st->it >= st->max_it) st->done = 1;
+    put_partials<1>(d, P.partials, g.lb);
 }
 
 __device__ __forceinline__ void residual_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
@@ -684,8 +681,6 @@ __global__ __launch_bounds__(VEC_BLOCK) void init_kernel(const DevProb* __restri
                                                         const int2* __restrict__ blk) {
     const Seg g = seg(tab, blk);
     const DevProb& P = *g.P;
-    KState* st = P.st;
-    __shared__ double sh[VEC_BLOCK / 64 + 1];
     const int i0 = g.lb * VEC_BLOCK + threadIdx.x, stride = P.nblk * VEC_BLOCK;
     double d[1] = {0.0};
     residual_rows(P.rowptr, P.col, P.val, P.b, P.u0, P.u, P.r, i0, stride, P.n, d);
@@ -697,21 +692,7 @@ __global__ __launch_bounds__(VEC_BLOCK) void init_kernel(const DevProb* __restri
             qk[i] = 0.0;
         }
     }
-    double tot[1];
-    if (!grid_sum<1, VEC_BLOCK>(d, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
-    if (threadIdx.x != 0) return;
-    st->r0n = sqrt(tot[0]);
-    st->rtol = P.rtol;
-    st->rel = tot[0] == 0.0 ? 0.0 : 1.0;
-    st->alpha = 0.0;
-    for (int i = 0; i < MAX_M; ++i) st->beta[i] = 0.0;
-    for (int i = 0; i <= MAX_M; ++i) st->pq[i] = 1.0;
-    st->rho = tot[0];
-    st->rr_true = 0.0;
-    st->it = 0;
-    st->max_it = P.max_it;
-    st->status = isfinite(tot[0]) ? 0 : DDMGNN_E_NONFINITE;
-    st->done = (tot[0] == 0.0 || !isfinite(tot[0]) || P.max_it <= 0) ? 1 : 0;
+    put_partials<1>(d, P.partials, g.lb);
 }
 
 // |b - A u|^2 of each problem into its state.
@@ -719,13 +700,77 @@ __global__ __launch_bounds__(VEC_BLOCK) void resid_kernel(const DevProb* __restr
                                                          const int2* __restrict__ blk) {
     const Seg g = seg(tab, blk);
     const DevProb& P = *g.P;
-    __shared__ double sh[VEC_BLOCK / 64 + 1];
     double d[1] = {0.0};
     residual_rows(P.rowptr, P.col, P.val, P.b, P.u, nullptr, nullptr, g.lb * VEC_BLOCK + threadIdx.x,
                   P.nblk * VEC_BLOCK, P.n, d);
-    double tot[1];
-    if (!grid_sum<1, VEC_BLOCK>(d, P.partials, P.counter, g.lb, P.nblk, tot, sh)) return;
-    if (threadIdx.x == 0) P.st->rr_true = tot[0];
+    put_partials<1>(d, P.partials, g.lb);
+}
+
+// Scalar recurrences of one problem from the partial sums of the preceding
+// large kernel; one workgroup per problem (list[blockIdx.x], or blockIdx.x).
+__global__ __launch_bounds__(VEC_BLOCK) void finalize_kernel(const DevProb* __restrict__ tab,
+                                                            const int* __restrict__ list, int stage, IterArgs ia) {
+    const DevProb& P = tab[list ? list[blockIdx.x] : blockIdx.x];
+    KState* st = P.st;
+    const bool always = stage == FIN_INIT || stage == FIN_RESID;
+    if (!always && st->done) return;
+    const bool t0 = threadIdx.x == 0;
+    if (stage == FIN_PROLONG) {
+        double tot[MAX_M + 1];
+        sum_partials<MAX_M + 1>(P.partials, P.nblk, tot);
+        if (!t0) return;
+        const int it = st->it, m = ia.m;
+        if (ia.mode == DDMGNN_FCG) {
+            // p_new = z - sum_k (<z, q_k> / <p_k, q_k>) p_k
+            for (int i = 0; i < MAX_M; ++i) st->beta[i] = i < m ? -tot[i] / st->pq[ring_prev(it, m, i)] : 0.0;
+        } else {
+            // Algorithm 1: beta = rho_{i+1} / rho_i, p = z + beta p
+            const double rho_new = tot[0];
+            st->beta[0] = it == 0 ? 0.0 : rho_new / st->rho;
+            st->rho = rho_new;
+        }
+    } else if (stage == FIN_SPMV) {
+        double tot[2];
+        sum_partials<2>(P.partials, P.nblk, tot);
+        if (t0) set_alpha(st, tot, ia.mode, ring_cur(st->it, ia.m));
+    } else if (stage == FIN_UPDATE) {
+        double tot[1];
+        sum_partials<1>(P.partials, P.nblk, tot);
+        if (!t0) return;
+        const double rr = tot[0];
+        st->it += 1;
+        if (!isfinite(rr)) {
+            st->status = DDMGNN_E_NONFINITE;
+            st->done = 1;
+            return;
+        }
+        st->rel = sqrt(rr) / st->r0n;
+        if (ia.mode == DDMGNN_CG) {  // M = I: rho = <r, r>, beta = rho_new / rho_old
+            st->beta[0] = rr / st->rho;
+            st->rho = rr;
+        }
+        if (st->rel <= st->rtol || st->it >= st->max_it) st->done = 1;
+    } else if (stage == FIN_INIT) {
+        double tot[1];
+        sum_partials<1>(P.partials, P.nblk, tot);
+        if (!t0) return;
+        st->r0n = sqrt(tot[0]);
+        st->rtol = P.rtol;
+        st->rel = tot[0] == 0.0 ? 0.0 : 1.0;
+        st->alpha = 0.0;
+        for (int i = 0; i < MAX_M; ++i) st->beta[i] = 0.0;
+        for (int i = 0; i <= MAX_M; ++i) st->pq[i] = 1.0;
+        st->rho = tot[0];
+        st->rr_true = 0.0;
+        st->it = 0;
+        st->max_it = P.max_it;
+        st->status = isfinite(tot[0]) ? 0 : DDMGNN_E_NONFINITE;
+        st->done = (tot[0] == 0.0 || !isfinite(tot[0]) || P.max_it <= 0) ? 1 : 0;
+    } else {  // FIN_RESID
+        double tot[1];
+        sum_partials<1>(P.partials, P.nblk, tot);
+        if (t0) st->rr_true = tot[0];
+    }
 }
 
 // Plain y = A x and a deterministic dot (entry points outside the solve).
@@ -796,31 +841,39 @@ hipError_t launch_coarse(const DevProb* tab, const int2* rows, int n_rows, hipSt
     return done(check);
 }
 
-hipError_t launch_prolong(const DevProb* tab, const int2* blk, int n_blk, const IterArgs& it, hipStream_t s,
-                          bool check) {
+hipError_t launch_prolong(const DevProb* tab, const int2* blk, int n_blk, int n_prob, const IterArgs& it,
+                          hipStream_t s, bool check) {
     hipLaunchKernelGGL(prolong_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    if (it.mode >= 0)
+        hipLaunchKernelGGL(finalize_kernel, dim3(n_prob), dim3(VEC_BLOCK), 0, s, tab, (const int*)nullptr,
+                           (int)FIN_PROLONG, it);
     return done(check);
 }
 
-hipError_t launch_krylov(const DevProb* tab, const int2* blk, int n_blk, const IterArgs& it, hipStream_t s,
-                         bool check) {
+hipError_t launch_krylov(const DevProb* tab, const int2* blk, int n_blk, int n_prob, const IterArgs& it,
+                         hipStream_t s, bool check) {
+    const int* all = nullptr;
     if (it.m == 1) {
         hipLaunchKernelGGL(spmv_p_dots_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
     } else {
         hipLaunchKernelGGL(pupdate_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
         hipLaunchKernelGGL(spmv_dots_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
     }
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_prob), dim3(VEC_BLOCK), 0, s, tab, all, (int)FIN_SPMV, it);
     hipLaunchKernelGGL(update_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_prob), dim3(VEC_BLOCK), 0, s, tab, all, (int)FIN_UPDATE, it);
     return done(check);
 }
 
-hipError_t launch_init(const DevProb* tab, const int2* blk, int n_blk, hipStream_t s) {
+hipError_t launch_init(const DevProb* tab, const int2* blk, int n_blk, const int* list, int n_list, hipStream_t s) {
     hipLaunchKernelGGL(init_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk);
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_list), dim3(VEC_BLOCK), 0, s, tab, list, (int)FIN_INIT, IterArgs{});
     return hipGetLastError();
 }
 
-hipError_t launch_resid(const DevProb* tab, const int2* blk, int n_blk, hipStream_t s) {
+hipError_t launch_resid(const DevProb* tab, const int2* blk, int n_blk, const int* list, int n_list, hipStream_t s) {
     hipLaunchKernelGGL(resid_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk);
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_list), dim3(VEC_BLOCK), 0, s, tab, list, (int)FIN_RESID, IterArgs{});
     return hipGetLastError();
 }
 

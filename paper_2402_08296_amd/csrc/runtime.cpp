@@ -38,10 +38,12 @@ struct Batch {
     int max_k_all = 0, max_k_rest = 0;
     DevBuf<int2> vec_blk;              // (problem, local workgroup)
     int n_vec = 0;
-    DevBuf<int2> coarse_rows;          // (problem, first of COARSE_ROWS rows)
+    DevBuf<int2> coarse_rows;          // (problem, row)
     int n_coarse = 0;
     DevBuf<int2> sub_blk;              // subset of vec_blk (init and residual of some problems)
     int n_sub_blk = 0;
+    DevBuf<int> sub_list;              // the problems of that subset (their finalize workgroups)
+    int n_sub_list = 0;
     DevBuf<KState> st_gather;
     KState* host_st = nullptr;         // pinned, one per problem
     hipGraphExec_t graph = nullptr;    // captured chunk of iterations
@@ -179,7 +181,7 @@ int enqueue_apply(Batch& B, const DevProb* tab, const ddmgnn_solve_opts& o, int 
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     if (o.coarse) HIP_TRY(launch_coarse(tab, B.coarse_rows.p, B.n_coarse, s, !capturing));
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-    HIP_TRY(launch_prolong(tab, B.vec_blk.p, B.n_vec, iter_args(o, mode), s, !capturing));
+    HIP_TRY(launch_prolong(tab, B.vec_blk.p, B.n_vec, (int)B.probs.size(), iter_args(o, mode), s, !capturing));
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     return DDMGNN_OK;
 }
@@ -196,7 +198,7 @@ int enqueue_iteration(Batch& B, const ddmgnn_solve_opts& o, hipEvent_t* ev, bool
     } else {
         if (int rc = enqueue_apply(B, B.tab.p, o, mode, ev, capturing)) return rc;
     }
-    HIP_TRY(launch_krylov(B.tab.p, B.vec_blk.p, B.n_vec, iter_args(o, mode), s, !capturing));
+    HIP_TRY(launch_krylov(B.tab.p, B.vec_blk.p, B.n_vec, (int)B.probs.size(), iter_args(o, mode), s, !capturing));
     if (ev) HIP_TRY(hipEventRecord(ev[4], s));
     return DDMGNN_OK;
 }
@@ -247,15 +249,19 @@ int upload_table(Batch& B) {
     return upload_list(B.tab, B.views, B.ctx->stream);
 }
 
-// Workgroup list of the problems flagged in `which`.
+// Workgroup list and problem list of the problems flagged in `which`.
 int upload_subset(Batch& B, const std::vector<uint8_t>* which) {
     std::vector<int2> sub;
+    std::vector<int> list;
     for (size_t i = 0; i < B.probs.size(); ++i) {
         if (which && !(*which)[i]) continue;
+        list.push_back((int)i);
         const int nb = vec_blocks(B.probs[i]->hs.n);
         for (int b = 0; b < nb; ++b) sub.push_back(make_int2((int)i, b));
     }
     B.n_sub_blk = (int)sub.size();
+    B.n_sub_list = (int)list.size();
+    if (int rc = upload_list(B.sub_list, list, B.ctx->stream)) return rc;
     return upload_list(B.sub_blk, sub, B.ctx->stream);
 }
 
@@ -287,7 +293,7 @@ int solve_batch(ddmgnn_ctx* ctx, Batch& B, const ddmgnn_solve_opts& o, double* c
     } guard{ev0, ev1, {}};
     if (int rc = batch_begin(B, o, nullptr)) return rc;
     HIP_TRY(hipEventRecord(ev0, s));
-    HIP_TRY(launch_init(B.tab.p, B.vec_blk.p, B.n_vec, s));
+    HIP_TRY(launch_init(B.tab.p, B.vec_blk.p, B.n_vec, nullptr, nb, s));
     // Iterations between host polls of the converged flags; a captured chunk
     // is replayed as a whole (problems that finish inside it idle).
     const int check = std::max(1, o.check_every);
@@ -396,7 +402,7 @@ int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& 
         for (int j = 0; j < P->hs.K; ++j) all.push_back({(int)(sp[j + 1] - sp[j]), i, j});
         const int nb = vec_blocks(P->hs.n);
         for (int b = 0; b < nb; ++b) vec.push_back(make_int2(i, b));
-        for (int r = 0; r < P->hs.K; r += COARSE_ROWS) rows.push_back(make_int2(i, r));
+        for (int r = 0; r < P->hs.K; ++r) rows.push_back(make_int2(i, r));
     }
     // Largest sub-meshes first (a deterministic order: size, then problem, then sub-mesh).
     std::stable_sort(all.begin(), all.end(), [](const W& a, const W& b) {
@@ -447,7 +453,8 @@ int batch_begin(Batch& B, const ddmgnn_solve_opts& o, const std::vector<uint8_t>
     if (int rc = upload_table(B)) return rc;
     if (init) {
         if (int rc = upload_subset(B, init)) return rc;
-        if (B.n_sub_blk) HIP_TRY(launch_init(B.tab.p, B.sub_blk.p, B.n_sub_blk, B.ctx->stream));
+        if (B.n_sub_blk)
+            HIP_TRY(launch_init(B.tab.p, B.sub_blk.p, B.n_sub_blk, B.sub_list.p, B.n_sub_list, B.ctx->stream));
     }
     return DDMGNN_OK;
 }
@@ -480,9 +487,10 @@ ddmgnn_problem* batch_problem(const Batch& B, int i) { return B.probs[i]; }
 int batch_true_residual(Batch& B, const std::vector<uint8_t>* which) {
     if (which) {
         if (int rc = upload_subset(B, which)) return rc;
-        if (B.n_sub_blk) HIP_TRY(launch_resid(B.tab.p, B.sub_blk.p, B.n_sub_blk, B.ctx->stream));
+        if (B.n_sub_blk)
+            HIP_TRY(launch_resid(B.tab.p, B.sub_blk.p, B.n_sub_blk, B.sub_list.p, B.n_sub_list, B.ctx->stream));
     } else {
-        HIP_TRY(launch_resid(B.tab.p, B.vec_blk.p, B.n_vec, B.ctx->stream));
+        HIP_TRY(launch_resid(B.tab.p, B.vec_blk.p, B.n_vec, nullptr, (int)B.probs.size(), B.ctx->stream));
     }
     return batch_poll(B);
 }
@@ -567,41 +575,52 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
     HIP_TRY(P->xyc32.upload(xyc32.data(), 2 * sk, s));
     HIP_TRY(P->a0inv.upload(hs.a0inv.data(), (size_t)K * K, s));
     {
-        // MFMA kernel records: each node's in-edges padded to a multiple of
-        // MFMA_EC with sentinel records (sender k_i, |d| 0), and the tile
-        // records pointing at them.
+        // MFMA kernel records, per tile of MFMA_TILE nodes (tile order): slot-major
+        // [slot][lane] blocks padded with sentinel records (sender k_i, |d| 0)
+        // to the tile's largest in-degree rounded up to MFMA_EC. Tile records
+        // hold the block's offset in the sub-mesh (low 24 bits) and its number
+        // of MFMA_EC-slot chunks (high 8 bits).
         std::vector<uint32_t> er;
-        er.reserve((size_t)hs.n_edges + (size_t)sk * (MFMA_EC - 1));
-        std::vector<int32_t> epad(K + 1, 0), e0pad(sk, 0);
+        er.reserve((size_t)hs.n_edges * 2 + 1);
+        std::vector<int32_t> epad(K + 1, 0);
+        std::vector<TileNode> tiles(sk);
         size_t need = 0;
         for (int i = 0; i < K; ++i) {
             const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
+            const int k = (int)(e - b);
             epad[i] = (int32_t)er.size();
-            for (int64_t slot = b; slot < e; ++slot) {
-                e0pad[slot] = (int32_t)er.size();
-                for (int64_t t = hs.edge_ptr[slot]; t < hs.edge_ptr[slot + 1]; ++t) er.push_back(hs.erec[t]);
-                while ((er.size() - e0pad[slot]) % MFMA_EC) er.push_back((uint32_t)(e - b));
+            for (int t0 = 0; t0 < k; t0 += MFMA_TILE) {
+                const int t1 = std::min(k, t0 + MFMA_TILE);
+                int maxdeg = 0;
+                for (int q = t0; q < t1; ++q) {
+                    const int64_t slot = b + hs.tnode[b + q];
+                    maxdeg = std::max<int>(maxdeg, (int)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]));
+                }
+                const int nch = (maxdeg + MFMA_EC - 1) / MFMA_EC;
+                const size_t off = er.size() - epad[i];
+                if (nch > 255 || off + (size_t)nch * MFMA_EC * MFMA_TILE >= (1u << 24))
+                    return fail(DDMGNN_E_INVALID, "sub-mesh edge block too large for the MFMA tile records");
+                er.resize(er.size() + (size_t)nch * MFMA_EC * MFMA_TILE, mfma_edge_record(k, 0));
+                for (int q = t0; q < t1; ++q) {
+                    const int32_t j = hs.tnode[b + q];
+                    const int64_t slot = b + j;
+                    for (int64_t t = hs.edge_ptr[slot]; t < hs.edge_ptr[slot + 1]; ++t)
+                        er[epad[i] + off + (size_t)(t - hs.edge_ptr[slot]) * MFMA_TILE + (q - t0)] =
+                            mfma_edge_record(hs.edge_src[t], (uint16_t)(hs.erec[t] >> 16));
+                    TileNode& tn = tiles[b + q];
+                    tn.e0 = (int32_t)((uint32_t)off | ((uint32_t)nch << 24));
+                    tn.j = (uint16_t)j;
+                    tn.deg = (uint16_t)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]);
+                    tn.xh = hs.xyhl[4 * slot + 0];
+                    tn.xl = hs.xyhl[4 * slot + 1];
+                    tn.yh = hs.xyhl[4 * slot + 2];
+                    tn.yl = hs.xyhl[4 * slot + 3];
+                }
             }
-            need = std::max(need, mfma_lds_need((int)(e - b), (int64_t)er.size() - epad[i]));
+            need = std::max(need, mfma_lds_need(k, (int64_t)er.size() - epad[i]));
         }
         epad[K] = (int32_t)er.size();
         P->mfma_fits = need <= MFMA_LDS_LIMIT;
-        std::vector<TileNode> tiles(sk);
-        for (int i = 0; i < K; ++i) {
-            const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
-            for (int64_t q = b; q < e; ++q) {
-                const int32_t j = hs.tnode[q];
-                const int64_t slot = b + j;
-                TileNode& t = tiles[q];
-                t.e0 = e0pad[slot];
-                t.j = (uint16_t)j;
-                t.deg = (uint16_t)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]);
-                t.xh = hs.xyhl[4 * slot + 0];
-                t.xl = hs.xyhl[4 * slot + 1];
-                t.yh = hs.xyhl[4 * slot + 2];
-                t.yl = hs.xyhl[4 * slot + 3];
-            }
-        }
         HIP_TRY(P->tiles.upload(tiles.data(), tiles.size(), s));
         HIP_TRY(P->erec.upload(er.data(), std::max<size_t>(er.size(), 1), s));
         HIP_TRY(P->epad_sub.upload(epad.data(), epad.size(), s));
