@@ -270,6 +270,17 @@ __device__ inline bf16x8 b_psi(const float (&h)[5], float c, float deg) {
 }
 
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU of a bf16 pair as a signed 16-bit max with 0: bf16 is sign-magnitude,
+// so negative values (and -0) are negative as integers and positive values
+// keep their order; equals rounding ReLU(x) to bf16.
+__device__ inline uint32_t bf16_relu2(float lo, float hi) {
+    const bf16x2 v = {(__bf16)lo, (__bf16)hi};
+    const i16x2 r = __builtin_elementwise_max(__builtin_bit_cast(i16x2, v), (i16x2){0, 0});
+    return __builtin_bit_cast(uint32_t, r);
+}
 
 __device__ inline h2 pk(float x, float y) { return (h2){(_Float16)x, (_Float16)y}; }
 
@@ -429,12 +440,9 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                 f32x16 hid = mfma(AH, b_psi(h[tt], c, (float)deg), zero);
                 hid = mfma16(ASA, sa, hid);
                 hid = mfma16(ASB, sb, hid);
-                bf16x8 bh;
-#pragma unroll
-                for (int m = 0; m < 5; ++m) bh[m] = (__bf16)fmaxf(hid[m], 0.0f);
-                bh[5] = (__bf16)1.0f;  // output bias column
-                bh[6] = (__bf16)0.0f;
-                bh[7] = (__bf16)0.0f;
+                // (ReLU(hidden) 5 components, 1 for the output bias column, 0, 0)
+                const bf16x8 bh = __builtin_bit_cast(
+                    bf16x8, (uint4){bf16_relu2(hid[0], hid[1]), bf16_relu2(hid[2], hid[3]), bf16_relu2(hid[4], 1.0f), 0u});
                 const f32x16 o = mfma(A2, bh, zero);
                 if (valid) {
 #pragma unroll
@@ -457,11 +465,8 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
         const bool valid = p < k;
         const TileNode tn = T[valid ? p : tile * MFMA_TILE];
         const f32x16 hd = mfma(AD1, b_psi(h[tt], 0.0f, 0.0f), zero);
-        bf16x8 bh;
-#pragma unroll
-        for (int m = 0; m < 5; ++m) bh[m] = (__bf16)fmaxf(hd[m], 0.0f);
-#pragma unroll
-        for (int m = 5; m < 8; ++m) bh[m] = (__bf16)0.0f;
+        const bf16x8 bh = __builtin_bit_cast(
+            bf16x8, (uint4){bf16_relu2(hd[0], hd[1]), bf16_relu2(hd[2], hd[3]), bf16_relu2(hd[4], 0.0f), 0u});
         const f32x16 o = mfma(AD2, bh, zero);
         if (valid && hf == 0) {
             const double r_tilde = (double)(o[0] + bd2);

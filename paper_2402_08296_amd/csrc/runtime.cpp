@@ -601,12 +601,33 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
                 if (nch > 255 || off + (size_t)nch * MFMA_EC * MFMA_TILE >= (1u << 24))
                     return fail(DDMGNN_E_INVALID, "sub-mesh edge block too large for the MFMA tile records");
                 er.resize(er.size() + (size_t)nch * MFMA_EC * MFMA_TILE, mfma_edge_record(k, 0));
+                // Slot by slot, each lane takes the remaining in-edge whose sender row
+                // starts on the least used LDS bank of the slot (rows are 5 dwords
+                // apart), so a wavefront's gathers spread over the banks. This only
+                // reorders each node's message sum.
+                std::vector<std::vector<int64_t>> rem(t1 - t0);
+                for (int q = t0; q < t1; ++q) {
+                    const int64_t slot = b + hs.tnode[b + q];
+                    for (int64_t t = hs.edge_ptr[slot]; t < hs.edge_ptr[slot + 1]; ++t) rem[q - t0].push_back(t);
+                }
+                for (int w = 0; w < maxdeg; ++w) {
+                    int used[32] = {0};
+                    for (int q = t0; q < t1; ++q) {
+                        auto& r = rem[q - t0];
+                        if (r.empty()) continue;
+                        size_t best = 0;
+                        for (size_t c = 1; c < r.size(); ++c)
+                            if (used[(5 * hs.edge_src[r[c]]) % 32] < used[(5 * hs.edge_src[r[best]]) % 32]) best = c;
+                        const int64_t t = r[best];
+                        r.erase(r.begin() + (long)best);
+                        used[(5 * hs.edge_src[t]) % 32]++;
+                        er[epad[i] + off + (size_t)w * MFMA_TILE + (q - t0)] =
+                            mfma_edge_record(hs.edge_src[t], (uint16_t)(hs.erec[t] >> 16));
+                    }
+                }
                 for (int q = t0; q < t1; ++q) {
                     const int32_t j = hs.tnode[b + q];
                     const int64_t slot = b + j;
-                    for (int64_t t = hs.edge_ptr[slot]; t < hs.edge_ptr[slot + 1]; ++t)
-                        er[epad[i] + off + (size_t)(t - hs.edge_ptr[slot]) * MFMA_TILE + (q - t0)] =
-                            mfma_edge_record(hs.edge_src[t], (uint16_t)(hs.erec[t] >> 16));
                     TileNode& tn = tiles[b + q];
                     tn.e0 = (int32_t)((uint32_t)off | ((uint32_t)nch << 24));
                     tn.j = (uint16_t)j;
