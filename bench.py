@@ -83,6 +83,45 @@ def apply_bytes(n: int, K: int, sum_k: int, n_edges: int, xy_bytes: int = 8) -> 
             + n * (4 + 1 + 8 + 8) + sum_k * (4 + 4 + 8 + 8))
 
 
+def lu_local_bytes(K: int, sum_k: int, sum_k2: int) -> float:
+    """Compulsory HBM bytes of one exact local-solve launch (DDM-LU): the inverses
+    8 sum k_i^2; per slot r gather 8, sub_nodes 4, weights 8, local output 8;
+    per sub-mesh sub_ptr 4, lu_off 8, s and y0 outputs 16."""
+    return 8.0 * sum_k2 + sum_k * (8 + 4 + 8 + 8) + K * (4 + 8 + 16)
+
+
+def bench_lu(dg, prob, u, hp, steps: int) -> dict:
+    """DDM-LU (eq. (7): exact local solves, unweighted glue, PCG) on the same problem."""
+    import torch
+    opts = dg.default_opts(krylov=dg.PCG, local_solver=dg.LOCAL_LU, prolong=dg.PROLONG_UNWEIGHTED,
+                           precision="fp64", rtol=1e-6, max_it=5000, check_every=16)
+    t = time.perf_counter()
+    first = prob.solve(u, opts, check=False)  # forms and uploads the local inverses
+    setup_s = time.perf_counter() - t - first.solve_ms * 1e-3
+    log(f"DDM-LU first solve: iterations={first.iterations} setup={setup_s:.1f}s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st = prob.solve(u, opts, check=False)
+    torch.cuda.synchronize()
+    elapsed = (time.perf_counter() - t0) / steps
+    sp = prob.solve(u, dg.default_opts(krylov=dg.PCG, local_solver=dg.LOCAL_LU, prolong=dg.PROLONG_UNWEIGHTED,
+                                       precision="fp64", rtol=1e-6, max_it=5000, profile=1), check=False)
+    n_it = max(1, sp.dss_launches)
+    k = np.diff(hp.sub_ptr).astype(np.int64)
+    nbytes = lu_local_bytes(hp.K, int(k.sum()), int((k * k).sum()))
+    local_ms = sp.dss_ms / n_it
+    achieved = nbytes / (local_ms * 1e-3) / 1e9
+    return {"krylov": "PCG", "prolong": "unweighted", "iterations": st.iterations, "converged": bool(st.converged),
+            "true_rel_residual": st.true_rel_residual, "time_to_solution_ms": 1e3 * elapsed,
+            "solves_per_s": 1.0 / elapsed, "host_setup_s": setup_s, "device_bytes": prob.device_bytes(),
+            "breakdown_ms_per_iteration": {"local": local_ms, "coarse": sp.coarse_ms / n_it,
+                                           "prolong": sp.prolong_ms / n_it, "krylov": sp.krylov_ms / n_it},
+            "roofline": {"kernel": "lu_local_kernel", "bound": "hbm", "achieved": achieved, "peak": HBM_GBPS,
+                         "unit": "GB/s", "frac": achieved / HBM_GBPS, "bytes_per_launch": nbytes,
+                         "avg_launch_ms": local_ms}}
+
+
 def _make(spec):
     """(seed, target_nodes, n_parts, jitter) -> (problem, host arrays); runs in a worker process."""
     import paper_2402_08296_amd as dg
@@ -250,6 +289,7 @@ def main():
     ap.add_argument("--serve", type=int, default=40, help="requests of the stream prefix (0: skip)")
     ap.add_argument("--serve-slow-rate", type=float, default=6.0, help="arrival rate of the sustained replay (1/s)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--lu-steps", type=int, default=1, help="timed DDM-LU solves of the main problem (0: skip)")
     ap.add_argument("--pmc-workload", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -364,6 +404,12 @@ def main():
                      "algorithmic_bytes_per_apply": abytes},
         "p99_latency_ms": None,
     }
+    if args.lu_steps > 0:
+        log("DDM-LU on the same problem")
+        out["ddm_lu"] = bench_lu(dg, prob, u, hp, args.lu_steps)
+        out["ddm_lu"]["gnn_vs_lu_time"] = out["ddm_lu"]["time_to_solution_ms"] / out["time_to_solution_ms"]
+        del prob  # frees the inverses before the batched legs
+        torch.cuda.synchronize()
     if args.batch8 > 1:
         log(f"{args.config} x{args.batch8} in one batch")
         out["batched_same_x8"] = bench_batched(dg, ctx, model, [(p, hp)] * args.batch8, opts, 1, False)

@@ -55,6 +55,9 @@ enum { DDMGNN_FCG = 0, DDMGNN_PCG = 1, DDMGNN_CG = 2 };
 enum { DDMGNN_FP64 = 0, DDMGNN_FP32 = 1, DDMGNN_BF16 = 2 };
 /* Weights of the gluing step 3: partition of unity D_i, or 1 (paper). */
 enum { DDMGNN_PROLONG_POU = 0, DDMGNN_PROLONG_UNWEIGHTED = 1 };
+/* Local solver of step 2: the DSS_theta model, or the exact solve of
+ * R_i A R_i^T (the paper's DDM-LU comparator, eq. (7)). */
+enum { DDMGNN_LOCAL_GNN = 0, DDMGNN_LOCAL_LU = 1 };
 
 typedef struct ddmgnn_ctx ddmgnn_ctx;
 typedef struct ddmgnn_model ddmgnn_model;
@@ -151,6 +154,9 @@ typedef struct {
     int32_t profile;     /* 1: time every stage with HIP events on the context stream */
     int32_t graph;       /* 1: replay chunks of check_every iterations as one captured HIP graph
                           * (ignored when profile = 1) */
+    int32_t local_solver;/* DDMGNN_LOCAL_GNN, or DDMGNN_LOCAL_LU: exact local solves with the
+                          * inverses of R_i A R_i^T (dense FP64, sum k_i^2 doubles of device
+                          * memory), formed on the host at the problem's first LU use */
 } ddmgnn_solve_opts;
 
 typedef struct {
@@ -166,15 +172,16 @@ typedef struct {
     double coarse_ms;          /* coarse solve (step 1) */
     double prolong_ms;         /* gluing (step 3) with its fused dot products */
     double krylov_ms;          /* direction update, SpMV with dots, solution update */
-    int32_t dss_kernel;        /* kernel that ran the DSS forward: 0 FP64 VALU, 1 FP32 VALU,
-                                * 2 BF16 MFMA (BF16 falls back to 1 when a sub-mesh exceeds its LDS budget) */
+    int32_t dss_kernel;        /* kernel that ran the local solves: 0 FP64 VALU DSS, 1 FP32 VALU DSS,
+                                * 2 BF16 MFMA DSS (BF16 falls back to 1 when a sub-mesh exceeds its LDS
+                                * budget), 3 exact local solves (DDM-LU) */
     int32_t status;            /* this problem's own status (DDMGNN_OK, E_MAXIT, E_BREAKDOWN, ...) */
     double latency_ms;         /* served requests: completion - submission (host clock);
                                 * solves: equal to solve_ms */
 } ddmgnn_stats;
 
 /* Fill opts with defaults (FCG, m_max 1, rtol 1e-6, max_it 10000, FP32, POU, coarse on,
- * check_every 16, graph replay on). */
+ * check_every 16, graph replay on, DSS local solver). */
 void ddmgnn_default_opts(ddmgnn_solve_opts* opts);
 
 /* Solve A u = b from the problem's u0. u_out: device, N doubles. On
@@ -268,7 +275,8 @@ void ddmgnn_free(void* p);
 int ddmgnn_problem_sizes(const ddmgnn_problem* prob, int64_t* n, int64_t* nnz, int32_t* k,
                          int64_t* sum_k, int64_t* n_edges);
 
-/* Device memory a problem holds (the budget unit of the server). */
+/* Device memory a problem holds (the budget unit of the server), including the
+ * local inverses of DDMGNN_LOCAL_LU once they are built. */
 int ddmgnn_problem_device_bytes(const ddmgnn_problem* prob, int64_t* bytes);
 
 /* Local DSS graph of sub-mesh `sub` as setup builds it from a descriptor
@@ -279,6 +287,11 @@ int ddmgnn_problem_device_bytes(const ddmgnn_problem* prob, int64_t* bytes);
  * *n_edges_sub only. The descriptor is validated first. */
 int ddmgnn_setup_local_graph(const ddmgnn_problem_desc* desc, int32_t sub, int32_t* rowptr, int32_t* col,
                              int64_t* n_edges_sub);
+
+/* Inverse of the local matrix R_i A R_i^T of sub-mesh `sub` as the exact local
+ * solver (DDM-LU, eq. (7)) forms it: dense, row-major k_sub x k_sub, into a
+ * caller-owned host buffer. E_NOT_SPD when its Cholesky factorisation fails. */
+int ddmgnn_setup_local_inverse(const ddmgnn_problem_desc* desc, int32_t sub, double* inv);
 
 /* Coarse operator A_0 = R_0 A R_0^T (eq. (7), Nicolaides basis from the
  * weights) and its inverse as setup forms them, row-major K x K into

@@ -18,6 +18,7 @@ from ._build import LIB as _LIB_PATH
 FCG, PCG, CG = 0, 1, 2
 FP64, FP32, BF16 = 0, 1, 2
 PROLONG_POU, PROLONG_UNWEIGHTED = 0, 1
+LOCAL_GNN, LOCAL_LU = 0, 1
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_HIP", -4: "E_NOT_SPD", -5: "E_BREAKDOWN",
           -6: "E_MAXIT", -7: "E_NONFINITE", -8: "E_BUDGET", -9: "E_PENDING"}
 PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
@@ -45,7 +46,7 @@ class ProblemDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("krylov", _i32), ("m_max", _i32), ("rtol", _f64), ("max_it", _i32), ("precision", _i32),
                 ("prolong", _i32), ("coarse", _i32), ("check_every", _i32), ("profile", _i32),
-                ("graph", _i32)]
+                ("graph", _i32), ("local_solver", _i32)]
 
 
 class Stats(ctypes.Structure):
@@ -109,6 +110,7 @@ def lib():
         "ddmgnn_setup_local_graph": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), _i32, _p, _p,
                                                     ctypes.POINTER(_i64)]),
         "ddmgnn_setup_coarse": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), _p, _p]),
+        "ddmgnn_setup_local_inverse": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), _i32, _p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -237,6 +239,15 @@ def setup_coarse(hp: HostProblem):
     a0inv = np.empty((hp.K, hp.K))
     _check(lib().ddmgnn_setup_coarse(ctypes.byref(d), a0.ctypes.data_as(_p), a0inv.ctypes.data_as(_p)))
     return a0, a0inv
+
+
+def setup_local_inverse(hp: HostProblem, sub: int):
+    """(R_i A R_i^T)^{-1} of sub-mesh `sub` as the library's exact local solver forms it."""
+    d = hp.desc()
+    k = int(hp.sub_ptr[sub + 1] - hp.sub_ptr[sub]) if 0 <= sub < hp.K else 0
+    inv = np.empty((k, k))
+    _check(lib().ddmgnn_setup_local_inverse(ctypes.byref(d), sub, inv.ctypes.data_as(_p)))
+    return inv
 
 
 def default_opts(**kw) -> SolveOpts:

@@ -75,6 +75,9 @@ struct DevProb {
     const int32_t* node_slots;
     const int32_t* slot_sub;
     const double* a0inv;        // K x K
+    const double* lu_inv;       // local exact solves: (R_i A R_i^T)^{-1} per sub-mesh, k_i rows of
+                                // stride k_i rounded up to even (16-byte aligned rows, zero pad)
+    const int64_t* lu_off;      // [K + 1] offsets into lu_inv (null until built)
     // iteration vectors
     double* u;
     double* r;                  // residual; input of the apply
@@ -122,6 +125,9 @@ hipError_t prepare_dss_valu(int precision, size_t shmem);
 hipError_t launch_dss_valu(const DevProb* tab, const int2* work, int n_work, int precision, bool qlds, int kbar,
                            double alpha, int apply, const float* theta32, const double* theta64, size_t shmem,
                            hipStream_t s, bool check);
+// Exact local solves (DDM-LU): restriction as in the DSS kernels, then
+// local = (R_i A R_i^T)^{-1} R_i r per sub-mesh.
+hipError_t launch_lu_local(const DevProb* tab, const int2* work, int n_work, hipStream_t s, bool check);
 hipError_t launch_coarse(const DevProb* tab, const int2* rows, int n_rows, hipStream_t s, bool check);
 // The Krylov launchers end with a finalize launch of one workgroup per
 // problem: n_prob = all problems of the table, or the problems of `list`.

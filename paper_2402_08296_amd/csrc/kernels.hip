@@ -434,6 +434,85 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
     }
 }
 
+// ------------------------------------------------------------------ exact local solves
+// DDM-LU (the paper's comparator, eq. (7)): local = (R_i A R_i^T)^{-1} R_i r with
+// the inverse M formed at setup; one workgroup per sub-mesh, R_i r staged in
+// LDS. M is symmetric, so local_j = sum_c M[c][j] x_c: a wavefront owns a
+// strip of LU_STRIP columns (two per lane, 16-byte loads of contiguous row
+// segments) and walks the rows in order with per-lane accumulators. Small
+// sub-meshes (fewer strips than wavefronts) also split the rows into parts
+// whose sums are added in part order through LDS. Also writes s_i = |R_i r|
+// and y0_i = (R_0 r)_i like the DSS kernels.
+constexpr int LU_STRIP = 128;
+constexpr int LU_WAVES = DSS_BLOCK / 64;
+
+__global__ __launch_bounds__(DSS_BLOCK) void lu_local_kernel(const DevProb* __restrict__ tab,
+                                                            const int2* __restrict__ work) {
+    const int2 wi = work[blockIdx.x];
+    const DevProb& P = tab[wi.x];
+    if (P.st && P.st->done) return;
+    __shared__ double xs[kMaxSubNodes];
+    __shared__ double yp[LU_WAVES * LU_STRIP];  // parts * k <= LU_WAVES * LU_STRIP
+    __shared__ double red[DSS_BLOCK / 64 + 1];
+    const int sub = wi.y;
+    const int base = P.sub_ptr[sub];
+    const int k = P.sub_ptr[sub + 1] - base;
+    const double* __restrict__ r = P.r;
+    double ss = 0.0, yy = 0.0;
+    for (int j = threadIdx.x; j < k; j += DSS_BLOCK) {
+        const double v = r[P.sub_nodes[base + j]];
+        xs[j] = v;
+        ss = fma(v, v, ss);
+        yy = fma(P.weights[base + j], v, yy);
+    }
+    // the barriers inside block_sum also publish xs
+    ss = block_sum<DSS_BLOCK>(ss, red);
+    yy = block_sum<DSS_BLOCK>(yy, red);
+    if (threadIdx.x == 0) {
+        P.s[sub] = sqrt(ss);
+        P.y0[sub] = yy;
+    }
+    const int ld = (k + 1) & ~1;
+    const double* __restrict__ M = P.lu_inv + P.lu_off[sub];
+    double* __restrict__ out = P.local + base;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ns = (k + LU_STRIP - 1) / LU_STRIP;
+    const int parts = ns > 0 ? max(1, LU_WAVES / ns) : 1;
+    const int rpp = (k + parts - 1) / parts;
+    for (int t = wave; t < ns * parts; t += LU_WAVES) {
+        const int strip = t % ns, part = t / ns;
+        const int j = strip * LU_STRIP + 2 * lane;
+        if (j >= k) continue;
+        const int c0 = part * rpp, c1 = min(k, c0 + rpp);
+        // column j + 1 may be the zero pad of an odd k
+        const double2* __restrict__ col = reinterpret_cast<const double2*>(M + j);
+        const int ld2 = ld >> 1;
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll 8
+        for (int c = c0; c < c1; ++c) {
+            const double2 v = col[(size_t)c * ld2];
+            const double xc = xs[c];
+            a0 = fma(v.x, xc, a0);
+            a1 = fma(v.y, xc, a1);
+        }
+        if (parts == 1) {
+            out[j] = a0;
+            if (j + 1 < k) out[j + 1] = a1;
+        } else {
+            yp[part * k + j] = a0;
+            if (j + 1 < k) yp[part * k + j + 1] = a1;
+        }
+    }
+    if (parts > 1) {  // uniform over the workgroup (depends on k only)
+        __syncthreads();
+        for (int j = threadIdx.x; j < k; j += DSS_BLOCK) {
+            double acc = yp[j];
+            for (int q = 1; q < parts; ++q) acc += yp[q * k + j];
+            out[j] = acc;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ coarse solve
 // y = A0inv y0: one workgroup per row (work item = (problem, row)), its four
 // wavefronts over interleaved column segments, combined in a fixed order.
@@ -832,6 +911,12 @@ hipError_t launch_dss_valu(const DevProb* tab, const int2* work, int n_work, int
         else
             hipLaunchKernelGGL((dss_kernel<float, true, false>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a, theta32);
     }
+    return done(check);
+}
+
+hipError_t launch_lu_local(const DevProb* tab, const int2* work, int n_work, hipStream_t s, bool check) {
+    if (n_work <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lu_local_kernel, dim3(n_work), dim3(DSS_BLOCK), 0, s, tab, work);
     return done(check);
 }
 

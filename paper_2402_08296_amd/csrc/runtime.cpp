@@ -65,6 +65,7 @@ DevProb make_view(ddmgnn_problem* P) {
     v.epad_sub = P->epad_sub.p;
     v.tiles = P->tiles.p; v.xy64 = P->xy64.p; v.xyc32 = P->xyc32.p;
     v.node_ptr = P->node_ptr.p; v.node_slots = P->node_slots.p; v.slot_sub = P->slot_sub.p; v.a0inv = P->a0inv.p;
+    v.lu_inv = P->lu_inv.p; v.lu_off = P->lu_off.p;
     v.u = P->u.p; v.r = P->r.p; v.z = P->z.p; v.c_in = nullptr;
     const int64_t n = P->hs.n;
     for (int i = 0; i <= MAX_M; ++i) {
@@ -108,6 +109,37 @@ size_t valu_shmem(int max_k, int precision) {
     return (size_t)max_k * 2 * D * esz;
 }
 
+// Exact local solves: the inverses of R_i A R_i^T, formed on the host from the
+// problem's matrix and sub-meshes (downloaded once) and uploaded.
+int prepare_lu(ddmgnn_problem* P) {
+    if (P->lu_inv.p) return DDMGNN_OK;
+    hipStream_t s = P->ctx->stream;
+    const auto& hs = P->hs;
+    std::vector<int32_t> rowptr(hs.n + 1), col(hs.nnz), sub_nodes(hs.sk);
+    std::vector<double> val(hs.nnz);
+    HIP_TRY(hipMemcpyAsync(rowptr.data(), P->rowptr.p, rowptr.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(col.data(), P->col.p, col.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(val.data(), P->val.p, val.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(sub_nodes.data(), P->sub_nodes.p, sub_nodes.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    ddmgnn_problem_desc d{};
+    d.n_nodes = hs.n;
+    d.a_rowptr = rowptr.data();
+    d.a_col = col.data();
+    d.a_val = val.data();
+    d.n_sub = hs.K;
+    d.sub_ptr = hs.sub_ptr.data();
+    d.sub_nodes = sub_nodes.data();
+    std::vector<double> inv;
+    std::vector<int64_t> off;
+    if (!build_local_inverses(d, inv, off).empty())
+        return fail(DDMGNN_E_NOT_SPD, "a local matrix R_i A R_i^T is not positive definite");
+    HIP_TRY(P->lu_off.upload(off.data(), off.size(), s));
+    HIP_TRY(P->lu_inv.upload(inv.data(), inv.size(), s));
+    P->device_bytes += inv.size() * sizeof(double) + off.size() * sizeof(int64_t);
+    return DDMGNN_OK;
+}
+
 // Allocates what the DSS launches of this precision need (fallback storage,
 // LDS attributes). Not allowed during stream capture; returns true in
 // `changed` when a problem's buffers moved (the table must be re-uploaded).
@@ -143,11 +175,16 @@ int prepare_dss(Batch& B, int precision, bool& changed) {
     return DDMGNN_OK;
 }
 
-// DSS forward over every sub-mesh of the table (apply: restriction and s r~).
-int enqueue_dss(Batch& B, const DevProb* tab, int precision, int apply, bool capturing) {
+// Local solves over every sub-mesh of the table: the DSS forward (apply:
+// restriction and s r~), or the exact solves of DDM-LU.
+int enqueue_dss(Batch& B, const DevProb* tab, int precision, int apply, bool capturing, int local = DDMGNN_LOCAL_GNN) {
     hipStream_t s = B.ctx->launch;
     const ModelDev& M = *B.model;
     const bool check = !capturing;
+    if (local == DDMGNN_LOCAL_LU) {
+        HIP_TRY(launch_lu_local(tab, B.work_all.p, B.n_all, s, check));
+        return DDMGNN_OK;
+    }
     if (precision == DDMGNN_BF16) {
         DssMfmaArgs a{tab, B.work_mfma.p, M.steps.p, M.dec.p, M.kbar, (float)M.alpha, apply};
         HIP_TRY(launch_dss_mfma(a, B.n_mfma, MFMA_LDS_LIMIT, s, check));
@@ -176,7 +213,7 @@ IterArgs iter_args(const ddmgnn_solve_opts& o, int mode) {
 // ev (optional): events recorded after the DSS (ev[1]), coarse (ev[2]) and prolong (ev[3]) launches.
 int enqueue_apply(Batch& B, const DevProb* tab, const ddmgnn_solve_opts& o, int mode, hipEvent_t* ev,
                   bool capturing) {
-    if (int rc = enqueue_dss(B, tab, o.precision, 1, capturing)) return rc;
+    if (int rc = enqueue_dss(B, tab, o.precision, 1, capturing, o.local_solver)) return rc;
     hipStream_t s = B.ctx->launch;
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     if (o.coarse) HIP_TRY(launch_coarse(tab, B.coarse_rows.p, B.n_coarse, s, !capturing));
@@ -204,8 +241,9 @@ int enqueue_iteration(Batch& B, const ddmgnn_solve_opts& o, hipEvent_t* ev, bool
 }
 
 uint64_t graph_key(const ddmgnn_solve_opts& o, int count) {
-    return ((uint64_t)o.krylov << 44) | ((uint64_t)o.m_max << 40) | ((uint64_t)o.precision << 36) |
-           ((uint64_t)o.prolong << 34) | ((uint64_t)o.coarse << 32) | (uint64_t)(uint32_t)count;
+    return ((uint64_t)o.local_solver << 48) | ((uint64_t)o.krylov << 44) | ((uint64_t)o.m_max << 40) |
+           ((uint64_t)o.precision << 36) | ((uint64_t)o.prolong << 34) | ((uint64_t)o.coarse << 32) |
+           (uint64_t)(uint32_t)count;
 }
 
 // Captures `count` iterations of the batch into B.graph (on the context's own
@@ -368,7 +406,7 @@ int solve_batch(ddmgnn_ctx* ctx, Batch& B, const ddmgnn_solve_opts& o, double* c
             S.coarse_ms = t_coarse;
             S.prolong_ms = t_prolong;
             S.krylov_ms = t_krylov;
-            S.dss_kernel = dss_kernel_of(B.probs[i], o.precision);
+            S.dss_kernel = dss_kernel_of(B.probs[i], o);
             S.status = k.status ? k.status : (converged ? DDMGNN_OK : DDMGNN_E_MAXIT);
             S.latency_ms = ms;
         }
@@ -443,8 +481,14 @@ int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& 
 
 int batch_begin(Batch& B, const ddmgnn_solve_opts& o, const std::vector<uint8_t>* init) {
     bool changed = false;
-    if (o.krylov != DDMGNN_CG)
+    if (o.krylov != DDMGNN_CG && o.local_solver == DDMGNN_LOCAL_LU) {
+        for (ddmgnn_problem* P : B.probs) {
+            changed = changed || !P->lu_inv.p;
+            if (int rc = prepare_lu(P)) return rc;
+        }
+    } else if (o.krylov != DDMGNN_CG) {
         if (int rc = prepare_dss(B, o.precision, changed)) return rc;
+    }
     if (changed && B.graph) {  // captured launches point at moved buffers
         (void)hipGraphExecDestroy(B.graph);
         B.graph = nullptr;
@@ -495,9 +539,10 @@ int batch_true_residual(Batch& B, const std::vector<uint8_t>* which) {
     return batch_poll(B);
 }
 
-int dss_kernel_of(const ddmgnn_problem* P, int precision) {
-    if (precision == DDMGNN_FP64) return 0;
-    return precision == DDMGNN_BF16 && P->mfma_fits ? 2 : 1;
+int dss_kernel_of(const ddmgnn_problem* P, const ddmgnn_solve_opts& o) {
+    if (o.local_solver == DDMGNN_LOCAL_LU) return 3;
+    if (o.precision == DDMGNN_FP64) return 0;
+    return o.precision == DDMGNN_BF16 && P->mfma_fits ? 2 : 1;
 }
 
 int check_opts(const ddmgnn_solve_opts& o) {
@@ -507,6 +552,7 @@ int check_opts(const ddmgnn_solve_opts& o) {
     if (o.max_it < 0) return fail(DDMGNN_E_INVALID, "max_it must be >= 0");
     if (o.precision < 0 || o.precision > 2) return fail(DDMGNN_E_INVALID, "precision must be FP64, FP32 or BF16");
     if (o.prolong < 0 || o.prolong > 1) return fail(DDMGNN_E_INVALID, "prolong must be POU or UNWEIGHTED");
+    if (o.local_solver < 0 || o.local_solver > 1) return fail(DDMGNN_E_INVALID, "local_solver must be GNN or LU");
     return DDMGNN_OK;
 }
 
@@ -574,6 +620,10 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
     HIP_TRY(P->xy64.upload(xy64.data(), 2 * sk, s));
     HIP_TRY(P->xyc32.upload(xyc32.data(), 2 * sk, s));
     HIP_TRY(P->a0inv.upload(hs.a0inv.data(), (size_t)K * K, s));
+    if (!hs.lu_inv.empty()) {
+        HIP_TRY(P->lu_off.upload(hs.lu_off.data(), hs.lu_off.size(), s));
+        HIP_TRY(P->lu_inv.upload(hs.lu_inv.data(), hs.lu_inv.size(), s));
+    }
     {
         // MFMA kernel records, per tile of MFMA_TILE nodes (tile order): slot-major
         // [slot][lane] blocks padded with sentinel records (sender k_i, |d| 0)
@@ -665,7 +715,11 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
     HIP_TRY(hipMemsetAsync(P->counters.p, 0, 4 * sizeof(unsigned), s));
     HIP_TRY(hipMemsetAsync(P->st.p, 0, sizeof(KState), s));
     HIP_TRY(hipStreamSynchronize(s));
-    P->device_bytes = problem_device_bytes(n, hs.nnz, K, sk, hs.n_edges);
+    P->device_bytes = problem_device_bytes(n, hs.nnz, K, sk, hs.n_edges) + P->lu_inv.n * sizeof(double) +
+                      P->lu_off.n * sizeof(int64_t);
+    // host copies of the uploaded local inverses are not needed again
+    std::vector<double>().swap(P->hs.lu_inv);
+    std::vector<int64_t>().swap(P->hs.lu_off);
     *out = P.release();
     return DDMGNN_OK;
 }
@@ -706,6 +760,7 @@ void ddmgnn_default_opts(ddmgnn_solve_opts* o) {
     o->check_every = 16;
     o->profile = 0;
     o->graph = 1;
+    o->local_solver = DDMGNN_LOCAL_GNN;
 }
 
 int ddmgnn_ctx_create(void* hip_stream, ddmgnn_ctx** out) {
@@ -836,6 +891,17 @@ int ddmgnn_setup_coarse(const ddmgnn_problem_desc* desc, double* a0, double* a0i
     return DDMGNN_OK;
 }
 
+int ddmgnn_setup_local_inverse(const ddmgnn_problem_desc* desc, int32_t sub, double* inv) {
+    int rc = ddmgnn_validate_problem(desc);
+    if (rc) return rc;
+    if (sub < 0 || sub >= desc->n_sub || !inv) return fail(DDMGNN_E_INVALID, "sub-mesh index out of range or null output");
+    std::vector<double> m;
+    if (!local_inverse(*desc, sub, m, true).empty())
+        return fail(DDMGNN_E_NOT_SPD, "local matrix R_i A R_i^T is not positive definite");
+    std::memcpy(inv, m.data(), m.size() * sizeof(double));
+    return DDMGNN_OK;
+}
+
 int ddmgnn_spmv(ddmgnn_ctx* ctx, ddmgnn_problem* P, const double* x, double* y) {
     if (!ctx || !P || !x || !y) return fail(DDMGNN_E_INVALID, "null argument");
     HIP_TRY(launch_spmv(P->rowptr.p, P->col.p, P->val.p, x, y, (int)P->hs.n, ctx->stream));
@@ -881,7 +947,11 @@ int ddmgnn_precond_apply(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_
     if (int rc = solo_batch(P)) return rc;
     Batch& B = *P->solo;
     bool changed = false;
-    if (int rc = prepare_dss(B, opts->precision, changed)) return rc;
+    if (opts->local_solver == DDMGNN_LOCAL_LU) {
+        if (int rc = prepare_lu(P)) return rc;
+    } else if (int rc = prepare_dss(B, opts->precision, changed)) {
+        return rc;
+    }
     DevProb v = make_view(P);
     v.r = const_cast<double*>(r);  // read only: the apply never writes its input
     v.z = z;

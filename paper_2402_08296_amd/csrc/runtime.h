@@ -98,8 +98,9 @@ int batch_size(const Batch& B);
 ddmgnn_problem* batch_problem(const Batch& B, int i);
 // True residuals of the problems flagged in `which` (all when null) into their states, synchronised.
 int batch_true_residual(Batch& B, const std::vector<uint8_t>* which);
-// DSS kernel that runs problem i at precision p: 0 FP64 VALU, 1 FP32 VALU, 2 BF16 MFMA.
-int dss_kernel_of(const ddmgnn_problem* P, int precision);
+// Kernel that runs the local solves of problem P: 0 FP64 VALU DSS, 1 FP32 VALU DSS,
+// 2 BF16 MFMA DSS, 3 exact local solves (DDM-LU).
+int dss_kernel_of(const ddmgnn_problem* P, const ddmgnn_solve_opts& o);
 
 int check_opts(const ddmgnn_solve_opts& o);
 
@@ -148,6 +149,9 @@ struct ddmgnn_problem {
     // apply buffers
     ddmgnn::DevBuf<double> s, y0, y, local;
     ddmgnn::DevBuf<double> qglobal64, hglobal64;
+    // exact local solves (built on the first solve with local_solver = LU)
+    ddmgnn::DevBuf<double> lu_inv;
+    ddmgnn::DevBuf<int64_t> lu_off;
     ddmgnn::DevBuf<float> qglobal32;
     // Krylov vectors
     ddmgnn::DevBuf<double> u, r, z;

@@ -59,8 +59,8 @@ void copy_in(std::vector<T>& dst, const T* src, int64_t n) {
 // Options that must agree among the problems of one batch.
 uint64_t structure_key(const ddmgnn_solve_opts& o) {
     const int m = o.krylov == DDMGNN_FCG ? o.m_max : 1;
-    return ((uint64_t)o.krylov << 24) | ((uint64_t)m << 16) | ((uint64_t)o.precision << 8) |
-           ((uint64_t)o.prolong << 4) | (uint64_t)(o.coarse != 0);
+    return ((uint64_t)o.local_solver << 32) | ((uint64_t)o.krylov << 24) | ((uint64_t)m << 16) |
+           ((uint64_t)o.precision << 8) | ((uint64_t)o.prolong << 4) | (uint64_t)(o.coarse != 0);
 }
 
 }  // namespace
@@ -114,14 +114,19 @@ void ddmgnn_server::setup_worker() {
         }
         std::string e = validate(r->desc);
         if (e.empty()) e = build_setup(r->desc, r->hs);
+        const bool lu = r->opts.local_solver == DDMGNN_LOCAL_LU && r->opts.krylov != DDMGNN_CG;
         if (e == "NOT_SPD") {
             r->setup_rc = DDMGNN_E_NOT_SPD;
             r->err = "coarse matrix R_0 A R_0^T is not positive definite";
         } else if (!e.empty()) {
             r->setup_rc = DDMGNN_E_INVALID;
             r->err = e;
+        } else if (lu && !build_local_inverses(r->desc, r->hs.lu_inv, r->hs.lu_off).empty()) {
+            r->setup_rc = DDMGNN_E_NOT_SPD;
+            r->err = "a local matrix R_i A R_i^T is not positive definite";
         } else {
-            r->bytes = problem_device_bytes(r->hs.n, r->hs.nnz, r->hs.K, r->hs.sk, r->hs.n_edges);
+            r->bytes = problem_device_bytes(r->hs.n, r->hs.nnz, r->hs.K, r->hs.sk, r->hs.n_edges) +
+                       r->hs.lu_inv.size() * sizeof(double) + r->hs.lu_off.size() * sizeof(int64_t);
         }
         std::lock_guard<std::mutex> lk(mu);
         ready[r->ticket] = r;
@@ -265,7 +270,7 @@ void ddmgnn_server::gpu_loop() {
             S.rel_residual = k.rel;
             S.true_rel_residual = k.r0n > 0 ? std::sqrt(k.rr_true) / k.r0n : 0.0;
             S.solve_ms = ms_between(r->t_admit, Clock::now());
-            S.dss_kernel = dss_kernel_of(P, gopts.precision);
+            S.dss_kernel = dss_kernel_of(P, gopts);
             if (e != hipSuccess) {
                 r->status = DDMGNN_E_HIP;
                 r->err = std::string("result copy: ") + hipGetErrorString(e);

@@ -46,68 +46,145 @@ inline double dot4(const double* a, const double* b, int64_t len) {
     return (s0 + s1) + (s2 + s3);
 }
 
-// Blocked right-looking Cholesky of the symmetric K x K matrix a (row-major),
-// then inv = A^{-1} by forward and backward substitution on blocks of 64
-// identity columns. Returns false when a pivot is not positive.
-bool dense_cholesky(const std::vector<double>& a, int32_t K, std::vector<double>& inv) {
+// ------------------------------------------------------------------ dense SPD inverse
+// C[m x n] -= A[m x np] B[np x n] for one register tile (m <= 4, n <= 8), all
+// row-major: A[r * lda + p], B[p * ldb + c], C[r * ldc + c]. Each entry sums p
+// in increasing order. Compiled twice (AVX2 + FMA and the base instruction set)
+// from one body; the first use picks the version the CPU runs.
+typedef double v4d __attribute__((vector_size(32)));
+
+__attribute__((always_inline)) inline v4d load4(const double* p) {
+    v4d v;
+    std::memcpy(&v, p, sizeof v);
+    return v;
+}
+
+__attribute__((always_inline)) inline void tile_body(int m, int n, int np, const double* A, int64_t lda,
+                                                     const double* B, int64_t ldb, double* C, int64_t ldc) {
+    if (m == 4 && n == 8) {
+        v4d c[4][2] = {};
+        const double *a0 = A, *a1 = A + lda, *a2 = A + 2 * lda, *a3 = A + 3 * lda;
+        for (int p = 0; p < np; ++p) {
+            const v4d b0 = load4(B + p * ldb), b1 = load4(B + p * ldb + 4);
+            const double x0 = a0[p], x1 = a1[p], x2 = a2[p], x3 = a3[p];
+            c[0][0] += x0 * b0; c[0][1] += x0 * b1;
+            c[1][0] += x1 * b0; c[1][1] += x1 * b1;
+            c[2][0] += x2 * b0; c[2][1] += x2 * b1;
+            c[3][0] += x3 * b0; c[3][1] += x3 * b1;
+        }
+        for (int r = 0; r < 4; ++r)
+            for (int h = 0; h < 2; ++h) {
+                const v4d v = load4(C + r * ldc + 4 * h) - c[r][h];
+                std::memcpy(C + r * ldc + 4 * h, &v, sizeof v);
+            }
+        return;
+    }
+    double acc[4][8] = {};
+    for (int p = 0; p < np; ++p)
+        for (int r = 0; r < m; ++r)
+            for (int q = 0; q < n; ++q) acc[r][q] += A[r * lda + p] * B[p * ldb + q];
+    for (int r = 0; r < m; ++r)
+        for (int q = 0; q < n; ++q) C[r * ldc + q] -= acc[r][q];
+}
+
+__attribute__((target("avx2,fma"))) void tile_avx2(int m, int n, int np, const double* A, int64_t lda,
+                                                   const double* B, int64_t ldb, double* C, int64_t ldc) {
+    tile_body(m, n, np, A, lda, B, ldb, C, ldc);
+}
+
+void tile_base(int m, int n, int np, const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+               int64_t ldc) {
+    tile_body(m, n, np, A, lda, B, ldb, C, ldc);
+}
+
+using TileFn = void (*)(int, int, int, const double*, int64_t, const double*, int64_t, double*, int64_t);
+
+TileFn tile_fn() {
+    static const TileFn f = [] {
+        __builtin_cpu_init();
+        return __builtin_cpu_supports("avx2") && __builtin_cpu_supports("fma") ? &tile_avx2 : &tile_base;
+    }();
+    return f;
+}
+
+// inv = A^{-1} for the symmetric positive definite K x K matrix a (row-major),
+// in three blocked steps of K^3/6 multiply-adds each:
+//   1. A = L L^T (right-looking, panels of 64; the trailing update in tiles),
+//   2. Y = L^{-1} (block rows; the part left of the diagonal block in tiles),
+//   3. A^{-1} = Y^T Y (lower triangle in tiles, mirrored).
+// With `parallel`, the tiles of each step are spread over host threads (each
+// tile on one thread, so the result does not depend on the thread count).
+// Returns false when a pivot is not positive.
+bool dense_cholesky(const std::vector<double>& a, int32_t K, std::vector<double>& inv, bool parallel = true) {
+    auto pfor = [&](int64_t n, auto&& f) {
+        if (parallel)
+            parallel_for(n, f);
+        else
+            for (int64_t i = 0; i < n; ++i) f(i);
+    };
+    const TileFn tile = tile_fn();
     constexpr int32_t B = 64;
     std::vector<double> L(a);
     auto at = [&](int64_t i, int64_t j) -> double& { return L[(size_t)i * K + j]; };
     std::vector<double> panel;
+    // 1. Cholesky; only the lower triangle of L is read (the tiles of the
+    // trailing update also write entries right of the diagonal, never read).
     for (int32_t kb = 0; kb < K; kb += B) {
-        const int32_t ke = std::min(K, kb + B), w = ke - kb;
-        // diagonal block (earlier panels already applied by the trailing updates)
+        const int32_t ke = std::min(K, kb + B), w = ke - kb, m = K - ke;
         for (int32_t j = kb; j < ke; ++j) {
             const double dsum = at(j, j) - dot4(&at(j, kb), &at(j, kb), j - kb);
             if (!(dsum > 0.0) || !std::isfinite(dsum)) return false;
             at(j, j) = std::sqrt(dsum);
             for (int32_t i = j + 1; i < ke; ++i) at(i, j) = (at(i, j) - dot4(&at(i, kb), &at(j, kb), j - kb)) / at(j, j);
         }
-        // panel rows below the block, then a packed copy of rows ke.. of the panel
-        parallel_for(K - ke, [&](int64_t t) {
+        pfor(m, [&](int64_t t) {
             const int64_t i = ke + t;
             for (int32_t j = kb; j < ke; ++j) at(i, j) = (at(i, j) - dot4(&at(i, kb), &at(j, kb), j - kb)) / at(j, j);
         });
-        panel.assign((size_t)(K - ke) * w, 0.0);
-        for (int64_t i = ke; i < K; ++i) std::memcpy(&panel[(size_t)(i - ke) * w], &at(i, kb), w * sizeof(double));
-        // trailing update of the lower triangle
-        parallel_for(K - ke, [&](int64_t t) {
-            const double* pi = &panel[(size_t)t * w];
-            double* row = &at(ke + t, ke);
-            for (int64_t u = 0; u <= t; ++u) row[u] -= dot4(pi, &panel[(size_t)u * w], w);
+        // panel transposed: panel[p * m + j] = L[ke + j][kb + p]
+        panel.assign((size_t)w * m, 0.0);
+        for (int32_t j = 0; j < m; ++j)
+            for (int32_t p = 0; p < w; ++p) panel[(size_t)p * m + j] = at(ke + j, kb + p);
+        pfor((m + 3) / 4, [&](int64_t t) {
+            const int32_t i0 = (int32_t)t * 4, rows = std::min(4, m - i0);
+            for (int32_t j0 = 0; j0 < i0 + rows; j0 += 8)
+                tile(rows, std::min(8, m - j0), w, &at(ke + i0, kb), K, &panel[j0], m, &at(ke + i0, ke + j0), K);
         });
     }
-    // L^T (row-major) for the backward substitution.
-    std::vector<double> LT((size_t)K * K, 0.0);
-    for (int64_t i = 0; i < K; ++i)
-        for (int64_t j = 0; j <= i; ++j) LT[(size_t)j * K + i] = at(i, j);
-    // Columns c0..c0+63 of A^{-1} on rows c0..K-1 (the lower triangle; the
-    // inverse is symmetric): L Y = E from row c0 down, then L^T X = Y from row
-    // K-1 up to row c0 (rows below c0 of X are not needed). Each row update is
-    // a multiply-add over 8 columns held in registers, p in a fixed order.
-    inv.assign((size_t)K * K, 0.0);
-    const int32_t nblk = (K + B - 1) / B;
-    parallel_for(nblk, [&](int64_t cb) {
-        const int32_t c0 = (int32_t)cb * B, w = std::min(K, c0 + B) - c0;
-        std::vector<double> Y((size_t)K * B, 0.0);  // row i: columns c0.. of Y, then of X
-        auto row_update = [&](const double* coef, int32_t p0, int32_t p1, int32_t i, bool forward) {
-            double* yi = &Y[(size_t)i * B];
-            for (int32_t cc = 0; cc < w; cc += 8) {
-                double acc[8];
-                for (int32_t c = 0; c < 8; ++c) acc[c] = forward ? ((i == c0 + cc + c) ? 1.0 : 0.0) : yi[cc + c];
-                for (int32_t p = p0; p < p1; ++p) {
-                    const double l = coef[p];
-                    const double* yp = &Y[(size_t)p * B + cc];
-                    for (int32_t c = 0; c < 8; ++c) acc[c] -= l * yp[c];
-                }
-                const double dinv = coef[i];
-                for (int32_t c = 0; c < 8; ++c) yi[cc + c] = acc[c] / dinv;
+    // 2. Y = L^{-1}, lower triangular, zeros above the diagonal. Rows of block
+    // [ib, ie): first C = -L[I][0:ib] Y[0:ib][0:ib] (Y[p][c] = 0 for p < c, so
+    // column tile c0 starts at p = c0), then forward substitution within the block.
+    std::vector<double> Y((size_t)K * K, 0.0);
+    auto y = [&](int64_t i, int64_t j) -> double& { return Y[(size_t)i * K + j]; };
+    for (int32_t ib = 0; ib < K; ib += B) {
+        const int32_t ie = std::min(K, ib + B), w = ie - ib;
+        pfor((ib + 7) / 8, [&](int64_t t) {
+            const int32_t c0 = (int32_t)t * 8, cols = std::min(8, ib - c0);
+            for (int32_t r0 = 0; r0 < w; r0 += 4)
+                tile(std::min(4, w - r0), cols, ib - c0, &at(ib + r0, c0), K, &y(c0, c0), K, &y(ib + r0, c0), K);
+        });
+        for (int32_t i = ib; i < ie; ++i) {
+            const double dinv = 1.0 / at(i, i);
+            double* yi = &y(i, 0);
+            for (int32_t q = ib; q < i; ++q) {
+                const double l = at(i, q);
+                const double* yq = &y(q, 0);
+                for (int32_t c = 0; c <= q; ++c) yi[c] -= l * yq[c];
             }
-        };
-        for (int32_t i = c0; i < K; ++i) row_update(&at(i, 0), c0, i, i, true);
-        for (int32_t i = K - 1; i >= c0; --i) row_update(&LT[(size_t)i * K], i + 1, K, i, false);
-        for (int32_t i = c0; i < K; ++i)
-            for (int32_t c = 0; c < w; ++c) inv[(size_t)i * K + c0 + c] = Y[(size_t)i * B + c];
+            yi[i] += 1.0;
+            for (int32_t c = 0; c <= i; ++c) yi[c] *= dinv;
+        }
+    }
+    // 3. A^{-1} = Y^T Y. With Yt = -Y^T (upper triangular, in L's storage), the
+    // tile C -= Yt Y gives X[a][b] = sum_p Y[p][a] Y[p][b]; rows a0.. start at
+    // p = a0 (earlier terms are zero).
+    for (int64_t i = 0; i < K; ++i)
+        for (int64_t j = 0; j < K; ++j) at(i, j) = j >= i ? -y(j, i) : 0.0;
+    inv.assign((size_t)K * K, 0.0);
+    pfor((K + 3) / 4, [&](int64_t t) {
+        const int32_t a0 = (int32_t)t * 4, rows = std::min(4, K - a0);
+        for (int32_t b0 = 0; b0 < a0 + rows; b0 += 8)
+            tile(rows, std::min(8, K - b0), K - a0, &at(a0, a0), K, &y(a0, b0), K, &inv[(size_t)a0 * K + b0], K);
     });
     // mirror the lower triangle (exactly symmetric inverse)
     for (int64_t i = 0; i < K; ++i)
@@ -362,6 +439,45 @@ void build_local_graphs(const ddmgnn_problem_desc& d, HostSetup& s) {
     s.max_edges_sub = 0;
     for (int32_t i = 0; i < K; ++i)
         s.max_edges_sub = std::max<int64_t>(s.max_edges_sub, s.edge_ptr[d.sub_ptr[i + 1]] - s.edge_ptr[d.sub_ptr[i]]);
+}
+
+std::string local_inverse(const ddmgnn_problem_desc& d, int32_t i, std::vector<double>& inv, bool parallel) {
+    const int64_t b = d.sub_ptr[i], e = d.sub_ptr[i + 1];
+    const int32_t k = (int32_t)(e - b);
+    std::vector<double> a((size_t)k * k, 0.0);
+    for (int32_t j = 0; j < k; ++j) {
+        const int32_t g = d.sub_nodes[b + j];
+        for (int32_t t = d.a_rowptr[g]; t < d.a_rowptr[g + 1]; ++t) {
+            const int32_t c = d.a_col[t];
+            const int32_t* first = d.sub_nodes + b;
+            const int32_t* it = std::lower_bound(first, d.sub_nodes + e, c);
+            if (it != d.sub_nodes + e && *it == c) a[(size_t)j * k + (it - first)] = d.a_val[t];
+        }
+    }
+    if (!dense_cholesky(a, k, inv, parallel)) return "NOT_SPD";
+    return "";
+}
+
+std::string build_local_inverses(const ddmgnn_problem_desc& d, std::vector<double>& inv, std::vector<int64_t>& off) {
+    const int32_t K = d.n_sub;
+    off.assign(K + 1, 0);
+    for (int32_t i = 0; i < K; ++i) {
+        const int64_t k = d.sub_ptr[i + 1] - d.sub_ptr[i];
+        off[i + 1] = off[i] + k * lu_ld(k);
+    }
+    inv.assign((size_t)off[K], 0.0);
+    std::atomic<int32_t> bad{-1};
+    parallel_for(K, [&](int64_t i) {
+        std::vector<double> m;
+        if (!local_inverse(d, (int32_t)i, m, false).empty()) {
+            bad.store((int32_t)i);
+            return;
+        }
+        const int64_t k = d.sub_ptr[i + 1] - d.sub_ptr[i], ld = lu_ld(k);
+        for (int64_t r = 0; r < k; ++r)
+            std::memcpy(&inv[(size_t)(off[i] + r * ld)], &m[(size_t)(r * k)], k * sizeof(double));
+    });
+    return bad.load() >= 0 ? "NOT_SPD" : "";
 }
 
 std::string build_setup(const ddmgnn_problem_desc& d, HostSetup& s) {

@@ -47,7 +47,21 @@ struct HostSetup {
     std::vector<uint32_t> erec;  // per edge: sender local id | FP16 bits of |d_jl| << 16
     int64_t max_edges_sub = 0;   // largest in-edge count of a sub-mesh
     std::vector<float> edge_nd;
+    // Exact local solves, when built before the problem is created: inverses
+    // of R_i A R_i^T, row stride lu_ld(k_i), sub-mesh i at lu_off[i] (empty otherwise).
+    std::vector<double> lu_inv;
+    std::vector<int64_t> lu_off;
 };
+
+// Inverse of the local matrix R_i A R_i^T of sub-mesh i (dense, row-major
+// k_i x k_i; the paper's exact local solve of DDM-LU) by Cholesky. "" or "NOT_SPD".
+std::string local_inverse(const ddmgnn_problem_desc& d, int32_t i, std::vector<double>& inv, bool parallel);
+// Row stride of a stored local inverse: k rounded up to even, so that every row
+// starts 16-byte aligned (the pad column holds zeros).
+inline int64_t lu_ld(int64_t k) { return (k + 1) & ~int64_t(1); }
+// All local inverses concatenated, sub-mesh i at off[i] = sum_{j < i} k_j lu_ld(k_j)
+// with row stride lu_ld(k_i) (sub-meshes in parallel).
+std::string build_local_inverses(const ddmgnn_problem_desc& d, std::vector<double>& inv, std::vector<int64_t>& off);
 
 // Round-to-nearest-even float -> bf16 bits.
 inline uint16_t bf16_rne_bits(float f) {

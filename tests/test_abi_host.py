@@ -55,6 +55,24 @@ def test_coarse_operator_vs_oracle():
     assert np.abs(a0inv @ ref - np.eye(hp.K)).max() <= 1e-10
 
 
+def test_local_inverse_vs_definition():
+    """(R_i A R_i^T)^{-1} of the exact local solver: the restriction picks rows and
+    columns of A (eq. (7)), and the product with that matrix is the identity."""
+    p, hp = small_problem()
+    A = p.A.to_scipy().tocsr()
+    for i in range(hp.K):
+        idx = hp.sub_nodes[hp.sub_ptr[i]:hp.sub_ptr[i + 1]]
+        Ai = A[idx][:, idx].toarray()
+        inv = dg.setup_local_inverse(hp, i)
+        assert inv.shape == Ai.shape
+        assert np.array_equal(inv, inv.T)
+        assert np.abs(inv @ Ai - np.eye(idx.size)).max() <= 1e-10
+        ref = np.linalg.inv(Ai)
+        assert np.abs(inv - ref).max() <= 1e-10 * np.abs(ref).max()
+    with pytest.raises(dg.DDMGNNError):
+        dg.setup_local_inverse(hp, hp.K)
+
+
 def _offdiag(h):
     rows = np.repeat(np.arange(h.n), np.diff(h.rowptr))
     return int(np.flatnonzero(rows != h.col)[0])

@@ -65,6 +65,30 @@ def test_batch_equals_solo(ctx, mix, prec):
             assert np.array_equal(ub.cpu().numpy(), u), (rep, i)
 
 
+def test_batch_lu_equals_solo(ctx, mix):
+    """DDM-LU (exact local solves) batched: same bits and iterations as solo; the
+    one-sub-mesh problem with its exact local solve converges at once."""
+    print("[gpu] batch vs solo DDM-LU", flush=True)
+    model = dg.Model(ctx, SMOOTHER)
+    opts = dg.default_opts(krylov=dg.PCG, local_solver=dg.LOCAL_LU, prolong=dg.PROLONG_UNWEIGHTED,
+                           precision="fp64", rtol=1e-8, max_it=500)
+    solo = _solo(ctx, model, mix, opts)
+    probs = [dg.Problem(ctx, hp, model) for _, hp in mix]
+    outs = [torch.empty(p.n, dtype=torch.float64, device="cuda") for p, _ in mix]
+    sts = dg.solve_batch(ctx, probs, outs, opts)
+    for i, ((u, it, status), ub, st) in enumerate(zip(solo, outs, sts)):
+        print(f"[gpu]   problem {i}: iterations solo={it} batch={st.iterations} kernel={st.dss_kernel}", flush=True)
+        assert status == 0 and st.status == 0 and st.converged and st.dss_kernel == 3
+        assert st.iterations == it
+        assert np.array_equal(ub.cpu().numpy(), u), i
+    one = [i for i, spec in enumerate(SPECS) if spec[2] == 1][0]
+    assert sts[one].iterations <= 2
+    # the inverses are held on the device: sum k_i^2 doubles more than before
+    hp = mix[1][1]
+    k = np.diff(hp.sub_ptr).astype(np.int64)
+    assert probs[1].device_bytes() >= int((k * k).sum()) * 8
+
+
 def test_batch_order_and_eager(ctx, mix):
     """Member order and eager launches do not change any member's result."""
     print("[gpu] batch order / eager", flush=True)
@@ -148,6 +172,31 @@ def test_server_matches_solo(ctx, mix):
     assert rc == 0 and st.iterations == solo64[0][1] and np.array_equal(u, solo64[0][0])
     with pytest.raises(KeyError):
         srv.poll(t64)
+    srv.close()
+
+
+def test_server_lu_and_gnn_groups(ctx, mix):
+    """DDM-LU requests (inverses built by the setup workers) and DDM-GNN requests
+    in one stream: each group batches on its own, results equal the solo solves."""
+    print("[gpu] server DDM-LU / DDM-GNN", flush=True)
+    model = dg.Model(ctx, SMOOTHER)
+    lu = dg.default_opts(krylov=dg.PCG, local_solver=dg.LOCAL_LU, prolong=dg.PROLONG_UNWEIGHTED,
+                         precision="fp64", rtol=1e-8, max_it=500, check_every=4)
+    gnn = dg.default_opts(precision="fp32", rtol=1e-6, max_it=3000, check_every=4)
+    solo_lu = _solo(ctx, model, mix, lu)
+    solo_gnn = _solo(ctx, model, mix[:2], gnn)
+    torch.cuda.synchronize()
+    sctx = dg.Context(torch.cuda.Stream())
+    srv = dg.Server(sctx, model, hbm_budget=8 << 30, max_active=4, setup_threads=2)
+    t_lu = [srv.submit(hp, lu) for _, hp in mix]
+    t_gnn = [srv.submit(hp, gnn) for _, hp in mix[:2]]
+    srv.drain()
+    for tickets, solo in ((t_lu, solo_lu), (t_gnn, solo_gnn)):
+        for t, (u0, it, _) in zip(tickets, solo):
+            rc, st, u = srv.poll(t)
+            print(f"[gpu]   ticket {t}: rc={rc} iterations={st.iterations} solo={it}", flush=True)
+            assert rc == 0 and st.converged and st.iterations == it
+            assert np.array_equal(u, u0)
     srv.close()
 
 

@@ -259,6 +259,60 @@ def test_krylov_modes(ctx, c1):
     assert st.converged and abs(st.iterations - ref.iterations) <= 1
 
 
+@pytest.mark.parametrize("prolong", [dg.PROLONG_UNWEIGHTED, dg.PROLONG_POU])
+def test_lu_apply_matches_oracle(ctx, c1, prolong):
+    """DDM-LU (eq. (7)): exact local solves, coarse solve and glue, FP64 throughout."""
+    print(f"[gpu] DDM-LU apply prolong={prolong}", flush=True)
+    p, hp = c1
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, XAVIER))
+    r = np.random.default_rng(4).standard_normal(p.n)
+    r[p.mesh.dirichlet == 1] = 0
+    z = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    prob.apply(_dev(r), z, dg.default_opts(local_solver=dg.LOCAL_LU, prolong=prolong))
+    s, _, _, loc = [t.cpu().numpy() for t in prob.intermediates()]
+    dec = dc.Decomposition(p.n, hp.sub_ptr, hp.sub_nodes, hp.weights)
+    M = sw.DDMLU(p.A.to_scipy(), p.mesh.dirichlet, dec,
+                 prolong="pou" if prolong == dg.PROLONG_POU else "unweighted")
+    import scipy.linalg as sla
+    worst = 0.0
+    for i in range(hp.K):
+        sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
+        ri = r[hp.sub_nodes[sl]]
+        assert abs(s[i] - np.linalg.norm(ri)) <= 1e-14 * np.linalg.norm(ri)
+        ref = sla.cho_solve(M.factors[i], ri)
+        worst = max(worst, np.abs(loc[sl] - ref).max() / np.abs(ref).max())
+    print(f"[gpu]   local solves worst relative error {worst:.3e}", flush=True)
+    assert worst <= 1e-10
+    zg = z.cpu().numpy()
+    ref_z = M(r)
+    assert np.all(zg[p.mesh.dirichlet == 1] == 0)
+    assert np.abs(zg - ref_z).max() <= 1e-10 * np.abs(ref_z).max()
+    z2 = torch.empty_like(z)
+    prob.apply(_dev(r), z2, dg.default_opts(local_solver=dg.LOCAL_LU, prolong=prolong))
+    assert torch.equal(z, z2)
+
+
+@pytest.mark.parametrize("krylov", [dg.PCG, dg.FCG])
+def test_lu_solve_matches_oracle(ctx, c1, krylov):
+    print(f"[gpu] DDM-LU solve krylov={krylov}", flush=True)
+    p, hp = c1
+    A = p.A.to_scipy()
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, SMOOTHER))
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    st = prob.solve(u, dg.default_opts(krylov=krylov, local_solver=dg.LOCAL_LU, precision="fp64",
+                                       prolong=dg.PROLONG_UNWEIGHTED, rtol=1e-10, max_it=500))
+    dec = dc.Decomposition(p.n, hp.sub_ptr, hp.sub_nodes, hp.weights)
+    M = sw.DDMLU(A, p.mesh.dirichlet, dec, prolong="unweighted")
+    solve = kr.pcg if krylov == dg.PCG else kr.fcg
+    ref = solve(A, p.b, p.u0, M, 1e-10, max_it=500)
+    print(f"[gpu]   iterations gpu={st.iterations} oracle={ref.iterations} kernel={st.dss_kernel}", flush=True)
+    assert st.dss_kernel == 3
+    assert ref.converged and st.converged and abs(st.iterations - ref.iterations) <= 1
+    assert st.true_rel_residual <= 2e-10
+    ug = u.cpu().numpy()
+    assert np.linalg.norm(ug - ref.u) / np.linalg.norm(ref.u) <= 1e-8
+
+
 def test_xavier_history_matches_oracle(ctx, c1):
     """The seeded (untrained) model stagnates; the GPU recurrence tracks the oracle's."""
     print("[gpu] xavier history", flush=True)
