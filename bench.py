@@ -40,6 +40,7 @@ FP16_PACKED_TF = FP32_VALU_TF  # packed FP16 VALU: two FP16 lanes per FP32 lane,
 BF16_MFMA_TF = 2500.0   # dense BF16 matrix-core peak
 HBM_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dss_mfma_kernel_c3_bf16_traffic.md")
+LU_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lu_local_kernel_c3_traffic.md")
 PMC_COPY_BYTES = 1 << 30
 
 
@@ -112,13 +113,18 @@ def bench_lu(dg, prob, u, hp, steps: int) -> dict:
     nbytes = lu_local_bytes(hp.K, int(k.sum()), int((k * k).sum()))
     local_ms = sp.dss_ms / n_it
     achieved = nbytes / (local_ms * 1e-3) / 1e9
+    from paper_2402_08296_amd import profiling
+    tr = profiling.read_traffic(LU_TRAFFIC_FILE)
+    traffic = None
+    if tr and tr.get("source_hash") == profiling.source_hash("lu_local_kernel"):
+        traffic = tr["traffic_bytes_per_dispatch"]
     return {"krylov": "PCG", "prolong": "unweighted", "iterations": st.iterations, "converged": bool(st.converged),
             "true_rel_residual": st.true_rel_residual, "time_to_solution_ms": 1e3 * elapsed,
             "solves_per_s": 1.0 / elapsed, "host_setup_s": setup_s, "device_bytes": prob.device_bytes(),
             "breakdown_ms_per_iteration": {"local": local_ms, "coarse": sp.coarse_ms / n_it,
                                            "prolong": sp.prolong_ms / n_it, "krylov": sp.krylov_ms / n_it},
             "roofline": {"kernel": "lu_local_kernel", "bound": "hbm", "achieved": achieved, "peak": HBM_GBPS,
-                         "unit": "GB/s", "frac": achieved / HBM_GBPS, "bytes_per_launch": nbytes,
+                         "unit": "GB/s", "frac": achieved / HBM_GBPS, "traffic": traffic, "bytes_per_launch": nbytes,
                          "avg_launch_ms": local_ms}}
 
 
@@ -272,7 +278,11 @@ def pmc_workload(args):
     for _ in range(6):
         prob.apply(r, z, opts)
     torch.cuda.synchronize()
-    log(f"pmc workload done: 3 copies of {PMC_COPY_BYTES} B, 6 applies ({args.precision})")
+    lu = dg.default_opts(local_solver=dg.LOCAL_LU, prolong=dg.PROLONG_UNWEIGHTED)
+    for _ in range(4):
+        prob.apply(r, z, lu)
+    torch.cuda.synchronize()
+    log(f"pmc workload done: 3 copies of {PMC_COPY_BYTES} B, 6 DSS applies ({args.precision}), 4 DDM-LU applies")
 
 
 def main():
@@ -369,7 +379,7 @@ def main():
     abytes = apply_bytes(prob.n, prob.K, prob.sum_k, prob.n_edges, 8 if args.precision == "fp64" else 4)
     traffic = None
     tr = profiling.read_traffic(TRAFFIC_FILE)
-    if tr and sp.dss_kernel == 2 and tr.get("source_hash") == profiling.source_hash():
+    if tr and sp.dss_kernel == 2 and tr.get("source_hash") == profiling.source_hash("dss_mfma_kernel"):
         traffic = tr["traffic_bytes_per_dispatch"]
     iters = stats[-1][0]
     out = {

@@ -18,7 +18,7 @@ namespace ddmgnn {
 constexpr int D = 10;           // latent width (Sec. IV.B)
 constexpr int MAX_M = 4;        // largest FCG truncation supported
 constexpr int VEC_BLOCK = 256;  // threads of the vector kernels
-constexpr int VEC_GRID = 512;   // max workgroups per problem in the vector kernels (each pays a fenced ticket in every reduction)
+constexpr int VEC_GRID = 1024;  // max workgroups per problem in the vector kernels
 constexpr int DSS_BLOCK = 512;  // threads of the VALU DSS kernel
 constexpr size_t LDS_LIMIT = 160 * 1024;
 

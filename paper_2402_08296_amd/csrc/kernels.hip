@@ -652,16 +652,38 @@ __global__ __launch_bounds__(VEC_BLOCK) void pupdate_kernel(const DevProb* __res
                  st->beta[2], st->beta[3], m, g.lb * VEC_BLOCK + threadIdx.x, P.nblk * VEC_BLOCK, P.n);
 }
 
-__device__ __forceinline__ void spmv_dots_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                               const double* __restrict__ val, const double* __restrict__ p,
-                                               double* __restrict__ q, const double* __restrict__ r, int i0,
-                                               int stride, int n, double (&d)[2]) {
-    for (int i = i0; i < n; i += stride) {
+// CSR SpMV in groups of VEC_BLOCK consecutive rows (group g of the problem is
+// handled by workgroup g mod nblk). The group's nonzeros are contiguous in CSR:
+// they are staged through LDS with coalesced loads (value, and the gathered
+// x(col)), then thread t sums row r0 + t in CSR order with the same fused
+// multiply-add chain as a row-per-thread loop. A group with more than
+// SPMV_CHUNK nonzeros is read row by row from global memory instead.
+constexpr int SPMV_CHUNK = 2048;
+
+template <class XF, class RowF>
+__device__ __forceinline__ void spmv_groups(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                                            const double* __restrict__ val, int n, int lb, int nblk, XF xof,
+                                            RowF row_done) {
+    __shared__ double sv[SPMV_CHUNK], sx[SPMV_CHUNK];
+    const int tid = threadIdx.x;
+    for (int r0 = lb * VEC_BLOCK; r0 < n; r0 += nblk * VEC_BLOCK) {
+        const int r1 = min(n, r0 + VEC_BLOCK);
+        const int e0 = rowptr[r0], e1 = rowptr[r1];
+        const int row = r0 + tid;
         double acc = 0.0;
-        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc = fma(val[e], p[col[e]], acc);
-        q[i] = acc;
-        d[0] = fma(p[i], acc, d[0]);
-        d[1] = fma(p[i], r[i], d[1]);
+        if (e1 - e0 <= SPMV_CHUNK) {  // uniform over the workgroup
+            for (int e = e0 + tid; e < e1; e += VEC_BLOCK) {
+                sv[e - e0] = val[e];
+                sx[e - e0] = xof(col[e]);
+            }
+            __syncthreads();
+            if (row < r1)
+                for (int e = rowptr[row]; e < rowptr[row + 1]; ++e) acc = fma(sv[e - e0], sx[e - e0], acc);
+            __syncthreads();
+        } else if (row < r1) {
+            for (int e = rowptr[row]; e < rowptr[row + 1]; ++e) acc = fma(val[e], xof(col[e]), acc);
+        }
+        if (row < r1) row_done(row, acc);
     }
 }
 
@@ -673,29 +695,17 @@ __global__ __launch_bounds__(VEC_BLOCK) void spmv_dots_kernel(const DevProb* __r
     KState* st = P.st;
     if (st->done) return;
     const int slot = ring_cur(st->it, ia.m);
+    const double* __restrict__ p = P.p[slot];
+    double* __restrict__ q = P.q[slot];
+    const double* __restrict__ r = P.r;
     double d[2] = {0.0, 0.0};
-    spmv_dots_rows(P.rowptr, P.col, P.val, P.p[slot], P.q[slot], P.r, g.lb * VEC_BLOCK + threadIdx.x,
-                   P.nblk * VEC_BLOCK, P.n, d);
+    spmv_groups(P.rowptr, P.col, P.val, P.n, g.lb, P.nblk, [&](int c) { return p[c]; },
+                [&](int i, double acc) {
+                    q[i] = acc;
+                    d[0] = fma(p[i], acc, d[0]);
+                    d[1] = fma(p[i], r[i], d[1]);
+                });
     put_partials<2>(d, P.partials, g.lb);
-}
-
-__device__ __forceinline__ void spmv_p_dots_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                                                 const double* __restrict__ val, const double* __restrict__ z,
-                                                 const double* __restrict__ p_old, double* __restrict__ p_new,
-                                                 double* __restrict__ q, const double* __restrict__ r, double beta,
-                                                 int i0, int stride, int n, double (&d)[2]) {
-    for (int i = i0; i < n; i += stride) {
-        double acc = 0.0;
-        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-            const int c = col[e];
-            acc = fma(val[e], fma(beta, p_old[c], z[c]), acc);
-        }
-        const double pi = fma(beta, p_old[i], z[i]);
-        p_new[i] = pi;
-        q[i] = acc;
-        d[0] = fma(pi, acc, d[0]);
-        d[1] = fma(pi, r[i], d[1]);
-    }
 }
 
 // One kept direction (FCG(1), PCG, CG): p_new = z + beta p_old is formed on the
@@ -710,9 +720,21 @@ __global__ __launch_bounds__(VEC_BLOCK) void spmv_p_dots_kernel(const DevProb* _
     if (st->done) return;
     const int it = st->it;
     const int slot = ring_cur(it, 1);
+    const double* __restrict__ z = dir_src(P, ia.mode);
+    const double* __restrict__ p_old = P.p[ring_prev(it, 1, 0)];
+    double* __restrict__ p_new = P.p[slot];
+    double* __restrict__ q = P.q[slot];
+    const double* __restrict__ r = P.r;
+    const double beta = st->beta[0];
     double d[2] = {0.0, 0.0};
-    spmv_p_dots_rows(P.rowptr, P.col, P.val, dir_src(P, ia.mode), P.p[ring_prev(it, 1, 0)], P.p[slot], P.q[slot],
-                     P.r, st->beta[0], g.lb * VEC_BLOCK + threadIdx.x, P.nblk * VEC_BLOCK, P.n, d);
+    spmv_groups(P.rowptr, P.col, P.val, P.n, g.lb, P.nblk, [&](int c) { return fma(beta, p_old[c], z[c]); },
+                [&](int i, double acc) {
+                    const double pi = fma(beta, p_old[i], z[i]);
+                    p_new[i] = pi;
+                    q[i] = acc;
+                    d[0] = fma(pi, acc, d[0]);
+                    d[1] = fma(pi, r[i], d[1]);
+                });
     put_partials<2>(d, P.partials, g.lb);
 }
 

@@ -22,13 +22,16 @@ import re
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# Sources whose change invalidates a traffic measurement of the MFMA DSS kernel.
-KERNEL_SOURCES = ("csrc/dss_mfma.hip", "csrc/dss_mfma.h", "csrc/device.h")
+# Sources whose change invalidates a traffic measurement of a kernel.
+KERNEL_SOURCES = {
+    "dss_mfma_kernel": ("csrc/dss_mfma.hip", "csrc/dss_mfma.h", "csrc/device.h"),
+    "lu_local_kernel": ("csrc/kernels.hip", "csrc/device.h"),
+}
 
 
-def source_hash() -> str:
+def source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[kernel]:
         with open(os.path.join(HERE, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -93,7 +96,7 @@ def traffic_summary(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int
         "fetch_scale": f_fetch, "write_scale": f_write,
         "fetch_bytes_per_dispatch": fetch_b, "write_bytes_per_dispatch": write_b,
         "traffic_bytes_per_dispatch": fetch_b + write_b,
-        "source_hash": source_hash(), "fetch_command": fetch_cmd, "write_command": write_cmd,
+        "source_hash": source_hash(kernel), "fetch_command": fetch_cmd, "write_command": write_cmd,
     }
 
 
