@@ -74,7 +74,10 @@ int ddmgnn_ctx_create(void* hip_stream, ddmgnn_ctx** out);
 int ddmgnn_ctx_destroy(ddmgnn_ctx* ctx);
 
 /* DSS_theta hyper-parameters (Sec. IV.B: kbar = 30, d = 10, hidden width d,
- * alpha = 1e-3). Only d = 10 is compiled in this build. */
+ * alpha = 1e-3; Table II sweeps kbar and d). kbar >= 1 is a run-time value;
+ * d is 5, 10 or 20 (E_INVALID otherwise). The BF16 matrix-core kernel runs
+ * d = 10 only: a BF16 solve with another width runs the FP32 VALU kernel
+ * (ddmgnn_stats.dss_kernel says which ran). */
 typedef struct {
     int32_t kbar;
     int32_t d;

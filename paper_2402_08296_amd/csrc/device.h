@@ -15,10 +15,11 @@
 
 namespace ddmgnn {
 
-constexpr int D = 10;           // latent width (Sec. IV.B)
+constexpr int D = 10;           // latent width of the paper's model (Sec. IV.B); the MFMA kernel's width
 constexpr int MAX_M = 4;        // largest FCG truncation supported
 constexpr int VEC_BLOCK = 256;  // threads of the vector kernels
 constexpr int VEC_GRID = 1024;  // max workgroups per problem in the vector kernels
+constexpr int N_XCD = 8;        // accelerator dies; workgroups are dispatched to them round-robin
 constexpr int DSS_BLOCK = 512;  // threads of the VALU DSS kernel
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
@@ -121,10 +122,10 @@ __host__ __device__ inline int ring_prev(int it, int m, int k) {
 // Launchers (kernels.hip). tab: device table; the int2 lists are device
 // arrays of (problem, item) pairs, one per workgroup. check = false skips
 // hipGetLastError (not allowed while a stream is being captured).
-hipError_t prepare_dss_valu(int precision, size_t shmem);
-hipError_t launch_dss_valu(const DevProb* tab, const int2* work, int n_work, int precision, bool qlds, int kbar,
-                           double alpha, int apply, const float* theta32, const double* theta64, size_t shmem,
-                           hipStream_t s, bool check);
+hipError_t prepare_dss_valu(int precision, int d, size_t shmem);
+hipError_t launch_dss_valu(const DevProb* tab, const int2* work, int n_work, int precision, int d, bool qlds,
+                           int kbar, double alpha, int apply, const float* theta32, const double* theta64,
+                           size_t shmem, hipStream_t s, bool check);
 // Exact local solves (DDM-LU): restriction as in the DSS kernels, then
 // local = (R_i A R_i^T)^{-1} R_i r per sub-mesh.
 hipError_t launch_lu_local(const DevProb* tab, const int2* work, int n_work, hipStream_t s, bool check);
@@ -144,9 +145,15 @@ hipError_t launch_dot(const double* x, const double* y, int64_t n, double* parti
                       hipStream_t s);
 
 // Workgroups a problem of n rows takes in the vector kernels.
+// Workgroups of a problem in the vector kernels: one per VEC_BLOCK rows up to
+// VEC_GRID, rounded up to a multiple of N_XCD (so that a problem's workgroups
+// start on die 0 in every launch and split evenly over the dies).
 inline int vec_blocks(int64_t n) {
-    const int64_t g = (n + VEC_BLOCK - 1) / VEC_BLOCK;
-    return (int)(g < 1 ? 1 : (g > VEC_GRID ? VEC_GRID : g));
+    int64_t g = (n + VEC_BLOCK - 1) / VEC_BLOCK;
+    g = g > VEC_GRID ? VEC_GRID : g;
+    g = (g + N_XCD - 1) / N_XCD * N_XCD;
+    return (int)(g < N_XCD ? N_XCD : g);
 }
+static_assert(VEC_GRID % N_XCD == 0, "vector grid must split over the dies");
 
 }  // namespace ddmgnn

@@ -412,24 +412,43 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
                 // (lanes past the end of the sub-mesh read sentinel records).
                 const uint32_t* Et = E + (tn.e0 & 0xffffff) + n;
                 const int nch = __builtin_amdgcn_readfirstlane((int)((uint32_t)tn.e0 >> 24));
-                for (int ch = 0; ch < nch; ++ch) {
-                    uint32_t rec[EC];
+                // The records of the next chunk are in flight while a chunk's sums
+                // run; a load past the last chunk re-reads the last chunk (clamped
+                // index) and goes unused.
+                auto ld_rec = [&](int ch, uint32_t (&r)[EC]) {
+                    const int c = min(ch, nch - 1);
 #pragma unroll
-                    for (int w = 0; w < EC; ++w) rec[w] = Et[(ch * EC + w) * MFMA_TILE];
-                    h2 qq[EC][5];
+                    for (int w = 0; w < EC; ++w) r[w] = Et[(c * EC + w) * MFMA_TILE];
+                };
+                auto ld_q = [&](const uint32_t (&r)[EC], h2 (&q)[EC][5]) {
 #pragma unroll
                     for (int w = 0; w < EC; ++w) {
-                        const h2* q = reinterpret_cast<const h2*>(reinterpret_cast<const char*>(Qh) + (rec[w] >> 16));
+                        const h2* row = reinterpret_cast<const h2*>(reinterpret_cast<const char*>(Qh) + (r[w] >> 16));
 #pragma unroll
-                        for (int t = 0; t < 5; ++t) qq[w][t] = q[t];
+                        for (int t = 0; t < 5; ++t) q[w][t] = row[t];
                     }
+                };
+                auto sums = [&](const uint32_t (&r)[EC], const h2 (&q)[EC][5]) {
 #pragma unroll
                     for (int w = 0; w < EC; ++w) {
-                        const _Float16 ndh = __builtin_bit_cast(_Float16, (uint16_t)(rec[w] & 0xffffu));
+                        const _Float16 ndh = __builtin_bit_cast(_Float16, (uint16_t)(r[w] & 0xffffu));
                         const h2 nd = {ndh, ndh};
 #pragma unroll
                         for (int t = 0; t < 5; ++t)
-                            S[t] += __builtin_elementwise_max(__builtin_elementwise_fma(wn[t], nd, P[t] + qq[w][t]), hzero);
+                            S[t] += __builtin_elementwise_max(__builtin_elementwise_fma(wn[t], nd, P[t] + q[w][t]), hzero);
+                    }
+                };
+                if (nch > 0) {
+                    uint32_t r0[EC];
+                    ld_rec(0, r0);
+                    for (int ch = 0; ch < nch; ++ch) {
+                        h2 q[EC][5];
+                        ld_q(r0, q);
+                        uint32_t r1[EC];
+                        ld_rec(ch + 1, r1);
+                        sums(r0, q);
+#pragma unroll
+                        for (int w = 0; w < EC; ++w) r0[w] = r1[w];
                     }
                 }
                 const float c = cbuf[j];

@@ -26,14 +26,19 @@ namespace ddmgnn {
 
 namespace {
 
-constexpr int IN_PHI = 2 * D + 3;                  // (h_j, h_l, d, |d|)
-constexpr int IN_PSI = 3 * D + 1;                  // (h_j, c_j, phi_out, phi_in)
-constexpr int OFF_PO = 0;                          // Phi_out
-constexpr int OFF_PI = OFF_PO + D * IN_PHI + D + D * D + D;
-constexpr int OFF_PS = OFF_PI + D * IN_PHI + D + D * D + D;
-constexpr int OFF_DE = OFF_PS + D * IN_PSI + D + D * D + D;
-constexpr int BLOCK_W = OFF_DE + D * D + D + D + 1;  // 11 d^2 + 15 d + 1
-static_assert(BLOCK_W == 1251, "weight block size");
+// Offsets in one weight block of latent width W (Sec. III.B; Table II counts).
+template <int W>
+struct DssLayout {
+    static constexpr int IN_PHI = 2 * W + 3;                  // (h_j, h_l, d, |d|)
+    static constexpr int IN_PSI = 3 * W + 1;                  // (h_j, c_j, phi_out, phi_in)
+    static constexpr int OFF_PO = 0;                          // Phi_out
+    static constexpr int OFF_PI = OFF_PO + W * IN_PHI + W + W * W + W;
+    static constexpr int OFF_PS = OFF_PI + W * IN_PHI + W + W * W + W;
+    static constexpr int OFF_DE = OFF_PS + W * IN_PSI + W + W * W + W;
+    static constexpr int BLOCK_W = OFF_DE + W * W + W + W + 1;  // 11 d^2 + 15 d + 1
+};
+static_assert(DssLayout<10>::BLOCK_W == 1251 && DssLayout<5>::BLOCK_W == 351 && DssLayout<20>::BLOCK_W == 4701,
+              "weight block size");
 constexpr int DSS_NPT = (kMaxSubNodes + DSS_BLOCK - 1) / DSS_BLOCK;
 
 // Which reduction a finalize launch completes.
@@ -148,6 +153,21 @@ __device__ inline Seg seg(const DevProb* __restrict__ tab, const int2* __restric
     return {tab + w.x, w.y};
 }
 
+// Row groups (VEC_BLOCK consecutive rows each) of local workgroup lb of a
+// problem with nblk workgroups (a multiple of N_XCD, the problem's first
+// workgroup on die 0): the workgroups one die runs take one contiguous slab of
+// groups, g0, g0 + gs, ... < g1, so a die's rows, their matrix columns and the
+// vectors one kernel writes and the next reads stay in that die's L2. Every
+// vector kernel uses the same map.
+struct Rows {
+    int g0, g1, gs;
+};
+__device__ inline Rows rows_of(int lb, int nblk, int n) {
+    const int G = (n + VEC_BLOCK - 1) / VEC_BLOCK;
+    const int x = lb % N_XCD;
+    return {(int)((int64_t)G * x / N_XCD) + lb / N_XCD, (int)((int64_t)G * (x + 1) / N_XCD), nblk / N_XCD};
+}
+
 // ------------------------------------------------------------------ DSS forward (VALU)
 template <typename T>
 struct DssArgs {
@@ -172,8 +192,11 @@ __device__ inline double relu(double x) { return fmax(x, 0.0); }
 // carry it), so an edge only adds w_|d| |d_jl|; coordinates are centred on the
 // sub-mesh to keep the cancellation small. Used for FP32; the FP64 path
 // evaluates W1_d d_jl per edge.
-template <typename T, bool HREG, bool QLDS>
+template <typename T, int D, bool HREG, bool QLDS>
 __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* __restrict__ theta) {
+    using L = DssLayout<D>;
+    constexpr int IN_PHI = L::IN_PHI, IN_PSI = L::IN_PSI, BLOCK_W = L::BLOCK_W;
+    constexpr int OFF_PO = L::OFF_PO, OFF_PI = L::OFF_PI, OFF_PS = L::OFF_PS, OFF_DE = L::OFF_DE;
     constexpr bool SEP = sizeof(T) == 4;
     const int2 wi = a.work[blockIdx.x];
     const DevProb& P = a.tab[wi.x];
@@ -554,8 +577,10 @@ __device__ __forceinline__ void prolong_rows(const int32_t* __restrict__ node_pt
                                              const double* __restrict__ r, double* __restrict__ z,
                                              const double* __restrict__ q0, const double* __restrict__ q1,
                                              const double* __restrict__ q2, const double* __restrict__ q3, int m,
-                                             bool unweighted, int i0, int stride, int n, double (&dots)[MAX_M + 1]) {
-    for (int i = i0; i < n; i += stride) {
+                                             bool unweighted, Rows rg, int n, double (&dots)[MAX_M + 1]) {
+    for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
+        const int i = gi * VEC_BLOCK + threadIdx.x;
+        if (i >= n) continue;
         double zn = 0.0;
         if (!dirichlet[i]) {
             for (int q = node_ptr[i]; q < node_ptr[i + 1]; ++q) {
@@ -592,17 +617,17 @@ __global__ __launch_bounds__(VEC_BLOCK) void prolong_kernel(const DevProb* __res
     const double* y = ia.coarse ? P.y : nullptr;
     double dots[MAX_M + 1];
     for (int i = 0; i <= MAX_M; ++i) dots[i] = 0.0;
-    const int i0 = g.lb * VEC_BLOCK + threadIdx.x, stride = P.nblk * VEC_BLOCK;
+    const Rows rg = rows_of(g.lb, P.nblk, P.n);
     const bool uw = ia.unweighted;
     if (mode == DDMGNN_FCG)
         prolong_rows<DDMGNN_FCG>(P.node_ptr, P.node_slots, P.slot_sub, P.weights, P.local, y, P.dirichlet, P.r,
-                                 P.z, qk[0], qk[1], qk[2], qk[3], m, uw, i0, stride, P.n, dots);
+                                 P.z, qk[0], qk[1], qk[2], qk[3], m, uw, rg, P.n, dots);
     else if (mode == DDMGNN_PCG)
         prolong_rows<DDMGNN_PCG>(P.node_ptr, P.node_slots, P.slot_sub, P.weights, P.local, y, P.dirichlet, P.r,
-                                 P.z, nullptr, nullptr, nullptr, nullptr, m, uw, i0, stride, P.n, dots);
+                                 P.z, nullptr, nullptr, nullptr, nullptr, m, uw, rg, P.n, dots);
     else
         prolong_rows<-1>(P.node_ptr, P.node_slots, P.slot_sub, P.weights, P.local, y, P.dirichlet, P.r, P.z,
-                         nullptr, nullptr, nullptr, nullptr, m, uw, i0, stride, P.n, dots);
+                         nullptr, nullptr, nullptr, nullptr, m, uw, rg, P.n, dots);
     if (mode < 0) return;
     put_partials<MAX_M + 1>(dots, P.partials, g.lb);
 }
@@ -627,8 +652,10 @@ __device__ inline void set_alpha(KState* st, const double (&tot)[2], int mode, i
 __device__ __forceinline__ void pupdate_rows(const double* __restrict__ z, double* __restrict__ pn,
                                              const double* __restrict__ p0, const double* __restrict__ p1,
                                              const double* __restrict__ p2, const double* __restrict__ p3, double b0,
-                                             double b1, double b2, double b3, int m, int i0, int stride, int n) {
-    for (int i = i0; i < n; i += stride) {
+                                             double b1, double b2, double b3, int m, Rows rg, int n) {
+    for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
+        const int i = gi * VEC_BLOCK + threadIdx.x;
+        if (i >= n) continue;
         double p = fma(b0, p0[i], z[i]);
         if (m > 1) p = fma(b1, p1[i], p);
         if (m > 2) p = fma(b2, p2[i], p);
@@ -649,11 +676,10 @@ __global__ __launch_bounds__(VEC_BLOCK) void pupdate_kernel(const DevProb* __res
     for (int i = 0; i < MAX_M; ++i)
         if (i < m) pk[i] = P.p[ring_prev(it, m, i)];
     pupdate_rows(dir_src(P, ia.mode), P.p[ring_cur(it, m)], pk[0], pk[1], pk[2], pk[3], st->beta[0], st->beta[1],
-                 st->beta[2], st->beta[3], m, g.lb * VEC_BLOCK + threadIdx.x, P.nblk * VEC_BLOCK, P.n);
+                 st->beta[2], st->beta[3], m, rows_of(g.lb, P.nblk, P.n), P.n);
 }
 
-// CSR SpMV in groups of VEC_BLOCK consecutive rows (group g of the problem is
-// handled by workgroup g mod nblk). The group's nonzeros are contiguous in CSR:
+// CSR SpMV in groups of VEC_BLOCK consecutive rows (the groups of rows_of). The group's nonzeros are contiguous in CSR:
 // they are staged through LDS with coalesced loads (value, and the gathered
 // x(col)), then thread t sums row r0 + t in CSR order with the same fused
 // multiply-add chain as a row-per-thread loop. A group with more than
@@ -666,7 +692,9 @@ __device__ __forceinline__ void spmv_groups(const int32_t* __restrict__ rowptr, 
                                             RowF row_done) {
     __shared__ double sv[SPMV_CHUNK], sx[SPMV_CHUNK];
     const int tid = threadIdx.x;
-    for (int r0 = lb * VEC_BLOCK; r0 < n; r0 += nblk * VEC_BLOCK) {
+    const Rows rg = rows_of(lb, nblk, n);
+    for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
+        const int r0 = gi * VEC_BLOCK;
         const int r1 = min(n, r0 + VEC_BLOCK);
         const int e0 = rowptr[r0], e1 = rowptr[r1];
         const int row = r0 + tid;
@@ -740,8 +768,10 @@ __global__ __launch_bounds__(VEC_BLOCK) void spmv_p_dots_kernel(const DevProb* _
 
 __device__ __forceinline__ void update_rows(double* __restrict__ u, double* __restrict__ r,
                                             const double* __restrict__ p, const double* __restrict__ q, double alpha,
-                                            int i0, int stride, int n, double (&d)[1]) {
-    for (int i = i0; i < n; i += stride) {
+                                            Rows rg, int n, double (&d)[1]) {
+    for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
+        const int i = gi * VEC_BLOCK + threadIdx.x;
+        if (i >= n) continue;
         u[i] = fma(alpha, p[i], u[i]);
         const double ri = fma(-alpha, q[i], r[i]);
         r[i] = ri;
@@ -758,16 +788,17 @@ __global__ __launch_bounds__(VEC_BLOCK) void update_kernel(const DevProb* __rest
     if (st->done) return;
     const int slot = ring_cur(st->it, ia.m);
     double d[1] = {0.0};
-    update_rows(P.u, P.r, P.p[slot], P.q[slot], st->alpha, g.lb * VEC_BLOCK + threadIdx.x, P.nblk * VEC_BLOCK, P.n,
-                d);
+    update_rows(P.u, P.r, P.p[slot], P.q[slot], st->alpha, rows_of(g.lb, P.nblk, P.n), P.n, d);
     put_partials<1>(d, P.partials, g.lb);
 }
 
 __device__ __forceinline__ void residual_rows(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                               const double* __restrict__ val, const double* __restrict__ b,
                                               const double* __restrict__ u, double* __restrict__ u_copy,
-                                              double* __restrict__ r, int i0, int stride, int n, double (&d)[1]) {
-    for (int i = i0; i < n; i += stride) {
+                                              double* __restrict__ r, Rows rg, int n, double (&d)[1]) {
+    for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
+        const int i = gi * VEC_BLOCK + threadIdx.x;
+        if (i >= n) continue;
         double acc = 0.0;
         for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc = fma(val[e], u[col[e]], acc);
         const double ri = b[i] - acc;
@@ -782,15 +813,18 @@ __global__ __launch_bounds__(VEC_BLOCK) void init_kernel(const DevProb* __restri
                                                         const int2* __restrict__ blk) {
     const Seg g = seg(tab, blk);
     const DevProb& P = *g.P;
-    const int i0 = g.lb * VEC_BLOCK + threadIdx.x, stride = P.nblk * VEC_BLOCK;
+    const Rows rg = rows_of(g.lb, P.nblk, P.n);
     double d[1] = {0.0};
-    residual_rows(P.rowptr, P.col, P.val, P.b, P.u0, P.u, P.r, i0, stride, P.n, d);
+    residual_rows(P.rowptr, P.col, P.val, P.b, P.u0, P.u, P.r, rg, P.n, d);
     for (int k = 0; k <= MAX_M; ++k) {
         double* __restrict__ pk = P.p[k];
         double* __restrict__ qk = P.q[k];
-        for (int i = i0; i < P.n; i += stride) {
-            pk[i] = 0.0;
-            qk[i] = 0.0;
+        for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
+            const int i = gi * VEC_BLOCK + threadIdx.x;
+            if (i < P.n) {
+                pk[i] = 0.0;
+                qk[i] = 0.0;
+            }
         }
     }
     put_partials<1>(d, P.partials, g.lb);
@@ -802,8 +836,7 @@ __global__ __launch_bounds__(VEC_BLOCK) void resid_kernel(const DevProb* __restr
     const Seg g = seg(tab, blk);
     const DevProb& P = *g.P;
     double d[1] = {0.0};
-    residual_rows(P.rowptr, P.col, P.val, P.b, P.u, nullptr, nullptr, g.lb * VEC_BLOCK + threadIdx.x,
-                  P.nblk * VEC_BLOCK, P.n, d);
+    residual_rows(P.rowptr, P.col, P.val, P.b, P.u, nullptr, nullptr, rows_of(g.lb, P.nblk, P.n), P.n, d);
     put_partials<1>(d, P.partials, g.lb);
 }
 
@@ -910,28 +943,59 @@ inline hipError_t done(bool check) { return check ? hipGetLastError() : hipSucce
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-hipError_t prepare_dss_valu(int precision, size_t shmem) {
-    const void* fn = precision == DDMGNN_FP64 ? (const void*)dss_kernel<double, false, true>
-                                              : (const void*)dss_kernel<float, true, true>;
+namespace {
+template <int W>
+hipError_t prepare_dss_valu_w(int precision, size_t shmem) {
+    const void* fn = precision == DDMGNN_FP64 ? (const void*)dss_kernel<double, W, false, true>
+                                              : (const void*)dss_kernel<float, W, true, true>;
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
 }
 
-hipError_t launch_dss_valu(const DevProb* tab, const int2* work, int n_work, int precision, bool qlds, int kbar,
-                           double alpha, int apply, const float* theta32, const double* theta64, size_t shmem,
-                           hipStream_t s, bool check) {
-    if (n_work <= 0) return hipSuccess;
+template <int W>
+void launch_dss_valu_w(const DevProb* tab, const int2* work, int n_work, int precision, bool qlds, int kbar,
+                       double alpha, int apply, const float* theta32, const double* theta64, size_t shmem,
+                       hipStream_t s) {
     if (precision == DDMGNN_FP64) {
         DssArgs<double> a{tab, work, kbar, alpha, apply};
         if (qlds)
-            hipLaunchKernelGGL((dss_kernel<double, false, true>), dim3(n_work), dim3(DSS_BLOCK), shmem, s, a, theta64);
+            hipLaunchKernelGGL((dss_kernel<double, W, false, true>), dim3(n_work), dim3(DSS_BLOCK), shmem, s, a,
+                               theta64);
         else
-            hipLaunchKernelGGL((dss_kernel<double, false, false>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a, theta64);
+            hipLaunchKernelGGL((dss_kernel<double, W, false, false>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a,
+                               theta64);
     } else {
         DssArgs<float> a{tab, work, kbar, (float)alpha, apply};
         if (qlds)
-            hipLaunchKernelGGL((dss_kernel<float, true, true>), dim3(n_work), dim3(DSS_BLOCK), shmem, s, a, theta32);
+            hipLaunchKernelGGL((dss_kernel<float, W, true, true>), dim3(n_work), dim3(DSS_BLOCK), shmem, s, a,
+                               theta32);
         else
-            hipLaunchKernelGGL((dss_kernel<float, true, false>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a, theta32);
+            hipLaunchKernelGGL((dss_kernel<float, W, true, false>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a,
+                               theta32);
+    }
+}
+}  // namespace
+
+hipError_t prepare_dss_valu(int precision, int d, size_t shmem) {
+    switch (d) {
+        case 5: return prepare_dss_valu_w<5>(precision, shmem);
+        case 10: return prepare_dss_valu_w<10>(precision, shmem);
+        case 20: return prepare_dss_valu_w<20>(precision, shmem);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_dss_valu(const DevProb* tab, const int2* work, int n_work, int precision, int d, bool qlds,
+                           int kbar, double alpha, int apply, const float* theta32, const double* theta64,
+                           size_t shmem, hipStream_t s, bool check) {
+    if (n_work <= 0) return hipSuccess;
+    switch (d) {
+        case 5: launch_dss_valu_w<5>(tab, work, n_work, precision, qlds, kbar, alpha, apply, theta32, theta64,
+                                     shmem, s); break;
+        case 10: launch_dss_valu_w<10>(tab, work, n_work, precision, qlds, kbar, alpha, apply, theta32, theta64,
+                                       shmem, s); break;
+        case 20: launch_dss_valu_w<20>(tab, work, n_work, precision, qlds, kbar, alpha, apply, theta32, theta64,
+                                       shmem, s); break;
+        default: return hipErrorInvalidValue;
     }
     return done(check);
 }

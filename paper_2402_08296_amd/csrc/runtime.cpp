@@ -99,14 +99,14 @@ int upload_list(DevBuf<T>& buf, const std::vector<T>& v, hipStream_t s) {
     return DDMGNN_OK;
 }
 
-bool valu_q_in_lds(int max_k, int precision) {
+bool valu_q_in_lds(int max_k, int precision, int d) {
     const size_t esz = precision == DDMGNN_FP64 ? sizeof(double) : sizeof(float);
-    return (size_t)max_k * 2 * D * esz + 1024 <= LDS_LIMIT;
+    return (size_t)max_k * 2 * d * esz + 1024 <= LDS_LIMIT;
 }
 
-size_t valu_shmem(int max_k, int precision) {
+size_t valu_shmem(int max_k, int precision, int d) {
     const size_t esz = precision == DDMGNN_FP64 ? sizeof(double) : sizeof(float);
-    return (size_t)max_k * 2 * D * esz;
+    return (size_t)max_k * 2 * d * esz;
 }
 
 // Exact local solves: the inverses of R_i A R_i^T, formed on the host from the
@@ -140,6 +140,10 @@ int prepare_lu(ddmgnn_problem* P) {
     return DDMGNN_OK;
 }
 
+// Whether the BF16 MFMA kernel runs problem P (its largest sub-mesh fits the
+// kernel's LDS budget and the model has the paper's latent width).
+bool runs_mfma(const Batch& B, const ddmgnn_problem* P) { return P->mfma_fits && B.model->d == D; }
+
 // Allocates what the DSS launches of this precision need (fallback storage,
 // LDS attributes). Not allowed during stream capture; returns true in
 // `changed` when a problem's buffers moved (the table must be re-uploaded).
@@ -152,26 +156,27 @@ int prepare_dss(Batch& B, int precision, bool& changed) {
     const int n_valu = bf16 ? B.n_rest : B.n_all;
     if (n_valu == 0) return DDMGNN_OK;
     const bool f64 = valu_prec == DDMGNN_FP64;
-    const bool in_lds = valu_q_in_lds(max_k, valu_prec);
+    const int d = B.model->d;
+    const bool in_lds = valu_q_in_lds(max_k, valu_prec, d);
     for (ddmgnn_problem* P : B.probs) {
-        if (bf16 && P->mfma_fits) continue;
+        if (bf16 && runs_mfma(B, P)) continue;
         const size_t sk = (size_t)P->hs.sk;
         if (!in_lds) {
-            if (f64 && P->qglobal64.n < sk * 2 * D) {
-                HIP_TRY(P->qglobal64.alloc(sk * 2 * D));
+            if (f64 && P->qglobal64.n < sk * 2 * d) {
+                HIP_TRY(P->qglobal64.alloc(sk * 2 * d));
                 changed = true;
             }
-            if (!f64 && P->qglobal32.n < sk * 2 * D) {
-                HIP_TRY(P->qglobal32.alloc(sk * 2 * D));
+            if (!f64 && P->qglobal32.n < sk * 2 * d) {
+                HIP_TRY(P->qglobal32.alloc(sk * 2 * d));
                 changed = true;
             }
         }
-        if (f64 && P->hglobal64.n < sk * D) {
-            HIP_TRY(P->hglobal64.alloc(sk * D));
+        if (f64 && P->hglobal64.n < sk * d) {
+            HIP_TRY(P->hglobal64.alloc(sk * d));
             changed = true;
         }
     }
-    if (in_lds) HIP_TRY(prepare_dss_valu(valu_prec, LDS_LIMIT - 1024));
+    if (in_lds) HIP_TRY(prepare_dss_valu(valu_prec, d, LDS_LIMIT - 1024));
     return DDMGNN_OK;
 }
 
@@ -188,14 +193,15 @@ int enqueue_dss(Batch& B, const DevProb* tab, int precision, int apply, bool cap
     if (precision == DDMGNN_BF16) {
         DssMfmaArgs a{tab, B.work_mfma.p, M.steps.p, M.dec.p, M.kbar, (float)M.alpha, apply};
         HIP_TRY(launch_dss_mfma(a, B.n_mfma, MFMA_LDS_LIMIT, s, check));
-        const bool qlds = valu_q_in_lds(B.max_k_rest, DDMGNN_FP32);
-        HIP_TRY(launch_dss_valu(tab, B.work_rest.p, B.n_rest, DDMGNN_FP32, qlds, M.kbar, M.alpha, apply,
-                                M.theta32.p, M.theta64.p, qlds ? valu_shmem(B.max_k_rest, DDMGNN_FP32) : 0, s,
+        const bool qlds = valu_q_in_lds(B.max_k_rest, DDMGNN_FP32, M.d);
+        HIP_TRY(launch_dss_valu(tab, B.work_rest.p, B.n_rest, DDMGNN_FP32, M.d, qlds, M.kbar, M.alpha, apply,
+                                M.theta32.p, M.theta64.p, qlds ? valu_shmem(B.max_k_rest, DDMGNN_FP32, M.d) : 0, s,
                                 check));
     } else {
-        const bool qlds = valu_q_in_lds(B.max_k_all, precision);
-        HIP_TRY(launch_dss_valu(tab, B.work_all.p, B.n_all, precision, qlds, M.kbar, M.alpha, apply, M.theta32.p,
-                                M.theta64.p, qlds ? valu_shmem(B.max_k_all, precision) : 0, s, check));
+        const bool qlds = valu_q_in_lds(B.max_k_all, precision, M.d);
+        HIP_TRY(launch_dss_valu(tab, B.work_all.p, B.n_all, precision, M.d, qlds, M.kbar, M.alpha, apply,
+                                M.theta32.p, M.theta64.p, qlds ? valu_shmem(B.max_k_all, precision, M.d) : 0, s,
+                                check));
     }
     return DDMGNN_OK;
 }
@@ -452,7 +458,7 @@ int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& 
     for (const W& w : all) {
         wa.push_back(make_int2(w.p, w.sub));
         B->max_k_all = std::max(B->max_k_all, w.k);
-        if (probs[w.p]->mfma_fits) {
+        if (probs[w.p]->mfma_fits && probs[w.p]->model->d == D) {
             wm.push_back(make_int2(w.p, w.sub));
         } else {
             wr.push_back(make_int2(w.p, w.sub));
@@ -542,7 +548,7 @@ int batch_true_residual(Batch& B, const std::vector<uint8_t>* which) {
 int dss_kernel_of(const ddmgnn_problem* P, const ddmgnn_solve_opts& o) {
     if (o.local_solver == DDMGNN_LOCAL_LU) return 3;
     if (o.precision == DDMGNN_FP64) return 0;
-    return o.precision == DDMGNN_BF16 && P->mfma_fits ? 2 : 1;
+    return o.precision == DDMGNN_BF16 && P->mfma_fits && P->model->d == D ? 2 : 1;
 }
 
 int check_opts(const ddmgnn_solve_opts& o) {
@@ -787,9 +793,10 @@ int ddmgnn_ctx_destroy(ddmgnn_ctx* ctx) {
 int ddmgnn_model_create(ddmgnn_ctx* ctx, const ddmgnn_model_desc* desc, const float* theta, int64_t n_theta,
                         ddmgnn_model** out) {
     if (!ctx || !desc || !theta || !out) return fail(DDMGNN_E_INVALID, "null argument");
-    if (desc->d != D) return fail(DDMGNN_E_INVALID, "only latent width d = 10 is compiled");
+    const int d = desc->d;
+    if (d != 5 && d != 10 && d != 20) return fail(DDMGNN_E_INVALID, "latent width d must be 5, 10 or 20");
     if (desc->kbar < 1) return fail(DDMGNN_E_INVALID, "kbar must be >= 1");
-    const int64_t expect = (int64_t)desc->kbar * (11 * D * D + 15 * D + 1);
+    const int64_t expect = (int64_t)desc->kbar * (11 * d * d + 15 * d + 1);
     if (n_theta != expect) return fail(DDMGNN_E_INVALID, "n_theta must equal kbar*(11d^2+15d+1)");
     for (int64_t i = 0; i < n_theta; ++i)
         if (!std::isfinite(theta[i])) return fail(DDMGNN_E_INVALID, "non-finite weight");
@@ -800,10 +807,11 @@ int ddmgnn_model_create(ddmgnn_ctx* ctx, const ddmgnn_model_desc* desc, const fl
     m->theta.assign(theta, theta + n_theta);
     std::vector<MfmaStep> steps;
     std::vector<MfmaDec> dec;
-    build_mfma_blobs(m->theta.data(), m->kbar, steps, dec);
+    if (d == D) build_mfma_blobs(m->theta.data(), m->kbar, steps, dec);
     auto dev = std::make_shared<ModelDev>();
     dev->id = g_next_id.fetch_add(1);
     dev->kbar = m->kbar;
+    dev->d = d;
     dev->alpha = m->alpha;
     hipStream_t s = ctx->stream;
     std::vector<double> th64(m->theta.begin(), m->theta.end());

@@ -61,6 +61,7 @@ struct DevBuf {
 struct ModelDev {
     uint64_t id = 0;
     int kbar = 0;
+    int d = D;  // latent width; the MFMA kernel runs only the paper's d = 10
     double alpha = 0;
     DevBuf<float> theta32;
     DevBuf<double> theta64;

@@ -22,18 +22,34 @@ import re
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# Sources whose change invalidates a traffic measurement of a kernel.
+# What a kernel is built from: (file, first line marker or None, end marker or None).
+# A change in any of these texts invalidates a traffic measurement of the kernel.
+_DEVPROB = ("csrc/device.h", "struct DevProb {", "\n};\n")
+_CONSTS = ("csrc/device.h", "constexpr int D =", "constexpr size_t LDS_LIMIT")
 KERNEL_SOURCES = {
-    "dss_mfma_kernel": ("csrc/dss_mfma.hip", "csrc/dss_mfma.h", "csrc/device.h"),
-    "lu_local_kernel": ("csrc/kernels.hip", "csrc/device.h"),
+    "dss_mfma_kernel": (("csrc/dss_mfma.hip", None, None), ("csrc/dss_mfma.h", None, None), _DEVPROB, _CONSTS),
+    "lu_local_kernel": (("csrc/kernels.hip", "// ---------------------------------------------------------------"
+                         "--- reductions", "// ------------------------------------------------------------------ "
+                         "DSS forward (VALU)"),
+                        ("csrc/kernels.hip", "// ------------------------------------------------------------------ "
+                         "exact local solves", "// ------------------------------------------------------------------"
+                         " coarse solve"), _DEVPROB, _CONSTS),
 }
+
+
+def _region(rel: str, start: str | None, end: str | None) -> bytes:
+    text = open(os.path.join(HERE, rel), encoding="utf-8").read()
+    if start is not None:
+        i = text.index(start)
+        j = text.index(end, i + len(start))
+        text = text[i:j]
+    return text.encode()
 
 
 def source_hash(kernel: str) -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES[kernel]:
-        with open(os.path.join(HERE, rel), "rb") as f:
-            h.update(f.read())
+    for part in KERNEL_SOURCES[kernel]:
+        h.update(_region(*part))
     return h.hexdigest()[:16]
 
 

@@ -100,6 +100,59 @@ def test_dss_forward_all_subdomains(ctx, c1, prec, tol, theta_name):
     assert worst <= tol
 
 
+@pytest.mark.parametrize("kbar,d", [(5, 5), (10, 20), (20, 10), (10, 5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16", 3e-5)])
+def test_dss_forward_widths(ctx, c1, kbar, d, prec, tol):
+    """(kbar, d) variants of DSS_theta (Table II sweep): Xavier weights of each size against
+    the oracle. BF16 runs the MFMA kernel only at d = 10; other widths take the FP32 kernel
+    (hence the FP32 bar)."""
+    print(f"[gpu] dss_forward kbar={kbar} d={d} {prec}", flush=True)
+    p, hp = c1
+    theta = W.xavier_theta(7, kbar, d)
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, theta, kbar=kbar, d=d))
+    c = _c_inputs(p, hp, 3)
+    out = torch.empty(hp.sub_nodes.size, dtype=torch.float64, device="cuda")
+    prob.dss_forward(_dev(c), out, prec)
+    got = out.cpu().numpy()
+    blocks = dss.unpack(theta, kbar, d)
+    worst = 0.0
+    for i in range(hp.K):
+        sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
+        g = dc.local_graph(hp.sub_nodes[sl], p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
+        ref = dss.forward(blocks, g, c[sl], 1e-3, d)
+        worst = max(worst, np.abs(got[sl] - ref).max() / np.abs(ref).max())
+    print(f"[gpu]   worst relative error {worst:.3e}", flush=True)
+    if prec == "bf16" and d == 10:
+        tol = 5e-2
+    assert worst <= tol
+
+
+@pytest.mark.parametrize("d", [5, 20])
+def test_solve_widths_match_oracle(ctx, c1, d):
+    """FCG with a constructed smoother of latent width d: FP64 iterations equal the oracle's;
+    a BF16 request runs the FP32 VALU kernel (kernel id 1)."""
+    print(f"[gpu] solve d={d}", flush=True)
+    p, hp = c1
+    theta = W.smoother_theta(kbar=10, d=d, omega=0.15, out_scale=1.7)
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, theta, kbar=10, d=d))
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    st = prob.solve(u, dg.default_opts(precision="fp64", rtol=1e-8, max_it=1000))
+    dec = dc.Decomposition(p.n, hp.sub_ptr, hp.sub_nodes, hp.weights)
+    M = sw.DDMGNN(p.A.to_scipy(), p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, dec, theta, kbar=10, d=d)
+    ref = kr.fcg(p.A.to_scipy(), p.b, p.u0, M, 1e-8, max_it=1000)
+    print(f"[gpu]   iterations gpu={st.iterations} oracle={ref.iterations}", flush=True)
+    assert ref.converged and st.converged and abs(st.iterations - ref.iterations) <= 1
+    st = prob.solve(u, dg.default_opts(precision="bf16", rtol=1e-6, max_it=1000))
+    assert st.converged and st.dss_kernel == 1
+
+
+def test_model_rejects_bad_sizes(ctx):
+    with pytest.raises(dg.DDMGNNError):
+        dg.Model(ctx, W.xavier_theta(7, 5, 10), kbar=5, d=7)
+    with pytest.raises(dg.DDMGNNError):
+        dg.Model(ctx, W.xavier_theta(7, 5, 10), kbar=6, d=10)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16", 5e-2)])
 @pytest.mark.parametrize("prolong", [dg.PROLONG_POU, dg.PROLONG_UNWEIGHTED])
 def test_apply_and_intermediates(ctx, c1, prec, tol, prolong):
