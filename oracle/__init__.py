@@ -12,7 +12,8 @@ Plain, slow, obviously correct numpy code in float64, written from the paper:
 * ``dss``     - the DSS_theta forward pass (Sec. III.B, eqs. (14)-(18)).
 * ``schwarz`` - the coarse problem and the DDM-GNN apply (Sec. III.A, eqs.
   (11)-(13) and the gluing step); the DDM-LU and one-level variants (eqs. (6)-(7)).
-* ``krylov``  - PCG as Algorithm 1, flexible CG (truncated FCG(m)), plain CG.
+* ``krylov``  - PCG as Algorithm 1, flexible CG (truncated FCG(m)), restarted flexible
+  GMRES, plain CG.
 
 Parity status of each function is stated in its docstring; every function is
 pinned by tests except where a docstring says "parity unpinned".

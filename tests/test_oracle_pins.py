@@ -386,6 +386,77 @@ def test_cg_finite_termination_tiny_dense():
         assert np.abs(A @ res.u - b).max() <= 1e-8 * np.abs(b).max()
 
 
+# ------------------------------------------------------------------ flexible GMRES
+def test_fgmres_matches_least_squares_definition():
+    """k GMRES steps (M = I) give min |b - A(u0 + K c)| over the Krylov matrix
+    K = [r0, A r0, ..., A^(k-1) r0], solved here by a dense least-squares routine."""
+    rng = np.random.default_rng(11)
+    n = 40
+    A = np.eye(n) * 4 + rng.standard_normal((n, n)) * 0.3   # nonsymmetric, well conditioned
+    b = rng.standard_normal(n)
+    u0 = np.zeros(n)
+    res = kr.fgmres(A, b, u0, lambda r: r.copy(), 1e-14, max_it=8, restart=50)
+    r0 = b - A @ u0
+    for k in range(1, 9):
+        K = np.stack([np.linalg.matrix_power(A, i) @ r0 for i in range(k)], 1)
+        c = np.linalg.lstsq(A @ K, r0, rcond=None)[0]
+        ls = np.linalg.norm(r0 - A @ K @ c) / np.linalg.norm(r0)
+        assert abs(res.history[k] - ls) <= 1e-9 * max(ls, 1e-12) + 1e-13, (k, res.history[k], ls)
+
+
+def test_fgmres_exact_preconditioner_one_iteration(small):
+    p, _ = small
+    A = p.A.to_scipy().tocsc()
+    lu = spl.splu(A)
+    res = kr.fgmres(A, p.b, p.u0, lambda r: lu.solve(r), 1e-10)
+    assert res.converged and res.iterations == 1 and res.true_rel_residual <= 1e-10
+
+
+def test_fgmres_residual_not_above_cg_and_pcg(small):
+    """Same Krylov space, GMRES minimises the residual norm: |r_k| <= CG's |r_k| (M = I)
+    and <= PCG's with a fixed SPD M (right preconditioning, x0 + M K_k(AM, r0))."""
+    p, dec = small
+    A = p.A.to_scipy()
+    g = kr.fgmres(A, p.b, p.u0, lambda r: r.copy(), 1e-8, max_it=60, restart=200)
+    c = kr.cg(A, p.b, p.u0, 1e-8, max_it=60)
+    for k in range(1, min(len(g.history), len(c.history))):
+        assert g.history[k] <= c.history[k] * (1 + 1e-7), k
+    M = sw.DDMLU(A, p.mesh.dirichlet, dec, prolong="unweighted")
+    g = kr.fgmres(A, p.b, p.u0, M, 1e-10, max_it=40, restart=200)
+    c = kr.pcg(A, p.b, p.u0, M, 1e-10, max_it=40)
+    for k in range(1, min(len(g.history), len(c.history))):
+        assert g.history[k] <= c.history[k] * (1 + 1e-7), k
+
+
+def test_fgmres_finite_termination_and_restarts():
+    rng = np.random.default_rng(5)
+    for n in (6, 12, 20):
+        A = np.eye(n) * 3 + rng.standard_normal((n, n))
+        b = rng.standard_normal(n)
+        res = kr.fgmres(A, b, np.zeros(n), lambda r: r.copy(), 1e-10, max_it=n + 1, restart=n + 5)
+        assert res.converged and res.iterations <= n
+        assert np.abs(A @ res.u - b).max() <= 1e-8 * np.abs(b).max()
+    # restarted: residual non-increasing across cycles, estimate = true residual at the end
+    A = np.eye(30) * 3 + rng.standard_normal((30, 30)) * 0.5
+    b = rng.standard_normal(30)
+    res = kr.fgmres(A, b, np.zeros(30), lambda r: r.copy(), 1e-9, max_it=300, restart=4)
+    assert res.converged
+    assert all(res.history[i + 1] <= res.history[i] * (1 + 1e-9) for i in range(len(res.history) - 1))
+    assert abs(res.true_rel_residual - res.history[-1]) <= 1e-6 * res.history[-1] + 1e-14
+
+
+def test_fgmres_nonlinear_preconditioner_converges(small):
+    """The flexible variant with the (nonlinear) DDM-GNN preconditioner reaches the
+    direct solution."""
+    p, dec = small
+    A = p.A.to_scipy()
+    M = sw.DDMGNN(A, p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, dec, W.smoother_theta(omega=0.15, out_scale=1.7))
+    res = kr.fgmres(A, p.b, p.u0, M, 1e-10, max_it=300, restart=30)
+    u_direct = spl.spsolve(A.tocsc(), p.b)
+    assert res.converged and res.true_rel_residual <= 1e-9
+    assert np.linalg.norm(res.u - u_direct) / np.linalg.norm(u_direct) <= 1e-8
+
+
 def test_solution_matches_direct_solve(small):
     p, dec = small
     A = p.A.to_scipy()
