@@ -128,6 +128,23 @@ def bench_lu(dg, prob, u, hp, steps: int) -> dict:
                          "avg_launch_ms": local_ms}}
 
 
+def bench_variant(dg, prob, u, opts, popts) -> dict:
+    """One warm-up solve (graph capture), one timed solve, one profiled solve of the main problem."""
+    import torch
+    prob.solve(u, opts, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = prob.solve(u, opts, check=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sp = prob.solve(u, popts, check=False)
+    n_it = max(1, sp.dss_launches)
+    return {"iterations": st.iterations, "converged": bool(st.converged), "rel_residual": st.rel_residual,
+            "true_rel_residual": st.true_rel_residual, "time_to_solution_ms": 1e3 * elapsed,
+            "breakdown_ms_per_iteration": {"dss": sp.dss_ms / n_it, "coarse": sp.coarse_ms / n_it,
+                                           "prolong": sp.prolong_ms / n_it, "krylov": sp.krylov_ms / n_it}}
+
+
 def _make(spec):
     """(seed, target_nodes, n_parts, jitter) -> (problem, host arrays); runs in a worker process."""
     import paper_2402_08296_amd as dg
@@ -304,6 +321,7 @@ def main():
     ap.add_argument("--serve-slow-rate", type=float, default=6.0, help="arrival rate of the sustained replay (1/s)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--lu-steps", type=int, default=1, help="timed DDM-LU solves of the main problem (0: skip)")
+    ap.add_argument("--variants", type=int, default=1, help="FGMRES and rtol 1e-9 legs on the main problem (0: skip)")
     ap.add_argument("--pmc-workload", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -418,6 +436,13 @@ def main():
                      "algorithmic_bytes_per_apply": abytes},
         "p99_latency_ms": None,
     }
+    if args.variants > 0:
+        log("FGMRES(30) and rtol 1e-9 on the same problem")
+        mk = lambda **kw: (dg.default_opts(precision=args.precision, max_it=max_it, check_every=16, **kw),
+                           dg.default_opts(precision=args.precision, max_it=max_it, check_every=16, profile=1, **kw))
+        out["fgmres30_c3"] = bench_variant(dg, prob, u, *mk(krylov=dg.FGMRES, restart=30, rtol=1e-6))
+        out["fcg_rtol1e-9_c3"] = bench_variant(dg, prob, u, *mk(rtol=1e-9))
+        out["fgmres30_rtol1e-9_c3"] = bench_variant(dg, prob, u, *mk(krylov=dg.FGMRES, restart=30, rtol=1e-9))
     if args.lu_steps > 0:
         log("DDM-LU on the same problem")
         out["ddm_lu"] = bench_lu(dg, prob, u, hp, args.lu_steps)

@@ -48,8 +48,9 @@ enum {
     DDMGNN_E_PENDING = -9     /* result not ready yet */
 };
 
-/* Krylov method (Algorithm 1 is PCG; FCG is its flexible variant). */
-enum { DDMGNN_FCG = 0, DDMGNN_PCG = 1, DDMGNN_CG = 2 };
+/* Krylov method (Algorithm 1 is PCG; FCG is its flexible variant; FGMRES is
+ * restarted flexible GMRES with right preconditioning, cycles of `restart` steps). */
+enum { DDMGNN_FCG = 0, DDMGNN_PCG = 1, DDMGNN_CG = 2, DDMGNN_FGMRES = 3 };
 /* Arithmetic of the DSS_theta forward pass. Krylov vectors, dot products,
  * the residual update and the coarse level are always FP64. */
 enum { DDMGNN_FP64 = 0, DDMGNN_FP32 = 1, DDMGNN_BF16 = 2 };
@@ -160,6 +161,8 @@ typedef struct {
     int32_t local_solver;/* DDMGNN_LOCAL_GNN, or DDMGNN_LOCAL_LU: exact local solves with the
                           * inverses of R_i A R_i^T (dense FP64, sum k_i^2 doubles of device
                           * memory), formed on the host at the problem's first LU use */
+    int32_t restart;     /* FGMRES: steps per cycle, 1..64 (30); the problem keeps
+                          * (2 restart + 1) N doubles of device memory for it */
 } ddmgnn_solve_opts;
 
 typedef struct {
@@ -184,7 +187,7 @@ typedef struct {
 } ddmgnn_stats;
 
 /* Fill opts with defaults (FCG, m_max 1, rtol 1e-6, max_it 10000, FP32, POU, coarse on,
- * check_every 16, graph replay on, DSS local solver). */
+ * check_every 16, graph replay on, DSS local solver, FGMRES restart 30). */
 void ddmgnn_default_opts(ddmgnn_solve_opts* opts);
 
 /* Solve A u = b from the problem's u0. u_out: device, N doubles. On

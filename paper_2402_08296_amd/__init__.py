@@ -15,7 +15,7 @@ import numpy as np
 
 from ._build import LIB as _LIB_PATH
 
-FCG, PCG, CG = 0, 1, 2
+FCG, PCG, CG, FGMRES = 0, 1, 2, 3
 FP64, FP32, BF16 = 0, 1, 2
 PROLONG_POU, PROLONG_UNWEIGHTED = 0, 1
 LOCAL_GNN, LOCAL_LU = 0, 1
@@ -46,7 +46,7 @@ class ProblemDesc(ctypes.Structure):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("krylov", _i32), ("m_max", _i32), ("rtol", _f64), ("max_it", _i32), ("precision", _i32),
                 ("prolong", _i32), ("coarse", _i32), ("check_every", _i32), ("profile", _i32),
-                ("graph", _i32), ("local_solver", _i32)]
+                ("graph", _i32), ("local_solver", _i32), ("restart", _i32)]
 
 
 class Stats(ctypes.Structure):

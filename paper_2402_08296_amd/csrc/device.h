@@ -17,6 +17,7 @@ namespace ddmgnn {
 
 constexpr int D = 10;           // latent width of the paper's model (Sec. IV.B); the MFMA kernel's width
 constexpr int MAX_M = 4;        // largest FCG truncation supported
+constexpr int MAX_RESTART = 64; // largest FGMRES cycle
 constexpr int VEC_BLOCK = 256;  // threads of the vector kernels
 constexpr int VEC_GRID = 1024;  // max workgroups per problem in the vector kernels
 constexpr int N_XCD = 8;        // accelerator dies; workgroups are dispatched to them round-robin
@@ -37,6 +38,13 @@ struct KState {
     int done;
     int status;
     int max_it;            // the update kernel raises done once it reaches max_it
+    // FGMRES cycle (unused by the other methods)
+    double gm_beta;        // |r| at the start of the cycle
+    double gm_hnext;       // h_{j,j-1}: norm of the unnormalised basis vector j
+    int gm_j;              // step of the cycle (basis vectors 0..gm_j exist)
+    int gm_k;              // steps of a finished cycle
+    int gm_end;            // the cycle is over: update u, restart or stop
+    int gm_conv;           // the residual estimate met the tolerance
 };
 
 // Per slot position in tile order (nodes of a sub-mesh by decreasing
@@ -95,6 +103,12 @@ struct DevProb {
     float* qg32;
     KState* st;                 // null: no Krylov scalars, no done flag
     double* partials;           // (MAX_M + 1) x VEC_GRID per-workgroup partial sums
+    // FGMRES storage (null until a problem is solved with FGMRES)
+    double* gm_v;               // (restart + 1) x n: Arnoldi basis V
+    double* gm_z;               // restart x n: preconditioned vectors Z = M(V)
+    double* gm_part;            // (restart + 1) x VEC_GRID partial sums of the Gram passes
+    double* gm_small;           // H [(restart + 1) x restart, column j at j * (restart + 1)],
+                                // cs, sn [restart], g [restart + 1], y [restart], tmp [restart + 1]
     unsigned* counter;          // unused by the solve kernels (kept zero)
     double rtol;                // read by the init kernel
     int max_it;
@@ -105,8 +119,8 @@ struct DevProb {
 
 // Options of one Krylov iteration, common to the problems of a launch.
 struct IterArgs {
-    int mode;        // DDMGNN_FCG / PCG / CG; < 0: bare apply (no Krylov scalars)
-    int m;           // directions kept (FCG m_max; 1 for PCG and CG)
+    int mode;        // DDMGNN_FCG / PCG / CG / FGMRES; < 0: bare apply (no Krylov scalars)
+    int m;           // directions kept (FCG m_max; 1 for PCG and CG); FGMRES: cycle length
     int unweighted;  // gluing without partition-of-unity weights
     int coarse;      // add the coarse correction
 };
@@ -134,6 +148,12 @@ hipError_t launch_coarse(const DevProb* tab, const int2* rows, int n_rows, hipSt
 // problem: n_prob = all problems of the table, or the problems of `list`.
 hipError_t launch_prolong(const DevProb* tab, const int2* blk, int n_blk, int n_prob, const IterArgs& it,
                           hipStream_t s, bool check);
+// FGMRES: one step of every problem of the table (after its apply) and the
+// normalisation that starts the next step (before it).
+hipError_t launch_fgmres_next(const DevProb* tab, const int2* blk, int n_blk, const IterArgs& it, hipStream_t s,
+                              bool check);
+hipError_t launch_fgmres_step(const DevProb* tab, const int2* blk, int n_blk, int n_prob, const IterArgs& it,
+                              hipStream_t s, bool check);
 hipError_t launch_krylov(const DevProb* tab, const int2* blk, int n_blk, int n_prob, const IterArgs& it,
                          hipStream_t s, bool check);
 hipError_t launch_init(const DevProb* tab, const int2* blk, int n_blk, const int* list, int n_list, hipStream_t s);

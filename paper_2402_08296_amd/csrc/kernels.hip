@@ -42,7 +42,8 @@ static_assert(DssLayout<10>::BLOCK_W == 1251 && DssLayout<5>::BLOCK_W == 351 && 
 constexpr int DSS_NPT = (kMaxSubNodes + DSS_BLOCK - 1) / DSS_BLOCK;
 
 // Which reduction a finalize launch completes.
-enum FinStage { FIN_PROLONG, FIN_SPMV, FIN_UPDATE, FIN_INIT, FIN_RESID };
+enum FinStage { FIN_PROLONG, FIN_SPMV, FIN_UPDATE, FIN_INIT, FIN_RESID, FIN_GM_DOT1, FIN_GM_DOT2, FIN_GM_ROT,
+                FIN_GM_RESTART };
 
 // ------------------------------------------------------------------ reductions
 // Deterministic: fixed shuffle tree inside a wave, fixed order across waves,
@@ -619,6 +620,11 @@ __global__ __launch_bounds__(VEC_BLOCK) void prolong_kernel(const DevProb* __res
     for (int i = 0; i <= MAX_M; ++i) dots[i] = 0.0;
     const Rows rg = rows_of(g.lb, P.nblk, P.n);
     const bool uw = ia.unweighted;
+    if (mode == DDMGNN_FGMRES) {  // z_j = M(v_j) goes to column j of Z, no dots
+        prolong_rows<-1>(P.node_ptr, P.node_slots, P.slot_sub, P.weights, P.local, y, P.dirichlet, P.r,
+                         P.gm_z + (size_t)st->gm_j * P.n, nullptr, nullptr, nullptr, nullptr, m, uw, rg, P.n, dots);
+        return;
+    }
     if (mode == DDMGNN_FCG)
         prolong_rows<DDMGNN_FCG>(P.node_ptr, P.node_slots, P.slot_sub, P.weights, P.local, y, P.dirichlet, P.r,
                                  P.z, qk[0], qk[1], qk[2], qk[3], m, uw, rg, P.n, dots);
@@ -840,6 +846,177 @@ __global__ __launch_bounds__(VEC_BLOCK) void resid_kernel(const DevProb* __restr
     put_partials<1>(d, P.partials, g.lb);
 }
 
+// ------------------------------------------------------------------ FGMRES
+// Restarted flexible GMRES (Saad's right-preconditioned variant): per step j,
+// v_j = w / h_{j,j-1} (or r / beta at the start of a cycle) into the basis and
+// into r, the apply z_j = M(v_j) into column j of Z, w = A z_j, then classical
+// Gram-Schmidt against v_0..v_j run twice (three passes over the basis: dots;
+// update and second dots; update and |w|), the Givens rotations and the
+// residual estimate in a finalize kernel. At the end of a cycle u += Z y, then
+// r = b - A u and a restart. The small arrays of a problem (ia.m = R steps per
+// cycle) hold H [(R + 1) x R, column-major], cs [R], sn [R], g [R + 1],
+// y [R] and tmp [R + 1].
+struct GmSmall {
+    double *H, *cs, *sn, *g, *y, *tmp;
+    int ld;
+};
+__device__ inline GmSmall gm_small(const DevProb& P, int R) {
+    double* b = P.gm_small;
+    GmSmall m;
+    m.ld = R + 1;
+    m.H = b;
+    m.cs = b + (size_t)(R + 1) * R;
+    m.sn = m.cs + R;
+    m.g = m.sn + R;
+    m.y = m.g + R + 1;
+    m.tmp = m.y + R;
+    return m;
+}
+
+// v_j into the basis and into r (the input of the apply).
+__global__ __launch_bounds__(VEC_BLOCK) void fgm_next_kernel(const DevProb* __restrict__ tab,
+                                                            const int2* __restrict__ blk, IterArgs ia) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    const KState* st = P.st;
+    if (st->done) return;
+    const int j = st->gm_j;
+    const size_t n = P.n;
+    double* __restrict__ vj = P.gm_v + j * n;
+    const double* src = j == 0 ? P.r : vj;
+    const double d = j == 0 ? st->gm_beta : st->gm_hnext;
+    double* __restrict__ r = P.r;
+    const Rows rg = rows_of(g.lb, P.nblk, P.n);
+    for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
+        const int i = gi * VEC_BLOCK + threadIdx.x;
+        if (i >= P.n) continue;
+        const double v = src[i] / d;
+        vj[i] = v;
+        r[i] = v;
+    }
+}
+
+// w = A z_j into basis column j + 1.
+__global__ __launch_bounds__(VEC_BLOCK) void fgm_spmv_kernel(const DevProb* __restrict__ tab,
+                                                            const int2* __restrict__ blk, IterArgs ia) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    const KState* st = P.st;
+    if (st->done) return;
+    const int j = st->gm_j;
+    const double* __restrict__ zj = P.gm_z + (size_t)j * P.n;
+    double* __restrict__ w = P.gm_v + (size_t)(j + 1) * P.n;
+    spmv_groups(P.rowptr, P.col, P.val, P.n, g.lb, P.nblk, [&](int c) { return zj[c]; },
+                [&](int i, double acc) { w[i] = acc; });
+}
+
+// Partial sums of <w, v_k>, k = 0..j, over this workgroup's rows, eight basis
+// vectors per sweep, into gm_part[k][lb].
+__device__ inline void gm_dots(const DevProb& P, const Rows& rg, int lb, int j, const double* __restrict__ w) {
+    __shared__ double sh[8 * (VEC_BLOCK / 64)];
+    const size_t n = P.n;
+    for (int k0 = 0; k0 <= j; k0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
+            const int i = gi * VEC_BLOCK + threadIdx.x;
+            if (i >= P.n) continue;
+            const double wi = w[i];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (k0 + q <= j) acc[q] = fma(wi, P.gm_v[(k0 + q) * n + i], acc[q]);
+        }
+        block_sum_n<8, VEC_BLOCK>(acc, sh);
+        if (threadIdx.x == 0)
+            for (int q = 0; q < 8 && k0 + q <= j; ++q) P.gm_part[(size_t)(k0 + q) * VEC_GRID + lb] = acc[q];
+    }
+}
+
+__global__ __launch_bounds__(VEC_BLOCK) void fgm_gram_kernel(const DevProb* __restrict__ tab,
+                                                            const int2* __restrict__ blk, IterArgs ia) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    const KState* st = P.st;
+    if (st->done) return;
+    const int j = st->gm_j;
+    gm_dots(P, rows_of(g.lb, P.nblk, P.n), g.lb, j, P.gm_v + (size_t)(j + 1) * P.n);
+}
+
+// w -= sum_k h_k v_k with h = tmp (the preceding dots); then (FINAL = false) the
+// dots of the new w for the second pass, or (FINAL = true) the partial |w|^2.
+template <bool FINAL>
+__global__ __launch_bounds__(VEC_BLOCK) void fgm_orth_kernel(const DevProb* __restrict__ tab,
+                                                            const int2* __restrict__ blk, IterArgs ia) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    const KState* st = P.st;
+    if (st->done) return;
+    const int j = st->gm_j;
+    const size_t n = P.n;
+    const double* __restrict__ h = gm_small(P, ia.m).tmp;
+    double* __restrict__ w = P.gm_v + (j + 1) * n;
+    const Rows rg = rows_of(g.lb, P.nblk, P.n);
+    double d[1] = {0.0};
+    for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
+        const int i = gi * VEC_BLOCK + threadIdx.x;
+        if (i >= P.n) continue;
+        double wi = w[i];
+        for (int k = 0; k <= j; ++k) wi = fma(-h[k], P.gm_v[k * n + i], wi);
+        w[i] = wi;
+        d[0] = fma(wi, wi, d[0]);
+    }
+    if (FINAL) {
+        put_partials<1>(d, P.gm_part, g.lb);
+    } else {
+        gm_dots(P, rg, g.lb, j, w);
+    }
+}
+
+// End of a cycle: u += sum_{q < k} y_q z_q.
+__global__ __launch_bounds__(VEC_BLOCK) void fgm_xupd_kernel(const DevProb* __restrict__ tab,
+                                                            const int2* __restrict__ blk, IterArgs ia) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    const KState* st = P.st;
+    if (st->done || !st->gm_end) return;
+    const int k = st->gm_k;
+    const size_t n = P.n;
+    const double* __restrict__ y = gm_small(P, ia.m).y;
+    double* __restrict__ u = P.u;
+    const Rows rg = rows_of(g.lb, P.nblk, P.n);
+    for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
+        const int i = gi * VEC_BLOCK + threadIdx.x;
+        if (i >= P.n) continue;
+        double ui = u[i];
+        for (int q = 0; q < k; ++q) ui = fma(y[q], P.gm_z[q * n + i], ui);
+        u[i] = ui;
+    }
+}
+
+// End of a cycle: r = b - A u with its partial |r|^2.
+__global__ __launch_bounds__(VEC_BLOCK) void fgm_resid_kernel(const DevProb* __restrict__ tab,
+                                                             const int2* __restrict__ blk, IterArgs ia) {
+    const Seg g = seg(tab, blk);
+    const DevProb& P = *g.P;
+    const KState* st = P.st;
+    if (st->done || !st->gm_end) return;
+    double d[1] = {0.0};
+    residual_rows(P.rowptr, P.col, P.val, P.b, P.u, nullptr, P.r, rows_of(g.lb, P.nblk, P.n), P.n, d);
+    put_partials<1>(d, P.partials, g.lb);
+}
+
+// Sums of gm_part[k][*] for k = 0..j in fixed order, one wavefront per k.
+__device__ inline void gm_sum_dots(const DevProb& P, int j, double* out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int k = wave; k <= j; k += VEC_BLOCK / 64) {
+        double acc = 0.0;
+        for (int b = lane; b < P.nblk; b += 64) acc += P.gm_part[(size_t)k * VEC_GRID + b];
+        acc = wave_sum(acc);
+        if (lane == 0) out[k] = acc;
+    }
+}
+
 // Scalar recurrences of one problem from the partial sums of the preceding
 // large kernel; one workgroup per problem (list[blockIdx.x], or blockIdx.x).
 __global__ __launch_bounds__(VEC_BLOCK) void finalize_kernel(const DevProb* __restrict__ tab,
@@ -898,8 +1075,88 @@ __global__ __launch_bounds__(VEC_BLOCK) void finalize_kernel(const DevProb* __re
         st->rr_true = 0.0;
         st->it = 0;
         st->max_it = P.max_it;
+        st->gm_beta = st->r0n;
+        st->gm_hnext = 0.0;
+        st->gm_j = 0;
+        st->gm_k = 0;
+        st->gm_end = 0;
+        st->gm_conv = 0;
         st->status = isfinite(tot[0]) ? 0 : DDMGNN_E_NONFINITE;
         st->done = (tot[0] == 0.0 || !isfinite(tot[0]) || P.max_it <= 0) ? 1 : 0;
+    } else if (stage == FIN_GM_DOT1 || stage == FIN_GM_DOT2) {
+        // h_k of the Gram pass into tmp; the second pass adds to column j of H
+        const GmSmall m = gm_small(P, ia.m);
+        const int j = st->gm_j;
+        gm_sum_dots(P, j, m.tmp);
+        __syncthreads();
+        for (int k = threadIdx.x; k <= j; k += VEC_BLOCK) {
+            double* hk = m.H + (size_t)j * m.ld + k;
+            *hk = stage == FIN_GM_DOT1 ? m.tmp[k] : *hk + m.tmp[k];
+        }
+    } else if (stage == FIN_GM_ROT) {
+        double tot[1];
+        sum_partials<1>(P.gm_part, P.nblk, tot);
+        if (!t0) return;
+        const GmSmall m = gm_small(P, ia.m);
+        const int j = st->gm_j, R = ia.m;
+        double* Hj = m.H + (size_t)j * m.ld;
+        const double hn = sqrt(tot[0]);
+        if (j == 0) m.g[0] = st->gm_beta;
+        // earlier rotations on column j, then the one that zeroes h_{j+1,j}
+        for (int i = 0; i < j; ++i) {
+            const double t = m.cs[i] * Hj[i] + m.sn[i] * Hj[i + 1];
+            Hj[i + 1] = -m.sn[i] * Hj[i] + m.cs[i] * Hj[i + 1];
+            Hj[i] = t;
+        }
+        const double dd = hypot(Hj[j], hn);
+        m.cs[j] = Hj[j] / dd;
+        m.sn[j] = hn / dd;
+        Hj[j] = dd;
+        Hj[j + 1] = 0.0;
+        m.g[j + 1] = -m.sn[j] * m.g[j];
+        m.g[j] = m.cs[j] * m.g[j];
+        st->it += 1;
+        const double rel = fabs(m.g[j + 1]) / st->r0n;
+        if (!isfinite(rel) || !isfinite(dd)) {
+            st->status = DDMGNN_E_NONFINITE;
+            st->done = 1;
+            return;
+        }
+        if (!(dd > 0.0)) {  // H_j singular: no update possible
+            st->status = DDMGNN_E_BREAKDOWN;
+            st->done = 1;
+            return;
+        }
+        st->rel = rel;
+        st->gm_conv = rel <= st->rtol || hn == 0.0;
+        if (st->gm_conv || j + 1 == R || st->it >= st->max_it) {
+            // y = H_k^{-1} g (upper triangular), k = j + 1
+            const int k = j + 1;
+            for (int i = k - 1; i >= 0; --i) {
+                double acc = m.g[i];
+                for (int c = i + 1; c < k; ++c) acc -= m.H[(size_t)c * m.ld + i] * m.y[c];
+                m.y[i] = acc / m.H[(size_t)i * m.ld + i];
+            }
+            st->gm_k = k;
+            st->gm_end = 1;
+        } else {
+            st->gm_j = j + 1;
+            st->gm_hnext = hn;
+        }
+    } else if (stage == FIN_GM_RESTART) {
+        if (!st->gm_end) return;
+        double tot[1];
+        sum_partials<1>(P.partials, P.nblk, tot);
+        if (!t0) return;
+        st->gm_end = 0;
+        st->gm_j = 0;
+        st->gm_beta = sqrt(tot[0]);
+        if (!isfinite(tot[0])) {
+            st->status = DDMGNN_E_NONFINITE;
+            st->done = 1;
+        } else if (st->gm_conv || st->it >= st->max_it || tot[0] == 0.0) {
+            st->done = 1;
+        }
     } else {  // FIN_RESID
         double tot[1];
         sum_partials<1>(P.partials, P.nblk, tot);
@@ -1015,7 +1272,7 @@ hipError_t launch_coarse(const DevProb* tab, const int2* rows, int n_rows, hipSt
 hipError_t launch_prolong(const DevProb* tab, const int2* blk, int n_blk, int n_prob, const IterArgs& it,
                           hipStream_t s, bool check) {
     hipLaunchKernelGGL(prolong_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
-    if (it.mode >= 0)
+    if (it.mode >= 0 && it.mode != DDMGNN_FGMRES)
         hipLaunchKernelGGL(finalize_kernel, dim3(n_prob), dim3(VEC_BLOCK), 0, s, tab, (const int*)nullptr,
                            (int)FIN_PROLONG, it);
     return done(check);
@@ -1033,6 +1290,28 @@ hipError_t launch_krylov(const DevProb* tab, const int2* blk, int n_blk, int n_p
     hipLaunchKernelGGL(finalize_kernel, dim3(n_prob), dim3(VEC_BLOCK), 0, s, tab, all, (int)FIN_SPMV, it);
     hipLaunchKernelGGL(update_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
     hipLaunchKernelGGL(finalize_kernel, dim3(n_prob), dim3(VEC_BLOCK), 0, s, tab, all, (int)FIN_UPDATE, it);
+    return done(check);
+}
+
+hipError_t launch_fgmres_next(const DevProb* tab, const int2* blk, int n_blk, const IterArgs& it, hipStream_t s,
+                              bool check) {
+    hipLaunchKernelGGL(fgm_next_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    return done(check);
+}
+
+hipError_t launch_fgmres_step(const DevProb* tab, const int2* blk, int n_blk, int n_prob, const IterArgs& it,
+                              hipStream_t s, bool check) {
+    const int* all = nullptr;
+    hipLaunchKernelGGL(fgm_spmv_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    hipLaunchKernelGGL(fgm_gram_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_prob), dim3(VEC_BLOCK), 0, s, tab, all, (int)FIN_GM_DOT1, it);
+    hipLaunchKernelGGL(fgm_orth_kernel<false>, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_prob), dim3(VEC_BLOCK), 0, s, tab, all, (int)FIN_GM_DOT2, it);
+    hipLaunchKernelGGL(fgm_orth_kernel<true>, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_prob), dim3(VEC_BLOCK), 0, s, tab, all, (int)FIN_GM_ROT, it);
+    hipLaunchKernelGGL(fgm_xupd_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    hipLaunchKernelGGL(fgm_resid_kernel, dim3(n_blk), dim3(VEC_BLOCK), 0, s, tab, blk, it);
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_prob), dim3(VEC_BLOCK), 0, s, tab, all, (int)FIN_GM_RESTART, it);
     return done(check);
 }
 

@@ -66,6 +66,7 @@ DevProb make_view(ddmgnn_problem* P) {
     v.tiles = P->tiles.p; v.xy64 = P->xy64.p; v.xyc32 = P->xyc32.p;
     v.node_ptr = P->node_ptr.p; v.node_slots = P->node_slots.p; v.slot_sub = P->slot_sub.p; v.a0inv = P->a0inv.p;
     v.lu_inv = P->lu_inv.p; v.lu_off = P->lu_off.p;
+    v.gm_v = P->gm_v.p; v.gm_z = P->gm_z.p; v.gm_part = P->gm_part.p; v.gm_small = P->gm_small.p;
     v.u = P->u.p; v.r = P->r.p; v.z = P->z.p; v.c_in = nullptr;
     const int64_t n = P->hs.n;
     for (int i = 0; i <= MAX_M; ++i) {
@@ -144,6 +145,23 @@ int prepare_lu(ddmgnn_problem* P) {
 // kernel's LDS budget and the model has the paper's latent width).
 bool runs_mfma(const Batch& B, const ddmgnn_problem* P) { return P->mfma_fits && B.model->d == D; }
 
+int prepare_fgmres(Batch& B, int R, bool& changed) {
+    for (ddmgnn_problem* P : B.probs) {
+        if (P->gm_R >= R) continue;
+        const size_t n = (size_t)P->hs.n;
+        P->device_bytes -= P->gm_R ? fgmres_bytes(P->hs.n, P->gm_R) : 0;
+        P->gm_R = 0;
+        HIP_TRY(P->gm_v.alloc((size_t)(R + 1) * n));
+        HIP_TRY(P->gm_z.alloc((size_t)R * n));
+        HIP_TRY(P->gm_part.alloc((size_t)(R + 1) * VEC_GRID));
+        HIP_TRY(P->gm_small.alloc((size_t)R * R + 6 * R + 2));
+        P->gm_R = R;
+        P->device_bytes += fgmres_bytes(P->hs.n, R);
+        changed = true;
+    }
+    return DDMGNN_OK;
+}
+
 // Allocates what the DSS launches of this precision need (fallback storage,
 // LDS attributes). Not allowed during stream capture; returns true in
 // `changed` when a problem's buffers moved (the table must be re-uploaded).
@@ -209,7 +227,7 @@ int enqueue_dss(Batch& B, const DevProb* tab, int precision, int apply, bool cap
 IterArgs iter_args(const ddmgnn_solve_opts& o, int mode) {
     IterArgs ia{};
     ia.mode = mode;
-    ia.m = mode == DDMGNN_FCG ? o.m_max : 1;
+    ia.m = mode == DDMGNN_FCG ? o.m_max : mode == DDMGNN_FGMRES ? o.restart : 1;
     ia.unweighted = o.prolong == DDMGNN_PROLONG_UNWEIGHTED;
     ia.coarse = o.coarse;
     return ia;
@@ -235,6 +253,14 @@ int enqueue_iteration(Batch& B, const ddmgnn_solve_opts& o, hipEvent_t* ev, bool
     hipStream_t s = B.ctx->launch;
     const int mode = o.krylov;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    if (mode == DDMGNN_FGMRES) {
+        HIP_TRY(launch_fgmres_next(B.tab.p, B.vec_blk.p, B.n_vec, iter_args(o, mode), s, !capturing));
+        if (int rc = enqueue_apply(B, B.tab.p, o, mode, ev, capturing)) return rc;
+        HIP_TRY(launch_fgmres_step(B.tab.p, B.vec_blk.p, B.n_vec, (int)B.probs.size(), iter_args(o, mode), s,
+                                   !capturing));
+        if (ev) HIP_TRY(hipEventRecord(ev[4], s));
+        return DDMGNN_OK;
+    }
     if (mode == DDMGNN_CG) {
         if (ev)
             for (int q = 1; q < 4; ++q) HIP_TRY(hipEventRecord(ev[q], s));
@@ -247,8 +273,9 @@ int enqueue_iteration(Batch& B, const ddmgnn_solve_opts& o, hipEvent_t* ev, bool
 }
 
 uint64_t graph_key(const ddmgnn_solve_opts& o, int count) {
-    return ((uint64_t)o.local_solver << 48) | ((uint64_t)o.krylov << 44) | ((uint64_t)o.m_max << 40) |
-           ((uint64_t)o.precision << 36) | ((uint64_t)o.prolong << 34) | ((uint64_t)o.coarse << 32) |
+    const int m = o.krylov == DDMGNN_FGMRES ? o.restart : o.m_max;
+    return ((uint64_t)o.local_solver << 56) | ((uint64_t)o.krylov << 52) | ((uint64_t)(m & 0xff) << 44) |
+           ((uint64_t)o.precision << 40) | ((uint64_t)o.prolong << 38) | ((uint64_t)(o.coarse != 0) << 36) |
            (uint64_t)(uint32_t)count;
 }
 
@@ -495,6 +522,8 @@ int batch_begin(Batch& B, const ddmgnn_solve_opts& o, const std::vector<uint8_t>
     } else if (o.krylov != DDMGNN_CG) {
         if (int rc = prepare_dss(B, o.precision, changed)) return rc;
     }
+    if (o.krylov == DDMGNN_FGMRES)
+        if (int rc = prepare_fgmres(B, o.restart, changed)) return rc;
     if (changed && B.graph) {  // captured launches point at moved buffers
         (void)hipGraphExecDestroy(B.graph);
         B.graph = nullptr;
@@ -545,6 +574,12 @@ int batch_true_residual(Batch& B, const std::vector<uint8_t>* which) {
     return batch_poll(B);
 }
 
+// FGMRES storage for cycles of R steps: basis (R + 1) x n, Z R x n, partial sums
+// (R + 1) x VEC_GRID, small arrays (H, rotations, g, y, tmp).
+size_t fgmres_bytes(int64_t n, int R) {
+    return 8 * ((size_t)(2 * R + 1) * n + (size_t)(R + 1) * VEC_GRID + (size_t)R * R + 6 * R + 2);
+}
+
 int dss_kernel_of(const ddmgnn_problem* P, const ddmgnn_solve_opts& o) {
     if (o.local_solver == DDMGNN_LOCAL_LU) return 3;
     if (o.precision == DDMGNN_FP64) return 0;
@@ -552,7 +587,9 @@ int dss_kernel_of(const ddmgnn_problem* P, const ddmgnn_solve_opts& o) {
 }
 
 int check_opts(const ddmgnn_solve_opts& o) {
-    if (o.krylov < 0 || o.krylov > 2) return fail(DDMGNN_E_INVALID, "krylov must be FCG, PCG or CG");
+    if (o.krylov < 0 || o.krylov > 3) return fail(DDMGNN_E_INVALID, "krylov must be FCG, PCG, CG or FGMRES");
+    if (o.krylov == DDMGNN_FGMRES && (o.restart < 1 || o.restart > MAX_RESTART))
+        return fail(DDMGNN_E_INVALID, "restart must be in [1, 64]");
     if (o.krylov == DDMGNN_FCG && (o.m_max < 1 || o.m_max > MAX_M)) return fail(DDMGNN_E_INVALID, "m_max must be in [1, 4]");
     if (!(o.rtol >= 0.0)) return fail(DDMGNN_E_INVALID, "rtol must be >= 0");
     if (o.max_it < 0) return fail(DDMGNN_E_INVALID, "max_it must be >= 0");
@@ -767,6 +804,7 @@ void ddmgnn_default_opts(ddmgnn_solve_opts* o) {
     o->profile = 0;
     o->graph = 1;
     o->local_solver = DDMGNN_LOCAL_GNN;
+    o->restart = 30;
 }
 
 int ddmgnn_ctx_create(void* hip_stream, ddmgnn_ctx** out) {

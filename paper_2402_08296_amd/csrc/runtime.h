@@ -101,6 +101,8 @@ ddmgnn_problem* batch_problem(const Batch& B, int i);
 int batch_true_residual(Batch& B, const std::vector<uint8_t>* which);
 // Kernel that runs the local solves of problem P: 0 FP64 VALU DSS, 1 FP32 VALU DSS,
 // 2 BF16 MFMA DSS, 3 exact local solves (DDM-LU).
+// Device bytes of the FGMRES storage of a problem of n nodes, cycles of R steps.
+size_t fgmres_bytes(int64_t n, int R);
 int dss_kernel_of(const ddmgnn_problem* P, const ddmgnn_solve_opts& o);
 
 int check_opts(const ddmgnn_solve_opts& o);
@@ -153,6 +155,10 @@ struct ddmgnn_problem {
     // exact local solves (built on the first solve with local_solver = LU)
     ddmgnn::DevBuf<double> lu_inv;
     ddmgnn::DevBuf<int64_t> lu_off;
+    // FGMRES basis, preconditioned vectors, partial sums and small arrays (built on
+    // the first FGMRES solve, for cycles of up to gm_R steps)
+    ddmgnn::DevBuf<double> gm_v, gm_z, gm_part, gm_small;
+    int gm_R = 0;
     ddmgnn::DevBuf<float> qglobal32;
     // Krylov vectors
     ddmgnn::DevBuf<double> u, r, z;

@@ -58,7 +58,7 @@ void copy_in(std::vector<T>& dst, const T* src, int64_t n) {
 
 // Options that must agree among the problems of one batch.
 uint64_t structure_key(const ddmgnn_solve_opts& o) {
-    const int m = o.krylov == DDMGNN_FCG ? o.m_max : 1;
+    const int m = o.krylov == DDMGNN_FCG ? o.m_max : o.krylov == DDMGNN_FGMRES ? o.restart : 1;
     return ((uint64_t)o.local_solver << 32) | ((uint64_t)o.krylov << 24) | ((uint64_t)m << 16) |
            ((uint64_t)o.precision << 8) | ((uint64_t)o.prolong << 4) | (uint64_t)(o.coarse != 0);
 }
@@ -126,7 +126,8 @@ void ddmgnn_server::setup_worker() {
             r->err = "a local matrix R_i A R_i^T is not positive definite";
         } else {
             r->bytes = problem_device_bytes(r->hs.n, r->hs.nnz, r->hs.K, r->hs.sk, r->hs.n_edges) +
-                       r->hs.lu_inv.size() * sizeof(double) + r->hs.lu_off.size() * sizeof(int64_t);
+                       r->hs.lu_inv.size() * sizeof(double) + r->hs.lu_off.size() * sizeof(int64_t) +
+                       (r->opts.krylov == DDMGNN_FGMRES ? fgmres_bytes(r->hs.n, r->opts.restart) : 0);
         }
         std::lock_guard<std::mutex> lk(mu);
         ready[r->ticket] = r;

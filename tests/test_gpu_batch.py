@@ -89,6 +89,22 @@ def test_batch_lu_equals_solo(ctx, mix):
     assert probs[1].device_bytes() >= int((k * k).sum()) * 8
 
 
+def test_batch_fgmres_equals_solo(ctx, mix):
+    """FGMRES(8) batched: restarts at different iterations per problem, same bits as solo."""
+    print("[gpu] batch vs solo FGMRES", flush=True)
+    model = dg.Model(ctx, SMOOTHER)
+    opts = dg.default_opts(krylov=dg.FGMRES, restart=8, precision="fp32", rtol=1e-7, max_it=800)
+    solo = _solo(ctx, model, mix, opts)
+    probs = [dg.Problem(ctx, hp, model) for _, hp in mix]
+    outs = [torch.empty(p.n, dtype=torch.float64, device="cuda") for p, _ in mix]
+    sts = dg.solve_batch(ctx, probs, outs, opts)
+    for i, ((u, it, status), ub, st) in enumerate(zip(solo, outs, sts)):
+        print(f"[gpu]   problem {i}: iterations solo={it} batch={st.iterations}", flush=True)
+        assert status == 0 and st.status == 0 and st.converged
+        assert st.iterations == it
+        assert np.array_equal(ub.cpu().numpy(), u), i
+
+
 def test_batch_order_and_eager(ctx, mix):
     """Member order and eager launches do not change any member's result."""
     print("[gpu] batch order / eager", flush=True)
@@ -176,8 +192,9 @@ def test_server_matches_solo(ctx, mix):
 
 
 def test_server_lu_and_gnn_groups(ctx, mix):
-    """DDM-LU requests (inverses built by the setup workers) and DDM-GNN requests
-    in one stream: each group batches on its own, results equal the solo solves."""
+    """DDM-LU requests (inverses built by the setup workers), DDM-GNN FCG and FGMRES
+    requests in one stream: each group batches on its own (eager chunks), results equal
+    the solo solves (graph replay)."""
     print("[gpu] server DDM-LU / DDM-GNN", flush=True)
     model = dg.Model(ctx, SMOOTHER)
     lu = dg.default_opts(krylov=dg.PCG, local_solver=dg.LOCAL_LU, prolong=dg.PROLONG_UNWEIGHTED,
@@ -188,10 +205,13 @@ def test_server_lu_and_gnn_groups(ctx, mix):
     torch.cuda.synchronize()
     sctx = dg.Context(torch.cuda.Stream())
     srv = dg.Server(sctx, model, hbm_budget=8 << 30, max_active=4, setup_threads=2)
+    fg = dg.default_opts(krylov=dg.FGMRES, restart=10, precision="fp32", rtol=1e-7, max_it=800, check_every=4)
+    solo_fg = _solo(ctx, model, mix[1:3], fg)
     t_lu = [srv.submit(hp, lu) for _, hp in mix]
     t_gnn = [srv.submit(hp, gnn) for _, hp in mix[:2]]
+    t_fg = [srv.submit(hp, fg) for _, hp in mix[1:3]]
     srv.drain()
-    for tickets, solo in ((t_lu, solo_lu), (t_gnn, solo_gnn)):
+    for tickets, solo in ((t_lu, solo_lu), (t_gnn, solo_gnn), (t_fg, solo_fg)):
         for t, (u0, it, _) in zip(tickets, solo):
             rc, st, u = srv.poll(t)
             print(f"[gpu]   ticket {t}: rc={rc} iterations={st.iterations} solo={it}", flush=True)

@@ -366,6 +366,50 @@ def test_lu_solve_matches_oracle(ctx, c1, krylov):
     assert np.linalg.norm(ug - ref.u) / np.linalg.norm(ref.u) <= 1e-8
 
 
+@pytest.mark.parametrize("restart,local", [(30, dg.LOCAL_GNN), (5, dg.LOCAL_GNN), (30, dg.LOCAL_LU)])
+def test_fgmres_solve_matches_oracle(ctx, c1, restart, local):
+    """Restarted flexible GMRES on the GPU (classical Gram-Schmidt run twice) against the
+    oracle's (modified Gram-Schmidt): the same iterate up to rounding, so iteration counts
+    within 2 and solutions within 1e-8 of each other at rtol 1e-10."""
+    print(f"[gpu] FGMRES({restart}) local={local}", flush=True)
+    p, hp = c1
+    A = p.A.to_scipy()
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, SMOOTHER))
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    st = prob.solve(u, dg.default_opts(krylov=dg.FGMRES, restart=restart, local_solver=local, precision="fp64",
+                                       rtol=1e-10, max_it=600))
+    dec = dc.Decomposition(p.n, hp.sub_ptr, hp.sub_nodes, hp.weights)
+    if local == dg.LOCAL_LU:
+        M = sw.DDMLU(A, p.mesh.dirichlet, dec, prolong="pou")
+    else:
+        M = _oracle_M(p, hp, SMOOTHER)
+    ref = kr.fgmres(A, p.b, p.u0, M, 1e-10, max_it=600, restart=restart)
+    print(f"[gpu]   iterations gpu={st.iterations} oracle={ref.iterations} rel={st.rel_residual:.2e} "
+          f"true={st.true_rel_residual:.2e}", flush=True)
+    assert ref.converged and st.converged and abs(st.iterations - ref.iterations) <= 2
+    assert st.true_rel_residual <= 2e-10
+    ug = u.cpu().numpy()
+    assert np.linalg.norm(ug - ref.u) / np.linalg.norm(ref.u) <= 1e-8
+
+
+def test_fgmres_bf16_and_graph_replay(ctx, c1):
+    """FGMRES with the BF16 DSS converges; a second solve (graph replay) repeats it bit for bit."""
+    print("[gpu] FGMRES bf16", flush=True)
+    p, hp = c1
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, SMOOTHER))
+    u1 = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    u2 = torch.empty_like(u1)
+    o = dg.default_opts(krylov=dg.FGMRES, restart=20, precision="bf16", rtol=1e-6, max_it=600)
+    s1 = prob.solve(u1, o)
+    s2 = prob.solve(u2, o)
+    print(f"[gpu]   iterations {s1.iterations} true_rel={s1.true_rel_residual:.2e}", flush=True)
+    assert s1.converged and s1.true_rel_residual <= 1.5e-6
+    assert s1.iterations == s2.iterations and torch.equal(u1, u2)
+    eager = prob.solve(u2, dg.default_opts(krylov=dg.FGMRES, restart=20, precision="bf16", rtol=1e-6,
+                                           max_it=600, graph=0))
+    assert eager.iterations == s1.iterations and torch.equal(u1, u2)
+
+
 def test_xavier_history_matches_oracle(ctx, c1):
     """The seeded (untrained) model stagnates; the GPU recurrence tracks the oracle's."""
     print("[gpu] xavier history", flush=True)
