@@ -284,6 +284,12 @@ def pmc_workload(args):
     ctx = dg.Context()
     model = dg.Model(ctx, W.smoother_theta(omega=0.15, out_scale=1.7))
     prob = dg.Problem(ctx, hp, model)
+    if args.tune:  # the schedule of the measured run (cached by it on this machine)
+        from paper_2402_08296_amd import tune
+        tinfo = tune.tuned(prob, hp, dg.default_opts(precision=args.precision, rtol=1e-6, max_it=5000,
+                                                     check_every=16),
+                           dg.lib().ddmgnn_version().decode().split()[-1], args.tune_cache)
+        log(f"schedule {tinfo['tuning']}")
     x = torch.ones(PMC_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     for _ in range(3):
@@ -322,6 +328,8 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--lu-steps", type=int, default=1, help="timed DDM-LU solves of the main problem (0: skip)")
     ap.add_argument("--variants", type=int, default=1, help="FGMRES and rtol 1e-9 legs on the main problem (0: skip)")
+    ap.add_argument("--tune", type=int, default=1, help="autotune the main problem's schedule (0: default schedule)")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: ~/.cache/ddmgnn_tune.json)")
     ap.add_argument("--pmc-workload", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -374,6 +382,14 @@ def main():
     u = torch.empty(p.n, dtype=torch.float64, device="cuda")
     max_it = 5000 if args.theta == "smoother" else 200
     opts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, check_every=16)
+    tuning = None
+    if args.tune:
+        from paper_2402_08296_amd import tune
+        t = time.perf_counter()
+        tuning = tune.tuned(prob, hp, opts, dg.lib().ddmgnn_version().decode().split()[-1], args.tune_cache)
+        tuning["seconds"] = time.perf_counter() - t
+        log(f"schedule {tuning['tuning']} ({'cached' if tuning['cached'] else 'autotuned'}, "
+            f"{tuning['seconds']:.2f}s)")
     popts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, profile=1, check_every=16)
     for w in range(args.warmup):
         st = prob.solve(u, opts, check=False)
@@ -390,7 +406,9 @@ def main():
     elapsed = time.perf_counter() - t0
     # One more solve with HIP events around every stage (outside the timed steps).
     sp = prob.solve(u, popts, check=False)
-    dss_kernel = {0: "dss_kernel<double>", 1: "dss_kernel<float>", 2: "dss_mfma_kernel"}[sp.dss_kernel]
+    dss_kernel = {0: "dss_kernel<double>", 1: "dss_kernel<float>", 2: "dss_mfma_kernel<1024>"}[sp.dss_kernel]
+    if sp.dss_kernel == 2 and prob.tuning().small_lds > 0:
+        dss_kernel += "+dss_mfma_kernel<512>"  # sub-meshes split over the two workgroup sizes
     n_it = max(1, sp.dss_launches)
     dss_avg_ms = sp.dss_ms / n_it
     dense, edge = dss_flops(30, 10, prob.sum_k, prob.n_edges)
@@ -401,7 +419,7 @@ def main():
     abytes = apply_bytes(prob.n, prob.K, prob.sum_k, prob.n_edges, 8 if args.precision == "fp64" else 4)
     traffic = None
     tr = profiling.read_traffic(TRAFFIC_FILE)
-    if tr and sp.dss_kernel == 2 and tr.get("source_hash") == profiling.source_hash("dss_mfma_kernel"):
+    if tr and tr.get("kernel") == dss_kernel and tr.get("source_hash") == profiling.source_hash("dss_mfma_kernel"):
         traffic = tr["traffic_bytes_per_dispatch"]
     iters = stats[-1][0]
     out = {
@@ -421,6 +439,7 @@ def main():
                                f"N={p.n}, K={hp.K} sub-meshes (overlap 2), sum k_i={hp.sub_nodes.size}, "
                                f"DSS kbar=30 d=10 ({args.theta} weights), FCG(1) to rel. residual 1e-6",
                    "nodes": p.n, "subdomains": hp.K, "dss_precision": args.precision, "weights": args.theta,
+                   "schedule": "autotuned" if args.tune else "default",
                    "target_nodes": cfg["target_nodes"]},
         "iterations": iters,
         "converged": bool(stats[-1][1]),
@@ -435,6 +454,7 @@ def main():
                      "flops_dense": dense, "flops_edge": edge, "avg_launch_ms": dss_avg_ms,
                      "algorithmic_bytes_per_apply": abytes},
         "p99_latency_ms": None,
+        "tuning": tuning,
     }
     if args.variants > 0:
         log("FGMRES(30) and rtol 1e-9 on the same problem")

@@ -277,6 +277,33 @@ int ddmgnn_pou_weights(int64_t n_nodes, const uint8_t* dirichlet, int32_t n_sub,
 
 void ddmgnn_free(void* p);
 
+/* Launch schedule of a problem: the choices of ddmgnn_autotune. small_lds never
+ * changes a result; vec_blocks changes the order of the Krylov reductions (the
+ * rounding, not the accuracy). */
+typedef struct {
+    int32_t small_lds;   /* BF16 MFMA DSS: sub-meshes of at most 1024 nodes whose LDS need is at
+                          * most this many bytes run in 512-thread workgroups, two per compute
+                          * unit; the others in 1024-thread workgroups, one per unit. 0: none;
+                          * at most 80 KiB - 1 KiB */
+    int32_t vec_blocks;  /* workgroups of the problem in the vector kernels (SpMV, gluing, Krylov
+                          * updates): 0 = one per 256 rows up to 1024; else a multiple of 8 in
+                          * [8, 1024], capped at the automatic count */
+} ddmgnn_tuning;
+
+/* Set / read a problem's schedule (E_INVALID for values out of range). Batches
+ * built before a change are rebuilt on their next solve. */
+int ddmgnn_problem_set_tuning(ddmgnn_problem* prob, const ddmgnn_tuning* t);
+int ddmgnn_problem_get_tuning(const ddmgnn_problem* prob, ddmgnn_tuning* t);
+
+/* Autotuner: times capped solves of `iterations` iterations with the options
+ * `opts` (graph replay on) for each candidate schedule (small_lds in {0, 48, 64,
+ * 79 KiB} when the MFMA kernel runs, then vec_blocks in {256, 512, 1024}
+ * capped at the automatic count), keeps the fastest per iteration in the
+ * problem and returns it with its time per iteration (ms). Leaves u and the
+ * Krylov state of the problem undefined. */
+int ddmgnn_autotune(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const ddmgnn_solve_opts* opts, int32_t iterations,
+                    ddmgnn_tuning* best, double* ms_per_iteration);
+
 /* Sizes of a problem: N, nnz, K, sum k_i, number of directed DSS edges. */
 int ddmgnn_problem_sizes(const ddmgnn_problem* prob, int64_t* n, int64_t* nnz, int32_t* k,
                          int64_t* sum_k, int64_t* n_edges);

@@ -49,6 +49,13 @@ class SolveOpts(ctypes.Structure):
                 ("graph", _i32), ("local_solver", _i32), ("restart", _i32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("small_lds", _i32), ("vec_blocks", _i32)]
+
+    def as_dict(self):
+        return {"small_lds": self.small_lds, "vec_blocks": self.vec_blocks}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("converged", _i32), ("rel_residual", _f64),
                 ("true_rel_residual", _f64), ("solve_ms", _f64), ("dss_launches", _i32), ("dss_ms", _f64),
@@ -96,6 +103,10 @@ def lib():
         "ddmgnn_server_drain": (ctypes.c_int, [_p]),
         "ddmgnn_server_destroy": (ctypes.c_int, [_p]),
         "ddmgnn_problem_device_bytes": (ctypes.c_int, [_p, ctypes.POINTER(_i64)]),
+        "ddmgnn_problem_set_tuning": (ctypes.c_int, [_p, ctypes.POINTER(Tuning)]),
+        "ddmgnn_problem_get_tuning": (ctypes.c_int, [_p, ctypes.POINTER(Tuning)]),
+        "ddmgnn_autotune": (ctypes.c_int, [_p, _p, ctypes.POINTER(SolveOpts), _i32, ctypes.POINTER(Tuning),
+                                           ctypes.POINTER(ctypes.c_double)]),
         "ddmgnn_precond_apply": (ctypes.c_int, [_p, _p, ctypes.POINTER(SolveOpts), _p, _p]),
         "ddmgnn_apply_intermediates": (ctypes.c_int, [_p, _p, _p, _p, _p, _p]),
         "ddmgnn_dss_forward": (ctypes.c_int, [_p, _p, _i32, _p, _p]),
@@ -344,6 +355,24 @@ class Problem:
         if check:
             _check(rc)
         return st
+
+    def set_tuning(self, small_lds: int = 0, vec_blocks: int = 0):
+        t = Tuning(small_lds, vec_blocks)
+        _check(lib().ddmgnn_problem_set_tuning(self.h, ctypes.byref(t)))
+
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        _check(lib().ddmgnn_problem_get_tuning(self.h, ctypes.byref(t)))
+        return t
+
+    def autotune(self, opts: SolveOpts | None = None, iterations: int = 16):
+        """Runs the library's autotuner; returns (Tuning, ms per iteration)."""
+        o = opts or default_opts()
+        t = Tuning()
+        ms = ctypes.c_double()
+        _check(lib().ddmgnn_autotune(self.ctx.h, self.h, ctypes.byref(o), iterations, ctypes.byref(t),
+                                     ctypes.byref(ms)))
+        return t, ms.value
 
     def device_bytes(self) -> int:
         b = _i64()

@@ -12,6 +12,12 @@
 namespace ddmgnn {
 
 constexpr int MFMA_BLOCK = 1024;  // 16 wavefronts, one sub-mesh per workgroup
+// Sub-meshes of at most MFMA_SMALL_K nodes may run in workgroups of
+// MFMA_SMALL_BLOCK threads instead: two fit on a compute unit when each needs at
+// most half its LDS, and one's barrier waits are the other's issue slots.
+constexpr int MFMA_SMALL_BLOCK = 512;
+constexpr int MFMA_SMALL_K = 1024;
+constexpr size_t MFMA_SMALL_LDS = 80 * 1024 - 1024;  // largest dynamic LDS of two co-resident workgroups
 constexpr int MFMA_TILE = 32;    // nodes per MFMA tile (the N dimension)
 // Edges per straight-line chunk of the message sums. Each node's in-edge
 // records are padded to a multiple of it with records of a sentinel sender
@@ -73,7 +79,10 @@ inline size_t mfma_lds_need(int k, int64_t ne_pad) {
 
 // Sets the dynamic-LDS limit of the kernel (not allowed during stream capture).
 hipError_t prepare_dss_mfma(size_t shmem);
-// check = false skips hipGetLastError (used while a stream is being captured).
-hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_work, size_t shmem, hipStream_t stream, bool check);
+// block: MFMA_BLOCK, or MFMA_SMALL_BLOCK for a list of sub-meshes of at most
+// MFMA_SMALL_K nodes. check = false skips hipGetLastError (used while a stream
+// is being captured).
+hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_work, size_t shmem, int block, hipStream_t stream,
+                           bool check);
 
 }  // namespace ddmgnn

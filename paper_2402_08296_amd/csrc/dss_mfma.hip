@@ -40,7 +40,11 @@ constexpr int OFF_PS = OFF_PI + D * IN_PHI + D + D * D + D;
 constexpr int OFF_DE = OFF_PS + D * IN_PSI + D + D * D + D;
 constexpr int BLOCK_W = OFF_DE + D * D + D + D + 1;
 constexpr int EC = MFMA_EC;
-constexpr int MAX_TILES_PER_WAVE = (2048 / MFMA_TILE + (MFMA_BLOCK / 64) - 1) / (MFMA_BLOCK / 64);
+// Tiles a wavefront holds (h in registers): a 1024-thread workgroup takes any
+// sub-mesh (64 tiles at most), a 512-thread one those of up to MFMA_SMALL_K nodes.
+constexpr int MAX_TILES_PER_WAVE = 4;
+static_assert(MAX_TILES_PER_WAVE * (MFMA_BLOCK / 64) * MFMA_TILE >= 2048, "largest sub-mesh");
+static_assert(MAX_TILES_PER_WAVE * (MFMA_SMALL_BLOCK / 64) * MFMA_TILE >= MFMA_SMALL_K, "small sub-meshes");
 
 // Round-to-nearest-even float -> bf16 bits (host).
 uint16_t bf16_bits(double v) {
@@ -229,11 +233,22 @@ __device__ inline f16x8 load_a16(const uint16_t* p) {
 
 __device__ inline __bf16 bits_bf16(uint32_t b) { return __builtin_bit_cast(__bf16, (uint16_t)(b & 0xffffu)); }
 
-__device__ inline double block_sum(double v, double* sh) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+// Sum over the MFMA_BLOCK virtual threads of a restriction, whatever the
+// workgroup size: thread t of a BLOCK-thread workgroup carries virtual threads
+// t + v BLOCK (v[] below), each wavefront's shuffle tree and the final sum over
+// the MFMA_BLOCK / 64 virtual wavefronts run in the order of a MFMA_BLOCK-thread
+// workgroup, so both workgroup sizes give the same bits.
+template <int BLOCK>
+__device__ inline double block_sum(const double (&v)[MFMA_BLOCK / BLOCK], double* sh) {
+    constexpr int VT = MFMA_BLOCK / BLOCK;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) sh[w] = v;
+#pragma unroll
+    for (int q = 0; q < VT; ++q) {
+        double x = v[q];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) sh[w + q * (BLOCK / 64)] = x;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         double acc = 0.0;
@@ -296,7 +311,9 @@ __device__ inline h2 pk(float x, float y) { return (h2){(_Float16)x, (_Float16)y
 //                  FP16 |d| | sender row byte offset << 16
 //   T   [k]        tile records (node id, degree, first edge, split coordinates)
 // The message sums run in packed FP16 (two units per instruction).
-__global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
+    constexpr int VT = MFMA_BLOCK / BLOCK;  // virtual threads per thread in the restriction sums
     const int2 wi = a.work[blockIdx.x];
     const DevProb& P = a.tab[wi.x];
     if (P.st && P.st->done) return;
@@ -313,38 +330,43 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     h2* Qd = reinterpret_cast<h2*>(lds + ((k + 3) & ~3));
     uint32_t* E = reinterpret_cast<uint32_t*>(Qd + ((10 * (k + 1) + 3) & ~3));
     TileNode* T = reinterpret_cast<TileNode*>(E + ((ne + 3) & ~3));
-    for (int i = tid; i < ne; i += MFMA_BLOCK) E[i] = P.erec[ebase + i];
+    for (int i = tid; i < ne; i += BLOCK) E[i] = P.erec[ebase + i];
     if (tid < 10) {  // sentinel rows: every message through them is ReLU(-inf) = 0
         const _Float16 ninf = __builtin_bit_cast(_Float16, (uint16_t)0xFC00u);
         Qd[(size_t)(tid / 5) * 5 * (k + 1) + 5 * k + tid % 5] = (h2){ninf, ninf};
     }
-    for (int i = tid; i < k; i += MFMA_BLOCK)
+    for (int i = tid; i < k; i += BLOCK)
         reinterpret_cast<uint4*>(T)[i] = reinterpret_cast<const uint4*>(P.tiles + base)[i];
 
     // Restriction and normalisation (Sec. III.A step 2).
     double s = 1.0;
     if (a.apply) {
-        double ss = 0.0, yy = 0.0;
-        for (int j = tid; j < k; j += MFMA_BLOCK) {
-            const double rv = P.r[P.sub_nodes[base + j]];
-            ss = fma(rv, rv, ss);
-            yy = fma(P.weights[base + j], rv, yy);
+        double ssv[VT], yyv[VT];
+#pragma unroll
+        for (int q = 0; q < VT; ++q) {
+            ssv[q] = 0.0;
+            yyv[q] = 0.0;
+            for (int j = tid + q * BLOCK; j < k; j += MFMA_BLOCK) {
+                const double rv = P.r[P.sub_nodes[base + j]];
+                ssv[q] = fma(rv, rv, ssv[q]);
+                yyv[q] = fma(P.weights[base + j], rv, yyv[q]);
+            }
         }
-        ss = block_sum(ss, red);
-        yy = block_sum(yy, red);
+        const double ss = block_sum<BLOCK>(ssv, red);
+        const double yy = block_sum<BLOCK>(yyv, red);
         s = sqrt(ss);
         if (tid == 0) {
             P.s[sub] = s;
             P.y0[sub] = yy;
         }
         if (s == 0.0) {
-            for (int j = tid; j < k; j += MFMA_BLOCK) out[base + j] = 0.0;
+            for (int j = tid; j < k; j += BLOCK) out[base + j] = 0.0;
             return;
         }
         const double inv = 1.0 / s;
-        for (int j = tid; j < k; j += MFMA_BLOCK) cbuf[j] = (float)(P.r[P.sub_nodes[base + j]] * inv);
+        for (int j = tid; j < k; j += BLOCK) cbuf[j] = (float)(P.r[P.sub_nodes[base + j]] * inv);
     } else {
-        for (int j = tid; j < k; j += MFMA_BLOCK) cbuf[j] = (float)P.c_in[base + j];
+        for (int j = tid; j < k; j += BLOCK) cbuf[j] = (float)P.c_in[base + j];
     }
     __syncthreads();
 
@@ -367,7 +389,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
             const bf16x8 AQ = load_a(L->a[A_Q][lane]);
 #pragma unroll
             for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt) {
-                const int tile = wave + (MFMA_BLOCK / 64) * tt;
+                const int tile = wave + (BLOCK / 64) * tt;
                 if (tile >= ntiles) break;
                 const int p = tile * MFMA_TILE + n;
                 const bool valid = p < k;
@@ -390,7 +412,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
             for (int t = 0; t < 5; ++t) wn[t] = pk(L->wn[2 * t][lane], L->wn[2 * t + 1][lane]);
 #pragma unroll
             for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt) {
-                const int tile = wave + (MFMA_BLOCK / 64) * tt;
+                const int tile = wave + (BLOCK / 64) * tt;
                 if (tile >= ntiles) break;
                 const int p = tile * MFMA_TILE + n;
                 const bool valid = p < k;
@@ -478,7 +500,7 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     const float bd2 = Ld->bd2;
 #pragma unroll
     for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt) {
-        const int tile = wave + (MFMA_BLOCK / 64) * tt;
+        const int tile = wave + (BLOCK / 64) * tt;
         if (tile >= ntiles) break;
         const int p = tile * MFMA_TILE + n;
         const bool valid = p < k;
@@ -497,12 +519,20 @@ __global__ __launch_bounds__(MFMA_BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
 }  // namespace
 
 hipError_t prepare_dss_mfma(size_t shmem) {
-    return hipFuncSetAttribute((const void*)dss_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    hipError_t e = hipFuncSetAttribute((const void*)dss_mfma_kernel<MFMA_BLOCK>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)dss_mfma_kernel<MFMA_SMALL_BLOCK>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
 }
 
-hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_work, size_t shmem, hipStream_t stream, bool check) {
+hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_work, size_t shmem, int block, hipStream_t stream,
+                           bool check) {
     if (n_work <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dss_mfma_kernel, dim3(n_work), dim3(MFMA_BLOCK), shmem, stream, a);
+    if (block == MFMA_SMALL_BLOCK)
+        hipLaunchKernelGGL(dss_mfma_kernel<MFMA_SMALL_BLOCK>, dim3(n_work), dim3(MFMA_SMALL_BLOCK), shmem, stream, a);
+    else
+        hipLaunchKernelGGL(dss_mfma_kernel<MFMA_BLOCK>, dim3(n_work), dim3(MFMA_BLOCK), shmem, stream, a);
     return check ? hipGetLastError() : hipSuccess;
 }
 

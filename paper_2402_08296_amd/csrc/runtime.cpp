@@ -35,6 +35,11 @@ struct Batch {
     // all sub-meshes; those of problems that fit the MFMA kernel; the others.
     DevBuf<int2> work_all, work_mfma, work_rest;
     int n_all = 0, n_mfma = 0, n_rest = 0;
+    // the MFMA list split by workgroup size: sub-meshes that run two per compute
+    // unit in MFMA_SMALL_BLOCK-thread workgroups, and the rest; dynamic LDS of each launch
+    DevBuf<int2> work_mfma_small;
+    int n_mfma_small = 0;
+    size_t lds_mfma = 0, lds_mfma_small = 0;
     int max_k_all = 0, max_k_rest = 0;
     DevBuf<int2> vec_blk;              // (problem, local workgroup)
     int n_vec = 0;
@@ -82,7 +87,7 @@ DevProb make_view(ddmgnn_problem* P) {
     v.max_it = P->max_it;
     v.n = (int)n;
     v.K = P->hs.K;
-    v.nblk = vec_blocks(n);
+    v.nblk = problem_vec_blocks(P);
     return v;
 }
 
@@ -168,7 +173,7 @@ int prepare_fgmres(Batch& B, int R, bool& changed) {
 int prepare_dss(Batch& B, int precision, bool& changed) {
     changed = false;
     const bool bf16 = precision == DDMGNN_BF16;
-    if (bf16 && B.n_mfma) HIP_TRY(prepare_dss_mfma(MFMA_LDS_LIMIT));
+    if (bf16 && B.n_mfma + B.n_mfma_small) HIP_TRY(prepare_dss_mfma(MFMA_LDS_LIMIT));
     const int valu_prec = bf16 ? DDMGNN_FP32 : precision;
     const int max_k = bf16 ? B.max_k_rest : B.max_k_all;
     const int n_valu = bf16 ? B.n_rest : B.n_all;
@@ -210,7 +215,9 @@ int enqueue_dss(Batch& B, const DevProb* tab, int precision, int apply, bool cap
     }
     if (precision == DDMGNN_BF16) {
         DssMfmaArgs a{tab, B.work_mfma.p, M.steps.p, M.dec.p, M.kbar, (float)M.alpha, apply};
-        HIP_TRY(launch_dss_mfma(a, B.n_mfma, MFMA_LDS_LIMIT, s, check));
+        HIP_TRY(launch_dss_mfma(a, B.n_mfma, B.lds_mfma, MFMA_BLOCK, s, check));
+        a.work = B.work_mfma_small.p;
+        HIP_TRY(launch_dss_mfma(a, B.n_mfma_small, B.lds_mfma_small, MFMA_SMALL_BLOCK, s, check));
         const bool qlds = valu_q_in_lds(B.max_k_rest, DDMGNN_FP32, M.d);
         HIP_TRY(launch_dss_valu(tab, B.work_rest.p, B.n_rest, DDMGNN_FP32, M.d, qlds, M.kbar, M.alpha, apply,
                                 M.theta32.p, M.theta64.p, qlds ? valu_shmem(B.max_k_rest, DDMGNN_FP32, M.d) : 0, s,
@@ -327,7 +334,7 @@ int upload_subset(Batch& B, const std::vector<uint8_t>* which) {
     for (size_t i = 0; i < B.probs.size(); ++i) {
         if (which && !(*which)[i]) continue;
         list.push_back((int)i);
-        const int nb = vec_blocks(B.probs[i]->hs.n);
+        const int nb = problem_vec_blocks(B.probs[i]);
         for (int b = 0; b < nb; ++b) sub.push_back(make_int2((int)i, b));
     }
     B.n_sub_blk = (int)sub.size();
@@ -471,7 +478,7 @@ int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& 
         const ddmgnn_problem* P = probs[i];
         const auto& sp = P->hs.sub_ptr;
         for (int j = 0; j < P->hs.K; ++j) all.push_back({(int)(sp[j + 1] - sp[j]), i, j});
-        const int nb = vec_blocks(P->hs.n);
+        const int nb = problem_vec_blocks(P);
         for (int b = 0; b < nb; ++b) vec.push_back(make_int2(i, b));
         for (int r = 0; r < P->hs.K; ++r) rows.push_back(make_int2(i, r));
     }
@@ -481,12 +488,20 @@ int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& 
         if (a.p != b.p) return a.p < b.p;
         return a.sub < b.sub;
     });
-    std::vector<int2> wa, wm, wr;
+    std::vector<int2> wa, wm, wms, wr;
     for (const W& w : all) {
         wa.push_back(make_int2(w.p, w.sub));
         B->max_k_all = std::max(B->max_k_all, w.k);
-        if (probs[w.p]->mfma_fits && probs[w.p]->model->d == D) {
-            wm.push_back(make_int2(w.p, w.sub));
+        const ddmgnn_problem* Q = probs[w.p];
+        if (Q->mfma_fits && Q->model->d == D) {
+            const size_t need = Q->mfma_need[w.sub];
+            if (w.k <= MFMA_SMALL_K && need <= (size_t)Q->tune.small_lds) {
+                wms.push_back(make_int2(w.p, w.sub));
+                B->lds_mfma_small = std::max(B->lds_mfma_small, need);
+            } else {
+                wm.push_back(make_int2(w.p, w.sub));
+                B->lds_mfma = std::max(B->lds_mfma, need);
+            }
         } else {
             wr.push_back(make_int2(w.p, w.sub));
             B->max_k_rest = std::max(B->max_k_rest, w.k);
@@ -495,11 +510,13 @@ int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& 
     hipStream_t s = ctx->stream;
     if (int rc = upload_list(B->work_all, wa, s)) return rc;
     if (int rc = upload_list(B->work_mfma, wm, s)) return rc;
+    if (int rc = upload_list(B->work_mfma_small, wms, s)) return rc;
     if (int rc = upload_list(B->work_rest, wr, s)) return rc;
     if (int rc = upload_list(B->vec_blk, vec, s)) return rc;
     if (int rc = upload_list(B->coarse_rows, rows, s)) return rc;
     B->n_all = (int)wa.size();
     B->n_mfma = (int)wm.size();
+    B->n_mfma_small = (int)wms.size();
     B->n_rest = (int)wr.size();
     B->n_vec = (int)vec.size();
     B->n_coarse = (int)rows.size();
@@ -572,6 +589,11 @@ int batch_true_residual(Batch& B, const std::vector<uint8_t>* which) {
         HIP_TRY(launch_resid(B.tab.p, B.vec_blk.p, B.n_vec, nullptr, (int)B.probs.size(), B.ctx->stream));
     }
     return batch_poll(B);
+}
+
+int problem_vec_blocks(const ddmgnn_problem* P) {
+    const int autom = vec_blocks(P->hs.n);
+    return P->tune.vec_blocks > 0 ? std::min(autom, P->tune.vec_blocks) : autom;
 }
 
 // FGMRES storage for cycles of R steps: basis (R + 1) x n, Z R x n, partial sums
@@ -676,6 +698,7 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
         std::vector<uint32_t> er;
         er.reserve((size_t)hs.n_edges * 2 + 1);
         std::vector<int32_t> epad(K + 1, 0);
+        P->mfma_need.assign(K, 0);
         std::vector<TileNode> tiles(sk);
         size_t need = 0;
         for (int i = 0; i < K; ++i) {
@@ -731,7 +754,8 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
                     tn.yl = hs.xyhl[4 * slot + 3];
                 }
             }
-            need = std::max(need, mfma_lds_need(k, (int64_t)er.size() - epad[i]));
+            P->mfma_need[i] = (uint32_t)mfma_lds_need(k, (int64_t)er.size() - epad[i]);
+            need = std::max(need, (size_t)P->mfma_need[i]);
         }
         epad[K] = (int32_t)er.size();
         P->mfma_fits = need <= MFMA_LDS_LIMIT;
@@ -777,13 +801,16 @@ ddmgnn_ctx::~ddmgnn_ctx() {
     if (cap) (void)hipStreamDestroy(cap);
 }
 
-ddmgnn_problem::~ddmgnn_problem() {
-    solo.reset();
-    if (ctx && ctx->last_batch) {
-        const auto& B = *ctx->last_batch;
-        if (std::find(B.ids.begin(), B.ids.end(), id) != B.ids.end()) ctx->last_batch.reset();
+// Drops the cached batches that hold P (its own and the context's last one).
+void drop_batches(ddmgnn_problem* P) {
+    P->solo.reset();
+    if (P->ctx && P->ctx->last_batch) {
+        const auto& B = *P->ctx->last_batch;
+        if (std::find(B.ids.begin(), B.ids.end(), P->id) != B.ids.end()) P->ctx->last_batch.reset();
     }
 }
+
+ddmgnn_problem::~ddmgnn_problem() { drop_batches(this); }
 
 // ------------------------------------------------------------------ C ABI
 extern "C" {
@@ -899,6 +926,84 @@ int ddmgnn_problem_sizes(const ddmgnn_problem* P, int64_t* n, int64_t* nnz, int3
     if (k) *k = P->hs.K;
     if (sum_k) *sum_k = P->hs.sk;
     if (n_edges) *n_edges = P->hs.n_edges;
+    return DDMGNN_OK;
+}
+
+int ddmgnn_problem_set_tuning(ddmgnn_problem* P, const ddmgnn_tuning* t) {
+    if (!P || !t) return fail(DDMGNN_E_INVALID, "null argument");
+    if (t->small_lds < 0 || t->small_lds > (int32_t)MFMA_SMALL_LDS)
+        return fail(DDMGNN_E_INVALID, "small_lds must be in [0, 80 KiB - 1 KiB]");
+    if (t->vec_blocks != 0 && (t->vec_blocks < N_XCD || t->vec_blocks > VEC_GRID || t->vec_blocks % N_XCD))
+        return fail(DDMGNN_E_INVALID, "vec_blocks must be 0 or a multiple of 8 in [8, 1024]");
+    if (t->small_lds != P->tune.small_lds || t->vec_blocks != P->tune.vec_blocks) {
+        P->tune = *t;
+        drop_batches(P);
+    }
+    return DDMGNN_OK;
+}
+
+int ddmgnn_problem_get_tuning(const ddmgnn_problem* P, ddmgnn_tuning* t) {
+    if (!P || !t) return fail(DDMGNN_E_INVALID, "null argument");
+    *t = P->tune;
+    return DDMGNN_OK;
+}
+
+int ddmgnn_autotune(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* opts, int32_t iterations,
+                    ddmgnn_tuning* best, double* ms_per_iteration) {
+    if (!ctx || !P || !opts) return fail(DDMGNN_E_INVALID, "null argument");
+    if (iterations < 1) return fail(DDMGNN_E_INVALID, "iterations must be >= 1");
+    if (int rc = check_opts(*opts)) return rc;
+    ddmgnn_solve_opts o = *opts;
+    o.max_it = iterations;
+    o.rtol = 0.0;  // run the capped number of iterations
+    o.graph = 1;
+    o.profile = 0;
+    o.check_every = std::min(iterations, 16);
+    // time per iteration of a candidate: best of two capped solves (the first of a
+    // schedule also captures its graph)
+    auto timed = [&](const ddmgnn_tuning& t, double& ms) -> int {
+        if (int rc = ddmgnn_problem_set_tuning(P, &t)) return rc;
+        if (int rc = solo_batch(P)) return rc;
+        double best_ms = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+            ddmgnn_stats st{};
+            double* outs[1] = {P->z.p};  // the solution copy lands in scratch
+            const int rc = solve_batch(ctx, *P->solo, o, outs, &st);
+            if (rc && rc != DDMGNN_E_MAXIT) return rc;
+            if (rep > 0) best_ms = std::min(best_ms, st.solve_ms / std::max(1, st.iterations));
+        }
+        ms = best_ms;
+        return DDMGNN_OK;
+    };
+    const bool mfma = o.krylov != DDMGNN_CG && o.local_solver == DDMGNN_LOCAL_GNN &&
+                      dss_kernel_of(P, o) == 2;
+    ddmgnn_tuning cur{0, 0}, top{0, 0};
+    double top_ms = 1e300;
+    std::vector<int32_t> lds = {0};
+    if (mfma) lds = {0, 48 * 1024, 64 * 1024, (int32_t)MFMA_SMALL_LDS};
+    for (int32_t v : lds) {
+        cur.small_lds = v;
+        double ms = 0;
+        if (int rc = timed(cur, ms)) return rc;
+        if (ms < top_ms) {
+            top_ms = ms;
+            top = cur;
+        }
+    }
+    cur = top;
+    for (int32_t vb : {256, 512, 1024}) {
+        if (vb > vec_blocks(P->hs.n)) continue;
+        cur.vec_blocks = vb;
+        double ms = 0;
+        if (int rc = timed(cur, ms)) return rc;
+        if (ms < top_ms) {
+            top_ms = ms;
+            top = cur;
+        }
+    }
+    if (int rc = ddmgnn_problem_set_tuning(P, &top)) return rc;
+    if (best) *best = top;
+    if (ms_per_iteration) *ms_per_iteration = top_ms;
     return DDMGNN_OK;
 }
 

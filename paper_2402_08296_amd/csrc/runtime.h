@@ -101,6 +101,8 @@ ddmgnn_problem* batch_problem(const Batch& B, int i);
 int batch_true_residual(Batch& B, const std::vector<uint8_t>* which);
 // Kernel that runs the local solves of problem P: 0 FP64 VALU DSS, 1 FP32 VALU DSS,
 // 2 BF16 MFMA DSS, 3 exact local solves (DDM-LU).
+// Workgroups of a problem in the vector kernels (its tuning, else vec_blocks(n)).
+int problem_vec_blocks(const ddmgnn_problem* P);
 // Device bytes of the FGMRES storage of a problem of n nodes, cycles of R steps.
 size_t fgmres_bytes(int64_t n, int R);
 int dss_kernel_of(const ddmgnn_problem* P, const ddmgnn_solve_opts& o);
@@ -149,6 +151,8 @@ struct ddmgnn_problem {
     ddmgnn::DevBuf<int32_t> epad_sub;  // [K + 1] ranges of the sub-meshes in erec
     ddmgnn::DevBuf<float> edge_nd;   // padded by 8 entries
     bool mfma_fits = false;          // every sub-mesh fits the MFMA kernel's LDS
+    std::vector<uint32_t> mfma_need; // per sub-mesh, LDS bytes of the MFMA kernel
+    ddmgnn_tuning tune{};            // launch schedule (ddmgnn_problem_set_tuning / ddmgnn_autotune)
     // apply buffers
     ddmgnn::DevBuf<double> s, y0, y, local;
     ddmgnn::DevBuf<double> qglobal64, hglobal64;

@@ -94,6 +94,8 @@ def per_dispatch(csv_path: str, counter: str) -> dict:
 
 def traffic_summary(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int, fetch_cmd: str,
                     write_cmd: str) -> dict:
+    """kernel: one kernel name, or several joined by '+' that run once each per
+    step (a stage split over launches): their per-dispatch means are added."""
     fetch = per_dispatch(fetch_csv, "FETCH_SIZE")
     write = per_dispatch(write_csv, "WRITE_SIZE")
     copy_name = next(k for k in fetch if "copyBuffer" in k)
@@ -102,17 +104,19 @@ def traffic_summary(fetch_csv: str, write_csv: str, kernel: str, copy_bytes: int
     cw = max(write[copy_name])
     f_fetch = copy_bytes / (cf * 1024.0)
     f_write = copy_bytes / (cw * 1024.0)
-    kf, kw = fetch[kernel], write[kernel]
-    fetch_b = sum(kf) / len(kf) * 1024.0 * f_fetch
-    write_b = sum(kw) / len(kw) * 1024.0 * f_write
+    names = kernel.split("+")
+    fk = sum(sum(fetch[k]) / len(fetch[k]) for k in names)
+    wk = sum(sum(write[k]) / len(write[k]) for k in names)
+    fetch_b = fk * 1024.0 * f_fetch
+    write_b = wk * 1024.0 * f_write
     return {
-        "kernel": kernel, "dispatches": len(kf),
-        "fetch_kib_per_dispatch": sum(kf) / len(kf), "write_kib_per_dispatch": sum(kw) / len(kw),
+        "kernel": kernel, "dispatches": min(len(fetch[k]) for k in names),
+        "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
         "copy_bytes": copy_bytes, "copy_fetch_kib": cf, "copy_write_kib": cw,
         "fetch_scale": f_fetch, "write_scale": f_write,
         "fetch_bytes_per_dispatch": fetch_b, "write_bytes_per_dispatch": write_b,
         "traffic_bytes_per_dispatch": fetch_b + write_b,
-        "source_hash": source_hash(kernel), "fetch_command": fetch_cmd, "write_command": write_cmd,
+        "source_hash": source_hash(names[0].split("<")[0]), "fetch_command": fetch_cmd, "write_command": write_cmd,
     }
 
 

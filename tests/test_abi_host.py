@@ -134,3 +134,34 @@ def test_setup_detects_singular_coarse():
     with pytest.raises(dg.DDMGNNError) as ei:
         dg.setup_coarse(hp2)
     assert ei.value.code == -4
+
+
+def test_tune_cache_roundtrip(tmp_path):
+    """The autotuner cache: one autotune per (arch, config class), later problems of the
+    class get the cached schedule (no GPU: a stand-in problem records the calls)."""
+    from paper_2402_08296_amd import tune
+
+    class FakeProb:
+        def __init__(self):
+            self.calls, self.set = 0, None
+
+        def autotune(self, opts, iterations):
+            self.calls += 1
+            return dg.Tuning(64 * 1024, 512), 0.5
+
+        def set_tuning(self, small_lds=0, vec_blocks=0):
+            self.set = (small_lds, vec_blocks)
+
+    _, hp = small_problem()
+    opts = dg.default_opts(precision="bf16")
+    path = str(tmp_path / "cache.json")
+    a = FakeProb()
+    r1 = tune.tuned(a, hp, opts, "gfx950", path)
+    assert a.calls == 1 and not r1["cached"] and r1["tuning"] == {"small_lds": 65536, "vec_blocks": 512}
+    b = FakeProb()
+    r2 = tune.tuned(b, hp, opts, "gfx950", path)
+    assert b.calls == 0 and r2["cached"] and b.set == (65536, 512) and r2["key"] == r1["key"]
+    c = FakeProb()
+    tune.tuned(c, hp, dg.default_opts(precision="fp32"), "gfx950", path)  # another class
+    assert c.calls == 1
+    assert tune.config_class(hp.n, hp.sub_ptr, opts) == tune.config_class(hp.n, list(hp.sub_ptr), opts)
