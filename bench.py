@@ -406,16 +406,24 @@ def main():
     elapsed = time.perf_counter() - t0
     # One more solve with HIP events around every stage (outside the timed steps).
     sp = prob.solve(u, popts, check=False)
+    # The stages of one apply as the solve's graphs run them (two forked DSS launches
+    # under the split schedule), each captured 20 times over in one graph timed
+    # between events.
+    r0 = torch.from_numpy(np.ascontiguousarray(p.b - p.A.to_scipy() @ p.u0)).cuda()
+    zt = torch.empty_like(r0)
+    g_local, g_coarse, g_glue = prob.time_apply_stages(r0, zt, opts, reps=20)
+    log(f"apply stages (graph replay): local {g_local * 1e3:.1f} us, coarse {g_coarse * 1e3:.1f} us, "
+        f"glue {g_glue * 1e3:.1f} us")
     dss_kernel = {0: "dss_kernel<double>", 1: "dss_kernel<float>", 2: "dss_mfma_kernel<1024>"}[sp.dss_kernel]
     if sp.dss_kernel == 2 and prob.tuning().small_lds > 0:
         dss_kernel += "+dss_mfma_kernel<512>"  # sub-meshes split over the two workgroup sizes
     n_it = max(1, sp.dss_launches)
-    dss_avg_ms = sp.dss_ms / n_it
+    dss_avg_ms = g_local
     dense, edge = dss_flops(30, 10, prob.sum_k, prob.n_edges)
     flops = dense + edge
     achieved = flops / (dss_avg_ms * 1e-3) / 1e12
     peak = dss_peak_tflops(args.precision if sp.dss_kernel == 2 or args.precision != "bf16" else "fp32", dense, edge)
-    apply_ms = (sp.dss_ms + sp.coarse_ms + sp.prolong_ms) / n_it
+    apply_ms = g_local + g_coarse + g_glue
     abytes = apply_bytes(prob.n, prob.K, prob.sum_k, prob.n_edges, 8 if args.precision == "fp64" else 4)
     traffic = None
     tr = profiling.read_traffic(TRAFFIC_FILE)
@@ -448,10 +456,14 @@ def main():
         "apply_ms": apply_ms,
         "apply_hbm_GBps": abytes / (apply_ms * 1e-3) / 1e9,
         "breakdown_ms_per_iteration": {"dss": sp.dss_ms / n_it, "coarse": sp.coarse_ms / n_it,
-                                       "prolong": sp.prolong_ms / n_it, "krylov": sp.krylov_ms / n_it},
+                                       "prolong": sp.prolong_ms / n_it, "krylov": sp.krylov_ms / n_it,
+                                       "timing": "eager solve with events between stages"},
+        "apply_stages_graph_ms": {"local": g_local, "coarse": g_coarse, "glue": g_glue,
+                                  "timing": "each stage captured 20 times over in one HIP graph, mean per stage"},
         "roofline": {"kernel": dss_kernel, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic, "flops_per_launch": flops,
                      "flops_dense": dense, "flops_edge": edge, "avg_launch_ms": dss_avg_ms,
+                     "avg_launch_timing": "DSS stage of one apply (both forked launches) in a replayed HIP graph",
                      "algorithmic_bytes_per_apply": abytes},
         "p99_latency_ms": None,
         "tuning": tuning,

@@ -238,6 +238,16 @@ int ddmgnn_server_destroy(ddmgnn_server* srv);
 int ddmgnn_precond_apply(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const ddmgnn_solve_opts* opts,
                          const double* r, double* z);
 
+/* Times the stages of one preconditioner apply z = M(r) as the solve runs them:
+ * each stage (local solves, coarse solve, gluing), repeated `reps` times, is
+ * captured as one HIP graph, launched once to warm up and once between events
+ * recorded on the context's stream; outputs are milliseconds per stage (the
+ * launch cost shared by the reps; NULL allowed). r, z: device, N doubles, must
+ * not alias. */
+int ddmgnn_time_apply_stages(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const ddmgnn_solve_opts* opts,
+                             const double* r, double* z, int32_t reps, double* local_ms, double* coarse_ms,
+                             double* glue_ms);
+
 /* Intermediates of the last ddmgnn_precond_apply on this problem, copied to
  * device buffers the caller owns (any pointer may be NULL):
  *   s[K]        |R_i r|

@@ -104,6 +104,9 @@ def lib():
         "ddmgnn_server_destroy": (ctypes.c_int, [_p]),
         "ddmgnn_problem_device_bytes": (ctypes.c_int, [_p, ctypes.POINTER(_i64)]),
         "ddmgnn_problem_set_tuning": (ctypes.c_int, [_p, ctypes.POINTER(Tuning)]),
+        "ddmgnn_time_apply_stages": (ctypes.c_int, [_p, _p, ctypes.POINTER(SolveOpts), _p, _p, _i32,
+                                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                                    ctypes.POINTER(ctypes.c_double)]),
         "ddmgnn_problem_get_tuning": (ctypes.c_int, [_p, ctypes.POINTER(Tuning)]),
         "ddmgnn_autotune": (ctypes.c_int, [_p, _p, ctypes.POINTER(SolveOpts), _i32, ctypes.POINTER(Tuning),
                                            ctypes.POINTER(ctypes.c_double)]),
@@ -355,6 +358,14 @@ class Problem:
         if check:
             _check(rc)
         return st
+
+    def time_apply_stages(self, r, z, opts: SolveOpts | None = None, reps: int = 10):
+        """(local, coarse, glue) milliseconds of one apply, each stage replayed as a HIP graph."""
+        o = opts or default_opts()
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(lib().ddmgnn_time_apply_stages(self.ctx.h, self.h, ctypes.byref(o), _dev(r), _dev(z), reps,
+                                              ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def set_tuning(self, small_lds: int = 0, vec_blocks: int = 0):
         t = Tuning(small_lds, vec_blocks)

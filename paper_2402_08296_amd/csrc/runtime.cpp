@@ -215,9 +215,23 @@ int enqueue_dss(Batch& B, const DevProb* tab, int precision, int apply, bool cap
     }
     if (precision == DDMGNN_BF16) {
         DssMfmaArgs a{tab, B.work_mfma.p, M.steps.p, M.dec.p, M.kbar, (float)M.alpha, apply};
-        HIP_TRY(launch_dss_mfma(a, B.n_mfma, B.lds_mfma, MFMA_BLOCK, s, check));
-        a.work = B.work_mfma_small.p;
-        HIP_TRY(launch_dss_mfma(a, B.n_mfma_small, B.lds_mfma_small, MFMA_SMALL_BLOCK, s, check));
+        if (B.n_mfma > 0 && B.n_mfma_small > 0) {
+            // the two workgroup sizes on two streams, so that either launch's last
+            // round overlaps the other's work; joined back before the next kernel
+            ddmgnn_ctx* ctx = B.ctx;
+            HIP_TRY(hipEventRecord(ctx->fork_ev, s));
+            HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->fork_ev, 0));
+            DssMfmaArgs small = a;
+            small.work = B.work_mfma_small.p;
+            HIP_TRY(launch_dss_mfma(small, B.n_mfma_small, B.lds_mfma_small, MFMA_SMALL_BLOCK, ctx->side, check));
+            HIP_TRY(hipEventRecord(ctx->join_ev, ctx->side));
+            HIP_TRY(launch_dss_mfma(a, B.n_mfma, B.lds_mfma, MFMA_BLOCK, s, check));
+            HIP_TRY(hipStreamWaitEvent(s, ctx->join_ev, 0));
+        } else {
+            HIP_TRY(launch_dss_mfma(a, B.n_mfma, B.lds_mfma, MFMA_BLOCK, s, check));
+            a.work = B.work_mfma_small.p;
+            HIP_TRY(launch_dss_mfma(a, B.n_mfma_small, B.lds_mfma_small, MFMA_SMALL_BLOCK, s, check));
+        }
         const bool qlds = valu_q_in_lds(B.max_k_rest, DDMGNN_FP32, M.d);
         HIP_TRY(launch_dss_valu(tab, B.work_rest.p, B.n_rest, DDMGNN_FP32, M.d, qlds, M.kbar, M.alpha, apply,
                                 M.theta32.p, M.theta64.p, qlds ? valu_shmem(B.max_k_rest, DDMGNN_FP32, M.d) : 0, s,
@@ -799,6 +813,9 @@ ddmgnn_ctx::~ddmgnn_ctx() {
     last_batch.reset();
     if (host_pinned) (void)hipHostFree(host_pinned);
     if (cap) (void)hipStreamDestroy(cap);
+    if (side) (void)hipStreamDestroy(side);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
 }
 
 // Drops the cached batches that hold P (its own and the context's last one).
@@ -841,6 +858,9 @@ int ddmgnn_ctx_create(void* hip_stream, ddmgnn_ctx** out) {
     c->launch = c->stream;
     HIP_TRY(hipGetDevice(&c->device));
     HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
     HIP_TRY(c->partials.alloc(VEC_GRID));
     HIP_TRY(c->counters.alloc(4));
     HIP_TRY(hipMemset(c->counters.p, 0, 4 * sizeof(unsigned)));
@@ -1088,6 +1108,75 @@ int ddmgnn_dss_forward(ddmgnn_ctx* ctx, ddmgnn_problem* P, int32_t precision, co
     if (int rc = enqueue_dss(B, B.hook.p, precision, 0, false)) return rc;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return DDMGNN_OK;
+}
+
+int ddmgnn_time_apply_stages(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* opts, const double* r,
+                             double* z, int32_t reps, double* local_ms, double* coarse_ms, double* glue_ms) {
+    if (!ctx || !P || !opts || !r || !z) return fail(DDMGNN_E_INVALID, "null argument");
+    if (r == z) return fail(DDMGNN_E_INVALID, "r and z must not alias");
+    if (reps < 1) return fail(DDMGNN_E_INVALID, "reps must be >= 1");
+    if (int rc = check_opts(*opts)) return rc;
+    if (int rc = solo_batch(P)) return rc;
+    Batch& B = *P->solo;
+    bool changed = false;
+    if (opts->local_solver == DDMGNN_LOCAL_LU) {
+        if (int rc = prepare_lu(P)) return rc;
+    } else if (int rc = prepare_dss(B, opts->precision, changed)) {
+        return rc;
+    }
+    DevProb v = make_view(P);
+    v.r = const_cast<double*>(r);  // read only
+    v.z = z;
+    v.st = nullptr;
+    HIP_TRY(upload_async(B.hook.p, &v, sizeof(v), ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    const IterArgs ia = iter_args(*opts, -1);
+    const DevProb* tab = B.hook.p;
+    double* outs[3] = {local_ms, coarse_ms, glue_ms};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int rc = DDMGNN_OK;
+    for (int stage = 0; stage < 3 && rc == DDMGNN_OK; ++stage) {
+        if (stage == 1 && !opts->coarse) {
+            if (outs[1]) *outs[1] = 0.0;
+            continue;
+        }
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        hipError_t he = hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeRelaxed);
+        if (he == hipSuccess) {
+            ctx->launch = ctx->cap;
+            for (int i = 0; i < reps && rc == DDMGNN_OK && he == hipSuccess; ++i) {
+                if (stage == 0)
+                    rc = enqueue_dss(B, tab, opts->precision, 1, true, opts->local_solver);
+                else if (stage == 1)
+                    he = launch_coarse(tab, B.coarse_rows.p, B.n_coarse, ctx->cap, false);
+                else
+                    he = launch_prolong(tab, B.vec_blk.p, B.n_vec, 1, ia, ctx->cap, false);
+            }
+            ctx->launch = ctx->stream;
+            const hipError_t ee = hipStreamEndCapture(ctx->cap, &g);
+            if (he == hipSuccess) he = ee;
+        }
+        if (he == hipSuccess && rc == DDMGNN_OK) he = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        float ms = 0.f;
+        if (he == hipSuccess && rc == DDMGNN_OK) {
+            he = hipGraphLaunch(ge, ctx->stream);  // warm-up
+            if (he == hipSuccess) he = hipEventRecord(e0, ctx->stream);
+            if (he == hipSuccess) he = hipGraphLaunch(ge, ctx->stream);
+            if (he == hipSuccess) he = hipEventRecord(e1, ctx->stream);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (ge) (void)hipGraphExecDestroy(ge);
+        if (he != hipSuccess && rc == DDMGNN_OK) rc = fail(DDMGNN_E_HIP, hipGetErrorString(he));
+        if (rc == DDMGNN_OK && outs[stage]) *outs[stage] = (double)ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int ddmgnn_precond_apply(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_solve_opts* opts, const double* r,

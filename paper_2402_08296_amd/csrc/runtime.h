@@ -115,6 +115,8 @@ struct ddmgnn_ctx {
     hipStream_t stream = nullptr;   // the caller's stream: all work runs here
     hipStream_t launch = nullptr;   // where kernels are enqueued (= stream, or cap while capturing)
     hipStream_t cap = nullptr;      // own non-blocking stream for graph capture (the null stream cannot be captured)
+    hipStream_t side = nullptr;     // second stream of a forked launch (joined back before the next step)
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     int device = 0;
     ddmgnn::DevBuf<double> partials;
     ddmgnn::DevBuf<unsigned> counters;
