@@ -86,3 +86,37 @@ def test_vector_workgroups_and_autotune(ctx, mixed):
         prob.set_tuning(small_lds=200_000)
     with pytest.raises(dg.DDMGNNError):
         prob.set_tuning(vec_blocks=12)
+
+
+def test_forked_schedule_in_batches_and_stage_timing(ctx, mixed):
+    """Problems with the split schedule (two DSS launches on two streams) solved in one
+    batch give the bits of their solo solves under the default schedule; the stage
+    timer leaves z = M(r) and reports positive times."""
+    print("[gpu] forked schedule in a batch / stage timing", flush=True)
+    p, hp = mixed
+    q = W.make_problem(32, 9000, 14, 0.45)
+    hq = host_problem(q)
+    model = dg.Model(ctx, SMOOTHER)
+    o = dg.default_opts(precision="bf16", rtol=1e-6)
+    solo = []
+    for pp, hh in ((p, hp), (q, hq)):
+        prob = dg.Problem(ctx, hh, model)
+        u = torch.empty(pp.n, dtype=torch.float64, device="cuda")
+        st = prob.solve(u, o)
+        solo.append((u.cpu().numpy(), st.iterations))
+    probs = [dg.Problem(ctx, hh, model) for hh in (hp, hq)]
+    for pr in probs:
+        pr.set_tuning(small_lds=79 * 1024)
+    outs = [torch.empty(pp.n, dtype=torch.float64, device="cuda") for pp in (p, q)]
+    sts = dg.solve_batch(ctx, probs, outs, o)
+    for (u, it), ub, st in zip(solo, outs, sts):
+        assert st.converged and st.iterations == it and np.array_equal(ub.cpu().numpy(), u)
+    r = np.random.default_rng(5).standard_normal(p.n)
+    r[p.mesh.dirichlet == 1] = 0
+    z1 = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    z2 = torch.empty_like(z1)
+    probs[0].apply(_dev(r), z1, o)
+    t_local, t_coarse, t_glue = probs[0].time_apply_stages(_dev(r), z2, o, reps=3)
+    print(f"[gpu]   stages {t_local:.3f} {t_coarse:.3f} {t_glue:.3f} ms", flush=True)
+    assert t_local > 0 and t_coarse > 0 and t_glue > 0
+    assert torch.equal(z1, z2)
