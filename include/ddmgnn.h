@@ -98,8 +98,22 @@ int ddmgnn_model_create(ddmgnn_ctx* ctx, const ddmgnn_model_desc* desc, const fl
                         int64_t n_theta, ddmgnn_model** out);
 int ddmgnn_model_destroy(ddmgnn_model* model);
 
+/* Seeded Xavier-uniform weights in the layout above (Sec. IV.B initialisation),
+ * host only: matrix entries in layout order take consecutive outputs x of one
+ * splitmix64 stream from state `seed`; u = (x >> 11) 2^-53 and the entry is
+ * a (2u - 1) in double with a = sqrt(6 / (fan_in + fan_out)), rounded to float.
+ * Biases are 0. theta_out holds n_theta = kbar (11 d^2 + 15 d + 1) floats
+ * (E_INVALID otherwise). */
+int ddmgnn_model_init_xavier(const ddmgnn_model_desc* desc, uint64_t seed, float* theta_out, int64_t n_theta);
+
+/* Where the arrays of a problem descriptor live. */
+enum { DDMGNN_MEM_HOST = 0, DDMGNN_MEM_DEVICE = 1 };
+
 /* One Poisson-Dirichlet problem A u = b (eqs. (1)-(2)) with its overlapping
- * decomposition (Sec. II.A). All pointers are host pointers.
+ * decomposition (Sec. II.A). All pointers are host pointers, or all are device
+ * pointers with mem_kind = DDMGNN_MEM_DEVICE (every entry point that takes a
+ * descriptor then copies the arrays to the host once, synchronously, for
+ * validation and setup).
  *   xy[2N]            node coordinates (x0, y0, x1, y1, ...)
  *   tri[3T]           triangles (node ids), used for the DSS graphs (Sec. III.B)
  *   dirichlet[N]      1 at Dirichlet nodes, else 0. Dirichlet rows of A must be
@@ -134,6 +148,7 @@ typedef struct {
     const int64_t* sub_ptr;
     const int32_t* sub_nodes;
     const double* weights;
+    int32_t mem_kind;    /* DDMGNN_MEM_HOST (0) or DDMGNN_MEM_DEVICE */
 } ddmgnn_problem_desc;
 
 /* Validate a descriptor on the host (no device needed). */
@@ -260,6 +275,11 @@ int ddmgnn_apply_intermediates(ddmgnn_ctx* ctx, ddmgnn_problem* prob, double* s,
 /* DSS_theta forward pass (Sec. III.B) on every sub-mesh of the problem. c and
  * out: device, sub_ptr[K] doubles in sub_nodes order; c holds each sub-mesh's
  * input c_i, out receives r~_i = D^kbar(H^kbar). */
+/* The same forward pass on sub-mesh `sub` alone: c and out are device arrays of
+ * k_sub = sub_ptr[sub+1] - sub_ptr[sub] doubles (the sub-mesh's nodes in
+ * sub_nodes order). Gives the bits of the matching slice of ddmgnn_dss_forward. */
+int ddmgnn_dss_forward_sub(ddmgnn_ctx* ctx, ddmgnn_problem* prob, int32_t precision, int32_t sub,
+                           const double* c, double* out);
 int ddmgnn_dss_forward(ddmgnn_ctx* ctx, ddmgnn_problem* prob, int32_t precision, const double* c,
                        double* out);
 

@@ -19,6 +19,7 @@ FCG, PCG, CG, FGMRES = 0, 1, 2, 3
 FP64, FP32, BF16 = 0, 1, 2
 PROLONG_POU, PROLONG_UNWEIGHTED = 0, 1
 LOCAL_GNN, LOCAL_LU = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
 STATUS = {0: "OK", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_HIP", -4: "E_NOT_SPD", -5: "E_BREAKDOWN",
           -6: "E_MAXIT", -7: "E_NONFINITE", -8: "E_BUDGET", -9: "E_PENDING"}
 PRECISION = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
@@ -40,7 +41,7 @@ class ModelDesc(ctypes.Structure):
 class ProblemDesc(ctypes.Structure):
     _fields_ = [("n_nodes", _i64), ("xy", _p), ("n_tri", _i64), ("tri", _p), ("dirichlet", _p),
                 ("a_rowptr", _p), ("a_col", _p), ("a_val", _p), ("b", _p), ("u0", _p),
-                ("n_sub", _i32), ("sub_ptr", _p), ("sub_nodes", _p), ("weights", _p)]
+                ("n_sub", _i32), ("sub_ptr", _p), ("sub_nodes", _p), ("weights", _p), ("mem_kind", _i32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -125,6 +126,8 @@ def lib():
                                                     ctypes.POINTER(_i64)]),
         "ddmgnn_setup_coarse": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), _p, _p]),
         "ddmgnn_setup_local_inverse": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), _i32, _p]),
+        "ddmgnn_dss_forward_sub": (ctypes.c_int, [_p, _p, _i32, _i32, _p, _p]),
+        "ddmgnn_model_init_xavier": (ctypes.c_int, [ctypes.POINTER(ModelDesc), ctypes.c_uint64, _p, _i64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -264,6 +267,15 @@ def setup_local_inverse(hp: HostProblem, sub: int):
     return inv
 
 
+def init_xavier(seed: int, kbar: int = 30, d: int = 10, alpha: float = 1e-3) -> np.ndarray:
+    """Seeded Xavier-uniform weights from the library (host only)."""
+    desc = ModelDesc(kbar, d, alpha)
+    n = kbar * (11 * d * d + 15 * d + 1)
+    th = np.empty(n, dtype=np.float32)
+    _check(lib().ddmgnn_model_init_xavier(ctypes.byref(desc), seed, th.ctypes.data_as(_p), n))
+    return th
+
+
 def default_opts(**kw) -> SolveOpts:
     o = SolveOpts()
     lib().ddmgnn_default_opts(ctypes.byref(o))
@@ -327,10 +339,12 @@ class Model:
 
 
 class Problem:
-    def __init__(self, ctx: Context, hp: HostProblem, model: Model):
+    def __init__(self, ctx: Context, hp: HostProblem, model: Model, desc: ProblemDesc | None = None):
+        """desc: a descriptor to use instead of hp's host arrays (e.g. device pointers
+        with mem_kind = MEM_DEVICE); hp still describes the problem's sizes."""
         self.ctx = ctx
         self.hp = hp
-        d = hp.desc()
+        d = desc if desc is not None else hp.desc()
         h = _p()
         _check(lib().ddmgnn_problem_create(ctx.h, ctypes.byref(d), model.h, ctypes.byref(h)))
         self.h = h
@@ -408,6 +422,12 @@ class Problem:
         if isinstance(precision, str):
             precision = PRECISION[precision]
         _check(lib().ddmgnn_dss_forward(self.ctx.h, self.h, precision, _dev(c), _dev(out)))
+
+    def dss_forward_sub(self, sub: int, c, out, precision=FP32):
+        """DSS forward of sub-mesh `sub` alone (c, out: its k_sub values)."""
+        if isinstance(precision, str):
+            precision = PRECISION[precision]
+        _check(lib().ddmgnn_dss_forward_sub(self.ctx.h, self.h, precision, sub, _dev(c), _dev(out)))
 
     def spmv(self, x, y):
         _check(lib().ddmgnn_spmv(self.ctx.h, self.h, _dev(x), _dev(y)))

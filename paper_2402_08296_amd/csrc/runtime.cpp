@@ -605,6 +605,52 @@ int batch_true_residual(Batch& B, const std::vector<uint8_t>* which) {
     return batch_poll(B);
 }
 
+int host_desc(const ddmgnn_problem_desc* in, HostDesc& h, const ddmgnn_problem_desc** out) {
+    if (in->mem_kind == DDMGNN_MEM_HOST) {
+        *out = in;
+        return DDMGNN_OK;
+    }
+    if (in->mem_kind != DDMGNN_MEM_DEVICE) return fail(DDMGNN_E_INVALID, "mem_kind must be HOST or DEVICE");
+    const int64_t n = in->n_nodes, nt = in->n_tri, K = in->n_sub;
+    if (n <= 0 || nt <= 0 || K <= 0 || !in->a_rowptr || !in->sub_ptr)
+        return fail(DDMGNN_E_INVALID, "empty problem");
+    auto get = [&](auto& vec, const auto* src, int64_t count) -> hipError_t {
+        if (!src || count <= 0) return hipSuccess;
+        vec.resize((size_t)count);
+        return hipMemcpy(vec.data(), src, (size_t)count * sizeof(vec[0]), hipMemcpyDeviceToHost);
+    };
+    HIP_TRY(get(h.a_rowptr, in->a_rowptr, n + 1));
+    HIP_TRY(get(h.sub_ptr, in->sub_ptr, K + 1));
+    const int64_t nnz = h.a_rowptr[n], sk = h.sub_ptr[K];
+    if (nnz < 0 || sk < 0) return fail(DDMGNN_E_INVALID, "negative sizes");
+    HIP_TRY(get(h.xy, in->xy, 2 * n));
+    HIP_TRY(get(h.tri, in->tri, 3 * nt));
+    HIP_TRY(get(h.dirichlet, in->dirichlet, n));
+    HIP_TRY(get(h.a_col, in->a_col, nnz));
+    HIP_TRY(get(h.a_val, in->a_val, nnz));
+    HIP_TRY(get(h.b, in->b, n));
+    HIP_TRY(get(h.u0, in->u0, n));
+    HIP_TRY(get(h.sub_nodes, in->sub_nodes, sk));
+    HIP_TRY(get(h.weights, in->weights, sk));
+    auto ptr = [](auto& vec) { return vec.empty() ? nullptr : vec.data(); };
+    ddmgnn_problem_desc& d = h.desc;
+    d = *in;
+    d.mem_kind = DDMGNN_MEM_HOST;
+    d.xy = ptr(h.xy);
+    d.tri = ptr(h.tri);
+    d.dirichlet = ptr(h.dirichlet);
+    d.a_rowptr = ptr(h.a_rowptr);
+    d.a_col = ptr(h.a_col);
+    d.a_val = ptr(h.a_val);
+    d.b = ptr(h.b);
+    d.u0 = ptr(h.u0);
+    d.sub_ptr = ptr(h.sub_ptr);
+    d.sub_nodes = ptr(h.sub_nodes);
+    d.weights = ptr(h.weights);
+    *out = &h.desc;
+    return DDMGNN_OK;
+}
+
 int problem_vec_blocks(const ddmgnn_problem* P) {
     const int autom = vec_blocks(P->hs.n);
     return P->tune.vec_blocks > 0 ? std::min(autom, P->tune.vec_blocks) : autom;
@@ -909,21 +955,62 @@ int ddmgnn_model_create(ddmgnn_ctx* ctx, const ddmgnn_model_desc* desc, const fl
     return DDMGNN_OK;
 }
 
+int ddmgnn_model_init_xavier(const ddmgnn_model_desc* desc, uint64_t seed, float* theta, int64_t n_theta) {
+    if (!desc || !theta) return fail(DDMGNN_E_INVALID, "null argument");
+    const int64_t d = desc->d, kbar = desc->kbar;
+    if (d < 1 || kbar < 1 || n_theta != kbar * (11 * d * d + 15 * d + 1))
+        return fail(DDMGNN_E_INVALID, "n_theta must equal kbar*(11d^2+15d+1)");
+    uint64_t state = seed;
+    auto next = [&]() {  // splitmix64
+        state += 0x9E3779B97F4A7C15ull;
+        uint64_t z = state;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    int64_t pos = 0;
+    auto layer = [&](int64_t fan_out, int64_t fan_in) {
+        const double a = std::sqrt(6.0 / (double)(fan_in + fan_out));
+        for (int64_t i = 0; i < fan_out * fan_in; ++i) {
+            const double u = (double)(next() >> 11) * 0x1.0p-53;
+            theta[pos++] = (float)(a * (2.0 * u - 1.0));
+        }
+        for (int64_t i = 0; i < fan_out; ++i) theta[pos++] = 0.0f;
+    };
+    for (int64_t k = 0; k < kbar; ++k) {
+        for (int phi = 0; phi < 2; ++phi) {
+            layer(d, 2 * d + 3);
+            layer(d, d);
+        }
+        layer(d, 3 * d + 1);
+        layer(d, d);
+        layer(d, d);
+        layer(1, d);
+    }
+    return DDMGNN_OK;
+}
+
 int ddmgnn_model_destroy(ddmgnn_model* m) {
     delete m;
     return DDMGNN_OK;
 }
 
-int ddmgnn_validate_problem(const ddmgnn_problem_desc* desc) {
-    if (!desc) return fail(DDMGNN_E_INVALID, "null descriptor");
+int ddmgnn_validate_problem(const ddmgnn_problem_desc* desc_in) {
+    if (!desc_in) return fail(DDMGNN_E_INVALID, "null descriptor");
+    HostDesc hd;
+    const ddmgnn_problem_desc* desc = nullptr;
+    if (int rc = host_desc(desc_in, hd, &desc)) return rc;
     std::string e = validate(*desc);
     if (!e.empty()) return fail(DDMGNN_E_INVALID, e);
     return DDMGNN_OK;
 }
 
-int ddmgnn_problem_create(ddmgnn_ctx* ctx, const ddmgnn_problem_desc* desc, const ddmgnn_model* model,
+int ddmgnn_problem_create(ddmgnn_ctx* ctx, const ddmgnn_problem_desc* desc_in, const ddmgnn_model* model,
                           ddmgnn_problem** out) {
-    if (!ctx || !desc || !model || !out) return fail(DDMGNN_E_INVALID, "null argument");
+    if (!ctx || !desc_in || !model || !out) return fail(DDMGNN_E_INVALID, "null argument");
+    HostDesc hd;
+    const ddmgnn_problem_desc* desc = nullptr;
+    if (int rc = host_desc(desc_in, hd, &desc)) return rc;
     int rc = ddmgnn_validate_problem(desc);
     if (rc) return rc;
     HostSetup hs;
@@ -1033,8 +1120,12 @@ int ddmgnn_problem_device_bytes(const ddmgnn_problem* P, int64_t* bytes) {
     return DDMGNN_OK;
 }
 
-int ddmgnn_setup_local_graph(const ddmgnn_problem_desc* desc, int32_t sub, int32_t* rowptr, int32_t* col,
+int ddmgnn_setup_local_graph(const ddmgnn_problem_desc* desc_in, int32_t sub, int32_t* rowptr, int32_t* col,
                              int64_t* n_edges_sub) {
+    if (!desc_in) return fail(DDMGNN_E_INVALID, "null descriptor");
+    HostDesc hd;
+    const ddmgnn_problem_desc* desc = nullptr;
+    if (int rc = host_desc(desc_in, hd, &desc)) return rc;
     int rc = ddmgnn_validate_problem(desc);
     if (rc) return rc;
     if (sub < 0 || sub >= desc->n_sub) return fail(DDMGNN_E_INVALID, "sub-mesh index out of range");
@@ -1050,7 +1141,11 @@ int ddmgnn_setup_local_graph(const ddmgnn_problem_desc* desc, int32_t sub, int32
     return DDMGNN_OK;
 }
 
-int ddmgnn_setup_coarse(const ddmgnn_problem_desc* desc, double* a0, double* a0inv) {
+int ddmgnn_setup_coarse(const ddmgnn_problem_desc* desc_in, double* a0, double* a0inv) {
+    if (!desc_in) return fail(DDMGNN_E_INVALID, "null descriptor");
+    HostDesc hd;
+    const ddmgnn_problem_desc* desc = nullptr;
+    if (int rc = host_desc(desc_in, hd, &desc)) return rc;
     int rc = ddmgnn_validate_problem(desc);
     if (rc) return rc;
     HostSetup hs;
@@ -1062,7 +1157,11 @@ int ddmgnn_setup_coarse(const ddmgnn_problem_desc* desc, double* a0, double* a0i
     return DDMGNN_OK;
 }
 
-int ddmgnn_setup_local_inverse(const ddmgnn_problem_desc* desc, int32_t sub, double* inv) {
+int ddmgnn_setup_local_inverse(const ddmgnn_problem_desc* desc_in, int32_t sub, double* inv) {
+    if (!desc_in) return fail(DDMGNN_E_INVALID, "null descriptor");
+    HostDesc hd;
+    const ddmgnn_problem_desc* desc = nullptr;
+    if (int rc = host_desc(desc_in, hd, &desc)) return rc;
     int rc = ddmgnn_validate_problem(desc);
     if (rc) return rc;
     if (sub < 0 || sub >= desc->n_sub || !inv) return fail(DDMGNN_E_INVALID, "sub-mesh index out of range or null output");
@@ -1107,6 +1206,46 @@ int ddmgnn_dss_forward(ddmgnn_ctx* ctx, ddmgnn_problem* P, int32_t precision, co
     HIP_TRY(upload_async(B.hook.p, &v, sizeof(v), ctx->stream));
     if (int rc = enqueue_dss(B, B.hook.p, precision, 0, false)) return rc;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DDMGNN_OK;
+}
+
+int ddmgnn_dss_forward_sub(ddmgnn_ctx* ctx, ddmgnn_problem* P, int32_t precision, int32_t sub, const double* c,
+                           double* out) {
+    if (!ctx || !P || !c || !out) return fail(DDMGNN_E_INVALID, "null argument");
+    if (precision < 0 || precision > 2) return fail(DDMGNN_E_INVALID, "bad precision");
+    if (sub < 0 || sub >= P->hs.K) return fail(DDMGNN_E_INVALID, "sub-mesh index out of range");
+    if (int rc = solo_batch(P)) return rc;
+    Batch& B = *P->solo;
+    bool changed = false;
+    if (int rc = prepare_dss(B, precision, changed)) return rc;
+    hipStream_t s = ctx->stream;
+    const int64_t base = P->hs.sub_ptr[sub], k = P->hs.sub_ptr[sub + 1] - base;
+    if (!P->fwd_in.p) {
+        HIP_TRY(P->fwd_in.alloc((size_t)P->hs.sk));
+        HIP_TRY(P->fwd_out.alloc((size_t)P->hs.sk));
+        HIP_TRY(P->one_work.alloc(1));
+    }
+    const int2 item = make_int2(0, sub);
+    HIP_TRY(upload_async(P->one_work.p, &item, sizeof(item), s));
+    HIP_TRY(hipMemcpyAsync(P->fwd_in.p + base, c, (size_t)k * sizeof(double), hipMemcpyDeviceToDevice, s));
+    DevProb v = make_view(P);
+    v.c_in = P->fwd_in.p;
+    v.local = P->fwd_out.p;
+    v.st = nullptr;
+    HIP_TRY(upload_async(B.hook.p, &v, sizeof(v), s));
+    const ModelDev& M = *B.model;
+    if (precision == DDMGNN_BF16 && runs_mfma(B, P)) {
+        DssMfmaArgs a{B.hook.p, P->one_work.p, M.steps.p, M.dec.p, M.kbar, (float)M.alpha, 0};
+        HIP_TRY(launch_dss_mfma(a, 1, P->mfma_need[sub], MFMA_BLOCK, s, true));
+    } else {
+        const int vprec = precision == DDMGNN_BF16 ? DDMGNN_FP32 : precision;
+        const int mk = precision == DDMGNN_BF16 ? B.max_k_rest : B.max_k_all;  // as prepare_dss sized it
+        const bool qlds = valu_q_in_lds(mk, vprec, M.d);
+        HIP_TRY(launch_dss_valu(B.hook.p, P->one_work.p, 1, vprec, M.d, qlds, M.kbar, M.alpha, 0, M.theta32.p,
+                                M.theta64.p, qlds ? valu_shmem(mk, vprec, M.d) : 0, s, true));
+    }
+    HIP_TRY(hipMemcpyAsync(out, P->fwd_out.p + base, (size_t)k * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return DDMGNN_OK;
 }
 

@@ -101,6 +101,17 @@ ddmgnn_problem* batch_problem(const Batch& B, int i);
 int batch_true_residual(Batch& B, const std::vector<uint8_t>* which);
 // Kernel that runs the local solves of problem P: 0 FP64 VALU DSS, 1 FP32 VALU DSS,
 // 2 BF16 MFMA DSS, 3 exact local solves (DDM-LU).
+// Host copies of a descriptor's arrays when they are device memory.
+struct HostDesc {
+    std::vector<double> xy, a_val, b, u0, weights;
+    std::vector<int32_t> tri, a_rowptr, a_col, sub_nodes;
+    std::vector<uint8_t> dirichlet;
+    std::vector<int64_t> sub_ptr;
+    ddmgnn_problem_desc desc{};
+};
+// *out = in when its arrays are host memory; else copies them into h (sizes
+// from n_nodes, n_tri, n_sub, a_rowptr[N] and sub_ptr[K]) and *out = &h.desc.
+int host_desc(const ddmgnn_problem_desc* in, HostDesc& h, const ddmgnn_problem_desc** out);
 // Workgroups of a problem in the vector kernels (its tuning, else vec_blocks(n)).
 int problem_vec_blocks(const ddmgnn_problem* P);
 // Device bytes of the FGMRES storage of a problem of n nodes, cycles of R steps.
@@ -155,6 +166,9 @@ struct ddmgnn_problem {
     bool mfma_fits = false;          // every sub-mesh fits the MFMA kernel's LDS
     std::vector<uint32_t> mfma_need; // per sub-mesh, LDS bytes of the MFMA kernel
     ddmgnn_tuning tune{};            // launch schedule (ddmgnn_problem_set_tuning / ddmgnn_autotune)
+    // one-sub-mesh forward entry: per-slot input and output, and its one-item work list
+    ddmgnn::DevBuf<double> fwd_in, fwd_out;
+    ddmgnn::DevBuf<int2> one_work;
     // apply buffers
     ddmgnn::DevBuf<double> s, y0, y, local;
     ddmgnn::DevBuf<double> qglobal64, hglobal64;

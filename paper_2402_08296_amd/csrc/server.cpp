@@ -309,10 +309,13 @@ int ddmgnn_server_create(ddmgnn_ctx* ctx, const ddmgnn_model* model, int64_t hbm
     return DDMGNN_OK;
 }
 
-int ddmgnn_server_submit(ddmgnn_server* srv, const ddmgnn_problem_desc* desc, const ddmgnn_solve_opts* opts,
+int ddmgnn_server_submit(ddmgnn_server* srv, const ddmgnn_problem_desc* desc_in, const ddmgnn_solve_opts* opts,
                          uint64_t* ticket) {
-    if (!srv || !desc || !opts || !ticket) return fail(DDMGNN_E_INVALID, "null argument");
+    if (!srv || !desc_in || !opts || !ticket) return fail(DDMGNN_E_INVALID, "null argument");
     if (int rc = check_opts(*opts)) return rc;
+    HostDesc hd;
+    const ddmgnn_problem_desc* desc = nullptr;
+    if (int rc = host_desc(desc_in, hd, &desc)) return rc;
     if (desc->n_nodes <= 0 || desc->n_tri <= 0 || desc->n_sub <= 0 || !desc->sub_ptr)
         return fail(DDMGNN_E_INVALID, "empty problem");
     auto r = std::make_unique<Request>();

@@ -165,3 +165,16 @@ def test_tune_cache_roundtrip(tmp_path):
     tune.tuned(c, hp, dg.default_opts(precision="fp32"), "gfx950", path)  # another class
     assert c.calls == 1
     assert tune.config_class(hp.n, hp.sub_ptr, opts) == tune.config_class(hp.n, list(hp.sub_ptr), opts)
+
+
+def test_library_xavier_matches_generator():
+    """ddmgnn_model_init_xavier and the seeded input generator build the same weights, bit for bit."""
+    for seed, kbar, d in [(42, 30, 10), (7, 5, 5), (3, 10, 20)]:
+        a = dg.init_xavier(seed, kbar, d)
+        b = W.xavier_theta(seed, kbar, d)
+        assert a.dtype == b.dtype and a.tobytes() == b.tobytes()
+    with pytest.raises(dg.DDMGNNError):
+        desc = dg.ModelDesc(30, 10, 1e-3)
+        import ctypes
+        th = np.empty(10, dtype=np.float32)
+        dg._check(dg.lib().ddmgnn_model_init_xavier(ctypes.byref(desc), 1, th.ctypes.data_as(ctypes.c_void_p), 10))

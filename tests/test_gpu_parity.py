@@ -410,6 +410,53 @@ def test_fgmres_bf16_and_graph_replay(ctx, c1):
     assert eager.iterations == s1.iterations and torch.equal(u1, u2)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_dss_forward_sub_matches_full(ctx, c1, prec):
+    """The one-sub-mesh forward entry gives the bits of the full forward's slice."""
+    print(f"[gpu] dss_forward_sub {prec}", flush=True)
+    p, hp = c1
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, XAVIER))
+    c = _c_inputs(p, hp, 4)
+    full = torch.empty(hp.sub_nodes.size, dtype=torch.float64, device="cuda")
+    prob.dss_forward(_dev(c), full, prec)
+    for i in (0, hp.K // 2, hp.K - 1):
+        sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
+        one = torch.empty(sl.stop - sl.start, dtype=torch.float64, device="cuda")
+        prob.dss_forward_sub(i, _dev(c[sl]), one, prec)
+        assert torch.equal(one, full[sl])
+    with pytest.raises(dg.DDMGNNError):
+        prob.dss_forward_sub(hp.K, _dev(c[:10]), one, prec)
+
+
+def test_problem_from_device_arrays(ctx, c1):
+    """A descriptor of device pointers (mem_kind = DEVICE) builds the same problem as the
+    host one: same sizes, bitwise equal solves."""
+    print("[gpu] problem from device arrays", flush=True)
+    import ctypes
+    p, hp = c1
+    model = dg.Model(ctx, SMOOTHER)
+    keep = {}
+
+    def dptr(name, a):
+        t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        keep[name] = t
+        return ctypes.c_void_p(t.data_ptr())
+
+    d = dg.ProblemDesc(hp.n, dptr("xy", hp.xy), hp.tri.size // 3, dptr("tri", hp.tri), dptr("dir", hp.dirichlet),
+                       dptr("rp", hp.rowptr), dptr("col", hp.col), dptr("val", hp.val), dptr("b", hp.b),
+                       dptr("u0", hp.u0), hp.K, dptr("sp", hp.sub_ptr), dptr("sn", hp.sub_nodes),
+                       dptr("w", hp.weights), dg.MEM_DEVICE)
+    torch.cuda.synchronize()
+    pd = dg.Problem(ctx, hp, model, desc=d)
+    ph = dg.Problem(ctx, hp, model)
+    assert (pd.n, pd.nnz, pd.K, pd.sum_k, pd.n_edges) == (ph.n, ph.nnz, ph.K, ph.sum_k, ph.n_edges)
+    u1 = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    u2 = torch.empty_like(u1)
+    o = dg.default_opts(precision="fp32", rtol=1e-6)
+    s1, s2 = pd.solve(u1, o), ph.solve(u2, o)
+    assert s1.converged and s1.iterations == s2.iterations and torch.equal(u1, u2)
+
+
 def test_xavier_history_matches_oracle(ctx, c1):
     """The seeded (untrained) model stagnates; the GPU recurrence tracks the oracle's."""
     print("[gpu] xavier history", flush=True)

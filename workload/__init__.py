@@ -228,30 +228,41 @@ def theta_size(kbar: int, d: int) -> int:
     return kbar * (11 * d * d + 15 * d + 1)
 
 
+def splitmix64(seed: int, n: int) -> np.ndarray:
+    """n outputs of the splitmix64 generator (Steele, Lea and Flood, 2014) from state `seed`:
+    state += 0x9E3779B97F4A7C15, then the output mix of the state (two xor-shift-multiply
+    rounds and a final xor-shift). Counter-based: output i depends on seed + (i + 1) * gamma only."""
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + np.arange(1, n + 1, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
 def xavier_theta(seed: int, kbar: int = 30, d: int = 10) -> np.ndarray:
     """Seeded Xavier-uniform weights, zero biases (Sec. IV.B initialisation).
 
     Flat float32 layout, block k = 1..kbar in order, each block holding
     Phi_out {W1[d,2d+3], b1[d], W2[d,d], b2[d]}, Phi_in {same},
     Psi {W1[d,3d+1], b1[d], W2[d,d], b2[d]}, Dec {W1[d,d], b1[d], W2[1,d], b2[1]},
-    matrices row-major (out, in).
+    matrices row-major (out, in). Matrix entries, in layout order, take consecutive
+    outputs of one splitmix64 stream: u = (x >> 11) 2^-53, w = a (2u - 1) in float64
+    with a = sqrt(6 / (fan_in + fan_out)), rounded to float32. The library's
+    ddmgnn_model_init_xavier implements the same recipe.
     """
-    rng = np.random.Generator(np.random.PCG64(seed))
-    parts = []
-
-    def lin(fan_out, fan_in):
-        a = np.sqrt(6.0 / (fan_in + fan_out))
-        parts.append(rng.uniform(-a, a, fan_out * fan_in))
-        parts.append(np.zeros(fan_out))
-
+    shapes = []
     for _ in range(kbar):
         for _phi in range(2):
-            lin(d, 2 * d + 3)
-            lin(d, d)
-        lin(d, 3 * d + 1)
-        lin(d, d)
-        lin(d, d)
-        lin(1, d)
+            shapes += [(d, 2 * d + 3), (d, d)]
+        shapes += [(d, 3 * d + 1), (d, d), (d, d), (1, d)]
+    n_mat = sum(o * i for o, i in shapes)
+    u = (splitmix64(seed, n_mat) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    parts, pos = [], 0
+    for fan_out, fan_in in shapes:
+        a = np.sqrt(6.0 / (fan_in + fan_out))
+        parts.append(a * (2.0 * u[pos:pos + fan_out * fan_in] - 1.0))
+        parts.append(np.zeros(fan_out))
+        pos += fan_out * fan_in
     th = np.concatenate(parts).astype(np.float32)
     assert th.size == theta_size(kbar, d)
     return th
