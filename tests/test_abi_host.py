@@ -178,3 +178,21 @@ def test_library_xavier_matches_generator():
         import ctypes
         th = np.empty(10, dtype=np.float32)
         dg._check(dg.lib().ddmgnn_model_init_xavier(ctypes.byref(desc), 1, th.ctypes.data_as(ctypes.c_void_p), 10))
+
+
+def test_validate_rejects_oversized_and_empty():
+    """A sub-mesh above the kernels' limit (2048 nodes) and an empty problem are refused on the host."""
+    p = W.make_problem(33, 3000, 1)
+    hp = host_problem_for(p)
+    assert hp.sub_ptr[1] > 2048
+    with pytest.raises(dg.DDMGNNError, match="larger than"):
+        dg.validate(hp)
+    d = hp.desc()
+    d.n_nodes = 0
+    import ctypes
+    assert dg.lib().ddmgnn_validate_problem(ctypes.byref(d)) != 0
+
+
+def host_problem_for(p):
+    from tests._cases import host_problem
+    return host_problem(p, delta=0)
