@@ -206,6 +206,94 @@ def cpu_baseline(p, hp, theta, iterations: int, sample: int) -> dict:
                       f"times the GPU solve's {iterations} iterations; {per_solve:.1f} s per solve"}
 
 
+_ORACLE = {}
+_LIMIT = []
+
+
+def _one_thread():
+    """Pool initializer: one BLAS thread per worker process (the processes are the cores)."""
+    import threadpoolctl
+    _LIMIT.append(threadpoolctl.threadpool_limits(1))
+
+
+def _oracle_local(i):
+    """DSS forward of sub-mesh i of the problem in _ORACLE (a pool worker's task)."""
+    from oracle import dss
+    o = _ORACLE
+    sl = slice(o["sub_ptr"][i], o["sub_ptr"][i + 1])
+    ri = o["r"][o["sub_nodes"][sl]]
+    s = np.linalg.norm(ri)
+    return i, s * dss.forward(o["blocks"], o["graphs"][i], ri / s, 1e-3, 10)
+
+
+def oracle_small_cpu(theta, workers: int) -> dict:
+    """c1 and c2: the oracle's preconditioner apply timed with one thread and with one
+    process per core over the sub-meshes. Runs before the GPU is touched (the worker
+    processes are forked from this one). Returns {name: (p, hp, timings)}."""
+    import multiprocessing as mp
+
+    import threadpoolctl
+    import workload as W
+    from oracle import decomp as dc, schwarz as sw
+    out = {}
+    for name in ("c1", "c2"):
+        cfg = W.CONFIGS[name]
+        p, hp = _make((cfg["seeds"][0], cfg["target_nodes"], cfg["n_parts"], cfg["jitter"]))
+        A = p.A.to_scipy()
+        r = np.ascontiguousarray(p.b - A @ p.u0)
+        dec = dc.Decomposition(p.n, hp.sub_ptr, hp.sub_nodes, hp.weights)
+        M = sw.DDMGNN(A, p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, dec, theta)
+        with threadpoolctl.threadpool_limits(1):
+            t0 = time.perf_counter()
+            M(r)
+            one = time.perf_counter() - t0
+        _ORACLE.update(sub_ptr=hp.sub_ptr, sub_nodes=hp.sub_nodes, r=r, blocks=M.blocks, graphs=M.graphs)
+        n_proc = min(workers, hp.K)
+        with mp.get_context("fork").Pool(n_proc, initializer=_one_thread) as pool:
+            pool.map(_oracle_local, range(min(hp.K, n_proc)))  # workers up
+            t0 = time.perf_counter()
+            loc = dict(pool.map(_oracle_local, range(hp.K), chunksize=max(1, hp.K // (4 * n_proc))))
+            z = np.zeros(p.n)
+            for i in range(hp.K):
+                sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
+                z[hp.sub_nodes[sl]] += hp.weights[sl] * loc[i]
+            z += M.coarse(r)
+            z[p.mesh.dirichlet == 1] = 0.0
+            allc = time.perf_counter() - t0
+        _ORACLE.clear()
+        log(f"{name}: oracle apply {one:.2f} s (1 thread), {allc:.2f} s ({n_proc} processes)")
+        out[name] = (p, hp, {"oracle_apply_s_1thread": one, "oracle_apply_s_allcore": allc,
+                             "oracle_processes": n_proc})
+    return out
+
+
+def gpu_small(dg, ctx, model, cpu: dict) -> dict:
+    """GPU solve and apply of c1 (FP64) and c2 (FP32) beside the oracle timings of oracle_small_cpu."""
+    import torch
+    out = {}
+    for name, prec in (("c1", "fp64"), ("c2", "fp32")):
+        p, hp, t = cpu[name]
+        prob = dg.Problem(ctx, hp, model)
+        u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+        opts = dg.default_opts(precision=prec, rtol=1e-6, max_it=5000)
+        prob.solve(u, opts, check=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = prob.solve(u, opts, check=False)
+        torch.cuda.synchronize()
+        gpu_solve = time.perf_counter() - t0
+        rt = torch.from_numpy(np.ascontiguousarray(p.b - p.A.to_scipy() @ p.u0)).cuda()
+        gl, gc, gg = prob.time_apply_stages(rt, torch.empty_like(rt), opts, reps=10)
+        out[name] = {"nodes": p.n, "subdomains": hp.K, "precision": prec, "gpu_iterations": st.iterations,
+                     "gpu_solve_ms": 1e3 * gpu_solve, "gpu_apply_ms": gl + gc + gg, **t,
+                     "oracle_solve_s_1thread": t["oracle_apply_s_1thread"] * st.iterations,
+                     "oracle_solve_s_allcore": t["oracle_apply_s_allcore"] * st.iterations,
+                     "note": "oracle per-solve = its apply time x the GPU's iteration count (the oracle's own "
+                             "FCG takes the same number up to the precision gap)"}
+        log(f"{name}: GPU {1e3 * gpu_solve:.1f} ms/solve, {st.iterations} iterations")
+    return out
+
+
 def bench_batched(dg, ctx, model, items, opts, reps: int, sequential: bool) -> dict:
     """One batched solve of all items (after a warm-up), and optionally the same one after another."""
     import torch
@@ -315,7 +403,7 @@ def pmc_workload(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
@@ -328,6 +416,7 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--lu-steps", type=int, default=1, help="timed DDM-LU solves of the main problem (0: skip)")
     ap.add_argument("--variants", type=int, default=1, help="FGMRES and rtol 1e-9 legs on the main problem (0: skip)")
+    ap.add_argument("--oracle-small", type=int, default=1, help="c1/c2 GPU and oracle timings (0: skip)")
     ap.add_argument("--tune", type=int, default=1, help="autotune the main problem's schedule (0: default schedule)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: ~/.cache/ddmgnn_tune.json)")
     ap.add_argument("--pmc-workload", action="store_true")
@@ -366,6 +455,14 @@ def main():
         log(f"stream c5: {len(stream)} requests, {sum(h.n for _, h in stream)} nodes over "
             f"{specs[-1][0]:.2f}s of arrivals ({time.perf_counter() - t:.1f}s)")
 
+    small_cpu = {}
+    if args.oracle_small > 0:
+        # the oracle's c1/c2 applies, timed before the GPU is touched (worker processes)
+        log("c1 and c2: CPU oracle")
+        theta_s = W.smoother_theta(omega=0.15, out_scale=1.7) if args.theta == "smoother" else \
+            W.xavier_theta(W.THETA_SEED)
+        small_cpu = oracle_small_cpu(theta_s, args.workers)
+
     import torch
 
     import paper_2402_08296_amd as dg
@@ -396,10 +493,13 @@ def main():
         log(f"warmup {w}: iterations={st.iterations} status={st.status} true_rel={st.true_rel_residual:.2e}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = []
+    t_prev = t0
+    stats, step_s = [], []
     for k in range(args.steps):
         st = prob.solve(u, opts, check=False)
         stats.append((st.iterations, st.converged, st.true_rel_residual, st.solve_ms))
+        step_s.append(time.perf_counter() - t_prev)
+        t_prev = time.perf_counter()
         log(f"step {k}: iterations={st.iterations} converged={st.converged} true_rel={st.true_rel_residual:.2e} "
             f"solve_ms={st.solve_ms:.1f}")
     torch.cuda.synchronize()
@@ -453,6 +553,7 @@ def main():
         "converged": bool(stats[-1][1]),
         "true_rel_residual": stats[-1][2],
         "time_to_solution_ms": 1e3 * elapsed / args.steps,
+        "time_to_solution_median_ms": 1e3 * float(np.median(step_s)),
         "apply_ms": apply_ms,
         "apply_hbm_GBps": abytes / (apply_ms * 1e-3) / 1e9,
         "breakdown_ms_per_iteration": {"dss": sp.dss_ms / n_it, "coarse": sp.coarse_ms / n_it,
@@ -499,6 +600,9 @@ def main():
     if args.cpu_sample > 0:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(p, hp, theta, iters, args.cpu_sample)
+    if small_cpu:
+        log("c1 and c2 on the GPU")
+        out["oracle_c1_c2"] = gpu_small(dg, ctx, model, small_cpu)
     print(json.dumps(out), flush=True)
 
 
