@@ -294,10 +294,14 @@ def gpu_small(dg, ctx, model, cpu: dict) -> dict:
     return out
 
 
-def bench_batched(dg, ctx, model, items, opts, reps: int, sequential: bool) -> dict:
-    """One batched solve of all items (after a warm-up), and optionally the same one after another."""
+def bench_batched(dg, ctx, model, items, opts, reps: int, sequential: bool, schedule=None) -> dict:
+    """One batched solve of all items (after a warm-up), and optionally the same one after another.
+    schedule: a tuning (dict) applied to every problem."""
     import torch
     probs = [dg.Problem(ctx, hp, model) for _, hp in items]
+    for pr in probs:
+        if schedule:
+            pr.set_tuning(**schedule)
     outs = [torch.empty(pr.n, dtype=torch.float64, device="cuda") for pr in probs]
     dg.solve_batch(ctx, probs, outs, opts, check=False)
     torch.cuda.synchronize()
@@ -584,7 +588,9 @@ def main():
         torch.cuda.synchronize()
     if args.batch8 > 1:
         log(f"{args.config} x{args.batch8} in one batch")
-        out["batched_same_x8"] = bench_batched(dg, ctx, model, [(p, hp)] * args.batch8, opts, 1, False)
+        out["batched_same_x8"] = bench_batched(dg, ctx, model, [(p, hp)] * args.batch8, opts, 1, False,
+                                               tuning["tuning"] if tuning else None)
+        out["batched_same_x8"]["schedule"] = "autotuned (main problem's)" if tuning else "default"
         out["batched_same_x8"]["vs_sequential_value"] = out["batched_same_x8"]["batched_solves_per_s"] / out["value"]
     if batch_items:
         log("batch c4")
