@@ -495,3 +495,26 @@ def test_zero_rhs_and_large_subdomain(ctx):
     st = prob0.solve(u)
     assert st.converged and st.iterations == 0
     assert torch.equal(u.cpu(), torch.from_numpy(p.u0))
+
+
+def test_failure_statuses_forced_by_data(ctx, c1):
+    """E_NONFINITE and E_BREAKDOWN, forced from the inputs (every kernel runs to its end):
+    a right-hand side of 1e200 (finite, so validation accepts it) makes |r_0|^2 overflow;
+    all-zero weights without the coarse level give z = 0, so <p, A p> = 0. In both cases
+    u is the last finite iterate, u_0."""
+    print("[gpu] failure statuses", flush=True)
+    p, hp = c1
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    hb = dg.HostProblem(hp.xy, hp.tri, hp.dirichlet, hp.rowptr, hp.col, hp.val, p.b * 1e200, p.u0,
+                        hp.sub_ptr, hp.sub_nodes, hp.weights)
+    prob = dg.Problem(ctx, hb, dg.Model(ctx, SMOOTHER))
+    st = prob.solve(u, dg.default_opts(precision="fp32", max_it=50), check=False)
+    print(f"[gpu]   huge rhs: status {st.status} iterations {st.iterations}", flush=True)
+    assert st.status == -7 and not st.converged and st.iterations == 0  # DDMGNN_E_NONFINITE
+    assert torch.equal(u.cpu(), torch.from_numpy(p.u0))
+    zero = np.zeros_like(W.xavier_theta(9))
+    prob0 = dg.Problem(ctx, hp, dg.Model(ctx, zero))
+    st = prob0.solve(u, dg.default_opts(precision="fp64", coarse=0, max_it=50), check=False)
+    print(f"[gpu]   zero preconditioner: status {st.status} iterations {st.iterations}", flush=True)
+    assert st.status == -5 and st.iterations == 0  # DDMGNN_E_BREAKDOWN
+    assert torch.equal(u.cpu(), torch.from_numpy(p.u0))
