@@ -248,6 +248,33 @@ int ddmgnn_server_drain(ddmgnn_server* srv);
 /* Drains, stops the threads and frees uncollected results. */
 int ddmgnn_server_destroy(ddmgnn_server* srv);
 
+/* Host-only model of the serving loop (no device): the same admission rule as
+ * the GPU thread, driven by simulated requests. Requests (in submission order)
+ * go through `setup_threads` setup workers (0: 4) in order, taking setup_s each
+ * from max(arrival, a free worker); set-up requests are admitted as by the
+ * server (ticket order, hbm_budget, max_active, equal group keys batch, no
+ * overtaking); every chunk_s seconds each active request completes one of its
+ * `chunks` chunks and leaves after the last. out[i] gets the admission and
+ * finish times (s) and the status (OK; E_BUDGET if larger than the budget;
+ * E_INVALID if setup_ok is 0; such requests are rejected as soon as their
+ * setup ends, even behind a waiting request, and finish at that time). */
+typedef struct {
+    double arrival;
+    double setup_s;
+    int64_t bytes;
+    uint64_t group;
+    int32_t chunks;
+    int32_t setup_ok;
+} ddmgnn_sim_request;
+typedef struct {
+    double admitted;
+    double finished;
+    int32_t status;
+} ddmgnn_sim_result;
+int ddmgnn_server_simulate(const ddmgnn_sim_request* reqs, int32_t n, int64_t hbm_budget, int32_t max_active,
+                           int32_t setup_threads, double chunk_s, ddmgnn_sim_result* out);
+
+
 /* One preconditioner apply z = M(r) (Sec. III.A steps 1-3). r, z: device, N
  * doubles, must not alias. */
 int ddmgnn_precond_apply(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const ddmgnn_solve_opts* opts,

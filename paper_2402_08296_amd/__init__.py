@@ -57,6 +57,15 @@ class Tuning(ctypes.Structure):
         return {"small_lds": self.small_lds, "vec_blocks": self.vec_blocks}
 
 
+class SimRequest(ctypes.Structure):
+    _fields_ = [("arrival", _f64), ("setup_s", _f64), ("bytes", _i64), ("group", ctypes.c_uint64),
+                ("chunks", _i32), ("setup_ok", _i32)]
+
+
+class SimResult(ctypes.Structure):
+    _fields_ = [("admitted", _f64), ("finished", _f64), ("status", _i32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("converged", _i32), ("rel_residual", _f64),
                 ("true_rel_residual", _f64), ("solve_ms", _f64), ("dss_launches", _i32), ("dss_ms", _f64),
@@ -105,6 +114,8 @@ def lib():
         "ddmgnn_server_destroy": (ctypes.c_int, [_p]),
         "ddmgnn_problem_device_bytes": (ctypes.c_int, [_p, ctypes.POINTER(_i64)]),
         "ddmgnn_problem_set_tuning": (ctypes.c_int, [_p, ctypes.POINTER(Tuning)]),
+        "ddmgnn_server_simulate": (ctypes.c_int, [ctypes.POINTER(SimRequest), _i32, _i64, _i32, _i32, _f64,
+                                                  ctypes.POINTER(SimResult)]),
         "ddmgnn_time_apply_stages": (ctypes.c_int, [_p, _p, ctypes.POINTER(SolveOpts), _p, _p, _i32,
                                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                                     ctypes.POINTER(ctypes.c_double)]),
@@ -274,6 +285,19 @@ def init_xavier(seed: int, kbar: int = 30, d: int = 10, alpha: float = 1e-3) -> 
     th = np.empty(n, dtype=np.float32)
     _check(lib().ddmgnn_model_init_xavier(ctypes.byref(desc), seed, th.ctypes.data_as(_p), n))
     return th
+
+
+def simulate_server(requests, hbm_budget: int, max_active: int, setup_threads: int = 4, chunk_s: float = 0.01):
+    """Host-only model of the serving loop: requests are dicts with arrival, setup_s, bytes,
+    group, chunks and setup_ok (default 1); returns a list of (admitted, finished, status)."""
+    n = len(requests)
+    reqs = (SimRequest * max(n, 1))()
+    for i, r in enumerate(requests):
+        reqs[i] = SimRequest(r["arrival"], r["setup_s"], r["bytes"], r.get("group", 0), r["chunks"],
+                             r.get("setup_ok", 1))
+    out = (SimResult * max(n, 1))()
+    _check(lib().ddmgnn_server_simulate(reqs, n, hbm_budget, max_active, setup_threads, chunk_s, out))
+    return [(out[i].admitted, out[i].finished, out[i].status) for i in range(n)]
 
 
 def default_opts(**kw) -> SolveOpts:

@@ -8,6 +8,7 @@
 // for the next admissions. A problem's arithmetic does not depend on the
 // other members of its batch (per-problem reductions in a fixed order), so a
 // served result equals the result of solving it alone.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -61,6 +62,44 @@ uint64_t structure_key(const ddmgnn_solve_opts& o) {
     const int m = o.krylov == DDMGNN_FCG ? o.m_max : o.krylov == DDMGNN_FGMRES ? o.restart : 1;
     return ((uint64_t)o.local_solver << 32) | ((uint64_t)o.krylov << 24) | ((uint64_t)m << 16) |
            ((uint64_t)o.precision << 8) | ((uint64_t)o.prolong << 4) | (uint64_t)(o.coarse != 0);
+}
+
+// One set-up request waiting for admission.
+struct Candidate {
+    size_t bytes;
+    uint64_t key;  // structure_key of its options
+    bool ok;       // setup succeeded
+};
+enum Decision { ADMIT, REJECT, WAIT };
+
+// The admission rule of the serving loop, over the set-up requests in ticket
+// order: one whose setup failed or that is larger than the budget is rejected
+// wherever it stands (it could never run); the others are admitted while they
+// share the active group's options key (any key when nothing is active), fit
+// the budget next to the active bytes and keep at most max_active active; the
+// first that does not is WAIT, and so is every later one (no overtaking).
+std::vector<Decision> plan_admission(const std::vector<Candidate>& ready, size_t bytes_active, int n_active,
+                                     uint64_t group, size_t budget, int max_active) {
+    std::vector<Decision> out(ready.size(), WAIT);
+    size_t bytes = bytes_active;
+    uint64_t g = group;
+    bool blocked = false;
+    for (size_t i = 0; i < ready.size(); ++i) {
+        const Candidate& c = ready[i];
+        if (!c.ok || c.bytes > budget) {
+            out[i] = REJECT;
+            continue;
+        }
+        if (blocked || (n_active > 0 && c.key != g) || n_active >= max_active || bytes + c.bytes > budget) {
+            blocked = true;
+            continue;
+        }
+        g = c.key;
+        bytes += c.bytes;
+        ++n_active;
+        out[i] = ADMIT;
+    }
+    return out;
 }
 
 }  // namespace
@@ -163,24 +202,19 @@ void ddmgnn_server::gpu_loop() {
             cv.wait(lk, [&] { return !active.empty() || !ready.empty() || (stop && in_flight == 0); });
             if (active.empty() && ready.empty() && stop && in_flight == 0) return;
             // Admission in ticket order; the first request that does not fit waits (no overtaking).
-            size_t bytes = bytes_active;
-            uint64_t g = active.empty() ? 0 : group;
-            int n_active = (int)active.size();
-            for (auto it = ready.begin(); it != ready.end();) {
-                Request* r = it->second;
-                if (r->setup_rc != DDMGNN_OK || r->bytes > budget) {
-                    reject.push_back(r);
-                    it = ready.erase(it);
-                    continue;
-                }
-                const uint64_t key = structure_key(r->opts);
-                if (n_active > 0 && key != g) break;
-                if (n_active >= max_active || bytes + r->bytes > budget) break;
-                g = key;
-                bytes += r->bytes;
-                ++n_active;
-                admit.push_back(r);
-                it = ready.erase(it);
+            std::vector<Candidate> cands;
+            std::vector<uint64_t> tickets;
+            for (const auto& kv : ready) {
+                cands.push_back({kv.second->bytes, structure_key(kv.second->opts), kv.second->setup_rc == DDMGNN_OK});
+                tickets.push_back(kv.first);
+            }
+            const std::vector<Decision> plan = plan_admission(cands, bytes_active, (int)active.size(),
+                                                              active.empty() ? 0 : group, budget, max_active);
+            for (size_t i = 0; i < plan.size(); ++i) {
+                if (plan[i] == WAIT) continue;
+                auto it = ready.find(tickets[i]);
+                (plan[i] == ADMIT ? admit : reject).push_back(it->second);
+                ready.erase(it);
             }
         }
         for (Request* r : reject) {
@@ -404,3 +438,81 @@ int ddmgnn_server_destroy(ddmgnn_server* srv) {
 }
 
 }  // extern "C"
+
+int ddmgnn_server_simulate(const ddmgnn_sim_request* reqs, int32_t n, int64_t hbm_budget, int32_t max_active,
+                           int32_t setup_threads, double chunk_s, ddmgnn_sim_result* out) {
+    if ((!reqs || !out) && n > 0) return fail(DDMGNN_E_INVALID, "null argument");
+    if (n < 0 || hbm_budget <= 0 || max_active < 1 || !(chunk_s > 0.0))
+        return fail(DDMGNN_E_INVALID, "n >= 0, hbm_budget > 0, max_active >= 1 and chunk_s > 0 required");
+    const int workers = setup_threads > 0 ? setup_threads : 4;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!(reqs[i].setup_s >= 0.0) || reqs[i].chunks < 1 || reqs[i].bytes < 0)
+            return fail(DDMGNN_E_INVALID, "setup_s >= 0, chunks >= 1 and bytes >= 0 required");
+        if (i > 0 && reqs[i].arrival < reqs[i - 1].arrival)
+            return fail(DDMGNN_E_INVALID, "requests must be in submission order");
+    }
+    // setup workers take the requests in submission order
+    std::vector<double> ready_at(n), free_at(workers, 0.0);
+    for (int32_t i = 0; i < n; ++i) {
+        auto w = std::min_element(free_at.begin(), free_at.end());
+        const double start = std::max(*w, reqs[i].arrival);
+        *w = start + reqs[i].setup_s;
+        ready_at[i] = *w;
+        out[i] = {-1.0, -1.0, DDMGNN_E_PENDING};
+    }
+    std::vector<int32_t> waiting(n);  // set-up or in setup, not yet decided, in ticket order
+    for (int32_t i = 0; i < n; ++i) waiting[i] = i;
+    struct Act {
+        int32_t i;
+        int32_t left;
+    };
+    std::vector<Act> active;
+    size_t bytes_active = 0;
+    uint64_t group = 0;
+    double t = 0.0;
+    while (!waiting.empty() || !active.empty()) {
+        std::vector<Candidate> cands;
+        std::vector<int32_t> idx;
+        for (int32_t i : waiting)
+            if (ready_at[i] <= t) {
+                cands.push_back({(size_t)reqs[i].bytes, reqs[i].group, reqs[i].setup_ok != 0});
+                idx.push_back(i);
+            }
+        const std::vector<Decision> plan =
+            plan_admission(cands, bytes_active, (int)active.size(), active.empty() ? 0 : group, (size_t)hbm_budget,
+                           max_active);
+        for (size_t q = 0; q < plan.size(); ++q) {
+            const int32_t i = idx[q];
+            if (plan[q] == WAIT) continue;
+            if (plan[q] == REJECT) {
+                out[i] = {t, t, reqs[i].setup_ok ? DDMGNN_E_BUDGET : DDMGNN_E_INVALID};
+            } else {
+                if (active.empty()) group = reqs[i].group;
+                active.push_back({i, reqs[i].chunks});
+                bytes_active += (size_t)reqs[i].bytes;
+                out[i].admitted = t;
+            }
+            waiting.erase(std::find(waiting.begin(), waiting.end(), i));
+        }
+        if (active.empty()) {  // idle until the next setup ends
+            double next = 1e300;
+            for (int32_t i : waiting) next = std::min(next, ready_at[i]);
+            if (next == 1e300) break;
+            t = std::max(t, next);
+            continue;
+        }
+        t += chunk_s;  // one chunk of every active request (one batched launch sequence)
+        for (size_t a = 0; a < active.size();) {
+            if (--active[a].left == 0) {
+                const int32_t i = active[a].i;
+                out[i].finished = t;
+                out[i].status = DDMGNN_OK;
+                bytes_active -= (size_t)reqs[i].bytes;
+                active.erase(active.begin() + (long)a);
+            } else {
+                ++a;
+            }
+        }
+    }
+    return DDMGNN_OK;
+}
