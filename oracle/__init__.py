@@ -14,8 +14,10 @@ Plain, slow, obviously correct numpy code in float64, written from the paper:
   (11)-(13) and the gluing step); the DDM-LU and one-level variants (eqs. (6)-(7)).
 * ``krylov``  - PCG as Algorithm 1, flexible CG (truncated FCG(m)), restarted flexible
   GMRES, plain CG.
+* ``train``   - the training loss of DSS_theta (the residual loss of Sec. II.B summed over
+  the blocks, Sec. III.B) with its gradient by float64 autograd, and the Adam step.
 
 Parity status of each function is stated in its docstring; every function is
 pinned by tests except where a docstring says "parity unpinned".
 """
-from . import decomp, dss, schwarz, krylov  # noqa: F401
+from . import decomp, dss, schwarz, krylov, train  # noqa: F401
