@@ -128,6 +128,39 @@ def bench_lu(dg, prob, u, hp, steps: int) -> dict:
                          "avg_launch_ms": local_ms}}
 
 
+def bench_train(dg, ctx, prob, steps: int, batch: int = 100) -> dict:
+    """Training throughput of DSS_theta (kbar 30, d 10, alpha 1e-3, Xavier start): `steps`
+    Adam steps over batches of `batch` local problems of this mesh, each a forward and
+    backward over all blocks (Sec. III.B loss) then an Adam step (Sec. IV.B)."""
+    import torch
+    import workload as W
+    from paper_2402_08296_amd import train as T
+    data = T.harvest(prob, [0])
+    st = T.init_state(torch.tensor(W.xavier_theta(0, 30, 10), device="cuda"))
+    rng = np.random.default_rng(0)
+    ptr = prob.hp.sub_ptr
+    batches = []
+    for _ in range(steps + 1):
+        subs = rng.choice(prob.K, size=min(batch, prob.K), replace=False)
+        batches.append((subs, [int(ptr[i]) for i in subs]))
+    def one(subs, offs):
+        loss, gn = prob.train_grad(st.theta, subs, data.c, offs, st.grad)
+        st.step += 1
+        dg.adam_step(ctx, st.theta, st.grad, st.m, st.v, gn, st.step, lr=1e-2, clip=1e-2)
+        return loss
+    one(*batches[0])  # warm-up: builds the local matrices and edge transposes
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = [one(*b) for b in batches[1:]]
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    nodes = float(np.mean([sum(int(ptr[i + 1] - ptr[i]) for i in b[0]) for b in batches[1:]]))
+    return {"kbar": 30, "d": 10, "batch": batch, "steps": steps, "ms_per_step": 1e3 * el,
+            "samples_per_s": batch / el, "nodes_per_batch": nodes, "loss_first": losses[0], "loss_last": losses[-1],
+            "data": "local right-hand sides of the initial residual (iterate 0) of this mesh",
+            "timing": "host clock around train_grad + adam_step, both synchronous"}
+
+
 def bench_variant(dg, prob, u, opts, popts) -> dict:
     """One warm-up solve (graph capture), one timed solve, one profiled solve of the main problem."""
     import torch
@@ -419,6 +452,7 @@ def main():
     ap.add_argument("--serve-slow-rate", type=float, default=6.0, help="arrival rate of the sustained replay (1/s)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--lu-steps", type=int, default=1, help="timed DDM-LU solves of the main problem (0: skip)")
+    ap.add_argument("--train-steps", type=int, default=5, help="timed training steps of DSS_theta (0: skip)")
     ap.add_argument("--variants", type=int, default=1, help="FGMRES and rtol 1e-9 legs on the main problem (0: skip)")
     ap.add_argument("--oracle-small", type=int, default=1, help="c1/c2 GPU and oracle timings (0: skip)")
     ap.add_argument("--tune", type=int, default=1, help="autotune the main problem's schedule (0: default schedule)")
@@ -580,6 +614,9 @@ def main():
         out["fgmres30_c3"] = bench_variant(dg, prob, u, *mk(krylov=dg.FGMRES, restart=30, rtol=1e-6))
         out["fcg_rtol1e-9_c3"] = bench_variant(dg, prob, u, *mk(rtol=1e-9))
         out["fgmres30_rtol1e-9_c3"] = bench_variant(dg, prob, u, *mk(krylov=dg.FGMRES, restart=30, rtol=1e-9))
+    if args.train_steps > 0:
+        log("training steps of DSS_theta on the same mesh")
+        out["train"] = bench_train(dg, ctx, prob, args.train_steps)
     if args.lu_steps > 0:
         log("DDM-LU on the same problem")
         out["ddm_lu"] = bench_lu(dg, prob, u, hp, args.lu_steps)

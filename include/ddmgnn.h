@@ -302,13 +302,46 @@ int ddmgnn_apply_intermediates(ddmgnn_ctx* ctx, ddmgnn_problem* prob, double* s,
 /* DSS_theta forward pass (Sec. III.B) on every sub-mesh of the problem. c and
  * out: device, sub_ptr[K] doubles in sub_nodes order; c holds each sub-mesh's
  * input c_i, out receives r~_i = D^kbar(H^kbar). */
+int ddmgnn_dss_forward(ddmgnn_ctx* ctx, ddmgnn_problem* prob, int32_t precision, const double* c,
+                       double* out);
 /* The same forward pass on sub-mesh `sub` alone: c and out are device arrays of
  * k_sub = sub_ptr[sub+1] - sub_ptr[sub] doubles (the sub-mesh's nodes in
  * sub_nodes order). Gives the bits of the matching slice of ddmgnn_dss_forward. */
 int ddmgnn_dss_forward_sub(ddmgnn_ctx* ctx, ddmgnn_problem* prob, int32_t precision, int32_t sub,
                            const double* c, double* out);
-int ddmgnn_dss_forward(ddmgnn_ctx* ctx, ddmgnn_problem* prob, int32_t precision, const double* c,
-                       double* out);
+
+/* ---- training of DSS_theta (Sec. III.B loss, Sec. IV.B set-up) ----
+ * A sample is a local problem of the two-level preconditioner: sub-mesh i of
+ * the problem, its local matrix A_i = R_i A R_i^T and a right-hand side c
+ * (Sec. IV.A: local problems met during the iterations of a PCG solve).
+ *
+ * ddmgnn_train_rhs: the right-hand sides of every sub-mesh at the iterate u:
+ * r = b - A u, c_i = R_i r / |R_i r| (0 where R_i r = 0). u: device, N
+ * doubles; c_out: device, sub_ptr[K] floats in sub_nodes order. */
+int ddmgnn_train_rhs(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const double* u, float* c_out);
+/* Loss and gradient over n samples, in FP32 on the device:
+ *   loss = scale * sum_s sum_{k=1..kbar} sum_j ((A_i D^k(H^k))_j - c_j)^2,
+ * the residual loss of Sec. II.B of every block's decoded state (Sec. III.B),
+ * summed; scale = 1 / (total nodes) gives the mean over the batch as one graph.
+ * model: kbar (1..64), d (10 only), alpha. theta: device, kbar(11d^2+15d+1)
+ * floats in the layout of ddmgnn_model_create. subs, c_off: host, n entries:
+ * sample s is sub-mesh subs[s] with right-hand side c + c_off[s] (device, k_i
+ * floats). grad: device, same size as theta, receives d loss / d theta. The
+ * gradient is deterministic (fixed-order sums; no atomics). *loss_out and
+ * *gnorm_out (host, may be NULL) receive the loss (FP64 sum of the FP32
+ * residuals) and |grad|_2. The first call builds the local matrices and edge
+ * transposes on the device; scratch grows to about 4 (kbar + 33) d k_i bytes per
+ * sample. E_NONFINITE when the loss or the gradient overflows. */
+int ddmgnn_train_grad(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const ddmgnn_model_desc* model, const float* theta,
+                      const int32_t* subs, int32_t n, const float* c, const int64_t* c_off, double scale,
+                      float* grad, double* loss_out, double* gnorm_out);
+/* One Adam step (Sec. IV.B's optimiser, with bias correction) on device FP32
+ * arrays of n entries: the gradient is first scaled to L2 norm `clip` when
+ * gnorm (its norm, as returned by ddmgnn_train_grad) exceeds it (clip <= 0: no
+ * clipping); then m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2 and
+ * theta -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps). t >= 1 is the step. */
+int ddmgnn_adam_step(ddmgnn_ctx* ctx, float* theta, const float* grad, float* m, float* v, int64_t n, double gnorm,
+                     int32_t t, double lr, double beta1, double beta2, double eps, double clip);
 
 /* y = A x with the problem's matrix (the q = A p step of Algorithm 1). x, y:
  * device, N doubles. */

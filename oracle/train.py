@@ -34,6 +34,14 @@ def local_matrix(A: sp.csr_matrix, nodes: np.ndarray) -> sp.csr_matrix:
     return sp.csr_matrix(A[nodes][:, nodes])
 
 
+def local_rhs(A: sp.csr_matrix, b: np.ndarray, u: np.ndarray, nodes: np.ndarray) -> np.ndarray:
+    """Right-hand side of a local problem at the iterate u: c_i = R_i r / |R_i r| with
+    r = b - A u (the normalised restriction of Sec. III.A); zero when R_i r = 0."""
+    r = (b - A @ u)[nodes]
+    s = float(np.sqrt(r @ r))
+    return r / s if s > 0 else np.zeros_like(r)
+
+
 def _mlp(x, W1, b1, W2, b2):
     return torch.relu(x @ W1.T + b1) @ W2.T + b2
 

@@ -138,6 +138,11 @@ def lib():
         "ddmgnn_setup_coarse": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), _p, _p]),
         "ddmgnn_setup_local_inverse": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), _i32, _p]),
         "ddmgnn_dss_forward_sub": (ctypes.c_int, [_p, _p, _i32, _i32, _p, _p]),
+        "ddmgnn_train_rhs": (ctypes.c_int, [_p, _p, _p, _p]),
+        "ddmgnn_train_grad": (ctypes.c_int, [_p, _p, ctypes.POINTER(ModelDesc), _p, ctypes.POINTER(_i32), _i32, _p,
+                                             ctypes.POINTER(_i64), _f64, _p, ctypes.POINTER(_f64),
+                                             ctypes.POINTER(_f64)]),
+        "ddmgnn_adam_step": (ctypes.c_int, [_p, _p, _p, _p, _p, _i64, _f64, _i32, _f64, _f64, _f64, _f64, _f64]),
         "ddmgnn_model_init_xavier": (ctypes.c_int, [ctypes.POINTER(ModelDesc), ctypes.c_uint64, _p, _i64]),
     }
     for name, (res, args) in sig.items():
@@ -455,6 +460,38 @@ class Problem:
 
     def spmv(self, x, y):
         _check(lib().ddmgnn_spmv(self.ctx.h, self.h, _dev(x), _dev(y)))
+
+    # ---- training of DSS_theta
+    def train_rhs(self, u, c_out):
+        """c_out (device float32, sum_k values) = R_i r / |R_i r| per sub-mesh, r = b - A u."""
+        _check(lib().ddmgnn_train_rhs(self.ctx.h, self.h, _dev(u), _dev(c_out, "float32")))
+
+    def train_grad(self, theta, subs, c, c_off, grad, kbar: int = 30, d: int = 10, alpha: float = 1e-3,
+                   scale: float | None = None):
+        """Loss and gradient of the training objective over samples (subs[s], c[c_off[s]:]).
+        scale defaults to 1 / (total nodes). Returns (loss, |grad|)."""
+        subs = np.ascontiguousarray(subs, np.int32)
+        offs = np.ascontiguousarray(c_off, np.int64)
+        if subs.shape != offs.shape:
+            raise ValueError("subs and c_off differ in length")
+        if scale is None:  # out-of-range indices are left to the library to reject
+            ptr = self.hp.sub_ptr
+            nodes = sum(int(ptr[i + 1] - ptr[i]) for i in subs if 0 <= i < self.K)
+            scale = 1.0 / nodes if nodes else 1.0
+        desc = ModelDesc(kbar, d, alpha)
+        loss, gn = _f64(), _f64()
+        _check(lib().ddmgnn_train_grad(self.ctx.h, self.h, ctypes.byref(desc), _dev(theta, "float32"),
+                                       subs.ctypes.data_as(ctypes.POINTER(_i32)), subs.size, _dev(c, "float32"),
+                                       offs.ctypes.data_as(ctypes.POINTER(_i64)), scale, _dev(grad, "float32"),
+                                       ctypes.byref(loss), ctypes.byref(gn)))
+        return loss.value, gn.value
+
+
+def adam_step(ctx: Context, theta, grad, m, v, gnorm: float, t: int, lr: float = 1e-2, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8, clip: float = 1e-2):
+    """One Adam step on device float32 tensors (gradient clipped to norm `clip`)."""
+    _check(lib().ddmgnn_adam_step(ctx.h, _dev(theta, "float32"), _dev(grad, "float32"), _dev(m, "float32"),
+                                  _dev(v, "float32"), theta.numel(), gnorm, t, lr, beta1, beta2, eps, clip))
 
 
 def solve_batch(ctx: Context, problems, u_outs, opts: SolveOpts | None = None, check=True):

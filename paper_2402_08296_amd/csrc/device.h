@@ -164,6 +164,45 @@ hipError_t launch_spmv(const int32_t* rowptr, const int32_t* col, const double* 
 hipError_t launch_dot(const double* x, const double* y, int64_t n, double* partials, unsigned* counter, double* out,
                       hipStream_t s);
 
+// Training of DSS_theta (train.hip): one TRAIN_BLOCK-thread workgroup per local
+// problem; TRAIN_NWB weights per block (d = D).
+constexpr int TRAIN_BLOCK = 512;
+constexpr int TRAIN_NWB = 11 * D * D + 15 * D + 1;
+struct TrainArgs {
+    const int32_t* sub_ptr;
+    const int32_t* edge_ptr;   // per slot, in-edge range
+    const uint16_t* edge_src;  // per in-edge, sender local id
+    const float* edge_nd;      // per in-edge, |d|
+    const double* xy64;        // per slot, coordinates
+    const int32_t* lm_ptr;     // per slot, range of its row of A_i = R_i A R_i^T
+    const uint16_t* lm_col;    // local column
+    const float* lm_val;
+    const int32_t* oe_ptr;     // per slot, range of its out-edges
+    const int32_t* oe_edge;    // the in-edge index of each out-edge
+    const uint16_t* oe_recv;   // its receiver's local id
+    const int32_t* subs;       // per sample: sub-mesh,
+    const int64_t* c_off;      // offset of its right-hand side in c,
+    const int64_t* s_off;      // offset of its scratch
+    const float* c;
+    const float* theta;        // kbar blocks of TRAIN_NWB weights
+    float* scratch;
+    float* gpart;              // per sample, kbar * TRAIN_NWB weight gradients
+    double* sse;               // per sample, sum of squared residuals over the blocks
+    int kbar;
+    float alpha;
+};
+int64_t train_scratch_floats(int kbar, int64_t k);
+hipError_t launch_train_grad(const TrainArgs& a, int n, hipStream_t s);
+// grad = scale * sum over samples of gpart; out2[0] = |grad|^2, out2[1] = sum of sse.
+hipError_t launch_train_reduce(const float* gpart, int n, int64_t nth, double scale, float* grad, double* out2,
+                               const double* sse, hipStream_t s);
+hipError_t launch_adam(float* theta, const float* grad, float* m, float* v, int64_t n, float gscale, float lr,
+                       float b1, float b2, float bc1, float bc2, float eps, hipStream_t s);
+// r = b - A u, then c = R_i r / |R_i r| per sub-mesh (slot order).
+hipError_t launch_train_rhs(const int32_t* rowptr, const int32_t* col, const double* val, const double* bb,
+                            const double* u, double* r, int n, const int32_t* sub_ptr, const int32_t* sub_nodes,
+                            int K, float* c, hipStream_t s);
+
 // Workgroups a problem of n rows takes in the vector kernels.
 // Workgroups of a problem in the vector kernels: one per VEC_BLOCK rows up to
 // VEC_GRID, rounded up to a multiple of N_XCD (so that a problem's workgroups

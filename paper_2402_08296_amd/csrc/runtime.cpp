@@ -146,6 +146,64 @@ int prepare_lu(ddmgnn_problem* P) {
     return DDMGNN_OK;
 }
 
+// Training structures of a problem: per slot, its row of A_i = R_i A R_i^T
+// (local columns, ascending) and the in-edges it sends (ordered by edge index).
+int prepare_train(ddmgnn_problem* P) {
+    if (P->lm_ptr.p) return DDMGNN_OK;
+    hipStream_t s = P->ctx->stream;
+    const auto& hs = P->hs;
+    std::vector<int32_t> rowptr(hs.n + 1), col(hs.nnz), sub_nodes(hs.sk);
+    std::vector<double> val(hs.nnz);
+    HIP_TRY(hipMemcpyAsync(rowptr.data(), P->rowptr.p, rowptr.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(col.data(), P->col.p, col.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(val.data(), P->val.p, val.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(sub_nodes.data(), P->sub_nodes.p, sub_nodes.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int32_t> lm_ptr(hs.sk + 1, 0), oe_ptr(hs.sk + 1, 0), oe_edge(std::max<int64_t>(hs.n_edges, 1));
+    std::vector<uint16_t> lm_col, oe_recv(std::max<int64_t>(hs.n_edges, 1));
+    std::vector<float> lm_val;
+    lm_col.reserve((size_t)hs.sk * 7);
+    lm_val.reserve((size_t)hs.sk * 7);
+    for (int32_t i = 0; i < hs.K; ++i) {
+        const int64_t b = hs.sub_ptr[i], e = hs.sub_ptr[i + 1];
+        const int32_t* first = sub_nodes.data() + b;
+        const int32_t* last = sub_nodes.data() + e;
+        for (int64_t q = b; q < e; ++q) {
+            const int32_t j = sub_nodes[q];
+            for (int32_t a = rowptr[j]; a < rowptr[j + 1]; ++a) {
+                const int32_t* f = std::lower_bound(first, last, col[a]);
+                if (f == last || *f != col[a]) continue;
+                lm_col.push_back((uint16_t)(f - first));
+                lm_val.push_back((float)val[a]);
+            }
+            lm_ptr[q + 1] = (int32_t)lm_col.size();
+        }
+        for (int64_t q = b; q < e; ++q)
+            for (int64_t t = hs.edge_ptr[q]; t < hs.edge_ptr[q + 1]; ++t) oe_ptr[b + hs.edge_src[t] + 1]++;
+    }
+    if (lm_col.size() >= (size_t)INT32_MAX) return fail(DDMGNN_E_INVALID, "local matrices too large");
+    for (int64_t q = 0; q < hs.sk; ++q) oe_ptr[q + 1] += oe_ptr[q];
+    std::vector<int32_t> fill(oe_ptr.begin(), oe_ptr.end() - 1);
+    for (int32_t i = 0; i < hs.K; ++i) {
+        const int64_t b = hs.sub_ptr[i], e = hs.sub_ptr[i + 1];
+        for (int64_t q = b; q < e; ++q)
+            for (int64_t t = hs.edge_ptr[q]; t < hs.edge_ptr[q + 1]; ++t) {
+                const int32_t at = fill[b + hs.edge_src[t]]++;
+                oe_edge[at] = (int32_t)t;
+                oe_recv[at] = (uint16_t)(q - b);
+            }
+    }
+    HIP_TRY(P->lm_ptr.upload(lm_ptr.data(), lm_ptr.size(), s));
+    HIP_TRY(P->lm_col.upload(lm_col.data(), std::max<size_t>(lm_col.size(), 1), s));
+    HIP_TRY(P->lm_val.upload(lm_val.data(), std::max<size_t>(lm_val.size(), 1), s));
+    HIP_TRY(P->oe_ptr.upload(oe_ptr.data(), oe_ptr.size(), s));
+    HIP_TRY(P->oe_edge.upload(oe_edge.data(), oe_edge.size(), s));
+    HIP_TRY(P->oe_recv.upload(oe_recv.data(), oe_recv.size(), s));
+    P->device_bytes += lm_ptr.size() * 4 + lm_col.size() * 2 + lm_val.size() * 4 + oe_ptr.size() * 4 +
+                       oe_edge.size() * 6;
+    return DDMGNN_OK;
+}
+
 // Whether the BF16 MFMA kernel runs problem P (its largest sub-mesh fits the
 // kernel's LDS budget and the model has the paper's latent width).
 bool runs_mfma(const Batch& B, const ddmgnn_problem* P) { return P->mfma_fits && B.model->d == D; }
@@ -1429,3 +1487,74 @@ int ddmgnn_pou_weights(int64_t n_nodes, const uint8_t* dirichlet, int32_t n_sub,
 void ddmgnn_free(void* p) { std::free(p); }
 
 }  // extern "C"
+
+int ddmgnn_train_rhs(ddmgnn_ctx* ctx, ddmgnn_problem* P, const double* u, float* c_out) {
+    if (!ctx || !P || !u || !c_out) return fail(DDMGNN_E_INVALID, "null argument");
+    hipStream_t s = ctx->stream;
+    if (P->tr_r.n < (size_t)P->hs.n) HIP_TRY(P->tr_r.alloc((size_t)P->hs.n));
+    HIP_TRY(launch_train_rhs(P->rowptr.p, P->col.p, P->val.p, P->b.p, u, P->tr_r.p, (int)P->hs.n, P->sub_ptr.p,
+                             P->sub_nodes.p, P->hs.K, c_out, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return DDMGNN_OK;
+}
+
+int ddmgnn_train_grad(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_model_desc* md, const float* theta,
+                      const int32_t* subs, int32_t n, const float* c, const int64_t* c_off, double scale,
+                      float* grad, double* loss_out, double* gnorm_out) {
+    if (!ctx || !P || !md || !theta || !subs || !c || !c_off || !grad) return fail(DDMGNN_E_INVALID, "null argument");
+    if (md->d != D) return fail(DDMGNN_E_INVALID, "training supports the latent width d = 10 only");
+    if (md->kbar < 1 || md->kbar > 64) return fail(DDMGNN_E_INVALID, "kbar must be in 1..64");
+    if (n < 1) return fail(DDMGNN_E_INVALID, "at least one sample required");
+    if (!(scale >= 0.0) || !std::isfinite(scale)) return fail(DDMGNN_E_INVALID, "scale must be finite and >= 0");
+    std::vector<int64_t> soff((size_t)n);
+    int64_t total = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (subs[i] < 0 || subs[i] >= P->hs.K) return fail(DDMGNN_E_INVALID, "sub-mesh index out of range");
+        if (c_off[i] < 0) return fail(DDMGNN_E_INVALID, "negative right-hand side offset");
+        soff[(size_t)i] = total;
+        total += train_scratch_floats(md->kbar, P->hs.sub_ptr[subs[i] + 1] - P->hs.sub_ptr[subs[i]]);
+    }
+    if (int rc = prepare_train(P)) return rc;
+    hipStream_t s = ctx->stream;
+    const int64_t nth = (int64_t)md->kbar * TRAIN_NWB;
+    if (P->tr_scratch.n < (size_t)total) HIP_TRY(P->tr_scratch.alloc((size_t)total));
+    if (P->tr_gpart.n < (size_t)(n * nth)) HIP_TRY(P->tr_gpart.alloc((size_t)(n * nth)));
+    if (P->tr_subs.n < (size_t)n) {
+        HIP_TRY(P->tr_subs.alloc((size_t)n));
+        HIP_TRY(P->tr_coff.alloc((size_t)n));
+        HIP_TRY(P->tr_soff.alloc((size_t)n));
+        HIP_TRY(P->tr_sse.alloc((size_t)n));
+    }
+    if (!P->tr_out.p) HIP_TRY(P->tr_out.alloc(2));
+    HIP_TRY(upload_async(P->tr_subs.p, subs, (size_t)n * 4, s));
+    HIP_TRY(upload_async(P->tr_coff.p, c_off, (size_t)n * 8, s));
+    HIP_TRY(upload_async(P->tr_soff.p, soff.data(), (size_t)n * 8, s));
+    TrainArgs a{P->sub_ptr.p, P->edge_ptr.p, P->edge_src.p, P->edge_nd.p, P->xy64.p, P->lm_ptr.p, P->lm_col.p,
+                P->lm_val.p, P->oe_ptr.p, P->oe_edge.p, P->oe_recv.p, P->tr_subs.p, P->tr_coff.p, P->tr_soff.p,
+                c, theta, P->tr_scratch.p, P->tr_gpart.p, P->tr_sse.p, md->kbar, (float)md->alpha};
+    HIP_TRY(launch_train_grad(a, n, s));
+    HIP_TRY(launch_train_reduce(P->tr_gpart.p, n, nth, scale, grad, P->tr_out.p, P->tr_sse.p, s));
+    double out2[2];
+    HIP_TRY(hipMemcpyAsync(out2, P->tr_out.p, sizeof(out2), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (loss_out) *loss_out = scale * out2[1];
+    if (gnorm_out) *gnorm_out = std::sqrt(out2[0]);
+    if (!std::isfinite(out2[0]) || !std::isfinite(out2[1]))
+        return fail(DDMGNN_E_NONFINITE, "training loss or gradient is not finite");
+    return DDMGNN_OK;
+}
+
+int ddmgnn_adam_step(ddmgnn_ctx* ctx, float* theta, const float* grad, float* m, float* v, int64_t n, double gnorm,
+                     int32_t t, double lr, double beta1, double beta2, double eps, double clip) {
+    if (!ctx || !theta || !grad || !m || !v) return fail(DDMGNN_E_INVALID, "null argument");
+    if (n < 1 || t < 1) return fail(DDMGNN_E_INVALID, "n >= 1 and step t >= 1 required");
+    if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0 && eps > 0.0 && lr >= 0.0))
+        return fail(DDMGNN_E_INVALID, "0 <= beta < 1, eps > 0 and lr >= 0 required");
+    if (!std::isfinite(gnorm) || gnorm < 0.0) return fail(DDMGNN_E_NONFINITE, "gradient norm is not finite");
+    const double gs = clip > 0.0 && gnorm > clip ? clip / gnorm : 1.0;
+    const double bc1 = 1.0 - std::pow(beta1, t), bc2 = 1.0 - std::pow(beta2, t);
+    HIP_TRY(launch_adam(theta, grad, m, v, n, (float)gs, (float)lr, (float)beta1, (float)beta2, (float)bc1,
+                        (float)bc2, (float)eps, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return DDMGNN_OK;
+}

@@ -180,6 +180,13 @@ struct ddmgnn_problem {
     ddmgnn::DevBuf<double> gm_v, gm_z, gm_part, gm_small;
     int gm_R = 0;
     ddmgnn::DevBuf<float> qglobal32;
+    // training: local matrices A_i and out-edge lists (built on the first training
+    // call), per-call scratch, per-sample arrays and the residual of ddmgnn_train_rhs
+    ddmgnn::DevBuf<int32_t> lm_ptr, oe_ptr, oe_edge, tr_subs;
+    ddmgnn::DevBuf<uint16_t> lm_col, oe_recv;
+    ddmgnn::DevBuf<float> lm_val, tr_scratch, tr_gpart;
+    ddmgnn::DevBuf<int64_t> tr_coff, tr_soff;
+    ddmgnn::DevBuf<double> tr_sse, tr_out, tr_r;
     // Krylov vectors
     ddmgnn::DevBuf<double> u, r, z;
     ddmgnn::DevBuf<double> ring;     // (MAX_M + 1) p vectors then (MAX_M + 1) q vectors

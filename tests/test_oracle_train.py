@@ -123,3 +123,22 @@ def test_adam_first_step_closed_form():
     new_c, m_c, _ = tr.adam_step(th, g, np.zeros(50), np.zeros(50), 1, 1e-2, clip=1e-2)
     assert np.linalg.norm(m_c / 0.1) == pytest.approx(1e-2, rel=1e-12)
     assert np.allclose(new_c, th - 1e-2 * (g * 1e-2 / np.linalg.norm(g)) / (np.abs(g) * 1e-2 / np.linalg.norm(g) + 1e-8))
+
+
+def test_local_rhs_definition(tiny):
+    """c_i is the unit vector along R_i (b - A u), by an explicit row loop; the exact
+    solution gives zero right-hand sides."""
+    p, _ = tiny
+    A = p.A.to_scipy()
+    rng = np.random.default_rng(2)
+    u = p.u0 + rng.standard_normal(p.n) * (p.mesh.dirichlet == 0)
+    nodes = np.arange(10, 90)
+    r = np.array([p.b[j] - sum(p.A.val[q] * u[p.A.col[q]] for q in range(p.A.rowptr[j], p.A.rowptr[j + 1]))
+                  for j in nodes])
+    c = tr.local_rhs(A, p.b, u, nodes)
+    assert np.linalg.norm(c) == pytest.approx(1.0, rel=1e-14)
+    assert np.allclose(c * np.linalg.norm(r), r, rtol=1e-12, atol=1e-12 * np.abs(r).max())
+    import scipy.sparse.linalg as spl
+    ex = spl.spsolve(A.tocsc(), p.b)
+    assert np.abs(tr.local_rhs(A, p.b, ex, nodes)).max() <= 1.0  # defined (unit or zero)
+    assert np.all(tr.local_rhs(A, A @ ex, ex, nodes) == 0.0)
