@@ -122,7 +122,7 @@ __device__ inline double block_sum_d(double v, double* sh) {
 
 // One block's forward for node j from H = H^{k-1}: messages, Psi, new state.
 // With keep, the intermediates are stored for the backward pass.
-__device__ inline void block_node(const TrainArgs& a, const Sample& S, const float* w, const float* H, float* Hn,
+__device__ __noinline__ void block_node(const TrainArgs& a, const Sample& S, const float* w, const float* H, float* Hn,
                                   const float* cs, int64_t b, int j, bool keep) {
     const int kb = a.kbar;
     float po[D], pi[D], mo[D], mi[D];
@@ -190,9 +190,27 @@ __device__ inline void block_node(const TrainArgs& a, const Sample& S, const flo
     }
 }
 
+// sum_{j<k} f(j) as four interleaved partial sums (j mod 4), combined in a fixed
+// order: several loads stay in flight.
+template <typename F>
+__device__ inline float sum4(int k, F f) {
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+    int j = 0;
+    for (; j + 4 <= k; j += 4) {
+        a0 += f(j);
+        a1 += f(j + 1);
+        a2 += f(j + 2);
+        a3 += f(j + 3);
+    }
+    if (j < k) a0 += f(j);
+    if (j + 1 < k) a1 += f(j + 1);
+    if (j + 2 < k) a2 += f(j + 2);
+    return (a0 + a1) + (a2 + a3);
+}
+
 // Gradient of block `blk`'s weight e: a sum over the nodes of a product of
 // two per-node quantities (fixed order).
-__device__ float grad_entry(const TrainArgs& a, const Sample& S, const float* cs, int64_t b, int blk, int e) {
+__device__ __noinline__ float grad_entry(const TrainArgs& a, const Sample& S, const float* cs, int64_t b, int blk, int e) {
     const int kb = a.kbar;
     const int k = (int)S.k;
     const float* Hp = S.hist(blk);      // H^{k-1}
@@ -253,20 +271,145 @@ __device__ float grad_entry(const TrainArgs& a, const Sample& S, const float* cs
             const float* G = S.sca(kb, SGR);
             const float* U = r < D * D + 2 * D ? S.arr(kb, UD) : nullptr;
             const int cu = r - D * D - D;
-            float acc = 0.0f;
-            for (int j = 0; j < k; ++j) acc = U ? fmaf(G[j], U[j * D + cu], acc) : acc + G[j];
-            return acc;
+            return U ? sum4(k, [&](int j) { return G[j] * U[j * D + cu]; }) : sum4(k, [&](int j) { return G[j]; });
         }
     }
-    float acc = 0.0f;
-    if (deg) {
-        for (int j = 0; j < k; ++j) acc = fmaf(A[j * D + ca], (float)(a.edge_ptr[b + j + 1] - a.edge_ptr[b + j]), acc);
-    } else if (B) {
-        for (int j = 0; j < k; ++j) acc = fmaf(A[j * D + ca], B[j * sb + cb], acc);
-    } else {
-        for (int j = 0; j < k; ++j) acc += A[j * D + ca];
-    }
+    float acc;
+    if (deg)
+        acc = sum4(k, [&](int j) { return A[j * D + ca] * (float)(a.edge_ptr[b + j + 1] - a.edge_ptr[b + j]); });
+    else if (B)
+        acc = sum4(k, [&](int j) { return A[j * D + ca] * B[j * sb + cb]; });
+    else
+        acc = sum4(k, [&](int j) { return A[j * D + ca]; });
     return sign * acc;
+}
+
+// Back through the decoder of H^k, Psi and the second message layers for node j.
+__device__ __noinline__ void psi_back_node(const TrainArgs& a, const Sample& S, const float* w, const float* cs,
+                                           int64_t b, int j) {
+    const int kb = a.kbar;
+    float acc = 0.0f;  // (A_i^T rho)_j = (A_i rho)_j: A_i is symmetric
+    for (int q = a.lm_ptr[b + j]; q < a.lm_ptr[b + j + 1]; ++q)
+        acc = fmaf(a.lm_val[q], S.sca(kb, SRHO)[a.lm_col[q]], acc);
+    const float gr = 2.0f * acc;
+    S.sca(kb, SGR)[j] = gr;
+    float zd[D], gzd[D], gh[D];
+    ld(S.arr(kb, ZD) + j * D, zd);
+#pragma unroll
+    for (int u = 0; u < D; ++u) gzd[u] = zd[u] > 0.0f ? w[O_DE + D * D + D + u] * gr : 0.0f;
+    st(S.arr(kb, GZD) + j * D, gzd);
+    ld(S.arr(kb, GH) + j * D, gh);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        float acc2 = gh[i];
+#pragma unroll
+        for (int u = 0; u < D; ++u) acc2 = fmaf(w[O_DE + u * D + i], gzd[u], acc2);
+        gh[i] = acc2;
+    }
+    float gps[D], zp[D], gz[D];
+#pragma unroll
+    for (int o = 0; o < D; ++o) gps[o] = a.alpha * gh[o];
+    st(S.arr(kb, GPS) + j * D, gps);
+    ld(S.arr(kb, ZP) + j * D, zp);
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+        float acc2 = 0.0f;
+#pragma unroll
+        for (int o = 0; o < D; ++o) acc2 = fmaf(w[O_PS + D * F_PSI + D + o * D + u], gps[o], acc2);
+        gz[u] = zp[u] > 0.0f ? acc2 : 0.0f;
+    }
+    st(S.arr(kb, GZ) + j * D, gz);
+    float gx[F_PSI];
+#pragma unroll
+    for (int i = 0; i < F_PSI; ++i) {
+        float acc2 = 0.0f;
+#pragma unroll
+        for (int u = 0; u < D; ++u) acc2 = fmaf(w[O_PS + u * F_PSI + i], gz[u], acc2);
+        gx[i] = acc2;
+    }
+    st(S.arr(kb, GFO) + j * D, gx + D + 1);
+    st(S.arr(kb, GFI) + j * D, gx + 2 * D + 1);
+    float gmo[D], gmi[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+        float ao = 0.0f, ai = 0.0f;
+#pragma unroll
+        for (int v = 0; v < D; ++v) {
+            ao = fmaf(w[O_PO + D * F_PHI + D + v * D + u], gx[D + 1 + v], ao);
+            ai = fmaf(w[O_PI + D * F_PHI + D + v * D + u], gx[2 * D + 1 + v], ai);
+        }
+        gmo[u] = ao;
+        gmi[u] = ai;
+    }
+    st(S.arr(kb, GMO) + j * D, gmo);
+    st(S.arr(kb, GMI) + j * D, gmi);
+#pragma unroll
+    for (int i = 0; i < D; ++i) gh[i] += gx[i];
+    st(S.arr(kb, GHN) + j * D, gh);
+}
+
+// Back through the first message layers for node j: per receiver and per sender
+// edge sums, one message direction at a time.
+__device__ __noinline__ void edge_back_node(const TrainArgs& a, const Sample& S, const float* w, int64_t b, int j) {
+    const int kb = a.kbar;
+    float gh[D];
+    ld(S.arr(kb, GHN) + j * D, gh);
+#pragma unroll 1
+    for (int dir = 0; dir < 2; ++dir) {
+        const float* wd = w + (dir ? O_PI : O_PO);
+        const float sx = dir ? -1.0f : 1.0f;
+        const float* P = S.arr(kb, dir ? PI : PO);
+        const float* Q = S.arr(kb, dir ? QI : QO);
+        const float* GM = S.arr(kb, dir ? GMI : GMO);
+        float p[D], gm[D], gr[D], nn[D], gx[D], gy[D];
+        ld(P + j * D, p);
+        ld(GM + j * D, gm);
+#pragma unroll
+        for (int u = 0; u < D; ++u) gr[u] = nn[u] = gx[u] = gy[u] = 0.0f;
+        for (int t = a.edge_ptr[b + j]; t < a.edge_ptr[b + j + 1]; ++t) {
+            const int l = a.edge_src[t];
+            const Edge e = edge(a, b, j, l, t);
+            const float* q = Q + l * D;
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                const float g = pre(p[u], q[u], wd + u * F_PHI, sx, e.dx, e.dy, e.nd) > 0.0f ? gm[u] : 0.0f;
+                gr[u] += g;
+                nn[u] = fmaf(g, e.nd, nn[u]);
+                gx[u] = fmaf(g, e.dx, gx[u]);
+                gy[u] = fmaf(g, e.dy, gy[u]);
+            }
+        }
+        st(S.arr(kb, dir ? GRI : GRO) + j * D, gr);
+        st(S.arr(kb, dir ? NI : NO) + j * D, nn);
+        st(S.arr(kb, dir ? DXI : DXO) + j * D, gx);
+        st(S.arr(kb, dir ? DYI : DYO) + j * D, gy);
+        // edges leaving j: j is the sender, r the receiver
+        float q[D], gs[D];
+        ld(Q + j * D, q);
+#pragma unroll
+        for (int u = 0; u < D; ++u) gs[u] = 0.0f;
+        for (int o = a.oe_ptr[b + j]; o < a.oe_ptr[b + j + 1]; ++o) {
+            const int r = a.oe_recv[o];
+            const Edge e = edge(a, b, r, j, a.oe_edge[o]);
+            const float* pr = P + r * D;
+            const float* gmr = GM + r * D;
+#pragma unroll
+            for (int u = 0; u < D; ++u)
+                gs[u] += pre(pr[u], q[u], wd + u * F_PHI, sx, e.dx, e.dy, e.nd) > 0.0f ? gmr[u] : 0.0f;
+        }
+        st(S.arr(kb, dir ? GSI : GSO) + j * D, gs);
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            float acc = gh[i];
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                acc = fmaf(wd[u * F_PHI + i], gr[u], acc);
+                acc = fmaf(wd[u * F_PHI + D + i], gs[u], acc);
+            }
+            gh[i] = acc;
+        }
+    }
+    st(S.arr(kb, GHN) + j * D, gh);
 }
 
 __global__ __launch_bounds__(TB) void train_grad_kernel(TrainArgs a) {
@@ -347,129 +490,10 @@ __global__ __launch_bounds__(TB) void train_grad_kernel(TrainArgs a) {
         }
         __syncthreads();
         // Back through the decoder, Psi and the second message layers.
-        for (int j = tid; j < k; j += TB) {
-            float acc = 0.0f;  // (A_i^T rho)_j = (A_i rho)_j: A_i is symmetric
-            for (int q = a.lm_ptr[b + j]; q < a.lm_ptr[b + j + 1]; ++q)
-                acc = fmaf(a.lm_val[q], S.sca(kb, SRHO)[a.lm_col[q]], acc);
-            const float gr = 2.0f * acc;
-            S.sca(kb, SGR)[j] = gr;
-            float zd[D], gzd[D], gh[D];
-            ld(S.arr(kb, ZD) + j * D, zd);
-#pragma unroll
-            for (int u = 0; u < D; ++u) gzd[u] = zd[u] > 0.0f ? w[O_DE + D * D + D + u] * gr : 0.0f;
-            st(S.arr(kb, GZD) + j * D, gzd);
-            ld(S.arr(kb, GH) + j * D, gh);
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                float acc2 = gh[i];
-#pragma unroll
-                for (int u = 0; u < D; ++u) acc2 = fmaf(w[O_DE + u * D + i], gzd[u], acc2);
-                gh[i] = acc2;
-            }
-            float gps[D], zp[D], gz[D];
-#pragma unroll
-            for (int o = 0; o < D; ++o) gps[o] = a.alpha * gh[o];
-            st(S.arr(kb, GPS) + j * D, gps);
-            ld(S.arr(kb, ZP) + j * D, zp);
-#pragma unroll
-            for (int u = 0; u < D; ++u) {
-                float acc2 = 0.0f;
-#pragma unroll
-                for (int o = 0; o < D; ++o) acc2 = fmaf(w[O_PS + D * F_PSI + D + o * D + u], gps[o], acc2);
-                gz[u] = zp[u] > 0.0f ? acc2 : 0.0f;
-            }
-            st(S.arr(kb, GZ) + j * D, gz);
-            float gx[F_PSI];
-#pragma unroll
-            for (int i = 0; i < F_PSI; ++i) {
-                float acc2 = 0.0f;
-#pragma unroll
-                for (int u = 0; u < D; ++u) acc2 = fmaf(w[O_PS + u * F_PSI + i], gz[u], acc2);
-                gx[i] = acc2;
-            }
-            st(S.arr(kb, GFO) + j * D, gx + D + 1);
-            st(S.arr(kb, GFI) + j * D, gx + 2 * D + 1);
-            float gmo[D], gmi[D];
-#pragma unroll
-            for (int u = 0; u < D; ++u) {
-                float ao = 0.0f, ai = 0.0f;
-#pragma unroll
-                for (int v = 0; v < D; ++v) {
-                    ao = fmaf(w[O_PO + D * F_PHI + D + v * D + u], gx[D + 1 + v], ao);
-                    ai = fmaf(w[O_PI + D * F_PHI + D + v * D + u], gx[2 * D + 1 + v], ai);
-                }
-                gmo[u] = ao;
-                gmi[u] = ai;
-            }
-            st(S.arr(kb, GMO) + j * D, gmo);
-            st(S.arr(kb, GMI) + j * D, gmi);
-#pragma unroll
-            for (int i = 0; i < D; ++i) gh[i] += gx[i];
-            st(S.arr(kb, GHN) + j * D, gh);
-        }
+        for (int j = tid; j < k; j += TB) psi_back_node(a, S, w, cs, b, j);
         __syncthreads();
-        // Back through the first message layers: per receiver and per sender edge sums,
-        // one message direction at a time.
-        for (int j = tid; j < k; j += TB) {
-            float gh[D];
-            ld(S.arr(kb, GHN) + j * D, gh);
-#pragma unroll 1
-            for (int dir = 0; dir < 2; ++dir) {
-                const float* wd = w + (dir ? O_PI : O_PO);
-                const float sx = dir ? -1.0f : 1.0f;
-                const float* P = S.arr(kb, dir ? PI : PO);
-                const float* Q = S.arr(kb, dir ? QI : QO);
-                const float* GM = S.arr(kb, dir ? GMI : GMO);
-                float p[D], gm[D], gr[D], nn[D], gx[D], gy[D];
-                ld(P + j * D, p);
-                ld(GM + j * D, gm);
-#pragma unroll
-                for (int u = 0; u < D; ++u) gr[u] = nn[u] = gx[u] = gy[u] = 0.0f;
-                for (int t = a.edge_ptr[b + j]; t < a.edge_ptr[b + j + 1]; ++t) {
-                    const int l = a.edge_src[t];
-                    const Edge e = edge(a, b, j, l, t);
-                    const float* q = Q + l * D;
-#pragma unroll
-                    for (int u = 0; u < D; ++u) {
-                        const float g = pre(p[u], q[u], wd + u * F_PHI, sx, e.dx, e.dy, e.nd) > 0.0f ? gm[u] : 0.0f;
-                        gr[u] += g;
-                        nn[u] = fmaf(g, e.nd, nn[u]);
-                        gx[u] = fmaf(g, e.dx, gx[u]);
-                        gy[u] = fmaf(g, e.dy, gy[u]);
-                    }
-                }
-                st(S.arr(kb, dir ? GRI : GRO) + j * D, gr);
-                st(S.arr(kb, dir ? NI : NO) + j * D, nn);
-                st(S.arr(kb, dir ? DXI : DXO) + j * D, gx);
-                st(S.arr(kb, dir ? DYI : DYO) + j * D, gy);
-                // edges leaving j: j is the sender, r the receiver
-                float q[D], gs[D];
-                ld(Q + j * D, q);
-#pragma unroll
-                for (int u = 0; u < D; ++u) gs[u] = 0.0f;
-                for (int o = a.oe_ptr[b + j]; o < a.oe_ptr[b + j + 1]; ++o) {
-                    const int r = a.oe_recv[o];
-                    const Edge e = edge(a, b, r, j, a.oe_edge[o]);
-                    const float* pr = P + r * D;
-                    const float* gmr = GM + r * D;
-#pragma unroll
-                    for (int u = 0; u < D; ++u)
-                        gs[u] += pre(pr[u], q[u], wd + u * F_PHI, sx, e.dx, e.dy, e.nd) > 0.0f ? gmr[u] : 0.0f;
-                }
-                st(S.arr(kb, dir ? GSI : GSO) + j * D, gs);
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    float acc = gh[i];
-#pragma unroll
-                    for (int u = 0; u < D; ++u) {
-                        acc = fmaf(wd[u * F_PHI + i], gr[u], acc);
-                        acc = fmaf(wd[u * F_PHI + D + i], gs[u], acc);
-                    }
-                    gh[i] = acc;
-                }
-            }
-            st(S.arr(kb, GHN) + j * D, gh);
-        }
+        // Back through the first message layers.
+        for (int j = tid; j < k; j += TB) edge_back_node(a, S, w, b, j);
         __syncthreads();
         // The block's weight gradient; the gradient w.r.t. H^{k-1} becomes the carried one.
         float* gout = a.gpart + (int64_t)s * kb * TRAIN_NWB + (int64_t)blk * TRAIN_NWB;
