@@ -190,98 +190,148 @@ __device__ __noinline__ void block_node(const TrainArgs& a, const Sample& S, con
     }
 }
 
-// sum_{j<k} f(j) as four interleaved partial sums (j mod 4), combined in a fixed
-// order: several loads stay in flight.
-template <typename F>
-__device__ inline float sum4(int k, F f) {
-    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
-    int j = 0;
-    for (; j + 4 <= k; j += 4) {
-        a0 += f(j);
-        a1 += f(j + 1);
-        a2 += f(j + 2);
-        a3 += f(j + 3);
+// Weight gradients as sums over node tiles staged in LDS. A tile holds, for
+// CH nodes, every per-node quantity a gradient entry multiplies: rows of CH
+// values (padded to CHP so that the rows of one wavefront's entries fall on
+// different banks), D rows per vector quantity, then the scalars c, dL/dr_hat
+// and the in-degree.
+constexpr int CH = 32;
+constexpr int CHP = CH + 1;
+enum TSlot { T_HP, T_HC, T_GRO, T_GSO, T_DXO, T_DYO, T_NO, T_GFO, T_MO, T_GRI, T_GSI, T_DXI, T_DYI, T_NI, T_GFI,
+             T_MI, T_GZ, T_FO, T_FI, T_GPS, T_UP, T_GZD, T_UD, N_TV };
+constexpr int ROW_C = N_TV * D, ROW_GR = ROW_C + 1, ROW_DEG = ROW_C + 2, N_ROWS = ROW_C + 3;
+constexpr int ROW_ONE = -1;
+
+__device__ inline const float* tile_src(const Sample& S, int kb, int blk, int slot) {
+    switch (slot) {
+        case T_HP: return S.hist(blk);
+        case T_HC: return S.hist(blk + 1);
+        case T_GRO: return S.arr(kb, GRO);
+        case T_GSO: return S.arr(kb, GSO);
+        case T_DXO: return S.arr(kb, DXO);
+        case T_DYO: return S.arr(kb, DYO);
+        case T_NO: return S.arr(kb, NO);
+        case T_GFO: return S.arr(kb, GFO);
+        case T_MO: return S.arr(kb, MO);
+        case T_GRI: return S.arr(kb, GRI);
+        case T_GSI: return S.arr(kb, GSI);
+        case T_DXI: return S.arr(kb, DXI);
+        case T_DYI: return S.arr(kb, DYI);
+        case T_NI: return S.arr(kb, NI);
+        case T_GFI: return S.arr(kb, GFI);
+        case T_MI: return S.arr(kb, MI);
+        case T_GZ: return S.arr(kb, GZ);
+        case T_FO: return S.arr(kb, FO);
+        case T_FI: return S.arr(kb, FI);
+        case T_GPS: return S.arr(kb, GPS);
+        case T_UP: return S.arr(kb, UP);
+        case T_GZD: return S.arr(kb, GZD);
+        default: return S.arr(kb, UD);
     }
-    if (j < k) a0 += f(j);
-    if (j + 1 < k) a1 += f(j + 1);
-    if (j + 2 < k) a2 += f(j + 2);
-    return (a0 + a1) + (a2 + a3);
 }
 
-// Gradient of block `blk`'s weight e: a sum over the nodes of a product of
-// two per-node quantities (fixed order).
-__device__ __noinline__ float grad_entry(const TrainArgs& a, const Sample& S, const float* cs, int64_t b, int blk, int e) {
-    const int kb = a.kbar;
-    const int k = (int)S.k;
-    const float* Hp = S.hist(blk);      // H^{k-1}
-    const float* Hc = S.hist(blk + 1);  // H^k
-    const float* A = nullptr;
-    const float* B = nullptr;
-    int ca = 0, cb = 0, sb = D;
-    float sign = 1.0f;
-    bool deg = false;
+// Gradient entry e of a block = sign * sum_j tile[ra][j] * tile[rb][j] (rb = ROW_ONE: 1).
+struct Ent {
+    int ra, rb;
+    float sign;
+};
+__device__ inline int row(int slot, int comp) { return slot * D + comp; }
+__device__ Ent decode(int e) {
     if (e < O_PS) {
         const bool out = e < O_PI;
         const int r = e - (out ? O_PO : O_PI);
-        const float* GR = S.arr(kb, out ? GRO : GRI);
+        const int GR_ = out ? T_GRO : T_GRI, GS_ = out ? T_GSO : T_GSI, DX_ = out ? T_DXO : T_DXI;
+        const int DY_ = out ? T_DYO : T_DYI, N_ = out ? T_NO : T_NI, GF_ = out ? T_GFO : T_GFI;
+        const int M_ = out ? T_MO : T_MI;
+        const float sg = out ? 1.0f : -1.0f;  // Phi_in sees d_lj = -d_jl
         if (r < D * F_PHI) {
             const int u = r / F_PHI, i = r % F_PHI;
-            ca = u;
-            if (i < D) { A = GR; B = Hp; cb = i; }
-            else if (i < 2 * D) { A = S.arr(kb, out ? GSO : GSI); B = Hp; cb = i - D; }
-            else if (i == 2 * D) { A = S.arr(kb, out ? DXO : DXI); sign = out ? 1.0f : -1.0f; }
-            else if (i == 2 * D + 1) { A = S.arr(kb, out ? DYO : DYI); sign = out ? 1.0f : -1.0f; }
-            else { A = S.arr(kb, out ? NO : NI); }
-        } else if (r < D * F_PHI + D) {
-            A = GR; ca = r - D * F_PHI;
-        } else if (r < D * F_PHI + D + D * D) {
-            const int q = r - D * F_PHI - D;
-            A = S.arr(kb, out ? GFO : GFI); ca = q / D;
-            B = S.arr(kb, out ? MO : MI); cb = q % D;
-        } else {
-            A = S.arr(kb, out ? GFO : GFI); ca = r - D * F_PHI - D - D * D;
-            deg = true;
+            if (i < D) return {row(GR_, u), row(T_HP, i), 1.0f};
+            if (i < 2 * D) return {row(GS_, u), row(T_HP, i - D), 1.0f};
+            if (i == 2 * D) return {row(DX_, u), ROW_ONE, sg};
+            if (i == 2 * D + 1) return {row(DY_, u), ROW_ONE, sg};
+            return {row(N_, u), ROW_ONE, 1.0f};
         }
-    } else if (e < O_DE) {
+        if (r < D * F_PHI + D) return {row(GR_, r - D * F_PHI), ROW_ONE, 1.0f};
+        if (r < D * F_PHI + D + D * D) {
+            const int q = r - D * F_PHI - D;
+            return {row(GF_, q / D), row(M_, q % D), 1.0f};
+        }
+        return {row(GF_, r - D * F_PHI - D - D * D), ROW_DEG, 1.0f};
+    }
+    if (e < O_DE) {
         const int r = e - O_PS;
         if (r < D * F_PSI) {
             const int u = r / F_PSI, i = r % F_PSI;
-            A = S.arr(kb, GZ); ca = u;
-            if (i < D) { B = Hp; cb = i; }
-            else if (i == D) { B = cs; sb = 1; }
-            else if (i < 2 * D + 1) { B = S.arr(kb, FO); cb = i - D - 1; }
-            else { B = S.arr(kb, FI); cb = i - 2 * D - 1; }
-        } else if (r < D * F_PSI + D) {
-            A = S.arr(kb, GZ); ca = r - D * F_PSI;
-        } else if (r < D * F_PSI + D + D * D) {
-            const int q = r - D * F_PSI - D;
-            A = S.arr(kb, GPS); ca = q / D;
-            B = S.arr(kb, UP); cb = q % D;
-        } else {
-            A = S.arr(kb, GPS); ca = r - D * F_PSI - D - D * D;
+            if (i < D) return {row(T_GZ, u), row(T_HP, i), 1.0f};
+            if (i == D) return {row(T_GZ, u), ROW_C, 1.0f};
+            if (i < 2 * D + 1) return {row(T_GZ, u), row(T_FO, i - D - 1), 1.0f};
+            return {row(T_GZ, u), row(T_FI, i - 2 * D - 1), 1.0f};
         }
-    } else {
-        const int r = e - O_DE;
-        if (r < D * D) {
-            A = S.arr(kb, GZD); ca = r / D; B = Hc; cb = r % D;
-        } else if (r < D * D + D) {
-            A = S.arr(kb, GZD); ca = r - D * D;
-        } else {
-            // output layer: the scalar gradient of r_hat (stride 1)
-            const float* G = S.sca(kb, SGR);
-            const float* U = r < D * D + 2 * D ? S.arr(kb, UD) : nullptr;
-            const int cu = r - D * D - D;
-            return U ? sum4(k, [&](int j) { return G[j] * U[j * D + cu]; }) : sum4(k, [&](int j) { return G[j]; });
+        if (r < D * F_PSI + D) return {row(T_GZ, r - D * F_PSI), ROW_ONE, 1.0f};
+        if (r < D * F_PSI + D + D * D) {
+            const int q = r - D * F_PSI - D;
+            return {row(T_GPS, q / D), row(T_UP, q % D), 1.0f};
+        }
+        return {row(T_GPS, r - D * F_PSI - D - D * D), ROW_ONE, 1.0f};
+    }
+    const int r = e - O_DE;
+    if (r < D * D) return {row(T_GZD, r / D), row(T_HC, r % D), 1.0f};
+    if (r < D * D + D) return {row(T_GZD, r - D * D), ROW_ONE, 1.0f};
+    if (r < D * D + 2 * D) return {ROW_GR, row(T_UD, r - D * D - D), 1.0f};
+    return {ROW_GR, ROW_ONE, 1.0f};
+}
+
+constexpr int GR_ROUNDS = (TRAIN_NWB + TB - 1) / TB;
+
+// Block `blk`'s weight gradient for this thread's entries (e = tid + r TB), summed
+// over the nodes in ascending order, tile by tile.
+__device__ void block_grad(const TrainArgs& a, const Sample& S, const float* cs, int64_t b, int blk, float* tile,
+                           float* gout) {
+    const int kb = a.kbar, k = (int)S.k, tid = threadIdx.x;
+    Ent ent[GR_ROUNDS];
+    float acc[GR_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < GR_ROUNDS; ++r) {
+        const int e = tid + r * TB;
+        ent[r] = e < TRAIN_NWB ? decode(e) : Ent{0, ROW_ONE, 0.0f};
+        acc[r] = 0.0f;
+    }
+    for (int j0 = 0; j0 < k; j0 += CH) {
+        __syncthreads();
+        for (int idx = tid; idx < N_TV * CH * D; idx += TB) {
+            const int slot = idx / (CH * D), rem = idx % (CH * D), n = rem / D, comp = rem % D;
+            const int j = j0 + n;
+            tile[(slot * D + comp) * CHP + n] = j < k ? tile_src(S, kb, blk, slot)[j * D + comp] : 0.0f;
+        }
+        for (int idx = tid; idx < 3 * CH; idx += TB) {
+            const int which = idx / CH, n = idx % CH, j = j0 + n;
+            float v = 0.0f;
+            if (j < k)
+                v = which == 0 ? cs[j]
+                               : which == 1 ? S.sca(kb, SGR)[j]
+                                            : (float)(a.edge_ptr[b + j + 1] - a.edge_ptr[b + j]);
+            tile[(ROW_C + which) * CHP + n] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < GR_ROUNDS; ++r) {
+            const float* A = tile + ent[r].ra * CHP;
+            float x = acc[r];
+            if (ent[r].rb == ROW_ONE) {
+                for (int n = 0; n < CH; ++n) x += A[n];
+            } else {
+                const float* B = tile + ent[r].rb * CHP;
+                for (int n = 0; n < CH; ++n) x = fmaf(A[n], B[n], x);
+            }
+            acc[r] = x;
         }
     }
-    float acc;
-    if (deg)
-        acc = sum4(k, [&](int j) { return A[j * D + ca] * (float)(a.edge_ptr[b + j + 1] - a.edge_ptr[b + j]); });
-    else if (B)
-        acc = sum4(k, [&](int j) { return A[j * D + ca] * B[j * sb + cb]; });
-    else
-        acc = sum4(k, [&](int j) { return A[j * D + ca]; });
-    return sign * acc;
+#pragma unroll
+    for (int r = 0; r < GR_ROUNDS; ++r) {
+        const int e = tid + r * TB;
+        if (e < TRAIN_NWB) gout[e] = ent[r].sign * acc[r];
+    }
 }
 
 // Back through the decoder of H^k, Psi and the second message layers for node j.
@@ -414,6 +464,7 @@ __device__ __noinline__ void edge_back_node(const TrainArgs& a, const Sample& S,
 
 __global__ __launch_bounds__(TB) void train_grad_kernel(TrainArgs a) {
     __shared__ float w[TRAIN_NWB];
+    __shared__ float tile[N_ROWS * CHP];
     __shared__ double red[TB / 64];
     const int s = blockIdx.x;
     const int sub = a.subs[s];
@@ -497,7 +548,7 @@ __global__ __launch_bounds__(TB) void train_grad_kernel(TrainArgs a) {
         __syncthreads();
         // The block's weight gradient; the gradient w.r.t. H^{k-1} becomes the carried one.
         float* gout = a.gpart + (int64_t)s * kb * TRAIN_NWB + (int64_t)blk * TRAIN_NWB;
-        for (int e = tid; e < TRAIN_NWB; e += TB) gout[e] = grad_entry(a, S, cs, b, blk, e);
+        block_grad(a, S, cs, b, blk, tile, gout);
         for (int64_t i = tid; i < (int64_t)k * D; i += TB) S.arr(kb, GH)[i] = S.arr(kb, GHN)[i];
     }
     const double tot = block_sum_d(sse, red);
