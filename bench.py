@@ -614,6 +614,12 @@ def main():
         out["fgmres30_c3"] = bench_variant(dg, prob, u, *mk(krylov=dg.FGMRES, restart=30, rtol=1e-6))
         out["fcg_rtol1e-9_c3"] = bench_variant(dg, prob, u, *mk(rtol=1e-9))
         out["fgmres30_rtol1e-9_c3"] = bench_variant(dg, prob, u, *mk(krylov=dg.FGMRES, restart=30, rtol=1e-9))
+        log("plain FP64 form: FP64 DSS, eager launches (no graph), convergence read every iteration")
+        plain = dg.default_opts(precision="fp64", rtol=1e-6, max_it=max_it, check_every=1, graph=0)
+        out["fp64_plain_c3"] = bench_variant(dg, prob, u, plain,
+                                             dg.default_opts(precision="fp64", rtol=1e-6, max_it=max_it,
+                                                             check_every=1, graph=0, profile=1))
+        out["fp64_plain_c3"]["main_speedup"] = out["fp64_plain_c3"]["time_to_solution_ms"] / out["time_to_solution_ms"]
     if args.train_steps > 0:
         log("training steps of DSS_theta on the same mesh")
         out["train"] = bench_train(dg, ctx, prob, args.train_steps)
