@@ -128,6 +128,30 @@ def bench_lu(dg, prob, u, hp, steps: int) -> dict:
                          "avg_launch_ms": local_ms}}
 
 
+def oracle_train_per_sample(p, hp, subs) -> dict:
+    """The oracle's loss and gradient (float64 autograd, kbar 30) on a few local problems of
+    the same mesh, seeded right-hand sides: CPU seconds per sample."""
+    import torch
+    import workload as W
+    from oracle import decomp as dc
+    from oracle import train as tro
+    A = p.A.to_scipy()
+    samples = []
+    for i in subs:
+        nodes = hp.sub_nodes[hp.sub_ptr[i]:hp.sub_ptr[i + 1]]
+        g = dc.local_graph(nodes, p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
+        c = np.random.default_rng(int(i)).standard_normal(g.k)
+        c[g.dirichlet == 1] = 0.0
+        samples.append((g, tro.local_matrix(A, nodes), c / np.linalg.norm(c)))
+    th = W.xavier_theta(0, 30, 10).astype(np.float64)
+    t0 = time.perf_counter()
+    tro.loss_and_grad(th, samples, 1e-3, 30, 10, 1.0 / sum(g.k for g, _, _ in samples))
+    el = time.perf_counter() - t0
+    return {"s_per_sample": el / len(samples), "samples": len(samples),
+            "nodes": int(sum(g.k for g, _, _ in samples)), "threads": torch.get_num_threads(),
+            "kind": "oracle (float64 autograd on the CPU)"}
+
+
 def bench_train(dg, ctx, prob, steps: int, batch: int = 100) -> dict:
     """Training throughput of DSS_theta (kbar 30, d 10, alpha 1e-3, Xavier start): `steps`
     Adam steps over batches of `batch` local problems of this mesh, each a forward and
@@ -623,6 +647,10 @@ def main():
     if args.train_steps > 0:
         log("training steps of DSS_theta on the same mesh")
         out["train"] = bench_train(dg, ctx, prob, args.train_steps)
+        if args.cpu_sample > 0:
+            orc = oracle_train_per_sample(p, hp, [0, 1])
+            orc["gpu_speedup_per_sample"] = orc["s_per_sample"] * out["train"]["samples_per_s"]
+            out["train"]["oracle"] = orc
     if args.lu_steps > 0:
         log("DDM-LU on the same problem")
         out["ddm_lu"] = bench_lu(dg, prob, u, hp, args.lu_steps)

@@ -87,12 +87,18 @@ def train_epoch(ctx: Context, prob: Problem, data: Harvest, st: TrainState, batc
         adam_step(ctx, st.theta, st.grad, st.m, st.v, gn, st.step, lr=st.lr, clip=clip)
         losses.append(loss)
     mean = float(np.mean(losses))
-    st.history.append(mean)
-    if mean < st.best:
-        st.best, st.stale = mean, 0
+    plateau(st, mean, patience, factor)
+    return mean
+
+
+def plateau(st: TrainState, loss: float, patience: int = 10, factor: float = 0.1) -> None:
+    """Record an epoch loss; after more than `patience` epochs without a new best, scale the
+    learning rate by `factor` and start counting again."""
+    st.history.append(loss)
+    if loss < st.best:
+        st.best, st.stale = loss, 0
     else:
         st.stale += 1
         if st.stale > patience:
             st.lr *= factor
             st.stale = 0
-    return mean

@@ -1,5 +1,6 @@
-"""Serving loop driven by a fake executor on the host: the server's admission rule
-(budget, max_active, option groups, ticket order) over simulated requests (no GPU)."""
+"""Host logic without a GPU: the serving loop driven by a fake executor (the server's admission
+rule over simulated requests: budget, max_active, option groups, ticket order) and the
+training driver's learning-rate schedule."""
 import numpy as np
 import pytest
 
@@ -107,3 +108,16 @@ def test_random_streams_keep_the_invariants(seed):
     lat = np.array([out[i][1] - rs[i]["arrival"] for i in ok])
     p50, p99 = np.percentile(lat, [50, 99])
     assert 0 < p50 <= p99 <= lat.max()
+
+
+def test_training_plateau_schedule():
+    """Host logic of the training driver: the learning rate drops by the factor after more
+    than `patience` epochs without a new best loss, and the count restarts."""
+    from paper_2402_08296_amd import train as T
+    st = T.TrainState(None, None, None, None, lr=1e-2)
+    for loss in [5.0, 4.0, 4.5, 4.2, 4.1]:
+        T.plateau(st, loss, patience=2, factor=0.1)
+    assert st.lr == pytest.approx(1e-3) and st.best == 4.0 and st.stale == 0
+    T.plateau(st, 3.0, patience=2)
+    assert st.best == 3.0 and st.lr == pytest.approx(1e-3)
+    assert st.history == [5.0, 4.0, 4.5, 4.2, 4.1, 3.0]
