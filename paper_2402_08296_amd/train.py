@@ -70,16 +70,22 @@ def init_state(theta0, lr: float = 1e-2) -> TrainState:
     return TrainState(th, torch.zeros_like(th), torch.zeros_like(th), torch.empty_like(th), lr=lr)
 
 
-def train_epoch(ctx: Context, prob: Problem, data: Harvest, st: TrainState, batch: int = 100, kbar: int = 30,
-                alpha: float = 1e-3, clip: float = 1e-2, seed: int = 0, patience: int = 10,
-                factor: float = 0.1) -> float:
-    """One pass over the samples in a seeded order; returns the mean batch loss."""
-    samples = data.samples()
-    order = np.random.default_rng(seed).permutation(len(samples))
-    ptr = prob.hp.sub_ptr
+def train_epoch(ctx: Context, pairs, st: TrainState, batch: int = 100, kbar: int = 30, alpha: float = 1e-3,
+                clip: float = 1e-2, seed: int = 0, patience: int = 10, factor: float = 0.1) -> float:
+    """One pass over the samples of every (problem, harvest) pair in a seeded order (a batch
+    holds samples of one problem); returns the mean batch loss."""
+    batches = []
+    rng = np.random.default_rng(seed)
+    for q, (prob, data) in enumerate(pairs):
+        samples = data.samples()
+        order = rng.permutation(len(samples))
+        for b0 in range(0, len(order), batch):
+            batches.append((q, [samples[i] for i in order[b0:b0 + batch]]))
     losses = []
-    for b0 in range(0, len(order), batch):
-        sel = [samples[q] for q in order[b0:b0 + batch]]
+    for bi in rng.permutation(len(batches)):
+        q, sel = batches[bi]
+        prob, data = pairs[q]
+        ptr = prob.hp.sub_ptr
         subs = [i for _, i in sel]
         offs = [t * data.sum_k + int(ptr[i]) for t, i in sel]
         loss, gn = prob.train_grad(st.theta, subs, data.c, offs, st.grad, kbar=kbar, alpha=alpha)
@@ -102,3 +108,71 @@ def plateau(st: TrainState, loss: float, patience: int = 10, factor: float = 0.1
         if st.stale > patience:
             st.lr *= factor
             st.stale = 0
+
+
+def main():
+    """Train DSS_theta on local problems of generated meshes (the Sec. IV.A recipe at the
+    generator's shapes) and compare FCG iterations on a held-out problem."""
+    import argparse
+    import json
+    import time
+    import torch
+    import workload as W
+    from . import FCG, FP32, Model, host_problem
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--problems", type=int, default=8)
+    ap.add_argument("--nodes", type=int, default=7000)
+    ap.add_argument("--parts", type=int, default=7)
+    ap.add_argument("--epochs", type=int, default=100)
+    ap.add_argument("--batch", type=int, default=100)
+    ap.add_argument("--lr", type=float, default=1e-2)
+    ap.add_argument("--clip", type=float, default=1e-2)
+    ap.add_argument("--kbar", type=int, default=30)
+    ap.add_argument("--alpha", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=None, help="write the trained weights here (.npy)")
+    a = ap.parse_args()
+    ctx = Context()
+    th0 = W.xavier_theta(a.seed, a.kbar, 10)
+    model = Model(ctx, th0, kbar=a.kbar, alpha=a.alpha)
+    mk = lambda s: (lambda p: (p, host_problem(p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, p.A.rowptr, p.A.col,
+                                                 p.A.val, p.b, p.u0, p.part, p.n_parts, 2)))(
+        W.make_problem(s, a.nodes, a.parts, 0.0))
+    pairs, t0 = [], time.perf_counter()
+    for s in range(100, 100 + a.problems):
+        p, hp = mk(s)
+        prob = Problem(ctx, hp, model)
+        u = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+        st = prob.solve(u, default_opts(krylov=PCG, local_solver=LOCAL_LU, prolong=PROLONG_UNWEIGHTED,
+                                        precision=FP64, rtol=1e-6, max_it=500), check=False)
+        pairs.append((prob, harvest(prob, list(range(st.iterations)))))
+    n_samples = sum(len(d.samples()) for _, d in pairs)
+    t_harvest = time.perf_counter() - t0
+    state = init_state(torch.tensor(th0, device="cuda"), lr=a.lr)
+    t0 = time.perf_counter()
+    losses = []
+    for e in range(a.epochs):
+        losses.append(train_epoch(ctx, pairs, state, a.batch, a.kbar, a.alpha, a.clip, seed=e))
+        if e % 10 == 0 or e == a.epochs - 1:
+            print(f"epoch {e}: loss {losses[-1]:.5g} lr {state.lr:.1e}", flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    theta = state.theta.cpu().numpy()
+    if a.out:
+        np.save(a.out, theta)
+    p, hp = mk(0)  # held out
+    res = {}
+    for name, th in (("xavier", th0), ("trained", theta)):
+        m = Model(ctx, th, kbar=a.kbar, alpha=a.alpha)
+        prob = Problem(ctx, hp, m)
+        u = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+        st = prob.solve(u, default_opts(krylov=FCG, precision=FP32, rtol=1e-6, max_it=600), check=False)
+        res[name] = {"iterations": st.iterations, "converged": bool(st.converged),
+                     "rel_residual": st.rel_residual}
+    print(json.dumps({"problems": a.problems, "samples": n_samples, "epochs": a.epochs, "steps": state.step,
+                      "harvest_s": t_harvest, "train_s": t_train, "loss_first": losses[0], "loss_last": losses[-1],
+                      "lr_final": state.lr, "held_out_fcg": res}))
+
+
+if __name__ == "__main__":
+    main()

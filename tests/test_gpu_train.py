@@ -189,7 +189,7 @@ def test_training_lowers_the_loss(setup):
     p, hp, ctx, prob, subs, torch = setup
     h = T.harvest(prob, [0, 2])
     st = T.init_state(torch.tensor(W.xavier_theta(8, 5, 10), device="cuda"))
-    losses = [T.train_epoch(ctx, prob, h, st, batch=4, kbar=5, alpha=0.3, seed=e) for e in range(6)]
+    losses = [T.train_epoch(ctx, [(prob, h)], st, batch=4, kbar=5, alpha=0.3, seed=e) for e in range(6)]
     print("epoch losses", ["%.4g" % x for x in losses])
     assert losses[-1] < 0.9 * losses[0]
     assert bool(torch.isfinite(st.theta).all())
