@@ -185,6 +185,29 @@ def bench_train(dg, ctx, prob, steps: int, batch: int = 100) -> dict:
             "timing": "host clock around train_grad + adam_step, both synchronous"}
 
 
+def bench_trained(dg, ctx, hp, opts, epochs: int) -> dict:
+    """The paper's pipeline end to end: train DSS_theta from Xavier weights on local problems of
+    generated 7k-node meshes (8 meshes, sub-meshes of about 1000 nodes, DDM-LU-PCG harvest), then
+    solve the main problem with the trained weights (same options as the main solve)."""
+    import torch
+    from paper_2402_08296_amd import train as T
+    theta, info = T.train_on_generated(ctx, epochs=epochs, log=log)
+    model = dg.Model(ctx, theta)
+    prob = dg.Problem(ctx, hp, model)
+    u = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    prob.solve(u, opts, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = prob.solve(u, opts, check=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info.update({"solve_iterations": st.iterations, "solve_converged": bool(st.converged),
+                 "solve_true_rel_residual": st.true_rel_residual, "solve_time_ms": 1e3 * el})
+    prob.close()
+    model.close()
+    return info
+
+
 def bench_variant(dg, prob, u, opts, popts) -> dict:
     """One warm-up solve (graph capture), one timed solve, one profiled solve of the main problem."""
     import torch
@@ -477,6 +500,8 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--lu-steps", type=int, default=1, help="timed DDM-LU solves of the main problem (0: skip)")
     ap.add_argument("--train-steps", type=int, default=5, help="timed training steps of DSS_theta (0: skip)")
+    ap.add_argument("--trained-epochs", type=int, default=40,
+                    help="train DSS_theta for this many epochs, then solve the main problem with it (0: skip)")
     ap.add_argument("--variants", type=int, default=1, help="FGMRES and rtol 1e-9 legs on the main problem (0: skip)")
     ap.add_argument("--oracle-small", type=int, default=1, help="c1/c2 GPU and oracle timings (0: skip)")
     ap.add_argument("--tune", type=int, default=1, help="autotune the main problem's schedule (0: default schedule)")
@@ -651,6 +676,9 @@ def main():
             orc = oracle_train_per_sample(p, hp, [0, 1])
             orc["gpu_speedup_per_sample"] = orc["s_per_sample"] * out["train"]["samples_per_s"]
             out["train"]["oracle"] = orc
+    if args.trained_epochs > 0:
+        log(f"trained DSS_theta ({args.trained_epochs} epochs on generated meshes) on the main problem")
+        out["trained_weights"] = bench_trained(dg, ctx, hp, opts, args.trained_epochs)
     if args.lu_steps > 0:
         log("DDM-LU on the same problem")
         out["ddm_lu"] = bench_lu(dg, prob, u, hp, args.lu_steps)

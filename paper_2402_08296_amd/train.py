@@ -110,15 +110,58 @@ def plateau(st: TrainState, loss: float, patience: int = 10, factor: float = 0.1
             st.stale = 0
 
 
+def train_on_generated(ctx: Context, problems: int = 8, nodes: int = 7000, parts: int = 7, epochs: int = 100,
+                       batch: int = 100, lr: float = 1e-2, clip: float = 1e-2, kbar: int = 30,
+                       alpha: float = 1e-3, seed: int = 0, log=None):
+    """Harvest the local problems of DDM-LU-PCG solves on `problems` generated meshes (seeds
+    100, 101, ...) and train from Xavier weights. Returns (theta numpy, info dict)."""
+    import time
+    import torch
+    import workload as W
+    from . import Model
+    th0 = W.xavier_theta(seed, kbar, 10)
+    model = Model(ctx, th0, kbar=kbar, alpha=alpha)
+    pairs, t0 = [], time.perf_counter()
+    for s in range(100, 100 + problems):
+        p, hp = generated(s, nodes, parts)
+        prob = Problem(ctx, hp, model)
+        u = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+        st = prob.solve(u, default_opts(krylov=PCG, local_solver=LOCAL_LU, prolong=PROLONG_UNWEIGHTED,
+                                        precision=FP64, rtol=1e-6, max_it=500), check=False)
+        pairs.append((prob, harvest(prob, list(range(st.iterations)))))
+    t_harvest = time.perf_counter() - t0
+    state = init_state(torch.tensor(th0, device="cuda"), lr=lr)
+    t0 = time.perf_counter()
+    losses = []
+    for e in range(epochs):
+        losses.append(train_epoch(ctx, pairs, state, batch, kbar, alpha, clip, seed=e))
+        if log and (e % 10 == 0 or e == epochs - 1):
+            log(f"epoch {e}: loss {losses[-1]:.5g} lr {state.lr:.1e}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    info = {"problems": problems, "nodes": nodes, "parts": parts, "samples": sum(len(d.samples()) for _, d in pairs),
+            "epochs": epochs, "steps": state.step, "harvest_s": t_harvest, "train_s": t_train,
+            "loss_first": losses[0], "loss_last": losses[-1], "lr_final": state.lr}
+    return state.theta.cpu().numpy(), info
+
+
+def generated(seed: int, nodes: int, parts: int):
+    """A generated problem (seeded mesh, P1 system, partition) and its host arrays."""
+    import workload as W
+    from . import host_problem
+    p = W.make_problem(seed, nodes, parts, 0.0)
+    return p, host_problem(p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, p.A.rowptr, p.A.col, p.A.val, p.b, p.u0,
+                           p.part, p.n_parts, 2)
+
+
 def main():
     """Train DSS_theta on local problems of generated meshes (the Sec. IV.A recipe at the
     generator's shapes) and compare FCG iterations on a held-out problem."""
     import argparse
     import json
-    import time
     import torch
     import workload as W
-    from . import FCG, FP32, Model, host_problem
+    from . import FCG, FP32, Model
     ap = argparse.ArgumentParser()
     ap.add_argument("--problems", type=int, default=8)
     ap.add_argument("--nodes", type=int, default=7000)
@@ -133,45 +176,21 @@ def main():
     ap.add_argument("--out", default=None, help="write the trained weights here (.npy)")
     a = ap.parse_args()
     ctx = Context()
-    th0 = W.xavier_theta(a.seed, a.kbar, 10)
-    model = Model(ctx, th0, kbar=a.kbar, alpha=a.alpha)
-    mk = lambda s: (lambda p: (p, host_problem(p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, p.A.rowptr, p.A.col,
-                                                 p.A.val, p.b, p.u0, p.part, p.n_parts, 2)))(
-        W.make_problem(s, a.nodes, a.parts, 0.0))
-    pairs, t0 = [], time.perf_counter()
-    for s in range(100, 100 + a.problems):
-        p, hp = mk(s)
-        prob = Problem(ctx, hp, model)
-        u = torch.empty(prob.n, dtype=torch.float64, device="cuda")
-        st = prob.solve(u, default_opts(krylov=PCG, local_solver=LOCAL_LU, prolong=PROLONG_UNWEIGHTED,
-                                        precision=FP64, rtol=1e-6, max_it=500), check=False)
-        pairs.append((prob, harvest(prob, list(range(st.iterations)))))
-    n_samples = sum(len(d.samples()) for _, d in pairs)
-    t_harvest = time.perf_counter() - t0
-    state = init_state(torch.tensor(th0, device="cuda"), lr=a.lr)
-    t0 = time.perf_counter()
-    losses = []
-    for e in range(a.epochs):
-        losses.append(train_epoch(ctx, pairs, state, a.batch, a.kbar, a.alpha, a.clip, seed=e))
-        if e % 10 == 0 or e == a.epochs - 1:
-            print(f"epoch {e}: loss {losses[-1]:.5g} lr {state.lr:.1e}", flush=True)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    theta = state.theta.cpu().numpy()
+    theta, info = train_on_generated(ctx, a.problems, a.nodes, a.parts, a.epochs, a.batch, a.lr, a.clip, a.kbar,
+                                     a.alpha, a.seed, log=lambda m: print(m, flush=True))
     if a.out:
         np.save(a.out, theta)
-    p, hp = mk(0)  # held out
+    p, hp = generated(0, a.nodes, a.parts)  # held out
     res = {}
-    for name, th in (("xavier", th0), ("trained", theta)):
+    for name, th in (("xavier", W.xavier_theta(a.seed, a.kbar, 10)), ("trained", theta)):
         m = Model(ctx, th, kbar=a.kbar, alpha=a.alpha)
         prob = Problem(ctx, hp, m)
         u = torch.empty(prob.n, dtype=torch.float64, device="cuda")
         st = prob.solve(u, default_opts(krylov=FCG, precision=FP32, rtol=1e-6, max_it=600), check=False)
         res[name] = {"iterations": st.iterations, "converged": bool(st.converged),
                      "rel_residual": st.rel_residual}
-    print(json.dumps({"problems": a.problems, "samples": n_samples, "epochs": a.epochs, "steps": state.step,
-                      "harvest_s": t_harvest, "train_s": t_train, "loss_first": losses[0], "loss_last": losses[-1],
-                      "lr_final": state.lr, "held_out_fcg": res}))
+    info["held_out_fcg"] = res
+    print(json.dumps(info))
 
 
 if __name__ == "__main__":
