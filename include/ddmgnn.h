@@ -330,8 +330,12 @@ int ddmgnn_train_rhs(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const double* u, flo
  * gradient is deterministic (fixed-order sums; no atomics). *loss_out and
  * *gnorm_out (host, may be NULL) receive the loss (FP64 sum of the FP32
  * residuals) and |grad|_2. The first call builds the local matrices and edge
- * transposes on the device; scratch grows to about 4 (kbar + 33) d k_i bytes per
- * sample. E_NONFINITE when the loss or the gradient overflows. */
+ * transposes on the device. Samples run in launches of 512 that share one
+ * scratch region of about 4 (kbar + 33) d k_i bytes per sample of a launch, plus
+ * 4 kbar(11d^2+15d+1) bytes per sample for the per-sample gradients. The
+ * problem's training buffers serve one call at a time: calls on one problem from
+ * several threads must be serialised. E_NONFINITE when the loss or the gradient
+ * overflows. */
 int ddmgnn_train_grad(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const ddmgnn_model_desc* model, const float* theta,
                       const int32_t* subs, int32_t n, const float* c, const int64_t* c_off, double scale,
                       float* grad, double* loss_out, double* gnorm_out);

@@ -190,7 +190,10 @@ struct TrainArgs {
     double* sse;               // per sample, sum of squared residuals over the blocks
     int kbar;
     float alpha;
+    int s0;                    // first sample of this launch (workgroup b takes sample s0 + b)
 };
+// Samples per launch of the training kernel: launches reuse one scratch region.
+constexpr int TRAIN_CHUNK = 512;
 int64_t train_scratch_floats(int kbar, int64_t k);
 hipError_t launch_train_grad(const TrainArgs& a, int n, hipStream_t s);
 // grad = scale * sum over samples of gpart; out2[0] = |grad|^2, out2[1] = sum of sse.

@@ -1506,13 +1506,16 @@ int ddmgnn_train_grad(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_model_des
     if (md->kbar < 1 || md->kbar > 64) return fail(DDMGNN_E_INVALID, "kbar must be in 1..64");
     if (n < 1) return fail(DDMGNN_E_INVALID, "at least one sample required");
     if (!(scale >= 0.0) || !std::isfinite(scale)) return fail(DDMGNN_E_INVALID, "scale must be finite and >= 0");
+    // scratch offsets restart with every chunk of TRAIN_CHUNK samples (one launch each)
     std::vector<int64_t> soff((size_t)n);
-    int64_t total = 0;
+    int64_t total = 0, used = 0;
     for (int32_t i = 0; i < n; ++i) {
         if (subs[i] < 0 || subs[i] >= P->hs.K) return fail(DDMGNN_E_INVALID, "sub-mesh index out of range");
         if (c_off[i] < 0) return fail(DDMGNN_E_INVALID, "negative right-hand side offset");
-        soff[(size_t)i] = total;
-        total += train_scratch_floats(md->kbar, P->hs.sub_ptr[subs[i] + 1] - P->hs.sub_ptr[subs[i]]);
+        if (i % TRAIN_CHUNK == 0) used = 0;
+        soff[(size_t)i] = used;
+        used += train_scratch_floats(md->kbar, P->hs.sub_ptr[subs[i] + 1] - P->hs.sub_ptr[subs[i]]);
+        total = std::max(total, used);
     }
     if (int rc = prepare_train(P)) return rc;
     hipStream_t s = ctx->stream;
@@ -1531,8 +1534,11 @@ int ddmgnn_train_grad(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_model_des
     HIP_TRY(upload_async(P->tr_soff.p, soff.data(), (size_t)n * 8, s));
     TrainArgs a{P->sub_ptr.p, P->edge_ptr.p, P->edge_src.p, P->edge_nd.p, P->xy64.p, P->lm_ptr.p, P->lm_col.p,
                 P->lm_val.p, P->oe_ptr.p, P->oe_edge.p, P->oe_recv.p, P->tr_subs.p, P->tr_coff.p, P->tr_soff.p,
-                c, theta, P->tr_scratch.p, P->tr_gpart.p, P->tr_sse.p, md->kbar, (float)md->alpha};
-    HIP_TRY(launch_train_grad(a, n, s));
+                c, theta, P->tr_scratch.p, P->tr_gpart.p, P->tr_sse.p, md->kbar, (float)md->alpha, 0};
+    for (int32_t s0 = 0; s0 < n; s0 += TRAIN_CHUNK) {
+        a.s0 = s0;
+        HIP_TRY(launch_train_grad(a, std::min(TRAIN_CHUNK, n - s0), s));
+    }
     HIP_TRY(launch_train_reduce(P->tr_gpart.p, n, nth, scale, grad, P->tr_out.p, P->tr_sse.p, s));
     double out2[2];
     HIP_TRY(hipMemcpyAsync(out2, P->tr_out.p, sizeof(out2), hipMemcpyDeviceToHost, s));

@@ -466,7 +466,7 @@ __global__ __launch_bounds__(TB) void train_grad_kernel(TrainArgs a) {
     __shared__ float w[TRAIN_NWB];
     __shared__ float tile[N_ROWS * CHP];
     __shared__ double red[TB / 64];
-    const int s = blockIdx.x;
+    const int s = a.s0 + blockIdx.x;
     const int sub = a.subs[s];
     const int64_t b = a.sub_ptr[sub];
     const int k = a.sub_ptr[sub + 1] - (int)b;

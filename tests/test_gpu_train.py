@@ -194,3 +194,26 @@ def test_training_lowers_the_loss(setup):
     assert losses[-1] < 0.9 * losses[0]
     assert bool(torch.isfinite(st.theta).all())
     assert st.step == 6 * ((len(h.samples()) + 3) // 4)
+
+
+def test_many_samples_run_in_chunks(setup):
+    """600 samples run as launches of 512 sharing one scratch region: the loss and gradient
+    equal those of the two parts computed separately (up to the order of the sample sum)."""
+    p, hp, ctx, prob, subs, torch = setup
+    cs = [_rhs(subs[i][1], 40 + i) for i in range(hp.K)]
+    starts = np.cumsum([0] + [c.size for c in cs[:-1]])
+    cdev = torch.tensor(np.concatenate(cs), device="cuda")
+    theta = torch.tensor(_theta(6, 2), device="cuda")
+    order = [i % hp.K for i in range(600)]
+    offs = [int(starts[i]) for i in order]
+    g, ga, gb = (torch.empty_like(theta) for _ in range(3))
+    L, _ = prob.train_grad(theta, order, cdev, offs, g, kbar=2, alpha=0.3, scale=1e-3)
+    La, _ = prob.train_grad(theta, order[:512], cdev, offs[:512], ga, kbar=2, alpha=0.3, scale=1e-3)
+    Lb, _ = prob.train_grad(theta, order[512:], cdev, offs[512:], gb, kbar=2, alpha=0.3, scale=1e-3)
+    assert L == pytest.approx(La + Lb, rel=1e-12)
+    assert torch.allclose(g, ga + gb, rtol=1e-5, atol=1e-6 * float(g.abs().max()))
+    # repeated samples contribute identical terms: L = sum_i count_i L_i over the sub-meshes
+    g1 = torch.empty_like(theta)
+    per = [prob.train_grad(theta, [i], cdev, [int(starts[i])], g1, kbar=2, alpha=0.3, scale=1e-3)[0]
+           for i in range(hp.K)]
+    assert L == pytest.approx(sum(order.count(i) * per[i] for i in range(hp.K)), rel=1e-12)
