@@ -19,15 +19,15 @@ from . import (FP64, LOCAL_LU, PCG, PROLONG_UNWEIGHTED, Context, Problem, adam_s
 
 @dataclass
 class Harvest:
-    """Right-hand sides of all sub-meshes at T iterates: c[t * sum_k + slot]."""
+    """Right-hand sides of all K sub-meshes at T iterates: c[t * sum_k + slot]."""
     c: object          # device float32 tensor, T * sum_k
-    iterates: list     # the PCG iteration of each block
+    iterates: list     # the PCG iteration of each block of sum_k values
     sum_k: int
+    K: int
 
     def samples(self):
-        return [(t, i) for t in range(len(self.iterates)) for i in range(self._K)]
-
-    _K: int = 0
+        """(iterate index, sub-mesh) of every sample."""
+        return [(t, i) for t in range(len(self.iterates)) for i in range(self.K)]
 
 
 def harvest(prob: Problem, iterates) -> Harvest:
@@ -46,9 +46,7 @@ def harvest(prob: Problem, iterates) -> Harvest:
                              rtol=1e-300, max_it=it)
             prob.solve(u, o, check=False)
         prob.train_rhs(u, c[t * sum_k:(t + 1) * sum_k])
-    h = Harvest(c, list(iterates), sum_k)
-    h._K = prob.K
-    return h
+    return Harvest(c, list(iterates), sum_k, prob.K)
 
 
 @dataclass
