@@ -217,3 +217,31 @@ def test_many_samples_run_in_chunks(setup):
     per = [prob.train_grad(theta, [i], cdev, [int(starts[i])], g1, kbar=2, alpha=0.3, scale=1e-3)[0]
            for i in range(hp.K)]
     assert L == pytest.approx(sum(order.count(i) * per[i] for i in range(hp.K)), rel=1e-12)
+
+
+def test_largest_sub_mesh_matches_oracle(setup):
+    """A sub-mesh of exactly 2048 nodes (the library's limit) against the oracle."""
+    p0, hp0, ctx, prob0, subs0, torch = setup
+    p = W.make_problem(11, 5400, 3, 0.0)
+    hp = dg.host_problem(p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, p.A.rowptr, p.A.col, p.A.val, p.b, p.u0,
+                         p.part, p.n_parts, 2)
+    sizes = np.diff(hp.sub_ptr)
+    big = int(np.argmax(sizes))
+    assert sizes[big] == 2048
+    model = dg.Model(ctx, W.xavier_theta(0, 30, 10))
+    prob = dg.Problem(ctx, hp, model)
+    nodes = hp.sub_nodes[hp.sub_ptr[big]:hp.sub_ptr[big + 1]]
+    g = dc.local_graph(nodes, p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
+    Ai = tr.local_matrix(p.A.to_scipy(), nodes)
+    c = _rhs(g, 77)
+    theta = _theta(9, 2)
+    grad = torch.empty(theta.size, dtype=torch.float32, device="cuda")
+    loss, _ = prob.train_grad(torch.tensor(theta, device="cuda"), [big], torch.tensor(c, device="cuda"), [0], grad,
+                              kbar=2, alpha=0.3)
+    L, G = tr.loss_and_grad(theta.astype(np.float64), [(g, Ai, c.astype(np.float64))], 0.3, 2, 10, 1.0 / g.k)
+    gg = grad.cpu().numpy()
+    print(f"k=2048: loss rel err {abs(loss - L) / L:.2e}, grad err {np.abs(gg - G).max() / np.abs(G).max():.2e}")
+    assert abs(loss - L) <= LOSS_RTOL * L
+    assert np.abs(gg - G).max() <= GRAD_ATOL * np.abs(G).max()
+    prob.close()
+    model.close()
