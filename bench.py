@@ -15,7 +15,11 @@ The same JSON line carries:
     64 problems of 10k-200k nodes, batched and one after another;
   * serve: a bounded prefix of the request stream (Poisson arrivals, 5k-2M
     nodes) through the serving loop, with p50/p99 latency;
-  * cpu_baseline: the CPU oracle timed on a bounded sample of the main workload.
+  * train / trained_weights: training steps of DSS_theta on local problems of the
+    main mesh, and a short training run on generated meshes followed by a solve
+    of the main problem with the trained weights;
+  * cpu_baseline: the CPU oracle timed on a bounded sample of the main workload
+    (and its training step on two local problems).
 
   python bench.py --pmc-workload    copies of known size and a few applies of the
                                     main workload, for rocprofv3 counter passes
@@ -672,10 +676,6 @@ def main():
     if args.train_steps > 0:
         log("training steps of DSS_theta on the same mesh")
         out["train"] = bench_train(dg, ctx, prob, args.train_steps)
-        if args.cpu_sample > 0:
-            orc = oracle_train_per_sample(p, hp, [0, 1])
-            orc["gpu_speedup_per_sample"] = orc["s_per_sample"] * out["train"]["samples_per_s"]
-            out["train"]["oracle"] = orc
     if args.trained_epochs > 0:
         log(f"trained DSS_theta ({args.trained_epochs} epochs on generated meshes) on the main problem")
         out["trained_weights"] = bench_trained(dg, ctx, hp, opts, args.trained_epochs)
@@ -705,6 +705,11 @@ def main():
     if args.cpu_sample > 0:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(p, hp, theta, iters, args.cpu_sample)
+        if "train" in out:  # the oracle's training step beside the GPU's
+            orc = oracle_train_per_sample(p, hp, [0, 1])
+            out["cpu_baseline"]["train_step"] = orc
+            out["train"]["oracle_s_per_sample"] = orc["s_per_sample"]
+            out["train"]["gpu_speedup_per_sample"] = orc["s_per_sample"] * out["train"]["samples_per_s"]
     if small_cpu:
         log("c1 and c2 on the GPU")
         out["oracle_c1_c2"] = gpu_small(dg, ctx, model, small_cpu)
