@@ -495,6 +495,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
+    ap.add_argument("--m-max", type=int, default=4, help="directions kept by FCG (truncated flexible CG)")
     ap.add_argument("--theta", default="smoother", choices=["smoother", "xavier"])
     ap.add_argument("--cpu-sample", type=int, default=160, help="sub-meshes in the oracle sample (0: skip)")
     ap.add_argument("--batch8", type=int, default=8, help="copies of the main problem in one batch (0: skip)")
@@ -569,7 +570,7 @@ def main():
     log(f"library setup {time.perf_counter() - t:.1f}s; edges={prob.n_edges}")
     u = torch.empty(p.n, dtype=torch.float64, device="cuda")
     max_it = 5000 if args.theta == "smoother" else 200
-    opts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, check_every=16)
+    opts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, check_every=16, m_max=args.m_max)
     tuning = None
     if args.tune:
         from paper_2402_08296_amd import tune
@@ -578,7 +579,8 @@ def main():
         tuning["seconds"] = time.perf_counter() - t
         log(f"schedule {tuning['tuning']} ({'cached' if tuning['cached'] else 'autotuned'}, "
             f"{tuning['seconds']:.2f}s)")
-    popts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, profile=1, check_every=16)
+    popts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, profile=1, check_every=16,
+                            m_max=args.m_max)
     for w in range(args.warmup):
         st = prob.solve(u, opts, check=False)
         log(f"warmup {w}: iterations={st.iterations} status={st.status} true_rel={st.true_rel_residual:.2e}")
@@ -636,7 +638,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: P1-FEM Poisson on a Delaunay mesh of a star polygon, "
                                f"N={p.n}, K={hp.K} sub-meshes (overlap 2), sum k_i={hp.sub_nodes.size}, "
-                               f"DSS kbar=30 d=10 ({args.theta} weights), FCG(1) to rel. residual 1e-6",
+                               f"DSS kbar=30 d=10 ({args.theta} weights), FCG({args.m_max}) to rel. residual 1e-6",
                    "nodes": p.n, "subdomains": hp.K, "dss_precision": args.precision, "weights": args.theta,
                    "schedule": "autotuned" if args.tune else "default",
                    "target_nodes": cfg["target_nodes"]},
@@ -661,17 +663,20 @@ def main():
         "tuning": tuning,
     }
     if args.variants > 0:
-        log("FGMRES(30) and rtol 1e-9 on the same problem")
+        other = 1 if args.m_max != 1 else 4
+        log(f"FGMRES(30), FCG({other}) and rtol 1e-9 on the same problem")
         mk = lambda **kw: (dg.default_opts(precision=args.precision, max_it=max_it, check_every=16, **kw),
                            dg.default_opts(precision=args.precision, max_it=max_it, check_every=16, profile=1, **kw))
         out["fgmres30_c3"] = bench_variant(dg, prob, u, *mk(krylov=dg.FGMRES, restart=30, rtol=1e-6))
-        out["fcg_rtol1e-9_c3"] = bench_variant(dg, prob, u, *mk(rtol=1e-9))
+        out[f"fcg{other}_c3"] = bench_variant(dg, prob, u, *mk(m_max=other, rtol=1e-6))
+        out["fcg_rtol1e-9_c3"] = bench_variant(dg, prob, u, *mk(m_max=args.m_max, rtol=1e-9))
         out["fgmres30_rtol1e-9_c3"] = bench_variant(dg, prob, u, *mk(krylov=dg.FGMRES, restart=30, rtol=1e-9))
         log("plain FP64 form: FP64 DSS, eager launches (no graph), convergence read every iteration")
         plain = dg.default_opts(precision="fp64", rtol=1e-6, max_it=max_it, check_every=1, graph=0)
         out["fp64_plain_c3"] = bench_variant(dg, prob, u, plain,
                                              dg.default_opts(precision="fp64", rtol=1e-6, max_it=max_it,
                                                              check_every=1, graph=0, profile=1))
+        out["fp64_plain_c3"]["krylov"] = "FCG(1)"
         out["fp64_plain_c3"]["main_speedup"] = out["fp64_plain_c3"]["time_to_solution_ms"] / out["time_to_solution_ms"]
     if args.train_steps > 0:
         log("training steps of DSS_theta on the same mesh")
@@ -696,7 +701,8 @@ def main():
         out["batch_c4"] = bench_batched(dg, ctx, model, batch_items, opts, 2, True)
     if stream:
         log("stream c5")
-        sopts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, check_every=8, graph=0)
+        sopts = dg.default_opts(precision=args.precision, rtol=1e-6, max_it=max_it, check_every=8, graph=0,
+                                m_max=args.m_max)
         out["serve_c5"] = bench_serve(dg, model, stream, sopts, 64 << 30)
         out["serve_c5"]["rate_per_s"] = W.STREAM_CONFIGS["c5"]["rate"]
         out["serve_c5_sustained"] = bench_serve(dg, model, stream_slow, sopts, 64 << 30)
