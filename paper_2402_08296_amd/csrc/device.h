@@ -166,7 +166,7 @@ hipError_t launch_dot(const double* x, const double* y, int64_t n, double* parti
 
 // Training of DSS_theta (train.hip): one TRAIN_BLOCK-thread workgroup per local
 // problem; TRAIN_NWB weights per block (d = D).
-constexpr int TRAIN_BLOCK = 512;
+constexpr int TRAIN_BLOCK = 1024;
 constexpr int TRAIN_NWB = 11 * D * D + 15 * D + 1;
 struct TrainArgs {
     const int32_t* sub_ptr;
