@@ -52,28 +52,51 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def dss_flops(kbar: int, d: int, sum_k: int, n_edges: int):
-    """Algorithmic flops of one DSS forward launch (multiply-add = 2 flops).
+LDS_TBPS = 128 * 256 * 2.4e9 / 1e12  # LDS: 128 B per clock per compute unit, 256 units, 2.4 GHz
 
-    Per node and block (dense layers): neighbour projections 4d^2, receiver
-    projections 4d^2+2d, message second layers 4d^2+2d, Psi 8d^2+7d (2110 at
-    d = 10); per directed edge and block: 2 (dx, dy) + 4 (|d|) + 2d * 9 (186 at
-    d = 10); final decoder 2d^2+4d+1 per node. Returns (dense, per-edge).
-    """
+
+def dss_work(kbar: int, d: int, sum_k: int, n_edges: int) -> dict:
+    """Algorithmic work of one DSS forward launch in the factorised form (multiply-add =
+    2 flops), from the actual node and edge counts.
+
+    Dense 10-wide layers per node and block (matrix cores): neighbour projections
+    Q' 4d^2 (both directions, coordinate terms folded in), receiver projections P'
+    4d^2+2d, message second layers 4d^2+2d, Psi 8d^2+7d (2110 at d = 10); the
+    final decoder 2d^2+4d+1 per node. Per directed edge and block (vector ALU), for
+    each of the 2d message units: P'+Q', the |d| term (multiply-add), ReLU and the
+    sum, 5 operations (100 at d = 10). LDS: per edge and block the gather of the
+    sender's Q' row, 2d FP16 values."""
     per_node = 4 * d * d + (4 * d * d + 2 * d) + (4 * d * d + 2 * d) + (8 * d * d + 7 * d)
-    per_edge = 6 + 2 * d * 9
     dense = kbar * per_node * sum_k + (2 * d * d + 4 * d + 1) * sum_k
-    return float(dense), float(kbar * per_edge * n_edges)
+    edge = float(kbar * 2 * d * 5 * n_edges)
+    lds = float(kbar * 2 * d * 2 * n_edges)
+    return {"flops_mfma": float(dense), "flops_valu": edge, "lds_bytes": lds}
 
 
-def dss_peak_tflops(precision: str, dense: float, edge: float) -> float:
-    """Peak rate for the DSS flop mix: the MFMA kernel runs the dense layers on
-    BF16 matrix cores and the edge sums in packed FP16 VALU, so its floor time
-    is dense/BF16 peak + edge/packed FP16 peak; the VALU kernels run all of it
-    on FP32 or FP64 vector units."""
+def dss_roofline(work: dict, t_ms: float, hbm_bytes: float, precision: str) -> dict:
+    """Fraction of the binding roof: the largest of the floors work/peak over matrix
+    cores, vector ALU, LDS and HBM, divided by the measured time. The MFMA kernel
+    runs the dense layers on BF16/FP16 matrix cores and the edge work on packed FP16
+    vector ALU (157.3 TFLOP/s, the packed FP32 rate); the VALU kernels run both on
+    FP32 or FP64 vector ALU."""
+    t = t_ms * 1e-3
     if precision == "bf16":
-        return (dense + edge) / (dense / BF16_MFMA_TF + edge / FP16_PACKED_TF)
-    return FP64_VALU_TF if precision == "fp64" else FP32_VALU_TF
+        floors = {"mfma": work["flops_mfma"] / (BF16_MFMA_TF * 1e12),
+                  "valu": work["flops_valu"] / (FP16_PACKED_TF * 1e12)}
+        valu_peak = FP16_PACKED_TF
+    else:
+        valu_peak = FP64_VALU_TF if precision == "fp64" else FP32_VALU_TF
+        floors = {"valu": (work["flops_mfma"] + work["flops_valu"]) / (valu_peak * 1e12)}
+    floors["lds"] = work["lds_bytes"] / (LDS_TBPS * 1e12)
+    floors["hbm"] = hbm_bytes / (HBM_GBPS * 1e9)
+    bound = max(floors, key=floors.get)
+    out = {"binding": bound, "floors_us": {k: v * 1e6 for k, v in floors.items()},
+           "frac_binding": floors[bound] / t}
+    if precision == "bf16":
+        out["achieved_valu_tflops"] = work["flops_valu"] / t / 1e12
+        out["valu_peak_tflops"] = valu_peak
+        out["mfma_frac"] = work["flops_mfma"] / t / 1e12 / BF16_MFMA_TF
+    return out
 
 
 def apply_bytes(n: int, K: int, sum_k: int, n_edges: int, xy_bytes: int = 8) -> float:
@@ -86,6 +109,41 @@ def apply_bytes(n: int, K: int, sum_k: int, n_edges: int, xy_bytes: int = 8) -> 
     """
     return (sum_k * (8 + 4 + 8 + xy_bytes + 4 + 8) + 2 * n_edges + 8.0 * K * K
             + n * (4 + 1 + 8 + 8) + sum_k * (4 + 4 + 8 + 8))
+
+
+def dss_hbm_bytes(sum_k: int, n_edges: int) -> float:
+    """Compulsory HBM bytes of one DSS forward launch: per slot the r gather 8,
+    sub_nodes 4, weights 8, tile record 16 and local output 8; per edge its 4-byte
+    record."""
+    return 44.0 * sum_k + 4.0 * n_edges
+
+
+_DIRECT = {}
+
+
+def _direct_solve_task():
+    import scipy.sparse.linalg as spl
+    A, b = _DIRECT["A"], _DIRECT["b"]
+    return spl.spsolve(A.tocsc(), b)
+
+
+class DirectSolve:
+    """scipy's sparse direct solve of A u = b in one forked worker process (started
+    before the GPU is touched, so it runs beside the GPU legs); result() joins it."""
+
+    def __init__(self, p):
+        import multiprocessing as mp
+        _DIRECT.update(A=p.A.to_scipy(), b=p.b)
+        self.pool = mp.get_context("fork").Pool(1)
+        self.job = self.pool.apply_async(_direct_solve_task)
+        _DIRECT.clear()
+
+    def result(self):
+        try:
+            return self.job.get(timeout=1800)
+        finally:
+            self.pool.close()
+            self.pool.join()
 
 
 def lu_local_bytes(K: int, sum_k: int, sum_k2: int) -> float:
@@ -245,77 +303,116 @@ def generate(specs, workers: int):
     if workers <= 1 or len(specs) <= 1:
         return [_make(s) for s in specs]
     import multiprocessing as mp
-    with mp.get_context("fork").Pool(min(workers, len(specs))) as pool:
-        return pool.map(_make, specs, chunksize=1)
+    pool = mp.get_context("fork").Pool(min(workers, len(specs)))
+    try:
+        out = pool.map(_make, specs, chunksize=1)
+        pool.close()
+    except BaseException:
+        pool.terminate()
+        raise
+    finally:
+        pool.join()
+    return out
 
 
-def cpu_baseline(p, hp, theta, iterations: int, sample: int) -> dict:
-    """The CPU oracle timed on a bounded sample of the same workload, scaled to solves/s."""
+_ORACLE = {}
+
+
+def _oracle_worker(w: int, nproc: int, bar, out):
+    """Forked worker of oracle_apply_parallel: builds the local graphs of its sub-meshes
+    (untimed), then runs their DSS forward passes between two barriers and returns their
+    local terms s_i r~_i."""
+    import threadpoolctl
+
+    from oracle import decomp as dc, dss
+    o = _ORACLE
+    mine = o["order"][w::nproc]
+    with threadpoolctl.threadpool_limits(1):
+        graphs = [dc.local_graph(o["sub_nodes"][o["sub_ptr"][i]:o["sub_ptr"][i + 1]], o["tri"], o["xy"],
+                                 o["dirichlet"]) for i in mine]
+        bar.wait(timeout=900)
+        res = []
+        for i, g in zip(mine, graphs):
+            ri = o["r"][o["sub_nodes"][o["sub_ptr"][i]:o["sub_ptr"][i + 1]]]
+            s = float(np.linalg.norm(ri))
+            res.append((int(i), s * dss.forward(o["blocks"], g, ri / s, 1e-3, 10) if s > 0 else np.zeros(ri.size)))
+        bar.wait(timeout=900)
+    out.put(res)
+
+
+def oracle_apply_parallel(p, hp, theta, nproc: int) -> dict:
+    """The oracle's preconditioner apply with one process per core: every sub-mesh's DSS
+    forward (the sub-meshes dealt round-robin by decreasing size), timed between two
+    barriers once every process has built its graphs, then the gluing and the coarse
+    solve in this process, and the rest of an FCG iteration (SpMV, dots, updates).
+    Forks before the GPU is touched; every process is joined."""
+    import multiprocessing as mp
+
     import threadpoolctl
 
     from oracle import decomp as dc, dss, schwarz as sw
-
-    rng = np.random.default_rng(0)
-    subs = np.sort(rng.choice(hp.K, size=min(sample, hp.K), replace=False))
     A = p.A.to_scipy()
-    r = p.b - A @ p.u0
-    blocks = dss.unpack(theta, 30, 10)
-    graphs = [dc.local_graph(hp.sub_nodes[hp.sub_ptr[i]:hp.sub_ptr[i + 1]], p.mesh.tri, p.mesh.xy,
-                             p.mesh.dirichlet) for i in subs]
-    t0 = time.perf_counter()
-    k_sample = 0
-    for i, g in zip(subs, graphs):
-        ri = r[hp.sub_nodes[hp.sub_ptr[i]:hp.sub_ptr[i + 1]]]
-        s = np.linalg.norm(ri)
-        dss.forward(blocks, g, ri / s, 1e-3, 10)
-        k_sample += ri.size
-    t_local = (time.perf_counter() - t0) * hp.sub_nodes.size / k_sample
+    r = np.ascontiguousarray(p.b - A @ p.u0)
+    k = np.diff(hp.sub_ptr)
+    _ORACLE.update(sub_ptr=hp.sub_ptr, sub_nodes=hp.sub_nodes, r=r, blocks=dss.unpack(theta, 30, 10),
+                   tri=p.mesh.tri, xy=p.mesh.xy, dirichlet=p.mesh.dirichlet, order=np.argsort(-k, kind="stable"))
+    nproc = max(1, min(nproc, hp.K))
+    ctx = mp.get_context("fork")
+    bar = ctx.Barrier(nproc + 1)
+    out = ctx.Queue()
+    procs = [ctx.Process(target=_oracle_worker, args=(w, nproc, bar, out)) for w in range(nproc)]
+    for pr in procs:
+        pr.start()
+    try:
+        bar.wait(timeout=900)
+        t0 = time.perf_counter()
+        bar.wait(timeout=900)
+        t_local = time.perf_counter() - t0
+        loc = {}
+        for _ in range(nproc):
+            loc.update(out.get(timeout=900))
+    finally:
+        for pr in procs:
+            pr.join(timeout=60)
+        _ORACLE.clear()
     dec = dc.Decomposition(p.n, hp.sub_ptr, hp.sub_nodes, hp.weights)
     coarse = sw.Coarse(A, dec)
-    t0 = time.perf_counter()
-    for _ in range(3):
-        z = coarse(r)
+    with threadpoolctl.threadpool_limits(1):
+        t0 = time.perf_counter()
+        z = np.zeros(p.n)
+        for i in range(hp.K):
+            sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
+            z[hp.sub_nodes[sl]] += hp.weights[sl] * loc[i]
+        z += coarse(r)
+        z[p.mesh.dirichlet == 1] = 0.0
+        t_glue = time.perf_counter() - t0
+        t0 = time.perf_counter()
         q = A @ z
         _ = (z @ q, z @ r, np.linalg.norm(r))
         u = p.u0 + 0.5 * z
         r2 = r - 0.5 * q
-    t_rest = (time.perf_counter() - t0) / 3
-    per_solve = iterations * (t_local + t_rest)
-    info = threadpoolctl.threadpool_info()
-    threads = max([i.get("num_threads", 1) for i in info] + [1])
+        t_krylov = time.perf_counter() - t0
     del u, r2
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"DSS forward of {len(subs)} of {hp.K} sub-meshes ({k_sample} of {hp.sub_nodes.size} "
-                      f"slots) extrapolated by slot count, plus one coarse solve, SpMV and vector updates, "
-                      f"times the GPU solve's {iterations} iterations; {per_solve:.1f} s per solve"}
+    return {"local_s": t_local, "glue_coarse_s": t_glue, "krylov_s": t_krylov,
+            "apply_s": t_local + t_glue, "iteration_s": t_local + t_glue + t_krylov, "processes": nproc}
 
 
-_ORACLE = {}
-_LIMIT = []
-
-
-def _one_thread():
-    """Pool initializer: one BLAS thread per worker process (the processes are the cores)."""
-    import threadpoolctl
-    _LIMIT.append(threadpoolctl.threadpool_limits(1))
-
-
-def _oracle_local(i):
-    """DSS forward of sub-mesh i of the problem in _ORACLE (a pool worker's task)."""
-    from oracle import dss
-    o = _ORACLE
-    sl = slice(o["sub_ptr"][i], o["sub_ptr"][i + 1])
-    ri = o["r"][o["sub_nodes"][sl]]
-    s = np.linalg.norm(ri)
-    return i, s * dss.forward(o["blocks"], o["graphs"][i], ri / s, 1e-3, 10)
+def cpu_baseline(p, hp, theta, nproc: int) -> dict:
+    """The CPU oracle on the main workload: one whole iteration (the apply over all
+    sub-meshes on nproc processes, one thread each, then the SpMV and vector work),
+    timed before the GPU is touched; scaled to solves/s by the GPU solve's iteration
+    count once that is known."""
+    t = oracle_apply_parallel(p, hp, theta, nproc)
+    t["sample"] = (f"one oracle FCG iteration of the whole workload: DSS forward of all {hp.K} sub-meshes "
+                   f"({hp.sub_nodes.size} slots) on {t['processes']} processes (one BLAS thread each), then "
+                   f"gluing, coarse solve, SpMV, dots and updates in one process")
+    return t
 
 
 def oracle_small_cpu(theta, workers: int) -> dict:
     """c1 and c2: the oracle's preconditioner apply timed with one thread and with one
-    process per core over the sub-meshes. Runs before the GPU is touched (the worker
-    processes are forked from this one). Returns {name: (p, hp, timings)}."""
-    import multiprocessing as mp
-
+    process per core over the sub-meshes, before the GPU is touched.
+    Returns {name: (p, hp, timings)}."""
     import threadpoolctl
     import workload as W
     from oracle import decomp as dc, schwarz as sw
@@ -331,23 +428,10 @@ def oracle_small_cpu(theta, workers: int) -> dict:
             t0 = time.perf_counter()
             M(r)
             one = time.perf_counter() - t0
-        _ORACLE.update(sub_ptr=hp.sub_ptr, sub_nodes=hp.sub_nodes, r=r, blocks=M.blocks, graphs=M.graphs)
-        n_proc = min(workers, hp.K)
-        with mp.get_context("fork").Pool(n_proc, initializer=_one_thread) as pool:
-            pool.map(_oracle_local, range(min(hp.K, n_proc)))  # workers up
-            t0 = time.perf_counter()
-            loc = dict(pool.map(_oracle_local, range(hp.K), chunksize=max(1, hp.K // (4 * n_proc))))
-            z = np.zeros(p.n)
-            for i in range(hp.K):
-                sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
-                z[hp.sub_nodes[sl]] += hp.weights[sl] * loc[i]
-            z += M.coarse(r)
-            z[p.mesh.dirichlet == 1] = 0.0
-            allc = time.perf_counter() - t0
-        _ORACLE.clear()
-        log(f"{name}: oracle apply {one:.2f} s (1 thread), {allc:.2f} s ({n_proc} processes)")
-        out[name] = (p, hp, {"oracle_apply_s_1thread": one, "oracle_apply_s_allcore": allc,
-                             "oracle_processes": n_proc})
+        par = oracle_apply_parallel(p, hp, theta, workers)
+        log(f"{name}: oracle apply {one:.2f} s (1 thread), {par['apply_s']:.2f} s ({par['processes']} processes)")
+        out[name] = (p, hp, {"oracle_apply_s_1thread": one, "oracle_apply_s_allcore": par["apply_s"],
+                             "oracle_processes": par["processes"]})
     return out
 
 
@@ -400,6 +484,13 @@ def bench_batched(dg, ctx, model, items, opts, reps: int, sequential: bool, sche
            "converged": int(sum(1 for s in sts if s.converged)),
            "iterations_max": int(max(s.iterations for s in sts)),
            "iterations_mean": float(np.mean([s.iterations for s in sts]))}
+    # every member's solution checked on the host (scipy, FP64)
+    worst = 0.0
+    for (q, _), ub in zip(items, outs):
+        A = q.A.to_scipy()
+        ug = ub.cpu().numpy()
+        worst = max(worst, float(np.linalg.norm(q.b - A @ ug) / np.linalg.norm(q.b - A @ q.u0)))
+    res["max_host_rel_residual"] = worst
     if sequential:
         for pr, u in zip(probs, outs):  # warm (graph capture per problem)
             pr.solve(u, opts, check=False)
@@ -416,36 +507,62 @@ def bench_batched(dg, ctx, model, items, opts, reps: int, sequential: bool, sche
     return res
 
 
-def bench_serve(dg, model, stream, opts, budget: int) -> dict:
-    """Replays a stream of requests (arrival offsets in s) through the serving loop."""
+def bench_serve(dg, model, stream, opts, budget: int, check_solutions: bool = True) -> dict:
+    """Replays a stream of requests (arrival offsets in s) through the serving loop.
+
+    Latency is counted from each request's scheduled arrival: the server's own figure
+    (submission to completion) plus the time by which the submission call returned
+    after the scheduled arrival. Every returned solution is checked on the host: its
+    relative residual |b - A u| / |b - A u0| recomputed with scipy in FP64."""
+    import scipy.sparse as sp
     import torch
     sctx = dg.Context(torch.cuda.Stream())
     srv = dg.Server(sctx, model, hbm_budget=budget, max_active=64, setup_threads=8)
     t0 = time.perf_counter()
-    tickets = []
+    tickets, lags = [], []
     for t_arr, hp in stream:
         wait = t0 + t_arr - time.perf_counter()
         if wait > 0:
             time.sleep(wait)
         tickets.append(srv.submit(hp, opts))
+        lags.append(time.perf_counter() - (t0 + t_arr))
     srv.drain()
     makespan = time.perf_counter() - t0
-    lat, its, ok, status = [], [], 0, {}
-    for t in tickets:
-        rc, st, _ = srv.poll(t, with_solution=False)
-        lat.append(st.latency_ms)
+    lat, its, ok, status, stages, worst = [], [], 0, {}, {"setup": [], "queue": [], "upload": [], "solve": []}, 0.0
+    for t, lag, (_, hp) in zip(tickets, lags, stream):
+        rc, st, u = srv.poll(t, with_solution=check_solutions)
+        lat.append(st.latency_ms + 1e3 * lag)
         its.append(st.iterations)
         ok += int(rc == 0)
         name = dg.STATUS.get(rc, str(rc))
         status[name] = status.get(name, 0) + 1
+        stages["setup"].append(st.setup_ms)
+        stages["queue"].append(st.queue_ms)
+        stages["upload"].append(st.upload_ms)
+        stages["solve"].append(st.solve_ms)
+        if check_solutions and rc == 0:
+            A = sp.csr_matrix((hp.val, hp.col, hp.rowptr), shape=(hp.n, hp.n))
+            res = np.linalg.norm(hp.b - A @ u) / np.linalg.norm(hp.b - A @ hp.u0)
+            worst = max(worst, float(res))
     srv.close()
     sctx.close()
     nodes = sum(hp.n for _, hp in stream)
-    return {"requests": len(stream), "completed_ok": ok, "status": status, "makespan_s": makespan,
-            "solves_per_s": len(stream) / makespan, "offered_rate_per_s": len(stream) / max(stream[-1][0], 1e-9),
-            "nodes_total": int(nodes), "p50_latency_ms": float(np.percentile(lat, 50)),
-            "p99_latency_ms": float(np.percentile(lat, 99)), "max_latency_ms": float(np.max(lat)),
-            "iterations_mean": float(np.mean(its))}
+    offered = len(stream) / max(stream[-1][0], 1e-9)
+    served = len(stream) / makespan
+    out = {"requests": len(stream), "completed_ok": ok, "status": status, "makespan_s": makespan,
+           "solves_per_s": served, "offered_rate_per_s": offered, "nodes_total": int(nodes),
+           "nodes_per_s": nodes / makespan,
+           "p50_latency_ms": float(np.percentile(lat, 50)), "p99_latency_ms": float(np.percentile(lat, 99)),
+           "max_latency_ms": float(np.max(lat)), "iterations_mean": float(np.mean(its)),
+           "submit_lag_ms_max": 1e3 * float(np.max(lags)),
+           "stage_p50_ms": {k: float(np.percentile(v, 50)) for k, v in stages.items()},
+           "stage_p99_ms": {k: float(np.percentile(v, 99)) for k, v in stages.items()},
+           "latency": "scheduled arrival to completion",
+           "regime": "overloaded (served rate below the offered rate: the queue grows over the replay, so the "
+                     "percentiles depend on the stream length)" if served < 0.95 * offered else "stable"}
+    if check_solutions:
+        out["max_host_rel_residual"] = worst
+    return out
 
 
 def pmc_workload(args):
@@ -497,11 +614,15 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32", "fp64"])
     ap.add_argument("--m-max", type=int, default=4, help="directions kept by FCG (truncated flexible CG)")
     ap.add_argument("--theta", default="smoother", choices=["smoother", "xavier"])
-    ap.add_argument("--cpu-sample", type=int, default=160, help="sub-meshes in the oracle sample (0: skip)")
+    ap.add_argument("--cpu-baseline", type=int, default=1,
+                    help="time one oracle iteration of the main workload on --workers processes (0: skip)")
+    ap.add_argument("--direct", type=int, default=1,
+                    help="scipy direct solve of the main problem in a worker process, for the solution's L2 error (0: skip)")
     ap.add_argument("--batch8", type=int, default=8, help="copies of the main problem in one batch (0: skip)")
     ap.add_argument("--batch", type=int, default=64, help="problems of the 10k-200k batch (0: skip)")
-    ap.add_argument("--serve", type=int, default=40, help="requests of the stream prefix (0: skip)")
+    ap.add_argument("--serve", type=int, default=500, help="requests of the c5 stream (500: all; 0: skip)")
     ap.add_argument("--serve-slow-rate", type=float, default=6.0, help="arrival rate of the sustained replay (1/s)")
+    ap.add_argument("--serve-slow", type=int, default=150, help="requests of the sustained replay (0: skip)")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--lu-steps", type=int, default=1, help="timed DDM-LU solves of the main problem (0: skip)")
     ap.add_argument("--train-steps", type=int, default=5, help="timed training steps of DSS_theta (0: skip)")
@@ -541,9 +662,10 @@ def main():
         specs = W.stream_specs("c5", args.serve)
         made = generate([s[1:] for s in specs], args.workers)
         stream = [(s[0], hp_) for s, (_, hp_) in zip(specs, made)]
-        # the same requests at a rate one GPU sustains
-        slow = W.stream_specs("c5", args.serve, rate=args.serve_slow_rate)
-        stream_slow = [(s[0], hp_) for s, (_, hp_) in zip(slow, made)]
+        # the first requests again at a rate one GPU sustains
+        if args.serve_slow > 0:
+            slow = W.stream_specs("c5", min(args.serve_slow, args.serve), rate=args.serve_slow_rate)
+            stream_slow = [(s[0], hp_) for s, (_, hp_) in zip(slow, made)]
         log(f"stream c5: {len(stream)} requests, {sum(h.n for _, h in stream)} nodes over "
             f"{specs[-1][0]:.2f}s of arrivals ({time.perf_counter() - t:.1f}s)")
 
@@ -554,14 +676,20 @@ def main():
         theta_s = W.smoother_theta(omega=0.15, out_scale=1.7) if args.theta == "smoother" else \
             W.xavier_theta(W.THETA_SEED)
         small_cpu = oracle_small_cpu(theta_s, args.workers)
+    theta = W.smoother_theta(omega=0.15, out_scale=1.7) if args.theta == "smoother" else \
+        W.xavier_theta(W.THETA_SEED)
+    cpu_it = None
+    if args.cpu_baseline > 0:
+        log(f"{args.config}: one oracle iteration on {args.workers} processes")
+        cpu_it = cpu_baseline(p, hp, theta, args.workers)
+        log(f"{args.config}: oracle iteration {cpu_it['iteration_s']:.2f} s")
+    direct = DirectSolve(p) if args.direct > 0 else None  # scipy, in a forked worker, beside the GPU legs
 
     import torch
 
     import paper_2402_08296_amd as dg
     from paper_2402_08296_amd import profiling
 
-    theta = W.smoother_theta(omega=0.15, out_scale=1.7) if args.theta == "smoother" else \
-        W.xavier_theta(W.THETA_SEED)
     torch.cuda.set_device(0)
     ctx = dg.Context()
     model = dg.Model(ctx, theta)
@@ -597,6 +725,10 @@ def main():
             f"solve_ms={st.solve_ms:.1f}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    u_host = u.cpu().numpy()
+    A_host = p.A.to_scipy()
+    host_res = float(np.linalg.norm(p.b - A_host @ u_host) / np.linalg.norm(p.b - A_host @ p.u0))
+    log(f"solution: scipy relative residual {host_res:.3e}")
     # One more solve with HIP events around every stage (outside the timed steps).
     sp = prob.solve(u, popts, check=False)
     # The stages of one apply as the solve's graphs run them (two forked DSS launches
@@ -612,10 +744,20 @@ def main():
         dss_kernel += "+dss_mfma_kernel<512>"  # sub-meshes split over the two workgroup sizes
     n_it = max(1, sp.dss_launches)
     dss_avg_ms = g_local
-    dense, edge = dss_flops(30, 10, prob.sum_k, prob.n_edges)
-    flops = dense + edge
-    achieved = flops / (dss_avg_ms * 1e-3) / 1e12
-    peak = dss_peak_tflops(args.precision if sp.dss_kernel == 2 or args.precision != "bf16" else "fp32", dense, edge)
+    work = dss_work(30, 10, prob.sum_k, prob.n_edges)
+    run_prec = args.precision if sp.dss_kernel == 2 or args.precision != "bf16" else "fp32"
+    rl = dss_roofline(work, dss_avg_ms, dss_hbm_bytes(prob.sum_k, prob.n_edges), run_prec)
+    t_s = dss_avg_ms * 1e-3
+    if rl["binding"] == "mfma":
+        bound, achieved, peak, unit = "mfma", work["flops_mfma"] / t_s / 1e12, BF16_MFMA_TF, "TFLOP/s"
+    elif rl["binding"] == "valu":
+        f = work["flops_valu"] if run_prec == "bf16" else work["flops_valu"] + work["flops_mfma"]
+        peak = FP16_PACKED_TF if run_prec == "bf16" else (FP64_VALU_TF if run_prec == "fp64" else FP32_VALU_TF)
+        bound, achieved, unit = "alu", f / t_s / 1e12, "TFLOP/s"
+    elif rl["binding"] == "lds":
+        bound, achieved, peak, unit = "lds", work["lds_bytes"] / t_s / 1e9, LDS_TBPS * 1e3, "GB/s"
+    else:
+        bound, achieved, peak, unit = "hbm", dss_hbm_bytes(prob.sum_k, prob.n_edges) / t_s / 1e9, HBM_GBPS, "GB/s"
     apply_ms = g_local + g_coarse + g_glue
     abytes = apply_bytes(prob.n, prob.K, prob.sum_k, prob.n_edges, 8 if args.precision == "fp64" else 4)
     traffic = None
@@ -654,11 +796,15 @@ def main():
                                        "timing": "eager solve with events between stages"},
         "apply_stages_graph_ms": {"local": g_local, "coarse": g_coarse, "glue": g_glue,
                                   "timing": "each stage captured 20 times over in one HIP graph, mean per stage"},
-        "roofline": {"kernel": dss_kernel, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": traffic, "flops_per_launch": flops,
-                     "flops_dense": dense, "flops_edge": edge, "avg_launch_ms": dss_avg_ms,
+        "roofline": {"kernel": dss_kernel, "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                     "frac": achieved / peak, "traffic": traffic, **rl, **work,
+                     "avg_launch_ms": dss_avg_ms,
                      "avg_launch_timing": "DSS stage of one apply (both forked launches) in a replayed HIP graph",
+                     "algorithmic_hbm_bytes_per_launch": dss_hbm_bytes(prob.sum_k, prob.n_edges),
                      "algorithmic_bytes_per_apply": abytes},
+        "solution_check": {"host_rel_residual": host_res,
+                           "method": "u copied to the host after the timed solves; |b - A u| / |b - A u0| by scipy "
+                                     "in FP64"},
         "p99_latency_ms": None,
         "tuning": tuning,
     }
@@ -705,12 +851,22 @@ def main():
                                 m_max=args.m_max)
         out["serve_c5"] = bench_serve(dg, model, stream, sopts, 64 << 30)
         out["serve_c5"]["rate_per_s"] = W.STREAM_CONFIGS["c5"]["rate"]
-        out["serve_c5_sustained"] = bench_serve(dg, model, stream_slow, sopts, 64 << 30)
-        out["serve_c5_sustained"]["rate_per_s"] = args.serve_slow_rate
-        out["p99_latency_ms"] = out["serve_c5"]["p99_latency_ms"]
-    if args.cpu_sample > 0:
-        log("timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(p, hp, theta, iters, args.cpu_sample)
+        log(f"c5: {out['serve_c5']['solves_per_s']:.2f} solves/s served of {out['serve_c5']['offered_rate_per_s']:.2f} "
+            f"offered; p50 {out['serve_c5']['p50_latency_ms']:.0f} ms p99 {out['serve_c5']['p99_latency_ms']:.0f} ms")
+        if stream_slow:
+            out["serve_c5_sustained"] = bench_serve(dg, model, stream_slow, sopts, 64 << 30)
+            out["serve_c5_sustained"]["rate_per_s"] = args.serve_slow_rate
+        if len(stream) == W.STREAM_CONFIGS["c5"]["count"]:  # p99 of the configured stream only
+            out["p99_latency_ms"] = out["serve_c5"]["p99_latency_ms"]
+    if cpu_it is not None:
+        per_solve = iters * cpu_it["iteration_s"]
+        out["cpu_baseline"] = {"value": 1.0 / per_solve, "unit": "solves/s", "cores": cpu_it["processes"],
+                               "kind": "oracle",
+                               "sample": cpu_it["sample"] + f"; {cpu_it['iteration_s']:.2f} s per iteration x the "
+                                         f"GPU solve's {iters} iterations = {per_solve:.0f} s per solve",
+                               "iteration_s": cpu_it["iteration_s"], "local_s": cpu_it["local_s"],
+                               "glue_coarse_s": cpu_it["glue_coarse_s"], "krylov_s": cpu_it["krylov_s"],
+                               "threads_per_process": 1}
         if "train" in out:  # the oracle's training step beside the GPU's
             orc = oracle_train_per_sample(p, hp, [0, 1])
             out["cpu_baseline"]["train_step"] = orc
@@ -719,6 +875,12 @@ def main():
     if small_cpu:
         log("c1 and c2 on the GPU")
         out["oracle_c1_c2"] = gpu_small(dg, ctx, model, small_cpu)
+    if direct is not None:
+        log("waiting for the direct solve")
+        ud = direct.result()
+        out["solution_check"]["l2_vs_direct"] = float(np.linalg.norm(u_host - ud) / np.linalg.norm(ud))
+        out["solution_check"]["direct"] = "scipy.sparse.linalg.spsolve (SuperLU) in FP64 in a worker process"
+        log(f"solution: relative L2 distance to the direct solve {out['solution_check']['l2_vs_direct']:.3e}")
     print(json.dumps(out), flush=True)
 
 

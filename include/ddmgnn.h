@@ -199,6 +199,10 @@ typedef struct {
     int32_t status;            /* this problem's own status (DDMGNN_OK, E_MAXIT, E_BREAKDOWN, ...) */
     double latency_ms;         /* served requests: completion - submission (host clock);
                                 * solves: equal to solve_ms */
+    /* Served requests only (0 for solves), host clock: */
+    double setup_ms;           /* host setup (validation, local graphs, coarse operator) on a setup thread */
+    double queue_ms;           /* waiting: for a setup thread, then for admission */
+    double upload_ms;          /* admission: device buffers allocated and filled by the GPU thread */
 } ddmgnn_stats;
 
 /* Fill opts with defaults (FCG, m_max 1, rtol 1e-6, max_it 10000, FP32, POU, coarse on,

@@ -70,7 +70,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("iterations", _i32), ("converged", _i32), ("rel_residual", _f64),
                 ("true_rel_residual", _f64), ("solve_ms", _f64), ("dss_launches", _i32), ("dss_ms", _f64),
                 ("coarse_ms", _f64), ("prolong_ms", _f64), ("krylov_ms", _f64), ("dss_kernel", _i32),
-                ("status", _i32), ("latency_ms", _f64)]
+                ("status", _i32), ("latency_ms", _f64), ("setup_ms", _f64), ("queue_ms", _f64),
+                ("upload_ms", _f64)]
 
 
 _lib = None
@@ -163,14 +164,44 @@ def _np(a, dtype):
     return a, a.ctypes.data_as(_p)
 
 
-def _dev(t, dtype_name="float64"):
-    """Pointer of a contiguous torch device tensor of the given dtype."""
+def _shape_check(t, dtype_name="float64", n=None, what="tensor"):
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError("expected a torch device tensor")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what}: expected a torch tensor")
     if not t.is_contiguous() or str(t.dtype) != f"torch.{dtype_name}":
-        raise TypeError(f"expected a contiguous {dtype_name} tensor")
+        raise TypeError(f"{what}: expected a contiguous {dtype_name} tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{what}: expected {n} values, got {t.numel()}")
+
+
+def _dev(t, dtype_name="float64", n=None, what="tensor"):
+    """Pointer of a contiguous torch device tensor of the given dtype holding exactly
+    n values (n = None: any length). The C ABI takes bare pointers, so every length the
+    library will read or write is checked here, before the device is touched."""
+    _shape_check(t, dtype_name, n, what)
+    if not t.is_cuda:
+        raise TypeError(f"{what}: expected a torch device tensor")
     return _p(t.data_ptr())
+
+
+def _devs(*specs):
+    """_dev over several (tensor, dtype, n, what) at once: every length is checked
+    before any device check."""
+    for sp in specs:
+        _shape_check(*sp)
+    return [_dev(*sp) for sp in specs]
+
+
+def _disjoint(a, b, what: str):
+    """Raises when two tensors share memory (the ABI requires distinct buffers)."""
+    a0, b0 = a.data_ptr(), b.data_ptr()
+    if a0 < b0 + b.numel() * b.element_size() and b0 < a0 + a.numel() * a.element_size():
+        raise ValueError(f"{what} must not alias")
+
+
+def n_theta(kbar: int, d: int) -> int:
+    """Weights of DSS_theta with kbar blocks of latent width d (Table II: kbar (11 d^2 + 15 d + 1))."""
+    return kbar * (11 * d * d + 15 * d + 1)
 
 
 # ------------------------------------------------------------------ host-only helpers
@@ -225,6 +256,22 @@ class HostProblem:
         self.sub_ptr = np.ascontiguousarray(self.sub_ptr, np.int64)
         self.sub_nodes = np.ascontiguousarray(self.sub_nodes, np.int32)
         self.weights = np.ascontiguousarray(self.weights, np.float64)
+        n = self.xy.shape[0] if self.xy.ndim == 2 else -1
+        K = self.sub_ptr.size - 1
+        checks = [
+            (self.xy.ndim == 2 and self.xy.shape[1] == 2, "xy must be (N, 2)"),
+            (self.tri.size % 3 == 0 and self.tri.size > 0, "tri must hold 3 node ids per triangle"),
+            (self.dirichlet.size == n and self.b.size == n and self.u0.size == n,
+             "dirichlet, b and u0 must hold N values"),
+            (self.rowptr.size == n + 1, "a_rowptr must hold N + 1 values"),
+            (self.rowptr.size == n + 1 and self.col.size == self.val.size == int(self.rowptr[-1]),
+             "a_col and a_val must hold a_rowptr[N] values"),
+            (K >= 1 and self.sub_nodes.size == self.weights.size == int(self.sub_ptr[-1]),
+             "sub_nodes and weights must hold sub_ptr[K] values"),
+        ]
+        for ok, msg in checks:
+            if not ok:
+                raise ValueError(msg)
 
     @property
     def n(self) -> int:
@@ -342,7 +389,8 @@ class Context:
 
     def dot(self, x, y) -> float:
         out = _f64()
-        _check(lib().ddmgnn_dot(self.h, x.numel(), _dev(x), _dev(y), ctypes.byref(out)))
+        xp, yp = _devs((x, "float64", None, "x"), (y, "float64", x.numel(), "y"))
+        _check(lib().ddmgnn_dot(self.h, x.numel(), xp, yp, ctypes.byref(out)))
         return out.value
 
 
@@ -397,7 +445,8 @@ class Problem:
     def solve(self, u_out, opts: SolveOpts | None = None, check=True) -> Stats:
         o = opts or default_opts()
         st = Stats()
-        rc = lib().ddmgnn_solve(self.ctx.h, self.h, ctypes.byref(o), _dev(u_out), ctypes.byref(st))
+        rc = lib().ddmgnn_solve(self.ctx.h, self.h, ctypes.byref(o), _dev(u_out, n=self.n, what="u_out"),
+                                ctypes.byref(st))
         if check:
             _check(rc)
         return st
@@ -406,7 +455,9 @@ class Problem:
         """(local, coarse, glue) milliseconds of one apply, each stage replayed as a HIP graph."""
         o = opts or default_opts()
         a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        _check(lib().ddmgnn_time_apply_stages(self.ctx.h, self.h, ctypes.byref(o), _dev(r), _dev(z), reps,
+        rp, zp = _devs((r, "float64", self.n, "r"), (z, "float64", self.n, "z"))
+        _disjoint(r, z, "r and z")
+        _check(lib().ddmgnn_time_apply_stages(self.ctx.h, self.h, ctypes.byref(o), rp, zp, reps,
                                               ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
 
@@ -435,7 +486,9 @@ class Problem:
 
     def apply(self, r, z, opts: SolveOpts | None = None):
         o = opts or default_opts()
-        _check(lib().ddmgnn_precond_apply(self.ctx.h, self.h, ctypes.byref(o), _dev(r), _dev(z)))
+        rp, zp = _devs((r, "float64", self.n, "r"), (z, "float64", self.n, "z"))
+        _disjoint(r, z, "r and z")
+        _check(lib().ddmgnn_precond_apply(self.ctx.h, self.h, ctypes.byref(o), rp, zp))
 
     def intermediates(self):
         import torch
@@ -450,21 +503,29 @@ class Problem:
     def dss_forward(self, c, out, precision=FP32):
         if isinstance(precision, str):
             precision = PRECISION[precision]
-        _check(lib().ddmgnn_dss_forward(self.ctx.h, self.h, precision, _dev(c), _dev(out)))
+        cp, op = _devs((c, "float64", self.sum_k, "c"), (out, "float64", self.sum_k, "out"))
+        _check(lib().ddmgnn_dss_forward(self.ctx.h, self.h, precision, cp, op))
 
     def dss_forward_sub(self, sub: int, c, out, precision=FP32):
         """DSS forward of sub-mesh `sub` alone (c, out: its k_sub values)."""
         if isinstance(precision, str):
             precision = PRECISION[precision]
-        _check(lib().ddmgnn_dss_forward_sub(self.ctx.h, self.h, precision, sub, _dev(c), _dev(out)))
+        if not 0 <= sub < self.K:
+            raise ValueError(f"sub-mesh {sub} out of range [0, {self.K})")
+        k = int(self.hp.sub_ptr[sub + 1] - self.hp.sub_ptr[sub])
+        cp, op = _devs((c, "float64", k, "c"), (out, "float64", k, "out"))
+        _check(lib().ddmgnn_dss_forward_sub(self.ctx.h, self.h, precision, sub, cp, op))
 
     def spmv(self, x, y):
-        _check(lib().ddmgnn_spmv(self.ctx.h, self.h, _dev(x), _dev(y)))
+        xp, yp = _devs((x, "float64", self.n, "x"), (y, "float64", self.n, "y"))
+        _disjoint(x, y, "x and y")
+        _check(lib().ddmgnn_spmv(self.ctx.h, self.h, xp, yp))
 
     # ---- training of DSS_theta
     def train_rhs(self, u, c_out):
         """c_out (device float32, sum_k values) = R_i r / |R_i r| per sub-mesh, r = b - A u."""
-        _check(lib().ddmgnn_train_rhs(self.ctx.h, self.h, _dev(u), _dev(c_out, "float32")))
+        up, cp = _devs((u, "float64", self.n, "u"), (c_out, "float32", self.sum_k, "c_out"))
+        _check(lib().ddmgnn_train_rhs(self.ctx.h, self.h, up, cp))
 
     def train_grad(self, theta, subs, c, c_off, grad, kbar: int = 30, d: int = 10, alpha: float = 1e-3,
                    scale: float | None = None):
@@ -474,15 +535,23 @@ class Problem:
         offs = np.ascontiguousarray(c_off, np.int64)
         if subs.shape != offs.shape:
             raise ValueError("subs and c_off differ in length")
-        if scale is None:  # out-of-range indices are left to the library to reject
-            ptr = self.hp.sub_ptr
-            nodes = sum(int(ptr[i + 1] - ptr[i]) for i in subs if 0 <= i < self.K)
+        ptr = self.hp.sub_ptr
+        if subs.size and (subs.min() < 0 or subs.max() >= self.K):
+            raise ValueError(f"sub-mesh index out of range [0, {self.K})")
+        ks = (ptr[subs + 1] - ptr[subs]) if subs.size else np.zeros(0, np.int64)
+        if offs.size and (offs.min() < 0 or int((offs + ks).max()) > c.numel()):
+            raise ValueError("a sample's right-hand side c[c_off : c_off + k_i] lies outside c")
+        if scale is None:
+            nodes = int(ks.sum())
             scale = 1.0 / nodes if nodes else 1.0
+        nt = n_theta(kbar, d)
         desc = ModelDesc(kbar, d, alpha)
         loss, gn = _f64(), _f64()
-        _check(lib().ddmgnn_train_grad(self.ctx.h, self.h, ctypes.byref(desc), _dev(theta, "float32"),
-                                       subs.ctypes.data_as(ctypes.POINTER(_i32)), subs.size, _dev(c, "float32"),
-                                       offs.ctypes.data_as(ctypes.POINTER(_i64)), scale, _dev(grad, "float32"),
+        tp, cp, gp = _devs((theta, "float32", nt, "theta"), (c, "float32", None, "c"),
+                           (grad, "float32", nt, "grad"))
+        _check(lib().ddmgnn_train_grad(self.ctx.h, self.h, ctypes.byref(desc), tp,
+                                       subs.ctypes.data_as(ctypes.POINTER(_i32)), subs.size, cp,
+                                       offs.ctypes.data_as(ctypes.POINTER(_i64)), scale, gp,
                                        ctypes.byref(loss), ctypes.byref(gn)))
         return loss.value, gn.value
 
@@ -490,8 +559,10 @@ class Problem:
 def adam_step(ctx: Context, theta, grad, m, v, gnorm: float, t: int, lr: float = 1e-2, beta1: float = 0.9,
               beta2: float = 0.999, eps: float = 1e-8, clip: float = 1e-2):
     """One Adam step on device float32 tensors (gradient clipped to norm `clip`)."""
-    _check(lib().ddmgnn_adam_step(ctx.h, _dev(theta, "float32"), _dev(grad, "float32"), _dev(m, "float32"),
-                                  _dev(v, "float32"), theta.numel(), gnorm, t, lr, beta1, beta2, eps, clip))
+    n = theta.numel()
+    ptrs = _devs((theta, "float32", None, "theta"), (grad, "float32", n, "grad"), (m, "float32", n, "m"),
+                 (v, "float32", n, "v"))
+    _check(lib().ddmgnn_adam_step(ctx.h, *ptrs, n, gnorm, t, lr, beta1, beta2, eps, clip))
 
 
 def solve_batch(ctx: Context, problems, u_outs, opts: SolveOpts | None = None, check=True):
@@ -499,7 +570,9 @@ def solve_batch(ctx: Context, problems, u_outs, opts: SolveOpts | None = None, c
     o = opts or default_opts()
     n = len(problems)
     hs = (_p * n)(*[p.h for p in problems])
-    outs = (_p * n)(*[_dev(u) for u in u_outs])
+    if len(u_outs) != n:
+        raise ValueError("one output vector per problem")
+    outs = (_p * n)(*_devs(*[(u, "float64", p.n, f"u_outs[{i}]") for i, (p, u) in enumerate(zip(problems, u_outs))]))
     st = (Stats * n)()
     rc = lib().ddmgnn_solve_batch(ctx.h, hs, n, ctypes.byref(o), outs, st)
     if check:

@@ -109,7 +109,6 @@ struct DevProb {
     double* gm_part;            // (restart + 1) x VEC_GRID partial sums of the Gram passes
     double* gm_small;           // H [(restart + 1) x restart, column j at j * (restart + 1)],
                                 // cs, sn [restart], g [restart + 1], y [restart], tmp [restart + 1]
-    unsigned* counter;          // unused by the solve kernels (kept zero)
     double rtol;                // read by the init kernel
     int max_it;
     int n;
@@ -159,10 +158,13 @@ hipError_t launch_krylov(const DevProb* tab, const int2* blk, int n_blk, int n_p
 hipError_t launch_init(const DevProb* tab, const int2* blk, int n_blk, const int* list, int n_list, hipStream_t s);
 hipError_t launch_resid(const DevProb* tab, const int2* blk, int n_blk, const int* list, int n_list, hipStream_t s);
 hipError_t launch_gather_states(const DevProb* tab, int n, KState* out, hipStream_t s);
+// Entry points: y = A x with the solve's grouped SpMV over nblk workgroups, and
+// *out = x.y (device) with the solve's two-kernel reduction (partials: VEC_GRID
+// doubles of scratch); n < 2^31.
 hipError_t launch_spmv(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, double* y,
-                       int n, hipStream_t s);
-hipError_t launch_dot(const double* x, const double* y, int64_t n, double* partials, unsigned* counter, double* out,
-                      hipStream_t s);
+                       int n, int nblk, hipStream_t s);
+hipError_t launch_dot(const double* x, const double* y, int n, double* partials, double* out, hipStream_t s,
+                      bool check);
 
 // Training of DSS_theta (train.hip): one TRAIN_BLOCK-thread workgroup per local
 // problem; TRAIN_NWB weights per block (d = D).

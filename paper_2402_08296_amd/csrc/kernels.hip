@@ -13,9 +13,10 @@
 //                   w_i(n) s_i r~_i(n) + D_i(n) y_i; z = 0 at Dirichlet nodes
 //                   (step 3), fused with the Krylov dot products that need z.
 // The Krylov iteration adds the direction update with the SpMV and its dots,
-// and the solution update with the convergence test. Scalar recurrences
-// (alpha, beta, the test) run on the device in the last workgroup of the
-// kernel that completes a reduction, so the host only polls a flag.
+// and the solution update with the convergence test. Every reduction writes
+// one partial sum per workgroup; a finalize kernel with one workgroup per
+// problem sums them in workgroup order and advances the scalar recurrences
+// (alpha, beta, the test) on the device, so the host only polls a flag.
 #include <hip/hip_runtime.h>
 
 #include "ddmgnn.h"
@@ -87,38 +88,6 @@ __device__ inline void block_sum_n(double (&v)[NV], double* sh) {
         v[i] = acc;
     }
     __syncthreads();
-}
-
-// Sums NV values over the nb workgroups of one problem (this one is local
-// workgroup lb). Returns true in the last of them to finish, where out[]
-// holds the totals (valid in every thread of that workgroup). Each workgroup
-// publishes its partial sums, then takes a ticket from the problem's counter
-// (release fence before, so the partials are visible to whoever draws the
-// last ticket); the last one reads all partials after an acquire fence, with
-// ordinary loads that can all be in flight at once.
-template <int NV, int BLOCK>
-__device__ bool grid_sum(const double (&v)[NV], double* partials, unsigned* counter, int lb, int nb,
-                         double (&out)[NV], double* /*unused*/) {
-    __shared__ double sh[NV * (BLOCK / 64)];
-    __shared__ int is_last;
-    double bs[NV];
-    for (int i = 0; i < NV; ++i) bs[i] = v[i];
-    block_sum_n<NV, BLOCK>(bs, sh);
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < NV; ++i) partials[i * VEC_GRID + lb] = bs[i];
-        __threadfence();
-        const unsigned t = atomicAdd(counter, 1u);
-        is_last = (t == (unsigned)nb - 1);
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    for (int i = 0; i < NV; ++i) out[i] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += BLOCK)
-        for (int i = 0; i < NV; ++i) out[i] += partials[i * VEC_GRID + b];
-    block_sum_n<NV, BLOCK>(out, sh);
-    if (threadIdx.x == 0) *counter = 0u;
-    return true;
 }
 
 // Two-kernel reductions of the Krylov iteration: every workgroup of a large
@@ -1164,27 +1133,34 @@ __global__ __launch_bounds__(VEC_BLOCK) void finalize_kernel(const DevProb* __re
     }
 }
 
-// Plain y = A x and a deterministic dot (entry points outside the solve).
+// Entry points outside the solve run the solver's own code: y = A x with the
+// grouped CSR SpMV over nblk workgroups, and x.y with the two-kernel
+// reduction (per-workgroup partials over the row groups of rows_of, then one
+// workgroup sums them in workgroup order).
 __global__ __launch_bounds__(VEC_BLOCK) void spmv_kernel(const int32_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ col,
                                                         const double* __restrict__ val, const double* __restrict__ x,
-                                                        double* __restrict__ y, int n) {
-    for (int i = blockIdx.x * VEC_BLOCK + threadIdx.x; i < n; i += gridDim.x * VEC_BLOCK) {
-        double acc = 0.0;
-        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) acc = fma(val[e], x[col[e]], acc);
-        y[i] = acc;
-    }
+                                                        double* __restrict__ y, int n, int nblk) {
+    spmv_groups(rowptr, col, val, n, blockIdx.x, nblk, [&](int c) { return x[c]; },
+                [&](int i, double acc) { y[i] = acc; });
 }
 
-__global__ __launch_bounds__(VEC_BLOCK) void dot_kernel(const double* __restrict__ x, const double* __restrict__ y,
-                                                       int64_t n, double* partials, unsigned* counter,
-                                                       double* out) {
-    __shared__ double sh[VEC_BLOCK / 64 + 1];
+__global__ __launch_bounds__(VEC_BLOCK) void dot_part_kernel(const double* __restrict__ x,
+                                                            const double* __restrict__ y, int n, int nblk,
+                                                            double* __restrict__ partials) {
     double d[1] = {0.0};
-    for (int64_t i = blockIdx.x * (int64_t)VEC_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * VEC_BLOCK)
-        d[0] = fma(x[i], y[i], d[0]);
+    const Rows rg = rows_of(blockIdx.x, nblk, n);
+    for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
+        const int i = gi * VEC_BLOCK + threadIdx.x;
+        if (i < n) d[0] = fma(x[i], y[i], d[0]);
+    }
+    put_partials<1>(d, partials, blockIdx.x);
+}
+
+__global__ __launch_bounds__(VEC_BLOCK) void dot_fin_kernel(const double* __restrict__ partials, int nblk,
+                                                           double* __restrict__ out) {
     double tot[1];
-    if (!grid_sum<1, VEC_BLOCK>(d, partials, counter, blockIdx.x, gridDim.x, tot, sh)) return;
+    sum_partials<1>(partials, nblk, tot);
     if (threadIdx.x == 0) *out = tot[0];
 }
 
@@ -1335,15 +1311,17 @@ hipError_t launch_gather_states(const DevProb* tab, int n, KState* out, hipStrea
 }
 
 hipError_t launch_spmv(const int32_t* rowptr, const int32_t* col, const double* val, const double* x, double* y,
-                       int n, hipStream_t s) {
-    hipLaunchKernelGGL(spmv_kernel, dim3(vec_blocks(n)), dim3(VEC_BLOCK), 0, s, rowptr, col, val, x, y, n);
+                       int n, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL(spmv_kernel, dim3(nblk), dim3(VEC_BLOCK), 0, s, rowptr, col, val, x, y, n, nblk);
     return hipGetLastError();
 }
 
-hipError_t launch_dot(const double* x, const double* y, int64_t n, double* partials, unsigned* counter, double* out,
-                      hipStream_t s) {
-    hipLaunchKernelGGL(dot_kernel, dim3(vec_blocks(n)), dim3(VEC_BLOCK), 0, s, x, y, n, partials, counter, out);
-    return hipGetLastError();
+hipError_t launch_dot(const double* x, const double* y, int n, double* partials, double* out, hipStream_t s,
+                      bool check) {
+    const int nblk = vec_blocks(n);
+    hipLaunchKernelGGL(dot_part_kernel, dim3(nblk), dim3(VEC_BLOCK), 0, s, x, y, n, nblk, partials);
+    hipLaunchKernelGGL(dot_fin_kernel, dim3(1), dim3(VEC_BLOCK), 0, s, partials, nblk, out);
+    return done(check);
 }
 
 }  // namespace ddmgnn

@@ -82,7 +82,6 @@ DevProb make_view(ddmgnn_problem* P) {
     v.qg64 = P->qglobal64.p; v.hg64 = P->hglobal64.p; v.qg32 = P->qglobal32.p;
     v.st = P->st.p;
     v.partials = P->partials.p;
-    v.counter = P->counters.p;
     v.rtol = P->rtol;
     v.max_it = P->max_it;
     v.n = (int)n;
@@ -896,8 +895,6 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
     HIP_TRY(P->ring.alloc((size_t)2 * (MAX_M + 1) * n));
     HIP_TRY(P->st.alloc(1));
     HIP_TRY(P->partials.alloc((size_t)(MAX_M + 1) * VEC_GRID));
-    HIP_TRY(P->counters.alloc(4));
-    HIP_TRY(hipMemsetAsync(P->counters.p, 0, 4 * sizeof(unsigned), s));
     HIP_TRY(hipMemsetAsync(P->st.p, 0, sizeof(KState), s));
     HIP_TRY(hipStreamSynchronize(s));
     P->device_bytes = problem_device_bytes(n, hs.nnz, K, sk, hs.n_edges) + P->lu_inv.n * sizeof(double) +
@@ -966,8 +963,6 @@ int ddmgnn_ctx_create(void* hip_stream, ddmgnn_ctx** out) {
     HIP_TRY(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
     HIP_TRY(c->partials.alloc(VEC_GRID));
-    HIP_TRY(c->counters.alloc(4));
-    HIP_TRY(hipMemset(c->counters.p, 0, 4 * sizeof(unsigned)));
     HIP_TRY(c->scalar.alloc(1));
     HIP_TRY(hipHostMalloc((void**)&c->host_pinned, 256, hipHostMallocDefault));
     *out = c.release();
@@ -1232,18 +1227,18 @@ int ddmgnn_setup_local_inverse(const ddmgnn_problem_desc* desc_in, int32_t sub, 
 
 int ddmgnn_spmv(ddmgnn_ctx* ctx, ddmgnn_problem* P, const double* x, double* y) {
     if (!ctx || !P || !x || !y) return fail(DDMGNN_E_INVALID, "null argument");
-    HIP_TRY(launch_spmv(P->rowptr.p, P->col.p, P->val.p, x, y, (int)P->hs.n, ctx->stream));
+    HIP_TRY(launch_spmv(P->rowptr.p, P->col.p, P->val.p, x, y, (int)P->hs.n, problem_vec_blocks(P), ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return DDMGNN_OK;
 }
 
 int ddmgnn_dot(ddmgnn_ctx* ctx, int64_t n, const double* x, const double* y, double* out) {
-    if (!ctx || !out || n < 0 || (n > 0 && (!x || !y))) return fail(DDMGNN_E_INVALID, "invalid argument");
+    if (!ctx || !out || n < 0 || n > INT32_MAX || (n > 0 && (!x || !y))) return fail(DDMGNN_E_INVALID, "invalid argument");
     if (n == 0) {
         *out = 0.0;
         return DDMGNN_OK;
     }
-    HIP_TRY(launch_dot(x, y, n, ctx->partials.p, ctx->counters.p, ctx->scalar.p, ctx->stream));
+    HIP_TRY(launch_dot(x, y, (int)n, ctx->partials.p, ctx->scalar.p, ctx->stream, true));
     HIP_TRY(hipMemcpyAsync(ctx->host_pinned, ctx->scalar.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     *out = ctx->host_pinned[0];

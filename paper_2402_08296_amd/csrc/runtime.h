@@ -130,7 +130,6 @@ struct ddmgnn_ctx {
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     int device = 0;
     ddmgnn::DevBuf<double> partials;
-    ddmgnn::DevBuf<unsigned> counters;
     ddmgnn::DevBuf<double> scalar;
     double* host_pinned = nullptr;
     ddmgnn::BatchPtr last_batch;  // batch of the last multi-problem solve
@@ -192,7 +191,6 @@ struct ddmgnn_problem {
     ddmgnn::DevBuf<double> ring;     // (MAX_M + 1) p vectors then (MAX_M + 1) q vectors
     ddmgnn::DevBuf<ddmgnn::KState> st;
     ddmgnn::DevBuf<double> partials;
-    ddmgnn::DevBuf<unsigned> counters;
     double rtol = 1e-6;              // of the current solve (read by the init kernel)
     int max_it = 0;
     ddmgnn::BatchPtr solo;  // batch of this problem alone

@@ -43,7 +43,7 @@ struct Request {
     int setup_rc = DDMGNN_OK;
     std::string err;
     size_t bytes = 0;
-    Clock::time_point t_submit, t_admit, t_done;
+    Clock::time_point t_submit, t_setup0, t_setup1, t_admit, t_created, t_done;
     ddmgnn_problem* prob = nullptr;
     bool fresh = false;  // admitted, not initialised yet
     // result
@@ -135,6 +135,10 @@ void ddmgnn_server::finish(Request* r) {
     r->t_done = Clock::now();
     r->stats.latency_ms = ms_between(r->t_submit, r->t_done);
     r->stats.status = r->status;
+    const Clock::time_point admitted = r->t_admit == Clock::time_point() ? r->t_done : r->t_admit;
+    r->stats.setup_ms = ms_between(r->t_setup0, r->t_setup1);
+    r->stats.queue_ms = ms_between(r->t_submit, r->t_setup0) + ms_between(r->t_setup1, admitted);
+    r->stats.upload_ms = r->t_created == Clock::time_point() ? 0.0 : ms_between(r->t_admit, r->t_created);
     std::lock_guard<std::mutex> lk(mu);
     finished[r->ticket] = r;
     --in_flight;
@@ -151,6 +155,7 @@ void ddmgnn_server::setup_worker() {
             r = pending.front();
             pending.pop_front();
         }
+        r->t_setup0 = Clock::now();
         std::string e = validate(r->desc);
         if (e.empty()) e = build_setup(r->desc, r->hs);
         const bool lu = r->opts.local_solver == DDMGNN_LOCAL_LU && r->opts.krylov != DDMGNN_CG;
@@ -168,6 +173,7 @@ void ddmgnn_server::setup_worker() {
                        r->hs.lu_inv.size() * sizeof(double) + r->hs.lu_off.size() * sizeof(int64_t) +
                        (r->opts.krylov == DDMGNN_FGMRES ? fgmres_bytes(r->hs.n, r->opts.restart) : 0);
         }
+        r->t_setup1 = Clock::now();
         std::lock_guard<std::mutex> lk(mu);
         ready[r->ticket] = r;
         cv.notify_all();
@@ -229,6 +235,7 @@ void ddmgnn_server::gpu_loop() {
             r->t_admit = Clock::now();
             ddmgnn_problem* P = nullptr;
             const int rc = create_problem(ctx, r->desc, model, std::move(r->hs), &P);
+            r->t_created = Clock::now();
             r->hs = HostSetup();
             if (rc) {
                 r->status = rc;

@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 
 import paper_2402_08296_amd as dg  # noqa: E402
 import workload as W  # noqa: E402
-from tests._cases import host_problem  # noqa: E402
+from tests._cases import oracle_problem  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def mix():
     out = []
     for seed, n, parts in SPECS:
         p = W.make_problem(seed, n, parts, 0.2)
-        out.append((p, host_problem(p)))
+        out.append((p, oracle_problem(p)))
     return out
 
 
@@ -63,6 +63,16 @@ def test_batch_equals_solo(ctx, mix, prec):
             assert status == 0 and st.status == 0 and st.converged
             assert st.iterations == it
             assert np.array_equal(ub.cpu().numpy(), u), (rep, i)
+    # each member's solution checked outside the library: scipy residual and direct solve
+    import scipy.sparse.linalg as spl
+    for (p, _), ub in zip(mix, outs):
+        A = p.A.to_scipy()
+        ug = ub.cpu().numpy()
+        res = np.linalg.norm(p.b - A @ ug) / np.linalg.norm(p.b - A @ p.u0)
+        ud = spl.spsolve(A.tocsc(), p.b)
+        err = np.linalg.norm(ug - ud) / np.linalg.norm(ud)
+        print(f"[gpu]   N={p.n}: scipy residual {res:.2e}, L2 vs direct {err:.2e}", flush=True)
+        assert res <= 1e-6 and err <= 1e-4
 
 
 def test_batch_lu_equals_solo(ctx, mix):

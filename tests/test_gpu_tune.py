@@ -13,7 +13,7 @@ torch = pytest.importorskip("torch")
 
 import paper_2402_08296_amd as dg  # noqa: E402
 import workload as W  # noqa: E402
-from tests._cases import host_problem  # noqa: E402
+from tests._cases import oracle_problem  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +30,7 @@ def ctx():
 def mixed():
     # sub-meshes of uneven size: some fit two workgroups per compute unit, some do not
     p = W.make_problem(31, 12000, 18, 0.45)  # sub-meshes of 470..1613 nodes
-    return p, host_problem(p)
+    return p, oracle_problem(p)
 
 
 def _dev(a):
@@ -95,7 +95,7 @@ def test_forked_schedule_in_batches_and_stage_timing(ctx, mixed):
     print("[gpu] forked schedule in a batch / stage timing", flush=True)
     p, hp = mixed
     q = W.make_problem(32, 9000, 14, 0.45)
-    hq = host_problem(q)
+    hq = oracle_problem(q)
     model = dg.Model(ctx, SMOOTHER)
     o = dg.default_opts(precision="bf16", rtol=1e-6)
     solo = []

@@ -342,6 +342,39 @@ def test_ddmlu_unweighted_symmetric_positive_definite():
     assert np.linalg.eigvalsh(0.5 * (Md + Md.T)).min() > 0
 
 
+def test_ddmlu_both_glues_match_elementwise_construction():
+    """eq. (7) written out with explicit matrices: R_i as a 0/1 matrix, A_i = R_i A R_i^T,
+    the local solve by a general dense solve, D_i as a diagonal, the Nicolaides Z
+    element by element; z = sum_i R_i^T W_i A_i^{-1} R_i r + Z A_0^{-1} Z^T r with
+    W_i = D_i (partition of unity) or I (the paper's glue), zero at Dirichlet nodes."""
+    p = W.make_problem(12, 500, 3)
+    dec = dc.decompose(p.n, p.mesh.tri, p.mesh.dirichlet, p.part, p.n_parts, 2)
+    A = p.A.to_scipy().toarray()
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(p.n)
+    r[p.mesh.dirichlet == 1] = 0.0
+    Z = np.zeros((p.n, dec.K))
+    for i in range(dec.K):
+        for node, w in zip(dec.nodes(i), dec.w(i)):
+            Z[node, i] = w
+    rc = Z @ np.linalg.solve(Z.T @ A @ Z, Z.T @ r)
+    for prolong in ("pou", "unweighted"):
+        expect = rc.copy()
+        for i in range(dec.K):
+            nodes = dec.nodes(i)
+            R = np.zeros((nodes.size, p.n))
+            R[np.arange(nodes.size), nodes] = 1.0
+            Wi = np.diag(dec.w(i)) if prolong == "pou" else np.eye(nodes.size)
+            expect += R.T @ (Wi @ np.linalg.solve(R @ A @ R.T, R @ r))
+        expect[p.mesh.dirichlet == 1] = 0.0
+        z = sw.DDMLU(p.A.to_scipy(), p.mesh.dirichlet, dec, prolong=prolong)(r)
+        assert np.abs(z - expect).max() <= 1e-11 * np.abs(expect).max(), prolong
+    # the two glues differ wherever sub-meshes overlap (the pin sees the weights)
+    zp = sw.DDMLU(p.A.to_scipy(), p.mesh.dirichlet, dec, prolong="pou")(r)
+    zu = sw.DDMLU(p.A.to_scipy(), p.mesh.dirichlet, dec, prolong="unweighted")(r)
+    assert np.abs(zp - zu).max() > 1e-3 * np.abs(zu).max()
+
+
 def test_ddmlu_single_subdomain_is_exact_inverse():
     p = W.make_problem(8, 900, 1)
     dec = dc.decompose(p.n, p.mesh.tri, p.mesh.dirichlet, p.part, 1, 0)
