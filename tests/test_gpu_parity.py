@@ -461,7 +461,7 @@ def test_dss_forward_sub_matches_full(ctx, c1, prec):
         one = torch.empty(sl.stop - sl.start, dtype=torch.float64, device="cuda")
         prob.dss_forward_sub(i, _dev(c[sl]), one, prec)
         assert torch.equal(one, full[sl])
-    with pytest.raises(dg.DDMGNNError):
+    with pytest.raises((dg.DDMGNNError, ValueError)):
         prob.dss_forward_sub(hp.K, _dev(c[:10]), one, prec)
 
 

@@ -152,11 +152,11 @@ def test_invalid_training_arguments(setup):
     tdev = torch.zeros(dss.n_weights(2, 10), dtype=torch.float32, device="cuda")
     grad = torch.empty_like(tdev)
     c = torch.zeros(4096, dtype=torch.float32, device="cuda")
-    with pytest.raises(dg.DDMGNNError):
+    with pytest.raises((dg.DDMGNNError, ValueError)):
         prob.train_grad(tdev, [hp.K], c, [0], grad, kbar=2)
-    with pytest.raises(dg.DDMGNNError):
+    with pytest.raises((dg.DDMGNNError, ValueError)):
         prob.train_grad(tdev, [0], c, [-1], grad, kbar=2)
-    with pytest.raises(dg.DDMGNNError):
+    with pytest.raises((dg.DDMGNNError, ValueError)):
         prob.train_grad(torch.zeros(10 * 2 * 5, dtype=torch.float32, device="cuda"), [0], c, [0],
                         torch.zeros(100, dtype=torch.float32, device="cuda"), kbar=2, d=5)
 
