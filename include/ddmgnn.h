@@ -359,6 +359,21 @@ int ddmgnn_spmv(ddmgnn_ctx* ctx, ddmgnn_problem* prob, const double* x, double* 
  * reductions of Algorithm 1); result written to *out (host). */
 int ddmgnn_dot(ddmgnn_ctx* ctx, int64_t n, const double* x, const double* y, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): ddmgnn_dot without any
+ * allocation. It runs the same two kernels (so the result equals ddmgnn_dot's
+ * bit for bit) with their per-workgroup partial sums in a static device array of
+ * 1024 doubles (8 KiB per device, held until the process ends; its address is
+ * looked up when the device's first context is created). x, y: device, n
+ * doubles; out: DEVICE pointer to one double, written asynchronously on the
+ * context's stream (no synchronisation, so the call can be captured). n = 0
+ * writes 0. n above DDMGNN_NOALLOC_DOT_MAX_N: E_INVALID. Calls no hipMalloc,
+ * hipFree or allocating routine. Every call on one device shares that array:
+ * calls that overlap on one GPU (several streams or threads) race, and must be
+ * serialised by the caller. */
+#define DDMGNN_NOALLOC_DOT_MAX_N 2147483647LL
+int ddmgnn_dot_noalloc(ddmgnn_ctx* ctx, int64_t n, const double* x, const double* y, double* out);
+
 /* ---- host-only helpers (no device needed) ---- */
 
 /* Overlapping sub-meshes: part i grown by `delta` layers of mesh adjacency

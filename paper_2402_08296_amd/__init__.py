@@ -128,6 +128,7 @@ def lib():
         "ddmgnn_dss_forward": (ctypes.c_int, [_p, _p, _i32, _p, _p]),
         "ddmgnn_spmv": (ctypes.c_int, [_p, _p, _p, _p]),
         "ddmgnn_dot": (ctypes.c_int, [_p, _i64, _p, _p, ctypes.POINTER(_f64)]),
+        "ddmgnn_dot_noalloc": (ctypes.c_int, [_p, _i64, _p, _p, _p]),
         "ddmgnn_expand_overlap": (ctypes.c_int, [_i64, _i64, _p, _p, _i32, _i32, ctypes.POINTER(_p),
                                                  ctypes.POINTER(_p)]),
         "ddmgnn_pou_weights": (ctypes.c_int, [_i64, _p, _i32, _p, _p, _p]),
@@ -392,6 +393,12 @@ class Context:
         xp, yp = _devs((x, "float64", None, "x"), (y, "float64", x.numel(), "y"))
         _check(lib().ddmgnn_dot(self.h, x.numel(), xp, yp, ctypes.byref(out)))
         return out.value
+
+    def dot_noalloc(self, x, y, out):
+        """x . y into the one-double device tensor out, asynchronously on the
+        context's stream, with no device allocation (ddmgnn_dot_noalloc)."""
+        xp, yp, op = _devs((x, "float64", None, "x"), (y, "float64", x.numel(), "y"), (out, "float64", 1, "out"))
+        _check(lib().ddmgnn_dot_noalloc(self.h, x.numel(), xp, yp, op))
 
 
 class Model:

@@ -166,6 +166,14 @@ hipError_t launch_spmv(const int32_t* rowptr, const int32_t* col, const double* 
 hipError_t launch_dot(const double* x, const double* y, int n, double* partials, double* out, hipStream_t s,
                       bool check);
 
+// Allocation-free entry points (noalloc.hip): a static device array of
+// NOALLOC_SCRATCH_DOUBLES doubles per device holds their scratch. noalloc_init
+// looks up the array's device address on the current device (once per device);
+// noalloc_scratch returns it (nullptr before noalloc_init ran on that device).
+constexpr int NOALLOC_SCRATCH_DOUBLES = VEC_GRID;  // the dot product's partial sums
+hipError_t noalloc_init(int device);
+double* noalloc_scratch(int device);
+
 // Training of DSS_theta (train.hip): one TRAIN_BLOCK-thread workgroup per local
 // problem; TRAIN_NWB weights per block (d = D).
 constexpr int TRAIN_BLOCK = 1024;

@@ -965,6 +965,7 @@ int ddmgnn_ctx_create(void* hip_stream, ddmgnn_ctx** out) {
     HIP_TRY(c->partials.alloc(VEC_GRID));
     HIP_TRY(c->scalar.alloc(1));
     HIP_TRY(hipHostMalloc((void**)&c->host_pinned, 256, hipHostMallocDefault));
+    HIP_TRY(noalloc_init(c->device));  // with the context's device current
     *out = c.release();
     return DDMGNN_OK;
 }
@@ -1242,6 +1243,17 @@ int ddmgnn_dot(ddmgnn_ctx* ctx, int64_t n, const double* x, const double* y, dou
     HIP_TRY(hipMemcpyAsync(ctx->host_pinned, ctx->scalar.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     *out = ctx->host_pinned[0];
+    return DDMGNN_OK;
+}
+
+int ddmgnn_dot_noalloc(ddmgnn_ctx* ctx, int64_t n, const double* x, const double* y, double* out) {
+    if (!ctx || !out || n < 0 || (n > 0 && (!x || !y))) return fail(DDMGNN_E_INVALID, "null argument or n < 0");
+    if (n > DDMGNN_NOALLOC_DOT_MAX_N)
+        return fail(DDMGNN_E_INVALID, "ddmgnn_dot_noalloc: n exceeds DDMGNN_NOALLOC_DOT_MAX_N (2^31 - 1)");
+    double* scr = noalloc_scratch(ctx->device);
+    if (!scr) return fail(DDMGNN_E_INVALID, "ddmgnn_dot_noalloc: no scratch address for the context's device");
+    // n = 0 runs the same kernels over no rows: the partials are 0 and so is *out.
+    HIP_TRY(launch_dot(x, y, (int)n, scr, out, ctx->stream, true));
     return DDMGNN_OK;
 }
 
