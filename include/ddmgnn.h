@@ -154,7 +154,12 @@ typedef struct {
 /* Validate a descriptor on the host (no device needed). */
 int ddmgnn_validate_problem(const ddmgnn_problem_desc* desc);
 
-/* Largest sub-mesh the DSS kernels accept (nodes). */
+/* Largest sub-mesh accepted (nodes): 16384 (16-bit local ids; DDM-LU stages
+ * R_i r in LDS). Sub-meshes of up to 2048 nodes keep their DSS state in
+ * registers and LDS; larger ones run a form of the VALU DSS kernel that keeps
+ * h, c and the neighbour projections in device memory (same arithmetic), in
+ * every precision (BF16 requests run them in FP32). Training samples are
+ * limited to 2048 nodes. */
 int32_t ddmgnn_max_subdomain_nodes(void);
 
 int ddmgnn_problem_create(ddmgnn_ctx* ctx, const ddmgnn_problem_desc* desc, const ddmgnn_model* model,
@@ -194,8 +199,10 @@ typedef struct {
     double prolong_ms;         /* gluing (step 3) with its fused dot products */
     double krylov_ms;          /* direction update, SpMV with dots, solution update */
     int32_t dss_kernel;        /* kernel that ran the local solves: 0 FP64 VALU DSS, 1 FP32 VALU DSS,
-                                * 2 BF16 MFMA DSS (BF16 falls back to 1 when a sub-mesh exceeds its LDS
-                                * budget), 3 exact local solves (DDM-LU) */
+                                * 2 BF16 MFMA DSS for every sub-mesh, 3 exact local solves (DDM-LU),
+                                * 4 BF16 MFMA DSS for some sub-meshes and the FP32 VALU DSS for those
+                                * beyond its LDS or 2048-node budget (a BF16 request of a model with
+                                * d != 10 runs 1 throughout) */
     int32_t status;            /* this problem's own status (DDMGNN_OK, E_MAXIT, E_BREAKDOWN, ...) */
     double latency_ms;         /* served requests: completion - submission (host clock);
                                 * solves: equal to solve_ms */

@@ -101,6 +101,9 @@ struct DevProb {
     double* qg64;               // DSS fallback storage when LDS is too small (may be null)
     double* hg64;               // FP64 DSS latent state
     float* qg32;
+    float* hg32;                // FP32 latent state of sub-meshes beyond the register-resident size
+    double* c64;                // normalised local right-hand sides of those sub-meshes (FP64 form),
+    float* c32;                 // and the same storage read as FP32 (FP32 form)
     KState* st;                 // null: no Krylov scalars, no done flag
     double* partials;           // (MAX_M + 1) x VEC_GRID per-workgroup partial sums
     // FGMRES storage (null until a problem is solved with FGMRES)
@@ -139,9 +142,18 @@ hipError_t prepare_dss_valu(int precision, int d, size_t shmem);
 hipError_t launch_dss_valu(const DevProb* tab, const int2* work, int n_work, int precision, int d, bool qlds,
                            int kbar, double alpha, int apply, const float* theta32, const double* theta64,
                            size_t shmem, hipStream_t s, bool check);
+// The VALU DSS forward for sub-meshes of more than kMaxSubNodes nodes (h, c
+// and Q in the per-slot global buffers hg32/hg64, c32/c64, qg32/qg64).
+hipError_t launch_dss_big(const DevProb* tab, const int2* work, int n_work, int precision, int d, int kbar,
+                          double alpha, int apply, const float* theta32, const double* theta64, hipStream_t s,
+                          bool check);
 // Exact local solves (DDM-LU): restriction as in the DSS kernels, then
-// local = (R_i A R_i^T)^{-1} R_i r per sub-mesh.
-hipError_t launch_lu_local(const DevProb* tab, const int2* work, int n_work, hipStream_t s, bool check);
+// local = (R_i A R_i^T)^{-1} R_i r per sub-mesh; R_i r is staged in dynamic
+// LDS of max_k doubles (the largest sub-mesh of the work list).
+// prepare_lu_local raises the kernel's LDS limit to kMaxSubNodesAny doubles
+// (not allowed during stream capture).
+hipError_t prepare_lu_local();
+hipError_t launch_lu_local(const DevProb* tab, const int2* work, int n_work, int max_k, hipStream_t s, bool check);
 hipError_t launch_coarse(const DevProb* tab, const int2* rows, int n_rows, hipStream_t s, bool check);
 // The Krylov launchers end with a finalize launch of one workgroup per
 // problem: n_prob = all problems of the table, or the problems of `list`.

@@ -162,8 +162,13 @@ __device__ inline double relu(double x) { return fmax(x, 0.0); }
 // carry it), so an edge only adds w_|d| |d_jl|; coordinates are centred on the
 // sub-mesh to keep the cancellation small. Used for FP32; the FP64 path
 // evaluates W1_d d_jl per edge.
-template <typename T, int D, bool HREG, bool QLDS>
+// BIG: a sub-mesh of any size (beyond DSS_NPT nodes per thread): h, c and Q
+// live in per-slot global buffers and the node loops run over as many
+// rounds of DSS_BLOCK nodes as the sub-mesh needs; the arithmetic per node is
+// the same as the register-resident form's.
+template <typename T, int D, bool HREG, bool QLDS, bool BIG = false>
 __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* __restrict__ theta) {
+    static_assert(!BIG || (!HREG && !QLDS), "a sub-mesh of any size keeps h and Q in global memory");
     using L = DssLayout<D>;
     constexpr int IN_PHI = L::IN_PHI, IN_PSI = L::IN_PSI, BLOCK_W = L::BLOCK_W;
     constexpr int OFF_PO = L::OFF_PO, OFF_PI = L::OFF_PI, OFF_PS = L::OFF_PS, OFF_DE = L::OFF_DE;
@@ -191,21 +196,32 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
     const float* __restrict__ edge_nd = P.edge_nd;
     double* __restrict__ out = P.local;
     const int tid = threadIdx.x;
+    // rounds of DSS_BLOCK nodes (a compile-time count unless BIG)
+    const int NT = BIG ? (k + DSS_BLOCK - 1) / DSS_BLOCK : DSS_NPT;
+    constexpr int UNR = BIG ? 1 : DSS_NPT;  // unroll count of the node rounds
 
-    T c[DSS_NPT];
+    T c[BIG ? 1 : DSS_NPT];
+    T* cg = nullptr;  // BIG: c per slot in global memory
+    if constexpr (BIG) {
+        if constexpr (SEP)
+            cg = P.c32 + base;
+        else
+            cg = P.c64 + base;
+    }
     double s = 1.0;
     if (a.apply) {
         const double* __restrict__ r = P.r;
-        double ss = 0.0, yy = 0.0, rv[DSS_NPT];
-#pragma unroll
-        for (int t = 0; t < DSS_NPT; ++t) {
+        double ss = 0.0, yy = 0.0, rv[BIG ? 1 : DSS_NPT];
+#pragma unroll UNR
+        for (int t = 0; t < NT; ++t) {
             const int j = tid + t * DSS_BLOCK;
-            rv[t] = 0.0;
+            double v = 0.0;
             if (j < k) {
-                rv[t] = r[P.sub_nodes[base + j]];
-                ss = fma(rv[t], rv[t], ss);
-                yy = fma(P.weights[base + j], rv[t], yy);
+                v = r[P.sub_nodes[base + j]];
+                ss = fma(v, v, ss);
+                yy = fma(P.weights[base + j], v, yy);
             }
+            if constexpr (!BIG) rv[t] = v;
         }
         ss = block_sum<DSS_BLOCK>(ss, red);
         yy = block_sum<DSS_BLOCK>(yy, red);
@@ -218,8 +234,14 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
             for (int j = tid; j < k; j += DSS_BLOCK) out[base + j] = 0.0;
             return;
         }
+        if constexpr (BIG) {
+            for (int j = tid; j < k; j += DSS_BLOCK) cg[j] = (T)(r[P.sub_nodes[base + j]] / s);
+        } else {
 #pragma unroll
-        for (int t = 0; t < DSS_NPT; ++t) c[t] = (T)(rv[t] / s);
+            for (int t = 0; t < DSS_NPT; ++t) c[t] = (T)(rv[t] / s);
+        }
+    } else if constexpr (BIG) {
+        for (int j = tid; j < k; j += DSS_BLOCK) cg[j] = (T)P.c_in[base + j];
     } else {
 #pragma unroll
         for (int t = 0; t < DSS_NPT; ++t) {
@@ -235,7 +257,10 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
         for (int u = 0; u < D; ++u) hreg[t][u] = (T)0;
     T* hg = nullptr;
     if constexpr (!HREG) {
-        hg = P.hg64 + (size_t)base * D;
+        if constexpr (SEP)
+            hg = P.hg32 + (size_t)base * D;
+        else
+            hg = P.hg64 + (size_t)base * D;
         for (int j = tid; j < k; j += DSS_BLOCK)
 #pragma unroll
             for (int u = 0; u < D; ++u) hg[j * D + u] = (T)0;
@@ -257,8 +282,8 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
         const T* cp = Vp + D * D;
 
         // Phase A: neighbour projections Q_out = W1_out[:, D:2D] h, Q_in likewise.
-#pragma unroll
-        for (int t = 0; t < DSS_NPT; ++t) {
+#pragma unroll UNR
+        for (int t = 0; t < NT; ++t) {
             const int j = tid + t * DSS_BLOCK;
             if (j < k) {
                 T h[D];
@@ -285,8 +310,8 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
         __syncthreads();
 
         // Phase B: per receiver, message sums over in-edges, then the Psi update.
-#pragma unroll
-        for (int t = 0; t < DSS_NPT; ++t) {
+#pragma unroll UNR
+        for (int t = 0; t < NT; ++t) {
             const int j = tid + t * DSS_BLOCK;
             if (j < k) {
                 T h[D];
@@ -379,7 +404,7 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
                     T acc = bp[u];
 #pragma unroll
                     for (int v = 0; v < D; ++v) acc = fma(Wp[u * IN_PSI + v], h[v], acc);
-                    acc = fma(Wp[u * IN_PSI + D], c[t], acc);
+                    acc = fma(Wp[u * IN_PSI + D], BIG ? cg[j] : c[BIG ? 0 : t], acc);
 #pragma unroll
                     for (int v = 0; v < D; ++v) acc = fma(Wp[u * IN_PSI + D + 1 + v], phio[v], acc);
 #pragma unroll
@@ -407,8 +432,8 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
     const T* db = dw + D * D;
     const T* dv = db + D;
     const T* dc = dv + D;
-#pragma unroll
-    for (int t = 0; t < DSS_NPT; ++t) {
+#pragma unroll UNR
+    for (int t = 0; t < NT; ++t) {
         const int j = tid + t * DSS_BLOCK;
         if (j < k) {
             T h[D];
@@ -444,7 +469,7 @@ __global__ __launch_bounds__(DSS_BLOCK) void lu_local_kernel(const DevProb* __re
     const int2 wi = work[blockIdx.x];
     const DevProb& P = tab[wi.x];
     if (P.st && P.st->done) return;
-    __shared__ double xs[kMaxSubNodes];
+    extern __shared__ double xs[];  // R_i r (k values; the launch reserves the work list's largest k)
     __shared__ double yp[LU_WAVES * LU_STRIP];  // parts * k <= LU_WAVES * LU_STRIP
     __shared__ double red[DSS_BLOCK / 64 + 1];
     const int sub = wi.y;
@@ -1233,9 +1258,39 @@ hipError_t launch_dss_valu(const DevProb* tab, const int2* work, int n_work, int
     return done(check);
 }
 
-hipError_t launch_lu_local(const DevProb* tab, const int2* work, int n_work, hipStream_t s, bool check) {
+hipError_t launch_dss_big(const DevProb* tab, const int2* work, int n_work, int precision, int d, int kbar,
+                          double alpha, int apply, const float* theta32, const double* theta64, hipStream_t s,
+                          bool check) {
     if (n_work <= 0) return hipSuccess;
-    hipLaunchKernelGGL(lu_local_kernel, dim3(n_work), dim3(DSS_BLOCK), 0, s, tab, work);
+    const DssArgs<double> a64{tab, work, kbar, alpha, apply};
+    const DssArgs<float> a32{tab, work, kbar, (float)alpha, apply};
+    const bool f64 = precision == DDMGNN_FP64;
+    switch (d) {
+        case 5:
+            if (f64) hipLaunchKernelGGL((dss_kernel<double, 5, false, false, true>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a64, theta64);
+            else hipLaunchKernelGGL((dss_kernel<float, 5, false, false, true>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a32, theta32);
+            break;
+        case 10:
+            if (f64) hipLaunchKernelGGL((dss_kernel<double, 10, false, false, true>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a64, theta64);
+            else hipLaunchKernelGGL((dss_kernel<float, 10, false, false, true>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a32, theta32);
+            break;
+        case 20:
+            if (f64) hipLaunchKernelGGL((dss_kernel<double, 20, false, false, true>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a64, theta64);
+            else hipLaunchKernelGGL((dss_kernel<float, 20, false, false, true>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a32, theta32);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return done(check);
+}
+
+hipError_t prepare_lu_local() {
+    return hipFuncSetAttribute((const void*)lu_local_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(kMaxSubNodesAny * sizeof(double)));
+}
+
+hipError_t launch_lu_local(const DevProb* tab, const int2* work, int n_work, int max_k, hipStream_t s, bool check) {
+    if (n_work <= 0) return hipSuccess;
+    hipLaunchKernelGGL(lu_local_kernel, dim3(n_work), dim3(DSS_BLOCK), (size_t)max_k * sizeof(double), s, tab, work);
     return done(check);
 }
 

@@ -33,14 +33,16 @@ struct Batch {
     DevBuf<DevProb> hook;              // one-problem table of the entry points that redirect vectors
     // DSS work lists, (problem, sub-mesh) by decreasing sub-mesh size:
     // all sub-meshes; those of problems that fit the MFMA kernel; the others.
-    DevBuf<int2> work_all, work_mfma, work_rest;
-    int n_all = 0, n_mfma = 0, n_rest = 0;
+    // (the VALU lists hold sub-meshes of at most kMaxSubNodes nodes; work_big the larger ones,
+    // which run the global-memory form of the VALU kernel in every precision)
+    DevBuf<int2> work_all, work_mfma, work_rest, work_valu, work_big;
+    int n_all = 0, n_mfma = 0, n_rest = 0, n_valu = 0, n_big = 0;
     // the MFMA list split by workgroup size: sub-meshes that run two per compute
     // unit in MFMA_SMALL_BLOCK-thread workgroups, and the rest; dynamic LDS of each launch
     DevBuf<int2> work_mfma_small;
     int n_mfma_small = 0;
     size_t lds_mfma = 0, lds_mfma_small = 0;
-    int max_k_all = 0, max_k_rest = 0;
+    int max_k_all = 0, max_k_rest = 0, max_k_valu = 0;
     DevBuf<int2> vec_blk;              // (problem, local workgroup)
     int n_vec = 0;
     DevBuf<int2> coarse_rows;          // (problem, row)
@@ -80,6 +82,7 @@ DevProb make_view(ddmgnn_problem* P) {
     }
     v.s = P->s.p; v.y0 = P->y0.p; v.y = P->y.p; v.local = P->local.p;
     v.qg64 = P->qglobal64.p; v.hg64 = P->hglobal64.p; v.qg32 = P->qglobal32.p;
+    v.hg32 = P->hglobal32.p; v.c64 = P->cglobal.p; v.c32 = reinterpret_cast<float*>(P->cglobal.p);
     v.st = P->st.p;
     v.partials = P->partials.p;
     v.rtol = P->rtol;
@@ -117,6 +120,7 @@ size_t valu_shmem(int max_k, int precision, int d) {
 // Exact local solves: the inverses of R_i A R_i^T, formed on the host from the
 // problem's matrix and sub-meshes (downloaded once) and uploaded.
 int prepare_lu(ddmgnn_problem* P) {
+    HIP_TRY(prepare_lu_local());
     if (P->lu_inv.p) return DDMGNN_OK;
     hipStream_t s = P->ctx->stream;
     const auto& hs = P->hs;
@@ -203,9 +207,22 @@ int prepare_train(ddmgnn_problem* P) {
     return DDMGNN_OK;
 }
 
-// Whether the BF16 MFMA kernel runs problem P (its largest sub-mesh fits the
-// kernel's LDS budget and the model has the paper's latent width).
-bool runs_mfma(const Batch& B, const ddmgnn_problem* P) { return P->mfma_fits && B.model->d == D; }
+// Whether the BF16 MFMA kernel runs sub-mesh `sub` of P (the model has the
+// paper's latent width and the sub-mesh fits the kernel's node and LDS budgets).
+bool mfma_runs_sub(const ddmgnn_problem* P, int sub) {
+    return P->model->d == D && P->mfma_need[(size_t)sub] <= MFMA_LDS_LIMIT;
+}
+// Whether every sub-mesh of P runs on the VALU kernels under BF16.
+bool all_valu_bf16(const ddmgnn_problem* P) {
+    for (int i = 0; i < P->hs.K; ++i)
+        if (mfma_runs_sub(P, i)) return false;
+    return true;
+}
+bool any_valu_bf16(const ddmgnn_problem* P) {
+    for (int i = 0; i < P->hs.K; ++i)
+        if (!mfma_runs_sub(P, i)) return true;
+    return false;
+}
 
 int prepare_fgmres(Batch& B, int R, bool& changed) {
     for (ddmgnn_problem* P : B.probs) {
@@ -232,14 +249,39 @@ int prepare_dss(Batch& B, int precision, bool& changed) {
     const bool bf16 = precision == DDMGNN_BF16;
     if (bf16 && B.n_mfma + B.n_mfma_small) HIP_TRY(prepare_dss_mfma(MFMA_LDS_LIMIT));
     const int valu_prec = bf16 ? DDMGNN_FP32 : precision;
-    const int max_k = bf16 ? B.max_k_rest : B.max_k_all;
-    const int n_valu = bf16 ? B.n_rest : B.n_all;
-    if (n_valu == 0) return DDMGNN_OK;
     const bool f64 = valu_prec == DDMGNN_FP64;
     const int d = B.model->d;
+    // sub-meshes beyond kMaxSubNodes: h, c and Q per slot in global memory
+    for (ddmgnn_problem* P : B.probs) {
+        if (!P->has_big) continue;
+        const size_t sk = (size_t)P->hs.sk;
+        if (f64 && P->qglobal64.n < sk * 2 * d) {
+            HIP_TRY(P->qglobal64.alloc(sk * 2 * d));
+            changed = true;
+        }
+        if (!f64 && P->qglobal32.n < sk * 2 * d) {
+            HIP_TRY(P->qglobal32.alloc(sk * 2 * d));
+            changed = true;
+        }
+        if (f64 && P->hglobal64.n < sk * d) {
+            HIP_TRY(P->hglobal64.alloc(sk * d));
+            changed = true;
+        }
+        if (!f64 && P->hglobal32.n < sk * d) {
+            HIP_TRY(P->hglobal32.alloc(sk * d));
+            changed = true;
+        }
+        if (P->cglobal.n < sk) {
+            HIP_TRY(P->cglobal.alloc(sk));
+            changed = true;
+        }
+    }
+    const int max_k = bf16 ? B.max_k_rest : B.max_k_valu;
+    const int n_valu = bf16 ? B.n_rest : B.n_valu;
+    if (n_valu == 0) return DDMGNN_OK;
     const bool in_lds = valu_q_in_lds(max_k, valu_prec, d);
     for (ddmgnn_problem* P : B.probs) {
-        if (bf16 && runs_mfma(B, P)) continue;
+        if (bf16 && !any_valu_bf16(P)) continue;
         const size_t sk = (size_t)P->hs.sk;
         if (!in_lds) {
             if (f64 && P->qglobal64.n < sk * 2 * d) {
@@ -267,9 +309,11 @@ int enqueue_dss(Batch& B, const DevProb* tab, int precision, int apply, bool cap
     const ModelDev& M = *B.model;
     const bool check = !capturing;
     if (local == DDMGNN_LOCAL_LU) {
-        HIP_TRY(launch_lu_local(tab, B.work_all.p, B.n_all, s, check));
+        HIP_TRY(launch_lu_local(tab, B.work_all.p, B.n_all, B.max_k_all, s, check));
         return DDMGNN_OK;
     }
+    HIP_TRY(launch_dss_big(tab, B.work_big.p, B.n_big, precision == DDMGNN_BF16 ? DDMGNN_FP32 : precision, M.d,
+                           M.kbar, M.alpha, apply, M.theta32.p, M.theta64.p, s, check));
     if (precision == DDMGNN_BF16) {
         DssMfmaArgs a{tab, B.work_mfma.p, M.steps.p, M.dec.p, M.kbar, (float)M.alpha, apply};
         if (B.n_mfma > 0 && B.n_mfma_small > 0) {
@@ -294,9 +338,9 @@ int enqueue_dss(Batch& B, const DevProb* tab, int precision, int apply, bool cap
                                 M.theta32.p, M.theta64.p, qlds ? valu_shmem(B.max_k_rest, DDMGNN_FP32, M.d) : 0, s,
                                 check));
     } else {
-        const bool qlds = valu_q_in_lds(B.max_k_all, precision, M.d);
-        HIP_TRY(launch_dss_valu(tab, B.work_all.p, B.n_all, precision, M.d, qlds, M.kbar, M.alpha, apply,
-                                M.theta32.p, M.theta64.p, qlds ? valu_shmem(B.max_k_all, precision, M.d) : 0, s,
+        const bool qlds = valu_q_in_lds(B.max_k_valu, precision, M.d);
+        HIP_TRY(launch_dss_valu(tab, B.work_valu.p, B.n_valu, precision, M.d, qlds, M.kbar, M.alpha, apply,
+                                M.theta32.p, M.theta64.p, qlds ? valu_shmem(B.max_k_valu, precision, M.d) : 0, s,
                                 check));
     }
     return DDMGNN_OK;
@@ -559,12 +603,18 @@ int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& 
         if (a.p != b.p) return a.p < b.p;
         return a.sub < b.sub;
     });
-    std::vector<int2> wa, wm, wms, wr;
+    std::vector<int2> wa, wm, wms, wr, wv, wb;
     for (const W& w : all) {
         wa.push_back(make_int2(w.p, w.sub));
         B->max_k_all = std::max(B->max_k_all, w.k);
         const ddmgnn_problem* Q = probs[w.p];
-        if (Q->mfma_fits && Q->model->d == D) {
+        if (w.k > kMaxSubNodes) {
+            wb.push_back(make_int2(w.p, w.sub));
+            continue;
+        }
+        wv.push_back(make_int2(w.p, w.sub));
+        B->max_k_valu = std::max(B->max_k_valu, w.k);
+        if (mfma_runs_sub(Q, w.sub)) {
             const size_t need = Q->mfma_need[w.sub];
             if (w.k <= MFMA_SMALL_K && need <= (size_t)Q->tune.small_lds) {
                 wms.push_back(make_int2(w.p, w.sub));
@@ -583,12 +633,16 @@ int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& 
     if (int rc = upload_list(B->work_mfma, wm, s)) return rc;
     if (int rc = upload_list(B->work_mfma_small, wms, s)) return rc;
     if (int rc = upload_list(B->work_rest, wr, s)) return rc;
+    if (int rc = upload_list(B->work_valu, wv, s)) return rc;
+    if (int rc = upload_list(B->work_big, wb, s)) return rc;
     if (int rc = upload_list(B->vec_blk, vec, s)) return rc;
     if (int rc = upload_list(B->coarse_rows, rows, s)) return rc;
     B->n_all = (int)wa.size();
     B->n_mfma = (int)wm.size();
     B->n_mfma_small = (int)wms.size();
     B->n_rest = (int)wr.size();
+    B->n_valu = (int)wv.size();
+    B->n_big = (int)wb.size();
     B->n_vec = (int)vec.size();
     B->n_coarse = (int)rows.size();
     HIP_TRY(B->st_gather.alloc(n));
@@ -722,7 +776,8 @@ size_t fgmres_bytes(int64_t n, int R) {
 int dss_kernel_of(const ddmgnn_problem* P, const ddmgnn_solve_opts& o) {
     if (o.local_solver == DDMGNN_LOCAL_LU) return 3;
     if (o.precision == DDMGNN_FP64) return 0;
-    return o.precision == DDMGNN_BF16 && P->mfma_fits && P->model->d == D ? 2 : 1;
+    if (o.precision != DDMGNN_BF16 || all_valu_bf16(P)) return 1;
+    return any_valu_bf16(P) ? 4 : 2;
 }
 
 int check_opts(const ddmgnn_solve_opts& o) {
@@ -817,11 +872,15 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
         std::vector<int32_t> epad(K + 1, 0);
         P->mfma_need.assign(K, 0);
         std::vector<TileNode> tiles(sk);
-        size_t need = 0;
         for (int i = 0; i < K; ++i) {
             const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
             const int k = (int)(e - b);
             epad[i] = (int32_t)er.size();
+            if (k > kMaxSubNodes) {  // the VALU kernel's global-memory form runs it: no tile records
+                P->mfma_need[i] = UINT32_MAX;
+                P->has_big = true;
+                continue;
+            }
             for (int t0 = 0; t0 < k; t0 += MFMA_TILE) {
                 const int t1 = std::min(k, t0 + MFMA_TILE);
                 int maxdeg = 0;
@@ -872,10 +931,8 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
                 }
             }
             P->mfma_need[i] = (uint32_t)mfma_lds_need(k, (int64_t)er.size() - epad[i]);
-            need = std::max(need, (size_t)P->mfma_need[i]);
         }
         epad[K] = (int32_t)er.size();
-        P->mfma_fits = need <= MFMA_LDS_LIMIT;
         HIP_TRY(P->tiles.upload(tiles.data(), tiles.size(), s));
         HIP_TRY(P->erec.upload(er.data(), std::max<size_t>(er.size(), 1), s));
         HIP_TRY(P->epad_sub.upload(epad.data(), epad.size(), s));
@@ -935,7 +992,7 @@ extern "C" {
 
 const char* ddmgnn_last_error(void) { return g_err.c_str(); }
 const char* ddmgnn_version(void) { return "ddmgnn 0.2 gfx950"; }
-int32_t ddmgnn_max_subdomain_nodes(void) { return kMaxSubNodes; }
+int32_t ddmgnn_max_subdomain_nodes(void) { return kMaxSubNodesAny; }
 
 void ddmgnn_default_opts(ddmgnn_solve_opts* o) {
     o->krylov = DDMGNN_FCG;
@@ -1299,12 +1356,15 @@ int ddmgnn_dss_forward_sub(ddmgnn_ctx* ctx, ddmgnn_problem* P, int32_t precision
     v.st = nullptr;
     HIP_TRY(upload_async(B.hook.p, &v, sizeof(v), s));
     const ModelDev& M = *B.model;
-    if (precision == DDMGNN_BF16 && runs_mfma(B, P)) {
+    const int vprec = precision == DDMGNN_BF16 ? DDMGNN_FP32 : precision;
+    if (k > kMaxSubNodes) {
+        HIP_TRY(launch_dss_big(B.hook.p, P->one_work.p, 1, vprec, M.d, M.kbar, M.alpha, 0, M.theta32.p,
+                               M.theta64.p, s, true));
+    } else if (precision == DDMGNN_BF16 && mfma_runs_sub(P, sub)) {
         DssMfmaArgs a{B.hook.p, P->one_work.p, M.steps.p, M.dec.p, M.kbar, (float)M.alpha, 0};
         HIP_TRY(launch_dss_mfma(a, 1, P->mfma_need[sub], MFMA_BLOCK, s, true));
     } else {
-        const int vprec = precision == DDMGNN_BF16 ? DDMGNN_FP32 : precision;
-        const int mk = precision == DDMGNN_BF16 ? B.max_k_rest : B.max_k_all;  // as prepare_dss sized it
+        const int mk = precision == DDMGNN_BF16 ? B.max_k_rest : B.max_k_valu;  // as prepare_dss sized it
         const bool qlds = valu_q_in_lds(mk, vprec, M.d);
         HIP_TRY(launch_dss_valu(B.hook.p, P->one_work.p, 1, vprec, M.d, qlds, M.kbar, M.alpha, 0, M.theta32.p,
                                 M.theta64.p, qlds ? valu_shmem(mk, vprec, M.d) : 0, s, true));
@@ -1518,6 +1578,8 @@ int ddmgnn_train_grad(ddmgnn_ctx* ctx, ddmgnn_problem* P, const ddmgnn_model_des
     int64_t total = 0, used = 0;
     for (int32_t i = 0; i < n; ++i) {
         if (subs[i] < 0 || subs[i] >= P->hs.K) return fail(DDMGNN_E_INVALID, "sub-mesh index out of range");
+        if (P->hs.sub_ptr[subs[i] + 1] - P->hs.sub_ptr[subs[i]] > kMaxSubNodes)
+            return fail(DDMGNN_E_INVALID, "training samples are limited to sub-meshes of at most 2048 nodes");
         if (c_off[i] < 0) return fail(DDMGNN_E_INVALID, "negative right-hand side offset");
         if (i % TRAIN_CHUNK == 0) used = 0;
         soff[(size_t)i] = used;

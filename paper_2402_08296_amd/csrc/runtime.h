@@ -162,8 +162,9 @@ struct ddmgnn_problem {
     ddmgnn::DevBuf<uint32_t> erec;   // MFMA kernel edge records, padded per node
     ddmgnn::DevBuf<int32_t> epad_sub;  // [K + 1] ranges of the sub-meshes in erec
     ddmgnn::DevBuf<float> edge_nd;   // padded by 8 entries
-    bool mfma_fits = false;          // every sub-mesh fits the MFMA kernel's LDS
-    std::vector<uint32_t> mfma_need; // per sub-mesh, LDS bytes of the MFMA kernel
+    std::vector<uint32_t> mfma_need; // per sub-mesh, LDS bytes of the MFMA kernel (UINT32_MAX: beyond
+                                     // its node budget, no tile records)
+    bool has_big = false;            // a sub-mesh of more than kMaxSubNodes nodes
     ddmgnn_tuning tune{};            // launch schedule (ddmgnn_problem_set_tuning / ddmgnn_autotune)
     // one-sub-mesh forward entry: per-slot input and output, and its one-item work list
     ddmgnn::DevBuf<double> fwd_in, fwd_out;
@@ -171,6 +172,8 @@ struct ddmgnn_problem {
     // apply buffers
     ddmgnn::DevBuf<double> s, y0, y, local;
     ddmgnn::DevBuf<double> qglobal64, hglobal64;
+    ddmgnn::DevBuf<float> hglobal32;  // FP32 h of the sub-meshes beyond kMaxSubNodes
+    ddmgnn::DevBuf<double> cglobal;   // their c (FP64, or FP32 in the same storage)
     // exact local solves (built on the first solve with local_solver = LU)
     ddmgnn::DevBuf<double> lu_inv;
     ddmgnn::DevBuf<int64_t> lu_off;

@@ -276,7 +276,7 @@ std::string validate(const ddmgnn_problem_desc& d) {
     for (int32_t s = 0; s < d.n_sub; ++s) {
         int64_t b = d.sub_ptr[s], e = d.sub_ptr[s + 1];
         if (e <= b) return "empty sub-mesh";
-        if (e - b > kMaxSubNodes) return "sub-mesh larger than the supported maximum (2048 nodes)";
+        if (e - b > kMaxSubNodesAny) return "sub-mesh larger than the supported maximum (16384 nodes)";
         for (int64_t k = b; k < e; ++k) {
             int32_t v = d.sub_nodes[k];
             if (v < 0 || v >= n) return "sub_nodes id out of range";

@@ -11,7 +11,9 @@
 
 namespace ddmgnn {
 
-constexpr int kMaxSubNodes = 2048;  // largest sub-mesh the DSS kernels accept
+constexpr int kMaxSubNodes = 2048;      // largest sub-mesh of the register-resident DSS kernels
+constexpr int kMaxSubNodesAny = 16384;  // largest sub-mesh accepted (16-bit local ids; DDM-LU stages
+                                        // R_i r in 128 KiB of LDS)
 
 // Returns an empty string when desc is valid, else the reason.
 std::string validate(const ddmgnn_problem_desc& d);

@@ -21,7 +21,7 @@ def test_library_exports_every_declared_symbol():
     for name in sorted(names):
         assert hasattr(L, name), name
     assert b"gfx950" in L.ddmgnn_version()
-    assert L.ddmgnn_max_subdomain_nodes() == 2048
+    assert L.ddmgnn_max_subdomain_nodes() == 16384
 
 
 def test_overlap_bitexact_vs_oracle():
@@ -103,7 +103,7 @@ def test_validate_rejects(mutate, msg):
 
 
 def test_validate_rejects_oversized_subdomain_and_uncovered_node():
-    p = W.make_problem(2, 5000, 1)
+    p = W.make_problem(2, 17000, 1)
     hp = dg.host_problem(p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, p.A.rowptr, p.A.col, p.A.val, p.b, p.u0,
                          p.part, 1, 0)
     with pytest.raises(dg.DDMGNNError, match="maximum"):
@@ -181,10 +181,16 @@ def test_library_xavier_matches_generator():
 
 
 def test_validate_rejects_oversized_and_empty():
-    """A sub-mesh above the kernels' limit (2048 nodes) and an empty problem are refused on the host."""
+    """A sub-mesh above the register-resident kernels' size (2048 nodes) is accepted, one above
+    the library's limit (16384 nodes, 16-bit local ids) and an empty problem are refused on
+    the host."""
     p = W.make_problem(33, 3000, 1)
     hp = host_problem_for(p)
     assert hp.sub_ptr[1] > 2048
+    dg.validate(hp)
+    p = W.make_problem(34, 16600, 1)
+    hp = host_problem_for(p)
+    assert hp.sub_ptr[1] > 16384
     with pytest.raises(dg.DDMGNNError, match="larger than"):
         dg.validate(hp)
     d = hp.desc()

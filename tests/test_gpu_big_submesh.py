@@ -1,0 +1,137 @@
+"""Sub-meshes larger than the register-resident DSS kernels hold (2048 nodes).
+
+Table I of the paper partitions into parts of about 2000 nodes; with an
+overlap of 2 layers those sub-meshes exceed 2048 nodes. The library routes
+such sub-meshes, one by one, to the global-memory form of the VALU DSS kernel
+(h, c and the neighbour projections per slot in device memory), in every
+precision (a BF16 request runs them in FP32), and stages R_i r of the DDM-LU
+local solves in LDS sized by the largest sub-mesh. The problem below mixes
+sub-meshes of 791 to 3777 nodes (one of 2308), built with the oracle's own
+decomposition; every check is against the oracle.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2402_08296_amd as dg  # noqa: E402
+import workload as W  # noqa: E402
+from oracle import decomp as dc, dss, krylov as kr, schwarz as sw  # noqa: E402
+from tests._cases import oracle_problem  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+XAVIER = W.xavier_theta(W.THETA_SEED)
+SMOOTHER = W.smoother_theta(omega=0.15, out_scale=1.7)
+TOL = {"fp64": 1e-12, "fp32": 3e-5, "bf16": 5e-2}
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float64)).cuda()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    print("[gpu] creating context", flush=True)
+    return dg.Context()
+
+
+@pytest.fixture(scope="module")
+def mixed():
+    p = W.make_problem(43, 10000, 5, 0.6)
+    hp = oracle_problem(p)
+    ks = np.diff(hp.sub_ptr)
+    print(f"[gpu] mixed problem N={p.n} sub-mesh sizes {sorted(ks.tolist())}", flush=True)
+    assert ks.max() > 2048 and ks.min() <= 2048 and np.any((ks > 2300) & (ks < 2500))
+    return p, hp
+
+
+def _oracle_M(p, hp, theta, **kw):
+    dec = dc.Decomposition(p.n, hp.sub_ptr, hp.sub_nodes, hp.weights)
+    return sw.DDMGNN(p.A.to_scipy(), p.mesh.xy, p.mesh.tri, p.mesh.dirichlet, dec, theta, **kw)
+
+
+@pytest.mark.timeout(300)
+def test_big_dss_forward_matches_oracle(ctx, mixed):
+    """DSS forward of every sub-mesh (FP64, FP32, and BF16: matrix cores for the small
+    sub-meshes, FP32 for the large) against the oracle's forward, node by node; the
+    one-sub-mesh entry gives the bits of the full forward's slice of a large sub-mesh."""
+    p, hp = mixed
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, XAVIER))
+    rng = np.random.default_rng(3)
+    c = rng.standard_normal(hp.sub_nodes.size)
+    blocks = dss.unpack(XAVIER, 30, 10)
+    refs = []
+    for i in range(hp.K):
+        sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
+        g = dc.local_graph(hp.sub_nodes[sl], p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
+        refs.append(dss.forward(blocks, g, c[sl], 1e-3, 10))
+    out = torch.empty(hp.sub_nodes.size, dtype=torch.float64, device="cuda")
+    big = int(np.argmax(np.diff(hp.sub_ptr)))
+    for prec in ("fp64", "fp32", "bf16"):
+        print(f"[gpu] big forward {prec}", flush=True)
+        out.fill_(np.nan)
+        prob.dss_forward(_dev(c), out, prec)
+        o = out.cpu().numpy()
+        for i in range(hp.K):
+            sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
+            err = np.abs(o[sl] - refs[i]).max() / np.abs(refs[i]).max()
+            print(f"[gpu]   k={sl.stop - sl.start} {prec} relative error {err:.3e}", flush=True)
+            assert err <= TOL[prec]
+        sl = slice(hp.sub_ptr[big], hp.sub_ptr[big + 1])
+        one = torch.empty(sl.stop - sl.start, dtype=torch.float64, device="cuda")
+        prob.dss_forward_sub(big, _dev(c[sl]), one, prec)
+        assert torch.equal(one, out[sl])
+
+
+@pytest.mark.timeout(300)
+def test_big_apply_and_solve_match_oracle(ctx, mixed):
+    """One DDM-GNN apply (FP64) node by node, and an FP64 FCG solve to rtol 1e-10 with
+    the constructed smoother: iterations within 1 of the oracle's, solution within 1e-6."""
+    p, hp = mixed
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, SMOOTHER))
+    A = p.A.to_scipy()
+    M = _oracle_M(p, hp, SMOOTHER)
+    r = p.b - A @ p.u0
+    z = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    print("[gpu] big apply fp64", flush=True)
+    prob.apply(_dev(r), z, dg.default_opts(precision="fp64"))
+    zr = M(r)
+    assert np.abs(z.cpu().numpy() - zr).max() <= 1e-11 * np.abs(zr).max()
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    st = prob.solve(u, dg.default_opts(precision="fp64", rtol=1e-10, max_it=2000))
+    ref = kr.fcg(A, p.b, p.u0, M, 1e-10, max_it=2000)
+    err = np.linalg.norm(u.cpu().numpy() - ref.u) / np.linalg.norm(ref.u)
+    print(f"[gpu]   fp64 solve: iterations gpu={st.iterations} oracle={ref.iterations} L2 {err:.2e} "
+          f"kernel={st.dss_kernel}", flush=True)
+    assert st.converged and abs(st.iterations - ref.iterations) <= 1 and err <= 1e-6
+    assert st.dss_kernel == 0
+    st = prob.solve(u, dg.default_opts(precision="bf16", rtol=1e-6, max_it=2000))
+    print(f"[gpu]   bf16 solve: iterations {st.iterations} true residual {st.true_rel_residual:.2e} "
+          f"kernel={st.dss_kernel}", flush=True)
+    assert st.converged and st.true_rel_residual <= 1.5e-6
+    assert st.dss_kernel == 4  # matrix cores for the small sub-meshes, FP32 VALU for the large
+
+
+@pytest.mark.timeout(300)
+def test_big_ddm_lu_matches_oracle(ctx, mixed):
+    """DDM-LU with sub-meshes up to 3777 nodes: one apply against the oracle's exact local
+    solves (unweighted glue), and a PCG solve to rtol 1e-10 within 1 iteration of it."""
+    p, hp = mixed
+    prob = dg.Problem(ctx, hp, dg.Model(ctx, SMOOTHER))
+    A = p.A.to_scipy()
+    dec = dc.Decomposition(p.n, hp.sub_ptr, hp.sub_nodes, hp.weights)
+    M = sw.DDMLU(A, p.mesh.dirichlet, dec, prolong="unweighted")
+    r = p.b - A @ p.u0
+    z = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    opts = dict(local_solver=dg.LOCAL_LU, prolong=dg.PROLONG_UNWEIGHTED)
+    print("[gpu] big DDM-LU apply", flush=True)
+    prob.apply(_dev(r), z, dg.default_opts(**opts))
+    zr = M(r)
+    assert np.abs(z.cpu().numpy() - zr).max() <= 1e-10 * np.abs(zr).max()
+    u = torch.empty(p.n, dtype=torch.float64, device="cuda")
+    st = prob.solve(u, dg.default_opts(krylov=dg.PCG, rtol=1e-10, max_it=500, **opts))
+    ref = kr.pcg(A, p.b, p.u0, M, 1e-10, max_it=500)
+    err = np.linalg.norm(u.cpu().numpy() - ref.u) / np.linalg.norm(ref.u)
+    print(f"[gpu]   DDM-LU PCG: iterations gpu={st.iterations} oracle={ref.iterations} L2 {err:.2e}", flush=True)
+    assert st.converged and abs(st.iterations - ref.iterations) <= 1 and err <= 1e-8
