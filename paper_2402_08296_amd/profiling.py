@@ -2,6 +2,11 @@
 
   python -m paper_2402_08296_amd.profiling stats <kernel_stats.csv> <out.md> --title T --command C
       kernel-trace statistics as a markdown table
+  python -m paper_2402_08296_amd.profiling traffic-table <fetch csv> <write csv> <out.md> --kernels K1,K2 ...
+      the same scaled bytes per dispatch for several kernels, as one table
+  python -m paper_2402_08296_amd.profiling counters <out.md> <counter csv>... --stage K1+K2 --stage-us T ...
+      per-dispatch means of SQ counters of a stage's kernels and the VALU/MFMA issue
+      floors they imply against the stage time
   python -m paper_2402_08296_amd.profiling traffic <fetch counter_collection.csv> <write counter_collection.csv>
       <out.md> --kernel NAME --copy-bytes B --fetch-command C1 --write-command C2
       HBM bytes per dispatch of a kernel from FETCH_SIZE and WRITE_SIZE (KiB per
@@ -149,6 +154,78 @@ def read_traffic(path: str) -> dict | None:
     return json.loads(m.group(1)) if m else None
 
 
+def traffic_table_markdown(fetch_csv: str, write_csv: str, kernels: list[str], copy_bytes: int, fetch_cmd: str,
+                           write_cmd: str, title: str, notes: str = "") -> str:
+    """HBM bytes per dispatch of several kernels (FETCH_SIZE, WRITE_SIZE, each scaled by
+    the plain copy's known bytes over the counter's reading for it in the same run)."""
+    fetch = per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = per_dispatch(write_csv, "WRITE_SIZE")
+    copy_name = next(k for k in fetch if "copyBuffer" in k)
+    f_fetch = copy_bytes / (max(fetch[copy_name]) * 1024.0)
+    f_write = copy_bytes / (max(write[copy_name]) * 1024.0)
+    lines = [f"# {title}", "", "FETCH_SIZE and WRITE_SIZE (KiB per dispatch) from two rocprofv3 counter passes, each "
+             "scaled by", "known bytes / counter reading of the largest plain copy (hipMemcpy device-to-device blit) "
+             "in the", "same run. Commands (from /tmp with TMPDIR=/tmp, repository at <repo>):", "", "```", fetch_cmd,
+             write_cmd, "```", "", f"Scales: fetch {f_fetch:.4f}, write {f_write:.4f} (copy of {copy_bytes} bytes).",
+             "", "| Kernel | Dispatches | Fetch MB | Write MB | Total MB |", "|---|---|---|---|---|"]
+    for k in kernels:
+        fk = sum(fetch[k]) / len(fetch[k]) * 1024.0 * f_fetch
+        wk = sum(write[k]) / len(write[k]) * 1024.0 * f_write
+        lines.append(f"| {k} | {len(fetch[k])} | {fk / 1e6:.1f} | {wk / 1e6:.1f} | {(fk + wk) / 1e6:.1f} |")
+    if notes:
+        lines += ["", notes]
+    return "\n".join(lines) + "\n"
+
+
+# Instruction issue model of the hardware (MI355X): 256 compute units of 4 SIMDs at
+# 2.4 GHz; a wave64 VALU instruction occupies its SIMD for 4 cycles, a
+# v_mfma_f32_32x32x16 (bf16 or f16) for 32 cycles (8 passes).
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+VALU_CYCLES = 4
+MFMA_CYCLES = 32
+
+
+def counters_markdown(csvs: list[str], stage: list[str], stage_us: float, title: str, commands: list[str],
+                      notes: str = "") -> str:
+    """Per-dispatch means of every SQ/GRBM counter of the kernels of one stage (several
+    kernels joined by '+' that run once each per stage are summed), and the issue floors
+    they imply: VALU instructions x 4 cycles and MFMA instructions x 32 cycles spread
+    over all SIMDs, against the stage's measured time."""
+    vals = defaultdict(lambda: defaultdict(list))
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            vals[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    names = sorted({c for k in stage for c in vals[k]})
+    lines = [f"# {title}", "", "Commands (from /tmp with TMPDIR=/tmp, repository at <repo>), one counter pass each:", "",
+             "```", *commands, "```", "", "Mean per dispatch (counter units as rocprofv3 reports them):", "",
+             "| Counter | " + " | ".join(stage) + " | stage |", "|---" * (len(stage) + 2) + "|"]
+    tot = {}
+    for c in names:
+        row = [sum(vals[k][c]) / len(vals[k][c]) if vals[k][c] else 0.0 for k in stage]
+        tot[c] = sum(row)
+        lines.append(f"| {c} | " + " | ".join(f"{v:,.0f}" for v in row) + f" | {tot[c]:,.0f} |")
+    lines += ["", f"Stage time: {stage_us:.1f} us.", ""]
+    if "SQ_INSTS_VALU" in tot:
+        fl = tot["SQ_INSTS_VALU"] * VALU_CYCLES / (SIMDS * CLOCK_HZ) * 1e6
+        lines.append(f"- VALU issue floor: {tot['SQ_INSTS_VALU']:,.0f} wave instructions x {VALU_CYCLES} cycles over "
+                     f"{SIMDS} SIMDs at {CLOCK_HZ / 1e9:.1f} GHz = {fl:.1f} us, i.e. VALU busy "
+                     f"{100 * fl / stage_us:.1f}% of the stage.")
+    if "SQ_INSTS_MFMA" in tot:
+        fm = tot["SQ_INSTS_MFMA"] * MFMA_CYCLES / (SIMDS * CLOCK_HZ) * 1e6
+        lines.append(f"- MFMA issue floor: {tot['SQ_INSTS_MFMA']:,.0f} x {MFMA_CYCLES} cycles = {fm:.1f} us, "
+                     f"MFMA busy {100 * fm / stage_us:.1f}%.")
+    if "SQ_WAVE_CYCLES" in tot and "SQ_WAIT_INST_ANY" in tot:
+        lines.append(f"- Waves wait on dependencies (s_waitcnt) {100 * tot['SQ_WAIT_INST_ANY'] / tot['SQ_WAVE_CYCLES']:.1f}% "
+                     f"of their cycles; on LDS {100 * tot.get('SQ_WAIT_INST_LDS', 0) / tot['SQ_WAVE_CYCLES']:.1f}%.")
+    if "SQ_LDS_BANK_CONFLICT" in tot and "SQ_ACTIVE_INST_LDS" in tot:
+        lines.append(f"- LDS bank-conflict cycles per LDS-active cycle: "
+                     f"{tot['SQ_LDS_BANK_CONFLICT'] / tot['SQ_ACTIVE_INST_LDS']:.2f}.")
+    if notes:
+        lines += ["", notes]
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -166,7 +243,34 @@ def main():
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--fetch-command", required=True)
     t.add_argument("--write-command", required=True)
+    tt = sub.add_parser("traffic-table")
+    tt.add_argument("fetch_csv")
+    tt.add_argument("write_csv")
+    tt.add_argument("out")
+    tt.add_argument("--kernels", required=True, help="kernel names joined by ','")
+    tt.add_argument("--copy-bytes", type=int, required=True)
+    tt.add_argument("--fetch-command", required=True)
+    tt.add_argument("--write-command", required=True)
+    tt.add_argument("--title", required=True)
+    tt.add_argument("--notes", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("out")
+    c.add_argument("csvs", nargs="+")
+    c.add_argument("--stage", required=True, help="kernel names of the stage joined by '+'")
+    c.add_argument("--stage-us", type=float, required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", action="append", required=True)
+    c.add_argument("--notes", default="")
     a = ap.parse_args()
+    if a.cmd == "traffic-table":
+        with open(a.out, "w") as f:
+            f.write(traffic_table_markdown(a.fetch_csv, a.write_csv, a.kernels.split(","), a.copy_bytes,
+                                           a.fetch_command, a.write_command, a.title, a.notes))
+        return
+    if a.cmd == "counters":
+        with open(a.out, "w") as f:
+            f.write(counters_markdown(a.csvs, a.stage.split("+"), a.stage_us, a.title, a.command, a.notes))
+        return
     if a.cmd == "stats":
         with open(a.out, "w") as f:
             f.write(stats_markdown(a.csv, a.title, a.command, a.notes))
