@@ -38,7 +38,7 @@ inline uint32_t mfma_edge_record(int sender, uint16_t nd_fp16_bits) {
 enum { A_Q = 0, A_P = 1, A_H = 2, A_SA = 3, A_SB = 4, A_2 = 5, N_ATILES = 6 };
 struct MfmaStep {
     uint16_t a[N_ATILES][64][8];  // Q', P', Psi hidden from (h,1,c,deg), from sums 0..7, 8..9, Psi output (with bias)
-    float wn[10][64];             // |d| coefficient of the lane's 10 message units
+    uint32_t wn2[5][64];          // |d| coefficients of the lane's 10 message units, FP16 pairs (2t, 2t+1)
 };
 static_assert(sizeof(MfmaStep) % 16 == 0, "step blob is copied in 16-byte units");
 
@@ -65,15 +65,18 @@ struct DssMfmaArgs {
     int kbar;
     float alpha;
     int apply;                   // 1: restrict P.r and write s r~ to P.local; 0: read P.c_in, write r~
+    uint32_t lds_bytes;          // dynamic LDS of the launch (set by launch_dss_mfma)
 };
 
-// LDS of a workgroup: c (k floats), Q' (2 x (k + 1) x 5 dwords, the last row
-// of each direction the sentinel), padded edge records (ne_pad uint32), each
-// region padded to 16 bytes, then tile records (k x 16 bytes). A problem whose
-// largest need exceeds the limit is not run by this kernel.
+// LDS of a workgroup: c (k floats), one or two (db) Q' buffers of
+// 2 x (k + 1) x 5 dwords (the last row of each direction the sentinel),
+// padded edge records (ne_pad uint32), each region padded to 16 bytes, then
+// tile records (k x 16 bytes). A sub-mesh whose single-buffer need exceeds the
+// limit is not run by this kernel; one whose double-buffer need fits the
+// launch's dynamic LDS runs with two buffers.
 constexpr size_t MFMA_LDS_LIMIT = 160 * 1024 - 1024;
-inline size_t mfma_lds_need(int k, int64_t ne_pad) {
-    return (size_t)((k + 3) & ~3) * 4 + (size_t)((10 * ((int64_t)k + 1) + 3) & ~3) * 4 +
+__host__ __device__ inline size_t mfma_lds_need(int k, int64_t ne_pad, bool db = false) {
+    return (size_t)((k + 3) & ~3) * 4 + (size_t)(db ? 2 : 1) * (size_t)((10 * ((int64_t)k + 1) + 3) & ~3) * 4 +
            (size_t)((ne_pad + 3) & ~3) * 4 + (size_t)k * 16;
 }
 

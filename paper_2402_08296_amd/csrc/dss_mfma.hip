@@ -183,7 +183,14 @@ void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaStep>& steps
         for (int lane = 0; lane < 64; ++lane) put(L.a[A_2][lane], lane);
         for (int lane = 0; lane < 64; ++lane) {
             const int hf = lane / 32;
-            for (int t = 0; t < D; ++t) L.wn[t][lane] = (float)W1(hf, t, 2 * D + 2);
+            for (int t = 0; t < D / 2; ++t) {  // rounded to FP16 (nearest even) as the kernel's sums use them
+                const _Float16 lo = (_Float16)(float)W1(hf, 2 * t, 2 * D + 2);
+                const _Float16 hi = (_Float16)(float)W1(hf, 2 * t + 1, 2 * D + 2);
+                uint16_t bl, bh;
+                std::memcpy(&bl, &lo, 2);
+                std::memcpy(&bh, &hi, 2);
+                L.wn2[t][lane] = (uint32_t)bl | ((uint32_t)bh << 16);
+            }
         }
     }
     // Decoder of the last block.
@@ -299,18 +306,195 @@ __device__ inline uint32_t bf16_relu2(float lo, float hi) {
 
 __device__ inline h2 pk(float x, float y) { return (h2){(_Float16)x, (_Float16)y}; }
 
+// Tile t of a wavefront's tiles (t < MAX_TILES_PER_WAVE): its tile index,
+// the node position of lane n in it and the tile record (past the end of the
+// sub-mesh: the tile's first node).
+struct TileRef {
+    int tile, p;
+    bool valid;
+    TileNode tn;
+};
+template <int BLOCK>
+__device__ inline TileRef tile_ref(const TileNode* T, int wave, int tt, int n, int k) {
+    TileRef r;
+    r.tile = wave + (BLOCK / 64) * tt;
+    r.p = r.tile * MFMA_TILE + n;
+    r.valid = r.p < k;
+    r.tn = T[r.valid ? r.p : r.tile * MFMA_TILE];
+    return r;
+}
+__device__ inline uint32_t split_xy(const TileNode& tn, int hf) {
+    return hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
+}
+
+// The kbar blocks of DSS_theta for the wavefront's tiles (h in registers).
+// Q' lives in LDS, row stride 5 dwords, one array per message direction.
+// DB = false: one Q' buffer; per block, phase A (Q' of every tile), barrier,
+// phase B (edge sums and updates), barrier. DB = true: two Q' buffers; phase B
+// of block k reads buffer k % 2 and each tile, once updated, writes its Q' of
+// block k + 1 to the other buffer right away, so one barrier per block
+// separates the blocks (the buffer written in block k was last read in block
+// k - 1, before the previous barrier). Both give the same bits.
+template <int BLOCK, bool DB>
+__device__ __forceinline__ void dss_blocks(const DssMfmaArgs& a, float (&h)[MAX_TILES_PER_WAVE][5],
+                                           const float* cbuf, h2* Qd, const uint32_t* E, const TileNode* T,
+                                           int k, int ntiles, int wave, int lane) {
+    const int n = lane & 31, hf = lane >> 5;
+    const f32x16 zero = {};
+    const h2 hzero = {(_Float16)0.0f, (_Float16)0.0f};
+    const size_t qbuf = (size_t)((10 * (k + 1) + 3) & ~3);  // h2 entries of one Q' buffer (both directions)
+    // Q' of the wave's tiles into buffer `buf` with the Q' tile AQ: the products
+    // of two tiles are issued back to back, then converted and stored.
+    auto phase_a = [&](const bf16x8& AQ, int buf) {
+#pragma unroll
+        for (int t2 = 0; t2 < MAX_TILES_PER_WAVE; t2 += 2) {
+            f32x16 q[2];
+            int jt[2] = {-1, -1};
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (wave + (BLOCK / 64) * (t2 + u) >= ntiles) break;
+                const TileRef r = tile_ref<BLOCK>(T, wave, t2 + u, n, k);
+                jt[u] = r.valid ? (int)r.tn.j : -1;
+                q[u] = mfma(AQ, b_pq(h[t2 + u], split_xy(r.tn, hf)), zero);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (jt[u] >= 0) {
+                    h2* dst = Qd + (size_t)buf * qbuf + (size_t)(hf * (k + 1) + jt[u]) * 5;
+#pragma unroll
+                    for (int t = 0; t < 5; ++t) dst[t] = pk(q[u][2 * t], q[u][2 * t + 1]);
+                }
+            }
+        }
+    };
+    // The weights of a block are the same for every tile: each lane loads its
+    // operands once per block (the next block's Q' tile while this block runs).
+    bf16x8 AQ = load_a(a.steps[0].a[A_Q][lane]);
+    if (DB) {
+        phase_a(AQ, 0);
+        if (a.kbar > 1) AQ = load_a(a.steps[1].a[A_Q][lane]);
+        __syncthreads();
+    }
+    for (int step = 0; step < a.kbar; ++step) {
+        const MfmaStep* L = a.steps + step;
+        const int cur = DB ? (step & 1) : 0;
+        if (!DB) phase_a(AQ, 0);
+        // the operands every tile needs before its edge sums (the Psi operands
+        // are fetched per tile, their latency hidden behind the tile's edge sums)
+        const bf16x8 AP = load_a(L->a[A_P][lane]);
+        h2 wn[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) wn[t] = __builtin_bit_cast(h2, L->wn2[t][lane]);
+        if (!DB) {
+            if (step + 1 < a.kbar) AQ = load_a(a.steps[step + 1].a[A_Q][lane]);
+            __syncthreads();
+        }
+        const h2* Qh = Qd + (size_t)cur * qbuf + (size_t)hf * 5 * (k + 1);  // this lane's direction
+        const bool next = DB && step + 1 < a.kbar;
+        // Phase B: receiver projections, edge sums, Psi update (and with DB the
+        // tile's Q' of the next block).
+#pragma unroll
+        for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt) {
+            if (wave + (BLOCK / 64) * tt >= ntiles) break;
+            const TileRef r = tile_ref<BLOCK>(T, wave, tt, n, k);
+            const TileNode& tn = r.tn;
+            const int j = tn.j;
+            const uint32_t xy2 = split_xy(tn, hf);
+            const f32x16 Pf = mfma(AP, b_pq(h[tt], xy2), zero);
+            const bf16x8 AH = load_a(L->a[A_H][lane]), A2 = load_a(L->a[A_2][lane]);
+            const f16x8 ASA = load_a16(L->a[A_SA][lane]), ASB = load_a16(L->a[A_SB][lane]);
+            h2 P[5], S[5];
+#pragma unroll
+            for (int t = 0; t < 5; ++t) {
+                P[t] = pk(Pf[2 * t], Pf[2 * t + 1]);
+                S[t] = hzero;
+            }
+            const int deg = r.valid ? (int)tn.deg : 0;
+            // The tile's edge block: EC slots per chunk, one column per lane
+            // (lanes past the end of the sub-mesh read sentinel records).
+            const uint32_t* Et = E + (tn.e0 & 0xffffff) + n;
+            const int nch = __builtin_amdgcn_readfirstlane((int)((uint32_t)tn.e0 >> 24));
+            // The records of the next chunk are in flight while a chunk's sums
+            // run; a load past the last chunk re-reads the last chunk (clamped
+            // index) and goes unused.
+            auto ld_rec = [&](int ch, uint32_t (&rc)[EC]) {
+                const int c = min(ch, nch - 1);
+#pragma unroll
+                for (int w = 0; w < EC; ++w) rc[w] = Et[(c * EC + w) * MFMA_TILE];
+            };
+            auto ld_q = [&](const uint32_t (&rc)[EC], h2 (&q)[EC][5]) {
+#pragma unroll
+                for (int w = 0; w < EC; ++w) {
+                    const h2* row = reinterpret_cast<const h2*>(reinterpret_cast<const char*>(Qh) + (rc[w] >> 16));
+#pragma unroll
+                    for (int t = 0; t < 5; ++t) q[w][t] = row[t];
+                }
+            };
+            auto sums = [&](const uint32_t (&rc)[EC], const h2 (&q)[EC][5]) {
+#pragma unroll
+                for (int w = 0; w < EC; ++w) {
+                    const _Float16 ndh = __builtin_bit_cast(_Float16, (uint16_t)(rc[w] & 0xffffu));
+                    const h2 nd = {ndh, ndh};
+#pragma unroll
+                    for (int t = 0; t < 5; ++t)
+                        S[t] += __builtin_elementwise_max(__builtin_elementwise_fma(wn[t], nd, P[t] + q[w][t]), hzero);
+                }
+            };
+            if (nch > 0) {
+                uint32_t r0[EC];
+                ld_rec(0, r0);
+                for (int ch = 0; ch < nch; ++ch) {
+                    h2 q[EC][5];
+                    ld_q(r0, q);
+                    uint32_t r1[EC];
+                    ld_rec(ch + 1, r1);
+                    sums(r0, q);
+#pragma unroll
+                    for (int w = 0; w < EC; ++w) r0[w] = r1[w];
+                }
+            }
+            const float c = cbuf[j];
+            // The message sums enter the FP16 matrix product as they are.
+            const f16x8 sa = {S[0][0], S[0][1], S[1][0], S[1][1], S[2][0], S[2][1], S[3][0], S[3][1]};
+            const _Float16 hz = (_Float16)0.0f;
+            const f16x8 sb = {S[4][0], S[4][1], hz, hz, hz, hz, hz, hz};
+            f32x16 hid = mfma(AH, b_psi(h[tt], c, (float)deg), zero);
+            hid = mfma16(ASA, sa, hid);
+            hid = mfma16(ASB, sb, hid);
+            // (ReLU(hidden) 5 components, 1 for the output bias column, 0, 0)
+            const bf16x8 bh = __builtin_bit_cast(
+                bf16x8, (uint4){bf16_relu2(hid[0], hid[1]), bf16_relu2(hid[2], hid[3]), bf16_relu2(hid[4], 1.0f), 0u});
+            const f32x16 o = mfma(A2, bh, zero);
+            if (r.valid) {
+#pragma unroll
+                for (int t = 0; t < 5; ++t) h[tt][t] = fmaf(a.alpha, o[t], h[tt][t]);
+                if (next) {
+                    const f32x16 q = mfma(AQ, b_pq(h[tt], xy2), zero);
+                    h2* dst = Qd + (size_t)(cur ^ 1) * qbuf + (size_t)(hf * (k + 1) + j) * 5;
+#pragma unroll
+                    for (int t = 0; t < 5; ++t) dst[t] = pk(q[2 * t], q[2 * t + 1]);
+                }
+            }
+        }
+        if (DB && step + 2 < a.kbar) AQ = load_a(a.steps[step + 2].a[A_Q][lane]);
+        __syncthreads();
+    }
+}
+
 // One workgroup per sub-mesh, everything the kbar blocks touch in LDS:
 //   c   [k]        normalised residual (FP32)
-//   Q'  [2][k+1][5] neighbour projections (FP16 pairs), one array per
-//                  direction, row k the -inf sentinel; the odd 5-dword row
-//                  stride spreads the random sender rows of an edge gather
-//                  over all LDS banks
+//   Q'  [nb][2][k+1][5] neighbour projections (FP16 pairs) in nb = 1 or 2
+//                  buffers, one array per direction, row k the -inf
+//                  sentinel; the odd 5-dword row stride spreads the random
+//                  sender rows of an edge gather over all LDS banks
 //   E   [ne_pad]   in-edge records per tile, slot-major ([slot][lane], so a
 //                  wavefront reads consecutive dwords), padded with sentinel
 //                  records to the tile's largest in-degree rounded up to EC:
 //                  FP16 |d| | sender row byte offset << 16
 //   T   [k]        tile records (node id, degree, first edge, split coordinates)
-// The message sums run in packed FP16 (two units per instruction).
+// A sub-mesh runs with two Q' buffers when they fit the launch's dynamic LDS
+// (a.lds_bytes), else with one. The message sums run in packed FP16 (two
+// units per instruction).
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     constexpr int VT = MFMA_BLOCK / BLOCK;  // virtual threads per thread in the restriction sums
@@ -325,19 +509,21 @@ __global__ __launch_bounds__(BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     const int tid = threadIdx.x;
     const int ebase = P.epad_sub[sub];
     const int ne = P.epad_sub[sub + 1] - ebase;
+    const bool db = mfma_lds_need(k, ne, true) <= a.lds_bytes;
+    const int nbuf = db ? 2 : 1;
     double* __restrict__ out = P.local;
     float* cbuf = lds;
     h2* Qd = reinterpret_cast<h2*>(lds + ((k + 3) & ~3));
-    uint32_t* E = reinterpret_cast<uint32_t*>(Qd + ((10 * (k + 1) + 3) & ~3));
+    uint32_t* E = reinterpret_cast<uint32_t*>(Qd + (size_t)nbuf * ((10 * (k + 1) + 3) & ~3));
     TileNode* T = reinterpret_cast<TileNode*>(E + ((ne + 3) & ~3));
     for (int i = tid; i < ne; i += BLOCK) E[i] = P.erec[ebase + i];
-    if (tid < 10) {  // sentinel rows: every message through them is ReLU(-inf) = 0
+    if (tid < 10 * nbuf) {  // sentinel rows: every message through them is ReLU(-inf) = 0
         const _Float16 ninf = __builtin_bit_cast(_Float16, (uint16_t)0xFC00u);
-        Qd[(size_t)(tid / 5) * 5 * (k + 1) + 5 * k + tid % 5] = (h2){ninf, ninf};
+        const int b = tid / 10, t = tid % 10;
+        Qd[(size_t)b * ((10 * (k + 1) + 3) & ~3) + (size_t)(t / 5) * 5 * (k + 1) + 5 * k + t % 5] = (h2){ninf, ninf};
     }
     for (int i = tid; i < k; i += BLOCK)
         reinterpret_cast<uint4*>(T)[i] = reinterpret_cast<const uint4*>(P.tiles + base)[i];
-
     // Restriction and normalisation (Sec. III.A step 2).
     double s = 1.0;
     if (a.apply) {
@@ -372,7 +558,6 @@ __global__ __launch_bounds__(BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
 
     const int wave = tid >> 6, lane = tid & 63;
     const int n = lane & 31, hf = lane >> 5;
-    const h2* Qh = Qd + (size_t)hf * 5 * (k + 1);  // this lane's direction
     const int ntiles = (k + MFMA_TILE - 1) / MFMA_TILE;
     float h[MAX_TILES_PER_WAVE][5];
 #pragma unroll
@@ -380,119 +565,10 @@ __global__ __launch_bounds__(BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
 #pragma unroll
         for (int t = 0; t < 5; ++t) h[tt][t] = 0.0f;
     const f32x16 zero = {};
-    const h2 hzero = {(_Float16)0.0f, (_Float16)0.0f};
-
-    for (int step = 0; step < a.kbar; ++step) {
-        const MfmaStep* L = a.steps + step;
-        // Phase A: neighbour projections Q' -> LDS (FP16).
-        {
-            const bf16x8 AQ = load_a(L->a[A_Q][lane]);
-#pragma unroll
-            for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt) {
-                const int tile = wave + (BLOCK / 64) * tt;
-                if (tile >= ntiles) break;
-                const int p = tile * MFMA_TILE + n;
-                const bool valid = p < k;
-                const TileNode tn = T[valid ? p : tile * MFMA_TILE];
-                const uint32_t xy2 = hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
-                const f32x16 q = mfma(AQ, b_pq(h[tt], xy2), zero);
-                if (valid) {
-                    h2* dst = Qd + (size_t)(hf * (k + 1) + tn.j) * 5;
-#pragma unroll
-                    for (int t = 0; t < 5; ++t) dst[t] = pk(q[2 * t], q[2 * t + 1]);
-                }
-            }
-        }
-        __syncthreads();
-        // Phase B: receiver projections, edge sums, Psi update.
-        {
-            const bf16x8 AP = load_a(L->a[A_P][lane]);
-            h2 wn[5];
-#pragma unroll
-            for (int t = 0; t < 5; ++t) wn[t] = pk(L->wn[2 * t][lane], L->wn[2 * t + 1][lane]);
-#pragma unroll
-            for (int tt = 0; tt < MAX_TILES_PER_WAVE; ++tt) {
-                const int tile = wave + (BLOCK / 64) * tt;
-                if (tile >= ntiles) break;
-                const int p = tile * MFMA_TILE + n;
-                const bool valid = p < k;
-                const TileNode tn = T[valid ? p : tile * MFMA_TILE];  // past the end: the tile's first node
-                const int j = tn.j;
-                const uint32_t xy2 = hf ? (uint32_t)tn.yh | ((uint32_t)tn.yl << 16) : (uint32_t)tn.xh | ((uint32_t)tn.xl << 16);
-                const f32x16 Pf = mfma(AP, b_pq(h[tt], xy2), zero);
-                // Psi weights, fetched now so their latency overlaps the edge sums
-                const bf16x8 AH = load_a(L->a[A_H][lane]), A2 = load_a(L->a[A_2][lane]);
-                const f16x8 ASA = load_a16(L->a[A_SA][lane]), ASB = load_a16(L->a[A_SB][lane]);
-                h2 P[5], S[5];
-#pragma unroll
-                for (int t = 0; t < 5; ++t) {
-                    P[t] = pk(Pf[2 * t], Pf[2 * t + 1]);
-                    S[t] = hzero;
-                }
-                const int deg = valid ? (int)tn.deg : 0;
-                // The tile's edge block: EC slots per chunk, one column per lane
-                // (lanes past the end of the sub-mesh read sentinel records).
-                const uint32_t* Et = E + (tn.e0 & 0xffffff) + n;
-                const int nch = __builtin_amdgcn_readfirstlane((int)((uint32_t)tn.e0 >> 24));
-                // The records of the next chunk are in flight while a chunk's sums
-                // run; a load past the last chunk re-reads the last chunk (clamped
-                // index) and goes unused.
-                auto ld_rec = [&](int ch, uint32_t (&r)[EC]) {
-                    const int c = min(ch, nch - 1);
-#pragma unroll
-                    for (int w = 0; w < EC; ++w) r[w] = Et[(c * EC + w) * MFMA_TILE];
-                };
-                auto ld_q = [&](const uint32_t (&r)[EC], h2 (&q)[EC][5]) {
-#pragma unroll
-                    for (int w = 0; w < EC; ++w) {
-                        const h2* row = reinterpret_cast<const h2*>(reinterpret_cast<const char*>(Qh) + (r[w] >> 16));
-#pragma unroll
-                        for (int t = 0; t < 5; ++t) q[w][t] = row[t];
-                    }
-                };
-                auto sums = [&](const uint32_t (&r)[EC], const h2 (&q)[EC][5]) {
-#pragma unroll
-                    for (int w = 0; w < EC; ++w) {
-                        const _Float16 ndh = __builtin_bit_cast(_Float16, (uint16_t)(r[w] & 0xffffu));
-                        const h2 nd = {ndh, ndh};
-#pragma unroll
-                        for (int t = 0; t < 5; ++t)
-                            S[t] += __builtin_elementwise_max(__builtin_elementwise_fma(wn[t], nd, P[t] + q[w][t]), hzero);
-                    }
-                };
-                if (nch > 0) {
-                    uint32_t r0[EC];
-                    ld_rec(0, r0);
-                    for (int ch = 0; ch < nch; ++ch) {
-                        h2 q[EC][5];
-                        ld_q(r0, q);
-                        uint32_t r1[EC];
-                        ld_rec(ch + 1, r1);
-                        sums(r0, q);
-#pragma unroll
-                        for (int w = 0; w < EC; ++w) r0[w] = r1[w];
-                    }
-                }
-                const float c = cbuf[j];
-                // The message sums enter the FP16 matrix product as they are.
-                const f16x8 sa = {S[0][0], S[0][1], S[1][0], S[1][1], S[2][0], S[2][1], S[3][0], S[3][1]};
-                const _Float16 hz = (_Float16)0.0f;
-                const f16x8 sb = {S[4][0], S[4][1], hz, hz, hz, hz, hz, hz};
-                f32x16 hid = mfma(AH, b_psi(h[tt], c, (float)deg), zero);
-                hid = mfma16(ASA, sa, hid);
-                hid = mfma16(ASB, sb, hid);
-                // (ReLU(hidden) 5 components, 1 for the output bias column, 0, 0)
-                const bf16x8 bh = __builtin_bit_cast(
-                    bf16x8, (uint4){bf16_relu2(hid[0], hid[1]), bf16_relu2(hid[2], hid[3]), bf16_relu2(hid[4], 1.0f), 0u});
-                const f32x16 o = mfma(A2, bh, zero);
-                if (valid) {
-#pragma unroll
-                    for (int t = 0; t < 5; ++t) h[tt][t] = fmaf(a.alpha, o[t], h[tt][t]);
-                }
-            }
-        }
-        __syncthreads();
-    }
+    if (db)
+        dss_blocks<BLOCK, true>(a, h, cbuf, Qd, E, T, k, ntiles, wave, lane);
+    else
+        dss_blocks<BLOCK, false>(a, h, cbuf, Qd, E, T, k, ntiles, wave, lane);
 
     // Decoder of the last block.
     const MfmaDec* Ld = a.dec + lane;
@@ -526,9 +602,11 @@ hipError_t prepare_dss_mfma(size_t shmem) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
 }
 
-hipError_t launch_dss_mfma(const DssMfmaArgs& a, int n_work, size_t shmem, int block, hipStream_t stream,
+hipError_t launch_dss_mfma(const DssMfmaArgs& args, int n_work, size_t shmem, int block, hipStream_t stream,
                            bool check) {
     if (n_work <= 0) return hipSuccess;
+    DssMfmaArgs a = args;
+    a.lds_bytes = (uint32_t)shmem;
     if (block == MFMA_SMALL_BLOCK)
         hipLaunchKernelGGL(dss_mfma_kernel<MFMA_SMALL_BLOCK>, dim3(n_work), dim3(MFMA_SMALL_BLOCK), shmem, stream, a);
     else

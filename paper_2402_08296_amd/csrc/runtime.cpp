@@ -604,6 +604,7 @@ int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& 
         return a.sub < b.sub;
     });
     std::vector<int2> wa, wm, wms, wr, wv, wb;
+    size_t lds_sb = 0, lds_db = 0, lds_small_sb = 0, lds_small_db = 0;
     for (const W& w : all) {
         wa.push_back(make_int2(w.p, w.sub));
         B->max_k_all = std::max(B->max_k_all, w.k);
@@ -616,18 +617,26 @@ int build_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int n, BatchPtr& 
         B->max_k_valu = std::max(B->max_k_valu, w.k);
         if (mfma_runs_sub(Q, w.sub)) {
             const size_t need = Q->mfma_need[w.sub];
+            // Each launch reserves the largest need of its members; with two Q'
+            // buffers where they fit that reserve (up to the kernel's limit, or
+            // half a compute unit's LDS for the small workgroups), one otherwise.
+            const size_t need_db = Q->mfma_need_db[w.sub];
             if (w.k <= MFMA_SMALL_K && need <= (size_t)Q->tune.small_lds) {
                 wms.push_back(make_int2(w.p, w.sub));
-                B->lds_mfma_small = std::max(B->lds_mfma_small, need);
+                lds_small_sb = std::max(lds_small_sb, need);
+                if (need_db <= MFMA_SMALL_LDS) lds_small_db = std::max(lds_small_db, need_db);
             } else {
                 wm.push_back(make_int2(w.p, w.sub));
-                B->lds_mfma = std::max(B->lds_mfma, need);
+                lds_sb = std::max(lds_sb, need);
+                if (need_db <= MFMA_LDS_LIMIT) lds_db = std::max(lds_db, need_db);
             }
         } else {
             wr.push_back(make_int2(w.p, w.sub));
             B->max_k_rest = std::max(B->max_k_rest, w.k);
         }
     }
+    B->lds_mfma = std::max(lds_sb, lds_db);
+    B->lds_mfma_small = std::max(lds_small_sb, lds_small_db);
     hipStream_t s = ctx->stream;
     if (int rc = upload_list(B->work_all, wa, s)) return rc;
     if (int rc = upload_list(B->work_mfma, wm, s)) return rc;
@@ -871,6 +880,7 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
         er.reserve((size_t)hs.n_edges * 2 + 1);
         std::vector<int32_t> epad(K + 1, 0);
         P->mfma_need.assign(K, 0);
+        P->mfma_need_db.assign(K, 0);
         std::vector<TileNode> tiles(sk);
         for (int i = 0; i < K; ++i) {
             const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
@@ -878,6 +888,7 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
             epad[i] = (int32_t)er.size();
             if (k > kMaxSubNodes) {  // the VALU kernel's global-memory form runs it: no tile records
                 P->mfma_need[i] = UINT32_MAX;
+                P->mfma_need_db[i] = UINT32_MAX;
                 P->has_big = true;
                 continue;
             }
@@ -931,6 +942,7 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
                 }
             }
             P->mfma_need[i] = (uint32_t)mfma_lds_need(k, (int64_t)er.size() - epad[i]);
+            P->mfma_need_db[i] = (uint32_t)mfma_lds_need(k, (int64_t)er.size() - epad[i], true);
         }
         epad[K] = (int32_t)er.size();
         HIP_TRY(P->tiles.upload(tiles.data(), tiles.size(), s));
@@ -1362,7 +1374,8 @@ int ddmgnn_dss_forward_sub(ddmgnn_ctx* ctx, ddmgnn_problem* P, int32_t precision
                                M.theta64.p, s, true));
     } else if (precision == DDMGNN_BF16 && mfma_runs_sub(P, sub)) {
         DssMfmaArgs a{B.hook.p, P->one_work.p, M.steps.p, M.dec.p, M.kbar, (float)M.alpha, 0};
-        HIP_TRY(launch_dss_mfma(a, 1, P->mfma_need[sub], MFMA_BLOCK, s, true));
+        const size_t shmem = P->mfma_need_db[sub] <= MFMA_LDS_LIMIT ? P->mfma_need_db[sub] : P->mfma_need[sub];
+        HIP_TRY(launch_dss_mfma(a, 1, shmem, MFMA_BLOCK, s, true));
     } else {
         const int mk = precision == DDMGNN_BF16 ? B.max_k_rest : B.max_k_valu;  // as prepare_dss sized it
         const bool qlds = valu_q_in_lds(mk, vprec, M.d);

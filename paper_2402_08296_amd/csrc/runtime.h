@@ -164,6 +164,7 @@ struct ddmgnn_problem {
     ddmgnn::DevBuf<float> edge_nd;   // padded by 8 entries
     std::vector<uint32_t> mfma_need; // per sub-mesh, LDS bytes of the MFMA kernel (UINT32_MAX: beyond
                                      // its node budget, no tile records)
+    std::vector<uint32_t> mfma_need_db;  // the same with two Q' buffers (one barrier per block)
     bool has_big = false;            // a sub-mesh of more than kMaxSubNodes nodes
     ddmgnn_tuning tune{};            // launch schedule (ddmgnn_problem_set_tuning / ddmgnn_autotune)
     // one-sub-mesh forward entry: per-slot input and output, and its one-item work list
