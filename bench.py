@@ -159,9 +159,9 @@ def bench_lu(dg, prob, u, hp, steps: int) -> dict:
     opts = dg.default_opts(krylov=dg.PCG, local_solver=dg.LOCAL_LU, prolong=dg.PROLONG_UNWEIGHTED,
                            precision="fp64", rtol=1e-6, max_it=5000, check_every=16)
     t = time.perf_counter()
-    first = prob.solve(u, opts, check=False)  # forms and uploads the local inverses
+    first = prob.solve(u, opts, check=False)  # assembles and inverts the local matrices on the device
     setup_s = time.perf_counter() - t - first.solve_ms * 1e-3
-    log(f"DDM-LU first solve: iterations={first.iterations} setup={setup_s:.1f}s")
+    log(f"DDM-LU first solve: iterations={first.iterations} factorisation={setup_s:.3f}s")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -182,7 +182,9 @@ def bench_lu(dg, prob, u, hp, steps: int) -> dict:
         traffic = tr["traffic_bytes_per_dispatch"]
     return {"krylov": "PCG", "prolong": "unweighted", "iterations": st.iterations, "converged": bool(st.converged),
             "true_rel_residual": st.true_rel_residual, "time_to_solution_ms": 1e3 * elapsed,
-            "solves_per_s": 1.0 / elapsed, "host_setup_s": setup_s, "device_bytes": prob.device_bytes(),
+            "solves_per_s": 1.0 / elapsed, "factorisation_s": setup_s,
+            "factorisation": "R_i A R_i^T assembled and inverted on the device (blocked Gauss-Jordan, FP64)",
+            "device_bytes": prob.device_bytes(),
             "breakdown_ms_per_iteration": {"local": local_ms, "coarse": sp.coarse_ms / n_it,
                                            "prolong": sp.prolong_ms / n_it, "krylov": sp.krylov_ms / n_it},
             "roofline": {"kernel": "lu_local_kernel", "bound": "hbm", "achieved": achieved, "peak": HBM_GBPS,

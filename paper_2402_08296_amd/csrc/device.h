@@ -153,6 +153,23 @@ hipError_t launch_dss_big(const DevProb* tab, const int2* work, int n_work, int 
 // prepare_lu_local raises the kernel's LDS limit to kMaxSubNodesAny doubles
 // (not allowed during stream capture).
 hipError_t prepare_lu_local();
+// Device factorisation of DDM-LU (factor.hip): assembles A_i = R_i A R_i^T of
+// every sub-mesh (row stride lu_ld(k_i), sub-mesh i at off[i] in inv) and
+// inverts it in place (blocked Gauss-Jordan, no pivoting: SPD). *status (device,
+// zeroed by the caller) gets bit 0 set when a pivot is not positive.
+hipError_t launch_lu_factor(const int32_t* rowptr, const int32_t* col, const double* val, const int64_t* sub_ptr,
+                            const int32_t* sub_nodes, const int64_t* off, double* inv, int n_sub, int* status,
+                            hipStream_t s);
+// Coarse level on the device (factor.hip): A_0 = Z^T A Z assembled into a0inv
+// (K x K, deterministic summation order), symmetrised and inverted in place by
+// blocked Gauss-Jordan over the whole device. scratch: coarse_setup_scratch(K)
+// doubles. *status (device, zeroed by the caller) gets bit 0 set when a pivot
+// is not positive (A_0 not SPD).
+hipError_t launch_coarse_setup(const int32_t* rowptr, const int32_t* col, const double* val, const int32_t* sub_ptr,
+                               const int32_t* sub_nodes, const double* weights, const int32_t* node_ptr,
+                               const int32_t* node_slots, const int32_t* slot_sub, int K, double* a0inv,
+                               double* scratch, int* status, hipStream_t s);
+size_t coarse_setup_scratch(int K);
 hipError_t launch_lu_local(const DevProb* tab, const int2* work, int n_work, int max_k, hipStream_t s, bool check);
 hipError_t launch_coarse(const DevProb* tab, const int2* rows, int n_rows, hipStream_t s, bool check);
 // The Krylov launchers end with a finalize launch of one workgroup per

@@ -117,35 +117,40 @@ size_t valu_shmem(int max_k, int precision, int d) {
     return (size_t)max_k * 2 * d * esz;
 }
 
-// Exact local solves: the inverses of R_i A R_i^T, formed on the host from the
-// problem's matrix and sub-meshes (downloaded once) and uploaded.
+// Exact local solves: the inverses of R_i A R_i^T, assembled from the problem's
+// device matrix and inverted on the device (one workgroup per sub-mesh).
 int prepare_lu(ddmgnn_problem* P) {
     HIP_TRY(prepare_lu_local());
     if (P->lu_inv.p) return DDMGNN_OK;
     hipStream_t s = P->ctx->stream;
     const auto& hs = P->hs;
-    std::vector<int32_t> rowptr(hs.n + 1), col(hs.nnz), sub_nodes(hs.sk);
-    std::vector<double> val(hs.nnz);
-    HIP_TRY(hipMemcpyAsync(rowptr.data(), P->rowptr.p, rowptr.size() * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(col.data(), P->col.p, col.size() * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(val.data(), P->val.p, val.size() * 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(sub_nodes.data(), P->sub_nodes.p, sub_nodes.size() * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    ddmgnn_problem_desc d{};
-    d.n_nodes = hs.n;
-    d.a_rowptr = rowptr.data();
-    d.a_col = col.data();
-    d.a_val = val.data();
-    d.n_sub = hs.K;
-    d.sub_ptr = hs.sub_ptr.data();
-    d.sub_nodes = sub_nodes.data();
-    std::vector<double> inv;
-    std::vector<int64_t> off;
-    if (!build_local_inverses(d, inv, off).empty())
-        return fail(DDMGNN_E_NOT_SPD, "a local matrix R_i A R_i^T is not positive definite");
-    HIP_TRY(P->lu_off.upload(off.data(), off.size(), s));
-    HIP_TRY(P->lu_inv.upload(inv.data(), inv.size(), s));
-    P->device_bytes += inv.size() * sizeof(double) + off.size() * sizeof(int64_t);
+    std::vector<int64_t> off((size_t)hs.K + 1, 0);
+    for (int32_t i = 0; i < hs.K; ++i) {
+        const int64_t k = hs.sub_ptr[i + 1] - hs.sub_ptr[i];
+        off[i + 1] = off[i] + k * lu_ld(k);
+    }
+    auto build = [&]() -> int {
+        DevBuf<int64_t> sub_ptr64;
+        DevBuf<int> status;
+        HIP_TRY(sub_ptr64.upload(hs.sub_ptr.data(), hs.sub_ptr.size(), s));
+        HIP_TRY(P->lu_off.upload(off.data(), off.size(), s));
+        HIP_TRY(P->lu_inv.alloc((size_t)std::max<int64_t>(off[hs.K], 1)));
+        HIP_TRY(status.alloc(1));
+        HIP_TRY(hipMemsetAsync(status.p, 0, sizeof(int), s));
+        HIP_TRY(launch_lu_factor(P->rowptr.p, P->col.p, P->val.p, sub_ptr64.p, P->sub_nodes.p, P->lu_off.p,
+                                 P->lu_inv.p, hs.K, status.p, s));
+        int bad = 0;
+        HIP_TRY(hipMemcpyAsync(&bad, status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (bad) return fail(DDMGNN_E_NOT_SPD, "a local matrix R_i A R_i^T is not positive definite");
+        return DDMGNN_OK;
+    };
+    if (int rc = build()) {  // leave no half-built inverses behind
+        P->lu_inv.reset();
+        P->lu_off.reset();
+        return rc;
+    }
+    P->device_bytes += (size_t)off[hs.K] * sizeof(double) + off.size() * sizeof(int64_t);
     return DDMGNN_OK;
 }
 
@@ -865,7 +870,23 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
     }
     HIP_TRY(P->xy64.upload(xy64.data(), 2 * sk, s));
     HIP_TRY(P->xyc32.upload(xyc32.data(), 2 * sk, s));
-    HIP_TRY(P->a0inv.upload(hs.a0inv.data(), (size_t)K * K, s));
+    if (!hs.a0inv.empty()) {
+        HIP_TRY(P->a0inv.upload(hs.a0inv.data(), (size_t)K * K, s));
+    } else {  // the coarse operator and its inverse, formed on the device
+        DevBuf<double> scratch;
+        DevBuf<int> status;
+        HIP_TRY(P->a0inv.alloc((size_t)K * K));
+        HIP_TRY(scratch.alloc(coarse_setup_scratch(K)));
+        HIP_TRY(status.alloc(1));
+        HIP_TRY(hipMemsetAsync(status.p, 0, sizeof(int), s));
+        HIP_TRY(launch_coarse_setup(P->rowptr.p, P->col.p, P->val.p, P->sub_ptr.p, P->sub_nodes.p, P->weights.p,
+                                    P->node_ptr.p, P->node_slots.p, P->slot_sub.p, K, P->a0inv.p, scratch.p,
+                                    status.p, s));
+        int bad = 0;
+        HIP_TRY(hipMemcpyAsync(&bad, status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (bad) return fail(DDMGNN_E_NOT_SPD, "coarse matrix R_0 A R_0^T is not positive definite");
+    }
     if (!hs.lu_inv.empty()) {
         HIP_TRY(P->lu_off.upload(hs.lu_off.data(), hs.lu_off.size(), s));
         HIP_TRY(P->lu_inv.upload(hs.lu_inv.data(), hs.lu_inv.size(), s));
@@ -1137,8 +1158,7 @@ int ddmgnn_problem_create(ddmgnn_ctx* ctx, const ddmgnn_problem_desc* desc_in, c
     int rc = ddmgnn_validate_problem(desc);
     if (rc) return rc;
     HostSetup hs;
-    std::string e = build_setup(*desc, hs);
-    if (e == "NOT_SPD") return fail(DDMGNN_E_NOT_SPD, "coarse matrix R_0 A R_0^T is not positive definite");
+    std::string e = build_setup(*desc, hs, false);  // the coarse level is formed on the device
     if (!e.empty()) return fail(DDMGNN_E_INVALID, e);
     return create_problem(ctx, *desc, model->dev, std::move(hs), out);
 }

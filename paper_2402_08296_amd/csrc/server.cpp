@@ -157,7 +157,7 @@ void ddmgnn_server::setup_worker() {
         }
         r->t_setup0 = Clock::now();
         std::string e = validate(r->desc);
-        if (e.empty()) e = build_setup(r->desc, r->hs);
+        if (e.empty()) e = build_setup(r->desc, r->hs, false);  // coarse level: on the device at admission
         const bool lu = r->opts.local_solver == DDMGNN_LOCAL_LU && r->opts.krylov != DDMGNN_CG;
         if (e == "NOT_SPD") {
             r->setup_rc = DDMGNN_E_NOT_SPD;
@@ -165,12 +165,16 @@ void ddmgnn_server::setup_worker() {
         } else if (!e.empty()) {
             r->setup_rc = DDMGNN_E_INVALID;
             r->err = e;
-        } else if (lu && !build_local_inverses(r->desc, r->hs.lu_inv, r->hs.lu_off).empty()) {
-            r->setup_rc = DDMGNN_E_NOT_SPD;
-            r->err = "a local matrix R_i A R_i^T is not positive definite";
         } else {
-            r->bytes = problem_device_bytes(r->hs.n, r->hs.nnz, r->hs.K, r->hs.sk, r->hs.n_edges) +
-                       r->hs.lu_inv.size() * sizeof(double) + r->hs.lu_off.size() * sizeof(int64_t) +
+            // DDM-LU requests: the local inverses are formed on the device at the
+            // first solve; their bytes count in the admission budget.
+            size_t lu_bytes = 0;
+            if (lu)
+                for (int32_t i = 0; i < r->hs.K; ++i) {
+                    const int64_t k = r->hs.sub_ptr[i + 1] - r->hs.sub_ptr[i];
+                    lu_bytes += (size_t)(k * lu_ld(k)) * sizeof(double) + sizeof(int64_t);
+                }
+            r->bytes = problem_device_bytes(r->hs.n, r->hs.nnz, r->hs.K, r->hs.sk, r->hs.n_edges) + lu_bytes +
                        (r->opts.krylov == DDMGNN_FGMRES ? fgmres_bytes(r->hs.n, r->opts.restart) : 0);
         }
         r->t_setup1 = Clock::now();

@@ -480,8 +480,9 @@ std::string build_local_inverses(const ddmgnn_problem_desc& d, std::vector<doubl
     return bad.load() >= 0 ? "NOT_SPD" : "";
 }
 
-std::string build_setup(const ddmgnn_problem_desc& d, HostSetup& s) {
+std::string build_setup(const ddmgnn_problem_desc& d, HostSetup& s, bool coarse) {
     build_local_graphs(d, s);
+    if (!coarse) return "";
     const int64_t n = d.n_nodes;
     const int32_t K = d.n_sub;
 

@@ -83,8 +83,9 @@ inline float bf16_bits_float(uint16_t b) {
 // Local DSS graphs, slot_sub, node membership lists and work order only.
 void build_local_graphs(const ddmgnn_problem_desc& d, HostSetup& s);
 
-// Builds everything above. Returns "" on success, "NOT_SPD" if the coarse
-// Cholesky fails, else an error message.
-std::string build_setup(const ddmgnn_problem_desc& d, HostSetup& s);
+// Builds everything above (the coarse operator and its inverse only when
+// `coarse`; the library forms them on the device). Returns "" on success,
+// "NOT_SPD" if the coarse Cholesky fails, else an error message.
+std::string build_setup(const ddmgnn_problem_desc& d, HostSetup& s, bool coarse = true);
 
 }  // namespace ddmgnn
