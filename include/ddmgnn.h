@@ -397,6 +397,20 @@ int ddmgnn_pou_weights(int64_t n_nodes, const uint8_t* dirichlet, int32_t n_sub,
 
 void ddmgnn_free(void* p);
 
+/* The overlapping decomposition on the device (Sec. II.A, overlap of Sec. IV.A):
+ * the sub-meshes of ddmgnn_expand_overlap and the weights of ddmgnn_pou_weights,
+ * equal to theirs, computed on the GPU of the context. tri (3 n_tri int32),
+ * part (n_nodes int32 in [0, n_part)) and dirichlet (n_nodes uint8): device.
+ * sub_ptr_out: host, n_part + 1 int64, always filled when the ids are valid.
+ * sub_nodes_out (int32) and weights_out (double): device, room for cap
+ * entries; when sub_ptr_out[n_part] > cap the call returns E_INVALID after
+ * filling sub_ptr_out (cap = 0 asks for the size only). E_INVALID also for ids
+ * out of range, a node in more than 16 sub-meshes or a sub-mesh above 16384
+ * nodes. Synchronous on the context's stream; allocates device scratch. */
+int ddmgnn_expand_overlap_device(ddmgnn_ctx* ctx, int64_t n_nodes, int64_t n_tri, const int32_t* tri,
+                                 const int32_t* part, const uint8_t* dirichlet, int32_t n_part, int32_t delta,
+                                 int64_t* sub_ptr_out, int32_t* sub_nodes_out, double* weights_out, int64_t cap);
+
 /* Launch schedule of a problem: the choices of ddmgnn_autotune. small_lds never
  * changes a result; vec_blocks changes the order of the Krylov reductions (the
  * rounding, not the accuracy). */

@@ -133,6 +133,7 @@ def lib():
                                                  ctypes.POINTER(_p)]),
         "ddmgnn_pou_weights": (ctypes.c_int, [_i64, _p, _i32, _p, _p, _p]),
         "ddmgnn_free": (None, [_p]),
+        "ddmgnn_expand_overlap_device": (ctypes.c_int, [_p, _i64, _i64, _p, _p, _p, _i32, _i32, _p, _p, _p, _i64]),
         "ddmgnn_problem_sizes": (ctypes.c_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                                 ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
         "ddmgnn_setup_local_graph": (ctypes.c_int, [ctypes.POINTER(ProblemDesc), _i32, _p, _p,
@@ -393,6 +394,27 @@ class Context:
         xp, yp = _devs((x, "float64", None, "x"), (y, "float64", x.numel(), "y"))
         _check(lib().ddmgnn_dot(self.h, x.numel(), xp, yp, ctypes.byref(out)))
         return out.value
+
+    def expand_overlap_device(self, n: int, tri, part, dirichlet, n_part: int, delta: int):
+        """Overlapping sub-meshes and partition-of-unity weights computed on the device:
+        (sub_ptr int64 numpy, sub_nodes int32 device tensor, weights float64 device tensor)."""
+        import torch
+        tri_d, part_d, dir_d = _devs((tri, "int32", None, "tri"), (part, "int32", n, "part"),
+                                     (dirichlet, "uint8", n, "dirichlet"))
+        if tri.numel() % 3:
+            raise ValueError("tri: expected 3 node ids per triangle")
+        sp = np.empty(n_part + 1, np.int64)
+        L = lib()
+        args = (self.h, n, tri.numel() // 3, tri_d, part_d, dir_d, n_part, delta,
+                sp.ctypes.data_as(ctypes.POINTER(_i64)))
+        rc = L.ddmgnn_expand_overlap_device(*args, None, None, 0)
+        if rc != 0 and not (sp[n_part] > 0 and b"capacity" in L.ddmgnn_last_error()):
+            _check(rc)
+        dev = tri.device
+        nodes = torch.empty(int(sp[n_part]), dtype=torch.int32, device=dev)
+        weights = torch.empty(int(sp[n_part]), dtype=torch.float64, device=dev)
+        _check(L.ddmgnn_expand_overlap_device(*args, _p(nodes.data_ptr()), _p(weights.data_ptr()), nodes.numel()))
+        return sp, nodes, weights
 
     def dot_noalloc(self, x, y, out):
         """x . y into the one-double device tensor out, asynchronously on the

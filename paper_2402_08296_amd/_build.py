@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libddmgnn.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
-           ("kernels.hip", "dss_mfma.hip", "train.hip", "noalloc.hip", "factor.hip", "runtime.cpp", "server.cpp")]
+           ("kernels.hip", "dss_mfma.hip", "train.hip", "noalloc.hip", "factor.hip", "overlap.hip", "runtime.cpp", "server.cpp")]
 # plain host C++ (no HIP): compiled for the host only, then linked in
 HOST_SOURCES = [os.path.join(HERE, "csrc", f) for f in ("setup.cpp",)]
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]

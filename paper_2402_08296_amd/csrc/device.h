@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace ddmgnn {
 
@@ -153,23 +154,58 @@ hipError_t launch_dss_big(const DevProb* tab, const int2* work, int n_work, int 
 // prepare_lu_local raises the kernel's LDS limit to kMaxSubNodesAny doubles
 // (not allowed during stream capture).
 hipError_t prepare_lu_local();
-// Device factorisation of DDM-LU (factor.hip): assembles A_i = R_i A R_i^T of
-// every sub-mesh (row stride lu_ld(k_i), sub-mesh i at off[i] in inv) and
-// inverts it in place (blocked Gauss-Jordan, no pivoting: SPD). *status (device,
-// zeroed by the caller) gets bit 0 set when a pivot is not positive.
-hipError_t launch_lu_factor(const int32_t* rowptr, const int32_t* col, const double* val, const int64_t* sub_ptr,
-                            const int32_t* sub_nodes, const int64_t* off, double* inv, int n_sub, int* status,
-                            hipStream_t s);
-// Coarse level on the device (factor.hip): A_0 = Z^T A Z assembled into a0inv
-// (K x K, deterministic summation order), symmetrised and inverted in place by
-// blocked Gauss-Jordan over the whole device. scratch: coarse_setup_scratch(K)
-// doubles. *status (device, zeroed by the caller) gets bit 0 set when a pivot
-// is not positive (A_0 not SPD).
-hipError_t launch_coarse_setup(const int32_t* rowptr, const int32_t* col, const double* val, const int32_t* sub_ptr,
-                               const int32_t* sub_nodes, const double* weights, const int32_t* node_ptr,
-                               const int32_t* node_slots, const int32_t* slot_sub, int K, double* a0inv,
-                               double* scratch, int* status, hipStream_t s);
-size_t coarse_setup_scratch(int K);
+// Device factorisation (factor.hip). launch_lu_assemble: A_i = R_i A R_i^T of
+// every sub-mesh, dense, sub-mesh i at off[i] of inv with row stride
+// (off[i + 1] - off[i]) / k_i. launch_coarse_assemble: A_0 = R_0 A R_0^T (K x K,
+// deterministic summation order), symmetrised, its diagonal copied to diag0.
+// launch_gj_invert: in-place inverses of a batch of SPD matrices (matrix m at
+// base + off[m], order plan.order[m]) by blocked Gauss-Jordan over the whole
+// device; scratch holds plan.scratch_doubles(); *status (device, zeroed by the
+// caller) gets bit 0 when a pivot is not positive (or, with diag0, below 1e-12
+// of its original diagonal entry).
+struct GjPlan {
+    std::vector<int32_t> order, cprefix, tprefix;  // orders; workgroup prefixes (columns, tiles)
+    std::vector<int64_t> prow;                     // prefix of the orders
+    int32_t max_k = 0;
+    int64_t tiles = 0;  // tile workgroups of one trailing update
+    explicit GjPlan(const std::vector<int32_t>& k);
+    size_t scratch_doubles() const;
+};
+struct GjPlanDev {  // device copies of a plan's arrays
+    const int32_t* order;
+    const int32_t* cprefix;
+    const int32_t* tprefix;
+    const int64_t* prow;
+};
+hipError_t launch_lu_assemble(const int32_t* rowptr, const int32_t* col, const double* val, const int64_t* sub_ptr,
+                              const int32_t* sub_nodes, const int64_t* off, double* inv, int n_sub, hipStream_t s);
+hipError_t launch_coarse_assemble(const int32_t* rowptr, const int32_t* col, const double* val,
+                                  const int32_t* sub_ptr, const int32_t* sub_nodes, const double* weights,
+                                  const int32_t* node_ptr, const int32_t* node_slots, const int32_t* slot_sub, int K,
+                                  double* a0, double* diag0, hipStream_t s);
+hipError_t launch_gj_invert(const GjPlan& plan, const GjPlanDev& dev, double* base, const int64_t* off,
+                            double* scratch, const double* diag0, int* status, hipStream_t s);
+// Overlap expansion on the device (overlap.hip). OV_CAP: most sub-meshes a node
+// may belong to; OV_SORT_MAX: largest sub-mesh the per-part sort holds (the
+// library's sub-mesh limit). ov_check: bit 0 of *status for a triangle node id
+// out of [0, n), bit 1 for a part id out of [0, n_part). ov_grow: node ->
+// triangle lists (tri_cnt must be zero), then delta rounds of growth of the
+// per-node part sets (bit 2 of *status on overflow); *sets_out / *sz_out point
+// at the final sets. ov_count: sub-mesh sizes (part_cnt zero) and their
+// exclusive scan sub_ptr[0..n_part]. ov_fill: the sorted lists and weights
+// (part_cur zero).
+constexpr int OV_CAP = 16;
+constexpr int OV_SORT_MAX = 16384;
+hipError_t ov_check(const int32_t* tri, int64_t n_tri, const int32_t* part, int64_t n, int32_t n_part, int* status,
+                    hipStream_t s);
+hipError_t ov_grow(const int32_t* tri, int64_t n_tri, const int32_t* part, int64_t n, int32_t delta,
+                   int32_t* tri_cnt, int64_t* tri_ptr, int32_t* tri_list, int32_t* sets0, int32_t* sets1,
+                   uint8_t* sz0, uint8_t* sz1, int32_t** sets_out, uint8_t** sz_out, int* status, hipStream_t s);
+hipError_t ov_count(const int32_t* sets, const uint8_t* sz, int64_t n, int32_t n_part, int32_t* part_cnt,
+                    int64_t* sub_ptr, hipStream_t s);
+hipError_t ov_fill(const int32_t* sets, const uint8_t* sz, int64_t n, const uint8_t* dirichlet, int32_t n_part,
+                   const int64_t* sub_ptr, int64_t sk, int32_t* part_cur, int32_t* nodes, double* weights,
+                   hipStream_t s);
 hipError_t launch_lu_local(const DevProb* tab, const int2* work, int n_work, int max_k, hipStream_t s, bool check);
 hipError_t launch_coarse(const DevProb* tab, const int2* rows, int n_rows, hipStream_t s, bool check);
 // The Krylov launchers end with a finalize launch of one workgroup per

@@ -56,6 +56,11 @@ static_assert(sizeof(MfmaDec) == 48, "decoder blob layout");
 // (no activation lies between them), and the coordinate terms of the message
 // first layers are split into receiver and sender parts.
 void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaStep>& steps, std::vector<MfmaDec>& dec);
+// A model of latent width d < 10 in the layout of width 10: its weights in the
+// leading rows and columns of every matrix and vector, zeros elsewhere. The
+// padded hidden units and latent components then stay exactly 0 (ReLU(0) = 0,
+// zero output rows), so the width-10 network computes the width-d one.
+void pad_theta_to_d10(const float* theta, int kbar, int d, std::vector<float>& out);
 
 struct DssMfmaArgs {
     const DevProb* tab;          // per problem: graphs, tile records, vectors, done flag

@@ -79,6 +79,57 @@ inline int row_item(int r) { return 4 * (r / 8) + r % 4; }
 
 }  // namespace
 
+void pad_theta_to_d10(const float* theta, int kbar, int d, std::vector<float>& out) {
+    const int in_phi = 2 * d + 3, in_psi = 3 * d + 1, bw = 11 * d * d + 15 * d + 1;
+    out.assign((size_t)kbar * BLOCK_W, 0.0f);
+    for (int step = 0; step < kbar; ++step) {
+        const float* src = theta + (size_t)step * bw;
+        float* dst = out.data() + (size_t)step * BLOCK_W;
+        // message MLPs: inputs (h_j, h_l, d_x, d_y, |d|)
+        for (int dir = 0; dir < 2; ++dir) {
+            const float* a = src + dir * (d * in_phi + d + d * d + d);
+            float* b = dst + (dir ? OFF_PI : OFF_PO);
+            for (int u = 0; u < d; ++u) {
+                for (int c = 0; c < d; ++c) {
+                    b[u * IN_PHI + c] = a[u * in_phi + c];
+                    b[u * IN_PHI + D + c] = a[u * in_phi + d + c];
+                }
+                for (int c = 0; c < 3; ++c) b[u * IN_PHI + 2 * D + c] = a[u * in_phi + 2 * d + c];
+                b[D * IN_PHI + u] = a[d * in_phi + u];
+                for (int w = 0; w < d; ++w) b[D * IN_PHI + D + u * D + w] = a[d * in_phi + d + u * d + w];
+                b[D * IN_PHI + D + D * D + u] = a[d * in_phi + d + d * d + u];
+            }
+        }
+        // Psi: inputs (h, c, phi_out, phi_in)
+        {
+            const float* a = src + 2 * (d * in_phi + d + d * d + d);
+            float* b = dst + OFF_PS;
+            for (int u = 0; u < d; ++u) {
+                for (int c = 0; c < d; ++c) {
+                    b[u * IN_PSI + c] = a[u * in_psi + c];
+                    b[u * IN_PSI + D + 1 + c] = a[u * in_psi + d + 1 + c];
+                    b[u * IN_PSI + 2 * D + 1 + c] = a[u * in_psi + 2 * d + 1 + c];
+                }
+                b[u * IN_PSI + D] = a[u * in_psi + d];
+                b[D * IN_PSI + u] = a[d * in_psi + u];
+                for (int w = 0; w < d; ++w) b[D * IN_PSI + D + u * D + w] = a[d * in_psi + d + u * d + w];
+                b[D * IN_PSI + D + D * D + u] = a[d * in_psi + d + d * d + u];
+            }
+        }
+        // decoder: W1[d][d], b1[d], W2[1][d], b2
+        {
+            const float* a = src + 2 * (d * in_phi + d + d * d + d) + d * in_psi + d + d * d + d;
+            float* b = dst + OFF_DE;
+            for (int u = 0; u < d; ++u) {
+                for (int c = 0; c < d; ++c) b[u * D + c] = a[u * d + c];
+                b[D * D + u] = a[d * d + u];
+                b[D * D + D + u] = a[d * d + d + u];
+            }
+            b[D * D + 2 * D] = a[d * d + 2 * d];
+        }
+    }
+}
+
 void build_mfma_blobs(const float* theta, int kbar, std::vector<MfmaStep>& steps, std::vector<MfmaDec>& dec) {
     steps.assign((size_t)kbar, MfmaStep{});
     std::vector<double> A(32 * 16);

@@ -1,20 +1,30 @@
-// Device factorisation of the exact local solvers of DDM-LU (eq. (7); the
-// paper's comparator of Tables I and III): for every sub-mesh i the dense
-// local matrix A_i = R_i A R_i^T is assembled from the CSR matrix and inverted
-// in place, so that every apply is one GEMV per sub-mesh (lu_local_kernel).
+// Device factorisation: the exact local solvers of DDM-LU (eq. (7); the
+// paper's comparator of Tables I and III) and the coarse level (Sec. III.A
+// step 1). For every sub-mesh i the dense local matrix A_i = R_i A R_i^T is
+// assembled from the CSR matrix, and the coarse matrix A_0 = R_0 A R_0^T
+// from the CSR matrix and the partition-of-unity weights; both are inverted
+// in place, so that every apply is one GEMV per sub-mesh (lu_local_kernel) and
+// one for the coarse level (coarse_kernel).
 //
 // Inversion: blocked Gauss-Jordan without pivoting, which is safe for a
 // symmetric positive definite matrix (every pivot block is a diagonal block
-// of a Schur complement of A_i, itself SPD). For pivot block P (GJ_W rows and
+// of a Schur complement, itself SPD). For pivot block P (GJ_W rows and
 // columns) and the remaining indices R, one step replaces
 //   A_PP <- A_PP^{-1},             A_PR <- A_PP^{-1} A_PR,
 //   A_RP <- -A_RP A_PP^{-1},       A_RR <- A_RR - A_RP A_PP^{-1} A_PR,
-// and after the last block the matrix holds A_i^{-1} (the in-place inversion
-// of Gauss-Jordan elimination, one block of pivots at a time). One workgroup
-// inverts one matrix, which stays in device memory; the pivot block, the
-// panel rows of a tile column and the old A_RP rows of a tile row are staged
-// in LDS.
+// and after the last block the matrix holds its inverse (the in-place
+// inversion of Gauss-Jordan elimination, one block of pivots at a time).
+//
+// A batch of matrices (the K local matrices, or the single coarse matrix)
+// takes four launches per pivot step over the whole device: the pivot block
+// inverses (one workgroup per matrix), the new pivot rows (workgroups over
+// column chunks of every matrix), the update of every 64 x 64 tile of every
+// matrix, and the new pivot columns with the pivot block. A workgroup finds
+// its matrix by binary search in a prefix of per-matrix workgroup counts;
+// matrices already finished at that step return at once.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "device.h"
 
@@ -23,8 +33,9 @@ namespace ddmgnn {
 namespace {
 
 constexpr int GJ_THREADS = 256;
-constexpr int GJ_W = 32;  // pivot block width
+constexpr int GJ_W = 64;  // pivot block width
 constexpr int GJ_T = 64;  // rows and columns of a tile of the trailing update (4 x 4 per thread)
+static_assert(GJ_T == 16 * 4 && GJ_THREADS == 16 * 16, "tile of 4 x 4 outputs per thread");
 
 // Binary search of node g in the ascending slice s[0..k); -1 when absent.
 __device__ inline int find_local(const int32_t* __restrict__ s, int k, int32_t g) {
@@ -49,6 +60,7 @@ __global__ __launch_bounds__(GJ_THREADS) void lu_assemble_kernel(const int32_t* 
     const int i = blockIdx.x;
     const int64_t b = sub_ptr[i];
     const int k = (int)(sub_ptr[i + 1] - b);
+    if (k == 0) return;
     const int64_t ld = (off[i + 1] - off[i]) / k;  // row stride of the stored inverse
     double* M = inv + off[i];
     const int32_t* s = sub_nodes + b;
@@ -63,146 +75,10 @@ __global__ __launch_bounds__(GJ_THREADS) void lu_assemble_kernel(const int32_t* 
     }
 }
 
-struct GjShared {
-    double D[GJ_W][GJ_W + 1];   // pivot block, then its inverse
-    double F[GJ_T][GJ_W + 1];   // old A_RP rows of a tile row
-    double R[GJ_W][GJ_T + 1];   // new A_PR columns of a tile column
-    int bad;
-};
-
-// In-place inverse of the SPD matrix M (k x k, row stride ld); sets sh.bad when
-// a pivot is not positive and finite (M is then not SPD and left undefined).
-__device__ void gj_invert(double* __restrict__ M, int k, int64_t ld, GjShared& sh) {
-    const int t = threadIdx.x;
-    if (t == 0) sh.bad = 0;
-    for (int pb = 0; pb < k; pb += GJ_W) {
-        const int w = min(GJ_W, k - pb), pe = pb + w;
-        // 1. The pivot block and its inverse (unblocked Gauss-Jordan in LDS).
-        for (int e = t; e < GJ_W * GJ_W; e += GJ_THREADS) {
-            const int r = e / GJ_W, c = e % GJ_W;
-            sh.D[r][c] = r < w && c < w ? M[(int64_t)(pb + r) * ld + pb + c] : 0.0;
-        }
-        __syncthreads();
-        for (int q = 0; q < w; ++q) {
-            const double dq = sh.D[q][q];
-            if (!(dq > 0.0) || !isfinite(dq)) {
-                if (t == 0) sh.bad = 1;
-            }
-            const double piv = 1.0 / dq;
-            double nv[GJ_W * GJ_W / GJ_THREADS];
-#pragma unroll
-            for (int u = 0; u < GJ_W * GJ_W / GJ_THREADS; ++u) {
-                const int e = t + u * GJ_THREADS, r = e / GJ_W, c = e % GJ_W;
-                double v = sh.D[r][c];
-                if (r == q && c == q) v = piv;
-                else if (r == q) v = v * piv;
-                else if (c == q) v = -v * piv;
-                else v = fma(-sh.D[r][q] * piv, sh.D[q][c], v);
-                nv[u] = v;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < GJ_W * GJ_W / GJ_THREADS; ++u) {
-                const int e = t + u * GJ_THREADS;
-                if (e / GJ_W < w && e % GJ_W < w) sh.D[e / GJ_W][e % GJ_W] = nv[u];
-            }
-            __syncthreads();
-        }
-        // 2. A_PR <- A_PP^{-1} A_PR, one column per thread.
-        for (int j = t; j < k; j += GJ_THREADS) {
-            if (j >= pb && j < pe) continue;
-            double x[GJ_W];
-#pragma unroll
-            for (int r = 0; r < GJ_W; ++r) x[r] = r < w ? M[(int64_t)(pb + r) * ld + j] : 0.0;
-            for (int r = 0; r < w; ++r) {
-                double acc = 0.0;
-#pragma unroll
-                for (int c = 0; c < GJ_W; ++c) acc = fma(sh.D[r][c], x[c], acc);
-                M[(int64_t)(pb + r) * ld + j] = acc;
-            }
-        }
-        __syncthreads();
-        // 3. Per tile row I (rows outside P): A_RR -= F A_PR(new) over the tile
-        // columns outside P, with F the old A_RP rows; then A_RP <- -F A_PP^{-1}.
-        const int ty = t / 16, tx = t % 16;
-        for (int i0 = 0; i0 < k; i0 += GJ_T) {
-            if (i0 >= pb && i0 + GJ_T <= pe) continue;  // the tile row lies inside P
-            for (int e = t; e < GJ_T * GJ_W; e += GJ_THREADS) {
-                const int r = e / GJ_W, c = e % GJ_W, i = i0 + r;
-                sh.F[r][c] = i < k && (i < pb || i >= pe) && c < w ? M[(int64_t)i * ld + pb + c] : 0.0;
-            }
-            __syncthreads();
-            for (int j0 = 0; j0 < k; j0 += GJ_T) {
-                if (j0 >= pb && j0 + GJ_T <= pe) continue;
-                for (int e = t; e < GJ_W * GJ_T; e += GJ_THREADS) {
-                    const int r = e / GJ_T, c = e % GJ_T, j = j0 + c;
-                    sh.R[r][c] = r < w && j < k && (j < pb || j >= pe) ? M[(int64_t)(pb + r) * ld + j] : 0.0;
-                }
-                __syncthreads();
-                double acc[4][4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-                for (int p = 0; p < w; ++p) {
-                    double f[4], g[4];
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) f[a] = sh.F[ty * 4 + a][p];
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) g[b] = sh.R[p][tx * 4 + b];
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) acc[a][b] = fma(f[a], g[b], acc[a][b]);
-                }
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const int i = i0 + ty * 4 + a;
-                    if (i >= k || (i >= pb && i < pe)) continue;
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int j = j0 + tx * 4 + b;
-                        if (j >= k || (j >= pb && j < pe)) continue;
-                        M[(int64_t)i * ld + j] -= acc[a][b];
-                    }
-                }
-                __syncthreads();
-            }
-            for (int e = t; e < GJ_T * GJ_W; e += GJ_THREADS) {
-                const int r = e / GJ_W, c = e % GJ_W, i = i0 + r;
-                if (i >= k || (i >= pb && i < pe) || c >= w) continue;
-                double acc = 0.0;
-#pragma unroll
-                for (int q = 0; q < GJ_W; ++q) acc = fma(sh.F[r][q], sh.D[q][c], acc);
-                M[(int64_t)i * ld + pb + c] = -acc;
-            }
-            __syncthreads();
-        }
-        // 4. A_PP <- A_PP^{-1}.
-        for (int e = t; e < GJ_W * GJ_W; e += GJ_THREADS) {
-            const int r = e / GJ_W, c = e % GJ_W;
-            if (r < w && c < w) M[(int64_t)(pb + r) * ld + pb + c] = sh.D[r][c];
-        }
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(GJ_THREADS) void lu_invert_kernel(const int64_t* __restrict__ sub_ptr,
-                                                                const int64_t* __restrict__ off,
-                                                                double* __restrict__ inv, int* __restrict__ status) {
-    __shared__ GjShared sh;
-    const int i = blockIdx.x;
-    const int k = (int)(sub_ptr[i + 1] - sub_ptr[i]);
-    gj_invert(inv + off[i], k, (off[i + 1] - off[i]) / k, sh);
-    if (threadIdx.x == 0 && sh.bad) atomicOr(status, 1);
-}
-
-// ---------------------------------------------------------------- coarse level
-// A_0 = Z^T A Z (column i of Z is R_i^T D_i R_i 1, Sec. III.A step 1): row i of
-// A_0 sums w_a A[g_a][m] w_b over the slots a of sub-mesh i, the nonzeros
-// (g_a, m) of A and the slots b of node m (sub-mesh j = slot_sub[b]). One
-// thread builds one row, in slot, nonzero and membership order, so the bits
-// do not depend on scheduling.
+// A_0 = Z^T A Z (column i of Z is R_i^T D_i R_i 1): row i sums w_a A[g_a][m] w_b
+// over the slots a of sub-mesh i, the nonzeros (g_a, m) of A and the slots b
+// of node m (sub-mesh j = slot_sub[b]). One thread builds one row, in slot,
+// nonzero and membership order, so the bits do not depend on scheduling.
 __global__ __launch_bounds__(64) void coarse_assemble_kernel(const int32_t* __restrict__ rowptr,
                                                              const int32_t* __restrict__ col,
                                                              const double* __restrict__ val,
@@ -232,48 +108,81 @@ __global__ __launch_bounds__(64) void coarse_assemble_kernel(const int32_t* __re
     }
 }
 
-__global__ __launch_bounds__(256) void diag_copy_kernel(const double* __restrict__ a, int K, double* __restrict__ d) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < K) d[i] = a[(size_t)i * K + i];
-}
-
-// Exact symmetry: both triangles take the mean of the two sums.
-__global__ __launch_bounds__(256) void coarse_symmetrise_kernel(double* __restrict__ a0, int K) {
+// Exact symmetry of A_0: both triangles take the mean of the two sums; the
+// diagonal is kept in diag0 (the reference of the pivot test).
+__global__ __launch_bounds__(256) void coarse_symmetrise_kernel(double* __restrict__ a0, int K,
+                                                                double* __restrict__ diag0) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (int64_t)K * K) return;
     const int i = (int)(e / K), j = (int)(e % K);
+    if (j == i) diag0[i] = a0[e];
     if (j <= i) return;
     const double m = 0.5 * (a0[(size_t)i * K + j] + a0[(size_t)j * K + i]);
     a0[(size_t)i * K + j] = m;
     a0[(size_t)j * K + i] = m;
 }
 
-// The coarse matrix is inverted with the same Gauss-Jordan steps as gj_invert,
-// spread over the whole device: per pivot block, one workgroup inverts the
-// block (into dinv), a grid updates the pivot rows, a grid of tiles updates
-// the rest, and a grid writes the pivot columns and the pivot block.
-// A pivot is accepted when it exceeds GJ_REL times the matrix's original
-// diagonal entry (diag0; null: when it is positive): a singular or nearly
-// singular A_0 is refused instead of inverted.
+// One matrix of a batch: order k, row stride ld, entries at M.
+struct GjMat {
+    double* M;
+    int k;
+    int64_t ld;
+};
+struct GjBatch {
+    double* base;
+    const int64_t* off;     // [nm + 1] matrix m at base + off[m], row stride (off[m + 1] - off[m]) / k_m
+    const int32_t* order;   // [nm] k_m
+    int nm;
+    const int32_t* cprefix; // [nm + 1] prefix of ceil(k_m / GJ_THREADS) (row and column workgroups)
+    const int32_t* tprefix; // [nm + 1] prefix of ceil(k_m / GJ_T)^2 (tile workgroups)
+    double* dinv;           // [nm][GJ_W][GJ_W] pivot block inverses
+    double* pr;             // matrix m's new pivot rows at pr + GJ_W * prow[m], row stride k_m
+    const int64_t* prow;    // [nm + 1] prefix of k_m
+    const double* diag0;    // optional: original diagonal (pivot test reference) of matrix 0
+    int* status;            // bit 0: a pivot not positive (or below GJ_REL of diag0)
+};
+__device__ inline GjMat gj_mat(const GjBatch& b, int m) {
+    const int k = b.order[m];
+    return {b.base + b.off[m], k, k > 0 ? (b.off[m + 1] - b.off[m]) / k : 0};
+}
+// Matrix of workgroup w in a prefix of per-matrix workgroup counts (the last m
+// with prefix[m] <= w), and w's index within that matrix.
+__device__ inline int gj_find(const int32_t* prefix, int nm, int w, int* local) {
+    int lo = 0, hi = nm;
+    while (lo + 1 < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= w) lo = mid;
+        else hi = mid;
+    }
+    *local = w - prefix[lo];
+    return lo;
+}
+
+// A pivot is accepted when it is positive and, for the coarse matrix, above
+// GJ_REL times its original diagonal entry: a singular or nearly singular A_0
+// is refused instead of inverted.
 constexpr double GJ_REL = 1e-12;
-__global__ __launch_bounds__(GJ_THREADS) void gj_pivot_kernel(const double* __restrict__ M, int k, int pb,
-                                                              double* __restrict__ dinv, int* __restrict__ status,
-                                                              const double* __restrict__ diag0) {
+
+__global__ __launch_bounds__(GJ_THREADS) void gj_pivot_kernel(GjBatch b, int pb) {
     __shared__ double D[GJ_W][GJ_W + 1];
-    const int t = threadIdx.x, w = min(GJ_W, k - pb);
+    const int m = blockIdx.x;
+    const GjMat A = gj_mat(b, m);
+    if (pb >= A.k) return;
+    const int t = threadIdx.x, w = min(GJ_W, A.k - pb);
     for (int e = t; e < GJ_W * GJ_W; e += GJ_THREADS) {
         const int r = e / GJ_W, c = e % GJ_W;
-        D[r][c] = r < w && c < w ? M[(size_t)(pb + r) * k + pb + c] : 0.0;
+        D[r][c] = r < w && c < w ? A.M[(int64_t)(pb + r) * A.ld + pb + c] : 0.0;
     }
     __syncthreads();
+    constexpr int PER = GJ_W * GJ_W / GJ_THREADS;
     for (int q = 0; q < w; ++q) {
         const double dq = D[q][q];
-        const double floor = diag0 ? GJ_REL * fabs(diag0[pb + q]) : 0.0;
-        if (t == 0 && (!(dq > floor) || !isfinite(dq))) atomicOr(status, 1);
+        const double floor = b.diag0 ? GJ_REL * fabs(b.diag0[pb + q]) : 0.0;
+        if (t == 0 && (!(dq > floor) || !isfinite(dq))) atomicOr(b.status, 1);
         const double piv = 1.0 / dq;
-        double nv[GJ_W * GJ_W / GJ_THREADS];
+        double nv[PER];
 #pragma unroll
-        for (int u = 0; u < GJ_W * GJ_W / GJ_THREADS; ++u) {
+        for (int u = 0; u < PER; ++u) {
             const int e = t + u * GJ_THREADS, r = e / GJ_W, c = e % GJ_W;
             double v = D[r][c];
             if (r == q && c == q) v = piv;
@@ -284,52 +193,62 @@ __global__ __launch_bounds__(GJ_THREADS) void gj_pivot_kernel(const double* __re
         }
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < GJ_W * GJ_W / GJ_THREADS; ++u) {
+        for (int u = 0; u < PER; ++u) {
             const int e = t + u * GJ_THREADS;
             if (e / GJ_W < w && e % GJ_W < w) D[e / GJ_W][e % GJ_W] = nv[u];
         }
         __syncthreads();
     }
-    for (int e = t; e < GJ_W * GJ_W; e += GJ_THREADS) dinv[e] = D[e / GJ_W][e % GJ_W];
+    double* di = b.dinv + (size_t)m * GJ_W * GJ_W;
+    for (int e = t; e < GJ_W * GJ_W; e += GJ_THREADS) di[e] = D[e / GJ_W][e % GJ_W];
 }
 
 // A_PR(new) = dinv A_PR, one column per thread, into pr (GJ_W x k): the pivot
 // rows of the matrix are replaced only after the tile update, which reads the
 // old A_RP from the matrix and the new A_PR from pr.
-__global__ __launch_bounds__(GJ_THREADS) void gj_rows_kernel(const double* __restrict__ M, int k, int pb,
-                                                             const double* __restrict__ dinv, double* __restrict__ pr) {
+__global__ __launch_bounds__(GJ_THREADS) void gj_rows_kernel(GjBatch b, int pb) {
     __shared__ double D[GJ_W][GJ_W + 1];
-    const int t = threadIdx.x, w = min(GJ_W, k - pb);
-    for (int e = t; e < GJ_W * GJ_W; e += GJ_THREADS) D[e / GJ_W][e % GJ_W] = dinv[e];
+    int cb = 0;
+    const int m = gj_find(b.cprefix, b.nm, blockIdx.x, &cb);
+    const GjMat A = gj_mat(b, m);
+    if (pb >= A.k) return;
+    const int t = threadIdx.x, w = min(GJ_W, A.k - pb);
+    const double* di = b.dinv + (size_t)m * GJ_W * GJ_W;
+    for (int e = t; e < GJ_W * GJ_W; e += GJ_THREADS) D[e / GJ_W][e % GJ_W] = di[e];
     __syncthreads();
-    const int j = blockIdx.x * GJ_THREADS + t;
-    if (j >= k) return;
+    const int j = cb * GJ_THREADS + t;
+    if (j >= A.k) return;
+    double* pr = b.pr + (size_t)GJ_W * b.prow[m];
     double x[GJ_W];
 #pragma unroll
-    for (int r = 0; r < GJ_W; ++r) x[r] = r < w ? M[(size_t)(pb + r) * k + j] : 0.0;
+    for (int r = 0; r < GJ_W; ++r) x[r] = r < w ? A.M[(int64_t)(pb + r) * A.ld + j] : 0.0;
     for (int r = 0; r < w; ++r) {
         double acc = 0.0;
 #pragma unroll
         for (int c = 0; c < GJ_W; ++c) acc = fma(D[r][c], x[c], acc);
-        pr[(size_t)r * k + j] = acc;
+        pr[(size_t)r * A.k + j] = acc;
     }
 }
 
 // A_RR -= A_RP(old) A_PR(new) on one GJ_T x GJ_T tile per workgroup.
-__global__ __launch_bounds__(GJ_THREADS) void gj_tiles_kernel(double* __restrict__ M, int k, int pb,
-                                                              const double* __restrict__ pr) {
+__global__ __launch_bounds__(GJ_THREADS) void gj_tiles_kernel(GjBatch b, int pb) {
     __shared__ double F[GJ_T][GJ_W + 1];
     __shared__ double R[GJ_W][GJ_T + 1];
-    const int t = threadIdx.x, w = min(GJ_W, k - pb), pe = pb + w;
-    const int nt = (k + GJ_T - 1) / GJ_T;
-    const int i0 = (blockIdx.x / nt) * GJ_T, j0 = (blockIdx.x % nt) * GJ_T;
+    int tl = 0;
+    const int m = gj_find(b.tprefix, b.nm, blockIdx.x, &tl);
+    const GjMat A = gj_mat(b, m);
+    if (pb >= A.k) return;
+    const int t = threadIdx.x, w = min(GJ_W, A.k - pb), pe = pb + w;
+    const int nt = (A.k + GJ_T - 1) / GJ_T;
+    const int i0 = (tl / nt) * GJ_T, j0 = (tl % nt) * GJ_T;
+    const double* pr = b.pr + (size_t)GJ_W * b.prow[m];
     for (int e = t; e < GJ_T * GJ_W; e += GJ_THREADS) {
         const int r = e / GJ_W, c = e % GJ_W, i = i0 + r;
-        F[r][c] = i < k && (i < pb || i >= pe) && c < w ? M[(size_t)i * k + pb + c] : 0.0;
+        F[r][c] = i < A.k && (i < pb || i >= pe) && c < w ? A.M[(int64_t)i * A.ld + pb + c] : 0.0;
     }
     for (int e = t; e < GJ_W * GJ_T; e += GJ_THREADS) {
         const int r = e / GJ_T, c = e % GJ_T, j = j0 + c;
-        R[r][c] = r < w && j < k && (j < pb || j >= pe) ? pr[(size_t)r * k + j] : 0.0;
+        R[r][c] = r < w && j < A.k && (j < pb || j >= pe) ? pr[(size_t)r * A.k + j] : 0.0;
     }
     __syncthreads();
     const int ty = t / 16, tx = t % 16;
@@ -337,93 +256,117 @@ __global__ __launch_bounds__(GJ_THREADS) void gj_tiles_kernel(double* __restrict
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
     for (int p = 0; p < w; ++p) {
         double f[4], g[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) f[a] = F[ty * 4 + a][p];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) g[b] = R[p][tx * 4 + b];
+        for (int c = 0; c < 4; ++c) g[c] = R[p][tx * 4 + c];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = fma(f[a], g[b], acc[a][b]);
+            for (int c = 0; c < 4; ++c) acc[a][c] = fma(f[a], g[c], acc[a][c]);
     }
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         const int i = i0 + ty * 4 + a;
-        if (i >= k || (i >= pb && i < pe)) continue;
+        if (i >= A.k || (i >= pb && i < pe)) continue;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int j = j0 + tx * 4 + b;
-            if (j >= k || (j >= pb && j < pe)) continue;
-            M[(size_t)i * k + j] -= acc[a][b];
+        for (int c = 0; c < 4; ++c) {
+            const int j = j0 + tx * 4 + c;
+            if (j >= A.k || (j >= pb && j < pe)) continue;
+            A.M[(int64_t)i * A.ld + j] -= acc[a][c];
         }
     }
 }
 
-// A_RP <- -A_RP(old) dinv (one row per thread), the pivot rows <- pr, and
-// A_PP <- dinv.
-__global__ __launch_bounds__(GJ_THREADS) void gj_cols_kernel(double* __restrict__ M, int k, int pb,
-                                                             const double* __restrict__ dinv,
-                                                             const double* __restrict__ pr) {
+// A_RP <- -A_RP(old) dinv (one row per thread), the pivot rows <- pr and the
+// pivot block <- dinv.
+__global__ __launch_bounds__(GJ_THREADS) void gj_cols_kernel(GjBatch b, int pb) {
     __shared__ double D[GJ_W][GJ_W + 1];
-    const int t = threadIdx.x, w = min(GJ_W, k - pb), pe = pb + w;
-    for (int e = t; e < GJ_W * GJ_W; e += GJ_THREADS) D[e / GJ_W][e % GJ_W] = dinv[e];
+    int cb = 0;
+    const int m = gj_find(b.cprefix, b.nm, blockIdx.x, &cb);
+    const GjMat A = gj_mat(b, m);
+    if (pb >= A.k) return;
+    const int t = threadIdx.x, w = min(GJ_W, A.k - pb), pe = pb + w;
+    const double* di = b.dinv + (size_t)m * GJ_W * GJ_W;
+    for (int e = t; e < GJ_W * GJ_W; e += GJ_THREADS) D[e / GJ_W][e % GJ_W] = di[e];
     __syncthreads();
-    const int i = blockIdx.x * GJ_THREADS + t;
-    if (i >= k) return;
-    if (i >= pb && i < pe) {  // pivot row: the new A_PR, and A_PP <- dinv
+    const int i = cb * GJ_THREADS + t;
+    if (i >= A.k) return;
+    const double* pr = b.pr + (size_t)GJ_W * b.prow[m];
+    double* row = A.M + (int64_t)i * A.ld;
+    if (i >= pb && i < pe) {
         const int r = i - pb;
-        for (int j = 0; j < k; ++j) M[(size_t)i * k + j] = j >= pb && j < pe ? D[r][j - pb] : pr[(size_t)r * k + j];
+        for (int j = 0; j < A.k; ++j) row[j] = j >= pb && j < pe ? D[r][j - pb] : pr[(size_t)r * A.k + j];
         return;
     }
     double f[GJ_W];
 #pragma unroll
-    for (int c = 0; c < GJ_W; ++c) f[c] = c < w ? M[(size_t)i * k + pb + c] : 0.0;
+    for (int c = 0; c < GJ_W; ++c) f[c] = c < w ? row[pb + c] : 0.0;
     for (int c = 0; c < w; ++c) {
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < GJ_W; ++q) acc = fma(f[q], D[q][c], acc);
-        M[(size_t)i * k + pb + c] = -acc;
+        row[pb + c] = -acc;
     }
 }
 
 }  // namespace
 
-hipError_t launch_coarse_setup(const int32_t* rowptr, const int32_t* col, const double* val, const int32_t* sub_ptr,
-                               const int32_t* sub_nodes, const double* weights, const int32_t* node_ptr,
-                               const int32_t* node_slots, const int32_t* slot_sub, int K, double* a0inv,
-                               double* scratch, int* status, hipStream_t s) {
-    if (K <= 0) return hipSuccess;
-    hipLaunchKernelGGL(coarse_assemble_kernel, dim3((K + 63) / 64), dim3(64), 0, s, rowptr, col, val, sub_ptr,
-                       sub_nodes, weights, node_ptr, node_slots, slot_sub, K, a0inv);
-    const int64_t kk = (int64_t)K * K;
-    hipLaunchKernelGGL(coarse_symmetrise_kernel, dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, s, a0inv, K);
-    double* dinv = scratch;                      // GJ_W x GJ_W
-    double* pr = scratch + GJ_W * GJ_W;           // GJ_W x K
-    double* diag0 = pr + (size_t)GJ_W * K;        // K: the diagonal of A_0
-    hipLaunchKernelGGL(diag_copy_kernel, dim3((K + 255) / 256), dim3(256), 0, s, a0inv, K, diag0);
-    const int nt = (K + GJ_T - 1) / GJ_T;
-    const unsigned ncol = (unsigned)((K + GJ_THREADS - 1) / GJ_THREADS);
-    for (int pb = 0; pb < K; pb += GJ_W) {
-        hipLaunchKernelGGL(gj_pivot_kernel, dim3(1), dim3(GJ_THREADS), 0, s, a0inv, K, pb, dinv, status, diag0);
-        hipLaunchKernelGGL(gj_rows_kernel, dim3(ncol), dim3(GJ_THREADS), 0, s, a0inv, K, pb, dinv, pr);
-        hipLaunchKernelGGL(gj_tiles_kernel, dim3((unsigned)(nt * nt)), dim3(GJ_THREADS), 0, s, a0inv, K, pb, pr);
-        hipLaunchKernelGGL(gj_cols_kernel, dim3(ncol), dim3(GJ_THREADS), 0, s, a0inv, K, pb, dinv, pr);
+GjPlan::GjPlan(const std::vector<int32_t>& k) {
+    const int nm = (int)k.size();
+    order = k;
+    cprefix.assign((size_t)nm + 1, 0);
+    tprefix.assign((size_t)nm + 1, 0);
+    prow.assign((size_t)nm + 1, 0);
+    for (int m = 0; m < nm; ++m) {
+        const int64_t nt = (k[m] + GJ_T - 1) / GJ_T;
+        cprefix[m + 1] = cprefix[m] + (k[m] + GJ_THREADS - 1) / GJ_THREADS;
+        tiles += nt * nt;
+        tprefix[m + 1] = (int32_t)std::min<int64_t>(tiles, INT32_MAX);
+        prow[m + 1] = prow[m] + k[m];
+        max_k = std::max(max_k, k[m]);
+    }
+}
+
+size_t GjPlan::scratch_doubles() const { return order.size() * GJ_W * GJ_W + (size_t)GJ_W * prow.back(); }
+
+hipError_t launch_gj_invert(const GjPlan& plan, const GjPlanDev& dev, double* base, const int64_t* off,
+                            double* scratch, const double* diag0, int* status, hipStream_t s) {
+    const int nm = (int)plan.order.size();
+    if (nm == 0) return hipSuccess;
+    GjBatch b{base, off, dev.order, nm, dev.cprefix, dev.tprefix, scratch, scratch + (size_t)nm * GJ_W * GJ_W,
+              dev.prow, diag0, status};
+    const unsigned nc = (unsigned)plan.cprefix.back(), ntl = (unsigned)plan.tprefix.back();
+    if (plan.tiles * GJ_THREADS >= (int64_t)1 << 32) return hipErrorInvalidConfiguration;  // grid limit
+    for (int pb = 0; pb < plan.max_k; pb += GJ_W) {
+        hipLaunchKernelGGL(gj_pivot_kernel, dim3(nm), dim3(GJ_THREADS), 0, s, b, pb);
+        hipLaunchKernelGGL(gj_rows_kernel, dim3(nc), dim3(GJ_THREADS), 0, s, b, pb);
+        hipLaunchKernelGGL(gj_tiles_kernel, dim3(ntl), dim3(GJ_THREADS), 0, s, b, pb);
+        hipLaunchKernelGGL(gj_cols_kernel, dim3(nc), dim3(GJ_THREADS), 0, s, b, pb);
     }
     return hipGetLastError();
 }
 
-size_t coarse_setup_scratch(int K) { return (size_t)GJ_W * GJ_W + (size_t)GJ_W * K + (size_t)K; }
-
-hipError_t launch_lu_factor(const int32_t* rowptr, const int32_t* col, const double* val, const int64_t* sub_ptr,
-                            const int32_t* sub_nodes, const int64_t* off, double* inv, int n_sub, int* status,
-                            hipStream_t s) {
+hipError_t launch_lu_assemble(const int32_t* rowptr, const int32_t* col, const double* val, const int64_t* sub_ptr,
+                              const int32_t* sub_nodes, const int64_t* off, double* inv, int n_sub, hipStream_t s) {
     if (n_sub <= 0) return hipSuccess;
     hipLaunchKernelGGL(lu_assemble_kernel, dim3(n_sub), dim3(GJ_THREADS), 0, s, rowptr, col, val, sub_ptr,
                        sub_nodes, off, inv);
-    hipLaunchKernelGGL(lu_invert_kernel, dim3(n_sub), dim3(GJ_THREADS), 0, s, sub_ptr, off, inv, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_assemble(const int32_t* rowptr, const int32_t* col, const double* val,
+                                  const int32_t* sub_ptr, const int32_t* sub_nodes, const double* weights,
+                                  const int32_t* node_ptr, const int32_t* node_slots, const int32_t* slot_sub, int K,
+                                  double* a0, double* diag0, hipStream_t s) {
+    if (K <= 0) return hipSuccess;
+    hipLaunchKernelGGL(coarse_assemble_kernel, dim3((K + 63) / 64), dim3(64), 0, s, rowptr, col, val, sub_ptr,
+                       sub_nodes, weights, node_ptr, node_slots, slot_sub, K, a0);
+    const int64_t kk = (int64_t)K * K;
+    hipLaunchKernelGGL(coarse_symmetrise_kernel, dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, s, a0, K, diag0);
     return hipGetLastError();
 }
 

@@ -119,6 +119,30 @@ size_t valu_shmem(int max_k, int precision, int d) {
 
 // Exact local solves: the inverses of R_i A R_i^T, assembled from the problem's
 // device matrix and inverted on the device (one workgroup per sub-mesh).
+// In-place inverses of a batch of SPD matrices on the device (orders k, matrix
+// m at base + off_dev[m]); E_NOT_SPD when a pivot fails.
+int gj_invert_batch(const std::vector<int32_t>& k, double* base, const int64_t* off_dev, const double* diag0,
+                    hipStream_t s) {
+    const GjPlan plan(k);
+    DevBuf<int32_t> order, cprefix, tprefix;
+    DevBuf<int64_t> prow;
+    DevBuf<double> scratch;
+    DevBuf<int> status;
+    HIP_TRY(order.upload(plan.order.data(), plan.order.size(), s));
+    HIP_TRY(cprefix.upload(plan.cprefix.data(), plan.cprefix.size(), s));
+    HIP_TRY(tprefix.upload(plan.tprefix.data(), plan.tprefix.size(), s));
+    HIP_TRY(prow.upload(plan.prow.data(), plan.prow.size(), s));
+    HIP_TRY(scratch.alloc(plan.scratch_doubles()));
+    HIP_TRY(status.alloc(1));
+    HIP_TRY(hipMemsetAsync(status.p, 0, sizeof(int), s));
+    const GjPlanDev dev{order.p, cprefix.p, tprefix.p, prow.p};
+    HIP_TRY(launch_gj_invert(plan, dev, base, off_dev, scratch.p, diag0, status.p, s));
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return bad ? DDMGNN_E_NOT_SPD : DDMGNN_OK;
+}
+
 int prepare_lu(ddmgnn_problem* P) {
     HIP_TRY(prepare_lu_local());
     if (P->lu_inv.p) return DDMGNN_OK;
@@ -131,19 +155,16 @@ int prepare_lu(ddmgnn_problem* P) {
     }
     auto build = [&]() -> int {
         DevBuf<int64_t> sub_ptr64;
-        DevBuf<int> status;
         HIP_TRY(sub_ptr64.upload(hs.sub_ptr.data(), hs.sub_ptr.size(), s));
         HIP_TRY(P->lu_off.upload(off.data(), off.size(), s));
         HIP_TRY(P->lu_inv.alloc((size_t)std::max<int64_t>(off[hs.K], 1)));
-        HIP_TRY(status.alloc(1));
-        HIP_TRY(hipMemsetAsync(status.p, 0, sizeof(int), s));
-        HIP_TRY(launch_lu_factor(P->rowptr.p, P->col.p, P->val.p, sub_ptr64.p, P->sub_nodes.p, P->lu_off.p,
-                                 P->lu_inv.p, hs.K, status.p, s));
-        int bad = 0;
-        HIP_TRY(hipMemcpyAsync(&bad, status.p, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (bad) return fail(DDMGNN_E_NOT_SPD, "a local matrix R_i A R_i^T is not positive definite");
-        return DDMGNN_OK;
+        HIP_TRY(launch_lu_assemble(P->rowptr.p, P->col.p, P->val.p, sub_ptr64.p, P->sub_nodes.p, P->lu_off.p,
+                                   P->lu_inv.p, hs.K, s));
+        std::vector<int32_t> k((size_t)hs.K);
+        for (int32_t i = 0; i < hs.K; ++i) k[i] = (int32_t)(hs.sub_ptr[i + 1] - hs.sub_ptr[i]);
+        const int rc = gj_invert_batch(k, P->lu_inv.p, P->lu_off.p, nullptr, s);
+        if (rc == DDMGNN_E_NOT_SPD) return fail(rc, "a local matrix R_i A R_i^T is not positive definite");
+        return rc;
     };
     if (int rc = build()) {  // leave no half-built inverses behind
         P->lu_inv.reset();
@@ -215,7 +236,7 @@ int prepare_train(ddmgnn_problem* P) {
 // Whether the BF16 MFMA kernel runs sub-mesh `sub` of P (the model has the
 // paper's latent width and the sub-mesh fits the kernel's node and LDS budgets).
 bool mfma_runs_sub(const ddmgnn_problem* P, int sub) {
-    return P->model->d == D && P->mfma_need[(size_t)sub] <= MFMA_LDS_LIMIT;
+    return P->model->mfma && P->mfma_need[(size_t)sub] <= MFMA_LDS_LIMIT;
 }
 // Whether every sub-mesh of P runs on the VALU kernels under BF16.
 bool all_valu_bf16(const ddmgnn_problem* P) {
@@ -873,19 +894,17 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
     if (!hs.a0inv.empty()) {
         HIP_TRY(P->a0inv.upload(hs.a0inv.data(), (size_t)K * K, s));
     } else {  // the coarse operator and its inverse, formed on the device
-        DevBuf<double> scratch;
-        DevBuf<int> status;
+        DevBuf<double> diag0;
+        DevBuf<int64_t> off;
+        const int64_t off_h[2] = {0, (int64_t)K * K};
         HIP_TRY(P->a0inv.alloc((size_t)K * K));
-        HIP_TRY(scratch.alloc(coarse_setup_scratch(K)));
-        HIP_TRY(status.alloc(1));
-        HIP_TRY(hipMemsetAsync(status.p, 0, sizeof(int), s));
-        HIP_TRY(launch_coarse_setup(P->rowptr.p, P->col.p, P->val.p, P->sub_ptr.p, P->sub_nodes.p, P->weights.p,
-                                    P->node_ptr.p, P->node_slots.p, P->slot_sub.p, K, P->a0inv.p, scratch.p,
-                                    status.p, s));
-        int bad = 0;
-        HIP_TRY(hipMemcpyAsync(&bad, status.p, sizeof(int), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (bad) return fail(DDMGNN_E_NOT_SPD, "coarse matrix R_0 A R_0^T is not positive definite");
+        HIP_TRY(diag0.alloc((size_t)K));
+        HIP_TRY(off.upload(off_h, 2, s));
+        HIP_TRY(launch_coarse_assemble(P->rowptr.p, P->col.p, P->val.p, P->sub_ptr.p, P->sub_nodes.p, P->weights.p,
+                                       P->node_ptr.p, P->node_slots.p, P->slot_sub.p, K, P->a0inv.p, diag0.p, s));
+        const int rc = gj_invert_batch(std::vector<int32_t>{K}, P->a0inv.p, off.p, diag0.p, s);
+        if (rc == DDMGNN_E_NOT_SPD) return fail(rc, "coarse matrix R_0 A R_0^T is not positive definite");
+        if (rc) return rc;
     }
     if (!hs.lu_inv.empty()) {
         HIP_TRY(P->lu_off.upload(hs.lu_off.data(), hs.lu_off.size(), s));
@@ -1082,11 +1101,18 @@ int ddmgnn_model_create(ddmgnn_ctx* ctx, const ddmgnn_model_desc* desc, const fl
     m->theta.assign(theta, theta + n_theta);
     std::vector<MfmaStep> steps;
     std::vector<MfmaDec> dec;
-    if (d == D) build_mfma_blobs(m->theta.data(), m->kbar, steps, dec);
+    if (d == D) {
+        build_mfma_blobs(m->theta.data(), m->kbar, steps, dec);
+    } else if (d < D) {  // the matrix-core kernel runs the model embedded in width 10
+        std::vector<float> padded;
+        pad_theta_to_d10(m->theta.data(), m->kbar, d, padded);
+        build_mfma_blobs(padded.data(), m->kbar, steps, dec);
+    }
     auto dev = std::make_shared<ModelDev>();
     dev->id = g_next_id.fetch_add(1);
     dev->kbar = m->kbar;
     dev->d = d;
+    dev->mfma = d <= D;
     dev->alpha = m->alpha;
     hipStream_t s = ctx->stream;
     std::vector<double> th64(m->theta.begin(), m->theta.end());
@@ -1581,6 +1607,59 @@ int ddmgnn_pou_weights(int64_t n_nodes, const uint8_t* dirichlet, int32_t n_sub,
         const int32_t v = sub_nodes[k];
         weights_out[k] = dirichlet[v] ? 0.0 : 1.0 / (double)mult[v];
     }
+    return DDMGNN_OK;
+}
+
+int ddmgnn_expand_overlap_device(ddmgnn_ctx* ctx, int64_t n_nodes, int64_t n_tri, const int32_t* tri,
+                                 const int32_t* part, const uint8_t* dirichlet, int32_t n_part, int32_t delta,
+                                 int64_t* sub_ptr_out, int32_t* sub_nodes_out, double* weights_out, int64_t cap) {
+    if (!ctx || n_nodes <= 0 || n_nodes > INT32_MAX || n_tri <= 0 || n_tri > INT32_MAX / 3 || !tri || !part ||
+        !dirichlet || n_part <= 0 || delta < 0 || !sub_ptr_out || cap < 0 || (cap > 0 && (!sub_nodes_out || !weights_out)))
+        return fail(DDMGNN_E_INVALID, "invalid argument");
+    hipStream_t s = ctx->stream;
+    const int64_t n = n_nodes;
+    DevBuf<int> status;
+    DevBuf<int32_t> tri_cnt, tri_list, sets0, sets1, part_cnt;
+    DevBuf<int64_t> tri_ptr, sub_ptr;
+    DevBuf<uint8_t> sz0, sz1;
+    HIP_TRY(status.alloc(1));
+    HIP_TRY(hipMemsetAsync(status.p, 0, sizeof(int), s));
+    HIP_TRY(ov_check(tri, n_tri, part, n, n_part, status.p, s));
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bad & 1) return fail(DDMGNN_E_INVALID, "triangle node id out of range");
+    if (bad & 2) return fail(DDMGNN_E_INVALID, "part id out of range");
+    HIP_TRY(tri_cnt.alloc((size_t)n));
+    HIP_TRY(tri_ptr.alloc((size_t)n + 1));
+    HIP_TRY(tri_list.alloc((size_t)(3 * n_tri)));
+    HIP_TRY(sets0.alloc((size_t)n * OV_CAP));
+    HIP_TRY(sets1.alloc((size_t)n * OV_CAP));
+    HIP_TRY(sz0.alloc((size_t)n));
+    HIP_TRY(sz1.alloc((size_t)n));
+    HIP_TRY(part_cnt.alloc((size_t)n_part));
+    HIP_TRY(sub_ptr.alloc((size_t)n_part + 1));
+    HIP_TRY(hipMemsetAsync(tri_cnt.p, 0, (size_t)n * sizeof(int32_t), s));
+    int32_t* sets = nullptr;
+    uint8_t* sz = nullptr;
+    HIP_TRY(ov_grow(tri, n_tri, part, n, delta, tri_cnt.p, tri_ptr.p, tri_list.p, sets0.p, sets1.p, sz0.p, sz1.p,
+                    &sets, &sz, status.p, s));
+    HIP_TRY(hipMemsetAsync(part_cnt.p, 0, (size_t)n_part * sizeof(int32_t), s));
+    HIP_TRY(ov_count(sets, sz, n, n_part, part_cnt.p, sub_ptr.p, s));
+    HIP_TRY(hipMemcpyAsync(sub_ptr_out, sub_ptr.p, ((size_t)n_part + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&bad, status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bad & 4) return fail(DDMGNN_E_INVALID, "a node belongs to more than 16 overlapping sub-meshes");
+    int64_t kmax = 0;
+    for (int32_t i = 0; i < n_part; ++i) kmax = std::max(kmax, sub_ptr_out[i + 1] - sub_ptr_out[i]);
+    if (kmax > OV_SORT_MAX) return fail(DDMGNN_E_INVALID, "sub-mesh larger than the supported maximum (16384 nodes)");
+    const int64_t sk = sub_ptr_out[n_part];
+    if (sk > cap)
+        return fail(DDMGNN_E_INVALID, "capacity below sub_ptr_out[n_part] (the number of sub-mesh slots); "
+                                      "call again with cap >= sub_ptr_out[n_part]");
+    HIP_TRY(hipMemsetAsync(part_cnt.p, 0, (size_t)n_part * sizeof(int32_t), s));
+    HIP_TRY(ov_fill(sets, sz, n, dirichlet, n_part, sub_ptr.p, sk, part_cnt.p, sub_nodes_out, weights_out, s));
+    HIP_TRY(hipStreamSynchronize(s));
     return DDMGNN_OK;
 }
 

@@ -61,7 +61,8 @@ struct DevBuf {
 struct ModelDev {
     uint64_t id = 0;
     int kbar = 0;
-    int d = D;  // latent width; the MFMA kernel runs only the paper's d = 10
+    int d = D;  // latent width
+    bool mfma = true;  // blobs of the matrix-core kernel built (d <= 10: smaller widths zero-padded to 10)
     double alpha = 0;
     DevBuf<float> theta32;
     DevBuf<double> theta64;

@@ -104,8 +104,8 @@ def test_dss_forward_all_subdomains(ctx, c1, prec, tol, theta_name):
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16", 3e-5)])
 def test_dss_forward_widths(ctx, c1, kbar, d, prec, tol):
     """(kbar, d) variants of DSS_theta (Table II sweep): Xavier weights of each size against
-    the oracle. BF16 runs the MFMA kernel only at d = 10; other widths take the FP32 kernel
-    (hence the FP32 bar)."""
+    the oracle. BF16 runs the matrix-core kernel at d = 10 and at d = 5 (embedded in width 10
+    with zero weights, hence the BF16 bar); d = 20 takes the FP32 kernel (hence the FP32 bar)."""
     print(f"[gpu] dss_forward kbar={kbar} d={d} {prec}", flush=True)
     p, hp = c1
     theta = W.xavier_theta(7, kbar, d)
@@ -122,7 +122,7 @@ def test_dss_forward_widths(ctx, c1, kbar, d, prec, tol):
         ref = dss.forward(blocks, g, c[sl], 1e-3, d)
         worst = max(worst, np.abs(got[sl] - ref).max() / np.abs(ref).max())
     print(f"[gpu]   worst relative error {worst:.3e}", flush=True)
-    if prec == "bf16" and d == 10:
+    if prec == "bf16" and d <= 10:
         tol = 5e-2
     assert worst <= tol
 
@@ -130,7 +130,8 @@ def test_dss_forward_widths(ctx, c1, kbar, d, prec, tol):
 @pytest.mark.parametrize("d", [5, 20])
 def test_solve_widths_match_oracle(ctx, c1, d):
     """FCG with a constructed smoother of latent width d: FP64 iterations equal the oracle's;
-    a BF16 request runs the FP32 VALU kernel (kernel id 1)."""
+    a BF16 request runs the matrix-core kernel at d = 5 (kernel id 2) and the FP32 VALU
+    kernel at d = 20 (kernel id 1)."""
     print(f"[gpu] solve d={d}", flush=True)
     p, hp = c1
     theta = W.smoother_theta(kbar=10, d=d, omega=0.15, out_scale=1.7)
@@ -143,7 +144,9 @@ def test_solve_widths_match_oracle(ctx, c1, d):
     print(f"[gpu]   iterations gpu={st.iterations} oracle={ref.iterations}", flush=True)
     assert ref.converged and st.converged and abs(st.iterations - ref.iterations) <= 1
     st = prob.solve(u, dg.default_opts(precision="bf16", rtol=1e-6, max_it=1000))
-    assert st.converged and st.dss_kernel == 1
+    print(f"[gpu]   bf16: iterations {st.iterations} kernel {st.dss_kernel} true residual "
+          f"{st.true_rel_residual:.2e}", flush=True)
+    assert st.converged and st.true_rel_residual <= 1.5e-6 and st.dss_kernel == (2 if d == 5 else 1)
 
 
 def test_model_rejects_bad_sizes(ctx):
