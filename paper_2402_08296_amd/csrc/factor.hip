@@ -77,23 +77,94 @@ __global__ __launch_bounds__(GJ_THREADS) void lu_assemble_kernel(const int32_t* 
 
 // A_0 = Z^T A Z (column i of Z is R_i^T D_i R_i 1): row i sums w_a A[g_a][m] w_b
 // over the slots a of sub-mesh i, the nonzeros (g_a, m) of A and the slots b
-// of node m (sub-mesh j = slot_sub[b]). One thread builds one row, in slot,
-// nonzero and membership order, so the bits do not depend on scheduling.
-__global__ __launch_bounds__(64) void coarse_assemble_kernel(const int32_t* __restrict__ rowptr,
-                                                             const int32_t* __restrict__ col,
-                                                             const double* __restrict__ val,
-                                                             const int32_t* __restrict__ sub_ptr,
-                                                             const int32_t* __restrict__ sub_nodes,
-                                                             const double* __restrict__ weights,
-                                                             const int32_t* __restrict__ node_ptr,
-                                                             const int32_t* __restrict__ node_slots,
-                                                             const int32_t* __restrict__ slot_sub, int K,
-                                                             double* __restrict__ a0) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (i >= K) return;
+// of node m (sub-mesh j = slot_sub[b]). One workgroup builds one row. A row has
+// few nonzero columns (the sub-meshes that touch sub-mesh i or its neighbours),
+// so the workgroup first marks them in an LDS bitmap, then every thread sums a
+// contiguous chunk of the slots into its own accumulator per marked column, and
+// the chunks' sums are added in thread order: the bits do not depend on
+// scheduling. A row with more than CA_MAXJ columns, or K above CA_MAXK, is
+// summed by one thread in slot, nonzero and membership order.
+constexpr int CA_THREADS = 256;
+constexpr int CA_MAXK = 16384;  // columns covered by the LDS bitmap
+constexpr int CA_MAXJ = 32;     // nonzero columns per row held in LDS
+__global__ __launch_bounds__(CA_THREADS) void coarse_assemble_kernel(const int32_t* __restrict__ rowptr,
+                                                                     const int32_t* __restrict__ col,
+                                                                     const double* __restrict__ val,
+                                                                     const int32_t* __restrict__ sub_ptr,
+                                                                     const int32_t* __restrict__ sub_nodes,
+                                                                     const double* __restrict__ weights,
+                                                                     const int32_t* __restrict__ node_ptr,
+                                                                     const int32_t* __restrict__ node_slots,
+                                                                     const int32_t* __restrict__ slot_sub, int K,
+                                                                     double* __restrict__ a0) {
+    __shared__ uint32_t bits[CA_MAXK / 32];
+    __shared__ int32_t wpre[CA_MAXK / 32 + 1];
+    __shared__ int32_t cols[CA_MAXJ];
+    __shared__ double acc[CA_MAXJ][CA_THREADS + 1];
+    const int i = blockIdx.x, t = threadIdx.x;
     double* row = a0 + (size_t)i * K;
-    for (int j = 0; j < K; ++j) row[j] = 0.0;
-    for (int a = sub_ptr[i]; a < sub_ptr[i + 1]; ++a) {
+    for (int j = t; j < K; j += CA_THREADS) row[j] = 0.0;
+    const int s0 = sub_ptr[i], s1 = sub_ptr[i + 1];
+    if (K <= CA_MAXK) {  // uniform over the workgroup
+        const int W = (K + 31) / 32;
+        for (int w = t; w < W; w += CA_THREADS) bits[w] = 0u;
+        __syncthreads();
+        for (int a = s0 + t; a < s1; a += CA_THREADS) {
+            if (weights[a] == 0.0) continue;
+            const int32_t g = sub_nodes[a];
+            for (int32_t e = rowptr[g]; e < rowptr[g + 1]; ++e) {
+                const int32_t m = col[e];
+                for (int32_t q = node_ptr[m]; q < node_ptr[m + 1]; ++q) {
+                    const int32_t j = slot_sub[node_slots[q]];
+                    atomicOr(&bits[j >> 5], 1u << (j & 31));
+                }
+            }
+        }
+        __syncthreads();
+        if (t == 0) {
+            int c = 0;
+            for (int w = 0; w < W; ++w) {
+                wpre[w] = c;
+                c += __popc(bits[w]);
+            }
+            wpre[W] = c;
+        }
+        __syncthreads();
+        const int nj = wpre[W];
+        if (nj <= CA_MAXJ) {  // uniform
+            for (int w = t; w < W; w += CA_THREADS) {
+                uint32_t b = bits[w];
+                for (int c = wpre[w]; b; ++c, b &= b - 1u) cols[c] = w * 32 + __ffs((int)b) - 1;
+            }
+            for (int c = 0; c < nj; ++c) acc[c][t] = 0.0;
+            const int per = (s1 - s0 + CA_THREADS - 1) / CA_THREADS;
+            const int a_lo = s0 + t * per, a_hi = min(s1, a_lo + per);
+            for (int a = a_lo; a < a_hi; ++a) {
+                const double wa = weights[a];
+                if (wa == 0.0) continue;
+                const int32_t g = sub_nodes[a];
+                for (int32_t e = rowptr[g]; e < rowptr[g + 1]; ++e) {
+                    const int32_t m = col[e];
+                    const double v = val[e] * wa;
+                    for (int32_t q = node_ptr[m]; q < node_ptr[m + 1]; ++q) {
+                        const int32_t b = node_slots[q], j = slot_sub[b];
+                        const int c = wpre[j >> 5] + __popc(bits[j >> 5] & ((1u << (j & 31)) - 1u));
+                        acc[c][t] += v * weights[b];
+                    }
+                }
+            }
+            __syncthreads();
+            for (int c = t; c < nj; c += CA_THREADS) {
+                double sum = 0.0;
+                for (int u = 0; u < CA_THREADS; ++u) sum += acc[c][u];
+                row[cols[c]] = sum;
+            }
+            return;
+        }
+    }
+    __syncthreads();  // the row is zero before the single-thread sum writes it
+    if (t != 0) return;
+    for (int a = s0; a < s1; ++a) {
         const double wa = weights[a];
         if (wa == 0.0) continue;
         const int32_t g = sub_nodes[a];
@@ -363,7 +434,7 @@ hipError_t launch_coarse_assemble(const int32_t* rowptr, const int32_t* col, con
                                   const int32_t* node_ptr, const int32_t* node_slots, const int32_t* slot_sub, int K,
                                   double* a0, double* diag0, hipStream_t s) {
     if (K <= 0) return hipSuccess;
-    hipLaunchKernelGGL(coarse_assemble_kernel, dim3((K + 63) / 64), dim3(64), 0, s, rowptr, col, val, sub_ptr,
+    hipLaunchKernelGGL(coarse_assemble_kernel, dim3(K), dim3(CA_THREADS), 0, s, rowptr, col, val, sub_ptr,
                        sub_nodes, weights, node_ptr, node_slots, slot_sub, K, a0);
     const int64_t kk = (int64_t)K * K;
     hipLaunchKernelGGL(coarse_symmetrise_kernel, dim3((unsigned)((kk + 255) / 256)), dim3(256), 0, s, a0, K, diag0);
