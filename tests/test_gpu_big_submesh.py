@@ -17,13 +17,14 @@ torch = pytest.importorskip("torch")
 import paper_2402_08296_amd as dg  # noqa: E402
 import workload as W  # noqa: E402
 from oracle import decomp as dc, dss, krylov as kr, schwarz as sw  # noqa: E402
+from tests import _bf16_model as bm  # noqa: E402
 from tests._cases import oracle_problem  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
 XAVIER = W.xavier_theta(W.THETA_SEED)
 SMOOTHER = W.smoother_theta(omega=0.15, out_scale=1.7)
-TOL = {"fp64": 1e-12, "fp32": 3e-5, "bf16": 5e-2}
+TOL = {"fp64": 1e-12, "fp32": 3e-5}  # BF16: the rounding model's bar on matrix cores, FP32's beyond 2048 nodes
 
 
 def _dev(a):
@@ -61,11 +62,15 @@ def test_big_dss_forward_matches_oracle(ctx, mixed):
     rng = np.random.default_rng(3)
     c = rng.standard_normal(hp.sub_nodes.size)
     blocks = dss.unpack(XAVIER, 30, 10)
-    refs = []
+    refs, graphs = [], []
     for i in range(hp.K):
         sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
         g = dc.local_graph(hp.sub_nodes[sl], p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
+        graphs.append(g)
         refs.append(dss.forward(blocks, g, c[sl], 1e-3, 10))
+    small = [i for i in range(hp.K) if hp.sub_ptr[i + 1] - hp.sub_ptr[i] <= 2048]
+    bf16_bar = bm.tolerance(blocks, [graphs[i] for i in small],
+                            [c[hp.sub_ptr[i]:hp.sub_ptr[i + 1]] for i in small], 1e-3, 10)
     out = torch.empty(hp.sub_nodes.size, dtype=torch.float64, device="cuda")
     big = int(np.argmax(np.diff(hp.sub_ptr)))
     for prec in ("fp64", "fp32", "bf16"):
@@ -76,8 +81,9 @@ def test_big_dss_forward_matches_oracle(ctx, mixed):
         for i in range(hp.K):
             sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
             err = np.abs(o[sl] - refs[i]).max() / np.abs(refs[i]).max()
-            print(f"[gpu]   k={sl.stop - sl.start} {prec} relative error {err:.3e}", flush=True)
-            assert err <= TOL[prec]
+            tol = TOL[prec] if prec != "bf16" else (bf16_bar if i in small else TOL["fp32"])
+            print(f"[gpu]   k={sl.stop - sl.start} {prec} relative error {err:.3e} (bar {tol:.3e})", flush=True)
+            assert err <= tol
         sl = slice(hp.sub_ptr[big], hp.sub_ptr[big + 1])
         one = torch.empty(sl.stop - sl.start, dtype=torch.float64, device="cuda")
         prob.dss_forward_sub(big, _dev(c[sl]), one, prec)

@@ -5,8 +5,10 @@ Tolerances:
     relative 1e-12 (DSS) / 1e-13 (linear algebra) of the largest magnitude.
   * FP32 DSS: one FP32 rounding per operation over 30 blocks; relative 3e-5
     of the largest output magnitude (measured errors are ~1e-6).
-  * BF16 DSS (MFMA operands rounded to bf16, 8-bit significand, FP32
-    accumulation): relative 5e-2 of the largest output magnitude.
+  * BF16 DSS (matrix-core kernel): twice the error of a float64 model of the
+    kernel's roundings (bf16 operands, FP16 projections and message sums;
+    tests/_bf16_model.py) against the oracle, relative to the largest output
+    magnitude.
 """
 import numpy as np
 import pytest
@@ -16,6 +18,7 @@ torch = pytest.importorskip("torch")
 import paper_2402_08296_amd as dg  # noqa: E402
 import workload as W  # noqa: E402
 from oracle import decomp as dc, dss, krylov as kr, schwarz as sw  # noqa: E402
+from tests import _bf16_model as bm  # noqa: E402
 from tests._cases import oracle_problem, small_problem  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -65,6 +68,15 @@ def test_spmv_and_dot(ctx):
         assert got == ctx.dot(_dev(a), _dev(b))  # deterministic
 
 
+def _c_of(hp, r):
+    """Per-slot normalised restrictions c_i = R_i r / |R_i r| of a residual r."""
+    c = np.empty(hp.sub_nodes.size)
+    for i in range(hp.K):
+        ri = r[hp.sub_nodes[hp.sub_ptr[i]:hp.sub_ptr[i + 1]]]
+        c[hp.sub_ptr[i]:hp.sub_ptr[i + 1]] = ri / np.linalg.norm(ri)
+    return c
+
+
 def _c_inputs(p, hp, seed):
     """Per-slot normalised restrictions c_i = R_i r / |R_i r| of a random residual."""
     r = np.random.default_rng(seed).standard_normal(p.n)
@@ -77,7 +89,16 @@ def _c_inputs(p, hp, seed):
     return c
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16", 5e-2)])
+def _graphs(p, hp):
+    return [dc.local_graph(hp.sub_nodes[hp.sub_ptr[i]:hp.sub_ptr[i + 1]], p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
+            for i in range(hp.K)]
+
+
+def _slices(hp, c):
+    return [c[hp.sub_ptr[i]:hp.sub_ptr[i + 1]] for i in range(hp.K)]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16", None)])
 @pytest.mark.parametrize("theta_name", ["xavier", "smoother"])
 def test_dss_forward_all_subdomains(ctx, c1, prec, tol, theta_name):
     print(f"[gpu] dss_forward {prec} {theta_name}", flush=True)
@@ -89,14 +110,16 @@ def test_dss_forward_all_subdomains(ctx, c1, prec, tol, theta_name):
     prob.dss_forward(_dev(c), out, prec)
     got = out.cpu().numpy()
     blocks = dss.unpack(theta, 30, 10)
+    graphs = _graphs(p, hp)
     worst = 0.0
-    for i in range(hp.K):
+    for i, g in enumerate(graphs):
         sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
-        g = dc.local_graph(hp.sub_nodes[sl], p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
         ref = dss.forward(blocks, g, c[sl], 1e-3, 10)
         err = np.abs(got[sl] - ref).max() / np.abs(ref).max()
         worst = max(worst, err)
-    print(f"[gpu]   worst relative error {worst:.3e}", flush=True)
+    if tol is None:
+        tol = bm.tolerance(blocks, graphs, _slices(hp, c), 1e-3, 10)
+    print(f"[gpu]   worst relative error {worst:.3e} (bar {tol:.3e})", flush=True)
     assert worst <= tol
 
 
@@ -105,7 +128,8 @@ def test_dss_forward_all_subdomains(ctx, c1, prec, tol, theta_name):
 def test_dss_forward_widths(ctx, c1, kbar, d, prec, tol):
     """(kbar, d) variants of DSS_theta (Table II sweep): Xavier weights of each size against
     the oracle. BF16 runs the matrix-core kernel at d = 10 and at d = 5 (embedded in width 10
-    with zero weights, hence the BF16 bar); d = 20 takes the FP32 kernel (hence the FP32 bar)."""
+    with zero weights, hence the rounding model's bar); d = 20 takes the FP32 kernel (hence the
+    FP32 bar)."""
     print(f"[gpu] dss_forward kbar={kbar} d={d} {prec}", flush=True)
     p, hp = c1
     theta = W.xavier_theta(7, kbar, d)
@@ -115,15 +139,15 @@ def test_dss_forward_widths(ctx, c1, kbar, d, prec, tol):
     prob.dss_forward(_dev(c), out, prec)
     got = out.cpu().numpy()
     blocks = dss.unpack(theta, kbar, d)
+    graphs = _graphs(p, hp)
     worst = 0.0
-    for i in range(hp.K):
+    for i, g in enumerate(graphs):
         sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
-        g = dc.local_graph(hp.sub_nodes[sl], p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
         ref = dss.forward(blocks, g, c[sl], 1e-3, d)
         worst = max(worst, np.abs(got[sl] - ref).max() / np.abs(ref).max())
-    print(f"[gpu]   worst relative error {worst:.3e}", flush=True)
     if prec == "bf16" and d <= 10:
-        tol = 5e-2
+        tol = bm.tolerance(blocks, graphs, _slices(hp, c), 1e-3, d)
+    print(f"[gpu]   worst relative error {worst:.3e} (bar {tol:.3e})", flush=True)
     assert worst <= tol
 
 
@@ -156,7 +180,7 @@ def test_model_rejects_bad_sizes(ctx):
         dg.Model(ctx, W.xavier_theta(7, 5, 10), kbar=6, d=10)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16", 5e-2)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 3e-5), ("bf16", None)])
 @pytest.mark.parametrize("prolong", [dg.PROLONG_POU, dg.PROLONG_UNWEIGHTED])
 def test_apply_and_intermediates(ctx, c1, prec, tol, prolong):
     print(f"[gpu] apply {prec} prolong={prolong}", flush=True)
@@ -180,6 +204,8 @@ def test_apply_and_intermediates(ctx, c1, prec, tol, prolong):
     ref_y = np.linalg.solve(M.coarse.A0, y0)
     assert np.abs(y - ref_y).max() <= 1e-10 * np.abs(ref_y).max()
     # a7: local terms s_i r~_i
+    if tol is None:
+        tol = bm.tolerance(dss.unpack(XAVIER, 30, 10), _graphs(p, hp), _slices(hp, _c_of(hp, r)), 1e-3, 10)
     worst = 0.0
     for i in range(hp.K):
         sl = slice(hp.sub_ptr[i], hp.sub_ptr[i + 1])
@@ -522,7 +548,8 @@ def test_zero_rhs_and_large_subdomain(ctx):
     g = dc.local_graph(hp.sub_nodes, p.mesh.tri, p.mesh.xy, p.mesh.dirichlet)
     ref = dss.forward(blocks, g, c, 1e-3, 10)
     out = torch.empty(hp.sub_nodes.size, dtype=torch.float64, device="cuda")
-    for prec, tol in (("fp64", 1e-12), ("fp32", 3e-5), ("bf16", 5e-2)):
+    bf16_bar = bm.tolerance(blocks, [g], [c], 1e-3, 10)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 3e-5), ("bf16", bf16_bar)):
         prob.dss_forward(_dev(c), out, prec)
         err = np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max()
         print(f"[gpu]   k={hp.sub_ptr[1]} {prec} relative error {err:.3e}", flush=True)
