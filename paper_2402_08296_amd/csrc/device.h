@@ -23,6 +23,8 @@ constexpr int VEC_BLOCK = 256;  // threads of the vector kernels
 constexpr int VEC_GRID = 1024;  // max workgroups per problem in the vector kernels
 constexpr int N_XCD = 8;        // accelerator dies; workgroups are dispatched to them round-robin
 constexpr int DSS_BLOCK = 512;  // threads of the VALU DSS kernel
+constexpr int DSS_WIDE_BLOCK = 1024;  // its form for launches of fewer sub-meshes than compute units
+constexpr int N_CU = 256;  // compute units of an MI355X
 constexpr size_t LDS_LIMIT = 160 * 1024;
 
 // Krylov scalars of one problem, resident in device memory.

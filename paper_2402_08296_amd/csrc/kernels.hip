@@ -40,7 +40,6 @@ struct DssLayout {
 };
 static_assert(DssLayout<10>::BLOCK_W == 1251 && DssLayout<5>::BLOCK_W == 351 && DssLayout<20>::BLOCK_W == 4701,
               "weight block size");
-constexpr int DSS_NPT = (kMaxSubNodes + DSS_BLOCK - 1) / DSS_BLOCK;
 
 // Which reduction a finalize launch completes.
 enum FinStage { FIN_PROLONG, FIN_SPMV, FIN_UPDATE, FIN_INIT, FIN_RESID, FIN_GM_DOT1, FIN_GM_DOT2, FIN_GM_ROT,
@@ -88,6 +87,33 @@ __device__ inline void block_sum_n(double (&v)[NV], double* sh) {
         v[i] = acc;
     }
     __syncthreads();
+}
+
+// The restriction sums of the VALU DSS kernel over DSS_VBLOCK virtual threads
+// (node j belongs to virtual thread j % DSS_VBLOCK, which sums its nodes in
+// ascending order): thread t of a BLOCK-thread workgroup carries the virtual
+// threads t + q BLOCK, and every wave's shuffle tree and the final sum over the
+// virtual waves run in the order of a DSS_VBLOCK-thread workgroup, so both
+// workgroup sizes of the kernel give the same bits.
+constexpr int DSS_VBLOCK = 1024;
+template <int BLOCK>
+__device__ inline double vblock_sum(const double (&v)[DSS_VBLOCK / BLOCK], double* sh) {
+    constexpr int VT = DSS_VBLOCK / BLOCK;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < VT; ++q) {
+        const double x = wave_sum(v[q]);
+        if (lane == 0) sh[w + q * (BLOCK / 64)] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        for (int i = 0; i < DSS_VBLOCK / 64; ++i) acc += sh[i];
+        sh[DSS_VBLOCK / 64] = acc;
+    }
+    __syncthreads();
+    return sh[DSS_VBLOCK / 64];
 }
 
 // Two-kernel reductions of the Krylov iteration: every workgroup of a large
@@ -162,22 +188,25 @@ __device__ inline double relu(double x) { return fmax(x, 0.0); }
 // carry it), so an edge only adds w_|d| |d_jl|; coordinates are centred on the
 // sub-mesh to keep the cancellation small. Used for FP32; the FP64 path
 // evaluates W1_d d_jl per edge.
-// BIG: a sub-mesh of any size (beyond DSS_NPT nodes per thread): h, c and Q
+// BIG: a sub-mesh of any size (beyond the kMaxSubNodes the others hold): h, c and Q
 // live in per-slot global buffers and the node loops run over as many
 // rounds of DSS_BLOCK nodes as the sub-mesh needs; the arithmetic per node is
 // the same as the register-resident form's.
-template <typename T, int D, bool HREG, bool QLDS, bool BIG = false>
-__global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* __restrict__ theta) {
+template <typename T, int D, bool HREG, bool QLDS, bool BIG = false, int BLOCK = DSS_BLOCK>
+__global__ __launch_bounds__(BLOCK) void dss_kernel(DssArgs<T> a, const T* __restrict__ theta) {
     static_assert(!BIG || (!HREG && !QLDS), "a sub-mesh of any size keeps h and Q in global memory");
     using L = DssLayout<D>;
     constexpr int IN_PHI = L::IN_PHI, IN_PSI = L::IN_PSI, BLOCK_W = L::BLOCK_W;
     constexpr int OFF_PO = L::OFF_PO, OFF_PI = L::OFF_PI, OFF_PS = L::OFF_PS, OFF_DE = L::OFF_DE;
     constexpr bool SEP = sizeof(T) == 4;
+    constexpr int NPT = (kMaxSubNodes + BLOCK - 1) / BLOCK;  // nodes per thread
+    constexpr int VT = DSS_VBLOCK / BLOCK;                   // virtual threads per thread
+    static_assert(VT == 1 || VT == 2, "512- or 1024-thread workgroups");
     const int2 wi = a.work[blockIdx.x];
     const DevProb& P = a.tab[wi.x];
     if (P.st && P.st->done) return;
     extern __shared__ unsigned char dyn_smem[];
-    __shared__ double red[DSS_BLOCK / 64 + 1];
+    __shared__ double red[DSS_VBLOCK / 64 + 1];
     const int sub = wi.y;
     const int base = P.sub_ptr[sub];
     const int k = P.sub_ptr[sub + 1] - base;
@@ -196,11 +225,11 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
     const float* __restrict__ edge_nd = P.edge_nd;
     double* __restrict__ out = P.local;
     const int tid = threadIdx.x;
-    // rounds of DSS_BLOCK nodes (a compile-time count unless BIG)
-    const int NT = BIG ? (k + DSS_BLOCK - 1) / DSS_BLOCK : DSS_NPT;
-    constexpr int UNR = BIG ? 1 : DSS_NPT;  // unroll count of the node rounds
+    // rounds of BLOCK nodes (a compile-time count unless BIG)
+    const int NT = BIG ? (k + BLOCK - 1) / BLOCK : NPT;
+    constexpr int UNR = BIG ? 1 : NPT;  // unroll count of the node rounds
 
-    T c[BIG ? 1 : DSS_NPT];
+    T c[BIG ? 1 : NPT];
     T* cg = nullptr;  // BIG: c per slot in global memory
     if constexpr (BIG) {
         if constexpr (SEP)
@@ -211,48 +240,55 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
     double s = 1.0;
     if (a.apply) {
         const double* __restrict__ r = P.r;
-        double ss = 0.0, yy = 0.0, rv[BIG ? 1 : DSS_NPT];
+        double ssv[VT], yyv[VT], rv[BIG ? 1 : NPT];
+#pragma unroll
+        for (int q = 0; q < VT; ++q) ssv[q] = yyv[q] = 0.0;
 #pragma unroll UNR
         for (int t = 0; t < NT; ++t) {
-            const int j = tid + t * DSS_BLOCK;
+            const int j = tid + t * BLOCK;  // virtual thread j % DSS_VBLOCK = tid + (t % VT) BLOCK
             double v = 0.0;
             if (j < k) {
                 v = r[P.sub_nodes[base + j]];
-                ss = fma(v, v, ss);
-                yy = fma(P.weights[base + j], v, yy);
+                if (VT == 1 || (t & 1) == 0) {
+                    ssv[0] = fma(v, v, ssv[0]);
+                    yyv[0] = fma(P.weights[base + j], v, yyv[0]);
+                } else {
+                    ssv[VT - 1] = fma(v, v, ssv[VT - 1]);
+                    yyv[VT - 1] = fma(P.weights[base + j], v, yyv[VT - 1]);
+                }
             }
             if constexpr (!BIG) rv[t] = v;
         }
-        ss = block_sum<DSS_BLOCK>(ss, red);
-        yy = block_sum<DSS_BLOCK>(yy, red);
+        const double ss = vblock_sum<BLOCK>(ssv, red);
+        const double yy = vblock_sum<BLOCK>(yyv, red);
         s = sqrt(ss);
         if (tid == 0) {
             P.s[sub] = s;
             P.y0[sub] = yy;
         }
         if (s == 0.0) {  // R_i r = 0: the local term is 0
-            for (int j = tid; j < k; j += DSS_BLOCK) out[base + j] = 0.0;
+            for (int j = tid; j < k; j += BLOCK) out[base + j] = 0.0;
             return;
         }
         if constexpr (BIG) {
-            for (int j = tid; j < k; j += DSS_BLOCK) cg[j] = (T)(r[P.sub_nodes[base + j]] / s);
+            for (int j = tid; j < k; j += BLOCK) cg[j] = (T)(r[P.sub_nodes[base + j]] / s);
         } else {
 #pragma unroll
-            for (int t = 0; t < DSS_NPT; ++t) c[t] = (T)(rv[t] / s);
+            for (int t = 0; t < NPT; ++t) c[t] = (T)(rv[t] / s);
         }
     } else if constexpr (BIG) {
-        for (int j = tid; j < k; j += DSS_BLOCK) cg[j] = (T)P.c_in[base + j];
+        for (int j = tid; j < k; j += BLOCK) cg[j] = (T)P.c_in[base + j];
     } else {
 #pragma unroll
-        for (int t = 0; t < DSS_NPT; ++t) {
-            const int j = tid + t * DSS_BLOCK;
+        for (int t = 0; t < NPT; ++t) {
+            const int j = tid + t * BLOCK;
             c[t] = j < k ? (T)P.c_in[base + j] : (T)0;
         }
     }
 
-    T hreg[HREG ? DSS_NPT : 1][D];
+    T hreg[HREG ? NPT : 1][D];
 #pragma unroll
-    for (int t = 0; t < (HREG ? DSS_NPT : 1); ++t)
+    for (int t = 0; t < (HREG ? NPT : 1); ++t)
 #pragma unroll
         for (int u = 0; u < D; ++u) hreg[t][u] = (T)0;
     T* hg = nullptr;
@@ -261,7 +297,7 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
             hg = P.hg32 + (size_t)base * D;
         else
             hg = P.hg64 + (size_t)base * D;
-        for (int j = tid; j < k; j += DSS_BLOCK)
+        for (int j = tid; j < k; j += BLOCK)
 #pragma unroll
             for (int u = 0; u < D; ++u) hg[j * D + u] = (T)0;
     }
@@ -284,7 +320,7 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
         // Phase A: neighbour projections Q_out = W1_out[:, D:2D] h, Q_in likewise.
 #pragma unroll UNR
         for (int t = 0; t < NT; ++t) {
-            const int j = tid + t * DSS_BLOCK;
+            const int j = tid + t * BLOCK;
             if (j < k) {
                 T h[D];
 #pragma unroll
@@ -312,7 +348,7 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
         // Phase B: per receiver, message sums over in-edges, then the Psi update.
 #pragma unroll UNR
         for (int t = 0; t < NT; ++t) {
-            const int j = tid + t * DSS_BLOCK;
+            const int j = tid + t * BLOCK;
             if (j < k) {
                 T h[D];
 #pragma unroll
@@ -434,7 +470,7 @@ __global__ __launch_bounds__(DSS_BLOCK) void dss_kernel(DssArgs<T> a, const T* _
     const T* dc = dv + D;
 #pragma unroll UNR
     for (int t = 0; t < NT; ++t) {
-        const int j = tid + t * DSS_BLOCK;
+        const int j = tid + t * BLOCK;
         if (j < k) {
             T h[D];
 #pragma unroll
@@ -1204,31 +1240,39 @@ inline hipError_t done(bool check) { return check ? hipGetLastError() : hipSucce
 namespace {
 template <int W>
 hipError_t prepare_dss_valu_w(int precision, size_t shmem) {
-    const void* fn = precision == DDMGNN_FP64 ? (const void*)dss_kernel<double, W, false, true>
-                                              : (const void*)dss_kernel<float, W, true, true>;
-    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    const bool f64 = precision == DDMGNN_FP64;
+    const void* fn = f64 ? (const void*)dss_kernel<double, W, false, true> : (const void*)dss_kernel<float, W, true, true>;
+    const void* fw = f64 ? (const void*)dss_kernel<double, W, false, true, false, DSS_WIDE_BLOCK>
+                         : (const void*)dss_kernel<float, W, true, true, false, DSS_WIDE_BLOCK>;
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    return e != hipSuccess ? e : hipFuncSetAttribute(fw, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
 }
 
+template <typename T, int W, bool HREG, int BLOCK>
+void launch_dss_valu_b(const DssArgs<T>& a, const T* theta, int n_work, bool qlds, size_t shmem, hipStream_t s) {
+    if (qlds)
+        hipLaunchKernelGGL((dss_kernel<T, W, HREG, true, false, BLOCK>), dim3(n_work), dim3(BLOCK), shmem, s, a,
+                           theta);
+    else
+        hipLaunchKernelGGL((dss_kernel<T, W, HREG, false, false, BLOCK>), dim3(n_work), dim3(BLOCK), 0, s, a, theta);
+}
+
+// A launch of fewer sub-meshes than the device has compute units takes the
+// 1024-thread form (d <= 10): each sub-mesh then has twice the wavefronts to
+// hide its latency (both forms give the same bits).
 template <int W>
 void launch_dss_valu_w(const DevProb* tab, const int2* work, int n_work, int precision, bool qlds, int kbar,
                        double alpha, int apply, const float* theta32, const double* theta64, size_t shmem,
                        hipStream_t s) {
+    const bool wide = n_work < N_CU && W <= 10;  // at d = 20 the 1024-thread form spills
     if (precision == DDMGNN_FP64) {
-        DssArgs<double> a{tab, work, kbar, alpha, apply};
-        if (qlds)
-            hipLaunchKernelGGL((dss_kernel<double, W, false, true>), dim3(n_work), dim3(DSS_BLOCK), shmem, s, a,
-                               theta64);
-        else
-            hipLaunchKernelGGL((dss_kernel<double, W, false, false>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a,
-                               theta64);
+        const DssArgs<double> a{tab, work, kbar, alpha, apply};
+        if (wide) launch_dss_valu_b<double, W, false, DSS_WIDE_BLOCK>(a, theta64, n_work, qlds, shmem, s);
+        else launch_dss_valu_b<double, W, false, DSS_BLOCK>(a, theta64, n_work, qlds, shmem, s);
     } else {
-        DssArgs<float> a{tab, work, kbar, (float)alpha, apply};
-        if (qlds)
-            hipLaunchKernelGGL((dss_kernel<float, W, true, true>), dim3(n_work), dim3(DSS_BLOCK), shmem, s, a,
-                               theta32);
-        else
-            hipLaunchKernelGGL((dss_kernel<float, W, true, false>), dim3(n_work), dim3(DSS_BLOCK), 0, s, a,
-                               theta32);
+        const DssArgs<float> a{tab, work, kbar, (float)alpha, apply};
+        if (wide) launch_dss_valu_b<float, W, true, DSS_WIDE_BLOCK>(a, theta32, n_work, qlds, shmem, s);
+        else launch_dss_valu_b<float, W, true, DSS_BLOCK>(a, theta32, n_work, qlds, shmem, s);
     }
 }
 }  // namespace

@@ -75,6 +75,28 @@ def test_batch_equals_solo(ctx, mix, prec):
         assert res <= 1e-6 and err <= 1e-4
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wide_and_narrow_dss_forms_agree(ctx, prec):
+    """A solve whose launches hold fewer sub-meshes than the device has compute units runs
+    the 1024-thread VALU DSS form; 33 copies of the same problem in one batch (264
+    sub-meshes) run the 512-thread form. Both forms sum the restriction norms over the same
+    virtual threads, so every copy equals the solo solve bit for bit."""
+    print(f"[gpu] wide vs narrow DSS form {prec}", flush=True)
+    p = W.config_problem("c1", 0)
+    hp = oracle_problem(p)
+    assert hp.K * 33 >= 256 > hp.K
+    model = dg.Model(ctx, SMOOTHER)
+    opts = dg.default_opts(precision=prec, rtol=1e-8, max_it=500)
+    (u, it, status), = _solo(ctx, model, [(p, hp)], opts)
+    probs = [dg.Problem(ctx, hp, model) for _ in range(33)]
+    outs = [torch.empty(p.n, dtype=torch.float64, device="cuda") for _ in probs]
+    sts = dg.solve_batch(ctx, probs, outs, opts)
+    print(f"[gpu]   solo {it} iterations, batch {[st.iterations for st in sts][:3]}...", flush=True)
+    assert status == 0
+    for st, ub in zip(sts, outs):
+        assert st.converged and st.iterations == it and np.array_equal(ub.cpu().numpy(), u)
+
+
 def test_batch_lu_equals_solo(ctx, mix):
     """DDM-LU (exact local solves) batched: same bits and iterations as solo; the
     one-sub-mesh problem with its exact local solve converges at once."""
