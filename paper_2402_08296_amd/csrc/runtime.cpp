@@ -122,23 +122,19 @@ size_t valu_shmem(int max_k, int precision, int d) {
 // In-place inverses of a batch of SPD matrices on the device (orders k, matrix
 // m at base + off_dev[m]); E_NOT_SPD when a pivot fails.
 int gj_invert_batch(const std::vector<int32_t>& k, double* base, const int64_t* off_dev, const double* diag0,
-                    hipStream_t s) {
+                    hipStream_t s, GjBufs& g) {
     const GjPlan plan(k);
-    DevBuf<int32_t> order, cprefix, tprefix;
-    DevBuf<int64_t> prow;
-    DevBuf<double> scratch;
-    DevBuf<int> status;
-    HIP_TRY(order.upload(plan.order.data(), plan.order.size(), s));
-    HIP_TRY(cprefix.upload(plan.cprefix.data(), plan.cprefix.size(), s));
-    HIP_TRY(tprefix.upload(plan.tprefix.data(), plan.tprefix.size(), s));
-    HIP_TRY(prow.upload(plan.prow.data(), plan.prow.size(), s));
-    HIP_TRY(scratch.alloc(plan.scratch_doubles()));
-    HIP_TRY(status.alloc(1));
-    HIP_TRY(hipMemsetAsync(status.p, 0, sizeof(int), s));
-    const GjPlanDev dev{order.p, cprefix.p, tprefix.p, prow.p};
-    HIP_TRY(launch_gj_invert(plan, dev, base, off_dev, scratch.p, diag0, status.p, s));
+    HIP_TRY(g.order.upload(plan.order.data(), plan.order.size(), s));
+    HIP_TRY(g.cprefix.upload(plan.cprefix.data(), plan.cprefix.size(), s));
+    HIP_TRY(g.tprefix.upload(plan.tprefix.data(), plan.tprefix.size(), s));
+    HIP_TRY(g.prow.upload(plan.prow.data(), plan.prow.size(), s));
+    HIP_TRY(g.scratch.alloc(plan.scratch_doubles()));
+    HIP_TRY(g.status.alloc(1));
+    HIP_TRY(hipMemsetAsync(g.status.p, 0, sizeof(int), s));
+    const GjPlanDev dev{g.order.p, g.cprefix.p, g.tprefix.p, g.prow.p};
+    HIP_TRY(launch_gj_invert(plan, dev, base, off_dev, g.scratch.p, diag0, g.status.p, s));
     int bad = 0;
-    HIP_TRY(hipMemcpyAsync(&bad, status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&bad, g.status.p, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return bad ? DDMGNN_E_NOT_SPD : DDMGNN_OK;
 }
@@ -162,7 +158,8 @@ int prepare_lu(ddmgnn_problem* P) {
                                    P->lu_inv.p, hs.K, s));
         std::vector<int32_t> k((size_t)hs.K);
         for (int32_t i = 0; i < hs.K; ++i) k[i] = (int32_t)(hs.sub_ptr[i + 1] - hs.sub_ptr[i]);
-        const int rc = gj_invert_batch(k, P->lu_inv.p, P->lu_off.p, nullptr, s);
+        GjBufs g;
+        const int rc = gj_invert_batch(k, P->lu_inv.p, P->lu_off.p, nullptr, s, g);
         if (rc == DDMGNN_E_NOT_SPD) return fail(rc, "a local matrix R_i A R_i^T is not positive definite");
         return rc;
     };
@@ -844,65 +841,159 @@ size_t problem_device_bytes(int64_t n, int64_t nnz, int32_t K, int64_t sk, int64
     return b;
 }
 
+// The device-ready host arrays of a problem (HostSetup::upload_ready): plain
+// host work, run by the caller of create_problem or by a server's setup worker.
+std::string prepare_upload(const ddmgnn_problem_desc& desc, HostSetup& hs) {
+    if (hs.upload_ready) return "";
+    const int64_t n = hs.n, sk = hs.sk;
+    const int K = hs.K;
+    hs.sp32.resize((size_t)K + 1);
+    for (int i = 0; i <= K; ++i) hs.sp32[i] = (int32_t)desc.sub_ptr[i];
+    hs.ep32.resize((size_t)sk + 1);
+    for (int64_t i = 0; i <= sk; ++i) hs.ep32[i] = (int32_t)hs.edge_ptr[i];
+    hs.np32.resize((size_t)n + 1);
+    for (int64_t i = 0; i <= n; ++i) hs.np32[i] = (int32_t)hs.node_ptr[i];
+    // padded by 8 entries: the chunked edge loops read up to 3 past a node's last edge
+    hs.src_pad.assign(hs.edge_src.begin(), hs.edge_src.end());
+    hs.src_pad.resize(hs.src_pad.size() + 8, 0);
+    hs.nd_pad.assign(hs.edge_nd.begin(), hs.edge_nd.end());
+    hs.nd_pad.resize(hs.nd_pad.size() + 8, 0.0f);
+    hs.xy64.resize((size_t)2 * sk);
+    hs.xyc32.resize((size_t)2 * sk);
+    for (int64_t k = 0; k < sk; ++k) {
+        const int32_t v = desc.sub_nodes[k];
+        hs.xy64[2 * k] = desc.xy[2 * v];
+        hs.xy64[2 * k + 1] = desc.xy[2 * v + 1];
+        hs.xyc32[2 * k] = (float)hs.xyc[2 * k];
+        hs.xyc32[2 * k + 1] = (float)hs.xyc[2 * k + 1];
+    }
+    // MFMA kernel records, per tile of MFMA_TILE nodes (tile order): slot-major
+    // [slot][lane] blocks padded with sentinel records (sender k_i, |d| 0)
+    // to the tile's largest in-degree rounded up to MFMA_EC. Tile records
+    // hold the block's offset in the sub-mesh (low 24 bits) and its number
+    // of MFMA_EC-slot chunks (high 8 bits).
+    std::vector<uint32_t>& er = hs.mfma_erec;
+    er.clear();
+    er.reserve((size_t)hs.n_edges * 2 + 1);
+    std::vector<int32_t>& epad = hs.mfma_epad;
+    epad.assign((size_t)K + 1, 0);
+    hs.mfma_need.assign(K, 0);
+    hs.mfma_need_db.assign(K, 0);
+    hs.has_big = false;
+    std::vector<TileNode> tiles(sk);
+    for (int i = 0; i < K; ++i) {
+        const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
+        const int k = (int)(e - b);
+        epad[i] = (int32_t)er.size();
+        if (k > kMaxSubNodes) {  // the VALU kernel's global-memory form runs it: no tile records
+            hs.mfma_need[i] = UINT32_MAX;
+            hs.mfma_need_db[i] = UINT32_MAX;
+            hs.has_big = true;
+            continue;
+        }
+        for (int t0 = 0; t0 < k; t0 += MFMA_TILE) {
+            const int t1 = std::min(k, t0 + MFMA_TILE);
+            int maxdeg = 0;
+            for (int q = t0; q < t1; ++q) {
+                const int64_t slot = b + hs.tnode[b + q];
+                maxdeg = std::max<int>(maxdeg, (int)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]));
+            }
+            const int nch = (maxdeg + MFMA_EC - 1) / MFMA_EC;
+            const size_t off = er.size() - epad[i];
+            if (nch > 255 || off + (size_t)nch * MFMA_EC * MFMA_TILE >= (1u << 24))
+                return "sub-mesh edge block too large for the MFMA tile records";
+            er.resize(er.size() + (size_t)nch * MFMA_EC * MFMA_TILE, mfma_edge_record(k, 0));
+            // Slot by slot, each lane takes the remaining in-edge whose sender row
+            // starts on the least used LDS bank of the slot (rows are 5 dwords
+            // apart), so a wavefront's gathers spread over the banks. This only
+            // reorders each node's message sum.
+            std::vector<std::vector<int64_t>> rem(t1 - t0);
+            for (int q = t0; q < t1; ++q) {
+                const int64_t slot = b + hs.tnode[b + q];
+                for (int64_t t = hs.edge_ptr[slot]; t < hs.edge_ptr[slot + 1]; ++t) rem[q - t0].push_back(t);
+            }
+            for (int w = 0; w < maxdeg; ++w) {
+                int used[32] = {0};
+                for (int q = t0; q < t1; ++q) {
+                    auto& r = rem[q - t0];
+                    if (r.empty()) continue;
+                    size_t best = 0;
+                    for (size_t c = 1; c < r.size(); ++c)
+                        if (used[(5 * hs.edge_src[r[c]]) % 32] < used[(5 * hs.edge_src[r[best]]) % 32]) best = c;
+                    const int64_t t = r[best];
+                    r.erase(r.begin() + (long)best);
+                    used[(5 * hs.edge_src[t]) % 32]++;
+                    er[epad[i] + off + (size_t)w * MFMA_TILE + (q - t0)] =
+                        mfma_edge_record(hs.edge_src[t], (uint16_t)(hs.erec[t] >> 16));
+                }
+            }
+            for (int q = t0; q < t1; ++q) {
+                const int32_t j = hs.tnode[b + q];
+                const int64_t slot = b + j;
+                TileNode& tn = tiles[b + q];
+                tn.e0 = (int32_t)((uint32_t)off | ((uint32_t)nch << 24));
+                tn.j = (uint16_t)j;
+                tn.deg = (uint16_t)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]);
+                tn.xh = hs.xyhl[4 * slot + 0];
+                tn.xl = hs.xyhl[4 * slot + 1];
+                tn.yh = hs.xyhl[4 * slot + 2];
+                tn.yl = hs.xyhl[4 * slot + 3];
+            }
+        }
+        hs.mfma_need[i] = (uint32_t)mfma_lds_need(k, (int64_t)er.size() - epad[i]);
+        hs.mfma_need_db[i] = (uint32_t)mfma_lds_need(k, (int64_t)er.size() - epad[i], true);
+    }
+    epad[K] = (int32_t)er.size();
+    static_assert(sizeof(TileNode) == 4 * sizeof(uint32_t), "tile records are four words");
+    hs.mfma_tiles.resize((size_t)4 * sk);
+    if (sk) std::memcpy(hs.mfma_tiles.data(), tiles.data(), (size_t)sk * sizeof(TileNode));
+    hs.upload_ready = true;
+    return "";
+}
+
 int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared_ptr<ModelDev> model,
-                   HostSetup&& hs_in, ddmgnn_problem** out) {
+                   HostSetup&& hs_in, ddmgnn_problem** out, hipStream_t stream) {
     auto P = std::make_unique<ddmgnn_problem>();
     P->ctx = ctx;
     P->id = g_next_id.fetch_add(1);
     P->hs = std::move(hs_in);
     P->model = std::move(model);
+    {
+        const std::string e = prepare_upload(desc, P->hs);
+        if (!e.empty()) return fail(DDMGNN_E_INVALID, e);
+    }
     const auto& hs = P->hs;
     const int64_t n = hs.n, sk = hs.sk;
     const int K = hs.K;
-    hipStream_t s = ctx->stream;
+    hipStream_t s = stream ? stream : ctx->stream;
     HIP_TRY(P->rowptr.upload(desc.a_rowptr, n + 1, s));
     HIP_TRY(P->col.upload(desc.a_col, hs.nnz, s));
     HIP_TRY(P->val.upload(desc.a_val, hs.nnz, s));
     HIP_TRY(P->b.upload(desc.b, n, s));
     HIP_TRY(P->u0.upload(desc.u0, n, s));
     HIP_TRY(P->dirichlet.upload(desc.dirichlet, n, s));
-    std::vector<int32_t> sp32(K + 1);
-    for (int i = 0; i <= K; ++i) sp32[i] = (int32_t)desc.sub_ptr[i];
-    HIP_TRY(P->sub_ptr.upload(sp32.data(), K + 1, s));
+    HIP_TRY(P->sub_ptr.upload(hs.sp32.data(), K + 1, s));
     HIP_TRY(P->sub_nodes.upload(desc.sub_nodes, sk, s));
     HIP_TRY(P->weights.upload(desc.weights, sk, s));
-    std::vector<int32_t> ep32(sk + 1);
-    for (int64_t i = 0; i <= sk; ++i) ep32[i] = (int32_t)hs.edge_ptr[i];
-    HIP_TRY(P->edge_ptr.upload(ep32.data(), sk + 1, s));
-    {
-        // padded by 8 entries: the chunked edge loops read up to 3 past a node's last edge
-        std::vector<uint16_t> src(hs.edge_src);
-        src.resize(src.size() + 8, 0);
-        HIP_TRY(P->edge_src.upload(src.data(), src.size(), s));
-    }
-    std::vector<int32_t> np32(n + 1);
-    for (int64_t i = 0; i <= n; ++i) np32[i] = (int32_t)hs.node_ptr[i];
-    HIP_TRY(P->node_ptr.upload(np32.data(), n + 1, s));
+    HIP_TRY(P->edge_ptr.upload(hs.ep32.data(), sk + 1, s));
+    HIP_TRY(P->edge_src.upload(hs.src_pad.data(), hs.src_pad.size(), s));
+    HIP_TRY(P->node_ptr.upload(hs.np32.data(), n + 1, s));
     HIP_TRY(P->node_slots.upload(hs.node_slots.data(), sk, s));
     HIP_TRY(P->slot_sub.upload(hs.slot_sub.data(), sk, s));
-    std::vector<double> xy64(2 * sk);
-    std::vector<float> xyc32(2 * sk);
-    for (int64_t k = 0; k < sk; ++k) {
-        const int32_t v = desc.sub_nodes[k];
-        xy64[2 * k] = desc.xy[2 * v];
-        xy64[2 * k + 1] = desc.xy[2 * v + 1];
-        xyc32[2 * k] = (float)hs.xyc[2 * k];
-        xyc32[2 * k + 1] = (float)hs.xyc[2 * k + 1];
-    }
-    HIP_TRY(P->xy64.upload(xy64.data(), 2 * sk, s));
-    HIP_TRY(P->xyc32.upload(xyc32.data(), 2 * sk, s));
+    HIP_TRY(P->xy64.upload(hs.xy64.data(), 2 * sk, s));
+    HIP_TRY(P->xyc32.upload(hs.xyc32.data(), 2 * sk, s));
     if (!hs.a0inv.empty()) {
         HIP_TRY(P->a0inv.upload(hs.a0inv.data(), (size_t)K * K, s));
     } else {  // the coarse operator and its inverse, formed on the device
-        DevBuf<double> diag0;
-        DevBuf<int64_t> off;
         const int64_t off_h[2] = {0, (int64_t)K * K};
         HIP_TRY(P->a0inv.alloc((size_t)K * K));
-        HIP_TRY(diag0.alloc((size_t)K));
-        HIP_TRY(off.upload(off_h, 2, s));
+        HIP_TRY(P->coarse_diag0.alloc((size_t)K));
+        HIP_TRY(P->coarse_off.upload(off_h, 2, s));
         HIP_TRY(launch_coarse_assemble(P->rowptr.p, P->col.p, P->val.p, P->sub_ptr.p, P->sub_nodes.p, P->weights.p,
-                                       P->node_ptr.p, P->node_slots.p, P->slot_sub.p, K, P->a0inv.p, diag0.p, s));
-        const int rc = gj_invert_batch(std::vector<int32_t>{K}, P->a0inv.p, off.p, diag0.p, s);
+                                       P->node_ptr.p, P->node_slots.p, P->slot_sub.p, K, P->a0inv.p,
+                                       P->coarse_diag0.p, s));
+        const int rc = gj_invert_batch(std::vector<int32_t>{K}, P->a0inv.p, P->coarse_off.p, P->coarse_diag0.p, s,
+                                       P->coarse_gj);
         if (rc == DDMGNN_E_NOT_SPD) return fail(rc, "coarse matrix R_0 A R_0^T is not positive definite");
         if (rc) return rc;
     }
@@ -910,90 +1001,13 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
         HIP_TRY(P->lu_off.upload(hs.lu_off.data(), hs.lu_off.size(), s));
         HIP_TRY(P->lu_inv.upload(hs.lu_inv.data(), hs.lu_inv.size(), s));
     }
-    {
-        // MFMA kernel records, per tile of MFMA_TILE nodes (tile order): slot-major
-        // [slot][lane] blocks padded with sentinel records (sender k_i, |d| 0)
-        // to the tile's largest in-degree rounded up to MFMA_EC. Tile records
-        // hold the block's offset in the sub-mesh (low 24 bits) and its number
-        // of MFMA_EC-slot chunks (high 8 bits).
-        std::vector<uint32_t> er;
-        er.reserve((size_t)hs.n_edges * 2 + 1);
-        std::vector<int32_t> epad(K + 1, 0);
-        P->mfma_need.assign(K, 0);
-        P->mfma_need_db.assign(K, 0);
-        std::vector<TileNode> tiles(sk);
-        for (int i = 0; i < K; ++i) {
-            const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
-            const int k = (int)(e - b);
-            epad[i] = (int32_t)er.size();
-            if (k > kMaxSubNodes) {  // the VALU kernel's global-memory form runs it: no tile records
-                P->mfma_need[i] = UINT32_MAX;
-                P->mfma_need_db[i] = UINT32_MAX;
-                P->has_big = true;
-                continue;
-            }
-            for (int t0 = 0; t0 < k; t0 += MFMA_TILE) {
-                const int t1 = std::min(k, t0 + MFMA_TILE);
-                int maxdeg = 0;
-                for (int q = t0; q < t1; ++q) {
-                    const int64_t slot = b + hs.tnode[b + q];
-                    maxdeg = std::max<int>(maxdeg, (int)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]));
-                }
-                const int nch = (maxdeg + MFMA_EC - 1) / MFMA_EC;
-                const size_t off = er.size() - epad[i];
-                if (nch > 255 || off + (size_t)nch * MFMA_EC * MFMA_TILE >= (1u << 24))
-                    return fail(DDMGNN_E_INVALID, "sub-mesh edge block too large for the MFMA tile records");
-                er.resize(er.size() + (size_t)nch * MFMA_EC * MFMA_TILE, mfma_edge_record(k, 0));
-                // Slot by slot, each lane takes the remaining in-edge whose sender row
-                // starts on the least used LDS bank of the slot (rows are 5 dwords
-                // apart), so a wavefront's gathers spread over the banks. This only
-                // reorders each node's message sum.
-                std::vector<std::vector<int64_t>> rem(t1 - t0);
-                for (int q = t0; q < t1; ++q) {
-                    const int64_t slot = b + hs.tnode[b + q];
-                    for (int64_t t = hs.edge_ptr[slot]; t < hs.edge_ptr[slot + 1]; ++t) rem[q - t0].push_back(t);
-                }
-                for (int w = 0; w < maxdeg; ++w) {
-                    int used[32] = {0};
-                    for (int q = t0; q < t1; ++q) {
-                        auto& r = rem[q - t0];
-                        if (r.empty()) continue;
-                        size_t best = 0;
-                        for (size_t c = 1; c < r.size(); ++c)
-                            if (used[(5 * hs.edge_src[r[c]]) % 32] < used[(5 * hs.edge_src[r[best]]) % 32]) best = c;
-                        const int64_t t = r[best];
-                        r.erase(r.begin() + (long)best);
-                        used[(5 * hs.edge_src[t]) % 32]++;
-                        er[epad[i] + off + (size_t)w * MFMA_TILE + (q - t0)] =
-                            mfma_edge_record(hs.edge_src[t], (uint16_t)(hs.erec[t] >> 16));
-                    }
-                }
-                for (int q = t0; q < t1; ++q) {
-                    const int32_t j = hs.tnode[b + q];
-                    const int64_t slot = b + j;
-                    TileNode& tn = tiles[b + q];
-                    tn.e0 = (int32_t)((uint32_t)off | ((uint32_t)nch << 24));
-                    tn.j = (uint16_t)j;
-                    tn.deg = (uint16_t)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]);
-                    tn.xh = hs.xyhl[4 * slot + 0];
-                    tn.xl = hs.xyhl[4 * slot + 1];
-                    tn.yh = hs.xyhl[4 * slot + 2];
-                    tn.yl = hs.xyhl[4 * slot + 3];
-                }
-            }
-            P->mfma_need[i] = (uint32_t)mfma_lds_need(k, (int64_t)er.size() - epad[i]);
-            P->mfma_need_db[i] = (uint32_t)mfma_lds_need(k, (int64_t)er.size() - epad[i], true);
-        }
-        epad[K] = (int32_t)er.size();
-        HIP_TRY(P->tiles.upload(tiles.data(), tiles.size(), s));
-        HIP_TRY(P->erec.upload(er.data(), std::max<size_t>(er.size(), 1), s));
-        HIP_TRY(P->epad_sub.upload(epad.data(), epad.size(), s));
-    }
-    {
-        std::vector<float> nd(hs.edge_nd);
-        nd.resize(nd.size() + 8, 0.0f);
-        HIP_TRY(P->edge_nd.upload(nd.data(), nd.size(), s));
-    }
+    P->mfma_need = hs.mfma_need;
+    P->mfma_need_db = hs.mfma_need_db;
+    P->has_big = hs.has_big;
+    HIP_TRY(P->tiles.upload(reinterpret_cast<const TileNode*>(hs.mfma_tiles.data()), (size_t)sk, s));
+    HIP_TRY(P->erec.upload(hs.mfma_erec.data(), std::max<size_t>(hs.mfma_erec.size(), 1), s));
+    HIP_TRY(P->epad_sub.upload(hs.mfma_epad.data(), hs.mfma_epad.size(), s));
+    HIP_TRY(P->edge_nd.upload(hs.nd_pad.data(), hs.nd_pad.size(), s));
     HIP_TRY(P->s.alloc(K));
     HIP_TRY(P->y0.alloc(K));
     HIP_TRY(P->y.alloc(K));
@@ -1008,9 +1022,21 @@ int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared
     HIP_TRY(hipStreamSynchronize(s));
     P->device_bytes = problem_device_bytes(n, hs.nnz, K, sk, hs.n_edges) + P->lu_inv.n * sizeof(double) +
                       P->lu_off.n * sizeof(int64_t);
-    // host copies of the uploaded local inverses are not needed again
+    // host copies of the uploaded arrays are not needed again
     std::vector<double>().swap(P->hs.lu_inv);
     std::vector<int64_t>().swap(P->hs.lu_off);
+    HostSetup& h = P->hs;
+    std::vector<int32_t>().swap(h.sp32);
+    std::vector<int32_t>().swap(h.ep32);
+    std::vector<int32_t>().swap(h.np32);
+    std::vector<double>().swap(h.xy64);
+    std::vector<float>().swap(h.xyc32);
+    std::vector<float>().swap(h.nd_pad);
+    std::vector<uint16_t>().swap(h.src_pad);
+    std::vector<uint32_t>().swap(h.mfma_erec);
+    std::vector<uint32_t>().swap(h.mfma_tiles);
+    std::vector<int32_t>().swap(h.mfma_epad);
+    h.upload_ready = false;
     *out = P.release();
     return DDMGNN_OK;
 }

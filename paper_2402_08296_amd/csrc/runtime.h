@@ -81,8 +81,22 @@ using BatchPtr = std::unique_ptr<Batch, BatchDeleter>;
 size_t problem_device_bytes(int64_t n, int64_t nnz, int32_t K, int64_t sk, int64_t n_edges);
 
 // Creates a problem from a validated descriptor and its host setup (moved in).
+// Fills the device-ready host arrays of hs (plain host work; "" or an error).
+std::string prepare_upload(const ddmgnn_problem_desc& desc, HostSetup& hs);
+// A problem on the device. The copies and the coarse-level kernels run on
+// `stream` (the context's stream when null); a server creates problems on a
+// stream of its own while the active problems iterate on the context's.
 int create_problem(ddmgnn_ctx* ctx, const ddmgnn_problem_desc& desc, std::shared_ptr<ModelDev> model,
-                   HostSetup&& hs, ddmgnn_problem** out);
+                   HostSetup&& hs, ddmgnn_problem** out, hipStream_t stream = nullptr);
+
+// Device buffers of one batched Gauss-Jordan inversion (the plan's arrays,
+// scratch and status word).
+struct GjBufs {
+    DevBuf<int32_t> order, cprefix, tprefix;
+    DevBuf<int64_t> prow;
+    DevBuf<double> scratch;
+    DevBuf<int> status;
+};
 
 // Batch of problems solved in lockstep (one launch per kernel and iteration).
 // All must share the model. Built once per membership; cheap to rebuild.
@@ -156,6 +170,11 @@ struct ddmgnn_problem {
     ddmgnn::DevBuf<uint8_t> dirichlet;
     // decomposition
     ddmgnn::DevBuf<int32_t> sub_ptr, sub_nodes, edge_ptr, node_ptr, node_slots, slot_sub;
+    // temporaries of the device coarse setup, kept with the problem: freeing them
+    // at creation would wait for the work of every stream on the device
+    ddmgnn::GjBufs coarse_gj;
+    ddmgnn::DevBuf<double> coarse_diag0;
+    ddmgnn::DevBuf<int64_t> coarse_off;
     ddmgnn::DevBuf<uint16_t> edge_src;
     ddmgnn::DevBuf<double> weights, xy64, a0inv;
     ddmgnn::DevBuf<float> xyc32;     // per slot, centred on the sub-mesh

@@ -124,6 +124,7 @@ struct ddmgnn_server {
     bool stop = false;
     std::thread gpu;
     std::vector<std::thread> workers;
+    hipStream_t upload = nullptr;      // problem creation, beside the active chunk on ctx's stream
     std::string loop_error;
 
     void setup_worker();
@@ -158,6 +159,7 @@ void ddmgnn_server::setup_worker() {
         r->t_setup0 = Clock::now();
         std::string e = validate(r->desc);
         if (e.empty()) e = build_setup(r->desc, r->hs, false);  // coarse level: on the device at admission
+        if (e.empty()) e = prepare_upload(r->desc, r->hs);      // admission then only copies
         const bool lu = r->opts.local_solver == DDMGNN_LOCAL_LU && r->opts.krylov != DDMGNN_CG;
         if (e == "NOT_SPD") {
             r->setup_rc = DDMGNN_E_NOT_SPD;
@@ -184,6 +186,10 @@ void ddmgnn_server::setup_worker() {
     }
 }
 
+// One round of the GPU thread: admissions are planned, the active set's
+// chunk of iterations is launched, the admitted problems are created on the
+// upload stream while it runs, then the chunk is polled, converged problems
+// retire and the new ones join the active set (a rebuilt batch next round).
 void ddmgnn_server::gpu_loop() {
     (void)hipSetDevice(ctx->device);
     std::vector<Request*> active;
@@ -235,32 +241,7 @@ void ddmgnn_server::gpu_loop() {
             r->status = r->setup_rc;
             finish(r);
         }
-        for (Request* r : admit) {
-            r->t_admit = Clock::now();
-            ddmgnn_problem* P = nullptr;
-            const int rc = create_problem(ctx, r->desc, model, std::move(r->hs), &P);
-            r->t_created = Clock::now();
-            r->hs = HostSetup();
-            if (rc) {
-                r->status = rc;
-                r->err = ddmgnn_last_error();
-                finish(r);
-                continue;
-            }
-            P->rtol = r->opts.rtol;
-            P->max_it = r->opts.max_it;
-            r->prob = P;
-            r->fresh = true;
-            if (active.empty()) {
-                group = structure_key(r->opts);
-                gopts = r->opts;
-            }
-            bytes_active += r->bytes;
-            active.push_back(r);
-            changed = true;
-        }
-        if (active.empty()) continue;
-        if (changed) {
+        if (!active.empty() && changed) {
             std::vector<ddmgnn_problem*> probs;
             std::vector<uint8_t> init;
             for (Request* r : active) {
@@ -271,16 +252,50 @@ void ddmgnn_server::gpu_loop() {
             B.reset();
             int rc = build_batch(ctx, probs.data(), (int)probs.size(), B);
             if (!rc) rc = batch_begin(*B, gopts, &init);
-            if (rc) {
-                fail_all(rc);
-                continue;
-            }
+            if (rc) fail_all(rc);
             changed = false;
         }
-        int rc = batch_iterate(*B, gopts, std::max(1, gopts.check_every), false);
+        int rc = DDMGNN_OK;
+        const bool running = !active.empty();
+        if (running) rc = batch_iterate(*B, gopts, std::max(1, gopts.check_every), false);  // asynchronous
+        std::vector<Request*> incoming;
+        for (Request* r : admit) {
+            r->t_admit = Clock::now();
+            ddmgnn_problem* P = nullptr;
+            const int crc = create_problem(ctx, r->desc, model, std::move(r->hs), &P, upload);
+            r->t_created = Clock::now();
+            r->hs = HostSetup();
+            if (crc) {
+                r->status = crc;
+                r->err = ddmgnn_last_error();
+                finish(r);
+                continue;
+            }
+            P->rtol = r->opts.rtol;
+            P->max_it = r->opts.max_it;
+            r->prob = P;
+            r->fresh = true;
+            incoming.push_back(r);
+        }
+        auto join_incoming = [&] {
+            for (Request* r : incoming) {
+                if (active.empty()) {
+                    group = structure_key(r->opts);
+                    gopts = r->opts;
+                }
+                bytes_active += r->bytes;
+                active.push_back(r);
+                changed = true;
+            }
+        };
+        if (!running) {
+            join_incoming();
+            continue;
+        }
         if (!rc) rc = batch_poll(*B);
         if (rc) {
             fail_all(rc);
+            join_incoming();
             continue;
         }
         std::vector<uint8_t> done(active.size(), 0);
@@ -289,10 +304,14 @@ void ddmgnn_server::gpu_loop() {
             done[i] = batch_state(*B, (int)i).done ? 1 : 0;
             any = any || done[i];
         }
-        if (!any) continue;
+        if (!any) {
+            join_incoming();
+            continue;
+        }
         rc = batch_true_residual(*B, &done);
         if (rc) {
             fail_all(rc);
+            join_incoming();
             continue;
         }
         std::vector<Request*> keep;
@@ -332,6 +351,7 @@ void ddmgnn_server::gpu_loop() {
         active.swap(keep);
         changed = true;
         if (active.empty()) B.reset();
+        join_incoming();
     }
 }
 
@@ -347,6 +367,8 @@ int ddmgnn_server_create(ddmgnn_ctx* ctx, const ddmgnn_model* model, int64_t hbm
     s->model = model->dev;
     s->budget = (size_t)hbm_budget;
     s->max_active = max_active;
+    if (hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking) != hipSuccess)
+        return fail(DDMGNN_E_HIP, "server upload stream");
     const int nw = setup_threads ? setup_threads : 4;
     for (int i = 0; i < nw; ++i) s->workers.emplace_back(&ddmgnn_server::setup_worker, s.get());
     s->gpu = std::thread(&ddmgnn_server::gpu_loop, s.get());
@@ -444,6 +466,7 @@ int ddmgnn_server_destroy(ddmgnn_server* srv) {
     for (auto& t : srv->workers)
         if (t.joinable()) t.join();
     for (auto& kv : srv->finished) delete kv.second;
+    if (srv->upload) (void)hipStreamDestroy(srv->upload);
     delete srv;
     return DDMGNN_OK;
 }

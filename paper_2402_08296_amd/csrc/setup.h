@@ -53,6 +53,20 @@ struct HostSetup {
     // of R_i A R_i^T, row stride lu_ld(k_i), sub-mesh i at lu_off[i] (empty otherwise).
     std::vector<double> lu_inv;
     std::vector<int64_t> lu_off;
+    // Device-ready arrays, filled by prepare_upload (the setup workers of a server
+    // run it, so that admission only copies): 32-bit index arrays, the slot
+    // coordinates (FP64 raw, FP32 centred), the padded edge arrays, and the records
+    // of the matrix-core DSS kernel (per sub-mesh edge-block offsets, slot-major edge
+    // records, 16-byte tile records as four words each, and the LDS need with one and
+    // two Q' buffers, UINT32_MAX for a sub-mesh that runs the VALU kernel).
+    bool upload_ready = false;
+    bool has_big = false;
+    std::vector<int32_t> sp32, ep32, np32;
+    std::vector<double> xy64;
+    std::vector<float> xyc32, nd_pad;
+    std::vector<uint16_t> src_pad;
+    std::vector<uint32_t> mfma_erec, mfma_tiles, mfma_need, mfma_need_db;
+    std::vector<int32_t> mfma_epad;
 };
 
 // Inverse of the local matrix R_i A R_i^T of sub-mesh i (dense, row-major
