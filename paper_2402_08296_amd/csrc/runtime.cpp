@@ -847,50 +847,79 @@ std::string prepare_upload(const ddmgnn_problem_desc& desc, HostSetup& hs) {
     if (hs.upload_ready) return "";
     const int64_t n = hs.n, sk = hs.sk;
     const int K = hs.K;
+    constexpr int64_t CH = 1 << 16;  // elements per task of the conversion loops
     hs.sp32.resize((size_t)K + 1);
     for (int i = 0; i <= K; ++i) hs.sp32[i] = (int32_t)desc.sub_ptr[i];
     hs.ep32.resize((size_t)sk + 1);
-    for (int64_t i = 0; i <= sk; ++i) hs.ep32[i] = (int32_t)hs.edge_ptr[i];
     hs.np32.resize((size_t)n + 1);
-    for (int64_t i = 0; i <= n; ++i) hs.np32[i] = (int32_t)hs.node_ptr[i];
+    hs.xy64.resize((size_t)2 * sk);
+    hs.xyc32.resize((size_t)2 * sk);
+    parallel_for((sk + CH) / CH, [&](int64_t c) {
+        for (int64_t k = c * CH; k < std::min(sk + 1, (c + 1) * CH); ++k) hs.ep32[k] = (int32_t)hs.edge_ptr[k];
+        for (int64_t k = c * CH; k < std::min(sk, (c + 1) * CH); ++k) {
+            const int32_t v = desc.sub_nodes[k];
+            hs.xy64[2 * k] = desc.xy[2 * v];
+            hs.xy64[2 * k + 1] = desc.xy[2 * v + 1];
+            hs.xyc32[2 * k] = (float)hs.xyc[2 * k];
+            hs.xyc32[2 * k + 1] = (float)hs.xyc[2 * k + 1];
+        }
+    });
+    parallel_for((n + CH) / CH, [&](int64_t c) {
+        for (int64_t i = c * CH; i < std::min(n + 1, (c + 1) * CH); ++i) hs.np32[i] = (int32_t)hs.node_ptr[i];
+    });
     // padded by 8 entries: the chunked edge loops read up to 3 past a node's last edge
     hs.src_pad.assign(hs.edge_src.begin(), hs.edge_src.end());
     hs.src_pad.resize(hs.src_pad.size() + 8, 0);
     hs.nd_pad.assign(hs.edge_nd.begin(), hs.edge_nd.end());
     hs.nd_pad.resize(hs.nd_pad.size() + 8, 0.0f);
-    hs.xy64.resize((size_t)2 * sk);
-    hs.xyc32.resize((size_t)2 * sk);
-    for (int64_t k = 0; k < sk; ++k) {
-        const int32_t v = desc.sub_nodes[k];
-        hs.xy64[2 * k] = desc.xy[2 * v];
-        hs.xy64[2 * k + 1] = desc.xy[2 * v + 1];
-        hs.xyc32[2 * k] = (float)hs.xyc[2 * k];
-        hs.xyc32[2 * k + 1] = (float)hs.xyc[2 * k + 1];
-    }
     // MFMA kernel records, per tile of MFMA_TILE nodes (tile order): slot-major
     // [slot][lane] blocks padded with sentinel records (sender k_i, |d| 0)
     // to the tile's largest in-degree rounded up to MFMA_EC. Tile records
     // hold the block's offset in the sub-mesh (low 24 bits) and its number
-    // of MFMA_EC-slot chunks (high 8 bits).
-    std::vector<uint32_t>& er = hs.mfma_erec;
-    er.clear();
-    er.reserve((size_t)hs.n_edges * 2 + 1);
-    std::vector<int32_t>& epad = hs.mfma_epad;
-    epad.assign((size_t)K + 1, 0);
+    // of MFMA_EC-slot chunks (high 8 bits). Sub-meshes are independent: the
+    // sizes of their edge blocks first, then their records in parallel.
     hs.mfma_need.assign(K, 0);
     hs.mfma_need_db.assign(K, 0);
+    std::vector<int64_t> esize((size_t)K, 0);
+    std::atomic<int> too_big{0};
+    parallel_for(K, [&](int64_t i) {
+        const int64_t b = desc.sub_ptr[i], k = desc.sub_ptr[i + 1] - b;
+        if (k > kMaxSubNodes) return;  // the VALU kernel's global-memory form runs it: no tile records
+        int64_t size = 0;
+        for (int64_t t0 = 0; t0 < k; t0 += MFMA_TILE) {
+            int maxdeg = 0;
+            for (int64_t q = t0; q < std::min<int64_t>(k, t0 + MFMA_TILE); ++q) {
+                const int64_t slot = b + hs.tnode[b + q];
+                maxdeg = std::max<int>(maxdeg, (int)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]));
+            }
+            const int nch = (maxdeg + MFMA_EC - 1) / MFMA_EC;
+            if (nch > 255 || size + (int64_t)nch * MFMA_EC * MFMA_TILE >= (1 << 24)) too_big = 1;
+            size += (int64_t)nch * MFMA_EC * MFMA_TILE;
+        }
+        esize[i] = size;
+    });
+    if (too_big) return "sub-mesh edge block too large for the MFMA tile records";
+    std::vector<int32_t>& epad = hs.mfma_epad;
+    epad.assign((size_t)K + 1, 0);
+    for (int i = 0; i < K; ++i) {
+        if (epad[i] + esize[i] >= INT32_MAX) return "edge records beyond 32-bit offsets";
+        epad[i + 1] = (int32_t)(epad[i] + esize[i]);
+    }
+    std::vector<uint32_t>& er = hs.mfma_erec;
+    er.assign((size_t)epad[K], 0u);
     hs.has_big = false;
     std::vector<TileNode> tiles(sk);
-    for (int i = 0; i < K; ++i) {
+    parallel_for(K, [&](int64_t i) {
         const int64_t b = desc.sub_ptr[i], e = desc.sub_ptr[i + 1];
         const int k = (int)(e - b);
-        epad[i] = (int32_t)er.size();
-        if (k > kMaxSubNodes) {  // the VALU kernel's global-memory form runs it: no tile records
+        if (k > kMaxSubNodes) {
             hs.mfma_need[i] = UINT32_MAX;
             hs.mfma_need_db[i] = UINT32_MAX;
-            hs.has_big = true;
-            continue;
+            return;
         }
+        std::vector<int64_t> cand;  // per lane of a tile: its in-edges, in order
+        std::vector<uint8_t> taken;
+        size_t off = 0;
         for (int t0 = 0; t0 < k; t0 += MFMA_TILE) {
             const int t1 = std::min(k, t0 + MFMA_TILE);
             int maxdeg = 0;
@@ -899,32 +928,34 @@ std::string prepare_upload(const ddmgnn_problem_desc& desc, HostSetup& hs) {
                 maxdeg = std::max<int>(maxdeg, (int)(hs.edge_ptr[slot + 1] - hs.edge_ptr[slot]));
             }
             const int nch = (maxdeg + MFMA_EC - 1) / MFMA_EC;
-            const size_t off = er.size() - epad[i];
-            if (nch > 255 || off + (size_t)nch * MFMA_EC * MFMA_TILE >= (1u << 24))
-                return "sub-mesh edge block too large for the MFMA tile records";
-            er.resize(er.size() + (size_t)nch * MFMA_EC * MFMA_TILE, mfma_edge_record(k, 0));
-            // Slot by slot, each lane takes the remaining in-edge whose sender row
-            // starts on the least used LDS bank of the slot (rows are 5 dwords
+            uint32_t* blk = er.data() + epad[i] + off;
+            std::fill(blk, blk + (size_t)nch * MFMA_EC * MFMA_TILE, mfma_edge_record(k, 0));
+            // Slot by slot, each lane takes the first remaining in-edge whose sender
+            // row starts on the least used LDS bank of the slot (rows are 5 dwords
             // apart), so a wavefront's gathers spread over the banks. This only
             // reorders each node's message sum.
-            std::vector<std::vector<int64_t>> rem(t1 - t0);
+            cand.assign((size_t)(t1 - t0) * maxdeg, -1);
+            taken.assign(cand.size(), 0);
             for (int q = t0; q < t1; ++q) {
                 const int64_t slot = b + hs.tnode[b + q];
-                for (int64_t t = hs.edge_ptr[slot]; t < hs.edge_ptr[slot + 1]; ++t) rem[q - t0].push_back(t);
+                for (int64_t t = hs.edge_ptr[slot]; t < hs.edge_ptr[slot + 1]; ++t)
+                    cand[(size_t)(q - t0) * maxdeg + (t - hs.edge_ptr[slot])] = t;
             }
             for (int w = 0; w < maxdeg; ++w) {
                 int used[32] = {0};
                 for (int q = t0; q < t1; ++q) {
-                    auto& r = rem[q - t0];
-                    if (r.empty()) continue;
-                    size_t best = 0;
-                    for (size_t c = 1; c < r.size(); ++c)
-                        if (used[(5 * hs.edge_src[r[c]]) % 32] < used[(5 * hs.edge_src[r[best]]) % 32]) best = c;
-                    const int64_t t = r[best];
-                    r.erase(r.begin() + (long)best);
+                    const int64_t* c = cand.data() + (size_t)(q - t0) * maxdeg;
+                    uint8_t* tk = taken.data() + (size_t)(q - t0) * maxdeg;
+                    int best = -1;
+                    for (int x = 0; x < maxdeg && c[x] >= 0; ++x)
+                        if (!tk[x] && (best < 0 || used[(5 * hs.edge_src[c[x]]) % 32] <
+                                                       used[(5 * hs.edge_src[c[best]]) % 32]))
+                            best = x;
+                    if (best < 0) continue;
+                    const int64_t t = c[best];
+                    tk[best] = 1;
                     used[(5 * hs.edge_src[t]) % 32]++;
-                    er[epad[i] + off + (size_t)w * MFMA_TILE + (q - t0)] =
-                        mfma_edge_record(hs.edge_src[t], (uint16_t)(hs.erec[t] >> 16));
+                    blk[(size_t)w * MFMA_TILE + (q - t0)] = mfma_edge_record(hs.edge_src[t], (uint16_t)(hs.erec[t] >> 16));
                 }
             }
             for (int q = t0; q < t1; ++q) {
@@ -939,11 +970,12 @@ std::string prepare_upload(const ddmgnn_problem_desc& desc, HostSetup& hs) {
                 tn.yh = hs.xyhl[4 * slot + 2];
                 tn.yl = hs.xyhl[4 * slot + 3];
             }
+            off += (size_t)nch * MFMA_EC * MFMA_TILE;
         }
-        hs.mfma_need[i] = (uint32_t)mfma_lds_need(k, (int64_t)er.size() - epad[i]);
-        hs.mfma_need_db[i] = (uint32_t)mfma_lds_need(k, (int64_t)er.size() - epad[i], true);
-    }
-    epad[K] = (int32_t)er.size();
+        hs.mfma_need[i] = (uint32_t)mfma_lds_need(k, esize[i]);
+        hs.mfma_need_db[i] = (uint32_t)mfma_lds_need(k, esize[i], true);
+    });
+    for (int i = 0; i < K; ++i) hs.has_big = hs.has_big || hs.mfma_need[i] == UINT32_MAX;
     static_assert(sizeof(TileNode) == 4 * sizeof(uint32_t), "tile records are four words");
     hs.mfma_tiles.resize((size_t)4 * sk);
     if (sk) std::memcpy(hs.mfma_tiles.data(), tiles.data(), (size_t)sk * sizeof(TileNode));

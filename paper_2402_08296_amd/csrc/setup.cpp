@@ -12,26 +12,6 @@ namespace ddmgnn {
 
 namespace {
 
-// Rows (or columns) 0..n-1 of a dense kernel spread over host threads; each
-// index is handled by one thread, so results do not depend on the thread count.
-template <class F>
-void parallel_for(int64_t n, F&& f) {
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const int64_t T = std::min<int64_t>({n, (int64_t)hw, 16});
-    if (T <= 1) {
-        for (int64_t i = 0; i < n; ++i) f(i);
-        return;
-    }
-    std::atomic<int64_t> next{0};
-    auto work = [&] {
-        for (int64_t i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
-    };
-    std::vector<std::thread> th;
-    for (int64_t t = 1; t < T; ++t) th.emplace_back(work);
-    work();
-    for (auto& t : th) t.join();
-}
-
 // sum_p a[p] b[p] with four interleaved partial sums (a fixed order).
 inline double dot4(const double* a, const double* b, int64_t len) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -200,32 +180,70 @@ namespace {
 // Sorted, de-duplicated mesh adjacency (nodes sharing a triangle edge).
 void mesh_adjacency(int64_t n, int64_t nt, const int32_t* tri, std::vector<int64_t>& ptr,
                     std::vector<int32_t>& adj) {
-    std::vector<int64_t> cnt(n + 1, 0);
-    for (int64_t t = 0; t < nt; ++t)
-        for (int i = 0; i < 3; ++i) cnt[tri[3 * t + i] + 1] += 2;
-    for (int64_t i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
-    std::vector<int32_t> tmp(cnt[n]);
-    std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
-    for (int64_t t = 0; t < nt; ++t) {
-        for (int i = 0; i < 3; ++i) {
-            int32_t a = tri[3 * t + i], b = tri[3 * t + (i + 1) % 3];
-            tmp[pos[a]++] = b;
-            tmp[pos[b]++] = a;
+    // Triangles scatter both directions of their edges into per-node ranges on
+    // host threads (any order), then each node's range is sorted and made unique,
+    // which fixes the result whatever the scatter order.
+    constexpr int64_t CH = 1 << 15;
+    std::vector<std::atomic<int64_t>> cnt((size_t)n + 1);
+    parallel_for((n + CH) / CH, [&](int64_t c) {
+        for (int64_t i = c * CH; i < std::min(n + 1, (c + 1) * CH); ++i) cnt[i].store(0, std::memory_order_relaxed);
+    });
+    parallel_for((nt + CH - 1) / CH, [&](int64_t c) {
+        for (int64_t t = c * CH; t < std::min(nt, (c + 1) * CH); ++t)
+            for (int i = 0; i < 3; ++i) cnt[tri[3 * t + i] + 1].fetch_add(2, std::memory_order_relaxed);
+    });
+    std::vector<int64_t> start((size_t)n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) start[i + 1] = start[i] + cnt[i + 1].load(std::memory_order_relaxed);
+    std::vector<int32_t> tmp((size_t)start[n]);
+    parallel_for((n + CH - 1) / CH, [&](int64_t c) {
+        for (int64_t i = c * CH; i < std::min(n, (c + 1) * CH); ++i) cnt[i].store(start[i], std::memory_order_relaxed);
+    });
+    parallel_for((nt + CH - 1) / CH, [&](int64_t c) {
+        for (int64_t t = c * CH; t < std::min(nt, (c + 1) * CH); ++t)
+            for (int i = 0; i < 3; ++i) {
+                const int32_t a = tri[3 * t + i], b = tri[3 * t + (i + 1) % 3];
+                tmp[cnt[a].fetch_add(1, std::memory_order_relaxed)] = b;
+                tmp[cnt[b].fetch_add(1, std::memory_order_relaxed)] = a;
+            }
+    });
+    std::vector<int64_t> uniq((size_t)n + 1, 0);
+    parallel_for((n + CH - 1) / CH, [&](int64_t c) {
+        for (int64_t i = c * CH; i < std::min(n, (c + 1) * CH); ++i) {
+            auto b = tmp.begin() + start[i], e = tmp.begin() + start[i + 1];
+            std::sort(b, e);
+            uniq[i + 1] = std::unique(b, e) - b;
         }
-    }
-    ptr.assign(n + 1, 0);
-    adj.clear();
-    adj.reserve(tmp.size() / 2 + 1);
-    for (int64_t i = 0; i < n; ++i) {
-        auto b = tmp.begin() + cnt[i], e = tmp.begin() + cnt[i + 1];
-        std::sort(b, e);
-        auto u = std::unique(b, e);
-        adj.insert(adj.end(), b, u);
-        ptr[i + 1] = (int64_t)adj.size();
-    }
+    });
+    ptr.assign((size_t)n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) ptr[i + 1] = ptr[i] + uniq[i + 1];
+    adj.resize((size_t)ptr[n]);
+    parallel_for((n + CH - 1) / CH, [&](int64_t c) {
+        for (int64_t i = c * CH; i < std::min(n, (c + 1) * CH); ++i)
+            std::copy(tmp.begin() + start[i], tmp.begin() + start[i] + (ptr[i + 1] - ptr[i]), adj.begin() + ptr[i]);
+    });
 }
 
 }  // namespace
+
+// The message of the lowest index i in [0, n) for which check(i) fails
+// (returns a message), or nullptr: chunks of indices on host threads, so the
+// result is that of a serial loop.
+template <class F>
+const char* first_failure(int64_t n, F&& check) {
+    constexpr int64_t CH = 1 << 15;
+    const int64_t nc = (n + CH - 1) / CH;
+    std::vector<const char*> msg((size_t)nc, nullptr);
+    parallel_for(nc, [&](int64_t c) {
+        for (int64_t i = c * CH; i < std::min(n, (c + 1) * CH); ++i)
+            if (const char* m = check(i)) {
+                msg[(size_t)c] = m;
+                return;
+            }
+    });
+    for (const char* m : msg)
+        if (m) return m;
+    return nullptr;
+}
 
 std::string validate(const ddmgnn_problem_desc& d) {
     const int64_t n = d.n_nodes;
@@ -235,40 +253,48 @@ std::string validate(const ddmgnn_problem_desc& d) {
         !d.sub_ptr || !d.sub_nodes || !d.weights)
         return "null pointer in problem descriptor";
     if (d.n_tri <= 0) return "n_tri must be positive";
-    for (int64_t t = 0; t < 3 * d.n_tri; ++t)
-        if (d.tri[t] < 0 || d.tri[t] >= n) return "triangle node id out of range";
-    for (int64_t i = 0; i < n; ++i) {
-        if (d.dirichlet[i] > 1) return "dirichlet flags must be 0 or 1";
-        if (!std::isfinite(d.xy[2 * i]) || !std::isfinite(d.xy[2 * i + 1])) return "non-finite coordinate";
-        if (!std::isfinite(d.b[i]) || !std::isfinite(d.u0[i])) return "non-finite b or u0";
-    }
+    if (const char* m = first_failure(3 * d.n_tri, [&](int64_t t) -> const char* {
+            return d.tri[t] < 0 || d.tri[t] >= n ? "triangle node id out of range" : nullptr;
+        }))
+        return m;
+    if (const char* m = first_failure(n, [&](int64_t i) -> const char* {
+            if (d.dirichlet[i] > 1) return "dirichlet flags must be 0 or 1";
+            if (!std::isfinite(d.xy[2 * i]) || !std::isfinite(d.xy[2 * i + 1])) return "non-finite coordinate";
+            if (!std::isfinite(d.b[i]) || !std::isfinite(d.u0[i])) return "non-finite b or u0";
+            return nullptr;
+        }))
+        return m;
     if (d.a_rowptr[0] != 0) return "a_rowptr[0] must be 0";
-    for (int64_t i = 0; i < n; ++i) {
-        int32_t s = d.a_rowptr[i], e = d.a_rowptr[i + 1];
-        if (e < s) return "a_rowptr must be non-decreasing";
-        bool diag = false;
-        for (int32_t k = s; k < e; ++k) {
-            int32_t c = d.a_col[k];
-            if (c < 0 || c >= n) return "column index out of range";
-            if (k > s && c <= d.a_col[k - 1]) return "columns must be strictly ascending in each row";
-            if (!std::isfinite(d.a_val[k])) return "non-finite matrix value";
-            if (c == i) diag = true;
-            if (d.dirichlet[i] && c != i) return "Dirichlet rows must be identity rows";
-            if (d.dirichlet[i] && d.a_val[k] != 1.0) return "Dirichlet rows must be identity rows";
-            if (!d.dirichlet[i] && d.dirichlet[c]) return "free rows must not couple to Dirichlet nodes";
-        }
-        if (!diag) return "missing diagonal entry";
-    }
-    // Symmetry: for every (i, c, v) the entry (c, i) exists with the same value.
-    for (int64_t i = 0; i < n; ++i) {
-        for (int32_t k = d.a_rowptr[i]; k < d.a_rowptr[i + 1]; ++k) {
-            int32_t c = d.a_col[k];
-            const int32_t* b = d.a_col + d.a_rowptr[c];
-            const int32_t* e = d.a_col + d.a_rowptr[c + 1];
-            const int32_t* it = std::lower_bound(b, e, (int32_t)i);
-            if (it == e || *it != i || d.a_val[it - d.a_col] != d.a_val[k]) return "matrix is not symmetric";
-        }
-    }
+    if (const char* m = first_failure(n, [&](int64_t i) -> const char* {
+            int32_t s = d.a_rowptr[i], e = d.a_rowptr[i + 1];
+            if (e < s) return "a_rowptr must be non-decreasing";
+            bool diag = false;
+            for (int32_t k = s; k < e; ++k) {
+                int32_t c = d.a_col[k];
+                if (c < 0 || c >= n) return "column index out of range";
+                if (k > s && c <= d.a_col[k - 1]) return "columns must be strictly ascending in each row";
+                if (!std::isfinite(d.a_val[k])) return "non-finite matrix value";
+                if (c == i) diag = true;
+                if (d.dirichlet[i] && c != i) return "Dirichlet rows must be identity rows";
+                if (d.dirichlet[i] && d.a_val[k] != 1.0) return "Dirichlet rows must be identity rows";
+                if (!d.dirichlet[i] && d.dirichlet[c]) return "free rows must not couple to Dirichlet nodes";
+            }
+            return diag ? nullptr : "missing diagonal entry";
+        }))
+        return m;
+    // Symmetry: for every (i, c, v) the entry (c, i) exists with the same value
+    // (the rows are valid by now).
+    if (const char* m = first_failure(n, [&](int64_t i) -> const char* {
+            for (int32_t k = d.a_rowptr[i]; k < d.a_rowptr[i + 1]; ++k) {
+                int32_t c = d.a_col[k];
+                const int32_t* b = d.a_col + d.a_rowptr[c];
+                const int32_t* e = d.a_col + d.a_rowptr[c + 1];
+                const int32_t* it = std::lower_bound(b, e, (int32_t)i);
+                if (it == e || *it != i || d.a_val[it - d.a_col] != d.a_val[k]) return "matrix is not symmetric";
+            }
+            return nullptr;
+        }))
+        return m;
     if (d.n_sub <= 0) return "n_sub must be positive";
     if (d.sub_ptr[0] != 0) return "sub_ptr[0] must be 0";
     std::vector<double> wsum(n, 0.0);

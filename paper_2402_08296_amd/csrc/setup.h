@@ -2,14 +2,37 @@
 // expansion, local DSS graphs, membership lists and the coarse operator.
 #pragma once
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ddmgnn.h"
 
 namespace ddmgnn {
+
+// Indices 0..n-1 spread over host threads; each index is handled by one thread,
+// so results do not depend on the thread count.
+template <class F>
+void parallel_for(int64_t n, F&& f) {
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const int64_t T = std::min<int64_t>({n, (int64_t)hw, 16});
+    if (T <= 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    auto work = [&] {
+        for (int64_t i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
+    };
+    std::vector<std::thread> th;
+    for (int64_t t = 1; t < T; ++t) th.emplace_back(work);
+    work();
+    for (auto& t : th) t.join();
+}
 
 constexpr int kMaxSubNodes = 2048;      // largest sub-mesh of the register-resident DSS kernels
 constexpr int kMaxSubNodesAny = 16384;  // largest sub-mesh accepted (16-bit local ids; DDM-LU stages
