@@ -130,9 +130,10 @@ enum { DDMGNN_MEM_HOST = 0, DDMGNN_MEM_DEVICE = 1 };
  *                     >= 0, summing to 1 over the sub-meshes of each free node
  *                     and 0 at Dirichlet nodes. They define the Nicolaides
  *                     coarse basis (column i of R_0^T is R_i^T D_i R_i 1).
- * Setup builds the local DSS graphs (edges l -> j for mesh edges inside the
- * sub-mesh, none received by Dirichlet nodes), R_0 A R_0^T and its inverse
- * (E_NOT_SPD if Cholesky fails), and uploads everything to the device. */
+ * Setup builds the local DSS graphs on the host (edges l -> j for mesh edges
+ * inside the sub-mesh, none received by Dirichlet nodes), uploads them, and
+ * forms R_0 A R_0^T and its inverse on the device (blocked Gauss-Jordan;
+ * E_NOT_SPD when a pivot is not above 1e-12 of its diagonal entry). */
 typedef struct {
     int64_t n_nodes;
     const double* xy;
@@ -180,7 +181,8 @@ typedef struct {
                           * (ignored when profile = 1) */
     int32_t local_solver;/* DDMGNN_LOCAL_GNN, or DDMGNN_LOCAL_LU: exact local solves with the
                           * inverses of R_i A R_i^T (dense FP64, sum k_i^2 doubles of device
-                          * memory), formed on the host at the problem's first LU use */
+                          * memory), assembled and inverted on the device at the problem's
+                          * first LU use (E_NOT_SPD when a pivot is not positive) */
     int32_t restart;     /* FGMRES: steps per cycle, 1..64 (30); the problem keeps
                           * (2 restart + 1) N doubles of device memory for it */
 } ddmgnn_solve_opts;
@@ -202,12 +204,13 @@ typedef struct {
                                 * 2 BF16 MFMA DSS for every sub-mesh, 3 exact local solves (DDM-LU),
                                 * 4 BF16 MFMA DSS for some sub-meshes and the FP32 VALU DSS for those
                                 * beyond its LDS or 2048-node budget (a BF16 request of a model with
-                                * d != 10 runs 1 throughout) */
+                                * d = 20 runs 1 throughout; d = 5 runs on matrix cores) */
     int32_t status;            /* this problem's own status (DDMGNN_OK, E_MAXIT, E_BREAKDOWN, ...) */
     double latency_ms;         /* served requests: completion - submission (host clock);
                                 * solves: equal to solve_ms */
     /* Served requests only (0 for solves), host clock: */
-    double setup_ms;           /* host setup (validation, local graphs, coarse operator) on a setup thread */
+    double setup_ms;           /* host setup (validation, local graphs, the device-ready arrays) on a
+                                * setup thread */
     double queue_ms;           /* waiting: for a setup thread, then for admission */
     double upload_ms;          /* admission: device buffers allocated and filled by the GPU thread */
 } ddmgnn_stats;
@@ -236,12 +239,14 @@ int ddmgnn_solve_batch(ddmgnn_ctx* ctx, ddmgnn_problem* const* probs, int32_t n,
 /* ---- serving: a stream of independent requests with continuous batching ----
  * The server owns ctx (its stream and device) until ddmgnn_server_destroy:
  * the caller makes no other call on ctx meanwhile. Requests are copied at
- * submission; `setup_threads` host threads (0: 4) run their setup; one GPU
- * thread admits set-up requests in submission order while their device
- * memory (ddmgnn_problem_device_bytes) fits `hbm_budget` bytes and at most
+ * submission; `setup_threads` host threads (0: 4) run their host setup
+ * (validation, local graphs, every array the device needs); one GPU thread
+ * admits set-up requests in submission order while their device memory
+ * (ddmgnn_problem_device_bytes) fits `hbm_budget` bytes and at most
  * `max_active` are active, advances all active requests together by chunks
- * of opts.check_every iterations (as ddmgnn_solve_batch) and retires each as
- * it converges. Requests batch together only when their Krylov method,
+ * of opts.check_every iterations (as ddmgnn_solve_batch), creates newly
+ * admitted problems on a stream of its own while a chunk runs, and retires
+ * each request as it converges. Requests batch together only when their Krylov method,
  * m_max, precision, prolong and coarse options agree; one that differs from
  * the active set waits until that set has drained (rtol and max_it are per
  * request). A request larger than the budget fails with E_BUDGET. */
@@ -455,15 +460,16 @@ int ddmgnn_problem_device_bytes(const ddmgnn_problem* prob, int64_t* bytes);
 int ddmgnn_setup_local_graph(const ddmgnn_problem_desc* desc, int32_t sub, int32_t* rowptr, int32_t* col,
                              int64_t* n_edges_sub);
 
-/* Inverse of the local matrix R_i A R_i^T of sub-mesh `sub` as the exact local
- * solver (DDM-LU, eq. (7)) forms it: dense, row-major k_sub x k_sub, into a
- * caller-owned host buffer. E_NOT_SPD when its Cholesky factorisation fails. */
+/* Inverse of the local matrix R_i A R_i^T of sub-mesh `sub` (the exact local
+ * solver of DDM-LU, eq. (7)), formed on the host by Cholesky: dense, row-major
+ * k_sub x k_sub, into a caller-owned host buffer (a host reference for the
+ * device factorisation). E_NOT_SPD when the Cholesky factorisation fails. */
 int ddmgnn_setup_local_inverse(const ddmgnn_problem_desc* desc, int32_t sub, double* inv);
 
 /* Coarse operator A_0 = R_0 A R_0^T (eq. (7), Nicolaides basis from the
- * weights) and its inverse as setup forms them, row-major K x K into
- * caller-owned host buffers (either may be NULL). E_NOT_SPD when the Cholesky
- * factorisation fails. */
+ * weights) and its inverse formed on the host (Cholesky), row-major K x K into
+ * caller-owned host buffers (either may be NULL): a host reference for the
+ * device setup. E_NOT_SPD when the Cholesky factorisation fails. */
 int ddmgnn_setup_coarse(const ddmgnn_problem_desc* desc, double* a0, double* a0inv);
 
 #ifdef __cplusplus
