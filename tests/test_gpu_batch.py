@@ -275,3 +275,34 @@ def test_server_budget_and_invalid(ctx, mix):
     rc, st, _ = srv.poll(t_bad)
     assert rc == -1
     srv.close()
+
+
+def test_server_admission_failure_beside_running_chunks(ctx, mix):
+    """A request whose coarse matrix is singular (two identical sub-meshes) fails with
+    E_NOT_SPD when the server forms its coarse level on the upload stream, while the
+    requests admitted around it iterate; they still finish with their solo bits."""
+    print("[gpu] server admission failure", flush=True)
+    model = dg.Model(ctx, SMOOTHER)
+    opts = dg.default_opts(precision="bf16", rtol=1e-6, max_it=3000, check_every=4)
+    solo = _solo(ctx, model, mix, opts)
+    hp = mix[1][1]
+    sp = np.concatenate([hp.sub_ptr, [hp.sub_ptr[-1] + hp.sub_ptr[1]]])
+    sn = np.concatenate([hp.sub_nodes, hp.sub_nodes[:hp.sub_ptr[1]]])
+    w = np.concatenate([hp.weights, hp.weights[:hp.sub_ptr[1]]])
+    w[:hp.sub_ptr[1]] *= 0.5
+    w[hp.sub_ptr[-1]:] *= 0.5
+    singular = dg.HostProblem(hp.xy, hp.tri, hp.dirichlet, hp.rowptr, hp.col, hp.val, hp.b, hp.u0, sp, sn, w)
+    sctx = dg.Context(torch.cuda.Stream())
+    srv = dg.Server(sctx, model, hbm_budget=1 << 34, max_active=8, setup_threads=2)
+    tickets = [srv.submit(h, opts) for _, h in mix[:2]]
+    t_bad = srv.submit(singular, opts)
+    tickets += [srv.submit(h, opts) for _, h in mix[2:]]
+    srv.drain()
+    rc, st, _ = srv.poll(t_bad)
+    print(f"[gpu]   singular request: rc={rc}", flush=True)
+    assert rc == -4 and st.status == -4
+    for i, t in enumerate(tickets):
+        rc, st, u = srv.poll(t)
+        assert rc == 0 and st.converged and st.iterations == solo[i][1]
+        assert np.array_equal(u, solo[i][0])
+    srv.close()
