@@ -367,8 +367,14 @@ int ddmgnn_server_create(ddmgnn_ctx* ctx, const ddmgnn_model* model, int64_t hbm
     s->model = model->dev;
     s->budget = (size_t)hbm_budget;
     s->max_active = max_active;
-    if (hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking) != hipSuccess)
-        return fail(DDMGNN_E_HIP, "server upload stream");
+    {  // the upload stream lives on the context's device (the caller's current device is restored)
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->upload, hipStreamNonBlocking);
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess) return fail(DDMGNN_E_HIP, std::string("server upload stream: ") + hipGetErrorString(e));
+    }
     const int nw = setup_threads ? setup_threads : 4;
     for (int i = 0; i < nw; ++i) s->workers.emplace_back(&ddmgnn_server::setup_worker, s.get());
     s->gpu = std::thread(&ddmgnn_server::gpu_loop, s.get());
