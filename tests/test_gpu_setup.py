@@ -67,17 +67,21 @@ def test_overlap_expansion_refuses_bad_ids(ctx):
 
 
 @pytest.mark.timeout(300)
-@pytest.mark.parametrize("seed,n,parts", [(11, 20_000, 40), (12, 120_000, 700)])
-def test_coarse_level_formed_on_device(ctx, seed, n, parts):
+@pytest.mark.parametrize("seed,n,parts,delta", [(11, 20_000, 40, 2), (12, 120_000, 700, 2), (15, 6000, 240, 4)])
+def test_coarse_level_formed_on_device(ctx, seed, n, parts, delta):
     """y = A_0^{-1} R_0 r of one apply against numpy's solve of the oracle's A_0 (K = 40 and
-    700: 2 and 22 pivot blocks of 32, up to 121 tiles of 64 x 64 per step)."""
+    700: one and eleven pivot blocks of 64, up to 121 tiles of 64 x 64 per step). The third
+    problem (small parts, overlap 4) has rows of A_0 with more than 32 nonzero columns, which
+    the assembly sums on one thread, beside rows summed by whole workgroups."""
     p = W.make_problem(seed, n, parts, 0.3)
-    hp = oracle_problem(p)
+    hp = oracle_problem(p, delta=delta)
     print(f"[gpu] device coarse level N={p.n} K={hp.K}", flush=True)
     prob = dg.Problem(ctx, hp, dg.Model(ctx, SMOOTHER))
     A = p.A.to_scipy()
     dec = dc.Decomposition(p.n, hp.sub_ptr, hp.sub_nodes, hp.weights)
     co = sw.Coarse(A, dec)
+    if delta == 4:
+        assert (np.count_nonzero(co.A0, axis=1) > 32).any() and (np.count_nonzero(co.A0, axis=1) <= 32).any()
     r = p.b - A @ p.u0
     z = torch.empty(p.n, dtype=torch.float64, device="cuda")
     prob.apply(torch.from_numpy(r).cuda(), z, dg.default_opts(precision="fp64"))
@@ -110,8 +114,8 @@ def test_singular_coarse_refused_on_device(ctx):
 @pytest.mark.timeout(300)
 def test_local_inverses_formed_on_device(ctx):
     """Local terms of a DDM-LU apply (the device inverses times R_i r) against numpy's solve
-    of each R_i A R_i^T (every seventh sub-mesh; sub-meshes of roughly a thousand nodes, tens
-    of pivot blocks of 32)."""
+    of each R_i A R_i^T (every seventh sub-mesh; sub-meshes of 219 to 6102 nodes, up to 96
+    pivot blocks of 64 in one batch)."""
     p = W.make_problem(14, 60_000, 60, 0.5)
     hp = oracle_problem(p)
     ks = np.diff(hp.sub_ptr)
