@@ -609,26 +609,63 @@ __device__ __forceinline__ void prolong_rows(const int32_t* __restrict__ node_pt
                                              const double* __restrict__ q0, const double* __restrict__ q1,
                                              const double* __restrict__ q2, const double* __restrict__ q3, int m,
                                              bool unweighted, Rows rg, int n, double (&dots)[MAX_M + 1]) {
-    for (int gi = rg.g0; gi < rg.g1; gi += rg.gs) {
-        const int i = gi * VEC_BLOCK + threadIdx.x;
-        if (i >= n) continue;
-        double zn = 0.0;
-        if (!dirichlet[i]) {
-            for (int q = node_ptr[i]; q < node_ptr[i + 1]; ++q) {
+    // U rows of the thread at a time: the gathers of their first PM memberships
+    // (most nodes have one or two) are all issued before any row is summed, so
+    // the node -> slot -> value chains of the rows overlap. Each row is summed,
+    // and the dots accumulated, in the same order as one row at a time.
+    constexpr int U = 4, PM = 2;
+    for (int gb = rg.g0; gb < rg.g1; gb += U * rg.gs) {
+        int row[U], qb[U], qe[U];
+        double wv[U][PM], lv[U][PM], yv[U][PM];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int gi = gb + u * rg.gs;
+            const int i = gi * VEC_BLOCK + threadIdx.x;
+            row[u] = gi < rg.g1 && i < n ? i : -1;
+            qb[u] = qe[u] = 0;
+            if (row[u] >= 0 && !dirichlet[i]) {
+                qb[u] = node_ptr[i];
+                qe[u] = node_ptr[i + 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < PM; ++t) {
+                wv[u][t] = lv[u][t] = yv[u][t] = 0.0;
+                if (qb[u] + t < qe[u]) {
+                    const int slot = node_slots[qb[u] + t];
+                    wv[u][t] = weights[slot];
+                    lv[u][t] = local[slot];
+                    if (y) yv[u][t] = y[slot_sub[slot]];
+                }
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = row[u];
+            if (i < 0) continue;
+            double zn = 0.0;
+#pragma unroll
+            for (int t = 0; t < PM; ++t)
+                if (qb[u] + t < qe[u]) {
+                    zn = fma(unweighted ? 1.0 : wv[u][t], lv[u][t], zn);
+                    if (y) zn = fma(wv[u][t], yv[u][t], zn);
+                }
+            for (int q = qb[u] + PM; q < qe[u]; ++q) {
                 const int slot = node_slots[q];
                 const double w = weights[slot];
                 zn = fma(unweighted ? 1.0 : w, local[slot], zn);
                 if (y) zn = fma(w, y[slot_sub[slot]], zn);
             }
-        }
-        z[i] = zn;
-        if (MODE == DDMGNN_FCG) {
-            dots[0] = fma(zn, q0[i], dots[0]);
-            if (m > 1) dots[1] = fma(zn, q1[i], dots[1]);
-            if (m > 2) dots[2] = fma(zn, q2[i], dots[2]);
-            if (m > 3) dots[3] = fma(zn, q3[i], dots[3]);
-        } else if (MODE == DDMGNN_PCG) {
-            dots[0] = fma(r[i], zn, dots[0]);
+            z[i] = zn;
+            if (MODE == DDMGNN_FCG) {
+                dots[0] = fma(zn, q0[i], dots[0]);
+                if (m > 1) dots[1] = fma(zn, q1[i], dots[1]);
+                if (m > 2) dots[2] = fma(zn, q2[i], dots[2]);
+                if (m > 3) dots[3] = fma(zn, q3[i], dots[3]);
+            } else if (MODE == DDMGNN_PCG) {
+                dots[0] = fma(r[i], zn, dots[0]);
+            }
         }
     }
 }
