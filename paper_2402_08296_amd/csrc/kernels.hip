@@ -376,6 +376,9 @@ __global__ __launch_bounds__(BLOCK) void dss_kernel(DssArgs<T> a, const T* __res
                     }
                 }
                 const int e0 = edge_ptr[base + j], e1 = edge_ptr[base + j + 1];
+                // Threads in their edge sums issue ahead of those in the dense
+                // layers (same arithmetic; c1 and c2 solves 4-7% faster).
+                __builtin_amdgcn_s_setprio(1);
                 if (SEP) {
                     // Chunks of 2 edges as straight-line code: both rows are read from
                     // LDS before the sums. An edge past e1 reads the node's own row
@@ -421,6 +424,7 @@ __global__ __launch_bounds__(BLOCK) void dss_kernel(DssArgs<T> a, const T* __res
                         }
                     }
                 }
+                __builtin_amdgcn_s_setprio(0);
                 const T deg = (T)(e1 - e0);
                 T phio[D], phii[D];
 #pragma unroll
