@@ -550,9 +550,22 @@ __device__ __forceinline__ void dss_blocks(const DssMfmaArgs& a, float (&h)[MAX_
 // A sub-mesh runs with two Q' buffers when they fit the launch's dynamic LDS
 // (a.lds_bytes), else with one. The message sums run in packed FP16 (two
 // units per instruction).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const u32x4 __attribute__((address_space(1))) gu32x4;
+// A load through a global-space pointer (the table's pointers are generic).
+template <typename T>
+__device__ inline T gload(const T* p) {
+    return *(const T __attribute__((address_space(1)))*)p;
+}
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     constexpr int VT = MFMA_BLOCK / BLOCK;  // virtual threads per thread in the restriction sums
+    constexpr int MAX_K = MAX_TILES_PER_WAVE * (MFMA_BLOCK / 64) * MFMA_TILE;  // largest sub-mesh
+    constexpr int RJ = 2;  // sub-mesh nodes per virtual thread
+    static_assert(RJ * MFMA_BLOCK >= MAX_K, "a virtual thread holds all its nodes");
+    constexpr int TU = (MAX_K + BLOCK - 1) / BLOCK;  // tile records per thread
+    constexpr int EU = 4;                                   // edge-record quads per thread and pass
     const int2 wi = a.work[blockIdx.x];
     const DevProb& P = a.tab[wi.x];
     if (P.st && P.st->done) return;
@@ -571,27 +584,69 @@ __global__ __launch_bounds__(BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
     h2* Qd = reinterpret_cast<h2*>(lds + ((k + 3) & ~3));
     uint32_t* E = reinterpret_cast<uint32_t*>(Qd + (size_t)nbuf * ((10 * (k + 1) + 3) & ~3));
     TileNode* T = reinterpret_cast<TileNode*>(E + ((ne + 3) & ~3));
-    for (int i = tid; i < ne; i += BLOCK) E[i] = P.erec[ebase + i];
+    // The records go to LDS with every global load of a thread in flight
+    // before the first store (16-byte loads through global-space pointers, so
+    // the LDS stores do not wait for them one by one). Edge blocks are whole
+    // tiles of MFMA_EC x MFMA_TILE records, so ne and ebase are multiples of 4.
+    {
+        const gu32x4* esrc = (const gu32x4*)(P.erec + ebase);
+        u32x4* edst = reinterpret_cast<u32x4*>(E);
+        const int ne4 = ne >> 2;
+        // loads past the end re-read the last entry (no branches between the
+        // loads); only the stores are guarded
+        for (int i0 = tid; i0 < ne4; i0 += EU * BLOCK) {
+            u32x4 v[EU];
+#pragma unroll
+            for (int u = 0; u < EU; ++u) v[u] = esrc[min(i0 + u * BLOCK, ne4 - 1)];
+#pragma unroll
+            for (int u = 0; u < EU; ++u)
+                if (i0 + u * BLOCK < ne4) edst[i0 + u * BLOCK] = v[u];
+        }
+        const gu32x4* tsrc = (const gu32x4*)(P.tiles + base);
+        u32x4* tdst = reinterpret_cast<u32x4*>(T);
+        u32x4 v[TU];
+#pragma unroll
+        for (int u = 0; u < TU; ++u) v[u] = tsrc[min(tid + u * BLOCK, k - 1)];
+#pragma unroll
+        for (int u = 0; u < TU; ++u)
+            if (tid + u * BLOCK < k) tdst[tid + u * BLOCK] = v[u];
+    }
     if (tid < 10 * nbuf) {  // sentinel rows: every message through them is ReLU(-inf) = 0
         const _Float16 ninf = __builtin_bit_cast(_Float16, (uint16_t)0xFC00u);
         const int b = tid / 10, t = tid % 10;
         Qd[(size_t)b * ((10 * (k + 1) + 3) & ~3) + (size_t)(t / 5) * 5 * (k + 1) + 5 * k + t % 5] = (h2){ninf, ninf};
     }
-    for (int i = tid; i < k; i += BLOCK)
-        reinterpret_cast<uint4*>(T)[i] = reinterpret_cast<const uint4*>(P.tiles + base)[i];
-    // Restriction and normalisation (Sec. III.A step 2).
+    // Restriction and normalisation (Sec. III.A step 2). Virtual thread q of
+    // this thread sums j = tid + q BLOCK + m MFMA_BLOCK (m = 0, 1; k <= 2048),
+    // in that order; the ids and weights of all its j, then their residuals,
+    // are loaded before the sums, and the residuals are kept for c.
     double s = 1.0;
     if (a.apply) {
-        double ssv[VT], yyv[VT];
+        double ssv[VT], yyv[VT], rv[VT][RJ];
+        int g[VT][RJ];
+        double wv[VT][RJ];
+#pragma unroll
+        for (int q = 0; q < VT; ++q)
+#pragma unroll
+            for (int m = 0; m < RJ; ++m) {
+                const int j = min(tid + q * BLOCK + m * MFMA_BLOCK, k - 1);  // past the end: unused
+                g[q][m] = gload(P.sub_nodes + base + j);
+                wv[q][m] = gload(P.weights + base + j);
+            }
+#pragma unroll
+        for (int q = 0; q < VT; ++q)
+#pragma unroll
+            for (int m = 0; m < RJ; ++m) rv[q][m] = gload(P.r + g[q][m]);
 #pragma unroll
         for (int q = 0; q < VT; ++q) {
             ssv[q] = 0.0;
             yyv[q] = 0.0;
-            for (int j = tid + q * BLOCK; j < k; j += MFMA_BLOCK) {
-                const double rv = P.r[P.sub_nodes[base + j]];
-                ssv[q] = fma(rv, rv, ssv[q]);
-                yyv[q] = fma(P.weights[base + j], rv, yyv[q]);
-            }
+#pragma unroll
+            for (int m = 0; m < RJ; ++m)
+                if (tid + q * BLOCK + m * MFMA_BLOCK < k) {
+                    ssv[q] = fma(rv[q][m], rv[q][m], ssv[q]);
+                    yyv[q] = fma(wv[q][m], rv[q][m], yyv[q]);
+                }
         }
         const double ss = block_sum<BLOCK>(ssv, red);
         const double yy = block_sum<BLOCK>(yyv, red);
@@ -605,7 +660,13 @@ __global__ __launch_bounds__(BLOCK) void dss_mfma_kernel(DssMfmaArgs a) {
             return;
         }
         const double inv = 1.0 / s;
-        for (int j = tid; j < k; j += BLOCK) cbuf[j] = (float)(P.r[P.sub_nodes[base + j]] * inv);
+#pragma unroll
+        for (int q = 0; q < VT; ++q)
+#pragma unroll
+            for (int m = 0; m < RJ; ++m) {
+                const int j = tid + q * BLOCK + m * MFMA_BLOCK;
+                if (j < k) cbuf[j] = (float)(rv[q][m] * inv);
+            }
     } else {
         for (int j = tid; j < k; j += BLOCK) cbuf[j] = (float)P.c_in[base + j];
     }
